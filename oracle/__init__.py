@@ -1,0 +1,215 @@
+"""CPU oracle (plain C, FP64) for the block-sparse multiply and sign iteration.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+CPU-baseline leg of ``bench.py``; never by the HIP library or its binding.
+The C source (``bsm_oracle.c``) is compiled with gcc into ``liboracle.so``
+next to it; it shares no code with the HIP path.  Matrices travel as
+``synth.BSR`` objects (plain arrays from the input generator).
+
+Parity status of each function (what pins it, see ``tests/test_oracle.py``):
+
+* ``multiply``      -- pinned: dense NumPy GEMM brute force on random tiny
+                       cases (mixed sizes, alpha/beta, filter), the block
+                       pattern by Python set logic.
+* ``filter``        -- pinned: keep rule re-derived per block from the dense
+                       matrix.
+* ``sign_ns``       -- pinned: eigen-decomposition sign (LAPACK) on tiny
+                       dense cases, scalar recurrence on diagonal H, 2x2
+                       closed form, trace = number of negative eigenvalues.
+* ``trace``, ``sqdist_identity``, ``inf_norm_shifted`` -- pinned against
+                       ``numpy`` on the dense matrix.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+from synth import BSR
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bsm_oracle.c")
+# A test may point this at a deliberately broken copy to show the pins fail.
+_LIB = os.environ.get("BSM_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+NORM_FROB, NORM_MAXABS = 0, 1
+OK, EINVAL, ENOMEM, ENOCONV, ENONFINITE = 0, -1, -2, -4, -5
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                               "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _OMat(C.Structure):
+    _fields_ = [("nbrows", C.c_int32), ("nbcols", C.c_int32),
+                ("rbs", C.c_void_p), ("cbs", C.c_void_p),
+                ("nnzb", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("values", C.c_void_p)]
+
+
+class _SignStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("n_multiplies", C.c_int32),
+                ("r_hist", C.c_double * 128), ("scale", C.c_double),
+                ("trace_x", C.c_double), ("trace_p", C.c_double),
+                ("flops", C.c_double)]
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build(force=False)
+            lib = C.CDLL(_LIB)
+            P = C.POINTER(_OMat)
+            lib.orc_multiply.argtypes = [C.c_double, P, P, C.c_double, P, C.c_double, C.c_int, P]
+            lib.orc_filter.argtypes = [P, C.c_double, C.c_int, P]
+            lib.orc_block_sqnorms.argtypes = [P, C.c_void_p]
+            lib.orc_trace.argtypes = [P]
+            lib.orc_trace.restype = C.c_double
+            lib.orc_sqdist_identity.argtypes = [P, C.c_double]
+            lib.orc_sqdist_identity.restype = C.c_double
+            lib.orc_inf_norm_shifted.argtypes = [P, C.c_double]
+            lib.orc_inf_norm_shifted.restype = C.c_double
+            lib.orc_shift_scale.argtypes = [P, C.c_double, C.c_double, P]
+            lib.orc_sign_ns.argtypes = [P, C.c_double, C.c_double, C.c_int, C.c_double,
+                                        C.c_int32, C.c_int32, P, C.POINTER(_SignStats)]
+            lib.orc_density_from_sign.argtypes = [P, P]
+            lib.orc_free.argtypes = [P]
+            lib.orc_num_threads.restype = C.c_int
+            _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data if a.size else 0
+
+
+def _in(m: BSR) -> tuple[_OMat, tuple]:
+    keep = (m.row_blk_size, m.col_blk_size, m.row_ptr, m.col_idx, m.values)
+    om = _OMat(m.nbrows, m.nbcols, _ptr(m.row_blk_size), _ptr(m.col_blk_size),
+               m.nnzb, _ptr(m.row_ptr), _ptr(m.col_idx), _ptr(m.values))
+    return om, keep
+
+
+def _out(om: _OMat, rbs: np.ndarray, cbs: np.ndarray) -> BSR:
+    lib = _load()
+    nnzb = int(om.nnzb)
+    rp = np.ctypeslib.as_array(C.cast(om.row_ptr, C.POINTER(C.c_int64)), (om.nbrows + 1,)).copy()
+    ci = (np.ctypeslib.as_array(C.cast(om.col_idx, C.POINTER(C.c_int32)), (nnzb,)).copy()
+          if nnzb else np.zeros(0, np.int32))
+    rows = np.repeat(np.arange(om.nbrows), np.diff(rp))
+    nval = int((rbs[rows].astype(np.int64) * cbs[ci].astype(np.int64)).sum())
+    vals = (np.ctypeslib.as_array(C.cast(om.values, C.POINTER(C.c_double)), (nval,)).copy()
+            if nval else np.zeros(0))
+    lib.orc_free(C.byref(om))
+    return BSR(rbs.copy(), cbs.copy(), rp, ci, vals)
+
+
+def _check(st: int, what: str):
+    if st != OK:
+        raise RuntimeError(f"oracle {what} failed with status {st}")
+
+
+def _norm(norm) -> int:
+    return {"frob": NORM_FROB, "maxabs": NORM_MAXABS, NORM_FROB: NORM_FROB,
+            NORM_MAXABS: NORM_MAXABS}[norm]
+
+
+def multiply(alpha: float, a: BSR, b: BSR, beta: float = 0.0, c: BSR | None = None,
+             eps: float = 0.0, norm="frob") -> BSR:
+    """C = alpha*A*B + beta*Cin, then the block-norm filter (plain loops)."""
+    lib = _load()
+    oa, ka = _in(a)
+    ob, kb = _in(b)
+    oc, kc = _in(c) if c is not None else (None, None)
+    out = _OMat()
+    st = lib.orc_multiply(alpha, C.byref(oa), C.byref(ob), beta,
+                          C.byref(oc) if oc is not None else None, eps, _norm(norm), C.byref(out))
+    _check(st, "multiply")
+    return _out(out, a.row_blk_size, b.col_blk_size)
+
+
+def filter(a: BSR, eps: float, norm="frob") -> BSR:  # noqa: A001 - mirrors the operation name
+    lib = _load()
+    oa, ka = _in(a)
+    out = _OMat()
+    _check(lib.orc_filter(C.byref(oa), eps, _norm(norm), C.byref(out)), "filter")
+    return _out(out, a.row_blk_size, a.col_blk_size)
+
+
+def block_sqnorms(a: BSR) -> np.ndarray:
+    lib = _load()
+    oa, ka = _in(a)
+    out = np.zeros(a.nnzb)
+    _check(lib.orc_block_sqnorms(C.byref(oa), _ptr(out)), "block_sqnorms")
+    return out
+
+
+def trace(a: BSR) -> float:
+    oa, ka = _in(a)
+    return float(_load().orc_trace(C.byref(oa)))
+
+
+def sqdist_identity(a: BSR, shift: float = 1.0) -> float:
+    oa, ka = _in(a)
+    return float(_load().orc_sqdist_identity(C.byref(oa), shift))
+
+
+def inf_norm_shifted(a: BSR, mu: float = 0.0) -> float:
+    oa, ka = _in(a)
+    return float(_load().orc_inf_norm_shifted(C.byref(oa), mu))
+
+
+def shift_scale(a: BSR, mu: float, scale: float) -> BSR:
+    lib = _load()
+    oa, ka = _in(a)
+    out = _OMat()
+    _check(lib.orc_shift_scale(C.byref(oa), mu, scale, C.byref(out)), "shift_scale")
+    return _out(out, a.row_blk_size, a.col_blk_size)
+
+
+def sign_ns(h: BSR, mu: float = 0.0, eps: float = 0.0, tol: float = 1e-6,
+            max_iter: int = 100, fixed_iters: int = 0, norm="frob"):
+    """Second-order Newton-Schulz sign iteration; returns (X, stats, status).
+
+    ``status`` is OK, ENOCONV or ENONFINITE; X is the last iterate in every
+    case that produced one.
+    """
+    lib = _load()
+    oh, kh = _in(h)
+    out = _OMat()
+    st = _SignStats()
+    status = lib.orc_sign_ns(C.byref(oh), mu, eps, _norm(norm), tol, max_iter, fixed_iters,
+                             C.byref(out), C.byref(st))
+    if status not in (OK, ENOCONV, ENONFINITE):
+        raise RuntimeError(f"oracle sign_ns failed with status {status}")
+    x = _out(out, h.row_blk_size, h.col_blk_size) if out.row_ptr else None
+    stats = dict(iterations=int(st.iterations), n_multiplies=int(st.n_multiplies),
+                 r_hist=[float(st.r_hist[k]) for k in range(st.iterations + 1)],
+                 scale=float(st.scale), trace_x=float(st.trace_x),
+                 trace_p=float(st.trace_p), flops=float(st.flops))
+    return x, stats, int(status)
+
+
+def density_from_sign(x: BSR) -> BSR:
+    lib = _load()
+    ox, kx = _in(x)
+    out = _OMat()
+    _check(lib.orc_density_from_sign(C.byref(ox), C.byref(out)), "density_from_sign")
+    return _out(out, x.row_blk_size, x.col_blk_size)
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())

@@ -1,0 +1,510 @@
+/*
+ * CPU oracle for the block-sparse multiply, the norm filter and the
+ * Newton-Schulz sign iteration.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: it exists so that tests, the smoke check and the CPU
+ * baseline leg of the benchmark can compare the HIP library against a plain,
+ * slow, obviously correct reference.  It shares no code, header or helper
+ * with the HIP library.
+ *
+ * Everything here is plain C, FP64, explicit loops, no BLAS, compiled with
+ * -O2 -ffp-contract=off so that no multiply-add is fused.  OpenMP only
+ * splits independent block rows between threads; each output element is
+ * summed by one thread in ascending k.
+ *
+ * Matrix layout (the blocked CSR of the DBCSR section): block-row pointers
+ * row_ptr[nbrows+1] (int64), column indices col_idx[nnzb] (int32, strictly
+ * increasing per row), values = stored blocks concatenated in CSR order, each
+ * block row-major, of size row_blk_size[i] x col_blk_size[j].
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int32_t nbrows, nbcols;
+    const int32_t *rbs;   /* row block sizes  [nbrows] */
+    const int32_t *cbs;   /* col block sizes  [nbcols] */
+    int64_t nnzb;
+    int64_t *row_ptr;     /* [nbrows+1] */
+    int32_t *col_idx;     /* [nnzb] */
+    double *values;       /* concatenated row-major blocks */
+} omat;
+
+enum { ORC_NORM_FROB = 0, ORC_NORM_MAXABS = 1 };
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ENOCONV = -4,
+       ORC_ENONFINITE = -5 };
+
+/* ---------------------------------------------------------------- helpers */
+
+static int64_t *block_offsets(const omat *a)
+{
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(a->nnzb + 1));
+    if (!off) return NULL;
+    off[0] = 0;
+    for (int32_t i = 0; i < a->nbrows; ++i)
+        for (int64_t t = a->row_ptr[i]; t < a->row_ptr[i + 1]; ++t)
+            off[t + 1] = off[t] + (int64_t)a->rbs[i] * a->cbs[a->col_idx[t]];
+    return off;
+}
+
+/* Position of block (i, j) in a, or -1 (binary search in row i). */
+static int64_t find_block(const omat *a, int32_t i, int32_t j)
+{
+    int64_t lo = a->row_ptr[i], hi = a->row_ptr[i + 1] - 1;
+    while (lo <= hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (a->col_idx[mid] == j) return mid;
+        if (a->col_idx[mid] < j) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+void orc_free(omat *m)
+{
+    if (!m) return;
+    free(m->row_ptr); free(m->col_idx); free(m->values);
+    m->row_ptr = NULL; m->col_idx = NULL; m->values = NULL; m->nnzb = 0;
+}
+
+/*
+ * Keep test of the norm filter (Sign-Method section: after every product,
+ * entries below eps_filter are flushed to zero to retain sparsity).  Read at
+ * block granularity: FROB drops a block iff sum(x^2) < eps^2, MAXABS drops it
+ * iff max|x| < eps.  With eps = 0 nothing is dropped.
+ */
+static int keep_block(const double *x, int64_t len, double eps, int kind)
+{
+    if (kind == ORC_NORM_MAXABS) {
+        double mx = 0.0;
+        for (int64_t e = 0; e < len; ++e) { double v = fabs(x[e]); if (v > mx) mx = v; }
+        return !(mx < eps);
+    }
+    double s = 0.0;
+    for (int64_t e = 0; e < len; ++e) s += x[e] * x[e];
+    return !(s < eps * eps);
+}
+
+/* Squared Frobenius norm of every stored block, in storage order. */
+int orc_block_sqnorms(const omat *a, double *out)
+{
+    int64_t *off = block_offsets(a);
+    if (!off) return ORC_ENOMEM;
+    for (int64_t t = 0; t < a->nnzb; ++t) {
+        double s = 0.0;
+        for (int64_t e = off[t]; e < off[t + 1]; ++e) s += a->values[e] * a->values[e];
+        out[t] = s;
+    }
+    free(off);
+    return ORC_OK;
+}
+
+/* ----------------------------------------------------- per-row assembly */
+
+typedef struct {
+    int64_t nblk, cap_blk, nval, cap_val;
+    int32_t *cols;
+    double *vals;
+} rowbuf;
+
+static int rowbuf_push(rowbuf *r, int32_t j, const double *blk, int64_t len)
+{
+    if (r->nblk == r->cap_blk) {
+        int64_t c = r->cap_blk ? 2 * r->cap_blk : 16;
+        int32_t *p = (int32_t *)realloc(r->cols, sizeof(int32_t) * (size_t)c);
+        if (!p) return ORC_ENOMEM;
+        r->cols = p; r->cap_blk = c;
+    }
+    if (r->nval + len > r->cap_val) {
+        int64_t c = r->cap_val ? 2 * r->cap_val : 1024;
+        while (c < r->nval + len) c *= 2;
+        double *p = (double *)realloc(r->vals, sizeof(double) * (size_t)c);
+        if (!p) return ORC_ENOMEM;
+        r->vals = p; r->cap_val = c;
+    }
+    r->cols[r->nblk++] = j;
+    memcpy(r->vals + r->nval, blk, sizeof(double) * (size_t)len);
+    r->nval += len;
+    return ORC_OK;
+}
+
+static int assemble(omat *out, int32_t nbrows, int32_t nbcols, const int32_t *rbs,
+                    const int32_t *cbs, rowbuf *rows)
+{
+    int64_t nnzb = 0, nval = 0;
+    for (int32_t i = 0; i < nbrows; ++i) { nnzb += rows[i].nblk; nval += rows[i].nval; }
+    out->nbrows = nbrows; out->nbcols = nbcols; out->rbs = rbs; out->cbs = cbs;
+    out->nnzb = nnzb;
+    out->row_ptr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nbrows + 1));
+    out->col_idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnzb ? nnzb : 1));
+    out->values = (double *)malloc(sizeof(double) * (size_t)(nval ? nval : 1));
+    if (!out->row_ptr || !out->col_idx || !out->values) { orc_free(out); return ORC_ENOMEM; }
+    int64_t pb = 0, pv = 0;
+    out->row_ptr[0] = 0;
+    for (int32_t i = 0; i < nbrows; ++i) {
+        if (rows[i].nblk) memcpy(out->col_idx + pb, rows[i].cols, sizeof(int32_t) * (size_t)rows[i].nblk);
+        if (rows[i].nval) memcpy(out->values + pv, rows[i].vals, sizeof(double) * (size_t)rows[i].nval);
+        pb += rows[i].nblk; pv += rows[i].nval;
+        out->row_ptr[i + 1] = pb;
+    }
+    return ORC_OK;
+}
+
+static void free_rows(rowbuf *rows, int32_t n)
+{
+    for (int32_t i = 0; i < n; ++i) { free(rows[i].cols); free(rows[i].vals); }
+    free(rows);
+}
+
+/* ------------------------------------------------------------- multiply */
+
+/*
+ * C = alpha * A * B + beta * Cin, then the norm filter.  This is the plain
+ * definition behind the DBCSR multiply (DBCSR section: matrix multiplication
+ * of blocked-CSR matrices; local multiplication as pairwise products of small
+ * dense blocks, C = C + A*B):
+ *
+ *   stored pattern S = {(i,j) : some k has A_ik and B_kj stored}
+ *                      union pattern(Cin) when beta != 0;
+ *   C_ij = alpha * sum_k A_ik B_kj + beta * Cin_ij  for (i,j) in S;
+ *   keep block (i,j) iff it passes the filter.
+ *
+ * Each C_ij is summed over k ascending, and inside a block product over the
+ * inner index ascending.  cin may be NULL (treated as empty); with beta == 0
+ * its pattern and values are ignored.
+ */
+int orc_multiply(double alpha, const omat *a, const omat *b, double beta,
+                 const omat *cin, double eps, int norm_kind, omat *out)
+{
+    if (a->nbcols != b->nbrows) return ORC_EINVAL;
+    for (int32_t k = 0; k < a->nbcols; ++k) if (a->cbs[k] != b->rbs[k]) return ORC_EINVAL;
+    for (int32_t i = 0; i < a->nbrows; ++i) if (a->rbs[i] < 1 || a->rbs[i] > 64) return ORC_EINVAL;
+    for (int32_t j = 0; j < b->nbcols; ++j) if (b->cbs[j] < 1 || b->cbs[j] > 64) return ORC_EINVAL;
+    if (eps < 0) return ORC_EINVAL;
+    int use_c = (beta != 0.0) && cin != NULL;
+    if (use_c && (cin->nbrows != a->nbrows || cin->nbcols != b->nbcols)) return ORC_EINVAL;
+
+    int64_t *aoff = block_offsets(a), *boff = block_offsets(b);
+    int64_t *coff = use_c ? block_offsets(cin) : NULL;
+    rowbuf *rows = (rowbuf *)calloc((size_t)(a->nbrows ? a->nbrows : 1), sizeof(rowbuf));
+    if (!aoff || !boff || (use_c && !coff) || !rows) {
+        free(aoff); free(boff); free(coff); free(rows); return ORC_ENOMEM;
+    }
+    int status = ORC_OK;
+
+#pragma omp parallel
+    {
+        unsigned char *mark = (unsigned char *)calloc((size_t)(b->nbcols ? b->nbcols : 1), 1);
+        double *acc = (double *)malloc(sizeof(double) * 64 * 64);
+        if (!mark || !acc) {
+#pragma omp atomic write
+            status = ORC_ENOMEM;
+        }
+#pragma omp for schedule(static)
+        for (int32_t i = 0; i < a->nbrows; ++i) {
+            if (!mark || !acc) continue;
+            const int32_t m = a->rbs[i];
+            /* pattern of row i */
+            for (int64_t ta = a->row_ptr[i]; ta < a->row_ptr[i + 1]; ++ta) {
+                int32_t k = a->col_idx[ta];
+                for (int64_t tb = b->row_ptr[k]; tb < b->row_ptr[k + 1]; ++tb)
+                    mark[b->col_idx[tb]] = 1;
+            }
+            if (use_c)
+                for (int64_t tc = cin->row_ptr[i]; tc < cin->row_ptr[i + 1]; ++tc)
+                    mark[cin->col_idx[tc]] = 1;
+            for (int32_t j = 0; j < b->nbcols; ++j) {
+                if (!mark[j]) continue;
+                mark[j] = 0;
+                const int32_t n = b->cbs[j];
+                for (int e = 0; e < m * n; ++e) acc[e] = 0.0;
+                for (int64_t ta = a->row_ptr[i]; ta < a->row_ptr[i + 1]; ++ta) {
+                    int32_t k = a->col_idx[ta];
+                    int64_t tb = find_block(b, k, j);
+                    if (tb < 0) continue;
+                    const int32_t kk = a->cbs[k];
+                    const double *ab = a->values + aoff[ta];
+                    const double *bb = b->values + boff[tb];
+                    for (int r = 0; r < m; ++r)
+                        for (int t = 0; t < kk; ++t) {
+                            const double av = ab[r * kk + t];
+                            for (int c = 0; c < n; ++c)
+                                acc[r * n + c] += av * bb[t * n + c];
+                        }
+                }
+                for (int e = 0; e < m * n; ++e) acc[e] *= alpha;
+                if (use_c) {
+                    int64_t tc = find_block(cin, i, j);
+                    if (tc >= 0) {
+                        const double *cb = cin->values + coff[tc];
+                        for (int e = 0; e < m * n; ++e) acc[e] += beta * cb[e];
+                    }
+                }
+                if (keep_block(acc, (int64_t)m * n, eps, norm_kind))
+                    if (rowbuf_push(&rows[i], j, acc, (int64_t)m * n) != ORC_OK) {
+#pragma omp atomic write
+                        status = ORC_ENOMEM;
+                    }
+            }
+        }
+        free(mark); free(acc);
+    }
+    if (status == ORC_OK)
+        status = assemble(out, a->nbrows, b->nbcols, a->rbs, b->cbs, rows);
+    free_rows(rows, a->nbrows);
+    free(aoff); free(boff); free(coff);
+    return status;
+}
+
+/* Filter a matrix on its own (same keep test as after a multiply). */
+int orc_filter(const omat *a, double eps, int norm_kind, omat *out)
+{
+    if (eps < 0) return ORC_EINVAL;
+    int64_t *off = block_offsets(a);
+    rowbuf *rows = (rowbuf *)calloc((size_t)(a->nbrows ? a->nbrows : 1), sizeof(rowbuf));
+    if (!off || !rows) { free(off); free(rows); return ORC_ENOMEM; }
+    int status = ORC_OK;
+    for (int32_t i = 0; i < a->nbrows && status == ORC_OK; ++i)
+        for (int64_t t = a->row_ptr[i]; t < a->row_ptr[i + 1]; ++t) {
+            int64_t len = off[t + 1] - off[t];
+            if (keep_block(a->values + off[t], len, eps, norm_kind))
+                status = rowbuf_push(&rows[i], a->col_idx[t], a->values + off[t], len);
+        }
+    if (status == ORC_OK)
+        status = assemble(out, a->nbrows, a->nbcols, a->rbs, a->cbs, rows);
+    free_rows(rows, a->nbrows);
+    free(off);
+    return status;
+}
+
+/* --------------------------------------------------- whole-matrix scalars */
+
+/* trace(A) for a square block matrix (DBCSR single-matrix operation). */
+double orc_trace(const omat *a)
+{
+    int64_t *off = block_offsets(a);
+    double tr = 0.0;
+    for (int32_t i = 0; i < a->nbrows; ++i) {
+        int64_t t = find_block(a, i, i);
+        if (t < 0) continue;
+        const int32_t m = a->rbs[i];
+        for (int r = 0; r < m; ++r) tr += a->values[off[t] + (int64_t)r * m + r];
+    }
+    free(off);
+    return tr;
+}
+
+/* ||A - shift*I||_F^2 with missing diagonal blocks counted as -shift*I. */
+double orc_sqdist_identity(const omat *a, double shift)
+{
+    int64_t *off = block_offsets(a);
+    double s = 0.0;
+    for (int32_t i = 0; i < a->nbrows; ++i) {
+        const int32_t m = a->rbs[i];
+        int have_diag = 0;
+        for (int64_t t = a->row_ptr[i]; t < a->row_ptr[i + 1]; ++t) {
+            const int32_t j = a->col_idx[t];
+            const int32_t n = a->cbs[j];
+            const double *x = a->values + off[t];
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < n; ++c) {
+                    double v = x[r * n + c] - ((j == i && r == c) ? shift : 0.0);
+                    s += v * v;
+                }
+            if (j == i) have_diag = 1;
+        }
+        if (!have_diag) s += (double)m * shift * shift;
+    }
+    free(off);
+    return s;
+}
+
+/* max over scalar rows of sum |a_rc| of (A - mu*I): the infinity norm. */
+double orc_inf_norm_shifted(const omat *a, double mu)
+{
+    int64_t *off = block_offsets(a);
+    double best = 0.0;
+    for (int32_t i = 0; i < a->nbrows; ++i) {
+        const int32_t m = a->rbs[i];
+        for (int r = 0; r < m; ++r) {
+            double s = 0.0;
+            int have_diag = 0;
+            for (int64_t t = a->row_ptr[i]; t < a->row_ptr[i + 1]; ++t) {
+                const int32_t j = a->col_idx[t];
+                const int32_t n = a->cbs[j];
+                const double *x = a->values + off[t] + (int64_t)r * n;
+                for (int c = 0; c < n; ++c)
+                    s += fabs(x[c] - ((j == i && c == r) ? mu : 0.0));
+                if (j == i) have_diag = 1;
+            }
+            if (!have_diag) s += fabs(mu);
+            if (s > best) best = s;
+        }
+    }
+    free(off);
+    return best;
+}
+
+/*
+ * out = scale * (A - mu*I), inserting a diagonal block where one is missing
+ * (needed for the shifted start X_0 of the sign iteration).
+ */
+int orc_shift_scale(const omat *a, double mu, double scale, omat *out)
+{
+    for (int32_t i = 0; i < a->nbrows; ++i) if (a->rbs[i] < 1 || a->rbs[i] > 64) return ORC_EINVAL;
+    for (int32_t j = 0; j < a->nbcols; ++j) if (a->cbs[j] < 1 || a->cbs[j] > 64) return ORC_EINVAL;
+    int64_t *off = block_offsets(a);
+    rowbuf *rows = (rowbuf *)calloc((size_t)(a->nbrows ? a->nbrows : 1), sizeof(rowbuf));
+    double *tmp = (double *)malloc(sizeof(double) * 64 * 64);
+    if (!off || !rows || !tmp) { free(off); free(rows); free(tmp); return ORC_ENOMEM; }
+    int status = ORC_OK;
+    for (int32_t i = 0; i < a->nbrows && status == ORC_OK; ++i) {
+        const int32_t m = a->rbs[i];
+        int64_t t = a->row_ptr[i];
+        int done_diag = 0;
+        for (;;) {
+            int32_t j = (t < a->row_ptr[i + 1]) ? a->col_idx[t] : a->nbcols;
+            if (!done_diag && j > i) {          /* missing diagonal block */
+                for (int e = 0; e < m * m; ++e) tmp[e] = 0.0;
+                for (int r = 0; r < m; ++r) tmp[r * m + r] = -scale * mu;
+                status = rowbuf_push(&rows[i], i, tmp, (int64_t)m * m);
+                done_diag = 1;
+                if (status != ORC_OK) break;
+            }
+            if (t >= a->row_ptr[i + 1]) break;
+            const int32_t n = a->cbs[j];
+            for (int e = 0; e < m * n; ++e) tmp[e] = scale * a->values[off[t] + e];
+            if (j == i) {
+                for (int r = 0; r < m; ++r) tmp[r * m + r] = scale * (a->values[off[t] + (int64_t)r * m + r] - mu);
+                done_diag = 1;
+            }
+            status = rowbuf_push(&rows[i], j, tmp, (int64_t)m * n);
+            if (status != ORC_OK) break;
+            ++t;
+        }
+    }
+    if (status == ORC_OK)
+        status = assemble(out, a->nbrows, a->nbcols, a->rbs, a->cbs, rows);
+    free_rows(rows, a->nbrows);
+    free(off); free(tmp);
+    return status;
+}
+
+/* ------------------------------------------------------- sign iteration */
+
+typedef struct {
+    int32_t iterations;     /* number of X updates performed */
+    int32_t n_multiplies;
+    double r_hist[128];     /* r_k = ||X_k^2 - I||_F / n for k = 0..iterations */
+    double scale;           /* s = ||H - mu I||_inf */
+    double trace_x;
+    double trace_p;         /* (n - trace X) / 2 */
+    double flops;           /* sum over products of 2 m n k */
+} orc_sign_stats;
+
+static double product_flops(const omat *a, const omat *b)
+{
+    double f = 0.0;
+    for (int32_t i = 0; i < a->nbrows; ++i)
+        for (int64_t ta = a->row_ptr[i]; ta < a->row_ptr[i + 1]; ++ta) {
+            int32_t k = a->col_idx[ta];
+            for (int64_t tb = b->row_ptr[k]; tb < b->row_ptr[k + 1]; ++tb)
+                f += 2.0 * a->rbs[i] * a->cbs[k] * b->cbs[b->col_idx[tb]];
+        }
+    return f;
+}
+
+/*
+ * Matrix sign by the second-order Newton-Schulz iteration, and the density
+ * matrix P = (I - sign(H - mu I)) / 2 with S = I (Sign-Method section,
+ * Eq. signdef, the density-matrix relation, and the first refinement function
+ * f_1(Z) = Z(3 - Y)/2 of the OT/IR paragraph, with Y = Z^2 for a symmetric
+ * Z and S = I):
+ *
+ *   s   = ||H - mu I||_inf               (scaling so the spectrum is in [-1, 1])
+ *   X_0 = (H - mu I) / s                 (not filtered)
+ *   for k = 0, 1, ...:
+ *       Y   = filter(X_k X_k)
+ *       r_k = ||Y - I||_F / n            (n = scalar dimension)
+ *       stop if r_k < tol                 (or after fixed_iters updates)
+ *       X_{k+1} = filter(1.5 X_k - 0.5 X_k Y)
+ *
+ * Filtering after every product follows the Sign-Method section.  Returns the
+ * last X (whose square was tested).  ORC_ENOCONV when r_k is not finite, when
+ * r_k >= r_{k-1} three times in a row, or when max_iter updates did not reach
+ * tol.
+ */
+int orc_sign_ns(const omat *h, double mu, double eps, int norm_kind, double tol,
+                int32_t max_iter, int32_t fixed_iters, omat *x_out, orc_sign_stats *st)
+{
+    if (h->nbrows != h->nbcols || eps < 0 || max_iter < 0 || max_iter > 120 ||
+        fixed_iters < 0 || fixed_iters > 120)
+        return ORC_EINVAL;
+    for (int32_t i = 0; i < h->nbrows; ++i) if (h->rbs[i] != h->cbs[i]) return ORC_EINVAL;
+    memset(st, 0, sizeof(*st));
+    double n = 0.0;
+    for (int32_t i = 0; i < h->nbrows; ++i) n += h->rbs[i];
+
+    double s = orc_inf_norm_shifted(h, mu);
+    st->scale = s;
+    if (!isfinite(s)) return ORC_ENONFINITE;
+    if (s == 0.0) return ORC_ENOCONV;
+    omat x = {0}, y = {0}, xn = {0};
+    int status = orc_shift_scale(h, mu, 1.0 / s, &x);
+    if (status != ORC_OK) return status;
+    int stall = 0;
+    for (int32_t k = 0;; ++k) {
+        st->flops += product_flops(&x, &x);
+        status = orc_multiply(1.0, &x, &x, 0.0, NULL, eps, norm_kind, &y);
+        st->n_multiplies++;
+        if (status != ORC_OK) break;
+        double r = sqrt(orc_sqdist_identity(&y, 1.0)) / n;
+        st->r_hist[k] = r;
+        st->iterations = k;
+        if (!isfinite(r)) { status = ORC_ENONFINITE; break; }
+        if (fixed_iters > 0) {
+            if (k == fixed_iters) break;
+        } else {
+            if (r < tol) break;
+            if (k > 0 && r >= st->r_hist[k - 1]) { if (++stall >= 3) { status = ORC_ENOCONV; break; } }
+            else stall = 0;
+            if (k == max_iter) { status = ORC_ENOCONV; break; }
+        }
+        st->flops += product_flops(&x, &y);
+        status = orc_multiply(-0.5, &x, &y, 1.5, &x, eps, norm_kind, &xn);
+        st->n_multiplies++;
+        orc_free(&y);
+        if (status != ORC_OK) break;
+        orc_free(&x);
+        x = xn;
+        memset(&xn, 0, sizeof(xn));
+    }
+    orc_free(&y);
+    if (status == ORC_OK || status == ORC_ENOCONV) {
+        st->trace_x = orc_trace(&x);
+        st->trace_p = 0.5 * (n - st->trace_x);
+    }
+    *x_out = x;
+    return status;
+}
+
+/* P = (I - X)/2 as a new matrix (inserts missing diagonal blocks). */
+int orc_density_from_sign(const omat *x, omat *p)
+{
+    /* (I - X)/2 = -0.5 * (X - 1*I) */
+    return orc_shift_scale(x, 1.0, -0.5, p);
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

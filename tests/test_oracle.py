@@ -1,0 +1,396 @@
+"""Pins for the CPU oracle: it is checked here against things other than itself
+(dense brute force, eigen-decomposition, closed forms, invariants, the
+polynomials printed in the paper).  All CPU-only."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from synth import BSR
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ helpers
+
+def _rand_case(rng, nbr, nbk, nbc, maxb, dens_a, dens_b, dens_c):
+    rs = rng.integers(1, maxb + 1, nbr)
+    ks = rng.integers(1, maxb + 1, nbk)
+    cs = rng.integers(1, maxb + 1, nbc)
+    a = synth.random_bsr(nbr, nbk, rs, ks, dens_a, rng)
+    b = synth.random_bsr(nbk, nbc, ks, cs, dens_b, rng)
+    c = synth.random_bsr(nbr, nbc, rs, cs, dens_c, rng)
+    return a, b, c
+
+
+def _blocks(m: BSR):
+    """dict (i, j) -> dense block, built independently of the oracle."""
+    out = {}
+    off = 0
+    for i in range(m.nbrows):
+        for t in range(m.row_ptr[i], m.row_ptr[i + 1]):
+            j = int(m.col_idx[t])
+            r, c = int(m.row_blk_size[i]), int(m.col_blk_size[j])
+            out[(i, j)] = m.values[off:off + r * c].reshape(r, c)
+            off += r * c
+    return out
+
+
+def _expected_product(alpha, a, b, beta, c, eps, norm):
+    """Dense brute force: D = alpha A B + beta C, pattern by set logic, filter."""
+    d = alpha * (a.to_dense() @ b.to_dense())
+    if beta != 0.0 and c is not None:
+        d = d + beta * c.to_dense()
+    pa, pb = a.pattern(), b.pattern()
+    rows_of_k = {}
+    for (k, j) in pb:
+        rows_of_k.setdefault(k, set()).add(j)
+    s = set()
+    for (i, k) in pa:
+        for j in rows_of_k.get(k, ()):
+            s.add((i, j))
+    if beta != 0.0 and c is not None:
+        s |= c.pattern()
+    ro = np.concatenate([[0], np.cumsum(a.row_blk_size)])
+    co = np.concatenate([[0], np.cumsum(b.col_blk_size)])
+    kept, border = {}, 0
+    for (i, j) in s:
+        blk = d[ro[i]:ro[i + 1], co[j]:co[j + 1]]
+        if norm == "frob":
+            v, thr = float((blk * blk).sum()), eps * eps
+        else:
+            v, thr = float(np.abs(blk).max()), eps
+        if thr > 0 and abs(v - thr) <= 1e-9 * thr:
+            border += 1
+        if not (v < thr):
+            kept[(i, j)] = blk
+    return d, s, kept, border
+
+
+def _rel(x, y):
+    ny = np.linalg.norm(y)
+    return np.linalg.norm(x - y) / (ny if ny > 0 else 1.0)
+
+
+# ---------------------------------------------------------------- multiply
+
+CASES = []
+_rng = np.random.default_rng(1234)
+for _ in range(40):
+    CASES.append(dict(
+        nbr=int(_rng.integers(1, 7)), nbk=int(_rng.integers(1, 7)), nbc=int(_rng.integers(1, 7)),
+        maxb=int(_rng.choice([1, 5, 13, 32])),
+        dens=tuple(float(x) for x in _rng.choice([0.0, 0.3, 0.7, 1.0], 3)),
+        alpha=float(_rng.choice([1.0, -0.5, 2.5, 0.0])),
+        beta=float(_rng.choice([0.0, 1.0, 1.5, -0.5])),
+        eps_q=float(_rng.choice([0.0, 0.3, 0.6])),
+        norm=str(_rng.choice(["frob", "maxabs"])),
+        seed=int(_rng.integers(0, 2**31)),
+    ))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"c{i}" for i in range(len(CASES))])
+def test_multiply_matches_dense_bruteforce(orc, case):
+    rng = np.random.default_rng(case["seed"])
+    a, b, c = _rand_case(rng, case["nbr"], case["nbk"], case["nbc"], case["maxb"], *case["dens"])
+    alpha, beta, norm = case["alpha"], case["beta"], case["norm"]
+    # choose eps between block norms of the unfiltered product, away from ties
+    _, _, unf, _ = _expected_product(alpha, a, b, beta, c, 0.0, norm)
+    eps = 0.0
+    if case["eps_q"] > 0 and unf:
+        if norm == "frob":
+            vals = sorted(float(np.sqrt((x * x).sum())) for x in unf.values())
+        else:
+            vals = sorted(float(np.abs(x).max()) for x in unf.values())
+        q = int(case["eps_q"] * (len(vals) - 1))
+        eps = vals[q] * 1.0000001 if vals[q] > 0 else 0.0
+    d, s, kept, border = _expected_product(alpha, a, b, beta, c, eps, norm)
+    assert border == 0
+    got = orc.multiply(alpha, a, b, beta, c, eps=eps, norm=norm)
+    got.check()
+    assert got.pattern() == set(kept.keys())
+    gb = _blocks(got)
+    for key, blk in kept.items():
+        assert _rel(gb[key], blk) <= 1e-13, key
+
+
+def test_multiply_full_832(orc):
+    a, b = synth.random_bsr_pair(64, 13, 0.2, seed=0)
+    d, s, kept, _ = _expected_product(1.0, a, b, 0.0, None, 0.0, "frob")
+    got = orc.multiply(1.0, a, b)
+    assert got.pattern() == s == set(kept.keys())
+    assert _rel(got.to_dense(), d) <= 1e-13
+
+
+def test_multiply_edge_cases(orc):
+    rng = np.random.default_rng(7)
+    a, b, c = _rand_case(rng, 4, 3, 5, 6, 0.0, 0.5, 0.5)   # empty A
+    got = orc.multiply(1.0, a, b)
+    assert got.nnzb == 0 and got.values.size == 0
+    got = orc.multiply(1.0, a, b, 2.0, c)                   # C = 2 Cin
+    assert got.pattern() == c.pattern()
+    assert np.array_equal(got.to_dense(), 2.0 * c.to_dense())
+    a, b, c = _rand_case(rng, 3, 3, 3, 4, 1.0, 1.0, 0.0)
+    got = orc.multiply(0.0, a, b)                           # alpha = 0 keeps the zero blocks
+    assert got.nnzb == 9 and not np.any(got.values)
+    with pytest.raises(RuntimeError):
+        orc.multiply(1.0, a, c if c.nbrows != a.nbcols else
+                     synth.random_bsr(3, 3, 9, 9, 1.0, rng))  # block-size mismatch
+    with pytest.raises(RuntimeError):
+        orc.multiply(1.0, a, b, eps=-1.0)
+
+
+# ------------------------------------------------------------------ filter
+
+@pytest.mark.parametrize("norm", ["frob", "maxabs"])
+def test_filter_rule(orc, norm):
+    rng = np.random.default_rng(3)
+    m = synth.random_bsr(8, 8, rng.integers(1, 9, 8), rng.integers(1, 9, 8), 0.6, rng)
+    m.values *= np.repeat(rng.uniform(0.0, 2.0, m.nnzb) ** 6,
+                          np.diff(m.block_offsets()))
+    for eps in [0.0, 0.05, 0.5, 3.0]:
+        got = orc.filter(m, eps, norm)
+        keep = set()
+        for key, blk in _blocks(m).items():
+            v = float((blk * blk).sum()) if norm == "frob" else float(np.abs(blk).max())
+            if not (v < (eps * eps if norm == "frob" else eps)):
+                keep.add(key)
+        assert got.pattern() == keep
+        gb, mb = _blocks(got), _blocks(m)
+        for key in keep:
+            assert np.array_equal(gb[key], mb[key])
+
+
+def test_block_sqnorms(orc):
+    rng = np.random.default_rng(4)
+    m = synth.random_bsr(5, 6, rng.integers(1, 30, 5), rng.integers(1, 30, 6), 0.5, rng)
+    ref = [float((blk * blk).sum()) for blk in _blocks(m).values()]
+    assert np.allclose(orc.block_sqnorms(m), ref, rtol=1e-14, atol=0)
+
+
+# ---------------------------------------------------- whole-matrix scalars
+
+def test_scalars_vs_dense(orc):
+    rng = np.random.default_rng(5)
+    sizes = rng.integers(1, 12, 9)
+    m = synth.random_bsr(9, 9, sizes, sizes, 0.4, rng)
+    d = m.to_dense()
+    n = d.shape[0]
+    assert orc.trace(m) == pytest.approx(np.trace(d), rel=1e-14, abs=1e-14)
+    for shift in [0.0, 1.0, -2.5]:
+        assert orc.sqdist_identity(m, shift) == pytest.approx(
+            np.linalg.norm(d - shift * np.eye(n)) ** 2, rel=1e-13)
+        assert orc.inf_norm_shifted(m, shift) == pytest.approx(
+            np.abs(d - shift * np.eye(n)).sum(1).max(), rel=1e-14)
+    sc = orc.shift_scale(m, 0.7, 0.25)
+    assert np.allclose(sc.to_dense(), 0.25 * (d - 0.7 * np.eye(n)), rtol=0, atol=1e-15)
+    assert all((i, i) in sc.pattern() for i in range(9))
+
+
+# ---------------------------------------------------------- sign iteration
+
+def _read_polys():
+    polys = {}
+    with open(os.path.join(GOLDEN, "sign_polynomials.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            name, order, coef, den = [x.strip() for x in line.split("|")]
+            polys[name] = (int(order), [float(x) for x in coef.split()], float(den))
+    return polys
+
+
+def test_golden_polynomials_are_sign_iterations():
+    """Closed form: g(x) = x q(x^2)/den has g(1) = 1 and g'(x) = c (1-x^2)^(p-1)."""
+    for name, (order, coef, den) in _read_polys().items():
+        # g(x) as a polynomial in x
+        g = np.zeros(2 * len(coef))
+        for p, cf in enumerate(coef):
+            g[2 * p + 1] = cf / den
+        gp = np.polynomial.polynomial.polyder(g)
+        target = np.polynomial.polynomial.polypow([1.0, 0.0, -1.0], order - 1)
+        ratio = gp[0] / target[0]
+        assert np.allclose(gp, ratio * target[:gp.size], atol=1e-12), name
+        assert np.polynomial.polynomial.polyval(1.0, g) == pytest.approx(1.0, abs=1e-14)
+        assert ratio > 0
+
+
+def _diag_matrix(vals, sizes):
+    """Block-diagonal BSR whose blocks are diagonal matrices."""
+    sizes = np.asarray(sizes, dtype=np.int32)
+    nb = sizes.size
+    blocks, p = [], 0
+    for s in sizes:
+        blk = np.zeros((s, s))
+        blk[np.arange(s), np.arange(s)] = vals[p:p + s]
+        p += s
+        blocks.append(blk.ravel())
+    return BSR(sizes, sizes, np.arange(nb + 1), np.arange(nb), np.concatenate(blocks))
+
+
+def test_sign_diagonal_scalar_recurrence(orc):
+    """Diagonal H: the iteration decouples into the scalar f_1 recurrence,
+    evaluated here in the same operation order, so X must agree bit for bit."""
+    rng = np.random.default_rng(11)
+    sizes = rng.integers(1, 7, 10)
+    n = int(sizes.sum())
+    h = rng.uniform(0.05, 5.0, n) * rng.choice([-1.0, 1.0], n)
+    mu = 0.01
+    tol = 1e-9
+    m = _diag_matrix(h, sizes)
+    x_got, st, status = orc.sign_ns(m, mu=mu, eps=0.0, tol=tol)
+    assert status == orc.OK
+    x = (h - mu) * (1.0 / np.abs(h - mu).max())
+    rs = []
+    for k in range(100):
+        y = x * x
+        r = math.sqrt(float(((y - 1.0) ** 2).sum())) / n
+        rs.append(r)
+        if r < tol:
+            break
+        x = -0.5 * (x * y) + 1.5 * x
+    assert st["iterations"] == k
+    assert np.allclose(st["r_hist"], rs, rtol=1e-13, atol=0)
+    assert np.array_equal(np.diag(x_got.to_dense()), x)
+    # same result through the printed polynomial f_1 = x (3 - x^2)/2
+    order, coef, den = _read_polys()["f1"]
+    xp = (h - mu) * (1.0 / np.abs(h - mu).max())
+    for _ in range(k):
+        y = xp * xp
+        xp = xp * (coef[0] + coef[1] * y) / den
+    assert np.allclose(xp, x, rtol=0, atol=1e-14)
+    assert st["trace_p"] == pytest.approx(0.5 * (n - x.sum()), abs=1e-12)
+
+
+def _eig_sign(d, mu=0.0):
+    w, v = np.linalg.eigh(d - mu * np.eye(d.shape[0]))
+    return (v * np.sign(w)) @ v.T, int((w < 0).sum())
+
+
+def _dense_to_bsr(d, sizes, keep_frac=1.0, rng=None):
+    sizes = np.asarray(sizes, dtype=np.int32)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    nb = sizes.size
+    rp, ci, vals = [0], [], []
+    for i in range(nb):
+        for j in range(nb):
+            blk = d[off[i]:off[i + 1], off[j]:off[j + 1]]
+            if np.any(blk):
+                ci.append(j)
+                vals.append(blk.ravel())
+        rp.append(len(ci))
+    return BSR(sizes, sizes, np.array(rp), np.array(ci), np.concatenate(vals))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_sign_matches_eigh_dense(orc, seed):
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(1, 14, 8)
+    n = int(sizes.sum())
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = rng.uniform(0.1, 3.0, n) * rng.choice([-1.0, 1.0], n)
+    d = (q * lam) @ q.T
+    d = 0.5 * (d + d.T)
+    m = _dense_to_bsr(d, sizes)
+    x, st, status = orc.sign_ns(m, mu=0.0, eps=0.0, tol=1e-13)
+    assert status == orc.OK
+    ref, nneg = _eig_sign(d)
+    dx = x.to_dense()
+    assert _rel(dx, ref) <= 1e-12
+    assert np.linalg.norm(dx - dx.T) / np.linalg.norm(dx) < 1e-12
+    assert st["trace_p"] == pytest.approx(nneg, abs=1e-9)
+
+
+def test_sign_2x2_closed_form(orc):
+    """sign(M) = (2M - tr(M) I)/sqrt(tr^2 - 4 det) when det < 0, else +-I."""
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        a, b, c = rng.normal(size=3) * 3
+        mm = np.array([[a, b], [b, c]])
+        tr, det = a + c, a * c - b * b
+        if abs(det) < 1e-3:
+            continue
+        ref = (2 * mm - tr * np.eye(2)) / math.sqrt(tr * tr - 4 * det) if det < 0 \
+            else np.sign(tr) * np.eye(2)
+        for sizes in ([2], [1, 1]):
+            x, st, status = orc.sign_ns(_dense_to_bsr(mm, sizes), tol=1e-14)
+            assert status == orc.OK
+            assert np.allclose(x.to_dense(), ref, rtol=0, atol=1e-13)
+
+
+def test_sign_neighbour_hamiltonian_vs_eigh(orc):
+    h = synth.neighbour_hamiltonian(64, 5, cutoff=4.0, seed=3)
+    x, st, status = orc.sign_ns(h, eps=0.0, tol=1e-12)
+    assert status == orc.OK
+    ref, nneg = _eig_sign(h.to_dense())
+    assert nneg == h.meta["n_occ"]
+    assert _rel(x.to_dense(), ref) <= 1e-11
+    assert st["trace_p"] == pytest.approx(h.meta["n_occ"], abs=1e-8)
+
+
+def test_sign_block_diagonal_vs_eigh(orc):
+    """Cutoff below every pair distance: each diagonal block on its own."""
+    h = synth.neighbour_hamiltonian(40, 7, cutoff=0.05, seed=2)
+    assert h.meta["n_pairs"] == 0
+    x, st, status = orc.sign_ns(h, eps=0.0, tol=1e-13)
+    assert status == orc.OK
+    xb = _blocks(x)
+    for (i, j), blk in _blocks(h).items():
+        ref, _ = _eig_sign(blk)
+        assert np.allclose(xb[(i, j)], ref, rtol=0, atol=1e-12)
+
+
+def test_sign_with_filter_invariants(orc):
+    h = synth.neighbour_hamiltonian(200, 5, cutoff=6.0, seed=4)
+    tol = 1e-7
+    x, st, status = orc.sign_ns(h, eps=1e-6, tol=tol)
+    assert status == orc.OK
+    n = h.shape[0]
+    d = x.to_dense()
+    # X Y and Y X differ once Y is filtered, so symmetry only holds to O(eps)
+    assert np.linalg.norm(d - d.T) / np.linalg.norm(d) < 1e-5
+    assert np.linalg.norm(d @ d - np.eye(n)) / n < 10 * tol
+    assert st["trace_p"] == pytest.approx(h.meta["n_occ"], abs=1e-3)
+    ref, _ = _eig_sign(h.to_dense())
+    assert _rel(d, ref) < 1e-4
+    # a coarse filter drops blocks, and r_k (taken on the filtered square)
+    # still reaches tol while the exact residual stays at the filter's level
+    x, st, status = orc.sign_ns(h, eps=1e-3, tol=1e-5)
+    assert status == orc.OK and x.nnzb < h.nbrows ** 2
+    d = x.to_dense()
+    assert np.linalg.norm(d @ d - np.eye(n)) / n < 1e-3
+    assert st["trace_p"] == pytest.approx(h.meta["n_occ"], abs=1e-2)
+
+
+def test_sign_fixed_iters(orc):
+    h = synth.neighbour_hamiltonian(64, 5, cutoff=4.0, seed=5)
+    x3, st3, s3 = orc.sign_ns(h, fixed_iters=3)
+    assert s3 == orc.OK and st3["iterations"] == 3 and len(st3["r_hist"]) == 4
+    x, st, s = orc.sign_ns(h, tol=0.0, max_iter=3)
+    assert s == orc.ENOCONV
+    assert np.array_equal(x.values, x3.values)
+
+
+def test_sign_failure_modes(orc):
+    sizes = np.array([2, 3])
+    vals = np.array([1.0, -2.0, 0.0, 3.0, 0.5])       # an eigenvalue exactly at mu = 0
+    x, st, status = orc.sign_ns(_diag_matrix(vals, sizes), tol=1e-10)
+    assert status == orc.ENOCONV
+    vals = np.array([1.0, -2.0, np.nan, 3.0, 0.5])
+    x, st, status = orc.sign_ns(_diag_matrix(vals, sizes), tol=1e-10)
+    assert status == orc.ENONFINITE
+
+
+def test_density_matrix_identities(orc):
+    h = synth.neighbour_hamiltonian(64, 5, cutoff=4.0, seed=6)
+    x, st, _ = orc.sign_ns(h, tol=1e-8)
+    p = orc.density_from_sign(x)
+    n = h.shape[0]
+    dp, dx = p.to_dense(), x.to_dense()
+    assert np.allclose(dp, 0.5 * (np.eye(n) - dx), rtol=0, atol=1e-15)
+    lhs = np.linalg.norm(dp @ dp - dp)
+    assert lhs == pytest.approx(0.25 * np.linalg.norm(dx @ dx - np.eye(n)), rel=1e-6)
+    assert orc.trace(p) == pytest.approx(st["trace_p"], abs=1e-12)

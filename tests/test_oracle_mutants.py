@@ -1,0 +1,58 @@
+"""Plant plausible mistakes in copies of the oracle (on the CPU) and check
+that the pins in test_oracle.py catch every one of them."""
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "bsm_oracle.c")
+
+# (name, original text, mutated text): each must occur exactly once.
+MUTANTS = [
+    ("alpha_sign", "acc[e] *= alpha;", "acc[e] *= -alpha;"),
+    ("beta_sign", "acc[e] += beta * cb[e];", "acc[e] -= beta * cb[e];"),
+    ("drop_cin_pattern", "mark[cin->col_idx[tc]] = 1;", "(void)tc;"),
+    ("filter_threshold", "return !(s < eps * eps);", "return !(s < eps);"),
+    ("filter_maxabs", "return !(mx < eps);", "return !(mx <= eps * 0.5);"),
+    ("mirrored_b", "acc[r * n + c] += av * bb[t * n + c];",
+     "acc[r * n + c] += av * bb[t * n + (n - 1 - c)];"),
+    ("a_row_index", "const double av = ab[r * kk + t];", "const double av = ab[(m - 1 - r) * kk + t];"),
+    ("ns_coefficient", "orc_multiply(-0.5, &x, &y, 1.5, &x,", "orc_multiply(-0.5, &x, &y, 1.25, &x,"),
+    ("ns_alpha", "orc_multiply(-0.5, &x, &y,", "orc_multiply(-0.45, &x, &y,"),
+    ("residual_norm", "double r = sqrt(orc_sqdist_identity(&y, 1.0)) / n;",
+     "double r = sqrt(orc_sqdist_identity(&y, 1.0) / n);"),
+    ("shift_sign", "tmp[r * m + r] = scale * (a->values[off[t] + (int64_t)r * m + r] - mu);",
+     "tmp[r * m + r] = scale * (a->values[off[t] + (int64_t)r * m + r] + mu);"),
+    ("inf_norm_abs", "s += fabs(x[c] - ((j == i && c == r) ? mu : 0.0));",
+     "s += (x[c] - ((j == i && c == r) ? mu : 0.0));"),
+    ("trace_p", "st->trace_p = 0.5 * (n - st->trace_x);", "st->trace_p = 0.5 * (n + st->trace_x);"),
+    ("skip_last_k", "for (int64_t ta = a->row_ptr[i]; ta < a->row_ptr[i + 1]; ++ta) {\n                    int32_t k",
+     "for (int64_t ta = a->row_ptr[i]; ta + 1 < a->row_ptr[i + 1]; ++ta) {\n                    int32_t k"),
+    ("stall_rule", "if (k == max_iter) { status = ORC_ENOCONV; break; }", "if (k == max_iter) { break; }"),
+]
+
+
+def _run_mutant(tmpdir, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    msrc = os.path.join(tmpdir, f"m_{name}.c")
+    mlib = os.path.join(tmpdir, f"m_{name}.so")
+    with open(msrc, "w") as f:
+        f.write(src.replace(old, new))
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                           "-shared", "-o", mlib, msrc, "-lm"])
+    env = dict(os.environ, BSM_ORACLE_LIB=mlib, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return name, r.returncode
+
+
+def test_every_planted_mistake_is_caught(tmp_path):
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        res = list(ex.map(lambda m: _run_mutant(str(tmp_path), *m), MUTANTS))
+    survivors = [name for name, rc in res if rc == 0]
+    assert not survivors, f"pins missed planted mistakes: {survivors}"
