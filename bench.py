@@ -1,0 +1,189 @@
+"""Benchmark: FP64 Newton-Schulz sign iteration on a synthetic neighbour-list
+Hamiltonian (2048 sites, one 23 x 23 block per site, cutoff 6 A at 0.1
+sites/A^3, eps_filter 1e-6, until ||X^2 - I||_F / n < 1e-6), run through the
+C ABI on one MI355X.
+
+One step = one whole pass of the path on the device-resident H: X_0 = H/s,
+every filtered block-sparse multiply of the iteration, convergence checks,
+P = (I - X)/2 and trace(P).  Prints ONE JSON line (rank 0):
+
+    value        algorithmic GFLOP/s of the block products over the whole step
+                 (sum of 2 m n k over executed block products / step time)
+    ms_per_step  time to the converged sign (+ P and its trace)
+    roofline     the block-product kernel: its flops / its HIP-event time vs
+                 the FP64 matrix-core peak of MI355X
+    cpu_baseline the CPU oracle on a bounded sample of the same workload
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--seed S]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 matrix (= FP64 vector) peak
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(h, rows: int):
+    """Oracle multiply of the first `rows` block rows of H by H (the first
+    product of the sign iteration), timed on the host cores."""
+    import numpy as np
+
+    import oracle
+    from synth import BSR
+    nnz = int(h.row_ptr[rows])
+    off = h.block_offsets()
+    sub = BSR(h.row_blk_size[:rows], h.col_blk_size, h.row_ptr[:rows + 1].copy(),
+              h.col_idx[:nnz].copy(), h.values[:off[nnz]].copy())
+    # algorithmic flops of the sample
+    rp, ci = h.row_ptr, h.col_idx
+    lens = np.diff(rp)
+    b = int(h.row_blk_size[0])
+    nprod = int(lens[ci[:nnz]].sum())
+    flops = 2.0 * b ** 3 * nprod
+    t0 = time.perf_counter()
+    oracle.multiply(1.0, sub, h, eps=1e-6)
+    dt = time.perf_counter() - t0
+    return dict(value=flops / dt / 1e9, unit="GFLOP/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"first {rows} of {h.nbrows} block rows of H*H (the first product of "
+                       f"the iteration), eps 1e-6, {flops / 1e9:.1f} GFLOP in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--sites", type=int, default=2048)
+    ap.add_argument("--eps", type=float, default=1e-6)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--cpu-rows", type=int, default=512)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
+                                   "sharding is a design (block rows of C per GPU), "
+                                   "not part of this build", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2003_03868_amd import bsm
+    bsm.load()
+    torch.cuda.set_device(0)
+
+    t0 = time.perf_counter()
+    h = synth.neighbour_hamiltonian(args.sites, 23, density=0.1, cutoff=6.0, seed=args.seed)
+    log(f"generated H: {h.nbrows} sites, {h.nnzb} blocks, n_occ {h.meta['n_occ']} "
+        f"({time.perf_counter() - t0:.1f} s)")
+    dh = bsm.Matrix.from_bsr(h, device=True)
+    torch.cuda.synchronize()
+
+    opts = bsm.bsm_sign_opts_default()
+    opts.eps_filter = args.eps
+    opts.tol = args.tol
+    stream = torch.cuda.current_stream()
+
+    def step():
+        st, xh, stats = bsm.bsm_sign_iterate(dh.handle, 0.0, opts, stream=stream)
+        if st != bsm.OK:
+            raise RuntimeError(f"sign iteration failed: {bsm.STATUS_NAMES[st]} "
+                               f"{bsm.bsm_last_error()}")
+        ph, tp = bsm.bsm_density_from_sign(xh, stream=stream)
+        bsm.bsm_destroy(ph)
+        bsm.bsm_destroy(xh)
+        return stats, tp
+
+    for w in range(args.warmup):
+        stats, tp = step()
+        log(f"warmup {w}: {stats.iterations} iterations, {stats.flops / 1e12:.2f} TFLOP, "
+            f"device {stats.device_ms:.0f} ms")
+
+    torch.cuda.synchronize()
+    times, all_stats = [], []
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        stats, tp = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        all_stats.append((stats, tp))
+        log(f"step {k}: {times[-1] * 1e3:.0f} ms, {stats.iterations} iterations, "
+            f"r={stats.r_hist[stats.iterations]:.2e}, trace(P)={tp:.6f}, "
+            f"smm {stats.smm_ms:.0f} ms, nnzb(X)={stats.nnzb_final}")
+    total = sum(times)
+    flops = sum(s.flops for s, _ in all_stats)
+    smm_ms = sum(s.smm_ms for s, _ in all_stats)
+    s0, tp0 = all_stats[-1]
+    ms_per_step = total / args.steps * 1e3
+    achieved = flops / (smm_ms * 1e-3) / 1e12 if smm_ms > 0 else 0.0
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle on a sample ...")
+        cpu = cpu_baseline(h, min(args.cpu_rows, h.nbrows))
+        log(f"cpu baseline: {cpu['value']:.2f} GFLOP/s on {cpu['cores']} threads")
+
+    n = float(h.shape[0])
+    out = {
+        "metric": "block-sparse multiply GFLOP/s (FP64 vs mixed); sign-iteration time to 1e-6",
+        "value": flops / total / 1e9,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "FP64 Newton-Schulz sign iteration, 2048-site neighbour-list "
+                        "Hamiltonian, 23x23 blocks, cutoff 6 A, 0.1 sites/A^3, "
+                        "eps_filter 1e-6, to ||X^2-I||_F/n < 1e-6",
+            "n_sites": h.nbrows, "block": 23, "n": int(n), "eps_filter": args.eps,
+            "tol": args.tol, "seed": args.seed, "nnzb_H": h.nnzb,
+        },
+        "time_to_sign_ms": ms_per_step,
+        "iterations": int(s0.iterations),
+        "multiplies": int(s0.n_multiplies),
+        "r_final": float(s0.r_hist[s0.iterations]),
+        "trace_p": float(tp0),
+        "n_occ": int(h.meta["n_occ"]),
+        "tflop_per_step": flops / args.steps / 1e12,
+        "products_per_step": int(sum(s.n_products for s, _ in all_stats) / args.steps),
+        "nnzb_X_final": int(s0.nnzb_final),
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "k_smm_f64_mfma",
+            "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": None,
+            "smm_ms_per_step": smm_ms / args.steps,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    dh.destroy()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * bsm -- block-sparse matrix multiply and Newton-Schulz sign iteration on
+ * AMD MI355X (gfx950).  C ABI: plain pointers and sizes, no C++ or torch
+ * types.  Every call returns a bsm_status; on failure the handles passed in
+ * are left unchanged and bsm_last_error() describes what went wrong.
+ *
+ * The operations follow the paper's statement of the problem:
+ *   - blocked compressed-sparse-row (blocked CSR) matrices whose block sizes
+ *     come from the atomic basis ("DBCSR library" section);
+ *   - C = alpha*A*B + beta*C computed as products of small dense blocks
+ *     ("Local multiplication" and "Batched execution" subsections);
+ *   - after each product, blocks below eps_filter are flushed to zero to keep
+ *     the matrix sparse ("Sign-Method" section);
+ *   - sign(A) = A (A^2)^{-1/2} (Sign-Method, Eq. signdef) by Newton-Schulz
+ *     iteration, and the density matrix P = (I - sign(H - mu I))/2 (the
+ *     density-matrix relation of the same section, with S = I).
+ *
+ * Matrix layout (host or device arrays, as the on_device flag says):
+ *   row_blk_size[nbrows], col_blk_size[nbcols]  int32, each in [1, 32],
+ *                                                always host arrays;
+ *   row_ptr[nbrows+1]  int64, row_ptr[0] = 0, non-decreasing, row_ptr[nbrows] = nnzb;
+ *   col_idx[nnzb]      int32, in [0, nbcols), strictly increasing in each row;
+ *   values             float64, the stored blocks concatenated in CSR order,
+ *                      block (i,j) row-major with row_blk_size[i] rows and
+ *                      col_blk_size[j] columns.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream).  Work is queued on it; calls that must learn a size computed on
+ * the device (the multiply, the filter, create from device arrays) wait for
+ * the stream before they return, and so do calls that return host values.
+ * Handles may be used from one thread at a time; a handle's memory lives on
+ * the device that was current when it was created.
+ *
+ * Filter rule (the paper flushes "elements smaller than eps_filter"; read
+ * here block by block): BSM_NORM_FROB drops block b iff sum(b_ij^2) <
+ * eps^2, BSM_NORM_MAXABS drops it iff max|b_ij| < eps.  eps = 0 drops
+ * nothing (exact-zero blocks are kept).
+ */
+#ifndef BSM_H
+#define BSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bsm_matrix_s *bsm_matrix;
+
+typedef enum {
+    BSM_OK = 0,
+    BSM_EINVAL = -1,      /* bad argument, non-canonical matrix, size mismatch */
+    BSM_ENOMEM = -2,      /* device allocation failed */
+    BSM_EDEVICE = -3,     /* a HIP runtime call failed */
+    BSM_ENOCONV = -4,     /* sign iteration did not reach tol */
+    BSM_ENONFINITE = -5,  /* NaN or Inf met in a norm */
+    BSM_ECAPACITY = -6    /* a fixed-capacity buffer was too small */
+} bsm_status;
+
+typedef enum {
+    BSM_FP64 = 0,        /* block products in FP64 */
+    BSM_FP32 = 1,        /* operands rounded to FP32, FP32 MFMA, FP32 accumulation per C block */
+    BSM_SPLIT_BF16 = 2   /* x = hi + lo in BF16, hi*hi + hi*lo + lo*hi on MFMA, FP32 accumulation */
+} bsm_precision;
+
+typedef enum { BSM_NORM_FROB = 0, BSM_NORM_MAXABS = 1 } bsm_norm;
+
+typedef struct {
+    int32_t nbrows, nbcols;
+    int64_t nnzb;        /* stored blocks */
+    int64_t nvalues;     /* stored scalars */
+    int64_t nrows, ncols;/* scalar dimensions */
+} bsm_info;
+
+typedef struct {
+    int64_t n_products;          /* block products A_ik*B_kj executed */
+    double flops;                /* sum over products of 2*m*n*k */
+    int64_t nnzb_unfiltered;     /* stored blocks of the product before the filter */
+    int64_t nnzb;                /* stored blocks of C after the filter */
+    double smm_ms;               /* device time of the block-product kernels (HIP events) */
+    double total_ms;             /* device time of the whole multiply (HIP events) */
+    int32_t smm_launches;        /* number of block-product kernel launches */
+    int32_t pad_;
+} bsm_mult_stats;
+
+typedef struct {
+    double eps_filter;       /* filter threshold after every product (>= 0) */
+    double tol;              /* stop when ||X^2 - I||_F / n < tol */
+    int32_t max_iter;        /* at most this many X updates (<= 120) */
+    int32_t fixed_iters;     /* > 0: exactly this many updates, tol ignored */
+    int32_t norm;            /* bsm_norm of the filter */
+    int32_t prec;            /* bsm_precision of the block products */
+    int32_t fp64_final_iters;/* mixed precision: last updates done in FP64 */
+    int32_t use_graph;       /* 1: replay captured iterations where possible */
+    double prec_switch_tol;  /* mixed precision: FP64 once r_k < this */
+} bsm_sign_opts;
+
+typedef struct {
+    int32_t iterations;      /* X updates performed */
+    int32_t n_multiplies;
+    double r_hist[128];      /* r_k = ||X_k^2 - I||_F / n, k = 0..iterations */
+    int32_t prec_hist[128];  /* precision of the products of update k */
+    double scale;            /* s = ||H - mu I||_inf used for X_0 = (H - mu I)/s */
+    double trace_x;          /* trace(X) of the returned iterate */
+    double trace_p;          /* trace(P) = (n - trace X)/2 */
+    double flops;            /* algorithmic flops of all block products */
+    int64_t n_products;
+    double smm_ms;           /* device time inside block-product kernels */
+    double device_ms;        /* device time from first to last kernel (HIP events) */
+    int64_t nnzb_final;      /* stored blocks of the returned X */
+    int32_t graph_replays;   /* iterations run by replaying a captured graph */
+    int32_t pad_;
+} bsm_sign_stats;
+
+/* Default options: eps 0, tol 1e-6, max_iter 100, FROB, FP64, no graph. */
+void bsm_sign_opts_default(bsm_sign_opts *opts);
+
+/*
+ * Create a matrix by copying the arrays described above (the library never
+ * aliases caller memory).  on_device = 1: row_ptr/col_idx/values are device
+ * pointers on the current device; 0: host pointers.  The matrix is checked
+ * for canonical form on the device; failures give BSM_EINVAL.  nnzb may be 0
+ * (then row_ptr is all zeros and col_idx/values may be NULL).
+ */
+int bsm_create(bsm_matrix *out, int32_t nbrows, int32_t nbcols,
+               const int32_t *row_blk_size, const int32_t *col_blk_size,
+               int64_t nnzb, const int64_t *row_ptr, const int32_t *col_idx,
+               const double *values, int on_device, void *stream);
+
+/* Free the handle and its device memory (queued on the handle's last stream). */
+int bsm_destroy(bsm_matrix m);
+
+/* Sizes of the matrix (host values). */
+int bsm_get_info(bsm_matrix m, bsm_info *info);
+
+/*
+ * Copy the matrix out into caller arrays of the sizes bsm_get_info gives
+ * (row_ptr[nbrows+1], col_idx[nnzb], values[nvalues]); any pointer may be
+ * NULL to skip that array.  on_device as in bsm_create.  Waits for the stream.
+ */
+int bsm_export(bsm_matrix m, int64_t *row_ptr, int32_t *col_idx, double *values,
+               int on_device, void *stream);
+
+/*
+ * C = alpha * A * B + beta * C, then the filter (DBCSR multiply; Sign-Method
+ * filtering).  The stored pattern of the result is every (i,j) with some k
+ * having A_ik and B_kj stored, together with C's old pattern when beta != 0;
+ * with beta == 0 C's old contents are ignored.  Blocks failing the filter
+ * are then removed.  C is replaced (new pattern and values); it may be the
+ * same handle as A or B.  A's column block sizes must equal B's row block
+ * sizes, and C's block sizes must be A's rows by B's columns (BSM_EINVAL).
+ * prec selects the arithmetic of the block products (bsm_precision); the
+ * result, norms and filter are always FP64.  stats may be NULL.
+ * BSM_ENONFINITE if a result block holds NaN or Inf (C is still replaced).
+ */
+int bsm_multiply(double alpha, bsm_matrix A, bsm_matrix B, double beta, bsm_matrix C,
+                 double eps_filter, int32_t norm, int32_t prec,
+                 bsm_mult_stats *stats, void *stream);
+
+/* Apply the filter to a matrix in place (same rule as after a multiply). */
+int bsm_filter(bsm_matrix m, double eps_filter, int32_t norm, void *stream);
+
+/*
+ * Squared Frobenius norm of every stored block, in storage order, into the
+ * device array out_dev[nnzb] (FP64; one wavefront reduction per block).
+ */
+int bsm_block_norms(bsm_matrix m, double *out_dev, void *stream);
+
+/* trace(A) of a square block matrix (FP64, fixed summation order). Waits. */
+int bsm_trace(bsm_matrix m, double *out, void *stream);
+
+/* ||A - shift*I||_F^2 (missing diagonal blocks count as -shift*I). Waits. */
+int bsm_sqdist_identity(bsm_matrix m, double shift, double *out, void *stream);
+
+/*
+ * out = scale * (A - mu*I) as a new handle (missing diagonal blocks are
+ * inserted).  Also gives P = (I - X)/2 with mu = 1, scale = -1/2.
+ */
+int bsm_shift_scale(bsm_matrix A, double mu, double scale, bsm_matrix *out, void *stream);
+
+/* max over scalar rows of sum_j |(A - mu I)_ij| (FP64). Waits. */
+int bsm_inf_norm(bsm_matrix A, double mu, double *out, void *stream);
+
+/*
+ * Matrix sign of H - mu*I by second-order Newton-Schulz iteration
+ * (Sign-Method section; Eq. signdef; the refinement function f_1 of the
+ * OT/IR paragraph, X <- X(3I - X^2)/2):
+ *   s = ||H - mu I||_inf;  X_0 = (H - mu I)/s;
+ *   loop k: Y = filter(X_k X_k); r_k = ||Y - I||_F / n; stop if r_k < tol;
+ *           X_{k+1} = filter(1.5 X_k - 0.5 X_k Y).
+ * The returned X (new handle in *x_out, caller destroys) is the iterate
+ * whose square was tested.  stats may be NULL.  BSM_ENOCONV if r_k is not
+ * finite, grows three times in a row, or max_iter is reached (X is still
+ * returned); BSM_ENONFINITE for NaN/Inf in H.
+ */
+int bsm_sign_iterate(bsm_matrix H, double mu, const bsm_sign_opts *opts,
+                     bsm_matrix *x_out, bsm_sign_stats *stats, void *stream);
+
+/* P = (I - X)/2 from a sign matrix X, as a new handle; trace_p (may be NULL) gets trace(P). */
+int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *bsm_last_error(void);
+
+/* Library version string. */
+const char *bsm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSM_H */

@@ -1,0 +1,260 @@
+// C-ABI entry points of libbsm (declared in include/bsm.h).
+#include <algorithm>
+#include <cstring>
+
+#include "bsm_internal.h"
+
+namespace bsm {
+const char *last_error();
+int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sign_stats *st,
+                 hipStream_t s);
+}  // namespace bsm
+
+using bsm::Mat;
+
+struct bsm_matrix_s {
+    Mat m;
+};
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+static int check_sizes(int32_t n, const int32_t *sz, const char *what) {
+    if (n < 0) { bsm::set_error("%s: negative block count", what); return BSM_EINVAL; }
+    if (n > 0 && sz == nullptr) { bsm::set_error("%s: block sizes missing", what); return BSM_EINVAL; }
+    for (int32_t i = 0; i < n; ++i)
+        if (sz[i] < 1 || sz[i] > bsm::kMaxBlock) {
+            bsm::set_error("%s: block size %d at %d outside [1, %d]", what, sz[i], i, bsm::kMaxBlock);
+            return BSM_EINVAL;
+        }
+    return BSM_OK;
+}
+
+static int upload_sizes(Mat &m, const int32_t *rbs, const int32_t *cbs, hipStream_t s) {
+    m.h_rbs.assign(rbs, rbs + m.nbrows);
+    m.h_cbs.assign(cbs, cbs + m.nbcols);
+    std::vector<int64_t> ro(m.nbrows + 1, 0), co(m.nbcols + 1, 0);
+    for (int32_t i = 0; i < m.nbrows; ++i) ro[i + 1] = ro[i] + rbs[i];
+    for (int32_t j = 0; j < m.nbcols; ++j) co[j + 1] = co[j] + cbs[j];
+    m.nrows = ro[m.nbrows];
+    m.ncols = co[m.nbcols];
+    m.max_rbs = m.nbrows ? *std::max_element(rbs, rbs + m.nbrows) : 1;
+    m.max_cbs = m.nbcols ? *std::max_element(cbs, cbs + m.nbcols) : 1;
+    m.uni_r = (m.nbrows && std::all_of(rbs, rbs + m.nbrows, [&](int32_t x) { return x == rbs[0]; })) ? rbs[0] : 0;
+    m.uni_c = (m.nbcols && std::all_of(cbs, cbs + m.nbcols, [&](int32_t x) { return x == cbs[0]; })) ? cbs[0] : 0;
+    BSM_TRY(bsm::dalloc(&m.rbs, m.nbrows, s));
+    BSM_TRY(bsm::dalloc(&m.cbs, m.nbcols, s));
+    BSM_TRY(bsm::dalloc(&m.roff, m.nbrows + 1, s));
+    BSM_TRY(bsm::dalloc(&m.coff, m.nbcols + 1, s));
+    if (m.nbrows) BSM_HIP(hipMemcpyAsync(m.rbs, rbs, sizeof(int32_t) * m.nbrows, hipMemcpyHostToDevice, s));
+    if (m.nbcols) BSM_HIP(hipMemcpyAsync(m.cbs, cbs, sizeof(int32_t) * m.nbcols, hipMemcpyHostToDevice, s));
+    BSM_HIP(hipMemcpyAsync(m.roff, ro.data(), sizeof(int64_t) * ro.size(), hipMemcpyHostToDevice, s));
+    BSM_HIP(hipMemcpyAsync(m.coff, co.data(), sizeof(int64_t) * co.size(), hipMemcpyHostToDevice, s));
+    // the host vectors above die at return: make the copies complete first
+    BSM_HIP(hipStreamSynchronize(s));
+    return BSM_OK;
+}
+
+extern "C" {
+
+void bsm_sign_opts_default(bsm_sign_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->eps_filter = 0.0;
+    o->tol = 1e-6;
+    o->max_iter = 100;
+    o->fixed_iters = 0;
+    o->norm = BSM_NORM_FROB;
+    o->prec = BSM_FP64;
+    o->fp64_final_iters = 2;
+    o->use_graph = 0;
+    o->prec_switch_tol = 1e-4;
+}
+
+int bsm_create(bsm_matrix *out, int32_t nbrows, int32_t nbcols, const int32_t *row_blk_size,
+               const int32_t *col_blk_size, int64_t nnzb, const int64_t *row_ptr,
+               const int32_t *col_idx, const double *values, int on_device, void *stream) {
+    bsm::clear_error();
+    if (!out) { bsm::set_error("out is NULL"); return BSM_EINVAL; }
+    BSM_TRY(check_sizes(nbrows, row_blk_size, "row_blk_size"));
+    BSM_TRY(check_sizes(nbcols, col_blk_size, "col_blk_size"));
+    if (nnzb < 0 || (nbrows == 0 && nnzb != 0)) { bsm::set_error("bad nnzb"); return BSM_EINVAL; }
+    if (row_ptr == nullptr && nbrows > 0) { bsm::set_error("row_ptr is NULL"); return BSM_EINVAL; }
+    if (nnzb > 0 && (col_idx == nullptr || values == nullptr)) { bsm::set_error("col_idx/values NULL"); return BSM_EINVAL; }
+    hipStream_t s = as_stream(stream);
+    auto *h = new bsm_matrix_s;
+    Mat &m = h->m;
+    int st = hipGetDevice(&m.device) == hipSuccess ? BSM_OK : BSM_EDEVICE;
+    m.nbrows = nbrows;
+    m.nbcols = nbcols;
+    m.nnzb = nnzb;
+    m.stream = s;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (st == BSM_OK) st = upload_sizes(m, row_blk_size, col_blk_size, s);
+    if (st == BSM_OK) st = bsm::dalloc(&m.row_ptr, nbrows + 1, s);
+    if (st == BSM_OK) st = bsm::dalloc(&m.col_idx, nnzb, s);
+    if (st == BSM_OK) {
+        hipError_t e = hipSuccess;
+        if (nbrows > 0) e = hipMemcpyAsync(m.row_ptr, row_ptr, sizeof(int64_t) * (nbrows + 1), kind, s);
+        else e = hipMemsetAsync(m.row_ptr, 0, sizeof(int64_t), s);
+        if (e == hipSuccess && nnzb > 0) e = hipMemcpyAsync(m.col_idx, col_idx, sizeof(int32_t) * nnzb, kind, s);
+        if (e != hipSuccess) { bsm::set_error("create: copy failed: %s", hipGetErrorString(e)); st = BSM_EDEVICE; }
+    }
+    if (st == BSM_OK) st = bsm::validate_pattern(m, s);
+    if (st == BSM_OK) st = bsm::compute_blk_off(m, s);
+    if (st == BSM_OK) {
+        int64_t nv = 0;
+        hipError_t e = hipMemcpyAsync(&nv, m.blk_off + nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { bsm::set_error("create: %s", hipGetErrorString(e)); st = BSM_EDEVICE; }
+        m.nvalues = nv;
+    }
+    if (st == BSM_OK) st = bsm::dalloc(&m.values, m.nvalues, s);
+    if (st == BSM_OK && m.nvalues > 0) {
+        hipError_t e = hipMemcpyAsync(m.values, values, sizeof(double) * m.nvalues, kind, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { bsm::set_error("create: values copy failed: %s", hipGetErrorString(e)); st = BSM_EDEVICE; }
+    }
+    if (st != BSM_OK) {
+        bsm::free_mat_arrays(m, s);
+        bsm::dfree(m.rbs, s); bsm::dfree(m.cbs, s); bsm::dfree(m.roff, s); bsm::dfree(m.coff, s);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return BSM_OK;
+}
+
+int bsm_destroy(bsm_matrix h) {
+    bsm::clear_error();
+    if (!h) return BSM_OK;
+    Mat &m = h->m;
+    hipStream_t s = m.stream;
+    bsm::free_mat_arrays(m, s);
+    bsm::dfree(m.rbs, s); bsm::dfree(m.cbs, s); bsm::dfree(m.roff, s); bsm::dfree(m.coff, s);
+    delete h;
+    return BSM_OK;
+}
+
+int bsm_get_info(bsm_matrix h, bsm_info *info) {
+    bsm::clear_error();
+    if (!h || !info) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    const Mat &m = h->m;
+    info->nbrows = m.nbrows; info->nbcols = m.nbcols;
+    info->nnzb = m.nnzb; info->nvalues = m.nvalues;
+    info->nrows = m.nrows; info->ncols = m.ncols;
+    return BSM_OK;
+}
+
+int bsm_export(bsm_matrix h, int64_t *row_ptr, int32_t *col_idx, double *values, int on_device,
+               void *stream) {
+    bsm::clear_error();
+    if (!h) { bsm::set_error("NULL handle"); return BSM_EINVAL; }
+    Mat &m = h->m;
+    hipStream_t s = as_stream(stream);
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (row_ptr) BSM_HIP(hipMemcpyAsync(row_ptr, m.row_ptr, sizeof(int64_t) * (m.nbrows + 1), kind, s));
+    if (col_idx && m.nnzb) BSM_HIP(hipMemcpyAsync(col_idx, m.col_idx, sizeof(int32_t) * m.nnzb, kind, s));
+    if (values && m.nvalues) BSM_HIP(hipMemcpyAsync(values, m.values, sizeof(double) * m.nvalues, kind, s));
+    BSM_HIP(hipStreamSynchronize(s));
+    return BSM_OK;
+}
+
+int bsm_multiply(double alpha, bsm_matrix A, bsm_matrix B, double beta, bsm_matrix C,
+                 double eps_filter, int32_t norm, int32_t prec, bsm_mult_stats *stats,
+                 void *stream) {
+    bsm::clear_error();
+    if (!A || !B || !C) { bsm::set_error("NULL handle"); return BSM_EINVAL; }
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    return bsm::multiply(alpha, A->m, B->m, beta, C->m, eps_filter, norm, prec, stats,
+                         as_stream(stream));
+}
+
+int bsm_filter(bsm_matrix h, double eps, int32_t norm, void *stream) {
+    bsm::clear_error();
+    if (!h) { bsm::set_error("NULL handle"); return BSM_EINVAL; }
+    if (!(eps >= 0.0) || !std::isfinite(eps)) { bsm::set_error("eps_filter must be finite and >= 0"); return BSM_EINVAL; }
+    if (norm != BSM_NORM_FROB && norm != BSM_NORM_MAXABS) { bsm::set_error("unknown norm"); return BSM_EINVAL; }
+    hipStream_t s = as_stream(stream);
+    int st = bsm::filter_inplace(h->m, eps, norm, s);
+    h->m.stream = s;
+    return st;
+}
+
+int bsm_block_norms(bsm_matrix h, double *out_dev, void *stream) {
+    bsm::clear_error();
+    if (!h || (!out_dev && h->m.nnzb)) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    return bsm::block_sqnorms(h->m, out_dev, as_stream(stream));
+}
+
+int bsm_trace(bsm_matrix h, double *out, void *stream) {
+    bsm::clear_error();
+    if (!h || !out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    return bsm::trace(h->m, out, as_stream(stream));
+}
+
+int bsm_sqdist_identity(bsm_matrix h, double shift, double *out, void *stream) {
+    bsm::clear_error();
+    if (!h || !out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    return bsm::sqdist_identity(h->m, shift, out, as_stream(stream));
+}
+
+int bsm_inf_norm(bsm_matrix h, double mu, double *out, void *stream) {
+    bsm::clear_error();
+    if (!h || !out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    return bsm::inf_norm(h->m, mu, out, as_stream(stream));
+}
+
+int bsm_shift_scale(bsm_matrix A, double mu, double scale, bsm_matrix *out, void *stream) {
+    bsm::clear_error();
+    if (!A || !out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    Mat *m = nullptr;
+    BSM_TRY(bsm::shift_scale(A->m, mu, scale, &m, as_stream(stream)));
+    auto *h = new bsm_matrix_s;
+    h->m = std::move(*m);
+    delete m;
+    *out = h;
+    return BSM_OK;
+}
+
+int bsm_sign_iterate(bsm_matrix H, double mu, const bsm_sign_opts *opts, bsm_matrix *x_out,
+                     bsm_sign_stats *stats, void *stream) {
+    bsm::clear_error();
+    if (!H || !x_out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    bsm_sign_opts o;
+    if (opts) o = *opts; else bsm_sign_opts_default(&o);
+    bsm_sign_stats local;
+    bsm_sign_stats *st = stats ? stats : &local;
+    std::memset(st, 0, sizeof(*st));
+    Mat *x = nullptr;
+    int rc = bsm::sign_iterate(H->m, mu, o, &x, st, as_stream(stream));
+    if (x) {
+        auto *h = new bsm_matrix_s;
+        h->m = std::move(*x);
+        delete x;
+        *x_out = h;
+    }
+    return rc;
+}
+
+int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void *stream) {
+    bsm::clear_error();
+    if (!X || !p_out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    hipStream_t s = as_stream(stream);
+    Mat *m = nullptr;
+    BSM_TRY(bsm::shift_scale(X->m, 1.0, -0.5, &m, s));
+    if (trace_p) {
+        int st = bsm::trace(*m, trace_p, s);
+        if (st != BSM_OK) { bsm::free_mat(m, s); return st; }
+    }
+    auto *h = new bsm_matrix_s;
+    h->m = std::move(*m);
+    delete m;
+    *p_out = h;
+    return BSM_OK;
+}
+
+const char *bsm_last_error(void) { return bsm::last_error(); }
+
+const char *bsm_version(void) { return "bsm 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal declarations shared by the bsm HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bsm.h"
+
+namespace bsm {
+
+constexpr int kMaxBlock = 32;          // largest supported block edge
+constexpr int kWave = 64;              // CDNA wavefront width
+constexpr int kXcds = 8;               // MI355X: 8 accelerator complex dies
+
+// Device-resident blocked-CSR matrix.  All pointers are device memory.
+struct Mat {
+    int device = 0;
+    int32_t nbrows = 0, nbcols = 0;
+    int64_t nnzb = 0, nvalues = 0, nrows = 0, ncols = 0;
+    std::vector<int32_t> h_rbs, h_cbs;       // host copies of the block sizes
+    int32_t max_rbs = 0, max_cbs = 0;
+    int32_t uni_r = 0, uni_c = 0;            // uniform block size, 0 if mixed
+    int32_t *rbs = nullptr, *cbs = nullptr;  // [nbrows], [nbcols]
+    int64_t *roff = nullptr, *coff = nullptr;// scalar offsets [nb+1]
+    int64_t *row_ptr = nullptr;              // [nbrows+1]
+    int32_t *col_idx = nullptr;              // [nnzb]
+    int64_t *blk_off = nullptr;              // [nnzb+1] value offsets
+    double *values = nullptr;                // [nvalues]
+    hipStream_t stream = nullptr;            // last stream the handle was used on
+};
+
+// ------------------------------------------------------------ error state
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define BSM_HIP(expr)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess) {                                                \
+            ::bsm::set_error("%s failed: %s (%s:%d)", #expr,                   \
+                             hipGetErrorString(e_), __FILE__, __LINE__);       \
+            return BSM_EDEVICE;                                                \
+        }                                                                      \
+    } while (0)
+
+#define BSM_TRY(expr)                                                          \
+    do {                                                                       \
+        int s_ = (expr);                                                       \
+        if (s_ != BSM_OK) return s_;                                           \
+    } while (0)
+
+// --------------------------------------------------------------- memory
+// Stream-ordered device allocations (hipMallocAsync on the default pool,
+// whose release threshold is raised so memory is cached between calls).
+int dalloc_bytes(void **p, size_t bytes, hipStream_t s);
+void dfree(void *p, hipStream_t s);
+template <class T>
+inline int dalloc(T **p, size_t n, hipStream_t s) {
+    return dalloc_bytes(reinterpret_cast<void **>(p), n * sizeof(T), s);
+}
+
+void free_mat_arrays(Mat &m, hipStream_t s);   // values/pattern (not sizes)
+void free_mat(Mat *m, hipStream_t s);
+
+// ------------------------------------------------------------- helpers
+inline unsigned grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > (1ll << 30)) g = 1ll << 30;
+    return static_cast<unsigned>(g);
+}
+
+// Exclusive scan of n int64 values into out[0..n]; out[n] = total.
+// `in` and `out` may alias.  Work space is allocated on the stream.
+int scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+
+// Block value offsets blk_off[nnzb+1] from row_ptr/col_idx/block sizes.
+int compute_blk_off(Mat &m, hipStream_t s);
+
+// Device check of canonical form; returns BSM_EINVAL with a message.
+int validate_pattern(const Mat &m, hipStream_t s);
+
+// ---------------------------------------------------------- multiply core
+struct MultiplyPlan;   // opaque per-call state (multiply.hip)
+
+int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps,
+             int norm, int prec, bsm_mult_stats *stats, hipStream_t s);
+int filter_inplace(Mat &m, double eps, int norm, hipStream_t s);
+
+// Reductions (reduce.hip)
+int block_sqnorms(const Mat &m, double *out, hipStream_t s);
+int trace(const Mat &m, double *out, hipStream_t s);
+int sqdist_identity(const Mat &m, double shift, double *out, hipStream_t s);
+int inf_norm(const Mat &m, double mu, double *out, hipStream_t s);
+int shift_scale(const Mat &a, double mu, double scale, Mat **out, hipStream_t s);
+int copy_mat(const Mat &a, Mat **out, hipStream_t s);
+int alloc_like_sizes(const Mat &proto_rows, const Mat &proto_cols, Mat **out, hipStream_t s);
+
+// Compaction kernels shared by multiply and filter (filter.hip)
+int compact_by_norm(Mat &m, const double *sq, const double *mx, double eps, int norm,
+                    hipStream_t s, int64_t *nnzb_after);
+
+}  // namespace bsm

@@ -1,0 +1,257 @@
+// C = alpha*A*B + beta*C with the norm filter: the device pipeline.
+//
+//   1. count     per C block row: C blocks, C scalars, products, flops
+//   2. scans     row pointers of C and of the product list (device), then one
+//                wait to learn the sizes
+//   3. pattern   C col_idx / owning row / matching C_in block
+//   4. offsets   C block value offsets (device scan)
+//   5. per chunk of block rows (bounded product count, like the paper's
+//                bounded batches): product stacks, then the block products
+//   6. filter    drop blocks failing the norm test and compact (device)
+//
+// C's old arrays stay alive until everything that reads them is queued, so C
+// may be the same handle as A or B.
+#include <algorithm>
+#include <vector>
+
+#include "smm.h"
+#include "symbolic.h"
+
+namespace bsm {
+
+// Products per chunk: bounds the stack memory (8 bytes per product).
+// BSM_CHUNK_PRODUCTS overrides it (tests use a small value to force chunks).
+static int64_t chunk_products() {
+    const char *e = getenv("BSM_CHUNK_PRODUCTS");
+    const long long x = e ? atoll(e) : 0;
+    return x > 0 ? static_cast<int64_t>(x) : (int64_t{1} << 27);
+}
+
+namespace {
+struct Events {
+    bool on = false;
+    hipEvent_t t0{}, t1{};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> smm;
+    ~Events() {
+        if (!on) return;
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+        for (auto &p : smm) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+    }
+};
+struct Scratch {
+    hipStream_t s;
+    std::vector<void *> ptrs;
+    explicit Scratch(hipStream_t st) : s(st) {}
+    template <class T>
+    int get(T **p, size_t n) {
+        int st = dalloc(p, n, s);
+        if (st == BSM_OK) ptrs.push_back(*p);
+        return st;
+    }
+    ~Scratch() { for (void *p : ptrs) dfree(p, s); }
+};
+}  // namespace
+
+static int check_shapes(const Mat &A, const Mat &B, const Mat &C) {
+    if (A.nbcols != B.nbrows || C.nbrows != A.nbrows || C.nbcols != B.nbcols) {
+        set_error("block grids do not match: A %dx%d, B %dx%d, C %dx%d", A.nbrows, A.nbcols,
+                  B.nbrows, B.nbcols, C.nbrows, C.nbcols);
+        return BSM_EINVAL;
+    }
+    if (A.h_cbs != B.h_rbs) { set_error("A column block sizes differ from B row block sizes"); return BSM_EINVAL; }
+    if (C.h_rbs != A.h_rbs || C.h_cbs != B.h_cbs) {
+        set_error("C block sizes must be A's row sizes by B's column sizes");
+        return BSM_EINVAL;
+    }
+    if (B.nbcols > kMaxBlockCols) {
+        set_error("at most %d block columns are supported (got %d)", kMaxBlockCols, B.nbcols);
+        return BSM_EINVAL;
+    }
+    if (A.nnzb >= (int64_t{1} << 31) || B.nnzb >= (int64_t{1} << 31)) {
+        set_error("operands with 2^31 or more stored blocks are not supported");
+        return BSM_EINVAL;
+    }
+    return BSM_OK;
+}
+
+int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int norm, int prec,
+             bsm_mult_stats *stats, hipStream_t s) {
+    BSM_TRY(check_shapes(A, B, C));
+    if (!(eps >= 0.0) || !std::isfinite(eps)) { set_error("eps_filter must be finite and >= 0"); return BSM_EINVAL; }
+    if (norm != BSM_NORM_FROB && norm != BSM_NORM_MAXABS) { set_error("unknown norm %d", norm); return BSM_EINVAL; }
+    if (prec != BSM_FP64 && prec != BSM_FP32 && prec != BSM_SPLIT_BF16) { set_error("unknown precision %d", prec); return BSM_EINVAL; }
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) { set_error("alpha and beta must be finite"); return BSM_EINVAL; }
+
+    const int32_t nbr = A.nbrows;
+    const bool use_c = (beta != 0.0) && C.nnzb > 0;
+    Events ev;
+    if (stats) {
+        ev.on = true;
+        BSM_HIP(hipEventCreate(&ev.t0));
+        BSM_HIP(hipEventCreate(&ev.t1));
+        BSM_HIP(hipEventRecord(ev.t0, s));
+    }
+    Scratch tmp(s);
+
+    SymArgs sa{};
+    sa.nbrows = nbr; sa.nbcols = B.nbcols;
+    sa.a_row_ptr = A.row_ptr; sa.a_col_idx = A.col_idx;
+    sa.b_row_ptr = B.row_ptr; sa.b_col_idx = B.col_idx;
+    sa.k_size = A.cbs; sa.c_rbs = A.rbs; sa.c_cbs = B.cbs;
+    sa.use_c = use_c ? 1 : 0;
+    sa.c_in_row_ptr = use_c ? C.row_ptr : nullptr;
+    sa.c_in_col_idx = use_c ? C.col_idx : nullptr;
+
+    // 1-2. counts and scans
+    int64_t *c_row_ptr = nullptr, *c_nval = nullptr, *p_row_ptr = nullptr;
+    double *flops_row = nullptr;
+    BSM_TRY(dalloc(&c_row_ptr, nbr + 1, s));      // becomes the new C's row_ptr
+    int st = tmp.get(&c_nval, nbr + 1);
+    if (st == BSM_OK) st = tmp.get(&p_row_ptr, nbr + 1);
+    if (st == BSM_OK) st = tmp.get(&flops_row, nbr + 1);
+    if (st == BSM_OK) st = sym_count(sa, c_row_ptr, c_nval, p_row_ptr, flops_row, s);
+    if (st == BSM_OK) st = scan_i64(c_row_ptr, c_row_ptr, nbr, s);
+    if (st == BSM_OK) st = scan_i64(c_nval, c_nval, nbr, s);
+    if (st == BSM_OK) st = scan_i64(p_row_ptr, p_row_ptr, nbr, s);
+    std::vector<int64_t> h_crp(nbr + 1), h_prp(nbr + 1);
+    std::vector<double> h_flops(nbr);
+    int64_t nval_c = 0;
+    if (st == BSM_OK) {
+        hipError_t e = hipMemcpyAsync(h_crp.data(), c_row_ptr, sizeof(int64_t) * (nbr + 1), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(h_prp.data(), p_row_ptr, sizeof(int64_t) * (nbr + 1), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && nbr) e = hipMemcpyAsync(h_flops.data(), flops_row, sizeof(double) * nbr, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&nval_c, c_nval + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { set_error("multiply: reading sizes failed: %s", hipGetErrorString(e)); st = BSM_EDEVICE; }
+    }
+    if (st != BSM_OK) { dfree(c_row_ptr, s); return st; }
+    const int64_t nnzb_c = h_crp[nbr];
+    const int64_t nprod = h_prp[nbr];
+    double flops = 0.0;
+    for (double f : h_flops) flops += f;
+
+    // 3-4. pattern and value offsets of the new C
+    Mat nc;
+    nc.nbrows = nbr; nc.nbcols = B.nbcols; nc.rbs = A.rbs; nc.cbs = B.cbs;
+    nc.row_ptr = c_row_ptr;
+    nc.nnzb = nnzb_c;
+    nc.nvalues = nval_c;
+    int32_t *c_row = nullptr;
+    int64_t *cin_map = nullptr;
+    double *sq = nullptr, *mx = nullptr;
+    int *flags = nullptr;
+    st = dalloc(&nc.col_idx, nnzb_c, s);
+    if (st == BSM_OK) st = dalloc(&nc.values, nval_c, s);
+    if (st == BSM_OK) st = tmp.get(&c_row, nnzb_c);
+    if (st == BSM_OK && use_c) st = tmp.get(&cin_map, nnzb_c);
+    if (st == BSM_OK) st = tmp.get(&sq, nnzb_c);
+    if (st == BSM_OK) st = tmp.get(&mx, nnzb_c);
+    if (st == BSM_OK) st = tmp.get(&flags, 1);
+    if (st == BSM_OK) {
+        hipError_t e = hipMemsetAsync(flags, 0, sizeof(int), s);
+        if (e != hipSuccess) { set_error("memset: %s", hipGetErrorString(e)); st = BSM_EDEVICE; }
+    }
+    if (st == BSM_OK) st = sym_pattern(sa, c_row_ptr, nc.col_idx, c_row, cin_map, s);
+    if (st == BSM_OK) st = compute_blk_off(nc, s);
+
+    // 5. chunks of block rows with a bounded number of products
+    std::vector<int32_t> cuts{0};
+    {
+        const int64_t lim = chunk_products();
+        int32_t r0 = 0;
+        while (r0 < nbr) {
+            int32_t r1 = r0 + 1;
+            while (r1 < nbr && h_prp[r1 + 1] - h_prp[r0] <= lim) ++r1;
+            cuts.push_back(r1);
+            r0 = r1;
+        }
+    }
+    int64_t max_p = 0, max_c = 0;
+    for (size_t q = 0; q + 1 < cuts.size(); ++q) {
+        max_p = std::max(max_p, h_prp[cuts[q + 1]] - h_prp[cuts[q]]);
+        max_c = std::max(max_c, h_crp[cuts[q + 1]] - h_crp[cuts[q]]);
+    }
+    int64_t *seg = nullptr;
+    int32_t *stk_a = nullptr, *stk_b = nullptr;
+    if (st == BSM_OK) st = tmp.get(&seg, max_c + 1);
+    if (st == BSM_OK) st = tmp.get(&stk_a, max_p);
+    if (st == BSM_OK) st = tmp.get(&stk_b, max_p);
+
+    SmmArgs ma{};
+    ma.c_row = c_row; ma.c_col = nc.col_idx; ma.c_blk_off = nc.blk_off; ma.c_vals = nc.values;
+    ma.c_rbs = A.rbs; ma.c_cbs = B.cbs;
+    ma.a_col_idx = A.col_idx; ma.a_blk_off = A.blk_off; ma.a_vals = A.values; ma.k_size = A.cbs;
+    ma.b_blk_off = B.blk_off; ma.b_vals = B.values;
+    ma.cin_map = cin_map;
+    ma.cin_blk_off = use_c ? C.blk_off : nullptr;
+    ma.cin_vals = use_c ? C.values : nullptr;
+    ma.alpha = alpha; ma.beta = beta;
+    ma.sq_out = sq; ma.mx_out = mx; ma.flags = flags;
+    ma.max_m = A.max_rbs; ma.max_n = B.max_cbs; ma.max_k = A.max_cbs;
+    ma.prec = prec;
+    ma.seg = seg; ma.stk_a = stk_a; ma.stk_b = stk_b;
+
+    for (size_t q = 0; st == BSM_OK && q + 1 < cuts.size(); ++q) {
+        const int32_t r0 = cuts[q], r1 = cuts[q + 1];
+        ma.c0 = h_crp[r0];
+        ma.nC = h_crp[r1] - h_crp[r0];
+        if (ma.nC == 0) continue;
+        st = sym_stack(sa, r0, r1, c_row_ptr, p_row_ptr, seg, stk_a, stk_b, s);
+        if (st != BSM_OK) break;
+        std::pair<hipEvent_t, hipEvent_t> pe{};
+        if (ev.on) {
+            BSM_HIP(hipEventCreate(&pe.first));
+            BSM_HIP(hipEventCreate(&pe.second));
+            BSM_HIP(hipEventRecord(pe.first, s));
+        }
+        st = smm_launch(ma, 0, s);
+        if (ev.on) {
+            BSM_HIP(hipEventRecord(pe.second, s));
+            ev.smm.push_back(pe);
+        }
+    }
+
+    // 6. filter
+    int64_t nnzb_after = nnzb_c;
+    if (st == BSM_OK && eps > 0.0) st = compact_by_norm(nc, sq, mx, eps, norm, s, &nnzb_after);
+    int h_flags = 0;
+    if (st == BSM_OK) {
+        hipError_t e = hipMemcpyAsync(&h_flags, flags, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (ev.on && e == hipSuccess) e = hipEventRecord(ev.t1, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { set_error("multiply: %s", hipGetErrorString(e)); st = BSM_EDEVICE; }
+    }
+    if (st != BSM_OK) {
+        dfree(nc.row_ptr, s); dfree(nc.col_idx, s); dfree(nc.blk_off, s); dfree(nc.values, s);
+        return st;
+    }
+
+    // swap the new arrays into C (old ones are freed in stream order)
+    free_mat_arrays(C, s);
+    C.row_ptr = nc.row_ptr; C.col_idx = nc.col_idx; C.blk_off = nc.blk_off; C.values = nc.values;
+    C.nnzb = nc.nnzb; C.nvalues = nc.nvalues;
+    C.stream = s;
+
+    if (stats) {
+        stats->n_products = nprod;
+        stats->flops = flops;
+        stats->nnzb_unfiltered = nnzb_c;
+        stats->nnzb = nnzb_after;
+        stats->smm_launches = static_cast<int32_t>(ev.smm.size());
+        float ms = 0.f;
+        double smm = 0.0;
+        for (auto &p : ev.smm) {
+            if (hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess) smm += ms;
+        }
+        stats->smm_ms = smm;
+        stats->total_ms = (hipEventElapsedTime(&ms, ev.t0, ev.t1) == hipSuccess) ? ms : 0.0;
+    }
+    if (h_flags & kFlagNonFinite) {
+        set_error("a product block holds NaN or Inf");
+        return BSM_ENONFINITE;
+    }
+    return BSM_OK;
+}
+
+}  // namespace bsm

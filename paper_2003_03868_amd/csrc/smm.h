@@ -1,0 +1,40 @@
+// Numeric phase (product-stack execution); see smm.hip.
+#pragma once
+
+#include "bsm_internal.h"
+
+namespace bsm {
+
+constexpr int kFlagNonFinite = 1;
+
+struct SmmArgs {
+    int64_t c0;                 // first C block of this launch
+    int64_t nC;                 // C blocks in this launch
+    const int64_t *seg;         // [nC+1] product segments, launch-relative
+    const int32_t *stk_a;       // A block index per product
+    const int32_t *stk_b;       // B block index per product
+    const int32_t *c_row;       // block row of every C block
+    const int32_t *c_col;       // block column of every C block
+    const int64_t *c_blk_off;   // value offset of every C block
+    double *c_vals;             // C values (written)
+    const int32_t *c_rbs, *c_cbs;
+    const int32_t *a_col_idx;
+    const int64_t *a_blk_off;
+    const double *a_vals;
+    const int32_t *k_size;      // A column block sizes
+    const int64_t *b_blk_off;
+    const double *b_vals;
+    const int64_t *cin_map;     // C_in block of every C block or -1; NULL when beta == 0
+    const int64_t *cin_blk_off;
+    const double *cin_vals;
+    double alpha, beta;
+    double *sq_out;             // sum of squares of every C block
+    double *mx_out;             // max |x| of every C block
+    int *flags;                 // kFlagNonFinite
+    int32_t max_m, max_n, max_k;
+    int32_t prec;               // bsm_precision
+};
+
+int smm_launch(const SmmArgs &a, int variant, hipStream_t s);
+
+}  // namespace bsm

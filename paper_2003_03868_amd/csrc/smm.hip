@@ -1,0 +1,163 @@
+// Numeric phase of the block-sparse multiply: execute the product stacks.
+//
+// The paper's GPU driver runs batches of small dense block products
+// C_blk += A_blk * B_blk with coalesced loads ("Batched execution"
+// subsection).  Here the batches are C-stationary: one wavefront owns one C
+// block, walks its segment of products (ascending k), keeps the sum in
+// registers and writes alpha*sum + beta*C_in once, together with the block's
+// squared Frobenius norm and max |x| for the filter.  No atomics, fixed
+// summation order.
+//
+// FP64 path: the block products run on the CDNA matrix cores with
+// V_MFMA_F64_16X16X4_F64; a C block of up to 32 x 32 is a 2 x 2 grid of
+// 16 x 16 accumulator tiles.  Operand blocks are staged through LDS with
+// contiguous (coalesced) global loads, then read in MFMA operand layout.
+#include "smm.h"
+
+namespace bsm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Work item of workgroup g: consecutive items go to the same XCD (the
+// hardware hands workgroup g to XCD g % 8), so C blocks of one block row --
+// which read the same A blocks -- share that XCD's L2.
+__device__ inline int64_t xcd_item(int64_t n_items) {
+    const int64_t per = (n_items + kXcds - 1) / kXcds;
+    return static_cast<int64_t>(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+
+__device__ inline double wave_sum(double v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Shared epilogue: v = alpha*acc + beta*C_in, store, and the block norms.
+template <int MT, int NT>
+__device__ inline void store_c_block(const SmmArgs &a, int64_t c, int m, int n,
+                                     const double (&acc)[MT][NT][4]) {
+    const int lane = threadIdx.x;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int64_t co = a.c_blk_off[c];
+    const double *cin = nullptr;
+    if (a.cin_map) {
+        const int64_t t = a.cin_map[c];
+        if (t >= 0) cin = a.cin_vals + a.cin_blk_off[t];
+    }
+    double sq = 0.0, mx = 0.0;
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = ti * 16 + 4 * kq + q, col = tj * 16 + r16;
+                if (row < m && col < n) {
+                    double v = a.alpha * acc[ti][tj][q];
+                    if (cin) v += a.beta * cin[row * n + col];
+                    a.c_vals[co + row * n + col] = v;
+                    sq += v * v;
+                    mx = fmax(mx, fabs(v));
+                }
+            }
+    sq = wave_sum(sq);
+    mx = wave_max(mx);
+    if (lane == 0) {
+        a.sq_out[c] = sq;
+        a.mx_out[c] = mx;
+        if (!isfinite(sq)) atomicOr(a.flags, kFlagNonFinite);
+    }
+}
+
+// FP64 MFMA kernel.  MT, NT: maximum number of 16-row / 16-column tiles
+// (1 or 2); tiles beyond the block's own m, n are skipped (wave-uniform).
+template <int MT, int NT>
+__global__ void __launch_bounds__(64)
+k_smm_f64_mfma(SmmArgs a) {
+    extern __shared__ double sm[];
+    const int64_t item = xcd_item(a.nC);
+    if (item >= a.nC) return;
+    const int lane = threadIdx.x;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int64_t c = a.c0 + item;
+    const int m = a.c_rbs[a.c_row[c]], n = a.c_cbs[a.c_col[c]];
+    const int mt = (m + 15) >> 4, nt = (n + 15) >> 4;
+    double *sA = sm;
+    double *sB = sm + a.max_m * a.max_k;
+
+    d4 acc[MT][NT];
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int64_t p_end = a.seg[item + 1];
+    for (int64_t p = a.seg[item]; p < p_end; ++p) {
+        const int32_t ta = a.stk_a[p], tb = a.stk_b[p];
+        const int k = a.k_size[a.a_col_idx[ta]];
+        const double *ga = a.a_vals + a.a_blk_off[ta];
+        const double *gb = a.b_vals + a.b_blk_off[tb];
+        for (int e = lane; e < m * k; e += kWave) sA[e] = ga[e];
+        for (int e = lane; e < k * n; e += kWave) sB[e] = gb[e];
+        __syncthreads();
+        for (int ks = 0; ks < k; ks += 4) {
+            const int kk = ks + kq;
+            double av[MT], bv[NT];
+#pragma unroll
+            for (int ti = 0; ti < MT; ++ti) {
+                const int r = ti * 16 + r16;
+                av[ti] = (r < m && kk < k) ? sA[r * k + kk] : 0.0;
+            }
+#pragma unroll
+            for (int tj = 0; tj < NT; ++tj) {
+                const int cc = tj * 16 + r16;
+                bv[tj] = (kk < k && cc < n) ? sB[kk * n + cc] : 0.0;
+            }
+#pragma unroll
+            for (int ti = 0; ti < MT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < NT; ++tj)
+                    if (ti < mt && tj < nt)
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj],
+                                                                           acc[ti][tj], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    double out[MT][NT][4];
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) out[ti][tj][q] = acc[ti][tj][q];
+    store_c_block<MT, NT>(a, c, m, n, out);
+}
+
+int smm_launch(const SmmArgs &a, int variant, hipStream_t s) {
+    if (a.nC <= 0) return BSM_OK;
+    const int64_t per = (a.nC + kXcds - 1) / kXcds;
+    const int64_t grid = per * kXcds;
+    if (grid > (1ll << 31) - 1) {
+        set_error("too many C blocks in one launch (%lld)", (long long)a.nC);
+        return BSM_EINVAL;
+    }
+    const size_t lds = sizeof(double) * (static_cast<size_t>(a.max_m) * a.max_k +
+                                         static_cast<size_t>(a.max_k) * a.max_n);
+    (void)variant;
+    if (a.max_m <= 16 && a.max_n <= 16)
+        k_smm_f64_mfma<1, 1><<<static_cast<unsigned>(grid), 64, lds, s>>>(a);
+    else if (a.max_m <= 16)
+        k_smm_f64_mfma<1, 2><<<static_cast<unsigned>(grid), 64, lds, s>>>(a);
+    else if (a.max_n <= 16)
+        k_smm_f64_mfma<2, 1><<<static_cast<unsigned>(grid), 64, lds, s>>>(a);
+    else
+        k_smm_f64_mfma<2, 2><<<static_cast<unsigned>(grid), 64, lds, s>>>(a);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+}  // namespace bsm

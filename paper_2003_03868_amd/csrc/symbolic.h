@@ -1,0 +1,35 @@
+// Symbolic phase (pattern of C and product stacks); see symbolic.hip.
+#pragma once
+
+#include "bsm_internal.h"
+
+namespace bsm {
+
+// Rows of a C block row whose block count exceeds this are stacked in
+// windows of this many C blocks (LDS counters per window).
+constexpr int kStackWindow = 4096;
+// Largest block-column count the LDS bitmaps support.
+constexpr int32_t kMaxBlockCols = 131072;
+
+struct SymArgs {
+    int32_t nbrows, nbcols;              // block grid of C
+    const int64_t *a_row_ptr;
+    const int32_t *a_col_idx;
+    const int64_t *b_row_ptr;
+    const int32_t *b_col_idx;
+    const int32_t *k_size;               // A column block sizes (= B row sizes)
+    const int32_t *c_rbs, *c_cbs;        // C block sizes
+    int use_c;                           // include C_in's pattern (beta != 0)
+    const int64_t *c_in_row_ptr;
+    const int32_t *c_in_col_idx;
+};
+
+int sym_count(const SymArgs &a, int64_t *c_cnt, int64_t *c_nval, int64_t *p_cnt, double *flops,
+              hipStream_t s);
+int sym_pattern(const SymArgs &a, const int64_t *c_row_ptr, int32_t *c_col_idx, int32_t *c_row,
+                int64_t *cin_map, hipStream_t s);
+int sym_stack(const SymArgs &a, int32_t r0, int32_t r1, const int64_t *c_row_ptr,
+              const int64_t *p_row_ptr, int64_t *seg, int32_t *stk_a, int32_t *stk_b,
+              hipStream_t s);
+
+}  // namespace bsm

@@ -1,0 +1,205 @@
+"""GPU parity of bsm_multiply / bsm_filter and the reductions against the
+CPU oracle, through the C ABI."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from synth import BSR
+from tests.gpu_util import (TOL_FP64_MULTIPLY, assert_same_matrix, block_norm_margin,
+                            from_dev, need_gpu, rel_fro, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _case(seed, nbr, nbk, nbc, maxb, dens):
+    rng = np.random.default_rng(seed)
+    rs = rng.integers(1, maxb + 1, nbr)
+    ks = rng.integers(1, maxb + 1, nbk)
+    cs = rng.integers(1, maxb + 1, nbc)
+    a = synth.random_bsr(nbr, nbk, rs, ks, dens[0], rng)
+    b = synth.random_bsr(nbk, nbc, ks, cs, dens[1], rng)
+    c = synth.random_bsr(nbr, nbc, rs, cs, dens[2], rng)
+    return a, b, c
+
+
+def _run(alpha, a, b, beta, c, eps=0.0, norm="frob"):
+    from paper_2003_03868_amd import bsm
+    da, db = to_dev(a), to_dev(b)
+    dc = to_dev(c) if c is not None else bsm.Matrix.empty_like(a.row_blk_size, b.col_blk_size)
+    st = bsm.bsm_multiply(alpha, da.handle, db.handle, beta, dc.handle, eps,
+                          bsm.NORM_FROB if norm == "frob" else bsm.NORM_MAXABS)
+    out = from_dev(dc)
+    for h in (da, db, dc):
+        h.destroy()
+    return out, st
+
+
+CASES = []
+_r = np.random.default_rng(99)
+for _q in range(24):
+    CASES.append(dict(seed=int(_r.integers(1 << 30)), nbr=int(_r.integers(1, 9)),
+                      nbk=int(_r.integers(1, 9)), nbc=int(_r.integers(1, 9)),
+                      maxb=int(_r.choice([1, 4, 5, 13, 16, 17, 23, 32])),
+                      dens=tuple(float(x) for x in _r.choice([0.0, 0.25, 0.6, 1.0], 3)),
+                      alpha=float(_r.choice([1.0, -0.5, 2.0])),
+                      beta=float(_r.choice([0.0, 1.0, 1.5]))))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"r{i}" for i in range(len(CASES))])
+def test_multiply_random_vs_oracle(orc, case):
+    a, b, c = _case(case["seed"], case["nbr"], case["nbk"], case["nbc"], case["maxb"], case["dens"])
+    ref = orc.multiply(case["alpha"], a, b, case["beta"], c)
+    got, st = _run(case["alpha"], a, b, case["beta"], c)
+    assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, "multiply")
+    assert st.nnzb == ref.nnzb
+
+
+def test_multiply_832_workload(orc):
+    """64 x 64 grid of 13 x 13 blocks, 20% present, eps = 0."""
+    a, b = synth.random_bsr_pair(64, 13, 0.2, seed=0)
+    ref = orc.multiply(1.0, a, b)
+    got, st = _run(1.0, a, b, 0.0, None)
+    err = assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, "832")
+    # flops and product count are integers fixed by the patterns
+    pa, pb = a.pattern(), b.pattern()
+    rows_of = {}
+    for (k, j) in pb:
+        rows_of.setdefault(k, 0)
+        rows_of[k] += 1
+    nprod = sum(rows_of.get(k, 0) for (_, k) in pa)
+    assert st.n_products == nprod
+    assert st.flops == 2.0 * 13 ** 3 * nprod
+    print(f"832 multiply: err {err:.2e}, products {nprod}")
+
+
+def test_multiply_chunked_matches_single(orc, monkeypatch):
+    """A tiny chunk size forces many product chunks; results must not change."""
+    a, b = synth.random_bsr_pair(24, 7, 0.4, seed=3)
+    ref = orc.multiply(1.0, a, b)
+    monkeypatch.setenv("BSM_CHUNK_PRODUCTS", "37")
+    got, _ = _run(1.0, a, b, 0.0, None)
+    assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, "chunked")
+
+
+@pytest.mark.parametrize("norm", ["frob", "maxabs"])
+@pytest.mark.parametrize("q", [0.2, 0.5, 0.9])
+def test_multiply_filter_vs_oracle(orc, norm, q):
+    a, b, c = _case(17, 7, 6, 7, 23, (0.6, 0.6, 0.5))
+    unf = orc.multiply(1.0, a, b, 1.5, c)
+    off = unf.block_offsets()
+    if norm == "frob":
+        vals = np.sort([np.sqrt((unf.values[off[t]:off[t + 1]] ** 2).sum()) for t in range(unf.nnzb)])
+    else:
+        vals = np.sort([np.abs(unf.values[off[t]:off[t + 1]]).max() for t in range(unf.nnzb)])
+    eps = float(vals[int(q * (len(vals) - 1))]) * (1 + 1e-7)
+    assert block_norm_margin(unf, eps, norm).min() > 1e-12   # no ties
+    ref = orc.multiply(1.0, a, b, 1.5, c, eps=eps, norm=norm)
+    got, st = _run(1.0, a, b, 1.5, c, eps=eps, norm=norm)
+    assert st.nnzb_unfiltered == unf.nnzb
+    assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, "filtered")
+
+
+def test_multiply_aliasing_c_is_a(orc):
+    """C may be the same handle as A (the sign update X <- 1.5X - 0.5 X Y)."""
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(40, 5, cutoff=4.0, seed=1)
+    x = orc.shift_scale(h, 0.0, 0.01)
+    y = orc.multiply(1.0, x, x)
+    ref = orc.multiply(-0.5, x, y, 1.5, x)
+    dx, dy = to_dev(x), to_dev(y)
+    bsm.bsm_multiply(-0.5, dx.handle, dy.handle, 1.5, dx.handle)
+    assert_same_matrix(from_dev(dx), ref, TOL_FP64_MULTIPLY, "aliased")
+
+
+def test_multiply_edge_cases(orc):
+    from paper_2003_03868_amd import bsm
+    a, b, c = _case(5, 4, 3, 5, 6, (0.0, 0.5, 0.5))          # empty A
+    got, st = _run(1.0, a, b, 0.0, None)
+    assert got.nnzb == 0 and st.n_products == 0
+    got, _ = _run(1.0, a, b, 2.0, c)                         # C = 2 Cin
+    assert_same_matrix(got, orc.multiply(1.0, a, b, 2.0, c), 0.0, "beta only")
+    a, b, _ = _case(6, 3, 3, 3, 4, (1.0, 1.0, 0.0))
+    got, _ = _run(0.0, a, b, 0.0, None)                      # alpha = 0 keeps zero blocks
+    assert got.nnzb == 9 and not np.any(got.values)
+    a1 = BSR(np.ones(1), np.ones(1), [0, 1], [0], [3.0])
+    got, _ = _run(2.0, a1, a1, 0.0, None)                    # 1 x 1 blocks
+    assert got.values.tolist() == [18.0]
+    # invalid calls
+    a, b, _ = _case(7, 3, 3, 3, 5, (0.5, 0.5, 0.0))
+    bad = synth.random_bsr(3, 3, 9, 9, 1.0, np.random.default_rng(0))
+    da, dbad = to_dev(a), to_dev(bad)
+    dc = bsm.Matrix.empty_like(a.row_blk_size, bad.col_blk_size)
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.bsm_multiply(1.0, da.handle, dbad.handle, 0.0, dc.handle)
+    assert e.value.status == bsm.EINVAL
+    db = to_dev(b)
+    dc2 = bsm.Matrix.empty_like(a.row_blk_size, b.col_blk_size)
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.bsm_multiply(1.0, da.handle, db.handle, 0.0, dc2.handle, -1.0)
+    assert e.value.status == bsm.EINVAL
+    # non-canonical input is refused at creation
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.Matrix.from_arrays([2, 2], [2, 2], [0, 2, 2], [1, 0], np.zeros(8))
+    assert e.value.status == bsm.EINVAL
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.Matrix.from_arrays([40], [2], [0, 1], [0], np.zeros(80))
+    assert e.value.status == bsm.EINVAL
+
+
+def test_multiply_nonfinite(orc):
+    from paper_2003_03868_amd import bsm
+    a, b, _ = _case(8, 3, 3, 3, 5, (1.0, 1.0, 0.0))
+    a.values[3] = np.nan
+    da, db = to_dev(a), to_dev(b)
+    dc = bsm.Matrix.empty_like(a.row_blk_size, b.col_blk_size)
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.bsm_multiply(1.0, da.handle, db.handle, 0.0, dc.handle)
+    assert e.value.status == bsm.ENONFINITE
+
+
+@pytest.mark.parametrize("norm", ["frob", "maxabs"])
+def test_filter_vs_oracle(orc, norm):
+    from paper_2003_03868_amd import bsm
+    rng = np.random.default_rng(21)
+    m = synth.random_bsr(9, 9, rng.integers(1, 33, 9), rng.integers(1, 33, 9), 0.6, rng)
+    m.values *= np.repeat(rng.uniform(0.0, 2.0, m.nnzb) ** 6, np.diff(m.block_offsets()))
+    for eps in [0.0, 0.05, 0.5, 3.0]:
+        if eps > 0:
+            assert block_norm_margin(m, eps, norm).min() > 1e-12
+        ref = orc.filter(m, eps, norm)
+        d = to_dev(m)
+        bsm.bsm_filter(d.handle, eps, bsm.NORM_FROB if norm == "frob" else bsm.NORM_MAXABS)
+        assert_same_matrix(from_dev(d), ref, 0.0, f"filter {eps}")
+
+
+def test_reductions_vs_oracle(orc):
+    import torch
+    from paper_2003_03868_amd import bsm
+    rng = np.random.default_rng(22)
+    sizes = rng.integers(1, 33, 12)
+    m = synth.random_bsr(12, 12, sizes, sizes, 0.4, rng)
+    d = to_dev(m)
+    assert bsm.bsm_trace(d.handle) == pytest.approx(orc.trace(m), rel=1e-13, abs=1e-13)
+    for shift in [0.0, 1.0, -2.5]:
+        assert bsm.bsm_sqdist_identity(d.handle, shift) == pytest.approx(
+            orc.sqdist_identity(m, shift), rel=1e-12)
+        assert bsm.bsm_inf_norm(d.handle, shift) == pytest.approx(
+            orc.inf_norm_shifted(m, shift), rel=1e-13)
+    out = torch.zeros(m.nnzb, dtype=torch.float64, device="cuda")
+    bsm.bsm_block_norms(d.handle, out)
+    torch.cuda.synchronize()
+    assert np.allclose(out.cpu().numpy(), orc.block_sqnorms(m), rtol=1e-13, atol=0)
+    # shift/scale with a missing diagonal block inserted
+    rp, ci = m.row_ptr.copy(), m.col_idx.copy()
+    has_diag = [any(ci[rp[i]:rp[i + 1]] == i) for i in range(12)]
+    assert not all(has_diag)
+    h2 = bsm.bsm_shift_scale(d.handle, 0.7, 0.25)
+    got = from_dev(bsm.Matrix(h2, sizes, sizes))
+    assert_same_matrix(got, orc.shift_scale(m, 0.7, 0.25), 1e-15, "shift_scale")

@@ -1,0 +1,92 @@
+"""GPU parity of bsm_sign_iterate / bsm_density_from_sign against the CPU
+oracle's Newton-Schulz iteration, plus the invariants that hold at any size."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import TOL_FP64, assert_same_matrix, from_dev, need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _gpu_sign(h, eps=0.0, tol=1e-6, fixed=0, norm="frob", mu=0.0, max_iter=100):
+    from paper_2003_03868_amd import bsm
+    d = to_dev(h)
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol, o.fixed_iters, o.max_iter = eps, tol, fixed, max_iter
+    o.norm = bsm.NORM_FROB if norm == "frob" else bsm.NORM_MAXABS
+    st, xh, stats = bsm.bsm_sign_iterate(d.handle, mu, o)
+    x = bsm.Matrix(xh, h.row_blk_size, h.col_blk_size) if xh else None
+    return st, x, stats, d
+
+
+SIGN_CASES = [
+    dict(n=64, b=5, rc=4.0, eps=0.0, seed=3),
+    dict(n=96, b=13, rc=4.5, eps=0.0, seed=4),
+    dict(n=200, b=5, rc=6.0, eps=1e-6, seed=5),
+    dict(n=100, b=23, rc=4.2, eps=1e-6, seed=6),
+]
+
+
+@pytest.mark.parametrize("c", SIGN_CASES, ids=lambda c: f"n{c['n']}b{c['b']}e{c['eps']:g}")
+def test_sign_vs_oracle(orc, c):
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(c["n"], c["b"], cutoff=c["rc"], seed=c["seed"])
+    x_ref, st_ref, s_ref = orc.sign_ns(h, eps=c["eps"], tol=1e-8)
+    st, x, stats, _ = _gpu_sign(h, eps=c["eps"], tol=1e-8)
+    assert st == bsm.OK and s_ref == orc.OK
+    assert stats.iterations == st_ref["iterations"]
+    assert np.allclose(list(stats.r_hist)[:stats.iterations + 1], st_ref["r_hist"], rtol=1e-6,
+                       atol=1e-15)
+    assert stats.scale == pytest.approx(st_ref["scale"], rel=1e-14)
+    err = assert_same_matrix(from_dev(x), x_ref, TOL_FP64, "sign")
+    assert stats.trace_p == pytest.approx(h.meta["n_occ"], abs=1e-4)
+    assert stats.trace_p == pytest.approx(st_ref["trace_p"], abs=1e-9)
+    print(f"sign n={c['n']} b={c['b']}: iters {stats.iterations} err {err:.2e}")
+
+
+def test_sign_fixed_iterations_vs_oracle(orc):
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(128, 13, cutoff=5.0, seed=7)
+    x_ref, st_ref, _ = orc.sign_ns(h, eps=1e-5, fixed_iters=4)
+    st, x, stats, _ = _gpu_sign(h, eps=1e-5, fixed=4)
+    assert st == bsm.OK and stats.iterations == 4
+    assert_same_matrix(from_dev(x), x_ref, TOL_FP64, "fixed")
+
+
+def test_sign_failure_modes(orc):
+    from paper_2003_03868_amd import bsm
+    sizes = np.array([2, 3], dtype=np.int32)
+    # eigenvalue exactly at mu: the residual stalls
+    vals = [1.0, 0, 0, -2.0, 0.0, 0, 0, 0, 0, 0, 0, 3.0, 0, 0, 0, 0.5]
+    vals = np.array([1.0, 0, 0, -2.0] + [0.0, 0, 0, 0, 3.0, 0, 0, 0, 0.5])
+    m = synth.BSR(sizes, sizes, [0, 1, 2], [0, 1], vals)
+    st, x, stats, _ = _gpu_sign(m, tol=1e-10)
+    assert st == bsm.ENOCONV
+    vals2 = vals.copy()
+    vals2[4] = np.nan
+    st, x, stats, _ = _gpu_sign(synth.BSR(sizes, sizes, [0, 1, 2], [0, 1], vals2), tol=1e-10)
+    assert st == bsm.ENONFINITE
+    d = to_dev(m)
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter = -1.0
+    with pytest.raises(bsm.BsmError):
+        bsm.bsm_sign_iterate(d.handle, 0.0, o)
+
+
+def test_density_from_sign(orc):
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(64, 5, cutoff=4.0, seed=8)
+    st, x, stats, _ = _gpu_sign(h, tol=1e-10)
+    ph, tp = bsm.bsm_density_from_sign(x.handle)
+    p = from_dev(bsm.Matrix(ph, h.row_blk_size, h.col_blk_size))
+    ref = orc.density_from_sign(from_dev(x))
+    assert_same_matrix(p, ref, 1e-15, "P")
+    assert tp == pytest.approx(h.meta["n_occ"], abs=1e-8)
+    dp = p.to_dense()
+    assert np.linalg.norm(dp @ dp - dp) / dp.shape[0] < 1e-9
