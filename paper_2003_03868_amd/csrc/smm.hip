@@ -36,6 +36,8 @@ __device__ inline double wave_max(double v) {
 }
 
 // Shared epilogue: v = alpha*acc + beta*C_in, store, and the block norms.
+// Accumulator layout of V_MFMA_F64_16X16X4_F64 (measured on gfx950): element
+// (i, j) of a 16 x 16 tile lives in lane j + 16*(i % 4), register i / 4.
 template <int MT, int NT>
 __device__ inline void store_c_block(const SmmArgs &a, int64_t c, int m, int n,
                                      const double (&acc)[MT][NT][4]) {
@@ -54,7 +56,7 @@ __device__ inline void store_c_block(const SmmArgs &a, int64_t c, int m, int n,
         for (int tj = 0; tj < NT; ++tj)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int row = ti * 16 + 4 * kq + q, col = tj * 16 + r16;
+                const int row = ti * 16 + 4 * q + kq, col = tj * 16 + r16;
                 if (row < m && col < n) {
                     double v = a.alpha * acc[ti][tj][q];
                     if (cin) v += a.beta * cin[row * n + col];

@@ -109,7 +109,7 @@ def test_multiply_filter_vs_oracle(orc, norm, q):
 def test_multiply_aliasing_c_is_a(orc):
     """C may be the same handle as A (the sign update X <- 1.5X - 0.5 X Y)."""
     from paper_2003_03868_amd import bsm
-    h = synth.neighbour_hamiltonian(40, 5, cutoff=4.0, seed=1)
+    h = synth.neighbour_hamiltonian(64, 5, cutoff=4.0, seed=1)
     x = orc.shift_scale(h, 0.0, 0.01)
     y = orc.multiply(1.0, x, x)
     ref = orc.multiply(-0.5, x, y, 1.5, x)
