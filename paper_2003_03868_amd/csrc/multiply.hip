@@ -27,6 +27,13 @@ static int64_t chunk_products() {
     return x > 0 ? static_cast<int64_t>(x) : (int64_t{1} << 27);
 }
 
+// Block-product kernel variant; BSM_SMM_VARIANT overrides the default
+// (tests and the tuner compare variants).
+static int smm_variant() {
+    const char *e = getenv("BSM_SMM_VARIANT");
+    return e ? atoi(e) : kSmmF64M4;
+}
+
 namespace {
 struct Events {
     bool on = false;
@@ -205,7 +212,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             BSM_HIP(hipEventCreate(&pe.second));
             BSM_HIP(hipEventRecord(pe.first, s));
         }
-        st = smm_launch(ma, 0, s);
+        st = smm_launch(ma, smm_variant(), s);
         if (ev.on) {
             BSM_HIP(hipEventRecord(pe.second, s));
             ev.smm.push_back(pe);

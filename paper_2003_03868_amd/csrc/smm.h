@@ -7,6 +7,12 @@ namespace bsm {
 
 constexpr int kFlagNonFinite = 1;
 
+// Block-product kernel variants.
+enum SmmVariant {
+    kSmmF64M16 = 0,   // V_MFMA_F64_16X16X4_F64, 16 x 16 tiles
+    kSmmF64M4 = 1,    // V_MFMA_F64_4X4X4_4B_F64, 4 x 4 tiles (default)
+};
+
 struct SmmArgs {
     int64_t c0;                 // first C block of this launch
     int64_t nC;                 // C blocks in this launch

@@ -139,6 +139,134 @@ k_smm_f64_mfma(SmmArgs a) {
     store_c_block<MT, NT>(a, c, m, n, out);
 }
 
+// ---------------------------------------------------------------------------
+// FP64 kernel on V_MFMA_F64_4X4X4_4B_F64 (four independent 4x4x4 products per
+// instruction).  On gfx950 this instruction sustains ~95% of the FP64 peak,
+// and its 4-wide tiles pad a 23 x 23 block only to 24 x 24.
+//
+// Lane layout (measured on gfx950): lane = 16*x + 4*b + y, b = block 0..3;
+// A_b(i,k): x = k, y = i;  B_b(k,j): x = k, y = j;  D_b(i,j): x = i, y = j.
+//
+// The C block (m, n <= 32) is cut into 4-row / 4-column tiles; instruction
+// block b = 2*bh + bw owns the tiles of row half bh and column half bw, so
+// each lane holds RT x CT accumulators (one element per tile).  Per k-step a
+// lane reads RT A values and CT B values from LDS and issues RT*CT MFMAs.
+// The next product's two operand blocks are prefetched into registers with
+// contiguous loads while the current one is multiplied.
+template <int RT, int CT>
+__global__ void __launch_bounds__(64)
+k_smm_f64_m4(SmmArgs a) {
+    constexpr int kMaxM = 8 * RT, kMaxN = 8 * CT, kMaxK = kMaxBlock;
+    constexpr int NA = (kMaxM * kMaxK + kWave - 1) / kWave;   // A doubles per lane
+    constexpr int NB = (kMaxK * kMaxN + kWave - 1) / kWave;   // B doubles per lane
+    extern __shared__ double sm[];
+    const int64_t item = xcd_item(a.nC);
+    if (item >= a.nC) return;
+    const int lane = threadIdx.x;
+    const int x = lane >> 4, blk = (lane >> 2) & 3, y = lane & 3;
+    const int bh = blk >> 1, bw = blk & 1;
+    const int64_t c = a.c0 + item;
+    const int m = a.c_rbs[a.c_row[c]], n = a.c_cbs[a.c_col[c]];
+    const int hr = (((m + 3) >> 2) + 1) >> 1;      // row tiles per half
+    const int hc = (((n + 3) >> 2) + 1) >> 1;      // column tiles per half
+    double *sA = sm;
+    double *sB = sm + a.max_m * a.max_k;
+
+    double acc[RT][CT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int u = 0; u < CT; ++u) acc[t][u] = 0.0;
+
+    const int64_t p0 = a.seg[item], p_end = a.seg[item + 1];
+    double ra[NA], rb[NB];
+    int k_next = 0;
+    auto prefetch = [&](int64_t p) {
+        const int32_t ta = a.stk_a[p], tb = a.stk_b[p];
+        k_next = a.k_size[a.a_col_idx[ta]];
+        const double *ga = a.a_vals + a.a_blk_off[ta];
+        const double *gb = a.b_vals + a.b_blk_off[tb];
+        const int na = m * k_next, nb = k_next * n;
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const int e = lane + q * kWave;
+            ra[q] = (e < na) ? ga[e] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = lane + q * kWave;
+            rb[q] = (e < nb) ? gb[e] : 0.0;
+        }
+    };
+    if (p0 < p_end) prefetch(p0);
+    for (int64_t p = p0; p < p_end; ++p) {
+        const int k = k_next;
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const int e = lane + q * kWave;
+            if (e < m * k) sA[e] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = lane + q * kWave;
+            if (e < k * n) sB[e] = rb[q];
+        }
+        __syncthreads();
+        if (p + 1 < p_end) prefetch(p + 1);
+        for (int ks = 0; ks < k; ks += 4) {
+            const int kk = ks + x;
+            double av[RT], bv[CT];
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const int r = 4 * (bh * hr + t) + y;
+                av[t] = (t < hr && r < m && kk < k) ? sA[r * k + kk] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < CT; ++u) {
+                const int cc = 4 * (bw * hc + u) + y;
+                bv[u] = (u < hc && cc < n && kk < k) ? sB[kk * n + cc] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+                for (int u = 0; u < CT; ++u)
+                    if (t < hr && u < hc)
+                        acc[t][u] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[t], bv[u], acc[t][u],
+                                                                       0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // epilogue: alpha*acc + beta*C_in, store, block norms
+    const int64_t co = a.c_blk_off[c];
+    const double *cin = nullptr;
+    if (a.cin_map) {
+        const int64_t t = a.cin_map[c];
+        if (t >= 0) cin = a.cin_vals + a.cin_blk_off[t];
+    }
+    double sq = 0.0, mx = 0.0;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int u = 0; u < CT; ++u) {
+            const int row = 4 * (bh * hr + t) + x, col = 4 * (bw * hc + u) + y;
+            if (t < hr && u < hc && row < m && col < n) {
+                double v = a.alpha * acc[t][u];
+                if (cin) v += a.beta * cin[row * n + col];
+                a.c_vals[co + row * n + col] = v;
+                sq += v * v;
+                mx = fmax(mx, fabs(v));
+            }
+        }
+    sq = wave_sum(sq);
+    mx = wave_max(mx);
+    if (lane == 0) {
+        a.sq_out[c] = sq;
+        a.mx_out[c] = mx;
+        if (!isfinite(sq)) atomicOr(a.flags, kFlagNonFinite);
+    }
+}
+
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s) {
     if (a.nC <= 0) return BSM_OK;
     const int64_t per = (a.nC + kXcds - 1) / kXcds;
@@ -149,7 +277,19 @@ int smm_launch(const SmmArgs &a, int variant, hipStream_t s) {
     }
     const size_t lds = sizeof(double) * (static_cast<size_t>(a.max_m) * a.max_k +
                                          static_cast<size_t>(a.max_k) * a.max_n);
-    (void)variant;
+    if (variant == kSmmF64M4) {
+        // tiles per half: ceil(ceil(max/4)/2)
+        const int rt = (((a.max_m + 3) / 4) + 1) / 2, ct = (((a.max_n + 3) / 4) + 1) / 2;
+        const unsigned g = static_cast<unsigned>(grid);
+#define BSM_M4(R, C) k_smm_f64_m4<R, C><<<g, 64, lds, s>>>(a)
+        if (rt <= 1 && ct <= 1) BSM_M4(1, 1);
+        else if (rt <= 2 && ct <= 2) BSM_M4(2, 2);
+        else if (rt <= 3 && ct <= 3) BSM_M4(3, 3);
+        else BSM_M4(4, 4);
+#undef BSM_M4
+        BSM_HIP(hipGetLastError());
+        return BSM_OK;
+    }
     if (a.max_m <= 16 && a.max_n <= 16)
         k_smm_f64_mfma<1, 1><<<static_cast<unsigned>(grid), 64, lds, s>>>(a);
     else if (a.max_m <= 16)

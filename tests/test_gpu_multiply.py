@@ -203,3 +203,24 @@ def test_reductions_vs_oracle(orc):
     h2 = bsm.bsm_shift_scale(d.handle, 0.7, 0.25)
     got = from_dev(bsm.Matrix(h2, sizes, sizes))
     assert_same_matrix(got, orc.shift_scale(m, 0.7, 0.25), 1e-15, "shift_scale")
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("maxb", [5, 13, 23, 26, 32])
+def test_multiply_kernel_variants(orc, monkeypatch, variant, maxb):
+    """Both FP64 block-product kernels (16x16 and 4x4 matrix-core tiles)
+    against the oracle, uniform and mixed block sizes up to maxb."""
+    monkeypatch.setenv("BSM_SMM_VARIANT", str(variant))
+    for seed, uniform in [(31, True), (32, False)]:
+        rng = np.random.default_rng(seed + maxb)
+        nb = 9
+        if uniform:
+            rs = ks = cs = np.full(nb, maxb)
+        else:
+            rs, ks, cs = (rng.integers(1, maxb + 1, nb) for _ in range(3))
+        a = synth.random_bsr(nb, nb, rs, ks, 0.5, rng)
+        b = synth.random_bsr(nb, nb, ks, cs, 0.5, rng)
+        c = synth.random_bsr(nb, nb, rs, cs, 0.3, rng)
+        ref = orc.multiply(-0.5, a, b, 1.5, c)
+        got, _ = _run(-0.5, a, b, 1.5, c)
+        assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"variant {variant} maxb {maxb}")
