@@ -72,6 +72,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cpu-rows", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
@@ -81,6 +83,18 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        # A plain copy of known size: each dispatch reads and writes exactly
+        # MIB MiB, which scales the HBM read/write counters of the profiler.
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.randn(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_mib": args.calibrate_copy, "dispatches": 5}))
+        return
 
     import synth
     from paper_2003_03868_amd import bsm

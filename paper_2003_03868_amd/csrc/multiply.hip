@@ -31,7 +31,7 @@ static int64_t chunk_products() {
 // (tests and the tuner compare variants).
 static int smm_variant() {
     const char *e = getenv("BSM_SMM_VARIANT");
-    return e ? atoi(e) : kSmmF64M4;
+    return e ? atoi(e) : kSmmF64Fixed;
 }
 
 namespace {
@@ -162,14 +162,20 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     if (st == BSM_OK) st = sym_pattern(sa, c_row_ptr, nc.col_idx, c_row, cin_map, s);
     if (st == BSM_OK) st = compute_blk_off(nc, s);
 
-    // 5. chunks of block rows with a bounded number of products
+    // 5. tiled work order, then chunks of whole row bands with a bounded
+    //    number of products
+    const int rb = tile_rows();
+    int64_t *worklist = nullptr;
+    if (st == BSM_OK) st = tmp.get(&worklist, nnzb_c);
+    if (st == BSM_OK) st = tile_order(c_row_ptr, nc.col_idx, nbr, B.nbcols, rb, worklist, s);
     std::vector<int32_t> cuts{0};
     {
         const int64_t lim = chunk_products();
         int32_t r0 = 0;
         while (r0 < nbr) {
-            int32_t r1 = r0 + 1;
-            while (r1 < nbr && h_prp[r1 + 1] - h_prp[r0] <= lim) ++r1;
+            int32_t r1 = std::min(nbr, r0 + rb);
+            while (r1 < nbr && h_prp[std::min(nbr, r1 + rb)] - h_prp[r0] <= lim)
+                r1 = std::min(nbr, r1 + rb);
             cuts.push_back(r1);
             r0 = r1;
         }
@@ -196,8 +202,10 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     ma.alpha = alpha; ma.beta = beta;
     ma.sq_out = sq; ma.mx_out = mx; ma.flags = flags;
     ma.max_m = A.max_rbs; ma.max_n = B.max_cbs; ma.max_k = A.max_cbs;
+    ma.uni_m = A.uni_r; ma.uni_n = B.uni_c; ma.uni_k = A.uni_c;
     ma.prec = prec;
     ma.seg = seg; ma.stk_a = stk_a; ma.stk_b = stk_b;
+    ma.worklist = worklist;
 
     for (size_t q = 0; st == BSM_OK && q + 1 < cuts.size(); ++q) {
         const int32_t r0 = cuts[q], r1 = cuts[q + 1];

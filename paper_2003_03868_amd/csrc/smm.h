@@ -10,12 +10,15 @@ constexpr int kFlagNonFinite = 1;
 // Block-product kernel variants.
 enum SmmVariant {
     kSmmF64M16 = 0,   // V_MFMA_F64_16X16X4_F64, 16 x 16 tiles
-    kSmmF64M4 = 1,    // V_MFMA_F64_4X4X4_4B_F64, 4 x 4 tiles (default)
+    kSmmF64M4 = 1,    // V_MFMA_F64_4X4X4_4B_F64, 4 x 4 tiles, run-time shapes
+    kSmmF64Fixed = 2, // same instruction, compile-time uniform shapes (default;
+                      // falls back to kSmmF64M4 for other shapes)
 };
 
 struct SmmArgs {
     int64_t c0;                 // first C block of this launch
     int64_t nC;                 // C blocks in this launch
+    const int64_t *worklist;    // C block of work item c0 + item (NULL: identity)
     const int64_t *seg;         // [nC+1] product segments, launch-relative
     const int32_t *stk_a;       // A block index per product
     const int32_t *stk_b;       // B block index per product
@@ -38,9 +41,11 @@ struct SmmArgs {
     double *mx_out;             // max |x| of every C block
     int *flags;                 // kFlagNonFinite
     int32_t max_m, max_n, max_k;
+    int32_t uni_m, uni_n, uni_k;  // uniform block sizes, 0 if mixed
     int32_t prec;               // bsm_precision
 };
 
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s);
+bool smm_fixed_available(int m, int n, int k);
 
 }  // namespace bsm

@@ -84,7 +84,7 @@ k_smm_f64_mfma(SmmArgs a) {
     if (item >= a.nC) return;
     const int lane = threadIdx.x;
     const int r16 = lane & 15, kq = lane >> 4;
-    const int64_t c = a.c0 + item;
+    const int64_t c = a.worklist ? a.worklist[a.c0 + item] : a.c0 + item;
     const int m = a.c_rbs[a.c_row[c]], n = a.c_cbs[a.c_col[c]];
     const int mt = (m + 15) >> 4, nt = (n + 15) >> 4;
     double *sA = sm;
@@ -96,8 +96,8 @@ k_smm_f64_mfma(SmmArgs a) {
 #pragma unroll
         for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
 
-    const int64_t p_end = a.seg[item + 1];
-    for (int64_t p = a.seg[item]; p < p_end; ++p) {
+    const int64_t p_end = a.seg[c - a.c0 + 1];
+    for (int64_t p = a.seg[c - a.c0]; p < p_end; ++p) {
         const int32_t ta = a.stk_a[p], tb = a.stk_b[p];
         const int k = a.k_size[a.a_col_idx[ta]];
         const double *ga = a.a_vals + a.a_blk_off[ta];
@@ -165,7 +165,7 @@ k_smm_f64_m4(SmmArgs a) {
     const int lane = threadIdx.x;
     const int x = lane >> 4, blk = (lane >> 2) & 3, y = lane & 3;
     const int bh = blk >> 1, bw = blk & 1;
-    const int64_t c = a.c0 + item;
+    const int64_t c = a.worklist ? a.worklist[a.c0 + item] : a.c0 + item;
     const int m = a.c_rbs[a.c_row[c]], n = a.c_cbs[a.c_col[c]];
     const int hr = (((m + 3) >> 2) + 1) >> 1;      // row tiles per half
     const int hc = (((n + 3) >> 2) + 1) >> 1;      // column tiles per half
@@ -178,7 +178,7 @@ k_smm_f64_m4(SmmArgs a) {
 #pragma unroll
         for (int u = 0; u < CT; ++u) acc[t][u] = 0.0;
 
-    const int64_t p0 = a.seg[item], p_end = a.seg[item + 1];
+    const int64_t p0 = a.seg[c - a.c0], p_end = a.seg[c - a.c0 + 1];
     double ra[NA], rb[NB];
     int k_next = 0;
     auto prefetch = [&](int64_t p) {
@@ -267,6 +267,157 @@ k_smm_f64_m4(SmmArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 kernel for uniform block sizes known at compile time (M x K times
+// K x N).  Same instruction and lane roles as k_smm_f64_m4, but:
+//  * the operand blocks sit in LDS exactly as in HBM (A then B, row-major,
+//    followed by a zeroed tail), so staging is a contiguous copy with
+//    immediate offsets and needs no per-lane index registers;
+//  * the k loop is fully unrolled with immediate LDS offsets;
+//  * only the k-padding lanes of the last k-step are masked: padding rows of
+//    A and padding columns of B just read neighbouring data, which reaches
+//    only accumulator rows/columns that are never stored.
+// Odd K and N (5, 13, 23) keep the rows one instruction reads in distinct
+// LDS banks.
+template <int M, int N, int K>
+struct FixedShape {
+    static constexpr int MT = (M + 3) / 4, NT = (N + 3) / 4, KS = (K + 3) / 4;
+    static constexpr int HR = (MT + 1) / 2, HC = (NT + 1) / 2;
+    static constexpr int KLAST = K - 4 * (KS - 1);     // valid x in the last k-step
+    static constexpr int TAIL = 4 * K + 8 * N + 8;     // covers padded reads past B
+    static constexpr int SIZE = M * K + K * N + TAIL;
+    static constexpr int NA = (M * K + kWave - 1) / kWave;
+    static constexpr int NB = (K * N + kWave - 1) / kWave;
+};
+
+template <int M, int N, int K, int WPE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+k_smm_f64_fixed(SmmArgs a) {
+    using S = FixedShape<M, N, K>;
+    __shared__ double sm[S::SIZE];
+    double *sA = sm;
+    double *sB = sm + M * K;
+    const int64_t item = xcd_item(a.nC);
+    if (item >= a.nC) return;
+    const int lane = threadIdx.x;
+    const int x = lane >> 4, blk = (lane >> 2) & 3, y = lane & 3;
+    const int bh = blk >> 1, bw = blk & 1;
+    const int64_t c = a.worklist ? a.worklist[a.c0 + item] : a.c0 + item;
+
+    for (int e = M * K + K * N + lane; e < S::SIZE; e += kWave) sm[e] = 0.0;
+    const int ra0 = (4 * bh * S::HR + y) * K + x;      // A(4*(bh*HR+t)+y, 4*ks+x)
+    const int rb0 = x * N + 4 * bw * S::HC + y;        // B(4*ks+x, 4*(bw*HC+u)+y)
+    const bool klast_ok = x < S::KLAST;
+
+    double acc[S::HR][S::HC];
+#pragma unroll
+    for (int t = 0; t < S::HR; ++t)
+#pragma unroll
+        for (int u = 0; u < S::HC; ++u) acc[t][u] = 0.0;
+
+    const int64_t p0 = a.seg[c - a.c0], p_end = a.seg[c - a.c0 + 1];
+    double pa[S::NA], pb[S::NB];
+    auto prefetch = [&](int64_t p) {
+        const double *ga = a.a_vals + a.a_blk_off[a.stk_a[p]];
+        const double *gb = a.b_vals + a.b_blk_off[a.stk_b[p]];
+#pragma unroll
+        for (int q = 0; q < S::NA; ++q)
+            if (q < S::NA - 1 || lane + q * kWave < M * K) pa[q] = ga[lane + q * kWave];
+#pragma unroll
+        for (int q = 0; q < S::NB; ++q)
+            if (q < S::NB - 1 || lane + q * kWave < K * N) pb[q] = gb[lane + q * kWave];
+    };
+    if (p0 < p_end) prefetch(p0);
+    for (int64_t p = p0; p < p_end; ++p) {
+#pragma unroll
+        for (int q = 0; q < S::NA; ++q)
+            if (q < S::NA - 1 || lane + q * kWave < M * K) sA[lane + q * kWave] = pa[q];
+#pragma unroll
+        for (int q = 0; q < S::NB; ++q)
+            if (q < S::NB - 1 || lane + q * kWave < K * N) sB[lane + q * kWave] = pb[q];
+        __syncthreads();
+        if (p + 1 < p_end) prefetch(p + 1);
+#pragma unroll
+        for (int ks = 0; ks < S::KS; ++ks) {
+            double av[S::HR], bv[S::HC];
+#pragma unroll
+            for (int t = 0; t < S::HR; ++t) av[t] = sA[ra0 + 4 * t * K + 4 * ks];
+#pragma unroll
+            for (int u = 0; u < S::HC; ++u) bv[u] = sB[rb0 + 4 * u + 4 * ks * N];
+            if (ks == S::KS - 1 && S::KLAST < 4) {
+#pragma unroll
+                for (int t = 0; t < S::HR; ++t) av[t] = klast_ok ? av[t] : 0.0;
+#pragma unroll
+                for (int u = 0; u < S::HC; ++u) bv[u] = klast_ok ? bv[u] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < S::HR; ++t)
+#pragma unroll
+                for (int u = 0; u < S::HC; ++u)
+                    acc[t][u] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[t], bv[u], acc[t][u], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    const int64_t co = a.c_blk_off[c];
+    const double *cin = nullptr;
+    if (a.cin_map) {
+        const int64_t t = a.cin_map[c];
+        if (t >= 0) cin = a.cin_vals + a.cin_blk_off[t];
+    }
+    double sq = 0.0, mx = 0.0;
+#pragma unroll
+    for (int t = 0; t < S::HR; ++t)
+#pragma unroll
+        for (int u = 0; u < S::HC; ++u) {
+            const int row = 4 * (bh * S::HR + t) + x, col = 4 * (bw * S::HC + u) + y;
+            if (row < M && col < N) {
+                double v = a.alpha * acc[t][u];
+                if (cin) v += a.beta * cin[row * N + col];
+                a.c_vals[co + row * N + col] = v;
+                sq += v * v;
+                mx = fmax(mx, fabs(v));
+            }
+        }
+    sq = wave_sum(sq);
+    mx = wave_max(mx);
+    if (lane == 0) {
+        a.sq_out[c] = sq;
+        a.mx_out[c] = mx;
+        if (!isfinite(sq)) atomicOr(a.flags, kFlagNonFinite);
+    }
+}
+
+// Uniform (m, n, k) shapes with a compile-time kernel.
+bool smm_fixed_available(int m, int n, int k) {
+    return (m == n && n == k) && (m == 5 || m == 13 || m == 23 || m == 26 || m == 32);
+}
+
+// Occupancy target of the fixed-shape kernels (waves per SIMD the register
+// allocation must allow); BSM_FIXED_WPE selects another compiled target.
+static int fixed_wpe() {
+    const char *e = getenv("BSM_FIXED_WPE");
+    return e ? atoi(e) : 0;
+}
+
+static int launch_fixed(const SmmArgs &a, int m, unsigned grid, hipStream_t s) {
+    const int wpe = fixed_wpe();
+    switch (m) {
+        case 5: k_smm_f64_fixed<5, 5, 5, 8><<<grid, 64, 0, s>>>(a); break;
+        case 13: k_smm_f64_fixed<13, 13, 13, 8><<<grid, 64, 0, s>>>(a); break;
+        case 23:
+            if (wpe == 5) k_smm_f64_fixed<23, 23, 23, 5><<<grid, 64, 0, s>>>(a);
+            else if (wpe == 6) k_smm_f64_fixed<23, 23, 23, 6><<<grid, 64, 0, s>>>(a);
+            else k_smm_f64_fixed<23, 23, 23, 4><<<grid, 64, 0, s>>>(a);
+            break;
+        case 26: k_smm_f64_fixed<26, 26, 26, 3><<<grid, 64, 0, s>>>(a); break;
+        case 32: k_smm_f64_fixed<32, 32, 32, 2><<<grid, 64, 0, s>>>(a); break;
+        default: set_error("no fixed-shape kernel for %d", m); return BSM_EINVAL;
+    }
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s) {
     if (a.nC <= 0) return BSM_OK;
     const int64_t per = (a.nC + kXcds - 1) / kXcds;
@@ -277,6 +428,11 @@ int smm_launch(const SmmArgs &a, int variant, hipStream_t s) {
     }
     const size_t lds = sizeof(double) * (static_cast<size_t>(a.max_m) * a.max_k +
                                          static_cast<size_t>(a.max_k) * a.max_n);
+    if (variant == kSmmF64Fixed) {
+        if (a.uni_m && smm_fixed_available(a.uni_m, a.uni_n, a.uni_k))
+            return launch_fixed(a, a.uni_m, static_cast<unsigned>(grid), s);
+        variant = kSmmF64M4;   // mixed sizes: runtime-shape kernel
+    }
     if (variant == kSmmF64M4) {
         // tiles per half: ceil(ceil(max/4)/2)
         const int rt = (((a.max_m + 3) / 4) + 1) / 2, ct = (((a.max_n + 3) / 4) + 1) / 2;

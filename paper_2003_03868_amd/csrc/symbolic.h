@@ -24,6 +24,15 @@ struct SymArgs {
     const int32_t *c_in_col_idx;
 };
 
+// Tiled order of the C blocks (bands of `rb` block rows, column bands of
+// tile_cols() columns); writes worklist[c] for every C block.
+int tile_order(const int64_t *c_row_ptr, const int32_t *c_col_idx, int32_t nbrows,
+               int32_t nbcols, int rb, int64_t *worklist, hipStream_t s);
+// Tile shape (BSM_TILE_ROWS / BSM_TILE_COLS override the defaults 16 / 32;
+// BSM_TILE_ROWS=1 with BSM_TILE_COLS >= nbcols gives plain CSR order).
+int tile_rows();
+int tile_cols();
+
 int sym_count(const SymArgs &a, int64_t *c_cnt, int64_t *c_nval, int64_t *p_cnt, double *flops,
               hipStream_t s);
 int sym_pattern(const SymArgs &a, const int64_t *c_row_ptr, int32_t *c_col_idx, int32_t *c_row,

@@ -249,6 +249,91 @@ k_sym_stack(SymArgs a, int32_t r0, int32_t r1, const int64_t *c_row_ptr,
     if (i == r1 - 1 && threadIdx.x == 0) seg[c_row_ptr[r1] - c0] = p_row_ptr[r1] - p_base;
 }
 
+// Tiled work order of the C blocks of one band of `rb` block rows: C blocks
+// are grouped by column band (`wb` consecutive block columns), then by row,
+// then by column.  Waves that run together on one XCD then share A blocks
+// (same row) and B blocks (same column) in that XCD's L2.  worklist[pos] =
+// C block index, pos covering the band's C blocks in the new order.
+constexpr int kOrderMaxRows = 16;
+constexpr int kOrderMaxBands = 256;
+
+__global__ void __launch_bounds__(kSymThreads)
+k_tile_order(const int64_t *c_row_ptr, const int32_t *c_col_idx, int32_t nbrows, int rb, int wb,
+             int nbands, int64_t *worklist) {
+    __shared__ int32_t cnt[kOrderMaxRows * kOrderMaxBands];    // [row][band]
+    __shared__ int32_t start[kOrderMaxRows * kOrderMaxBands];  // position in band order
+    __shared__ int32_t rowpre[kOrderMaxRows * kOrderMaxBands]; // CSR offset in the row
+    __shared__ int32_t scratch[kSymWaves];
+    const int32_t i0 = blockIdx.x * rb;
+    const int32_t i1 = min(i0 + rb, nbrows);
+    const int nr = i1 - i0;
+    const int cells = nr * nbands;
+    for (int q = threadIdx.x; q < cells; q += kSymThreads) cnt[q] = 0;
+    __syncthreads();
+    const int64_t cb0 = c_row_ptr[i0];
+    for (int r = 0; r < nr; ++r)
+        for (int64_t c = c_row_ptr[i0 + r] + threadIdx.x; c < c_row_ptr[i0 + r + 1];
+             c += kSymThreads)
+            atomicAdd(&cnt[r * nbands + c_col_idx[c] / wb], 1);
+    __syncthreads();
+    // exclusive scan in (band, row) order -> start; along bands per row -> rowpre
+    const int per = (cells + kSymThreads - 1) / kSymThreads;
+    const int q0 = threadIdx.x * per;
+    int32_t local = 0;
+    for (int q = q0; q < q0 + per && q < cells; ++q) {
+        const int band = q / nr, r = q % nr;
+        local += cnt[r * nbands + band];
+    }
+    int32_t total;
+    int32_t run = wg_exscan(local, scratch, &total);
+    for (int q = q0; q < q0 + per && q < cells; ++q) {
+        const int band = q / nr, r = q % nr;
+        start[r * nbands + band] = run;
+        run += cnt[r * nbands + band];
+    }
+    if (threadIdx.x < nr) {
+        int32_t acc = 0;
+        for (int band = 0; band < nbands; ++band) {
+            rowpre[threadIdx.x * nbands + band] = acc;
+            acc += cnt[threadIdx.x * nbands + band];
+        }
+    }
+    __syncthreads();
+    for (int r = 0; r < nr; ++r) {
+        const int64_t rs = c_row_ptr[i0 + r];
+        for (int64_t c = rs + threadIdx.x; c < c_row_ptr[i0 + r + 1]; c += kSymThreads) {
+            const int band = c_col_idx[c] / wb;
+            const int64_t pos = start[r * nbands + band] + (c - rs - rowpre[r * nbands + band]);
+            worklist[cb0 + pos] = c;
+        }
+    }
+}
+
+int tile_order(const int64_t *c_row_ptr, const int32_t *c_col_idx, int32_t nbrows,
+               int32_t nbcols, int rb, int64_t *worklist, hipStream_t s) {
+    if (nbrows == 0) return BSM_OK;
+    if (rb < 1 || rb > kOrderMaxRows) { set_error("tile rows must be in [1, %d]", kOrderMaxRows); return BSM_EINVAL; }
+    int wb = tile_cols();
+    if ((nbcols + wb - 1) / wb > kOrderMaxBands) wb = (nbcols + kOrderMaxBands - 1) / kOrderMaxBands;
+    const int nbands = (nbcols + wb - 1) / wb;
+    const int nb = (nbrows + rb - 1) / rb;
+    k_tile_order<<<nb, kSymThreads, 0, s>>>(c_row_ptr, c_col_idx, nbrows, rb, wb, nbands,
+                                            worklist);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+int tile_rows() {
+    const char *e = getenv("BSM_TILE_ROWS");
+    const int v = e ? atoi(e) : 16;
+    return v < 1 ? 1 : (v > kOrderMaxRows ? kOrderMaxRows : v);
+}
+int tile_cols() {
+    const char *e = getenv("BSM_TILE_COLS");
+    const int v = e ? atoi(e) : 32;
+    return v < 1 ? 1 : v;
+}
+
 int sym_count(const SymArgs &a, int64_t *c_cnt, int64_t *c_nval, int64_t *p_cnt, double *flops,
               hipStream_t s) {
     if (a.nbrows == 0) return BSM_OK;

@@ -205,10 +205,10 @@ def test_reductions_vs_oracle(orc):
     assert_same_matrix(got, orc.shift_scale(m, 0.7, 0.25), 1e-15, "shift_scale")
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("maxb", [5, 13, 23, 26, 32])
 def test_multiply_kernel_variants(orc, monkeypatch, variant, maxb):
-    """Both FP64 block-product kernels (16x16 and 4x4 matrix-core tiles)
+    """All FP64 block-product kernels (16x16 tiles, 4x4 tiles, fixed shapes)
     against the oracle, uniform and mixed block sizes up to maxb."""
     monkeypatch.setenv("BSM_SMM_VARIANT", str(variant))
     for seed, uniform in [(31, True), (32, False)]:
