@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cpu-rows", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16"], default="fp64",
+                    help="block-product precision (fp32 / split-bf16 switch to FP64 once "
+                         "r_k < 1e-4)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -111,6 +114,7 @@ def main():
     opts = bsm.bsm_sign_opts_default()
     opts.eps_filter = args.eps
     opts.tol = args.tol
+    opts.prec = {"fp64": bsm.FP64, "fp32": bsm.FP32, "bf16": bsm.SPLIT_BF16}[args.prec]
     stream = torch.cuda.current_stream()
 
     def step():

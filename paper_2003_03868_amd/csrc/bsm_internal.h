@@ -53,8 +53,8 @@ void clear_error();
     } while (0)
 
 // --------------------------------------------------------------- memory
-// Stream-ordered device allocations (hipMallocAsync on the default pool,
-// whose release threshold is raised so memory is cached between calls).
+// Device allocations from the library's caching allocator (util.hip): blocks
+// freed on a stream are reused by later allocations on the same stream.
 int dalloc_bytes(void **p, size_t bytes, hipStream_t s);
 void dfree(void *p, hipStream_t s);
 template <class T>

@@ -207,6 +207,24 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     ma.seg = seg; ma.stk_a = stk_a; ma.stk_b = stk_b;
     ma.worklist = worklist;
 
+    if (st == BSM_OK && prec != BSM_FP64) {
+        if (!(A.uni_r && A.uni_c && B.uni_c && smm_lowp_available(A.uni_r, B.uni_c, A.uni_c))) {
+            set_error("reduced-precision products need uniform block sizes 5, 13, 23, 26 or 32");
+            st = BSM_EINVAL;
+        }
+        uint32_t *apk = nullptr, *bpk = nullptr;
+        if (st == BSM_OK) st = tmp.get(&apk, A.nvalues);
+        if (st == BSM_OK) st = pack_lowp(A.values, A.nvalues, apk, prec, s);
+        if (st == BSM_OK && &A != &B) {
+            st = tmp.get(&bpk, B.nvalues);
+            if (st == BSM_OK) st = pack_lowp(B.values, B.nvalues, bpk, prec, s);
+        } else {
+            bpk = apk;
+        }
+        ma.a_pk = apk;
+        ma.b_pk = bpk;
+    }
+
     for (size_t q = 0; st == BSM_OK && q + 1 < cuts.size(); ++q) {
         const int32_t r0 = cuts[q], r1 = cuts[q + 1];
         ma.c0 = h_crp[r0];
@@ -220,7 +238,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             BSM_HIP(hipEventCreate(&pe.second));
             BSM_HIP(hipEventRecord(pe.first, s));
         }
-        st = smm_launch(ma, smm_variant(), s);
+        st = (prec == BSM_FP64) ? smm_launch(ma, smm_variant(), s) : smm_launch_lowp(ma, s);
         if (ev.on) {
             BSM_HIP(hipEventRecord(pe.second, s));
             ev.smm.push_back(pe);

@@ -33,6 +33,7 @@ struct SmmArgs {
     const int32_t *k_size;      // A column block sizes
     const int64_t *b_blk_off;
     const double *b_vals;
+    const uint32_t *a_pk, *b_pk;  // packed reduced-precision operands (prec != FP64)
     const int64_t *cin_map;     // C_in block of every C block or -1; NULL when beta == 0
     const int64_t *cin_blk_off;
     const double *cin_vals;
@@ -47,5 +48,10 @@ struct SmmArgs {
 
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s);
 bool smm_fixed_available(int m, int n, int k);
+
+// Reduced-precision products (smm_lowp.hip).
+int pack_lowp(const double *v, int64_t n, uint32_t *out, int prec, hipStream_t s);
+bool smm_lowp_available(int m, int n, int k);
+int smm_launch_lowp(const SmmArgs &a, hipStream_t s);
 
 }  // namespace bsm

@@ -290,6 +290,7 @@ struct FixedShape {
     static constexpr int NB = (K * N + kWave - 1) / kWave;
 };
 
+// WPE: the occupancy (waves per SIMD) the register allocation aims for.
 template <int M, int N, int K, int WPE>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_smm_f64_fixed(SmmArgs a) {
@@ -393,23 +394,11 @@ bool smm_fixed_available(int m, int n, int k) {
     return (m == n && n == k) && (m == 5 || m == 13 || m == 23 || m == 26 || m == 32);
 }
 
-// Occupancy target of the fixed-shape kernels (waves per SIMD the register
-// allocation must allow); BSM_FIXED_WPE selects another compiled target.
-static int fixed_wpe() {
-    const char *e = getenv("BSM_FIXED_WPE");
-    return e ? atoi(e) : 0;
-}
-
 static int launch_fixed(const SmmArgs &a, int m, unsigned grid, hipStream_t s) {
-    const int wpe = fixed_wpe();
     switch (m) {
         case 5: k_smm_f64_fixed<5, 5, 5, 8><<<grid, 64, 0, s>>>(a); break;
         case 13: k_smm_f64_fixed<13, 13, 13, 8><<<grid, 64, 0, s>>>(a); break;
-        case 23:
-            if (wpe == 5) k_smm_f64_fixed<23, 23, 23, 5><<<grid, 64, 0, s>>>(a);
-            else if (wpe == 6) k_smm_f64_fixed<23, 23, 23, 6><<<grid, 64, 0, s>>>(a);
-            else k_smm_f64_fixed<23, 23, 23, 4><<<grid, 64, 0, s>>>(a);
-            break;
+        case 23: k_smm_f64_fixed<23, 23, 23, 4><<<grid, 64, 0, s>>>(a); break;
         case 26: k_smm_f64_fixed<26, 26, 26, 3><<<grid, 64, 0, s>>>(a); break;
         case 32: k_smm_f64_fixed<32, 32, 32, 2><<<grid, 64, 0, s>>>(a); break;
         default: set_error("no fixed-shape kernel for %d", m); return BSM_EINVAL;

@@ -1,0 +1,318 @@
+// Reduced-precision block products (the approximate-computing direction of
+// the paper: lower or mixed precision where FP64 accuracy is not needed,
+// "Approximate Computing" section and the DBCSR "Outlook").
+//
+// Two forms, both accumulating each block product in FP32 on the matrix
+// cores and adding it into an FP64 accumulator per C block (so the error of
+// one product does not grow with the length of the product stack); the
+// result, its norms and the filter stay FP64:
+//
+//  * FP32:       operands rounded to FP32; V_MFMA_F32_16X16X4_F32.
+//  * split-BF16: x = hi + lo with hi = bf16(x), lo = bf16(x - hi) (both
+//                round-to-nearest-even); A*B ~ lo*hi + hi*lo + hi*hi with
+//                V_MFMA_F32_32X32X16_BF16 (the lo*lo term is dropped).
+//
+// Operands are packed once per multiply into one 32-bit word per element:
+// the FP32 bits, or (hi << 16 | lo) for split-BF16.  Kernels exist for
+// uniform block sizes (compile-time shapes, up to 32).
+#include "smm.h"
+
+namespace bsm {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+
+// --------------------------------------------------------------- packing
+
+// Round-to-odd double -> float followed by round-to-nearest-even float ->
+// bf16 gives the correctly rounded (RNE) bf16 of the double: the float keeps
+// 24 significant bits, more than the 8 + 2 the second rounding needs.
+__device__ inline uint32_t bf16_rne(double x) {
+    float t = __double2float_rz(x);
+    if (static_cast<double>(t) != x) t = __uint_as_float(__float_as_uint(t) | 1u);
+    uint32_t u = __float_as_uint(t);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ inline double bf16_to_double(uint32_t h) {
+    return static_cast<double>(__uint_as_float(h << 16));
+}
+
+__global__ void k_pack_lowp(const double *v, int64_t n, uint32_t *out, int prec) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = v[i];
+    if (prec == BSM_FP32) {
+        out[i] = __float_as_uint(__double2float_rn(x));
+    } else {
+        const uint32_t hi = bf16_rne(x);
+        const uint32_t lo = bf16_rne(x - bf16_to_double(hi));
+        out[i] = (hi << 16) | lo;
+    }
+}
+
+int pack_lowp(const double *v, int64_t n, uint32_t *out, int prec, hipStream_t s) {
+    if (n == 0) return BSM_OK;
+    k_pack_lowp<<<grid_for(n, 256), 256, 0, s>>>(v, n, out, prec);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+__device__ inline int64_t lp_item(int64_t n_items) {
+    const int64_t per = (n_items + kXcds - 1) / kXcds;
+    return static_cast<int64_t>(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+
+__device__ inline double lp_wave_sum(double v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ inline double lp_wave_max(double v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Epilogue shared by both forms: out(row, col) for the lane's 16 slots.
+template <int M, int N, class RowCol>
+__device__ inline void lp_store(const SmmArgs &a, int64_t c, const double (&acc)[16],
+                                RowCol rc) {
+    const int64_t co = a.c_blk_off[c];
+    const double *cin = nullptr;
+    if (a.cin_map) {
+        const int64_t t = a.cin_map[c];
+        if (t >= 0) cin = a.cin_vals + a.cin_blk_off[t];
+    }
+    double sq = 0.0, mx = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        int row, col;
+        rc(q, row, col);
+        if (row < M && col < N) {
+            double v = a.alpha * acc[q];
+            if (cin) v += a.beta * cin[row * N + col];
+            a.c_vals[co + row * N + col] = v;
+            sq += v * v;
+            mx = fmax(mx, fabs(v));
+        }
+    }
+    sq = lp_wave_sum(sq);
+    mx = lp_wave_max(mx);
+    if (threadIdx.x == 0) {
+        a.sq_out[c] = sq;
+        a.mx_out[c] = mx;
+        if (!isfinite(sq)) atomicOr(a.flags, kFlagNonFinite);
+    }
+}
+
+// ------------------------------------------------------------ split-BF16
+// One wavefront per C block, the block padded to one 32 x 32 tile.
+// LDS: A_hi, A_lo as [32][LDK] and B_hi^T, B_lo^T as [32][LDK] (bf16), so
+// each lane reads its 8 consecutive k values with one 16-byte load.
+// Lane layout of V_MFMA_F32_32X32X16_BF16 (measured on gfx950):
+// A(i,k): lane i + 32*(k/8), element k%8; B(k,j): lane j + 32*(k/8),
+// element k%8; D(i,j): lane j + 32*((i/4)%2), register 4*(i/8) + i%4.
+template <int M, int N, int K>
+__global__ void __launch_bounds__(64)
+k_smm_bf16x3(SmmArgs a) {
+    constexpr int LDK = 40;                         // 80-byte rows: conflict-free 16 B reads
+    constexpr int PLANE = 32 * LDK;
+    constexpr int KS = (K + 15) / 16;
+    constexpr int NA = (M * K + kWave - 1) / kWave, NB = (K * N + kWave - 1) / kWave;
+    __shared__ __attribute__((aligned(16))) unsigned short sm[4 * PLANE];
+    unsigned short *ahi = sm, *alo = sm + PLANE, *bhi = sm + 2 * PLANE, *blo = sm + 3 * PLANE;
+    const int64_t item = lp_item(a.nC);
+    if (item >= a.nC) return;
+    const int lane = threadIdx.x;
+    const int64_t c = a.worklist ? a.worklist[a.c0 + item] : a.c0 + item;
+    for (int e = lane; e < 4 * PLANE; e += kWave) sm[e] = 0;
+
+    int oa[NA], ob[NB];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        const int e = lane + q * kWave;
+        oa[q] = (e < M * K) ? (e / K) * LDK + (e % K) : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int e = lane + q * kWave;
+        ob[q] = (e < K * N) ? (e % N) * LDK + (e / N) : -1;
+    }
+    const int r32 = lane & 31, h = lane >> 5;
+
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+
+    const int64_t p0 = a.seg[c - a.c0], p_end = a.seg[c - a.c0 + 1];
+    uint32_t pa[NA], pb[NB];
+    auto prefetch = [&](int64_t p) {
+        const uint32_t *ga = a.a_pk + a.a_blk_off[a.stk_a[p]];
+        const uint32_t *gb = a.b_pk + a.b_blk_off[a.stk_b[p]];
+#pragma unroll
+        for (int q = 0; q < NA; ++q) pa[q] = (oa[q] >= 0) ? ga[lane + q * kWave] : 0u;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) pb[q] = (ob[q] >= 0) ? gb[lane + q * kWave] : 0u;
+    };
+    if (p0 < p_end) prefetch(p0);
+    __syncthreads();
+    for (int64_t p = p0; p < p_end; ++p) {
+#pragma unroll
+        for (int q = 0; q < NA; ++q)
+            if (oa[q] >= 0) {
+                ahi[oa[q]] = static_cast<unsigned short>(pa[q] >> 16);
+                alo[oa[q]] = static_cast<unsigned short>(pa[q] & 0xFFFFu);
+            }
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (ob[q] >= 0) {
+                bhi[ob[q]] = static_cast<unsigned short>(pb[q] >> 16);
+                blo[ob[q]] = static_cast<unsigned short>(pb[q] & 0xFFFFu);
+            }
+        __syncthreads();
+        if (p + 1 < p_end) prefetch(p + 1);
+        f16v part = {};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int off_a = r32 * LDK + 16 * ks + 8 * h;
+            const us8 xah = *reinterpret_cast<const us8 *>(ahi + off_a);
+            const us8 xal = *reinterpret_cast<const us8 *>(alo + off_a);
+            const us8 xbh = *reinterpret_cast<const us8 *>(bhi + off_a);
+            const us8 xbl = *reinterpret_cast<const us8 *>(blo + off_a);
+            const bf8 vah = __builtin_bit_cast(bf8, xah), val = __builtin_bit_cast(bf8, xal);
+            const bf8 vbh = __builtin_bit_cast(bf8, xbh), vbl = __builtin_bit_cast(bf8, xbl);
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(val, vbh, part, 0, 0, 0);
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbl, part, 0, 0, 0);
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbh, part, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] += static_cast<double>(part[q]);
+        __syncthreads();
+    }
+    lp_store<M, N>(a, c, acc, [&](int q, int &row, int &col) {
+        row = 8 * (q >> 2) + 4 * h + (q & 3);
+        col = r32;
+    });
+}
+
+// ------------------------------------------------------------------ FP32
+// One wavefront per C block as a 2 x 2 grid of 16 x 16 tiles.
+// Lane layout of V_MFMA_F32_16X16X4_F32 (measured on gfx950):
+// A(i,k): lane i + 16k; B(k,j): lane j + 16k; D(i,j): lane j + 16*(i/4),
+// register i%4.
+template <int M, int N, int K>
+__global__ void __launch_bounds__(64)
+k_smm_f32(SmmArgs a) {
+    constexpr int LDA = 33, LDB = 32;               // A rows in distinct banks
+    constexpr int KP = 4 * ((K + 3) / 4);
+    constexpr int MT = (M + 15) / 16, NT = (N + 15) / 16;
+    constexpr int NA = (M * K + kWave - 1) / kWave, NB = (K * N + kWave - 1) / kWave;
+    __shared__ float sA[32 * LDA];
+    __shared__ float sB[KP * LDB];
+    const int64_t item = lp_item(a.nC);
+    if (item >= a.nC) return;
+    const int lane = threadIdx.x;
+    const int64_t c = a.worklist ? a.worklist[a.c0 + item] : a.c0 + item;
+    for (int e = lane; e < 32 * LDA; e += kWave) sA[e] = 0.f;
+    for (int e = lane; e < KP * LDB; e += kWave) sB[e] = 0.f;
+    int oa[NA], ob[NB];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        const int e = lane + q * kWave;
+        oa[q] = (e < M * K) ? (e / K) * LDA + (e % K) : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int e = lane + q * kWave;
+        ob[q] = (e < K * N) ? (e / N) * LDB + (e % N) : -1;
+    }
+    const int r16 = lane & 15, kq = lane >> 4;
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+
+    const int64_t p0 = a.seg[c - a.c0], p_end = a.seg[c - a.c0 + 1];
+    uint32_t pa[NA], pb[NB];
+    auto prefetch = [&](int64_t p) {
+        const uint32_t *ga = a.a_pk + a.a_blk_off[a.stk_a[p]];
+        const uint32_t *gb = a.b_pk + a.b_blk_off[a.stk_b[p]];
+#pragma unroll
+        for (int q = 0; q < NA; ++q) pa[q] = (oa[q] >= 0) ? ga[lane + q * kWave] : 0u;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) pb[q] = (ob[q] >= 0) ? gb[lane + q * kWave] : 0u;
+    };
+    if (p0 < p_end) prefetch(p0);
+    __syncthreads();
+    for (int64_t p = p0; p < p_end; ++p) {
+#pragma unroll
+        for (int q = 0; q < NA; ++q)
+            if (oa[q] >= 0) sA[oa[q]] = __uint_as_float(pa[q]);
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (ob[q] >= 0) sB[ob[q]] = __uint_as_float(pb[q]);
+        __syncthreads();
+        if (p + 1 < p_end) prefetch(p + 1);
+        f4 part[2][2] = {};
+#pragma unroll
+        for (int ks = 0; ks < KP / 4; ++ks) {
+            float av[2], bv[2];
+#pragma unroll
+            for (int t = 0; t < MT; ++t) av[t] = sA[(16 * t + r16) * LDA + 4 * ks + kq];
+#pragma unroll
+            for (int u = 0; u < NT; ++u) bv[u] = sB[(4 * ks + kq) * LDB + 16 * u + r16];
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                for (int u = 0; u < NT; ++u)
+                    part[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[u], part[t][u],
+                                                                      0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[(t * 2 + u) * 4 + r] += static_cast<double>(part[t][u][r]);
+        __syncthreads();
+    }
+    lp_store<M, N>(a, c, acc, [&](int q, int &row, int &col) {
+        const int tile = q >> 2, r = q & 3;
+        const int t = tile >> 1, u = tile & 1;
+        row = 16 * t + 4 * kq + r;
+        col = 16 * u + r16;
+        if (t >= MT || u >= NT) row = 1 << 20;   // tile not present
+    });
+}
+
+bool smm_lowp_available(int m, int n, int k) {
+    return (m == n && n == k) && (m == 5 || m == 13 || m == 23 || m == 26 || m == 32);
+}
+
+int smm_launch_lowp(const SmmArgs &a, hipStream_t s) {
+    if (a.nC <= 0) return BSM_OK;
+    const int64_t per = (a.nC + kXcds - 1) / kXcds;
+    const unsigned grid = static_cast<unsigned>(per * kXcds);
+    if (!(a.uni_m && smm_lowp_available(a.uni_m, a.uni_n, a.uni_k))) {
+        set_error("reduced-precision products need uniform block sizes 5, 13, 23, 26 or 32");
+        return BSM_EINVAL;
+    }
+#define BSM_LP(SZ)                                                                  \
+    case SZ:                                                                        \
+        if (a.prec == BSM_FP32) k_smm_f32<SZ, SZ, SZ><<<grid, 64, 0, s>>>(a);       \
+        else k_smm_bf16x3<SZ, SZ, SZ><<<grid, 64, 0, s>>>(a);                       \
+        break;
+    switch (a.uni_m) {
+        BSM_LP(5)
+        BSM_LP(13)
+        BSM_LP(23)
+        BSM_LP(26)
+        BSM_LP(32)
+        default: break;
+    }
+#undef BSM_LP
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+}  // namespace bsm

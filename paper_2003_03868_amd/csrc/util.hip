@@ -1,8 +1,10 @@
-// Error state, stream-ordered device memory, prefix scan, block offsets and
+// Error state, the caching device allocator, prefix scan, block offsets and
 // the canonical-form check of blocked-CSR matrices.
 #include <cstdarg>
 #include <cstdio>
+#include <map>
 #include <mutex>
+#include <unordered_map>
 
 #include "bsm_internal.h"
 
@@ -22,35 +24,85 @@ void clear_error() { g_err.clear(); }
 const char *last_error() { return g_err.c_str(); }
 
 // ----------------------------------------------------------------- memory
+// Caching device allocator.  Freed blocks go to a free list of the stream
+// they were released on and are handed out again (best fit, at most 1.25x
+// the request) to later requests on that stream: stream order makes the
+// reuse safe without synchronisation.  hipMalloc runs only when no cached
+// block fits; when it fails, cached blocks are returned to the runtime and
+// the allocation is retried once.  Sizes are rounded (256 B below 1 MiB,
+// 2 MiB above) so similar requests share blocks.
 
-static std::once_flag g_pool_once[64];
+namespace {
+struct AllocCache {
+    std::mutex mu;
+    // (device, stream) -> size -> pointers
+    std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void *>> free_lists;
+    std::unordered_map<void *, std::pair<int, size_t>> live;   // ptr -> (device, size)
+};
+AllocCache &cache() {
+    static AllocCache *c = new AllocCache;   // never destroyed: runtime teardown order
+    return *c;
+}
+size_t round_size(size_t b) {
+    if (b < (size_t{1} << 20)) return (b + 255) & ~size_t{255};
+    const size_t g = size_t{2} << 20;
+    return (b + g - 1) / g * g;
+}
+}  // namespace
 
-static void raise_pool_threshold(int dev) {
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+static void release_cached(int dev) {
+    AllocCache &c = cache();
+    std::vector<void *> victims;
+    for (auto &kv : c.free_lists) {
+        if (kv.first.first != dev) continue;
+        for (auto &e : kv.second) victims.push_back(e.second);
+        kv.second.clear();
+    }
+    if (victims.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (void *p : victims) {
+        c.live.erase(p);
+        (void)hipFree(p);
     }
 }
 
 int dalloc_bytes(void **p, size_t bytes, hipStream_t s) {
     int dev = 0;
     BSM_HIP(hipGetDevice(&dev));
-    if (dev >= 0 && dev < 64) std::call_once(g_pool_once[dev], raise_pool_threshold, dev);
+    const size_t want = round_size(bytes == 0 ? 256 : bytes);
+    AllocCache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto &fl = c.free_lists[{dev, s}];
+    auto it = fl.lower_bound(want);
+    if (it != fl.end() && it->first <= want + want / 4) {
+        *p = it->second;
+        fl.erase(it);
+        return BSM_OK;
+    }
     *p = nullptr;
-    if (bytes == 0) bytes = 256;
-    hipError_t e = hipMallocAsync(p, bytes, s);
+    hipError_t e = hipMalloc(p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        release_cached(dev);
+        e = hipMalloc(p, want);
+    }
     if (e != hipSuccess || *p == nullptr) {
         (void)hipGetLastError();
         set_error("device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
         *p = nullptr;
         return BSM_ENOMEM;
     }
+    c.live[*p] = {dev, want};
     return BSM_OK;
 }
 
 void dfree(void *p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
+    if (!p) return;
+    AllocCache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;   // not ours
+    c.free_lists[{it->second.first, s}].emplace(it->second.second, p);
 }
 
 void free_mat_arrays(Mat &m, hipStream_t s) {

@@ -1,0 +1,76 @@
+"""Reduced-precision block products (FP32, split-BF16 on the matrix cores)
+and the mixed-precision sign iteration, against the FP64 oracle.
+
+Tolerances come from the arithmetic: FP32 operands carry a relative error
+of 2^-24 and a block product of k <= 32 terms accumulates a few more units,
+so a multiply stays within 2e-6 relative Frobenius error; split-BF16 keeps
+about 2^-17 of each operand and drops the lo*lo term (<= 2^-18 relative),
+so a multiply stays within 3e-5.  The sign iteration switches to FP64
+products once r_k < 1e-4, and Newton-Schulz contracts the low-precision
+error quadratically, so X must match the FP64 oracle within 1e-6."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import TOL_MIXED, from_dev, need_gpu, rel_fro, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_MULT = {1: 2e-6, 2: 3e-5}   # bsm precision code -> relative Frobenius bound
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "split_bf16"])
+@pytest.mark.parametrize("b", [5, 13, 23, 26, 32])
+def test_lowp_multiply_error_bound(orc, prec, b):
+    from paper_2003_03868_amd import bsm
+    rng = np.random.default_rng(100 + b)
+    a = synth.random_bsr(10, 10, b, b, 0.5, rng)
+    bb = synth.random_bsr(10, 10, b, b, 0.5, rng)
+    c = synth.random_bsr(10, 10, b, b, 0.3, rng)
+    ref = orc.multiply(-0.5, a, bb, 1.5, c)
+    da, db, dc = to_dev(a), to_dev(bb), to_dev(c)
+    bsm.bsm_multiply(-0.5, da.handle, db.handle, 1.5, dc.handle, 0.0, bsm.NORM_FROB, prec)
+    got = from_dev(dc)
+    assert np.array_equal(got.col_idx, ref.col_idx) and np.array_equal(got.row_ptr, ref.row_ptr)
+    err = rel_fro(got.values, ref.values)
+    print(f"prec {prec} b {b}: rel err {err:.2e}")
+    assert err <= TOL_MULT[prec]
+    assert err > 0.0          # really ran in reduced precision
+
+
+def test_lowp_rejects_mixed_sizes(orc):
+    from paper_2003_03868_amd import bsm
+    rng = np.random.default_rng(5)
+    sz = rng.integers(1, 20, 6)
+    a = synth.random_bsr(6, 6, sz, sz, 0.5, rng)
+    da = to_dev(a)
+    dc = bsm.Matrix.empty_like(sz, sz)
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.bsm_multiply(1.0, da.handle, da.handle, 0.0, dc.handle, 0.0, bsm.NORM_FROB, 2)
+    assert e.value.status == bsm.EINVAL
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "split_bf16"])
+def test_mixed_precision_sign_vs_fp64_oracle(orc, prec):
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(100, 23, cutoff=4.2, seed=6)
+    x_ref, st_ref, _ = orc.sign_ns(h, eps=1e-6, tol=1e-8)
+    d = to_dev(h)
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol, o.prec = 1e-6, 1e-8, prec
+    st, xh, stats = bsm.bsm_sign_iterate(d.handle, 0.0, o)
+    assert st == bsm.OK, bsm.bsm_last_error()
+    x = from_dev(bsm.Matrix(xh, h.row_blk_size, h.col_blk_size))
+    used = list(stats.prec_hist)[:stats.iterations + 1]
+    assert used[0] == prec and used[-1] == bsm.FP64
+    dx, dr = x.to_dense(), x_ref.to_dense()
+    err = rel_fro(dx, dr)
+    print(f"prec {prec}: iterations {stats.iterations} (oracle {st_ref['iterations']}), "
+          f"precisions {used}, rel err {err:.2e}, trace(P) {stats.trace_p:.10f}")
+    assert err <= TOL_MIXED
+    assert abs(stats.trace_p - h.meta["n_occ"]) < 1e-4
