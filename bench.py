@@ -61,6 +61,20 @@ def cpu_baseline(h, rows: int):
                        f"the iteration), eps 1e-6, {flops / 1e9:.1f} GFLOP in {dt:.1f} s")
 
 
+def measured_traffic(kernel_src: str, workload: str):
+    """HBM bytes per launch of the block-product kernel from the committed
+    rocprofv3 counter summary, or None when the kernel source has changed
+    since the counters were taken (or none were taken for this workload)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    try:
+        d = json.load(open(path))
+        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return d["hbm_bytes_per_launch"] if d.get("source_sha256") == sha else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,12 +203,16 @@ def main():
         "nnzb_X_final": int(s0.nnzb_final),
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_smm_f64_mfma",
+            "kernel": "k_smm_f64_fixed<23,23,23>" if args.prec == "fp64" else "k_smm_lowp",
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(
+                os.path.join(ROOT, "paper_2003_03868_amd", "csrc", "smm.hip"), "sign23")
+            if (args.prec == "fp64" and args.sites == 2048 and args.eps == 1e-6) else None,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, "
+                            "profiles/k_smm_f64_fixed_sign23.md)",
             "smm_ms_per_step": smm_ms / args.steps,
         },
         "cpu_baseline": cpu,
