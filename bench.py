@@ -81,7 +81,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--sites", type=int, default=2048)
+    ap.add_argument("--workload", choices=["sign23", "mixed"], default="sign23",
+                    help="sign23: 2048 sites x 23; mixed: 4096 sites, sizes {5,13,23,26}")
+    ap.add_argument("--sites", type=int, default=0, help="override the site count")
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cpu-rows", type=int, default=512)
@@ -119,7 +121,13 @@ def main():
     torch.cuda.set_device(0)
 
     t0 = time.perf_counter()
-    h = synth.neighbour_hamiltonian(args.sites, 23, density=0.1, cutoff=6.0, seed=args.seed)
+    if args.workload == "sign23":
+        args.sites = args.sites or 2048
+        h = synth.neighbour_hamiltonian(args.sites, 23, density=0.1, cutoff=6.0, seed=args.seed)
+    else:
+        args.sites = args.sites or 4096
+        h = synth.neighbour_hamiltonian(args.sites, density=0.1, cutoff=6.0, seed=args.seed,
+                                        size_choices=(5, 13, 23, 26))
     log(f"generated H: {h.nbrows} sites, {h.nnzb} blocks, n_occ {h.meta['n_occ']} "
         f"({time.perf_counter() - t0:.1f} s)")
     dh = bsm.Matrix.from_bsr(h, device=True)
@@ -166,7 +174,7 @@ def main():
     achieved = flops / (smm_ms * 1e-3) / 1e12 if smm_ms > 0 else 0.0
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "sign23":
         log("timing the CPU oracle on a sample ...")
         cpu = cpu_baseline(h, min(args.cpu_rows, h.nbrows))
         log(f"cpu baseline: {cpu['value']:.2f} GFLOP/s on {cpu['cores']} threads")
@@ -186,10 +194,14 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "FP64 Newton-Schulz sign iteration, 2048-site neighbour-list "
-                        "Hamiltonian, 23x23 blocks, cutoff 6 A, 0.1 sites/A^3, "
-                        "eps_filter 1e-6, to ||X^2-I||_F/n < 1e-6",
-            "n_sites": h.nbrows, "block": 23, "n": int(n), "eps_filter": args.eps,
+            "workload": (f"{args.prec.upper()} Newton-Schulz sign iteration, {h.nbrows}-site "
+                         "neighbour-list Hamiltonian, "
+                         + ("23x23 blocks" if args.workload == "sign23"
+                            else "block sizes {5,13,23,26}") +
+                         f", cutoff 6 A, 0.1 sites/A^3, eps_filter {args.eps:g}, "
+                         f"to ||X^2-I||_F/n < {args.tol:g}"),
+            "n_sites": h.nbrows, "block": 23 if args.workload == "sign23" else "5/13/23/26",
+            "n": int(n), "eps_filter": args.eps,
             "tol": args.tol, "seed": args.seed, "nnzb_H": h.nnzb,
         },
         "time_to_sign_ms": ms_per_step,
@@ -210,7 +222,8 @@ def main():
             "frac": achieved / PEAK_FP64_TFLOPS,
             "traffic": measured_traffic(
                 os.path.join(ROOT, "paper_2003_03868_amd", "csrc", "smm.hip"), "sign23")
-            if (args.prec == "fp64" and args.sites == 2048 and args.eps == 1e-6) else None,
+            if (args.prec == "fp64" and args.workload == "sign23" and args.sites == 2048
+                and args.eps == 1e-6) else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, "
                             "profiles/k_smm_f64_fixed_sign23.md)",
             "smm_ms_per_step": smm_ms / args.steps,

@@ -34,6 +34,17 @@ static int smm_variant() {
     return e ? atoi(e) : kSmmF64Fixed;
 }
 
+// Kernel family for a chunk with mixed block sizes (uniform sizes keep the
+// requested variant).  Default: per-class launches when every size is in
+// {5, 13, 23, 26}, else the fused persistent kernel.
+static int mixed_variant(const SmmArgs &a, int requested) {
+    const bool uniform = a.uni_m && a.uni_n && a.uni_k;
+    if (uniform) return requested;
+    if (requested == kSmmF64Class && !a.fused_ok) return kSmmF64Fused;
+    if (requested == kSmmF64Fixed) return a.fused_ok ? kSmmF64Class : kSmmF64Fused;
+    return requested;
+}
+
 namespace {
 struct Events {
     bool on = false;
@@ -165,8 +176,10 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     // 5. tiled work order, then chunks of whole row bands with a bounded
     //    number of products
     const int rb = tile_rows();
-    int64_t *worklist = nullptr;
+    const int variant = smm_variant();
+    int64_t *worklist = nullptr, *worklist2 = nullptr;
     if (st == BSM_OK) st = tmp.get(&worklist, nnzb_c);
+    if (st == BSM_OK) st = tmp.get(&worklist2, nnzb_c);   // target of the work-list sorts
     if (st == BSM_OK) st = tile_order(c_row_ptr, nc.col_idx, nbr, B.nbcols, rb, worklist, s);
     std::vector<int32_t> cuts{0};
     {
@@ -203,6 +216,14 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     ma.sq_out = sq; ma.mx_out = mx; ma.flags = flags;
     ma.max_m = A.max_rbs; ma.max_n = B.max_cbs; ma.max_k = A.max_cbs;
     ma.uni_m = A.uni_r; ma.uni_n = B.uni_c; ma.uni_k = A.uni_c;
+    {
+        auto in_set = [](const std::vector<int32_t> &v) {
+            for (int32_t b : v)
+                if (b != 5 && b != 13 && b != 23 && b != 26) return false;
+            return true;
+        };
+        ma.fused_ok = (in_set(A.h_rbs) && in_set(A.h_cbs) && in_set(B.h_cbs)) ? 1 : 0;
+    }
     ma.prec = prec;
     ma.seg = seg; ma.stk_a = stk_a; ma.stk_b = stk_b;
     ma.worklist = worklist;
@@ -232,13 +253,41 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         if (ma.nC == 0) continue;
         st = sym_stack(sa, r0, r1, c_row_ptr, p_row_ptr, seg, stk_a, stk_b, s);
         if (st != BSM_OK) break;
+        // mixed sizes: cost-sorted list for the fused persistent launch, or
+        // class-sorted list for one launch per (m, n) class
+        const int var = (prec == BSM_FP64) ? mixed_variant(ma, variant) : -1;
+        int64_t hist[64] = {0};
+        if (var == kSmmF64Fused || var == kSmmF64Class) {
+            if (worklist2 == nullptr) { set_error("internal: no sort buffer"); st = BSM_EDEVICE; break; }
+            st = sort_worklist(worklist, worklist2, ma.c0, ma.nC,
+                               var == kSmmF64Fused ? kKeyCost : kKeyClass, c_row, nc.col_idx,
+                               A.rbs, B.cbs, seg, var == kSmmF64Class ? hist : nullptr, s);
+            if (st != BSM_OK) break;
+            ma.worklist = worklist2;
+        } else {
+            ma.worklist = worklist;
+        }
         std::pair<hipEvent_t, hipEvent_t> pe{};
         if (ev.on) {
             BSM_HIP(hipEventCreate(&pe.first));
             BSM_HIP(hipEventCreate(&pe.second));
             BSM_HIP(hipEventRecord(pe.first, s));
         }
-        st = (prec == BSM_FP64) ? smm_launch(ma, smm_variant(), s) : smm_launch_lowp(ma, s);
+        if (prec != BSM_FP64) {
+            st = smm_launch_lowp(ma, s);
+        } else if (var == kSmmF64Class) {
+            SmmArgs cls = ma;
+            int64_t off = 0;
+            for (int b = 0; b < 17 && st == BSM_OK; ++b) {
+                if (hist[b] == 0) continue;
+                cls.worklist = worklist2 + off;
+                cls.nC = hist[b];
+                st = (b < 16) ? launch_class(cls, b, s) : smm_launch(cls, kSmmF64M4, s);
+                off += hist[b];
+            }
+        } else {
+            st = smm_launch(ma, var, s);
+        }
         if (ev.on) {
             BSM_HIP(hipEventRecord(pe.second, s));
             ev.smm.push_back(pe);

@@ -11,8 +11,12 @@ constexpr int kFlagNonFinite = 1;
 enum SmmVariant {
     kSmmF64M16 = 0,   // V_MFMA_F64_16X16X4_F64, 16 x 16 tiles
     kSmmF64M4 = 1,    // V_MFMA_F64_4X4X4_4B_F64, 4 x 4 tiles, run-time shapes
-    kSmmF64Fixed = 2, // same instruction, compile-time uniform shapes (default;
-                      // falls back to kSmmF64M4 for other shapes)
+    kSmmF64Fixed = 2, // same instruction, compile-time uniform shapes (default
+                      // for uniform sizes)
+    kSmmF64Fused = 3, // persistent kernel: all (m, n) classes of a chunk in one
+                      // launch, cost-sorted work queue, run-time shapes
+    kSmmF64Class = 4, // one launch per (m, n) class of {5,13,23,26}^2 with an
+                      // (m, n)-specialised kernel, run-time k
 };
 
 struct SmmArgs {
@@ -43,11 +47,15 @@ struct SmmArgs {
     int *flags;                 // kFlagNonFinite
     int32_t max_m, max_n, max_k;
     int32_t uni_m, uni_n, uni_k;  // uniform block sizes, 0 if mixed
+    int32_t fused_ok;             // every block size is in {5, 13, 23, 26}
+    int32_t pad_;
     int32_t prec;               // bsm_precision
 };
 
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s);
 bool smm_fixed_available(int m, int n, int k);
+int class_of_size(int b);                       // 0..3 for 5, 13, 23, 26; else -1
+int launch_class(const SmmArgs &a, int cls, hipStream_t s);   // cls = 4*class(m)+class(n)
 
 // Reduced-precision products (smm_lowp.hip).
 int pack_lowp(const double *v, int64_t n, uint32_t *out, int prec, hipStream_t s);

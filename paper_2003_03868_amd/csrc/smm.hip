@@ -154,18 +154,13 @@ k_smm_f64_mfma(SmmArgs a) {
 // The next product's two operand blocks are prefetched into registers with
 // contiguous loads while the current one is multiplied.
 template <int RT, int CT>
-__global__ void __launch_bounds__(64)
-k_smm_f64_m4(SmmArgs a) {
+__device__ inline void m4_cblock(const SmmArgs &a, int64_t c, double *sm) {
     constexpr int kMaxM = 8 * RT, kMaxN = 8 * CT, kMaxK = kMaxBlock;
     constexpr int NA = (kMaxM * kMaxK + kWave - 1) / kWave;   // A doubles per lane
     constexpr int NB = (kMaxK * kMaxN + kWave - 1) / kWave;   // B doubles per lane
-    extern __shared__ double sm[];
-    const int64_t item = xcd_item(a.nC);
-    if (item >= a.nC) return;
     const int lane = threadIdx.x;
     const int x = lane >> 4, blk = (lane >> 2) & 3, y = lane & 3;
     const int bh = blk >> 1, bw = blk & 1;
-    const int64_t c = a.worklist ? a.worklist[a.c0 + item] : a.c0 + item;
     const int m = a.c_rbs[a.c_row[c]], n = a.c_cbs[a.c_col[c]];
     const int hr = (((m + 3) >> 2) + 1) >> 1;      // row tiles per half
     const int hc = (((n + 3) >> 2) + 1) >> 1;      // column tiles per half
@@ -265,6 +260,16 @@ k_smm_f64_m4(SmmArgs a) {
         a.mx_out[c] = mx;
         if (!isfinite(sq)) atomicOr(a.flags, kFlagNonFinite);
     }
+    __syncthreads();   // LDS is reused by the next C block of a persistent wave
+}
+
+template <int RT, int CT>
+__global__ void __launch_bounds__(64)
+k_smm_f64_m4(SmmArgs a) {
+    extern __shared__ double sm[];
+    const int64_t item = xcd_item(a.nC);
+    if (item >= a.nC) return;
+    m4_cblock<RT, CT>(a, a.worklist ? a.worklist[a.c0 + item] : a.c0 + item, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -389,6 +394,168 @@ k_smm_f64_fixed(SmmArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Per-(m, n)-class FP64 kernel with run-time k: M and N are compile-time, the
+// k of each product is read from the stack.  Launched once per class over the
+// class's contiguous range of the class-sorted work list.  LDS holds the two
+// operand blocks contiguously (as in HBM) plus a zeroed tail; lanes whose k
+// index passes the product's k read zero.
+constexpr int kClassKmax = 26;   // largest k of the class set {5, 13, 23, 26}
+
+template <int M, int N>
+__global__ void __launch_bounds__(64)
+k_smm_f64_class(SmmArgs a) {
+    constexpr int MT = (M + 3) / 4, NT = (N + 3) / 4;
+    constexpr int HR = (MT + 1) / 2, HC = (NT + 1) / 2;
+    constexpr int NA = (M * kClassKmax + kWave - 1) / kWave;
+    constexpr int NB = (kClassKmax * N + kWave - 1) / kWave;
+    constexpr int TAIL = 4 * kClassKmax + 8 * N + 8;
+    __shared__ double sm[M * kClassKmax + kClassKmax * N + TAIL];
+    const int64_t item = xcd_item(a.nC);
+    if (item >= a.nC) return;
+    const int64_t c = a.worklist[a.c0 + item];
+    const int lane = threadIdx.x;
+    const int x = lane >> 4, blk = (lane >> 2) & 3, y = lane & 3;
+    const int bh = blk >> 1, bw = blk & 1;
+    double acc[HR][HC];
+#pragma unroll
+    for (int t = 0; t < HR; ++t)
+#pragma unroll
+        for (int u = 0; u < HC; ++u) acc[t][u] = 0.0;
+    const int64_t p0 = a.seg[c - a.c0], p_end = a.seg[c - a.c0 + 1];
+    double pa[NA], pb[NB];
+    int kn = 0;
+    auto prefetch = [&](int64_t p) {
+        const int32_t ta = a.stk_a[p];
+        kn = a.k_size[a.a_col_idx[ta]];
+        const double *ga = a.a_vals + a.a_blk_off[ta];
+        const double *gb = a.b_vals + a.b_blk_off[a.stk_b[p]];
+#pragma unroll
+        for (int q = 0; q < NA; ++q)
+            if (lane + q * kWave < M * kn) pa[q] = ga[lane + q * kWave];
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (lane + q * kWave < kn * N) pb[q] = gb[lane + q * kWave];
+    };
+    if (p0 < p_end) prefetch(p0);
+    for (int64_t p = p0; p < p_end; ++p) {
+        const int k = kn;
+        double *sA = sm, *sB = sm + M * k;
+        __syncthreads();                       // previous product's reads are done
+#pragma unroll
+        for (int q = 0; q < NA; ++q)
+            if (lane + q * kWave < M * k) sA[lane + q * kWave] = pa[q];
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (lane + q * kWave < k * N) sB[lane + q * kWave] = pb[q];
+        for (int e = M * k + k * N + lane; e < M * k + k * N + TAIL; e += kWave) sm[e] = 0.0;
+        __syncthreads();
+        if (p + 1 < p_end) prefetch(p + 1);
+        int ra[HR];
+#pragma unroll
+        for (int t = 0; t < HR; ++t) ra[t] = (4 * (bh * HR + t) + y) * k + x;
+        const int rb = x * N + 4 * bw * HC + y;
+#pragma unroll 1
+        for (int ks = 0; 4 * ks < k; ++ks) {
+            const bool ok = 4 * ks + x < k;
+            double av[HR], bv[HC];
+#pragma unroll
+            for (int t = 0; t < HR; ++t) av[t] = ok ? sA[ra[t] + 4 * ks] : 0.0;
+#pragma unroll
+            for (int u = 0; u < HC; ++u) bv[u] = ok ? sB[rb + 4 * u + 4 * ks * N] : 0.0;
+#pragma unroll
+            for (int t = 0; t < HR; ++t)
+#pragma unroll
+                for (int u = 0; u < HC; ++u)
+                    acc[t][u] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[t], bv[u], acc[t][u], 0, 0, 0);
+        }
+    }
+    const int64_t co = a.c_blk_off[c];
+    const double *cin = nullptr;
+    if (a.cin_map) {
+        const int64_t t = a.cin_map[c];
+        if (t >= 0) cin = a.cin_vals + a.cin_blk_off[t];
+    }
+    double sq = 0.0, mx = 0.0;
+#pragma unroll
+    for (int t = 0; t < HR; ++t)
+#pragma unroll
+        for (int u = 0; u < HC; ++u) {
+            const int row = 4 * (bh * HR + t) + x, col = 4 * (bw * HC + u) + y;
+            if (row < M && col < N) {
+                double v = a.alpha * acc[t][u];
+                if (cin) v += a.beta * cin[row * N + col];
+                a.c_vals[co + row * N + col] = v;
+                sq += v * v;
+                mx = fmax(mx, fabs(v));
+            }
+        }
+    sq = wave_sum(sq);
+    mx = wave_max(mx);
+    if (lane == 0) {
+        a.sq_out[c] = sq;
+        a.mx_out[c] = mx;
+        if (!isfinite(sq)) atomicOr(a.flags, kFlagNonFinite);
+    }
+}
+
+int class_of_size(int b) { return b == 5 ? 0 : b == 13 ? 1 : b == 23 ? 2 : b == 26 ? 3 : -1; }
+
+int launch_class(const SmmArgs &a, int cls, hipStream_t s) {
+    if (a.nC <= 0) return BSM_OK;
+    const int64_t per = (a.nC + kXcds - 1) / kXcds;
+    const unsigned grid = static_cast<unsigned>(per * kXcds);
+    switch (cls) {
+#define BSM_CL(ID, MM, NN) case ID: k_smm_f64_class<MM, NN><<<grid, 64, 0, s>>>(a); break;
+        BSM_CL(0, 5, 5) BSM_CL(1, 5, 13) BSM_CL(2, 5, 23) BSM_CL(3, 5, 26)
+        BSM_CL(4, 13, 5) BSM_CL(5, 13, 13) BSM_CL(6, 13, 23) BSM_CL(7, 13, 26)
+        BSM_CL(8, 23, 5) BSM_CL(9, 23, 13) BSM_CL(10, 23, 23) BSM_CL(11, 23, 26)
+        BSM_CL(12, 26, 5) BSM_CL(13, 26, 13) BSM_CL(14, 26, 23) BSM_CL(15, 26, 26)
+#undef BSM_CL
+        default: set_error("no class kernel %d", cls); return BSM_EINVAL;
+    }
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Fused persistent FP64 kernel: a fixed grid of single-wave workgroups drains
+// the whole work list of a chunk -- every (m, n) class -- through an atomic
+// counter, running the run-time-shape 4 x 4-tile code path for each C block.
+// The list is sorted by descending cost (largest stacks first), so the tail
+// of the launch is short.  Every wave exits when the counter passes the end.
+__global__ void __launch_bounds__(64)
+k_smm_f64_persistent(SmmArgs a, unsigned long long *counter) {
+    extern __shared__ double sm[];
+    for (;;) {
+        int64_t item = 0;
+        if (threadIdx.x == 0) item = static_cast<int64_t>(atomicAdd(counter, 1ull));
+        item = __shfl(item, 0, kWave);
+        if (item >= a.nC) break;
+        m4_cblock<4, 4>(a, a.worklist ? a.worklist[a.c0 + item] : a.c0 + item, sm);
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
+
+static int launch_persistent(const SmmArgs &a, hipStream_t s) {
+    int dev = 0, cus = 256;
+    BSM_HIP(hipGetDevice(&dev));
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const size_t lds = sizeof(double) * (static_cast<size_t>(a.max_m) * a.max_k +
+                                         static_cast<size_t>(a.max_k) * a.max_n);
+    unsigned long long *counter = nullptr;
+    BSM_TRY(dalloc(&counter, 1, s));
+    k_zero_u64<<<1, 1, 0, s>>>(counter);
+    const int64_t want = static_cast<int64_t>(cus) * 8;    // 2 waves per SIMD (its occupancy)
+    const unsigned grid = static_cast<unsigned>(want < a.nC ? want : a.nC);
+    k_smm_f64_persistent<<<grid, 64, lds, s>>>(a, counter);
+    const hipError_t e = hipGetLastError();
+    dfree(counter, s);
+    if (e != hipSuccess) { set_error("persistent launch: %s", hipGetErrorString(e)); return BSM_EDEVICE; }
+    return BSM_OK;
+}
+
 // Uniform (m, n, k) shapes with a compile-time kernel.
 bool smm_fixed_available(int m, int n, int k) {
     return (m == n && n == k) && (m == 5 || m == 13 || m == 23 || m == 26 || m == 32);
@@ -420,8 +587,9 @@ int smm_launch(const SmmArgs &a, int variant, hipStream_t s) {
     if (variant == kSmmF64Fixed) {
         if (a.uni_m && smm_fixed_available(a.uni_m, a.uni_n, a.uni_k))
             return launch_fixed(a, a.uni_m, static_cast<unsigned>(grid), s);
-        variant = kSmmF64M4;   // mixed sizes: runtime-shape kernel
+        variant = kSmmF64M4;      // mixed sizes (the host picks fused/class launches)
     }
+    if (variant == kSmmF64Fused) return launch_persistent(a, s);
     if (variant == kSmmF64M4) {
         // tiles per half: ceil(ceil(max/4)/2)
         const int rt = (((a.max_m + 3) / 4) + 1) / 2, ct = (((a.max_n + 3) / 4) + 1) / 2;

@@ -33,6 +33,13 @@ int tile_order(const int64_t *c_row_ptr, const int32_t *c_col_idx, int32_t nbrow
 int tile_rows();
 int tile_cols();
 
+// Bucket sort of the work list entries [c0, c0+n) (see symbolic.hip);
+// hist_host (64 entries, may be NULL) receives the bucket sizes (waits).
+constexpr int kKeyCost = 0, kKeyClass = 1;
+int sort_worklist(const int64_t *wl_in, int64_t *wl_out, int64_t c0, int64_t n, int mode,
+                  const int32_t *c_row, const int32_t *c_col, const int32_t *rbs,
+                  const int32_t *cbs, const int64_t *seg, int64_t *hist_host, hipStream_t s);
+
 int sym_count(const SymArgs &a, int64_t *c_cnt, int64_t *c_nval, int64_t *p_cnt, double *flops,
               hipStream_t s);
 int sym_pattern(const SymArgs &a, const int64_t *c_row_ptr, int32_t *c_col_idx, int32_t *c_row,

@@ -323,6 +323,111 @@ int tile_order(const int64_t *c_row_ptr, const int32_t *c_col_idx, int32_t nbrow
     return BSM_OK;
 }
 
+// ---------------------------------------------------------- work-list sort
+// Bucket sort of a chunk's work list (the paper sorts stacks by (m, n, k) so
+// that homogeneous batches reach specialised kernels).  Key modes:
+//   kKeyCost:  bucket = 63 - floor(log2(cost)), cost = products * m * n, so
+//              ascending buckets are descending cost (largest stacks first);
+//   kKeyClass: bucket = 4*class(m) + class(n) for sizes {5,13,23,26}, 16 else.
+// Within a bucket the order is that of the input list within a workgroup.
+constexpr int kSortThreads = 256;
+constexpr int kMaxBuckets = 64;
+
+__device__ inline int class_of(int b) { return b == 5 ? 0 : b == 13 ? 1 : b == 23 ? 2 : b == 26 ? 3 : -1; }
+
+__device__ inline int wl_key(int mode, int64_t c, int64_t c0, const int32_t *c_row,
+                             const int32_t *c_col, const int32_t *rbs, const int32_t *cbs,
+                             const int64_t *seg) {
+    const int m = rbs[c_row[c]], n = cbs[c_col[c]];
+    if (mode == kKeyClass) {
+        const int cm = class_of(m), cn = class_of(n);
+        return (cm < 0 || cn < 0) ? 16 : 4 * cm + cn;
+    }
+    const unsigned long long cost =
+        static_cast<unsigned long long>(seg[c - c0 + 1] - seg[c - c0]) * m * n + 1ull;
+    const int lg = 63 - __clzll(cost);
+    return 63 - lg;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_wl_hist(const int64_t *wl, int64_t n, int64_t c0, int mode, const int32_t *c_row,
+          const int32_t *c_col, const int32_t *rbs, const int32_t *cbs, const int64_t *seg,
+          unsigned long long *hist) {
+    __shared__ unsigned int lh[kMaxBuckets];
+    if (threadIdx.x < kMaxBuckets) lh[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&lh[wl_key(mode, wl[c0 + i], c0, c_row, c_col, rbs, cbs, seg)], 1u);
+    __syncthreads();
+    if (threadIdx.x < kMaxBuckets && lh[threadIdx.x])
+        atomicAdd(&hist[threadIdx.x], static_cast<unsigned long long>(lh[threadIdx.x]));
+}
+
+// cursor[b] starts at the bucket's first position; each workgroup reserves
+// one range per bucket and places its elements in thread order.
+__global__ void __launch_bounds__(kSortThreads)
+k_wl_scatter(const int64_t *wl, int64_t n, int64_t c0, int mode, const int32_t *c_row,
+             const int32_t *c_col, const int32_t *rbs, const int32_t *cbs, const int64_t *seg,
+             unsigned long long *cursor, int64_t *out) {
+    __shared__ unsigned int lh[kMaxBuckets];
+    __shared__ unsigned long long base[kMaxBuckets];
+    __shared__ int keys[kSortThreads];
+    if (threadIdx.x < kMaxBuckets) lh[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kSortThreads + threadIdx.x;
+    int key = -1;
+    int64_t c = 0;
+    if (i < n) {
+        c = wl[c0 + i];
+        key = wl_key(mode, c, c0, c_row, c_col, rbs, cbs, seg);
+        atomicAdd(&lh[key], 1u);
+    }
+    keys[threadIdx.x] = key;
+    __syncthreads();
+    if (threadIdx.x < kMaxBuckets && lh[threadIdx.x])
+        base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], static_cast<unsigned long long>(lh[threadIdx.x]));
+    __syncthreads();
+    if (key >= 0) {
+        unsigned int rank = 0;
+        for (int t = 0; t < static_cast<int>(threadIdx.x); ++t) rank += (keys[t] == key);
+        out[c0 + base[key] + rank] = c;
+    }
+}
+
+__global__ void k_wl_zero(unsigned long long *p) { p[threadIdx.x] = 0ull; }
+
+__global__ void k_wl_cursor(const unsigned long long *hist, unsigned long long *cursor) {
+    if (threadIdx.x == 0) {
+        unsigned long long run = 0;
+        for (int b = 0; b < kMaxBuckets; ++b) { cursor[b] = run; run += hist[b]; }
+    }
+}
+
+int sort_worklist(const int64_t *wl_in, int64_t *wl_out, int64_t c0, int64_t n, int mode,
+                  const int32_t *c_row, const int32_t *c_col, const int32_t *rbs,
+                  const int32_t *cbs, const int64_t *seg, int64_t *hist_host, hipStream_t s) {
+    if (n <= 0) return BSM_OK;
+    unsigned long long *buf = nullptr;
+    BSM_TRY(dalloc(&buf, 2 * kMaxBuckets, s));
+    unsigned long long *hist = buf, *cursor = buf + kMaxBuckets;
+    k_wl_zero<<<1, 2 * kMaxBuckets, 0, s>>>(buf);
+    const unsigned g = grid_for(n, kSortThreads);
+    k_wl_hist<<<g, kSortThreads, 0, s>>>(wl_in, n, c0, mode, c_row, c_col, rbs, cbs, seg, hist);
+    k_wl_cursor<<<1, 64, 0, s>>>(hist, cursor);
+    k_wl_scatter<<<g, kSortThreads, 0, s>>>(wl_in, n, c0, mode, c_row, c_col, rbs, cbs, seg,
+                                            cursor, wl_out);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && hist_host) {
+        unsigned long long h[kMaxBuckets];
+        e = hipMemcpyAsync(h, hist, sizeof(h), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        for (int b = 0; b < kMaxBuckets; ++b) hist_host[b] = static_cast<int64_t>(h[b]);
+    }
+    dfree(buf, s);
+    if (e != hipSuccess) { set_error("work-list sort: %s", hipGetErrorString(e)); return BSM_EDEVICE; }
+    return BSM_OK;
+}
+
 int tile_rows() {
     const char *e = getenv("BSM_TILE_ROWS");
     const int v = e ? atoi(e) : 16;

@@ -205,7 +205,7 @@ def test_reductions_vs_oracle(orc):
     assert_same_matrix(got, orc.shift_scale(m, 0.7, 0.25), 1e-15, "shift_scale")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("maxb", [5, 13, 23, 26, 32])
 def test_multiply_kernel_variants(orc, monkeypatch, variant, maxb):
     """All FP64 block-product kernels (16x16 tiles, 4x4 tiles, fixed shapes)
@@ -224,3 +224,24 @@ def test_multiply_kernel_variants(orc, monkeypatch, variant, maxb):
         ref = orc.multiply(-0.5, a, b, 1.5, c)
         got, _ = _run(-0.5, a, b, 1.5, c)
         assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"variant {variant} maxb {maxb}")
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+def test_multiply_mixed_class_sizes(orc, monkeypatch, variant):
+    """Block sizes drawn from {5, 13, 23, 26}: the per-class launches (4), the
+    fused persistent launch (3) and the run-time-shape kernel (1) agree with
+    the oracle, also with several chunks."""
+    monkeypatch.setenv("BSM_SMM_VARIANT", str(variant))
+    rng = np.random.default_rng(77)
+    nb = 14
+    rs, ks, cs = (rng.choice([5, 13, 23, 26], nb) for _ in range(3))
+    a = synth.random_bsr(nb, nb, rs, ks, 0.5, rng)
+    b = synth.random_bsr(nb, nb, ks, cs, 0.5, rng)
+    c = synth.random_bsr(nb, nb, rs, cs, 0.3, rng)
+    ref = orc.multiply(1.0, a, b, -0.5, c)
+    got, _ = _run(1.0, a, b, -0.5, c)
+    assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"variant {variant}")
+    monkeypatch.setenv("BSM_CHUNK_PRODUCTS", "300")
+    monkeypatch.setenv("BSM_TILE_ROWS", "2")
+    got, _ = _run(1.0, a, b, -0.5, c)
+    assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"variant {variant} chunked")

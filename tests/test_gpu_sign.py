@@ -90,3 +90,15 @@ def test_density_from_sign(orc):
     assert tp == pytest.approx(h.meta["n_occ"], abs=1e-8)
     dp = p.to_dense()
     assert np.linalg.norm(dp @ dp - dp) / dp.shape[0] < 1e-9
+
+
+def test_sign_mixed_block_sizes_vs_oracle(orc):
+    """Neighbour Hamiltonian with block sizes drawn from {5, 13, 23, 26}."""
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(120, seed=9, cutoff=4.5, size_choices=(5, 13, 23, 26))
+    x_ref, st_ref, _ = orc.sign_ns(h, eps=1e-6, tol=1e-8)
+    st, x, stats, _ = _gpu_sign(h, eps=1e-6, tol=1e-8)
+    assert st == bsm.OK
+    assert stats.iterations == st_ref["iterations"]
+    assert_same_matrix(from_dev(x), x_ref, TOL_FP64, "mixed sign")
+    assert stats.trace_p == pytest.approx(h.meta["n_occ"], abs=1e-4)
