@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--prec", choices=["fp64", "fp32", "bf16"], default="fp64",
                     help="block-product precision (fp32 / split-bf16 switch to FP64 once "
                          "r_k < 1e-4)")
+    ap.add_argument("--table", choices=["exhaustive", "mlp", "none"], default="exhaustive",
+                    help="kernel-parameter table: measured (exhaustive autotuning), predicted "
+                         "by the MLP, or none (built-in choices)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -116,9 +119,10 @@ def main():
         return
 
     import synth
-    from paper_2003_03868_amd import bsm
+    from paper_2003_03868_amd import bsm, tune
     bsm.load()
     torch.cuda.set_device(0)
+    tune.install_default(args.table)
 
     t0 = time.perf_counter()
     if args.workload == "sign23":
@@ -201,7 +205,7 @@ def main():
                          f", cutoff 6 A, 0.1 sites/A^3, eps_filter {args.eps:g}, "
                          f"to ||X^2-I||_F/n < {args.tol:g}"),
             "n_sites": h.nbrows, "block": 23 if args.workload == "sign23" else "5/13/23/26",
-            "n": int(n), "eps_filter": args.eps,
+            "n": int(n), "eps_filter": args.eps, "kernel_table": args.table,
             "tol": args.tol, "seed": args.seed, "nnzb_H": h.nnzb,
         },
         "time_to_sign_ms": ms_per_step,

@@ -199,6 +199,43 @@ int bsm_sign_iterate(bsm_matrix H, double mu, const bsm_sign_opts *opts,
 /* P = (I - X)/2 from a sign matrix X, as a new handle; trace_p (may be NULL) gets trace(P). */
 int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void *stream);
 
+/*
+ * Autotuning support (the paper autotunes its block-product kernels per
+ * (m, n, k), "Batched execution" subsection).  Kernel parameters of the
+ * run-time-shape FP64 block-product kernel:
+ *   family   0: 16x16x4 FP64 matrix-core tiles; 1: 4x4x4 (four blocks per
+ *            instruction); 2: the (m, n)-specialised kernel (m, n in
+ *            {5, 13, 23, 26}, k <= 26); 3: the compile-time-shape kernel
+ *            (m = n = k in {5, 13, 23, 26, 32});
+ *   wpg      C blocks (wavefronts) per workgroup: 1, 2 or 4;
+ *   prefetch 1: load the next product's operands while multiplying.
+ */
+typedef struct {
+    int32_t family;
+    int32_t wpg;
+    int32_t prefetch;
+    int32_t reserved;
+} bsm_smm_params;
+
+/*
+ * Time n_params parameter sets on a synthetic stack: n_cblocks C blocks of
+ * m x n, each with prods_per_cblock products A(m x k) * B(k x n) whose
+ * operand blocks are drawn from pools of 1024 blocks (k = 0: the products
+ * cycle through k = 5, 13, 23, 26).  ms_out[i] (host) gets the median kernel
+ * time of `reps` runs of params[i].  Sizes 1..32; waits for the stream.
+ */
+int bsm_smm_bench(int32_t m, int32_t n, int32_t k, int64_t n_cblocks,
+                  int32_t prods_per_cblock, int32_t n_params, const bsm_smm_params *params,
+                  int32_t reps, double *ms_out, void *stream);
+
+/*
+ * Install kernel parameters for (m, n, k) triples (mnk holds 3 ints per
+ * entry; k = 0 means "any k", used for the per-class launches of mixed
+ * block sizes).  Later entries replace earlier ones; n_entries < 0 clears
+ * the table.  Multiplies whose shapes have no entry use built-in choices.
+ */
+int bsm_set_smm_table(int32_t n_entries, const int32_t *mnk, const bsm_smm_params *params);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *bsm_last_error(void);
 

@@ -58,6 +58,11 @@ class bsm_sign_stats(C.Structure):
                 ("graph_replays", C.c_int32), ("pad_", C.c_int32)]
 
 
+class bsm_smm_params(C.Structure):
+    _fields_ = [("family", C.c_int32), ("wpg", C.c_int32), ("prefetch", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -83,6 +88,10 @@ _SIGS = [
                                    C.POINTER(C.c_void_p), C.POINTER(bsm_sign_stats), C.c_void_p]),
     ("bsm_density_from_sign", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p),
                                         C.POINTER(C.c_double), C.c_void_p]),
+    ("bsm_smm_bench", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
+                                C.POINTER(bsm_smm_params), C.c_int32, C.POINTER(C.c_double),
+                                C.c_void_p]),
+    ("bsm_set_smm_table", C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(bsm_smm_params)]),
     ("bsm_last_error", C.c_char_p, []),
     ("bsm_version", C.c_char_p, []),
 ]
@@ -226,6 +235,27 @@ def bsm_density_from_sign(h, stream=None):
     _check(load().bsm_density_from_sign(h, C.byref(out), C.byref(tp), _stream(stream)),
            "bsm_density_from_sign")
     return out.value, tp.value
+
+
+def bsm_smm_bench(m, n, k, n_cblocks, prods_per_cblock, params, reps=3, stream=None):
+    """Median kernel ms of every (family, wpg, prefetch) tuple in `params`."""
+    arr = (bsm_smm_params * len(params))(*[bsm_smm_params(f, w, p, 0) for f, w, p in params])
+    out = (C.c_double * len(params))()
+    _check(load().bsm_smm_bench(m, n, k, n_cblocks, prods_per_cblock, len(params), arr, reps,
+                                out, _stream(stream)), "bsm_smm_bench")
+    return list(out)
+
+
+def bsm_set_smm_table(entries) -> None:
+    """entries: iterable of ((m, n, k), (family, wpg, prefetch)); None clears."""
+    if entries is None:
+        _check(load().bsm_set_smm_table(-1, None, None), "bsm_set_smm_table")
+        return
+    entries = list(entries)
+    mnk = (C.c_int32 * (3 * len(entries)))(*[v for (t, _) in entries for v in t])
+    prm = (bsm_smm_params * len(entries))(*[bsm_smm_params(f, w, p, 0)
+                                            for (_, (f, w, p)) in entries])
+    _check(load().bsm_set_smm_table(len(entries), mnk, prm), "bsm_set_smm_table")
 
 
 def bsm_last_error() -> str:

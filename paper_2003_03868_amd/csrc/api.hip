@@ -3,6 +3,7 @@
 #include <cstring>
 
 #include "bsm_internal.h"
+#include "smm.h"
 
 namespace bsm {
 const char *last_error();
@@ -250,6 +251,37 @@ int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void
     h->m = std::move(*m);
     delete m;
     *p_out = h;
+    return BSM_OK;
+}
+
+int bsm_smm_bench(int32_t m, int32_t n, int32_t k, int64_t n_cblocks, int32_t prods_per_cblock,
+                  int32_t n_params, const bsm_smm_params *params, int32_t reps, double *ms_out,
+                  void *stream) {
+    bsm::clear_error();
+    if (!params || !ms_out || n_params < 1) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    static_assert(sizeof(bsm_smm_params) == sizeof(bsm::SmmParams), "params layout");
+    return bsm::smm_bench(m, n, k, n_cblocks, prods_per_cblock, n_params,
+                          reinterpret_cast<const bsm::SmmParams *>(params), reps, ms_out,
+                          as_stream(stream));
+}
+
+int bsm_set_smm_table(int32_t n_entries, const int32_t *mnk, const bsm_smm_params *params) {
+    bsm::clear_error();
+    if (n_entries > 0 && (!mnk || !params)) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    for (int32_t i = 0; i < n_entries; ++i) {
+        const bsm_smm_params &p = params[i];
+        if (p.family < 0 || p.family > 3 || (p.wpg != 1 && p.wpg != 2 && p.wpg != 4) ||
+            (p.prefetch != 0 && p.prefetch != 1)) {
+            bsm::set_error("bad parameters in entry %d", i);
+            return BSM_EINVAL;
+        }
+        if (mnk[3 * i] < 1 || mnk[3 * i] > bsm::kMaxBlock || mnk[3 * i + 1] < 1 ||
+            mnk[3 * i + 1] > bsm::kMaxBlock || mnk[3 * i + 2] < 0 || mnk[3 * i + 2] > bsm::kMaxBlock) {
+            bsm::set_error("bad (m, n, k) in entry %d", i);
+            return BSM_EINVAL;
+        }
+    }
+    bsm::table_set(n_entries, mnk, reinterpret_cast<const bsm::SmmParams *>(params));
     return BSM_OK;
 }
 

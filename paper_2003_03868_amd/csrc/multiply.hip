@@ -282,7 +282,16 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
                 if (hist[b] == 0) continue;
                 cls.worklist = worklist2 + off;
                 cls.nC = hist[b];
-                st = (b < 16) ? launch_class(cls, b, s) : smm_launch(cls, kSmmF64M4, s);
+                // per class: the (m, n)-specialised kernel unless the tuning
+                // table holds run-time-kernel parameters for (m, n, any k)
+                static const int sz[4] = {5, 13, 23, 26};
+                SmmParams prm;
+                if (b < 16 && !(table_lookup(sz[b / 4], sz[b % 4], 0, &prm) && prm.family != 2))
+                    st = launch_class(cls, b, s);
+                else if (b < 16)
+                    st = launch_rt(cls, prm, s);
+                else
+                    st = smm_launch(cls, kSmmF64Tuned, s);
                 off += hist[b];
             }
         } else {

@@ -7,6 +7,15 @@ namespace bsm {
 
 constexpr int kFlagNonFinite = 1;
 
+// Parameters of the tunable run-time-shape kernel (smm_rt.hip).
+struct SmmParams {
+    int32_t family;    // 0: 16x16x4 FP64 MFMA, 1: 4x4x4 FP64 MFMA, 2: per-class kernel,
+                       // 3: compile-time-shape kernel (m = n = k in {5,13,23,26,32})
+    int32_t wpg;       // C blocks (wavefronts) per workgroup: 1, 2, 4
+    int32_t prefetch;  // 1: prefetch the next product's operands
+    int32_t reserved;
+};
+
 // Block-product kernel variants.
 enum SmmVariant {
     kSmmF64M16 = 0,   // V_MFMA_F64_16X16X4_F64, 16 x 16 tiles
@@ -17,6 +26,7 @@ enum SmmVariant {
                       // launch, cost-sorted work queue, run-time shapes
     kSmmF64Class = 4, // one launch per (m, n) class of {5,13,23,26}^2 with an
                       // (m, n)-specialised kernel, run-time k
+    kSmmF64Tuned = 5, // tunable run-time-shape kernel, parameters from the table
 };
 
 struct SmmArgs {
@@ -54,8 +64,16 @@ struct SmmArgs {
 
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s);
 bool smm_fixed_available(int m, int n, int k);
+int launch_fixed(const SmmArgs &a, int m, unsigned grid, hipStream_t s);
 int class_of_size(int b);                       // 0..3 for 5, 13, 23, 26; else -1
 int launch_class(const SmmArgs &a, int cls, hipStream_t s);   // cls = 4*class(m)+class(n)
+
+// Tunable run-time-shape kernels (smm_rt.hip) and the tuning table (tune.hip).
+int launch_rt(const SmmArgs &a, const SmmParams &prm, hipStream_t s);
+bool table_lookup(int m, int n, int k, SmmParams *out);    // k = 0: mixed k
+void table_set(int count, const int32_t *mnk, const SmmParams *prm);   // count < 0 clears
+int smm_bench(int m, int n, int k, int64_t n_c, int per_c, int n_prm, const SmmParams *prm,
+              int reps, double *ms_out, hipStream_t s);
 
 // Reduced-precision products (smm_lowp.hip).
 int pack_lowp(const double *v, int64_t n, uint32_t *out, int prec, hipStream_t s);

@@ -8,10 +8,13 @@
 // squared Frobenius norm and max |x| for the filter.  No atomics, fixed
 // summation order.
 //
-// FP64 path: the block products run on the CDNA matrix cores with
-// V_MFMA_F64_16X16X4_F64; a C block of up to 32 x 32 is a 2 x 2 grid of
-// 16 x 16 accumulator tiles.  Operand blocks are staged through LDS with
+// FP64 path: the block products run on the CDNA matrix cores, mainly with
+// V_MFMA_F64_4X4X4_4B_F64.  Operand blocks are staged through LDS with
 // contiguous (coalesced) global loads, then read in MFMA operand layout.
+// This file holds the compile-time-shape kernels (uniform sizes, per-(m, n)
+// class), the run-time-shape code path used by the fused persistent launch,
+// and the launch dispatch; smm_rt.hip holds the tunable run-time-shape
+// kernels and smm_lowp.hip the reduced-precision ones.
 #include "smm.h"
 
 namespace bsm {
@@ -35,114 +38,11 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
-// Shared epilogue: v = alpha*acc + beta*C_in, store, and the block norms.
-// Accumulator layout of V_MFMA_F64_16X16X4_F64 (measured on gfx950): element
-// (i, j) of a 16 x 16 tile lives in lane j + 16*(i % 4), register i / 4.
-template <int MT, int NT>
-__device__ inline void store_c_block(const SmmArgs &a, int64_t c, int m, int n,
-                                     const double (&acc)[MT][NT][4]) {
-    const int lane = threadIdx.x;
-    const int r16 = lane & 15, kq = lane >> 4;
-    const int64_t co = a.c_blk_off[c];
-    const double *cin = nullptr;
-    if (a.cin_map) {
-        const int64_t t = a.cin_map[c];
-        if (t >= 0) cin = a.cin_vals + a.cin_blk_off[t];
-    }
-    double sq = 0.0, mx = 0.0;
-#pragma unroll
-    for (int ti = 0; ti < MT; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int row = ti * 16 + 4 * q + kq, col = tj * 16 + r16;
-                if (row < m && col < n) {
-                    double v = a.alpha * acc[ti][tj][q];
-                    if (cin) v += a.beta * cin[row * n + col];
-                    a.c_vals[co + row * n + col] = v;
-                    sq += v * v;
-                    mx = fmax(mx, fabs(v));
-                }
-            }
-    sq = wave_sum(sq);
-    mx = wave_max(mx);
-    if (lane == 0) {
-        a.sq_out[c] = sq;
-        a.mx_out[c] = mx;
-        if (!isfinite(sq)) atomicOr(a.flags, kFlagNonFinite);
-    }
-}
-
-// FP64 MFMA kernel.  MT, NT: maximum number of 16-row / 16-column tiles
-// (1 or 2); tiles beyond the block's own m, n are skipped (wave-uniform).
-template <int MT, int NT>
-__global__ void __launch_bounds__(64)
-k_smm_f64_mfma(SmmArgs a) {
-    extern __shared__ double sm[];
-    const int64_t item = xcd_item(a.nC);
-    if (item >= a.nC) return;
-    const int lane = threadIdx.x;
-    const int r16 = lane & 15, kq = lane >> 4;
-    const int64_t c = a.worklist ? a.worklist[a.c0 + item] : a.c0 + item;
-    const int m = a.c_rbs[a.c_row[c]], n = a.c_cbs[a.c_col[c]];
-    const int mt = (m + 15) >> 4, nt = (n + 15) >> 4;
-    double *sA = sm;
-    double *sB = sm + a.max_m * a.max_k;
-
-    d4 acc[MT][NT];
-#pragma unroll
-    for (int ti = 0; ti < MT; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
-
-    const int64_t p_end = a.seg[c - a.c0 + 1];
-    for (int64_t p = a.seg[c - a.c0]; p < p_end; ++p) {
-        const int32_t ta = a.stk_a[p], tb = a.stk_b[p];
-        const int k = a.k_size[a.a_col_idx[ta]];
-        const double *ga = a.a_vals + a.a_blk_off[ta];
-        const double *gb = a.b_vals + a.b_blk_off[tb];
-        for (int e = lane; e < m * k; e += kWave) sA[e] = ga[e];
-        for (int e = lane; e < k * n; e += kWave) sB[e] = gb[e];
-        __syncthreads();
-        for (int ks = 0; ks < k; ks += 4) {
-            const int kk = ks + kq;
-            double av[MT], bv[NT];
-#pragma unroll
-            for (int ti = 0; ti < MT; ++ti) {
-                const int r = ti * 16 + r16;
-                av[ti] = (r < m && kk < k) ? sA[r * k + kk] : 0.0;
-            }
-#pragma unroll
-            for (int tj = 0; tj < NT; ++tj) {
-                const int cc = tj * 16 + r16;
-                bv[tj] = (kk < k && cc < n) ? sB[kk * n + cc] : 0.0;
-            }
-#pragma unroll
-            for (int ti = 0; ti < MT; ++ti)
-#pragma unroll
-                for (int tj = 0; tj < NT; ++tj)
-                    if (ti < mt && tj < nt)
-                        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj],
-                                                                           acc[ti][tj], 0, 0, 0);
-        }
-        __syncthreads();
-    }
-
-    double out[MT][NT][4];
-#pragma unroll
-    for (int ti = 0; ti < MT; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) out[ti][tj][q] = acc[ti][tj][q];
-    store_c_block<MT, NT>(a, c, m, n, out);
-}
-
 // ---------------------------------------------------------------------------
-// FP64 kernel on V_MFMA_F64_4X4X4_4B_F64 (four independent 4x4x4 products per
-// instruction).  On gfx950 this instruction sustains ~95% of the FP64 peak,
-// and its 4-wide tiles pad a 23 x 23 block only to 24 x 24.
+// Run-time-shape C-block code path on V_MFMA_F64_4X4X4_4B_F64 (four
+// independent 4x4x4 products per instruction), used by the fused persistent
+// launch.  On gfx950 this instruction sustains ~95% of the FP64 peak, and its
+// 4-wide tiles pad a 23 x 23 block only to 24 x 24.
 //
 // Lane layout (measured on gfx950): lane = 16*x + 4*b + y, b = block 0..3;
 // A_b(i,k): x = k, y = i;  B_b(k,j): x = k, y = j;  D_b(i,j): x = i, y = j.
@@ -263,18 +163,10 @@ __device__ inline void m4_cblock(const SmmArgs &a, int64_t c, double *sm) {
     __syncthreads();   // LDS is reused by the next C block of a persistent wave
 }
 
-template <int RT, int CT>
-__global__ void __launch_bounds__(64)
-k_smm_f64_m4(SmmArgs a) {
-    extern __shared__ double sm[];
-    const int64_t item = xcd_item(a.nC);
-    if (item >= a.nC) return;
-    m4_cblock<RT, CT>(a, a.worklist ? a.worklist[a.c0 + item] : a.c0 + item, sm);
-}
-
 // ---------------------------------------------------------------------------
 // FP64 kernel for uniform block sizes known at compile time (M x K times
-// K x N).  Same instruction and lane roles as k_smm_f64_m4, but:
+// K x N).  Same instruction and lane roles as the run-time-shape 4 x 4-tile
+// path (m4_cblock), but:
 //  * the operand blocks sit in LDS exactly as in HBM (A then B, row-major,
 //    followed by a zeroed tail), so staging is a contiguous copy with
 //    immediate offsets and needs no per-lane index registers;
@@ -561,7 +453,7 @@ bool smm_fixed_available(int m, int n, int k) {
     return (m == n && n == k) && (m == 5 || m == 13 || m == 23 || m == 26 || m == 32);
 }
 
-static int launch_fixed(const SmmArgs &a, int m, unsigned grid, hipStream_t s) {
+int launch_fixed(const SmmArgs &a, int m, unsigned grid, hipStream_t s) {
     switch (m) {
         case 5: k_smm_f64_fixed<5, 5, 5, 8><<<grid, 64, 0, s>>>(a); break;
         case 13: k_smm_f64_fixed<13, 13, 13, 8><<<grid, 64, 0, s>>>(a); break;
@@ -574,6 +466,19 @@ static int launch_fixed(const SmmArgs &a, int m, unsigned grid, hipStream_t s) {
     return BSM_OK;
 }
 
+// Tuned parameters for a launch whose shapes are (max_m, max_n, max_k), or
+// the uniform sizes when they are uniform; defaults when the table has none.
+static SmmParams tuned_params(const SmmArgs &a) {
+    SmmParams p{1, 1, 1, 0};
+    if (a.uni_m && a.uni_n && a.uni_k) {
+        if (table_lookup(a.uni_m, a.uni_n, a.uni_k, &p) && p.family != 2) return p;
+        return SmmParams{1, 1, 1, 0};
+    }
+    SmmParams q;
+    if (table_lookup(a.max_m, a.max_n, 0, &q) && q.family != 2) return q;
+    return p;
+}
+
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s) {
     if (a.nC <= 0) return BSM_OK;
     const int64_t per = (a.nC + kXcds - 1) / kXcds;
@@ -582,37 +487,27 @@ int smm_launch(const SmmArgs &a, int variant, hipStream_t s) {
         set_error("too many C blocks in one launch (%lld)", (long long)a.nC);
         return BSM_EINVAL;
     }
-    const size_t lds = sizeof(double) * (static_cast<size_t>(a.max_m) * a.max_k +
-                                         static_cast<size_t>(a.max_k) * a.max_n);
-    if (variant == kSmmF64Fixed) {
-        if (a.uni_m && smm_fixed_available(a.uni_m, a.uni_n, a.uni_k))
-            return launch_fixed(a, a.uni_m, static_cast<unsigned>(grid), s);
-        variant = kSmmF64M4;      // mixed sizes (the host picks fused/class launches)
+    switch (variant) {
+        case kSmmF64M16: return launch_rt(a, SmmParams{0, 1, 0, 0}, s);
+        case kSmmF64M4: return launch_rt(a, SmmParams{1, 1, 1, 0}, s);
+        case kSmmF64Fixed: {
+            // uniform sizes: the tuning table may choose the family; without
+            // an entry the compile-time-shape kernel is used where it exists
+            const bool uni = a.uni_m && a.uni_n && a.uni_k;
+            SmmParams p;
+            const bool have = uni && table_lookup(a.uni_m, a.uni_n, a.uni_k, &p);
+            if (have && p.family == 2 && class_of_size(a.uni_m) >= 0 && class_of_size(a.uni_n) >= 0 &&
+                a.uni_k <= 26 && a.worklist)
+                return launch_class(a, 4 * class_of_size(a.uni_m) + class_of_size(a.uni_n), s);
+            if (have && (p.family == 0 || p.family == 1)) return launch_rt(a, p, s);
+            if (uni && smm_fixed_available(a.uni_m, a.uni_n, a.uni_k))
+                return launch_fixed(a, a.uni_m, static_cast<unsigned>(grid), s);
+            return launch_rt(a, tuned_params(a), s);
+        }
+        case kSmmF64Fused: return launch_persistent(a, s);
+        case kSmmF64Tuned: return launch_rt(a, tuned_params(a), s);
+        default: set_error("unknown kernel variant %d", variant); return BSM_EINVAL;
     }
-    if (variant == kSmmF64Fused) return launch_persistent(a, s);
-    if (variant == kSmmF64M4) {
-        // tiles per half: ceil(ceil(max/4)/2)
-        const int rt = (((a.max_m + 3) / 4) + 1) / 2, ct = (((a.max_n + 3) / 4) + 1) / 2;
-        const unsigned g = static_cast<unsigned>(grid);
-#define BSM_M4(R, C) k_smm_f64_m4<R, C><<<g, 64, lds, s>>>(a)
-        if (rt <= 1 && ct <= 1) BSM_M4(1, 1);
-        else if (rt <= 2 && ct <= 2) BSM_M4(2, 2);
-        else if (rt <= 3 && ct <= 3) BSM_M4(3, 3);
-        else BSM_M4(4, 4);
-#undef BSM_M4
-        BSM_HIP(hipGetLastError());
-        return BSM_OK;
-    }
-    if (a.max_m <= 16 && a.max_n <= 16)
-        k_smm_f64_mfma<1, 1><<<static_cast<unsigned>(grid), 64, lds, s>>>(a);
-    else if (a.max_m <= 16)
-        k_smm_f64_mfma<1, 2><<<static_cast<unsigned>(grid), 64, lds, s>>>(a);
-    else if (a.max_n <= 16)
-        k_smm_f64_mfma<2, 1><<<static_cast<unsigned>(grid), 64, lds, s>>>(a);
-    else
-        k_smm_f64_mfma<2, 2><<<static_cast<unsigned>(grid), 64, lds, s>>>(a);
-    BSM_HIP(hipGetLastError());
-    return BSM_OK;
 }
 
 }  // namespace bsm

@@ -245,3 +245,55 @@ def test_multiply_mixed_class_sizes(orc, monkeypatch, variant):
     monkeypatch.setenv("BSM_TILE_ROWS", "2")
     got, _ = _run(1.0, a, b, -0.5, c)
     assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"variant {variant} chunked")
+
+
+CATALOGUE = [(f, w, p) for f in (0, 1) for w in (1, 2, 4) for p in (0, 1)]
+
+
+@pytest.mark.parametrize("entry", CATALOGUE, ids=lambda e: f"f{e[0]}w{e[1]}p{e[2]}")
+def test_tuned_kernel_parameters_vs_oracle(orc, monkeypatch, entry):
+    """Every tunable kernel parameter set gives the oracle's product, for a
+    uniform size without a fixed-shape kernel and for mixed class sizes."""
+    from paper_2003_03868_amd import bsm
+    monkeypatch.setenv("BSM_SMM_VARIANT", "5")
+    rng = np.random.default_rng(303)
+    nb = 11
+    for rs, ks, cs in [(np.full(nb, 17), np.full(nb, 9), np.full(nb, 30)),
+                       tuple(rng.integers(1, 33, nb) for _ in range(3))]:
+        a = synth.random_bsr(nb, nb, rs, ks, 0.5, rng)
+        b = synth.random_bsr(nb, nb, ks, cs, 0.5, rng)
+        c = synth.random_bsr(nb, nb, rs, cs, 0.3, rng)
+        key = (int(rs.max()), int(cs.max()), int(ks.max()) if (rs == rs[0]).all() else 0)
+        bsm.bsm_set_smm_table([((int(rs[0]), int(cs[0]), int(ks[0])), entry), (key, entry)])
+        try:
+            ref = orc.multiply(1.5, a, b, -1.0, c)
+            got, _ = _run(1.5, a, b, -1.0, c)
+        finally:
+            bsm.bsm_set_smm_table(None)
+        assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"entry {entry}")
+    # class launches with a run-time kernel chosen by the table
+    monkeypatch.setenv("BSM_SMM_VARIANT", "4")
+    rs, ks, cs = (rng.choice([5, 13, 23, 26], nb) for _ in range(3))
+    a = synth.random_bsr(nb, nb, rs, ks, 0.5, rng)
+    b = synth.random_bsr(nb, nb, ks, cs, 0.5, rng)
+    bsm.bsm_set_smm_table([((m, n, 0), entry) for m in (5, 13, 23, 26) for n in (5, 13, 23, 26)])
+    try:
+        got, _ = _run(1.0, a, b, 0.0, None)
+    finally:
+        bsm.bsm_set_smm_table(None)
+    assert_same_matrix(got, orc.multiply(1.0, a, b), TOL_FP64_MULTIPLY, f"class {entry}")
+
+
+def test_smm_bench_entry_point():
+    from paper_2003_03868_amd import bsm
+    cat = CATALOGUE + [(2, 1, 1)]
+    ms = bsm.bsm_smm_bench(23, 13, 26, 500, 16, cat, reps=2)
+    assert len(ms) == len(cat) and all(t > 0 for t in ms)
+    ms = bsm.bsm_smm_bench(23, 13, 0, 300, 8, cat, reps=1)   # mixed k
+    assert all(t > 0 for t in ms)
+    with pytest.raises(bsm.BsmError):
+        bsm.bsm_smm_bench(40, 5, 5, 10, 4, CATALOGUE, reps=1)
+    with pytest.raises(bsm.BsmError):
+        bsm.bsm_smm_bench(7, 5, 5, 10, 4, [(2, 1, 1)], reps=1)   # no class kernel for 7
+    with pytest.raises(bsm.BsmError):
+        bsm.bsm_set_smm_table([((5, 5, 5), (4, 1, 1))])
