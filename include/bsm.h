@@ -108,8 +108,9 @@ typedef struct {
     double smm_ms;           /* device time inside block-product kernels */
     double device_ms;        /* device time from first to last kernel (HIP events) */
     int64_t nnzb_final;      /* stored blocks of the returned X */
-    int32_t graph_replays;   /* iterations run by replaying a captured graph */
-    int32_t pad_;
+    int32_t graph_replays;   /* iterations run by replaying captured graphs */
+    int32_t graph_fallbacks; /* replayed iterations redone on the normal path because
+                                the filter kept other blocks (or NaN/Inf appeared) */
 } bsm_sign_stats;
 
 /* Default options: eps 0, tol 1e-6, max_iter 100, FROB, FP64, no graph. */
@@ -192,6 +193,11 @@ int bsm_inf_norm(bsm_matrix A, double mu, double *out, void *stream);
  * whose square was tested.  stats may be NULL.  BSM_ENOCONV if r_k is not
  * finite, grows three times in a row, or max_iter is reached (X is still
  * returned); BSM_ENONFINITE for NaN/Inf in H.
+ * opts->use_graph = 1: once an update leaves X's block pattern unchanged, the
+ * following iterations replay captured hipGraphs of the numeric kernels (one
+ * wait per iteration; no symbolic phase, allocation or compaction scan).  A
+ * replayed iteration whose filter would keep other blocks is redone on the
+ * normal path, so the results are those of use_graph = 0, bit for bit.
  */
 int bsm_sign_iterate(bsm_matrix H, double mu, const bsm_sign_opts *opts,
                      bsm_matrix *x_out, bsm_sign_stats *stats, void *stream);

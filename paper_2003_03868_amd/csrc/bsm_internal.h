@@ -84,10 +84,15 @@ int compute_blk_off(Mat &m, hipStream_t s);
 int validate_pattern(const Mat &m, hipStream_t s);
 
 // ---------------------------------------------------------- multiply core
-struct MultiplyPlan;   // opaque per-call state (multiply.hip)
+// Symbolic state of one multiply kept for numeric-only repetitions with the
+// same operand patterns (graph replay in the sign iteration); plan.hip.
+struct MulPlan;
+void free_plan(MulPlan *p);
 
+// plan (may be NULL): on success receives the retained symbolic state.
 int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps,
-             int norm, int prec, bsm_mult_stats *stats, hipStream_t s);
+             int norm, int prec, bsm_mult_stats *stats, hipStream_t s,
+             MulPlan **plan = nullptr);
 int filter_inplace(Mat &m, double eps, int norm, hipStream_t s);
 
 // Reductions (reduce.hip)
@@ -99,8 +104,20 @@ int shift_scale(const Mat &a, double mu, double scale, Mat **out, hipStream_t s)
 int copy_mat(const Mat &a, Mat **out, hipStream_t s);
 int alloc_like_sizes(const Mat &proto_rows, const Mat &proto_cols, Mat **out, hipStream_t s);
 
-// Compaction kernels shared by multiply and filter (filter.hip)
+// Compaction after the filter (reduce.hip).  keep (may be NULL): instead of
+// freeing them, hand over the keep scan kidx[n+1], the kept-value offsets
+// koff[n+1] and the unfiltered arrays of m (col_idx, blk_off, values).
+struct CompactKeep {
+    int64_t *kidx = nullptr, *koff = nullptr;
+    int64_t *row_ptr = nullptr, *blk_off = nullptr;
+    int32_t *col_idx = nullptr;
+    double *values = nullptr;
+    bool compacted = false;      // false: nothing was dropped, m unchanged
+};
 int compact_by_norm(Mat &m, const double *sq, const double *mx, double eps, int norm,
-                    hipStream_t s, int64_t *nnzb_after);
+                    hipStream_t s, int64_t *nnzb_after, CompactKeep *keep = nullptr);
+
+// ||A - shift I||_F^2 into a device scalar (part: nbrows doubles of scratch).
+int sqdist_identity_dev(const Mat &m, double shift, double *part, double *d_out, hipStream_t s);
 
 }  // namespace bsm

@@ -11,10 +11,14 @@
 //
 // C's old arrays stay alive until everything that reads them is queued, so C
 // may be the same handle as A or B.
+//
+// With a plan requested, the symbolic results (stacks per chunk, sorted work
+// lists, the launches, the filter's keep-set and compaction maps) are kept in
+// plan-owned memory for numeric-only repetitions (plan.hip).
 #include <algorithm>
 #include <vector>
 
-#include "smm.h"
+#include "plan.h"
 #include "symbolic.h"
 
 namespace bsm {
@@ -94,7 +98,7 @@ static int check_shapes(const Mat &A, const Mat &B, const Mat &C) {
 }
 
 int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int norm, int prec,
-             bsm_mult_stats *stats, hipStream_t s) {
+             bsm_mult_stats *stats, hipStream_t s, MulPlan **plan) {
     BSM_TRY(check_shapes(A, B, C));
     if (!(eps >= 0.0) || !std::isfinite(eps)) { set_error("eps_filter must be finite and >= 0"); return BSM_EINVAL; }
     if (norm != BSM_NORM_FROB && norm != BSM_NORM_MAXABS) { set_error("unknown norm %d", norm); return BSM_EINVAL; }
@@ -103,6 +107,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
 
     const int32_t nbr = A.nbrows;
     const bool use_c = (beta != 0.0) && C.nnzb > 0;
+    const int64_t cin_nnzb = C.nnzb;
     Events ev;
     if (stats) {
         ev.on = true;
@@ -111,6 +116,19 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         BSM_HIP(hipEventRecord(ev.t0, s));
     }
     Scratch tmp(s);
+    MulPlan *pl = plan ? new MulPlan : nullptr;
+    if (pl) pl->s = s;
+    // buffers the plan keeps (plan mode) or that die with this call
+    auto keep_buf = [&](auto **ptr, size_t n) -> int {
+        if (!pl) return tmp.get(ptr, n);
+        const int r = dalloc(ptr, n, s);
+        if (r == BSM_OK) pl->owned.push_back(*ptr);
+        return r;
+    };
+    struct PlanGuard {
+        MulPlan *&p;
+        ~PlanGuard() { free_plan(p); }
+    } plan_guard{pl};
 
     SymArgs sa{};
     sa.nbrows = nbr; sa.nbcols = B.nbcols;
@@ -161,10 +179,10 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     int *flags = nullptr;
     st = dalloc(&nc.col_idx, nnzb_c, s);
     if (st == BSM_OK) st = dalloc(&nc.values, nval_c, s);
-    if (st == BSM_OK) st = tmp.get(&c_row, nnzb_c);
-    if (st == BSM_OK && use_c) st = tmp.get(&cin_map, nnzb_c);
-    if (st == BSM_OK) st = tmp.get(&sq, nnzb_c);
-    if (st == BSM_OK) st = tmp.get(&mx, nnzb_c);
+    if (st == BSM_OK) st = keep_buf(&c_row, nnzb_c);
+    if (st == BSM_OK && use_c) st = keep_buf(&cin_map, nnzb_c);
+    if (st == BSM_OK) st = keep_buf(&sq, nnzb_c);
+    if (st == BSM_OK) st = keep_buf(&mx, nnzb_c);
     if (st == BSM_OK) st = tmp.get(&flags, 1);
     if (st == BSM_OK) {
         hipError_t e = hipMemsetAsync(flags, 0, sizeof(int), s);
@@ -178,8 +196,8 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     const int rb = tile_rows();
     const int variant = smm_variant();
     int64_t *worklist = nullptr, *worklist2 = nullptr;
-    if (st == BSM_OK) st = tmp.get(&worklist, nnzb_c);
-    if (st == BSM_OK) st = tmp.get(&worklist2, nnzb_c);   // target of the work-list sorts
+    if (st == BSM_OK) st = keep_buf(&worklist, nnzb_c);
+    if (st == BSM_OK) st = keep_buf(&worklist2, nnzb_c);  // target of the work-list sorts
     if (st == BSM_OK) st = tile_order(c_row_ptr, nc.col_idx, nbr, B.nbcols, rb, worklist, s);
     std::vector<int32_t> cuts{0};
     {
@@ -198,11 +216,12 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         max_p = std::max(max_p, h_prp[cuts[q + 1]] - h_prp[cuts[q]]);
         max_c = std::max(max_c, h_crp[cuts[q + 1]] - h_crp[cuts[q]]);
     }
+    // one set of stack buffers reused by every chunk; a plan keeps one per chunk
     int64_t *seg = nullptr;
     int32_t *stk_a = nullptr, *stk_b = nullptr;
-    if (st == BSM_OK) st = tmp.get(&seg, max_c + 1);
-    if (st == BSM_OK) st = tmp.get(&stk_a, max_p);
-    if (st == BSM_OK) st = tmp.get(&stk_b, max_p);
+    if (st == BSM_OK && !pl) st = tmp.get(&seg, max_c + 1);
+    if (st == BSM_OK && !pl) st = tmp.get(&stk_a, max_p);
+    if (st == BSM_OK && !pl) st = tmp.get(&stk_b, max_p);
 
     SmmArgs ma{};
     ma.c_row = c_row; ma.c_col = nc.col_idx; ma.c_blk_off = nc.blk_off; ma.c_vals = nc.values;
@@ -227,6 +246,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     ma.prec = prec;
     ma.seg = seg; ma.stk_a = stk_a; ma.stk_b = stk_b;
     ma.worklist = worklist;
+    if (st == BSM_OK && pl) st = keep_buf(&ma.counter, 1);   // persistent kernel's counter
 
     if (st == BSM_OK && prec != BSM_FP64) {
         if (!(A.uni_r && A.uni_c && B.uni_c && smm_lowp_available(A.uni_r, B.uni_c, A.uni_c))) {
@@ -234,23 +254,38 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             st = BSM_EINVAL;
         }
         uint32_t *apk = nullptr, *bpk = nullptr;
-        if (st == BSM_OK) st = tmp.get(&apk, A.nvalues);
+        if (st == BSM_OK) st = keep_buf(&apk, A.nvalues);
         if (st == BSM_OK) st = pack_lowp(A.values, A.nvalues, apk, prec, s);
         if (st == BSM_OK && &A != &B) {
-            st = tmp.get(&bpk, B.nvalues);
+            st = keep_buf(&bpk, B.nvalues);
             if (st == BSM_OK) st = pack_lowp(B.values, B.nvalues, bpk, prec, s);
         } else {
             bpk = apk;
         }
         ma.a_pk = apk;
         ma.b_pk = bpk;
+        if (pl) { pl->apk = apk; pl->bpk = bpk; }
     }
+
+    auto launch = [&](const MulOp &op) -> int {
+        const int r = run_op(op, s);
+        if (r == BSM_OK && pl) pl->ops.push_back(op);
+        return r;
+    };
 
     for (size_t q = 0; st == BSM_OK && q + 1 < cuts.size(); ++q) {
         const int32_t r0 = cuts[q], r1 = cuts[q + 1];
         ma.c0 = h_crp[r0];
         ma.nC = h_crp[r1] - h_crp[r0];
         if (ma.nC == 0) continue;
+        if (pl) {
+            const int64_t np = h_prp[r1] - h_prp[r0];
+            st = keep_buf(&seg, ma.nC + 1);
+            if (st == BSM_OK) st = keep_buf(&stk_a, np);
+            if (st == BSM_OK) st = keep_buf(&stk_b, np);
+            if (st != BSM_OK) break;
+            ma.seg = seg; ma.stk_a = stk_a; ma.stk_b = stk_b;
+        }
         st = sym_stack(sa, r0, r1, c_row_ptr, p_row_ptr, seg, stk_a, stk_b, s);
         if (st != BSM_OK) break;
         // mixed sizes: cost-sorted list for the fused persistent launch, or
@@ -273,29 +308,38 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             BSM_HIP(hipEventCreate(&pe.second));
             BSM_HIP(hipEventRecord(pe.first, s));
         }
+        MulOp op;
+        op.a = ma;
         if (prec != BSM_FP64) {
-            st = smm_launch_lowp(ma, s);
+            op.kind = kOpLowp;
+            st = launch(op);
         } else if (var == kSmmF64Class) {
-            SmmArgs cls = ma;
             int64_t off = 0;
             for (int b = 0; b < 17 && st == BSM_OK; ++b) {
                 if (hist[b] == 0) continue;
-                cls.worklist = worklist2 + off;
-                cls.nC = hist[b];
+                op.a.worklist = worklist2 + off;
+                op.a.nC = hist[b];
                 // per class: the (m, n)-specialised kernel unless the tuning
                 // table holds run-time-kernel parameters for (m, n, any k)
                 static const int sz[4] = {5, 13, 23, 26};
                 SmmParams prm;
-                if (b < 16 && !(table_lookup(sz[b / 4], sz[b % 4], 0, &prm) && prm.family != 2))
-                    st = launch_class(cls, b, s);
-                else if (b < 16)
-                    st = launch_rt(cls, prm, s);
-                else
-                    st = smm_launch(cls, kSmmF64Tuned, s);
+                if (b < 16 && !(table_lookup(sz[b / 4], sz[b % 4], 0, &prm) && prm.family != 2)) {
+                    op.kind = kOpClass;
+                    op.id = b;
+                } else if (b < 16) {
+                    op.kind = kOpRt;
+                    op.prm = prm;
+                } else {
+                    op.kind = kOpVariant;
+                    op.id = kSmmF64Tuned;
+                }
+                st = launch(op);
                 off += hist[b];
             }
         } else {
-            st = smm_launch(ma, var, s);
+            op.kind = kOpVariant;
+            op.id = var;
+            st = launch(op);
         }
         if (ev.on) {
             BSM_HIP(hipEventRecord(pe.second, s));
@@ -305,7 +349,36 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
 
     // 6. filter
     int64_t nnzb_after = nnzb_c;
-    if (st == BSM_OK && eps > 0.0) st = compact_by_norm(nc, sq, mx, eps, norm, s, &nnzb_after);
+    CompactKeep ck;
+    if (st == BSM_OK && eps > 0.0)
+        st = compact_by_norm(nc, sq, mx, eps, norm, s, &nnzb_after, pl ? &ck : nullptr);
+    if (pl) {
+        // the plan owns the keep maps and the unfiltered layout
+        for (void *q : {static_cast<void *>(ck.kidx), static_cast<void *>(ck.koff),
+                        static_cast<void *>(ck.row_ptr), static_cast<void *>(ck.col_idx),
+                        static_cast<void *>(ck.blk_off), static_cast<void *>(ck.values)})
+            if (q) pl->owned.push_back(q);
+        if (st == BSM_OK) {
+            pl->compacted = ck.compacted;
+            if (ck.compacted) {
+                pl->c_col_u = ck.col_idx;
+                pl->c_blk_off_u = ck.blk_off;
+                pl->c_vals_u = ck.values;
+            } else {
+                st = keep_buf(&pl->c_col_u, nnzb_c);
+                if (st == BSM_OK) st = keep_buf(&pl->c_blk_off_u, nnzb_c + 1);
+                hipError_t e = hipSuccess;
+                if (st == BSM_OK && nnzb_c)
+                    e = hipMemcpyAsync(pl->c_col_u, nc.col_idx, sizeof(int32_t) * nnzb_c,
+                                       hipMemcpyDeviceToDevice, s);
+                if (st == BSM_OK && e == hipSuccess)
+                    e = hipMemcpyAsync(pl->c_blk_off_u, nc.blk_off, sizeof(int64_t) * (nnzb_c + 1),
+                                       hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) { set_error("plan copy: %s", hipGetErrorString(e)); st = BSM_EDEVICE; }
+            }
+            for (MulOp &o : pl->ops) { o.a.c_col = pl->c_col_u; o.a.c_blk_off = pl->c_blk_off_u; }
+        }
+    }
     int h_flags = 0;
     if (st == BSM_OK) {
         hipError_t e = hipMemcpyAsync(&h_flags, flags, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -338,10 +411,23 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         stats->smm_ms = smm;
         stats->total_ms = (hipEventElapsedTime(&ms, ev.t0, ev.t1) == hipSuccess) ? ms : 0.0;
     }
+    if (pl) {
+        pl->alpha = alpha; pl->beta = beta; pl->eps = eps; pl->norm = norm; pl->prec = prec;
+        pl->use_c = use_c;
+        pl->same_ab = (&A == &B);
+        pl->a_nnzb = A.nnzb; pl->b_nnzb = B.nnzb; pl->a_nval = A.nvalues; pl->b_nval = B.nvalues;
+        pl->cin_nnzb = use_c ? cin_nnzb : 0;
+        pl->nnzb_u = nnzb_c; pl->nval_u = nval_c;
+        pl->nnzb = nc.nnzb; pl->nval = nc.nvalues;
+        pl->flops = flops; pl->nprod = nprod;
+        pl->sq = sq; pl->mx = mx;
+        pl->kidx = ck.kidx; pl->koff = ck.koff;
+    }
     if (h_flags & kFlagNonFinite) {
         set_error("a product block holds NaN or Inf");
         return BSM_ENONFINITE;
     }
+    if (pl) { *plan = pl; pl = nullptr; }
     return BSM_OK;
 }
 

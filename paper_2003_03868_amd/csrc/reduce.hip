@@ -114,7 +114,7 @@ k_compact_blocks(const int64_t *kidx, const int64_t *koff, const int32_t *col_id
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
 
 int compact_by_norm(Mat &m, const double *sq, const double *mx, double eps, int norm,
-                    hipStream_t s, int64_t *nnzb_after) {
+                    hipStream_t s, int64_t *nnzb_after, CompactKeep *keep) {
     const int64_t n = m.nnzb;
     *nnzb_after = n;
     if (n == 0) return BSM_OK;
@@ -151,7 +151,13 @@ int compact_by_norm(Mat &m, const double *sq, const double *mx, double eps, int 
             if (e != hipSuccess) { set_error("filter kernels: %s", hipGetErrorString(e)); st = BSM_EDEVICE; }
         }
         if (st == BSM_OK) {
-            free_mat_arrays(m, s);
+            if (keep) {
+                keep->row_ptr = m.row_ptr; keep->col_idx = m.col_idx;
+                keep->blk_off = m.blk_off; keep->values = m.values;
+                keep->compacted = true;
+            } else {
+                free_mat_arrays(m, s);
+            }
             m.row_ptr = nm.row_ptr; m.col_idx = nm.col_idx; m.blk_off = nm.blk_off;
             m.values = nm.values;
             m.nnzb = tot[0];
@@ -160,8 +166,13 @@ int compact_by_norm(Mat &m, const double *sq, const double *mx, double eps, int 
             dfree(nm.row_ptr, s); dfree(nm.col_idx, s); dfree(nm.blk_off, s); dfree(nm.values, s);
         }
     }
-    dfree(kidx, s);
-    dfree(koff, s);
+    if (keep && st == BSM_OK) {
+        keep->kidx = kidx;
+        keep->koff = koff;
+    } else {
+        dfree(kidx, s);
+        dfree(koff, s);
+    }
     *nnzb_after = m.nnzb;
     return st;
 }
@@ -261,6 +272,15 @@ k_sqdist_rows(const int64_t *row_ptr, const int32_t *col_idx, const int64_t *blk
         if (!has_diag) r += static_cast<double>(m) * shift * shift;
         part[i] = r;
     }
+}
+
+int sqdist_identity_dev(const Mat &m, double shift, double *part, double *d_out, hipStream_t s) {
+    if (m.nbrows == 0) { set_error("empty matrix"); return BSM_EINVAL; }
+    k_sqdist_rows<<<m.nbrows, kRedThreads, 0, s>>>(m.row_ptr, m.col_idx, m.blk_off, m.values,
+                                                   m.rbs, m.cbs, shift, part);
+    k_reduce_final<<<1, 1024, 0, s>>>(part, m.nbrows, d_out, 0);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
 }
 
 int sqdist_identity(const Mat &m, double shift, double *out, hipStream_t s) {

@@ -9,10 +9,20 @@
 //
 // The spectrum is first scaled into [-1, 1] by the infinity norm (a
 // Gershgorin bound), so every eigenvalue converges monotonically to +-1.
+//
+// Graph replay (opts.use_graph): once an update leaves the block pattern of X
+// unchanged, the symbolic results of both multiplies stay valid for the next
+// iteration as long as the filter keeps the same blocks.  The numeric kernels
+// of the square (with the residual reduction) and of the update are then
+// captured into hipGraphs -- one pair per parity of two ping-pong value
+// buffers of X -- and replayed with one wait per iteration.  The replayed
+// multiplies check on the device that the filter's keep-set is unchanged; if
+// it is not, the affected iteration is redone on the normal path from the
+// intact previous iterate, so results equal those of the normal path.
 #include <cmath>
 #include <cstring>
 
-#include "bsm_internal.h"
+#include "plan.h"
 
 namespace bsm {
 
@@ -29,6 +39,180 @@ static int validate_opts(const Mat &H, const bsm_sign_opts &o) {
     if (o.prec != BSM_FP64 && o.prec != BSM_FP32 && o.prec != BSM_SPLIT_BF16) { set_error("sign: unknown precision"); return BSM_EINVAL; }
     if (o.fp64_final_iters < 0) { set_error("sign: fp64_final_iters must be >= 0"); return BSM_EINVAL; }
     return BSM_OK;
+}
+
+// Precision of the products of iteration k: reduced until the residual first
+// drops below prec_switch_tol (with fixed_iters: for all but the last
+// fp64_final_iters updates), FP64 afterwards.
+static int prec_of(const bsm_sign_opts &o, const bsm_sign_stats &st, int k) {
+    if (o.prec == BSM_FP64) return BSM_FP64;
+    if (o.fixed_iters > 0) return k < o.fixed_iters - o.fp64_final_iters ? o.prec : BSM_FP64;
+    for (int j = 0; j < k; ++j)
+        if (st.r_hist[j] < o.prec_switch_tol) return BSM_FP64;
+    return o.prec;
+}
+
+enum { kGoOn = 0, kStop = 1, kStopNoConv = 2 };
+
+// Stopping rule after r_k is known (stall counts non-decreasing residuals).
+static int decide(const bsm_sign_opts &o, const bsm_sign_stats &st, int k, double r, int *stall) {
+    if (o.fixed_iters > 0) return k == o.fixed_iters ? kStop : kGoOn;
+    if (r < o.tol) return kStop;
+    if (k > 0 && r >= st.r_hist[k - 1]) {
+        if (++*stall >= 3) {
+            set_error("sign: residual stopped decreasing at %g (iteration %d)", r, k);
+            return kStopNoConv;
+        }
+    } else {
+        *stall = 0;
+    }
+    if (k == o.max_iter) {
+        set_error("sign: no convergence to %g in %d iterations (r = %g)", o.tol, k, r);
+        return kStopNoConv;
+    }
+    return kGoOn;
+}
+
+namespace {
+// Device status of a replayed iteration, read back with one copy.
+struct Status {
+    double d;        // ||Y - I||_F^2
+    int32_t f_sq;    // flags of the square
+    int32_t f_up;    // flags of the update
+    int32_t diff;    // pattern comparison
+    int32_t pad_[3];
+};
+
+struct Replay {
+    hipStream_t s = nullptr;
+    bool on = false;
+    int prec = 0;
+    MulPlan *psq = nullptr, *pup = nullptr;
+    double *xbuf[2] = {nullptr, nullptr};   // X's values alternate between these
+    int p = 0;                               // X->values == xbuf[p]
+    hipGraphExec_t gsq[2] = {nullptr, nullptr}, gup[2] = {nullptr, nullptr};
+    double *part = nullptr;                  // per-block-row residual partial sums
+    Status *stat = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool up_pending = false;
+    int64_t *snap_rp = nullptr;              // pattern of X before the update
+    int32_t *snap_ci = nullptr;
+    int64_t snap_nnzb = -1, snap_cap = 0;
+
+    void drop_plans() {
+        free_plan(psq); psq = nullptr;
+        free_plan(pup); pup = nullptr;
+    }
+    // Leave replay mode; X keeps the buffer it points at.
+    void leave(Mat &X) {
+        if (!on) return;
+        (void)hipStreamSynchronize(s);
+        for (int q = 0; q < 2; ++q) {
+            if (gsq[q]) (void)hipGraphExecDestroy(gsq[q]);
+            if (gup[q]) (void)hipGraphExecDestroy(gup[q]);
+            gsq[q] = gup[q] = nullptr;
+        }
+        for (double *b : xbuf)
+            if (b && b != X.values) dfree(b, s);
+        xbuf[0] = xbuf[1] = nullptr;
+        on = false;
+        up_pending = false;
+        drop_plans();
+    }
+    ~Replay() {
+        drop_plans();
+        dfree(part, s); dfree(stat, s); dfree(snap_rp, s); dfree(snap_ci, s);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// Capture the kernels body() queues on a private stream into an executable graph.
+template <class F>
+int capture(F body, hipGraphExec_t *out) {
+    hipStream_t cs = nullptr;
+    BSM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        set_error("sign: graph capture: %s", hipGetErrorString(e));
+        return BSM_EDEVICE;
+    }
+    const int rc = body(cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    if (rc == BSM_OK && e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (rc != BSM_OK) return rc;
+    if (e != hipSuccess) { set_error("sign: graph capture: %s", hipGetErrorString(e)); return BSM_EDEVICE; }
+    return BSM_OK;
+}
+}  // namespace
+
+// Keep a copy of X's block pattern (before an update).
+static int snapshot(Replay &R, const Mat &X, hipStream_t s) {
+    if (X.nnzb > R.snap_cap || !R.snap_rp) {
+        dfree(R.snap_ci, s);
+        R.snap_ci = nullptr;
+        R.snap_cap = 0;
+        BSM_TRY(dalloc(&R.snap_ci, X.nnzb + 1, s));
+        R.snap_cap = X.nnzb + 1;
+        if (!R.snap_rp) BSM_TRY(dalloc(&R.snap_rp, X.nbrows + 1, s));
+    }
+    BSM_HIP(hipMemcpyAsync(R.snap_rp, X.row_ptr, sizeof(int64_t) * (X.nbrows + 1),
+                           hipMemcpyDeviceToDevice, s));
+    if (X.nnzb)
+        BSM_HIP(hipMemcpyAsync(R.snap_ci, X.col_idx, sizeof(int32_t) * X.nnzb,
+                               hipMemcpyDeviceToDevice, s));
+    R.snap_nnzb = X.nnzb;
+    return BSM_OK;
+}
+
+// After an update with retained plans: if X's pattern did not change, capture
+// the replay graphs and switch to replay mode; otherwise drop the plans.
+static int maybe_enter(Replay &R, Mat &X, Mat &Y, int prec, hipStream_t s) {
+    bool same = (X.nnzb == R.snap_nnzb) && R.psq->nval == Y.nvalues && R.pup->nval == X.nvalues &&
+                R.psq->a_nval == X.nvalues;
+    if (same) {
+        BSM_TRY(pattern_differs(R.snap_rp, R.snap_ci, X.row_ptr, X.col_idx, X.nbrows, X.nnzb,
+                                &R.stat->diff, s));
+        Status h{};
+        BSM_HIP(hipMemcpyAsync(&h, R.stat, sizeof(Status), hipMemcpyDeviceToHost, s));
+        BSM_HIP(hipStreamSynchronize(s));
+        same = (h.diff == 0);
+    }
+    if (!same) {
+        R.drop_plans();
+        return BSM_OK;
+    }
+    double *other = nullptr;
+    BSM_TRY(dalloc(&other, X.nvalues, s));
+    int rc = zero_flag(&R.stat->f_sq, s);
+    if (rc == BSM_OK) rc = zero_flag(&R.stat->f_up, s);
+    if (rc != BSM_OK) { dfree(other, s); return rc; }
+    R.xbuf[0] = X.values;
+    R.xbuf[1] = other;
+    R.p = 0;
+    for (int q = 0; q < 2 && rc == BSM_OK; ++q) {
+        X.values = R.xbuf[q];
+        double *next = R.xbuf[1 - q];
+        rc = capture([&](hipStream_t cs) -> int {
+            BSM_TRY(zero_flag(&R.stat->f_sq, cs));
+            BSM_TRY(replay_multiply(*R.psq, X, X, nullptr, Y.values, &R.stat->f_sq, cs));
+            return sqdist_identity_dev(Y, 1.0, R.part, &R.stat->d, cs);
+        }, &R.gsq[q]);
+        if (rc != BSM_OK) break;
+        rc = capture([&](hipStream_t cs) -> int {
+            BSM_TRY(zero_flag(&R.stat->f_up, cs));
+            return replay_multiply(*R.pup, X, Y, &X, next, &R.stat->f_up, cs);
+        }, &R.gup[q]);
+    }
+    X.values = R.xbuf[0];
+    R.on = true;            // leave() cleans up what was made
+    R.prec = prec;
+    if (rc != BSM_OK) R.leave(X);
+    return rc;
 }
 
 int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sign_stats *st,
@@ -54,19 +238,95 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
     rc = alloc_like_sizes(*X, *X, &Y, s);
     if (rc != BSM_OK) { free_mat(X, s); return rc; }
 
-    bool low = (o.prec != BSM_FP64);
+    const bool want_graph = o.use_graph != 0;
+    Replay R;
+    R.s = s;
+    if (want_graph) {
+        rc = dalloc(&R.part, X->nbrows, s);
+        if (rc == BSM_OK) rc = dalloc(&R.stat, 1, s);
+        for (int i = 0; i < 4 && rc == BSM_OK; ++i)
+            if (hipEventCreate(&R.ev[i]) != hipSuccess) { set_error("sign: event creation failed"); rc = BSM_EDEVICE; }
+        if (rc != BSM_OK) { free_mat(X, s); free_mat(Y, s); return rc; }
+    }
+
     int stall = 0;
-    for (int k = 0;; ++k) {
-        // precision of this round's products
-        int prec = BSM_FP64;
-        if (low) {
-            if (o.fixed_iters > 0) low = (k < o.fixed_iters - o.fp64_final_iters);
-            else if (k > 0 && st->r_hist[k - 1] < o.prec_switch_tol) low = false;
-            if (low) prec = o.prec;
-        }
+    int stall_at[128] = {0};   // stall count before the decision of iteration k
+    for (int k = 0;;) {
+        const int prec = prec_of(o, *st, k);
         st->prec_hist[k] = prec;
+        if (R.on) {
+            // numeric-only iteration from the captured graphs
+            const bool same_prec = (prec == R.prec);
+            if (same_prec) {
+                (void)hipEventRecord(R.ev[0], s);
+                if (hipGraphLaunch(R.gsq[R.p], s) != hipSuccess) { set_error("sign: graph launch failed"); rc = BSM_EDEVICE; break; }
+                (void)hipEventRecord(R.ev[1], s);
+            }
+            Status h{};
+            if (hipMemcpyAsync(&h, R.stat, sizeof(Status), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                set_error("sign: reading the replay status failed");
+                rc = BSM_EDEVICE;
+                break;
+            }
+            float ms = 0.f;
+            const bool had_up = R.up_pending;
+            if (had_up && hipEventElapsedTime(&ms, R.ev[2], R.ev[3]) == hipSuccess) st->smm_ms += ms;
+            R.up_pending = false;
+            if (had_up && h.f_up) {
+                // the replayed update of iteration k-1 is not valid (its filter
+                // keeps other blocks, or NaN/Inf): back to X_{k-1}, redo k-1
+                st->n_multiplies -= 2;
+                st->flops -= R.psq->flops + R.pup->flops;
+                st->n_products -= R.psq->nprod + R.pup->nprod;
+                st->graph_replays--;
+                st->graph_fallbacks++;
+                R.p ^= 1;
+                X->values = R.xbuf[R.p];
+                R.leave(*X);
+                --k;
+                stall = stall_at[k];
+                continue;
+            }
+            if (same_prec && h.f_sq == 0) {
+                if (hipEventElapsedTime(&ms, R.ev[0], R.ev[1]) == hipSuccess) st->smm_ms += ms;
+                st->n_multiplies++;
+                st->flops += R.psq->flops;
+                st->n_products += R.psq->nprod;
+                const double r = std::sqrt(h.d) / n;
+                st->r_hist[k] = r;
+                st->iterations = k;
+                if (!std::isfinite(r)) {
+                    set_error("sign: residual is not finite at iteration %d", k);
+                    rc = BSM_ENONFINITE;
+                    break;
+                }
+                stall_at[k] = stall;
+                const int dcs = decide(o, *st, k, r, &stall);
+                if (dcs != kGoOn) { rc = (dcs == kStop) ? BSM_OK : BSM_ENOCONV; break; }
+                (void)hipEventRecord(R.ev[2], s);
+                if (hipGraphLaunch(R.gup[R.p], s) != hipSuccess) { set_error("sign: graph launch failed"); rc = BSM_EDEVICE; break; }
+                (void)hipEventRecord(R.ev[3], s);
+                R.up_pending = true;
+                st->n_multiplies++;
+                st->flops += R.pup->flops;
+                st->n_products += R.pup->nprod;
+                st->graph_replays++;
+                R.p ^= 1;
+                X->values = R.xbuf[R.p];
+                ++k;
+                continue;
+            }
+            // another precision from here on, or the square's keep-set changed
+            if (same_prec) st->graph_fallbacks++;
+            R.leave(*X);
+        }
+
+        // iteration k on the normal path (retaining plans when graphs are wanted)
+        R.drop_plans();
         bsm_mult_stats ms{};
-        rc = multiply(1.0, *X, *X, 0.0, *Y, o.eps_filter, o.norm, prec, &ms, s);
+        rc = multiply(1.0, *X, *X, 0.0, *Y, o.eps_filter, o.norm, prec, &ms, s,
+                      want_graph ? &R.psq : nullptr);
         st->n_multiplies++;
         st->flops += ms.flops;
         st->n_products += ms.n_products;
@@ -83,32 +343,28 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
             rc = BSM_ENONFINITE;
             break;
         }
-        if (o.fixed_iters > 0) {
-            if (k == o.fixed_iters) break;
-        } else {
-            if (r < o.tol) break;
-            if (k > 0 && r >= st->r_hist[k - 1]) {
-                if (++stall >= 3) {
-                    set_error("sign: residual stopped decreasing at %g (iteration %d)", r, k);
-                    rc = BSM_ENOCONV;
-                    break;
-                }
-            } else {
-                stall = 0;
-            }
-            if (k == o.max_iter) {
-                set_error("sign: no convergence to %g in %d iterations (r = %g)", o.tol, k, r);
-                rc = BSM_ENOCONV;
-                break;
-            }
+        stall_at[k] = stall;
+        const int dcs = decide(o, *st, k, r, &stall);
+        if (dcs != kGoOn) { rc = (dcs == kStop) ? BSM_OK : BSM_ENOCONV; break; }
+        if (want_graph && R.psq) {
+            rc = snapshot(R, *X, s);
+            if (rc != BSM_OK) break;
         }
-        rc = multiply(-0.5, *X, *Y, 1.5, *X, o.eps_filter, o.norm, prec, &ms, s);
+        rc = multiply(-0.5, *X, *Y, 1.5, *X, o.eps_filter, o.norm, prec, &ms, s,
+                      (want_graph && R.psq) ? &R.pup : nullptr);
         st->n_multiplies++;
         st->flops += ms.flops;
         st->n_products += ms.n_products;
         st->smm_ms += ms.smm_ms;
         if (rc != BSM_OK) break;
+        if (want_graph && R.psq && R.pup) {
+            rc = maybe_enter(R, *X, *Y, prec, s);
+            if (rc != BSM_OK) break;
+        }
+        ++k;
     }
+    R.leave(*X);
+    R.drop_plans();
     free_mat(Y, s);
     if (rc == BSM_OK || rc == BSM_ENOCONV) {
         double tx = 0.0;

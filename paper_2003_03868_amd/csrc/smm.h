@@ -60,6 +60,7 @@ struct SmmArgs {
     int32_t fused_ok;             // every block size is in {5, 13, 23, 26}
     int32_t pad_;
     int32_t prec;               // bsm_precision
+    unsigned long long *counter;  // work counter of the persistent kernel (NULL: allocated per launch)
 };
 
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s);

@@ -436,14 +436,14 @@ static int launch_persistent(const SmmArgs &a, hipStream_t s) {
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const size_t lds = sizeof(double) * (static_cast<size_t>(a.max_m) * a.max_k +
                                          static_cast<size_t>(a.max_k) * a.max_n);
-    unsigned long long *counter = nullptr;
-    BSM_TRY(dalloc(&counter, 1, s));
+    unsigned long long *counter = a.counter;
+    if (!counter) BSM_TRY(dalloc(&counter, 1, s));
     k_zero_u64<<<1, 1, 0, s>>>(counter);
     const int64_t want = static_cast<int64_t>(cus) * 8;    // 2 waves per SIMD (its occupancy)
     const unsigned grid = static_cast<unsigned>(want < a.nC ? want : a.nC);
     k_smm_f64_persistent<<<grid, 64, lds, s>>>(a, counter);
     const hipError_t e = hipGetLastError();
-    dfree(counter, s);
+    if (!a.counter) dfree(counter, s);
     if (e != hipSuccess) { set_error("persistent launch: %s", hipGetErrorString(e)); return BSM_EDEVICE; }
     return BSM_OK;
 }

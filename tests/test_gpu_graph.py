@@ -1,0 +1,119 @@
+"""Sign iterations replayed from captured hipGraphs (opts.use_graph = 1).
+
+Replays run the same kernels on the same symbolic data as the normal path,
+so every residual r_k and the returned X must match the normal path bit for
+bit; against the oracle they are held to the FP64 tolerance.  Each sign call
+replays its graphs many times with host waits and eager work (the normal-path
+iterations before capture, the trace) in between, and every replay's square
+is checked through its residual."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import TOL_FP64, TOL_MIXED, assert_same_matrix, from_dev, need_gpu, rel_fro, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _run(h, eps, tol, use_graph, prec=0, fixed=0):
+    from paper_2003_03868_amd import bsm
+    d = to_dev(h)
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol, o.prec, o.use_graph, o.fixed_iters = eps, tol, prec, use_graph, fixed
+    st, xh, stats = bsm.bsm_sign_iterate(d.handle, 0.0, o)
+    x = from_dev(bsm.Matrix(xh, h.row_blk_size, h.col_blk_size)) if xh else None
+    return st, x, stats
+
+
+def _same_run(a, b):
+    (st0, x0, s0), (st1, x1, s1) = a, b
+    assert st0 == st1
+    assert s0.iterations == s1.iterations
+    k = s0.iterations + 1
+    assert np.array_equal(np.array(s0.r_hist[:k]), np.array(s1.r_hist[:k])), "residuals differ"
+    assert list(s0.prec_hist[:k]) == list(s1.prec_hist[:k])
+    assert s0.n_multiplies == s1.n_multiplies
+    assert s0.n_products == s1.n_products
+    assert s0.flops == s1.flops
+    assert np.array_equal(x0.row_ptr, x1.row_ptr) and np.array_equal(x0.col_idx, x1.col_idx)
+    assert np.array_equal(x0.values, x1.values), "X differs from the normal path"
+    assert s0.trace_x == s1.trace_x
+
+
+GRAPH_CASES = [
+    # eps = 0: X fills in after a few updates, then every iteration replays
+    dict(n=64, b=5, rc=4.0, eps=0.0, seed=3, tol=1e-10, replays=True),
+    dict(n=96, b=13, rc=4.5, eps=0.0, seed=4, tol=1e-10, replays=True),
+    # filtered: the kept pattern settles near convergence
+    dict(n=200, b=5, rc=6.0, eps=1e-6, seed=5, tol=1e-8, replays=False),
+    dict(n=100, b=23, rc=4.2, eps=1e-6, seed=6, tol=1e-8, replays=False),
+    # coarse filter: keep-sets change often (exercises the fallback)
+    dict(n=160, b=13, rc=5.0, eps=1e-3, seed=11, tol=1e-4, replays=False),
+]
+
+
+@pytest.mark.parametrize("c", GRAPH_CASES, ids=lambda c: f"n{c['n']}b{c['b']}e{c['eps']:g}")
+def test_graph_replay_matches_normal_path_and_oracle(orc, c):
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(c["n"], c["b"], cutoff=c["rc"], seed=c["seed"])
+    ref = _run(h, c["eps"], c["tol"], 0)
+    got = _run(h, c["eps"], c["tol"], 1)
+    assert got[0] == bsm.OK, bsm.bsm_last_error()
+    _same_run(ref, got)
+    s = got[2]
+    print(f"n={c['n']} b={c['b']} eps={c['eps']:g}: iterations {s.iterations}, "
+          f"replays {s.graph_replays}, fallbacks {s.graph_fallbacks}")
+    if c["replays"]:
+        assert s.graph_replays > 0
+    assert ref[2].graph_replays == 0
+    x_ref, st_ref, s_ref = orc.sign_ns(h, eps=c["eps"], tol=c["tol"])
+    assert s_ref == orc.OK and s.iterations == st_ref["iterations"]
+    assert_same_matrix(got[1], x_ref, TOL_FP64, "graph sign")
+
+
+def test_graph_replay_fixed_iterations(orc):
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(64, 5, cutoff=4.0, seed=3)
+    ref = _run(h, 0.0, 0.0, 0, fixed=12)
+    got = _run(h, 0.0, 0.0, 1, fixed=12)
+    assert got[0] == bsm.OK and got[2].iterations == 12
+    _same_run(ref, got)
+    assert got[2].graph_replays > 0
+    x_ref, _, _ = orc.sign_ns(h, eps=0.0, fixed_iters=12)
+    assert_same_matrix(got[1], x_ref, TOL_FP64, "graph fixed")
+
+
+@pytest.mark.parametrize("variant", ["3", "4"], ids=["persistent", "class"])
+def test_graph_replay_mixed_sizes_and_chunks(orc, monkeypatch, variant):
+    """Mixed block sizes (class or persistent kernels) in several chunks."""
+    from paper_2003_03868_amd import bsm
+    monkeypatch.setenv("BSM_SMM_VARIANT", variant)
+    monkeypatch.setenv("BSM_CHUNK_PRODUCTS", "3000")
+    h = synth.neighbour_hamiltonian(100, seed=9, cutoff=4.5, size_choices=(5, 13, 23, 26))
+    ref = _run(h, 0.0, 1e-9, 0)
+    got = _run(h, 0.0, 1e-9, 1)
+    assert got[0] == bsm.OK, bsm.bsm_last_error()
+    _same_run(ref, got)
+    assert got[2].graph_replays > 0
+    x_ref, _, _ = orc.sign_ns(h, eps=0.0, tol=1e-9)
+    assert_same_matrix(got[1], x_ref, TOL_FP64, "graph mixed")
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "split_bf16"])
+def test_graph_replay_mixed_precision(orc, prec):
+    """Reduced-precision replays, then the switch to FP64 leaves replay mode."""
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(64, 13, cutoff=4.0, seed=12)
+    ref = _run(h, 0.0, 1e-9, 0, prec=prec)
+    got = _run(h, 0.0, 1e-9, 1, prec=prec)
+    assert got[0] == bsm.OK, bsm.bsm_last_error()
+    _same_run(ref, got)
+    used = list(got[2].prec_hist[:got[2].iterations + 1])
+    assert used[0] == prec and used[-1] == bsm.FP64
+    x_ref, _, _ = orc.sign_ns(h, eps=0.0, tol=1e-9)
+    assert rel_fro(got[1].to_dense(), x_ref.to_dense()) <= TOL_MIXED
