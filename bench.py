@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--table", choices=["exhaustive", "mlp", "none"], default="exhaustive",
                     help="kernel-parameter table: measured (exhaustive autotuning), predicted "
                          "by the MLP, or none (built-in choices)")
+    ap.add_argument("--graph", type=int, choices=[0, 1], default=0,
+                    help="1: replay captured hipGraphs once X's block pattern stops changing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -141,6 +143,7 @@ def main():
     opts.eps_filter = args.eps
     opts.tol = args.tol
     opts.prec = {"fp64": bsm.FP64, "fp32": bsm.FP32, "bf16": bsm.SPLIT_BF16}[args.prec]
+    opts.use_graph = args.graph
     stream = torch.cuda.current_stream()
 
     def step():
@@ -169,7 +172,8 @@ def main():
         all_stats.append((stats, tp))
         log(f"step {k}: {times[-1] * 1e3:.0f} ms, {stats.iterations} iterations, "
             f"r={stats.r_hist[stats.iterations]:.2e}, trace(P)={tp:.6f}, "
-            f"smm {stats.smm_ms:.0f} ms, nnzb(X)={stats.nnzb_final}")
+            f"smm {stats.smm_ms:.0f} ms, nnzb(X)={stats.nnzb_final}, "
+            f"graph replays {stats.graph_replays} (fallbacks {stats.graph_fallbacks})")
     total = sum(times)
     flops = sum(s.flops for s, _ in all_stats)
     smm_ms = sum(s.smm_ms for s, _ in all_stats)
@@ -207,6 +211,7 @@ def main():
             "n_sites": h.nbrows, "block": 23 if args.workload == "sign23" else "5/13/23/26",
             "n": int(n), "eps_filter": args.eps, "kernel_table": args.table,
             "tol": args.tol, "seed": args.seed, "nnzb_H": h.nnzb,
+            "graph_replay": bool(args.graph),
         },
         "time_to_sign_ms": ms_per_step,
         "iterations": int(s0.iterations),
@@ -217,6 +222,8 @@ def main():
         "tflop_per_step": flops / args.steps / 1e12,
         "products_per_step": int(sum(s.n_products for s, _ in all_stats) / args.steps),
         "nnzb_X_final": int(s0.nnzb_final),
+        "graph_replays": int(s0.graph_replays),
+        "graph_fallbacks": int(s0.graph_fallbacks),
         "roofline": {
             "bound": "mfma",
             "kernel": "k_smm_f64_fixed<23,23,23>" if args.prec == "fp64" else "k_smm_lowp",

@@ -361,14 +361,19 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         if (st == BSM_OK) {
             pl->compacted = ck.compacted;
             if (ck.compacted) {
+                pl->c_row_ptr_u = ck.row_ptr;
                 pl->c_col_u = ck.col_idx;
                 pl->c_blk_off_u = ck.blk_off;
                 pl->c_vals_u = ck.values;
             } else {
                 st = keep_buf(&pl->c_col_u, nnzb_c);
                 if (st == BSM_OK) st = keep_buf(&pl->c_blk_off_u, nnzb_c + 1);
+                if (st == BSM_OK) st = keep_buf(&pl->c_row_ptr_u, nbr + 1);
                 hipError_t e = hipSuccess;
-                if (st == BSM_OK && nnzb_c)
+                if (st == BSM_OK)
+                    e = hipMemcpyAsync(pl->c_row_ptr_u, nc.row_ptr, sizeof(int64_t) * (nbr + 1),
+                                       hipMemcpyDeviceToDevice, s);
+                if (st == BSM_OK && e == hipSuccess && nnzb_c)
                     e = hipMemcpyAsync(pl->c_col_u, nc.col_idx, sizeof(int32_t) * nnzb_c,
                                        hipMemcpyDeviceToDevice, s);
                 if (st == BSM_OK && e == hipSuccess)

@@ -42,7 +42,8 @@ struct MulPlan {
     bool compacted = false;           // the filter dropped blocks
     double flops = 0.0;
     int64_t nprod = 0;
-    int32_t *c_col_u = nullptr;       // unfiltered pattern (plan-owned)
+    int64_t *c_row_ptr_u = nullptr;   // unfiltered pattern (plan-owned)
+    int32_t *c_col_u = nullptr;
     int64_t *c_blk_off_u = nullptr;
     double *c_vals_u = nullptr;       // unfiltered values when compacted
     double *sq = nullptr, *mx = nullptr;  // block norms of the product
@@ -58,6 +59,12 @@ struct MulPlan {
 // collects kFlagNonFinite and kFlagPattern; the caller clears it beforehand.
 int replay_multiply(MulPlan &p, const Mat &A, const Mat &B, const Mat *Cin, double *out,
                     int *flags, hipStream_t s);
+
+// Rebuild m from a replay's unfiltered product (vals_u: the plan's
+// unfiltered layout; may be m.values) and filter it anew.  Used when the
+// filter of a replay keeps other blocks than the plan recorded: the product
+// itself is still exact, only its compaction changes.
+int refilter(const MulPlan &p, const double *vals_u, Mat &m, hipStream_t s);
 
 // *f = 0 by a kernel (usable inside a captured graph).
 int zero_flag(int *f, hipStream_t s);

@@ -88,6 +88,37 @@ int replay_multiply(MulPlan &p, const Mat &A, const Mat &B, const Mat *Cin, doub
     return BSM_OK;
 }
 
+int refilter(const MulPlan &p, const double *vals_u, Mat &m, hipStream_t s) {
+    int64_t *rp = nullptr, *bo = nullptr;
+    int32_t *ci = nullptr;
+    double *v = nullptr;
+    int st = dalloc(&rp, m.nbrows + 1, s);
+    if (st == BSM_OK) st = dalloc(&ci, p.nnzb_u, s);
+    if (st == BSM_OK) st = dalloc(&bo, p.nnzb_u + 1, s);
+    if (st == BSM_OK) st = dalloc(&v, p.nval_u, s);
+    hipError_t e = hipSuccess;
+    if (st == BSM_OK) {
+        e = hipMemcpyAsync(rp, p.c_row_ptr_u, sizeof(int64_t) * (m.nbrows + 1), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && p.nnzb_u)
+            e = hipMemcpyAsync(ci, p.c_col_u, sizeof(int32_t) * p.nnzb_u, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(bo, p.c_blk_off_u, sizeof(int64_t) * (p.nnzb_u + 1), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && p.nval_u)
+            e = hipMemcpyAsync(v, vals_u, sizeof(double) * p.nval_u, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) { set_error("refilter: %s", hipGetErrorString(e)); st = BSM_EDEVICE; }
+    }
+    if (st != BSM_OK) {
+        dfree(rp, s); dfree(ci, s); dfree(bo, s); dfree(v, s);
+        return st;
+    }
+    free_mat_arrays(m, s);
+    m.row_ptr = rp; m.col_idx = ci; m.blk_off = bo; m.values = v;
+    m.nnzb = p.nnzb_u;
+    m.nvalues = p.nval_u;
+    int64_t after = 0;
+    return compact_by_norm(m, p.sq, p.mx, p.eps, p.norm, s, &after);
+}
+
 __global__ void k_pattern_diff(const int64_t *rp_a, const int32_t *ci_a, const int64_t *rp_b,
                                const int32_t *ci_b, int32_t nbrows, int64_t nnzb, int *diff) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;

@@ -17,8 +17,10 @@
 // captured into hipGraphs -- one pair per parity of two ping-pong value
 // buffers of X -- and replayed with one wait per iteration.  The replayed
 // multiplies check on the device that the filter's keep-set is unchanged; if
-// it is not, the affected iteration is redone on the normal path from the
-// intact previous iterate, so results equal those of the normal path.
+// it is not, the (exact) unfiltered product of the replay is filtered and
+// compacted anew and the iteration continues on the normal path, so results
+// equal those of the normal path.  NaN/Inf in a replayed update sends the
+// iteration back to the intact previous iterate, to be redone normally.
 #include <cmath>
 #include <cstring>
 
@@ -254,6 +256,7 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
     for (int k = 0;;) {
         const int prec = prec_of(o, *st, k);
         st->prec_hist[k] = prec;
+        bool have_y = false;   // Y of iteration k already formed from a replay
         if (R.on) {
             // numeric-only iteration from the captured graphs
             const bool same_prec = (prec == R.prec);
@@ -273,9 +276,9 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
             const bool had_up = R.up_pending;
             if (had_up && hipEventElapsedTime(&ms, R.ev[2], R.ev[3]) == hipSuccess) st->smm_ms += ms;
             R.up_pending = false;
-            if (had_up && h.f_up) {
-                // the replayed update of iteration k-1 is not valid (its filter
-                // keeps other blocks, or NaN/Inf): back to X_{k-1}, redo k-1
+            if (had_up && (h.f_up & kFlagNonFinite)) {
+                // NaN/Inf in the replayed update of iteration k-1: back to
+                // X_{k-1} and redo k-1 on the normal path (which reports it)
                 st->n_multiplies -= 2;
                 st->flops -= R.psq->flops + R.pup->flops;
                 st->n_products -= R.psq->nprod + R.pup->nprod;
@@ -288,7 +291,28 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
                 stall = stall_at[k];
                 continue;
             }
-            if (same_prec && h.f_sq == 0) {
+            if (had_up && h.f_up) {
+                // X_k's product is exact but its filter keeps other blocks:
+                // filter it anew; iteration k then runs on the normal path
+                double *old = X->values;
+                rc = refilter(*R.pup, R.pup->compacted ? R.pup->c_vals_u : old, *X, s);
+                for (double *&b : R.xbuf)
+                    if (b == old) b = nullptr;   // released with X's old arrays
+                st->graph_fallbacks++;
+                R.leave(*X);
+                if (rc != BSM_OK) break;
+            } else if (same_prec && h.f_sq == kFlagPattern) {
+                // the square is exact but its filter keeps other blocks
+                if (hipEventElapsedTime(&ms, R.ev[0], R.ev[1]) == hipSuccess) st->smm_ms += ms;
+                st->n_multiplies++;
+                st->flops += R.psq->flops;
+                st->n_products += R.psq->nprod;
+                rc = refilter(*R.psq, R.psq->compacted ? R.psq->c_vals_u : Y->values, *Y, s);
+                st->graph_fallbacks++;
+                R.leave(*X);
+                if (rc != BSM_OK) break;
+                have_y = true;
+            } else if (same_prec && h.f_sq == 0) {
                 if (hipEventElapsedTime(&ms, R.ev[0], R.ev[1]) == hipSuccess) st->smm_ms += ms;
                 st->n_multiplies++;
                 st->flops += R.psq->flops;
@@ -316,21 +340,24 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
                 X->values = R.xbuf[R.p];
                 ++k;
                 continue;
+            } else {
+                // another precision from here on, or NaN/Inf in the square
+                if (same_prec) st->graph_fallbacks++;
+                R.leave(*X);
             }
-            // another precision from here on, or the square's keep-set changed
-            if (same_prec) st->graph_fallbacks++;
-            R.leave(*X);
         }
 
         // iteration k on the normal path (retaining plans when graphs are wanted)
         R.drop_plans();
         bsm_mult_stats ms{};
-        rc = multiply(1.0, *X, *X, 0.0, *Y, o.eps_filter, o.norm, prec, &ms, s,
-                      want_graph ? &R.psq : nullptr);
-        st->n_multiplies++;
-        st->flops += ms.flops;
-        st->n_products += ms.n_products;
-        st->smm_ms += ms.smm_ms;
+        if (!have_y) {
+            rc = multiply(1.0, *X, *X, 0.0, *Y, o.eps_filter, o.norm, prec, &ms, s,
+                          want_graph ? &R.psq : nullptr);
+            st->n_multiplies++;
+            st->flops += ms.flops;
+            st->n_products += ms.n_products;
+            st->smm_ms += ms.smm_ms;
+        }
         if (rc != BSM_OK && rc != BSM_ENONFINITE) break;
         double d = 0.0;
         if (rc == BSM_OK) rc = sqdist_identity(*Y, 1.0, &d, s);

@@ -47,13 +47,13 @@ def _same_run(a, b):
 
 GRAPH_CASES = [
     # eps = 0: X fills in after a few updates, then every iteration replays
-    dict(n=64, b=5, rc=4.0, eps=0.0, seed=3, tol=1e-10, replays=True),
-    dict(n=96, b=13, rc=4.5, eps=0.0, seed=4, tol=1e-10, replays=True),
-    # filtered: the kept pattern settles near convergence
-    dict(n=200, b=5, rc=6.0, eps=1e-6, seed=5, tol=1e-8, replays=False),
-    dict(n=100, b=23, rc=4.2, eps=1e-6, seed=6, tol=1e-8, replays=False),
-    # coarse filter: keep-sets change often (exercises the fallback)
-    dict(n=160, b=13, rc=5.0, eps=1e-3, seed=11, tol=1e-4, replays=False),
+    dict(n=64, b=5, rc=4.0, eps=0.0, seed=3, tol=1e-10, replays=True, fallbacks=False),
+    dict(n=96, b=13, rc=4.5, eps=0.0, seed=4, tol=1e-10, replays=True, fallbacks=False),
+    # filtered: the kept pattern settles near convergence, and replayed
+    # products whose filter keeps other blocks are re-filtered
+    dict(n=200, b=5, rc=6.0, eps=1e-6, seed=5, tol=1e-8, replays=True, fallbacks=True),
+    dict(n=100, b=23, rc=4.2, eps=1e-6, seed=6, tol=1e-8, replays=False, fallbacks=True),
+    dict(n=160, b=13, rc=5.0, eps=1e-3, seed=11, tol=1e-4, replays=True, fallbacks=True),
 ]
 
 
@@ -70,6 +70,8 @@ def test_graph_replay_matches_normal_path_and_oracle(orc, c):
           f"replays {s.graph_replays}, fallbacks {s.graph_fallbacks}")
     if c["replays"]:
         assert s.graph_replays > 0
+    if c["fallbacks"]:
+        assert s.graph_fallbacks > 0
     assert ref[2].graph_replays == 0
     x_ref, st_ref, s_ref = orc.sign_ns(h, eps=c["eps"], tol=c["tol"])
     assert s_ref == orc.OK and s.iterations == st_ref["iterations"]
