@@ -85,6 +85,10 @@ def _load():
             lib.orc_shift_scale.argtypes = [P, C.c_double, C.c_double, P]
             lib.orc_sign_ns.argtypes = [P, C.c_double, C.c_double, C.c_int, C.c_double,
                                         C.c_int32, C.c_int32, P, C.POINTER(_SignStats)]
+            lib.orc_sign.argtypes = [P, C.c_double, C.c_double, C.c_int, C.c_double,
+                                     C.c_int32, C.c_int32, C.c_int32, P, C.POINTER(_SignStats)]
+            lib.orc_add.argtypes = [C.c_double, P, C.c_double, P, C.c_double, C.c_double,
+                                    C.c_int, P]
             lib.orc_density_from_sign.argtypes = [P, P]
             lib.orc_free.argtypes = [P]
             lib.orc_num_threads.restype = C.c_int
@@ -180,9 +184,22 @@ def shift_scale(a: BSR, mu: float, scale: float) -> BSR:
     return _out(out, a.row_blk_size, a.col_blk_size)
 
 
+def add(alpha: float, a: BSR, beta: float = 0.0, b: BSR | None = None, gamma: float = 0.0,
+        eps: float = 0.0, norm="frob") -> BSR:
+    """C = alpha A + beta B + gamma I (pattern union), then the filter."""
+    lib = _load()
+    oa, ka = _in(a)
+    ob, kb = _in(b) if b is not None else (None, None)
+    out = _OMat()
+    _check(lib.orc_add(alpha, C.byref(oa), beta, C.byref(ob) if ob is not None else None,
+                       gamma, eps, _norm(norm), C.byref(out)), "add")
+    return _out(out, a.row_blk_size, a.col_blk_size)
+
+
 def sign_ns(h: BSR, mu: float = 0.0, eps: float = 0.0, tol: float = 1e-6,
-            max_iter: int = 100, fixed_iters: int = 0, norm="frob"):
-    """Second-order Newton-Schulz sign iteration; returns (X, stats, status).
+            max_iter: int = 100, fixed_iters: int = 0, norm="frob", order: int = 2):
+    """Sign iteration of the given order (2: Newton-Schulz, 3, 5); returns
+    (X, stats, status).
 
     ``status`` is OK, ENOCONV or ENONFINITE; X is the last iterate in every
     case that produced one.
@@ -191,10 +208,10 @@ def sign_ns(h: BSR, mu: float = 0.0, eps: float = 0.0, tol: float = 1e-6,
     oh, kh = _in(h)
     out = _OMat()
     st = _SignStats()
-    status = lib.orc_sign_ns(C.byref(oh), mu, eps, _norm(norm), tol, max_iter, fixed_iters,
-                             C.byref(out), C.byref(st))
+    status = lib.orc_sign(C.byref(oh), mu, eps, _norm(norm), tol, max_iter, fixed_iters, order,
+                          C.byref(out), C.byref(st))
     if status not in (OK, ENOCONV, ENONFINITE):
-        raise RuntimeError(f"oracle sign_ns failed with status {status}")
+        raise RuntimeError(f"oracle sign iteration failed with status {status}")
     x = _out(out, h.row_blk_size, h.col_blk_size) if out.row_ptr else None
     stats = dict(iterations=int(st.iterations), n_multiplies=int(st.n_multiplies),
                  r_hist=[float(st.r_hist[k]) for k in range(st.iterations + 1)],

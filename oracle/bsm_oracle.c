@@ -395,6 +395,75 @@ int orc_shift_scale(const omat *a, double mu, double scale, omat *out)
     return status;
 }
 
+/*
+ * C = alpha * A + beta * B + gamma * I, then the norm filter: the matrix sum
+ * of the DBCSR operations (DBCSR section lists multiply, sum, trace and
+ * transpose).  Stored pattern = pattern(A) union pattern(B), plus the diagonal
+ * blocks when gamma != 0 (square diagonal blocks required then).  Per element
+ * v = alpha*a + beta*b with a, b = 0 where a block is absent, then v += gamma
+ * on the diagonal.  b may be NULL (empty).
+ */
+int orc_add(double alpha, const omat *a, double beta, const omat *b, double gamma,
+            double eps, int norm_kind, omat *out)
+{
+    if (b && (a->nbrows != b->nbrows || a->nbcols != b->nbcols)) return ORC_EINVAL;
+    for (int32_t i = 0; i < a->nbrows; ++i) if (a->rbs[i] < 1 || a->rbs[i] > 64) return ORC_EINVAL;
+    for (int32_t j = 0; j < a->nbcols; ++j) if (a->cbs[j] < 1 || a->cbs[j] > 64) return ORC_EINVAL;
+    if (b) {
+        for (int32_t i = 0; i < a->nbrows; ++i) if (a->rbs[i] != b->rbs[i]) return ORC_EINVAL;
+        for (int32_t j = 0; j < a->nbcols; ++j) if (a->cbs[j] != b->cbs[j]) return ORC_EINVAL;
+    }
+    if (gamma != 0.0) {
+        if (a->nbrows != a->nbcols) return ORC_EINVAL;
+        for (int32_t i = 0; i < a->nbrows; ++i) if (a->rbs[i] != a->cbs[i]) return ORC_EINVAL;
+    }
+    if (eps < 0) return ORC_EINVAL;
+    int64_t *offa = block_offsets(a);
+    int64_t *offb = b ? block_offsets(b) : NULL;
+    rowbuf *rows = (rowbuf *)calloc((size_t)(a->nbrows ? a->nbrows : 1), sizeof(rowbuf));
+    double *tmp = (double *)malloc(sizeof(double) * 64 * 64);
+    if (!offa || (b && !offb) || !rows || !tmp) {
+        free(offa); free(offb); free(rows); free(tmp);
+        return ORC_ENOMEM;
+    }
+    int status = ORC_OK;
+    for (int32_t i = 0; i < a->nbrows && status == ORC_OK; ++i) {
+        const int32_t m = a->rbs[i];
+        int64_t ta = a->row_ptr[i], tb = b ? b->row_ptr[i] : 0;
+        const int64_t ea = a->row_ptr[i + 1], eb = b ? b->row_ptr[i + 1] : 0;
+        int done_diag = (gamma == 0.0);
+        for (;;) {
+            const int32_t ja = ta < ea ? a->col_idx[ta] : a->nbcols;
+            const int32_t jb = tb < eb ? b->col_idx[tb] : a->nbcols;
+            const int32_t jd = done_diag ? a->nbcols : i;
+            int32_t j = ja < jb ? ja : jb;
+            if (jd < j) j = jd;
+            if (j >= a->nbcols) break;
+            if (j == i) done_diag = 1;
+            const int32_t n = a->cbs[j];
+            for (int e = 0; e < m * n; ++e) tmp[e] = 0.0;
+            if (ja == j) {
+                for (int e = 0; e < m * n; ++e) tmp[e] = alpha * a->values[offa[ta] + e];
+                ++ta;
+            }
+            if (jb == j) {
+                for (int e = 0; e < m * n; ++e) tmp[e] = tmp[e] + beta * b->values[offb[tb] + e];
+                ++tb;
+            }
+            if (j == i && gamma != 0.0)
+                for (int r = 0; r < m; ++r) tmp[r * m + r] = tmp[r * m + r] + gamma;
+            if (keep_block(tmp, (int64_t)m * n, eps, norm_kind))
+                status = rowbuf_push(&rows[i], j, tmp, (int64_t)m * n);
+            if (status != ORC_OK) break;
+        }
+    }
+    if (status == ORC_OK)
+        status = assemble(out, a->nbrows, a->nbcols, a->rbs, a->cbs, rows);
+    free_rows(rows, a->nbrows);
+    free(offa); free(offb); free(tmp);
+    return status;
+}
+
 /* ------------------------------------------------------- sign iteration */
 
 typedef struct {
@@ -420,11 +489,72 @@ static double product_flops(const omat *a, const omat *b)
 }
 
 /*
- * Matrix sign by the second-order Newton-Schulz iteration, and the density
- * matrix P = (I - sign(H - mu I)) / 2 with S = I (Sign-Method section,
- * Eq. signdef, the density-matrix relation, and the first refinement function
- * f_1(Z) = Z(3 - Y)/2 of the OT/IR paragraph, with Y = Z^2 for a symmetric
- * Z and S = I):
+ * Update X_{k+1} = X_k q(Y) / d from Y = X_k^2 for the iteration orders of
+ * the Sign-Method section (Newton-Schulz, and the Pade-type iterations of
+ * third and fifth order; Eq. fifth_order_sign), written with the OT/IR
+ * refinement functions f_1, f_2 (Y = Z^2 for symmetric Z, S = I):
+ *
+ *   order 2:  X' = filter(1.5 X - 0.5 X Y)                      f_1 = Z(3 - Y)/2
+ *   order 3:  W  = filter(3 Y Y + (15 I - 10 Y))
+ *             X' = filter(X W / 8)                              f_2 = Z(15 - 10Y + 3Y^2)/8
+ *   order 5:  Y2 = filter(Y Y)
+ *             V  = filter(35 Y2 - 180 Y + 378 I)
+ *             U  = filter(Y2 V + (315 I - 420 Y))
+ *             X' = filter(X U / 128)                            Eq. fifth_order_sign
+ *
+ * The fifth-order form uses four multiplies per iteration (with the square
+ * Y), as the Sign-Method section states; every product is filtered.  The
+ * constant-plus-Y terms enter a multiply as its C_in.
+ */
+static int sign_update(int32_t order, const omat *x, const omat *y, double eps, int norm_kind,
+                       omat *xn, orc_sign_stats *st)
+{
+    omat c = {0}, w = {0}, y2 = {0}, v = {0};
+    int status;
+    if (order == 2) {
+        st->flops += product_flops(x, y);
+        st->n_multiplies++;
+        return orc_multiply(-0.5, x, y, 1.5, x, eps, norm_kind, xn);
+    }
+    if (order == 3) {
+        status = orc_shift_scale(y, 1.5, -10.0, &c);                  /* 15 I - 10 Y */
+        if (status == ORC_OK) {
+            st->flops += product_flops(y, y);
+            st->n_multiplies++;
+            status = orc_multiply(3.0, y, y, 1.0, &c, eps, norm_kind, &w);
+        }
+        if (status == ORC_OK) {
+            st->flops += product_flops(x, &w);
+            st->n_multiplies++;
+            status = orc_multiply(0.125, x, &w, 0.0, NULL, eps, norm_kind, xn);
+        }
+        orc_free(&c); orc_free(&w);
+        return status;
+    }
+    /* order 5 */
+    st->flops += product_flops(y, y);
+    st->n_multiplies++;
+    status = orc_multiply(1.0, y, y, 0.0, NULL, eps, norm_kind, &y2);
+    if (status == ORC_OK) status = orc_add(35.0, &y2, -180.0, y, 378.0, eps, norm_kind, &v);
+    if (status == ORC_OK) status = orc_shift_scale(y, 0.75, -420.0, &c);   /* 315 I - 420 Y */
+    if (status == ORC_OK) {
+        st->flops += product_flops(&y2, &v);
+        st->n_multiplies++;
+        status = orc_multiply(1.0, &y2, &v, 1.0, &c, eps, norm_kind, &w);
+    }
+    if (status == ORC_OK) {
+        st->flops += product_flops(x, &w);
+        st->n_multiplies++;
+        status = orc_multiply(1.0 / 128.0, x, &w, 0.0, NULL, eps, norm_kind, xn);
+    }
+    orc_free(&c); orc_free(&w); orc_free(&y2); orc_free(&v);
+    return status;
+}
+
+/*
+ * Matrix sign by the iterations of sign_update, and the density matrix
+ * P = (I - sign(H - mu I)) / 2 with S = I (Sign-Method section, Eq. signdef
+ * and the density-matrix relation):
  *
  *   s   = ||H - mu I||_inf               (scaling so the spectrum is in [-1, 1])
  *   X_0 = (H - mu I) / s                 (not filtered)
@@ -432,18 +562,19 @@ static double product_flops(const omat *a, const omat *b)
  *       Y   = filter(X_k X_k)
  *       r_k = ||Y - I||_F / n            (n = scalar dimension)
  *       stop if r_k < tol                 (or after fixed_iters updates)
- *       X_{k+1} = filter(1.5 X_k - 0.5 X_k Y)
+ *       X_{k+1} = X_k q(Y) / d            (sign_update; order 2: 1.5 X - 0.5 X Y)
  *
  * Filtering after every product follows the Sign-Method section.  Returns the
  * last X (whose square was tested).  ORC_ENOCONV when r_k is not finite, when
  * r_k >= r_{k-1} three times in a row, or when max_iter updates did not reach
  * tol.
  */
-int orc_sign_ns(const omat *h, double mu, double eps, int norm_kind, double tol,
-                int32_t max_iter, int32_t fixed_iters, omat *x_out, orc_sign_stats *st)
+int orc_sign(const omat *h, double mu, double eps, int norm_kind, double tol,
+             int32_t max_iter, int32_t fixed_iters, int32_t order, omat *x_out,
+             orc_sign_stats *st)
 {
     if (h->nbrows != h->nbcols || eps < 0 || max_iter < 0 || max_iter > 120 ||
-        fixed_iters < 0 || fixed_iters > 120)
+        fixed_iters < 0 || fixed_iters > 120 || (order != 2 && order != 3 && order != 5))
         return ORC_EINVAL;
     for (int32_t i = 0; i < h->nbrows; ++i) if (h->rbs[i] != h->cbs[i]) return ORC_EINVAL;
     memset(st, 0, sizeof(*st));
@@ -475,9 +606,7 @@ int orc_sign_ns(const omat *h, double mu, double eps, int norm_kind, double tol,
             else stall = 0;
             if (k == max_iter) { status = ORC_ENOCONV; break; }
         }
-        st->flops += product_flops(&x, &y);
-        status = orc_multiply(-0.5, &x, &y, 1.5, &x, eps, norm_kind, &xn);
-        st->n_multiplies++;
+        status = sign_update(order, &x, &y, eps, norm_kind, &xn, st);
         orc_free(&y);
         if (status != ORC_OK) break;
         orc_free(&x);
@@ -491,6 +620,13 @@ int orc_sign_ns(const omat *h, double mu, double eps, int norm_kind, double tol,
     }
     *x_out = x;
     return status;
+}
+
+/* The second-order (Newton-Schulz) form of orc_sign. */
+int orc_sign_ns(const omat *h, double mu, double eps, int norm_kind, double tol,
+                int32_t max_iter, int32_t fixed_iters, omat *x_out, orc_sign_stats *st)
+{
+    return orc_sign(h, mu, eps, norm_kind, tol, max_iter, fixed_iters, 2, x_out, st);
 }
 
 /* P = (I - X)/2 as a new matrix (inserts missing diagonal blocks). */

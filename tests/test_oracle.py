@@ -394,3 +394,103 @@ def test_density_matrix_identities(orc):
     lhs = np.linalg.norm(dp @ dp - dp)
     assert lhs == pytest.approx(0.25 * np.linalg.norm(dx @ dx - np.eye(n)), rel=1e-6)
     assert orc.trace(p) == pytest.approx(st["trace_p"], abs=1e-12)
+
+
+# ----------------------------------------------------------- matrix sum
+
+def _expected_add(alpha, a, beta, b, gamma, eps, norm):
+    """Dense alpha A + beta B + gamma I, pattern by set logic, then the filter."""
+    d = alpha * a.to_dense()
+    s = set(a.pattern())
+    if b is not None:
+        d = d + beta * b.to_dense()
+        s |= b.pattern()
+    if gamma != 0.0:
+        d = d + gamma * np.eye(d.shape[0])
+        s |= {(i, i) for i in range(a.nbrows)}
+    ro = np.concatenate([[0], np.cumsum(a.row_blk_size)])
+    co = np.concatenate([[0], np.cumsum(a.col_blk_size)])
+    kept = {}
+    for (i, j) in s:
+        blk = d[ro[i]:ro[i + 1], co[j]:co[j + 1]]
+        v, thr = ((float((blk * blk).sum()), eps * eps) if norm == "frob"
+                  else (float(np.abs(blk).max()), eps))
+        if not (v < thr):
+            kept[(i, j)] = blk
+    return kept
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_add_matches_dense(orc, seed):
+    """C = alpha A + beta B + gamma I against dense arithmetic and set logic."""
+    rng = np.random.default_rng(700 + seed)
+    nb = int(rng.integers(1, 9))
+    sizes = rng.integers(1, 12, nb)
+    a = synth.random_bsr(nb, nb, sizes, sizes, float(rng.choice([0.0, 0.3, 0.7])), rng)
+    b = synth.random_bsr(nb, nb, sizes, sizes, float(rng.choice([0.0, 0.3, 0.7])), rng)
+    alpha, beta = float(rng.normal()), float(rng.normal())
+    for gamma in (0.0, 378.0):
+        for norm, eps in (("frob", 0.0), ("frob", 0.8), ("maxabs", 0.3)):
+            got = orc.add(alpha, a, beta, b, gamma, eps=eps, norm=norm)
+            exp = _expected_add(alpha, a, beta, b, gamma, eps, norm)
+            gb = _blocks(got)
+            assert set(gb) == set(exp)
+            for key, blk in exp.items():
+                assert np.allclose(gb[key], blk, rtol=1e-15, atol=1e-15)
+    # B absent
+    got = orc.add(-420.0, a, gamma=315.0)
+    assert set(_blocks(got)) == set(_expected_add(-420.0, a, 0.0, None, 315.0, 0.0, "frob"))
+
+
+# ------------------------------------------- higher-order sign iterations
+
+@pytest.mark.parametrize("order,poly", [(2, "f1"), (3, "f2"), (5, "p5")])
+def test_sign_orders_follow_printed_polynomials(orc, order, poly):
+    """Diagonal H: every update of the order-p iteration must equal the
+    polynomial printed in the paper (OT/IR f_1, f_2; Eq. fifth_order_sign),
+    g(x) = x q(x^2)/den, evaluated independently with numpy."""
+    _, coef, den = _read_polys()[poly]
+    rng = np.random.default_rng(40 + order)
+    sizes = rng.integers(1, 6, 9)
+    n = int(sizes.sum())
+    h = rng.uniform(0.05, 4.0, n) * rng.choice([-1.0, 1.0], n)
+    m = _diag_matrix(h, sizes)
+    x = h / np.abs(h).max()
+    for k in range(1, 4):
+        xk, st, status = orc.sign_ns(m, eps=0.0, fixed_iters=k, order=order)
+        assert status == orc.OK and st["iterations"] == k
+        x = x * np.polynomial.polynomial.polyval(x * x, coef) / den
+        assert np.allclose(np.diag(xk.to_dense()), x, rtol=1e-13, atol=1e-15)
+        per_update = {2: 2, 3: 3, 5: 4}[order]
+        assert st["n_multiplies"] == per_update * k + 1
+
+
+@pytest.mark.parametrize("order", [3, 5])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_sign_higher_orders_match_eigh(orc, order, seed):
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(1, 14, 8)
+    n = int(sizes.sum())
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = rng.uniform(0.1, 3.0, n) * rng.choice([-1.0, 1.0], n)
+    d = (q * lam) @ q.T
+    d = 0.5 * (d + d.T)
+    m = _dense_to_bsr(d, sizes)
+    x, st, status = orc.sign_ns(m, eps=0.0, tol=1e-13, order=order)
+    assert status == orc.OK
+    _, st2, _ = orc.sign_ns(m, eps=0.0, tol=1e-13, order=2)
+    assert st["iterations"] < st2["iterations"]
+    ref, nneg = _eig_sign(d)
+    assert _rel(x.to_dense(), ref) <= 1e-12
+    assert st["trace_p"] == pytest.approx(nneg, abs=1e-9)
+
+
+def test_sign_higher_orders_filtered_neighbour(orc):
+    """Filtered order-5 run on a neighbour Hamiltonian: trace(P) is the
+    occupied count and X^2 is the identity to the filter's accuracy."""
+    h = synth.neighbour_hamiltonian(200, 5, cutoff=6.0, seed=4)
+    x, st, status = orc.sign_ns(h, eps=1e-6, tol=1e-7, order=5)
+    assert status == orc.OK
+    assert st["trace_p"] == pytest.approx(h.meta["n_occ"], abs=1e-4)
+    dx = x.to_dense()
+    assert np.linalg.norm(dx @ dx - np.eye(dx.shape[0])) / dx.shape[0] < 1e-5

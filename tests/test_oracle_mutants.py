@@ -20,8 +20,16 @@ MUTANTS = [
     ("mirrored_b", "acc[r * n + c] += av * bb[t * n + c];",
      "acc[r * n + c] += av * bb[t * n + (n - 1 - c)];"),
     ("a_row_index", "const double av = ab[r * kk + t];", "const double av = ab[(m - 1 - r) * kk + t];"),
-    ("ns_coefficient", "orc_multiply(-0.5, &x, &y, 1.5, &x,", "orc_multiply(-0.5, &x, &y, 1.25, &x,"),
-    ("ns_alpha", "orc_multiply(-0.5, &x, &y,", "orc_multiply(-0.45, &x, &y,"),
+    ("ns_coefficient", "orc_multiply(-0.5, x, y, 1.5, x,", "orc_multiply(-0.5, x, y, 1.25, x,"),
+    ("ns_alpha", "orc_multiply(-0.5, x, y,", "orc_multiply(-0.45, x, y,"),
+    ("o3_coefficient", "orc_shift_scale(y, 1.5, -10.0, &c)", "orc_shift_scale(y, 1.5, -9.0, &c)"),
+    ("o3_scale", "orc_multiply(0.125, x, &w,", "orc_multiply(0.25, x, &w,"),
+    ("o5_coefficient", "orc_add(35.0, &y2, -180.0, y, 378.0,", "orc_add(35.0, &y2, -180.0, y, 387.0,"),
+    ("o5_cin", "orc_shift_scale(y, 0.75, -420.0, &c)", "orc_shift_scale(y, 0.75, -410.0, &c)"),
+    ("o5_scale", "orc_multiply(1.0 / 128.0, x, &w,", "orc_multiply(1.0 / 64.0, x, &w,"),
+    ("add_gamma", "tmp[r * m + r] = tmp[r * m + r] + gamma;", "tmp[r * m + r] = tmp[r * m + r] - gamma;"),
+    ("add_b_index", "tmp[e] = tmp[e] + beta * b->values[offb[tb] + e];",
+     "tmp[e] = tmp[e] + beta * b->values[offb[tb]];"),
     ("residual_norm", "double r = sqrt(orc_sqdist_identity(&y, 1.0)) / n;",
      "double r = sqrt(orc_sqdist_identity(&y, 1.0) / n);"),
     ("shift_sign", "tmp[r * m + r] = scale * (a->values[off[t] + (int64_t)r * m + r] - mu);",
