@@ -93,6 +93,8 @@ typedef struct {
     int32_t fp64_final_iters;/* mixed precision: last updates done in FP64 */
     int32_t use_graph;       /* 1: replay captured iterations where possible */
     double prec_switch_tol;  /* mixed precision: FP64 once r_k < this */
+    int32_t order;           /* 2 (Newton-Schulz), 3 or 5: see bsm_sign_iterate */
+    int32_t pad_;
 } bsm_sign_opts;
 
 typedef struct {
@@ -113,7 +115,7 @@ typedef struct {
                                 the filter kept other blocks (or NaN/Inf appeared) */
 } bsm_sign_stats;
 
-/* Default options: eps 0, tol 1e-6, max_iter 100, FROB, FP64, no graph. */
+/* Default options: eps 0, tol 1e-6, max_iter 100, FROB, FP64, no graph, order 2. */
 void bsm_sign_opts_default(bsm_sign_opts *opts);
 
 /*
@@ -193,7 +195,15 @@ int bsm_inf_norm(bsm_matrix A, double mu, double *out, void *stream);
  * whose square was tested.  stats may be NULL.  BSM_ENOCONV if r_k is not
  * finite, grows three times in a row, or max_iter is reached (X is still
  * returned); BSM_ENONFINITE for NaN/Inf in H.
- * opts->use_graph = 1: once an update leaves X's block pattern unchanged, the
+ * opts->order selects the update X_{k+1} = X_k q(Y)/d from Y = X_k^2 (the
+ * Newton-Schulz and Pade-type iterations of the Sign-Method section, in the
+ * form of the OT/IR refinement functions; every product filtered):
+ *   2: X' = 1.5 X - 0.5 X Y                                   (2 multiplies)
+ *   3: W = 3 Y Y + (15 I - 10 Y);  X' = X W / 8               (3 multiplies)
+ *   5: Y2 = Y Y;  V = 35 Y2 - 180 Y + 378 I (bsm_add);
+ *      U = Y2 V + (315 I - 420 Y);  X' = X U / 128            (4 multiplies,
+ *      Eq. fifth_order_sign)
+ * opts->use_graph = 1 (order 2 only): once an update leaves X's block pattern unchanged, the
  * following iterations replay captured hipGraphs of the numeric kernels (one
  * wait per iteration; no symbolic phase, allocation or compaction scan).  A
  * replayed iteration whose filter would keep other blocks is redone on the
@@ -201,6 +211,19 @@ int bsm_inf_norm(bsm_matrix A, double mu, double *out, void *stream);
  */
 int bsm_sign_iterate(bsm_matrix H, double mu, const bsm_sign_opts *opts,
                      bsm_matrix *x_out, bsm_sign_stats *stats, void *stream);
+
+/*
+ * C = alpha*A + beta*B + gamma*I, then the norm filter, as a new handle (the
+ * matrix sum among the DBCSR operations of the DBCSR section).  B may be NULL
+ * (treated as empty); otherwise A and B must have the same block sizes.
+ * Pattern: pattern(A) union pattern(B), plus every diagonal block when
+ * gamma != 0 (then A must be square with square diagonal blocks).  Per
+ * element v = alpha*a + beta*b (absent blocks read as zero), then v += gamma
+ * on the diagonal.  BSM_EINVAL for mismatched sizes, eps < 0 or non-finite
+ * coefficients.
+ */
+int bsm_add(double alpha, bsm_matrix A, double beta, bsm_matrix B, double gamma,
+            double eps_filter, int32_t norm, bsm_matrix *out, void *stream);
 
 /* P = (I - X)/2 from a sign matrix X, as a new handle; trace_p (may be NULL) gets trace(P). */
 int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void *stream);

@@ -46,7 +46,7 @@ class bsm_sign_opts(C.Structure):
     _fields_ = [("eps_filter", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("fixed_iters", C.c_int32), ("norm", C.c_int32), ("prec", C.c_int32),
                 ("fp64_final_iters", C.c_int32), ("use_graph", C.c_int32),
-                ("prec_switch_tol", C.c_double)]
+                ("prec_switch_tol", C.c_double), ("order", C.c_int32), ("pad_", C.c_int32)]
 
 
 class bsm_sign_stats(C.Structure):
@@ -86,6 +86,8 @@ _SIGS = [
     ("bsm_inf_norm", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double), C.c_void_p]),
     ("bsm_sign_iterate", C.c_int, [C.c_void_p, C.c_double, C.POINTER(bsm_sign_opts),
                                    C.POINTER(C.c_void_p), C.POINTER(bsm_sign_stats), C.c_void_p]),
+    ("bsm_add", C.c_int, [C.c_double, C.c_void_p, C.c_double, C.c_void_p, C.c_double,
+                          C.c_double, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
     ("bsm_density_from_sign", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p),
                                         C.POINTER(C.c_double), C.c_void_p]),
     ("bsm_smm_bench", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
@@ -227,6 +229,14 @@ def bsm_sign_iterate(h, mu=0.0, opts: bsm_sign_opts | None = None, stream=None):
     if st not in (OK, ENOCONV, ENONFINITE):
         _check(st, "bsm_sign_iterate")
     return st, out.value, stats
+
+
+def bsm_add(alpha, a, beta=0.0, b=None, gamma=0.0, eps_filter=0.0, norm=0, stream=None) -> int:
+    """C = alpha A + beta B + gamma I, filtered, as a new handle."""
+    out = C.c_void_p()
+    _check(load().bsm_add(float(alpha), a, float(beta), b, float(gamma), float(eps_filter),
+                          int(norm), C.byref(out), _stream(stream)), "bsm_add")
+    return out.value
 
 
 def bsm_density_from_sign(h, stream=None):

@@ -68,6 +68,7 @@ void bsm_sign_opts_default(bsm_sign_opts *o) {
     o->prec = BSM_FP64;
     o->fp64_final_iters = 2;
     o->use_graph = 0;
+    o->order = 2;
     o->prec_switch_tol = 1e-4;
 }
 
@@ -210,6 +211,20 @@ int bsm_shift_scale(bsm_matrix A, double mu, double scale, bsm_matrix *out, void
     if (!A || !out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
     Mat *m = nullptr;
     BSM_TRY(bsm::shift_scale(A->m, mu, scale, &m, as_stream(stream)));
+    auto *h = new bsm_matrix_s;
+    h->m = std::move(*m);
+    delete m;
+    *out = h;
+    return BSM_OK;
+}
+
+int bsm_add(double alpha, bsm_matrix A, double beta, bsm_matrix B, double gamma,
+            double eps_filter, int32_t norm, bsm_matrix *out, void *stream) {
+    bsm::clear_error();
+    if (!A || !out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    Mat *m = nullptr;
+    BSM_TRY(bsm::add_mat(alpha, A->m, beta, B ? &B->m : nullptr, gamma, eps_filter, norm, &m,
+                         as_stream(stream)));
     auto *h = new bsm_matrix_s;
     h->m = std::move(*m);
     delete m;

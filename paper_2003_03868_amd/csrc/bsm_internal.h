@@ -102,6 +102,9 @@ int sqdist_identity(const Mat &m, double shift, double *out, hipStream_t s);
 int inf_norm(const Mat &m, double mu, double *out, hipStream_t s);
 int shift_scale(const Mat &a, double mu, double scale, Mat **out, hipStream_t s);
 int copy_mat(const Mat &a, Mat **out, hipStream_t s);
+// C = alpha A + beta B + gamma I (b may be NULL), filtered, as a new matrix (add.hip).
+int add_mat(double alpha, const Mat &a, double beta, const Mat *b, double gamma, double eps,
+            int norm, Mat **out, hipStream_t s);
 int alloc_like_sizes(const Mat &proto_rows, const Mat &proto_cols, Mat **out, hipStream_t s);
 
 // Compaction after the filter (reduce.hip).  keep (may be NULL): instead of

@@ -6,7 +6,8 @@
 //   3. pattern   C col_idx / owning row / matching C_in block
 //   4. offsets   C block value offsets (device scan)
 //   5. per chunk of block rows (bounded product count, like the paper's
-//                bounded batches): product stacks, then the block products
+//                bounded batches): product stacks (for the quad kernel merged
+//                per 2 x 2 group of C blocks, quad.hip), then the block products
 //   6. filter    drop blocks failing the norm test and compact (device)
 //
 // C's old arrays stay alive until everything that reads them is queued, so C
@@ -35,7 +36,7 @@ static int64_t chunk_products() {
 // (tests and the tuner compare variants).
 static int smm_variant() {
     const char *e = getenv("BSM_SMM_VARIANT");
-    return e ? atoi(e) : kSmmF64Fixed;
+    return e ? atoi(e) : kSmmF64Quad;
 }
 
 // Kernel family for a chunk with mixed block sizes (uniform sizes keep the
@@ -45,7 +46,8 @@ static int mixed_variant(const SmmArgs &a, int requested) {
     const bool uniform = a.uni_m && a.uni_n && a.uni_k;
     if (uniform) return requested;
     if (requested == kSmmF64Class && !a.fused_ok) return kSmmF64Fused;
-    if (requested == kSmmF64Fixed) return a.fused_ok ? kSmmF64Class : kSmmF64Fused;
+    if (requested == kSmmF64Fixed || requested == kSmmF64Quad)
+        return a.fused_ok ? kSmmF64Class : kSmmF64Fused;
     return requested;
 }
 
@@ -201,12 +203,14 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     if (st == BSM_OK) st = tile_order(c_row_ptr, nc.col_idx, nbr, B.nbcols, rb, worklist, s);
     std::vector<int32_t> cuts{0};
     {
+        // whole row bands; an even step keeps the quads' row pairs in one chunk
         const int64_t lim = chunk_products();
+        const int step = rb + (rb & 1);
         int32_t r0 = 0;
         while (r0 < nbr) {
-            int32_t r1 = std::min(nbr, r0 + rb);
-            while (r1 < nbr && h_prp[std::min(nbr, r1 + rb)] - h_prp[r0] <= lim)
-                r1 = std::min(nbr, r1 + rb);
+            int32_t r1 = std::min(nbr, r0 + step);
+            while (r1 < nbr && h_prp[std::min(nbr, r1 + step)] - h_prp[r0] <= lim)
+                r1 = std::min(nbr, r1 + step);
             cuts.push_back(r1);
             r0 = r1;
         }
@@ -216,12 +220,22 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         max_p = std::max(max_p, h_prp[cuts[q + 1]] - h_prp[cuts[q]]);
         max_c = std::max(max_c, h_crp[cuts[q + 1]] - h_crp[cuts[q]]);
     }
-    // one set of stack buffers reused by every chunk; a plan keeps one per chunk
+    // the quad kernel serves uniform sizes with a compile-time shape unless
+    // the tuning table picks another kernel family for them
+    bool use_quad = false;
+    if (prec == BSM_FP64 && variant == kSmmF64Quad && A.uni_r && A.uni_c && B.uni_c &&
+        smm_quad_available(A.uni_r, B.uni_c, A.uni_c)) {
+        SmmParams tp;
+        use_quad = !(table_lookup(A.uni_r, B.uni_c, A.uni_c, &tp) && tp.family != 3);
+    }
+
+    // one set of stack buffers reused by every chunk; a plan keeps one per
+    // chunk; the quad kernel builds its own lists
     int64_t *seg = nullptr;
     int32_t *stk_a = nullptr, *stk_b = nullptr;
-    if (st == BSM_OK && !pl) st = tmp.get(&seg, max_c + 1);
-    if (st == BSM_OK && !pl) st = tmp.get(&stk_a, max_p);
-    if (st == BSM_OK && !pl) st = tmp.get(&stk_b, max_p);
+    if (st == BSM_OK && !pl && !use_quad) st = tmp.get(&seg, max_c + 1);
+    if (st == BSM_OK && !pl && !use_quad) st = tmp.get(&stk_a, max_p);
+    if (st == BSM_OK && !pl && !use_quad) st = tmp.get(&stk_b, max_p);
 
     SmmArgs ma{};
     ma.c_row = c_row; ma.c_col = nc.col_idx; ma.c_blk_off = nc.blk_off; ma.c_vals = nc.values;
@@ -278,6 +292,62 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         ma.c0 = h_crp[r0];
         ma.nC = h_crp[r1] - h_crp[r0];
         if (ma.nC == 0) continue;
+        if (use_quad) {
+            // quads of this chunk's C blocks and their merged entry lists;
+            // without a plan the buffers live for this chunk only
+            Scratch ctmp(s);
+            auto qbuf = [&](auto **ptr, size_t n) -> int { return pl ? keep_buf(ptr, n) : ctmp.get(ptr, n); };
+            const int64_t npairs = (static_cast<int64_t>(r1 - r0) + 1) / 2;
+            int64_t *q_off = nullptr, *q_cblk = nullptr, *e_off = nullptr;
+            int4 *ent = nullptr;
+            int64_t nq = 0, ne = 0;
+            auto read_total = [&](const int64_t *d, int64_t *h) -> int {
+                hipError_t e = hipMemcpyAsync(h, d, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                if (e != hipSuccess) { set_error("quads: %s", hipGetErrorString(e)); return BSM_EDEVICE; }
+                return BSM_OK;
+            };
+            st = qbuf(&q_off, npairs + 1);
+            if (st == BSM_OK) st = quad_rows(c_row_ptr, nc.col_idx, r0, r1, q_off, nullptr, nullptr, s);
+            if (st == BSM_OK) st = scan_i64(q_off, q_off, npairs, s);
+            if (st == BSM_OK) st = read_total(q_off + npairs, &nq);
+            if (st == BSM_OK) st = qbuf(&q_cblk, 4 * nq);
+            if (st == BSM_OK) st = quad_rows(c_row_ptr, nc.col_idx, r0, r1, nullptr, q_off, q_cblk, s);
+            QuadSymArgs qa{};
+            qa.r0 = r0; qa.r1 = r1; qa.nbcols = B.nbcols;
+            qa.a_row_ptr = A.row_ptr; qa.a_col_idx = A.col_idx;
+            qa.b_row_ptr = B.row_ptr; qa.b_col_idx = B.col_idx;
+            qa.c_row_ptr = c_row_ptr; qa.c_col_idx = nc.col_idx;
+            qa.q_off = q_off;
+            if (st == BSM_OK) st = qbuf(&e_off, nq + 1);
+            qa.e_off = e_off;
+            if (st == BSM_OK) st = quad_stack(qa, false, s);
+            if (st == BSM_OK) st = scan_i64(e_off, e_off, nq, s);
+            if (st == BSM_OK) st = read_total(e_off + nq, &ne);
+            if (st == BSM_OK) st = qbuf(&ent, ne);
+            qa.ent = ent;
+            if (st == BSM_OK) st = quad_stack(qa, true, s);
+            if (st != BSM_OK) break;
+            MulOp op;
+            op.a = ma;
+            op.kind = kOpQuad;
+            op.a.n_quads = nq;
+            op.a.q_cblk = q_cblk;
+            op.a.q_seg = e_off;
+            op.a.q_ent = ent;
+            std::pair<hipEvent_t, hipEvent_t> pe{};
+            if (ev.on) {
+                BSM_HIP(hipEventCreate(&pe.first));
+                BSM_HIP(hipEventCreate(&pe.second));
+                BSM_HIP(hipEventRecord(pe.first, s));
+            }
+            st = launch(op);
+            if (ev.on) {
+                BSM_HIP(hipEventRecord(pe.second, s));
+                ev.smm.push_back(pe);
+            }
+            continue;
+        }
         if (pl) {
             const int64_t np = h_prp[r1] - h_prp[r0];
             st = keep_buf(&seg, ma.nC + 1);
@@ -288,6 +358,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         }
         st = sym_stack(sa, r0, r1, c_row_ptr, p_row_ptr, seg, stk_a, stk_b, s);
         if (st != BSM_OK) break;
+
         // mixed sizes: cost-sorted list for the fused persistent launch, or
         // class-sorted list for one launch per (m, n) class
         const int var = (prec == BSM_FP64) ? mixed_variant(ma, variant) : -1;

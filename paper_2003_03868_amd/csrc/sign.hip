@@ -10,6 +10,15 @@
 // The spectrum is first scaled into [-1, 1] by the infinity norm (a
 // Gershgorin bound), so every eigenvalue converges monotonically to +-1.
 //
+// Orders 3 and 5 (the Pade-type iterations of the Sign-Method section; the
+// fifth-order one is Eq. fifth_order_sign, with four multiplies per
+// iteration) use the same square Y and residual, then (every product
+// filtered):
+//   3:  W = 3 Y Y + (15 I - 10 Y);  X' = X W / 8              (f_2 of OT/IR)
+//   5:  Y2 = Y Y;  V = 35 Y2 - 180 Y + 378 I;  U = Y2 V + (315 I - 420 Y);
+//       X' = X U / 128
+// where the constant-plus-Y term enters the multiply as its C_in.
+//
 // Graph replay (opts.use_graph): once an update leaves the block pattern of X
 // unchanged, the symbolic results of both multiplies stay valid for the next
 // iteration as long as the filter keeps the same blocks.  The numeric kernels
@@ -40,6 +49,7 @@ static int validate_opts(const Mat &H, const bsm_sign_opts &o) {
     if (o.norm != BSM_NORM_FROB && o.norm != BSM_NORM_MAXABS) { set_error("sign: unknown norm"); return BSM_EINVAL; }
     if (o.prec != BSM_FP64 && o.prec != BSM_FP32 && o.prec != BSM_SPLIT_BF16) { set_error("sign: unknown precision"); return BSM_EINVAL; }
     if (o.fp64_final_iters < 0) { set_error("sign: fp64_final_iters must be >= 0"); return BSM_EINVAL; }
+    if (o.order != 2 && o.order != 3 && o.order != 5) { set_error("sign: order must be 2, 3 or 5"); return BSM_EINVAL; }
     return BSM_OK;
 }
 
@@ -217,6 +227,39 @@ static int maybe_enter(Replay &R, Mat &X, Mat &Y, int prec, hipStream_t s) {
     return rc;
 }
 
+// X <- X q(Y) / d for orders 3 and 5 (see the top of this file); Y = X^2.
+static int higher_order_update(const bsm_sign_opts &o, int prec, Mat &X, Mat &Y,
+                               bsm_sign_stats *st, hipStream_t s) {
+    auto mult = [&](double alpha, Mat &A, Mat &B, double beta, Mat &C) -> int {
+        bsm_mult_stats ms{};
+        const int rc = multiply(alpha, A, B, beta, C, o.eps_filter, o.norm, prec, &ms, s);
+        st->n_multiplies++;
+        st->flops += ms.flops;
+        st->n_products += ms.n_products;
+        st->smm_ms += ms.smm_ms;
+        return rc;
+    };
+    Mat *c = nullptr, *y2 = nullptr, *v = nullptr;
+    int rc = BSM_OK;
+    if (o.order == 3) {
+        rc = shift_scale(Y, 1.5, -10.0, &c, s);                      // 15 I - 10 Y
+        if (rc == BSM_OK) rc = mult(3.0, Y, Y, 1.0, *c);             // W = 3 Y Y + C
+        if (rc == BSM_OK) rc = mult(0.125, X, *c, 0.0, X);           // X W / 8
+    } else {
+        rc = alloc_like_sizes(Y, Y, &y2, s);
+        if (rc == BSM_OK) rc = mult(1.0, Y, Y, 0.0, *y2);            // Y2
+        if (rc == BSM_OK)
+            rc = add_mat(35.0, *y2, -180.0, &Y, 378.0, o.eps_filter, o.norm, &v, s);
+        if (rc == BSM_OK) rc = shift_scale(Y, 0.75, -420.0, &c, s);  // 315 I - 420 Y
+        if (rc == BSM_OK) rc = mult(1.0, *y2, *v, 1.0, *c);          // U = Y2 V + C
+        if (rc == BSM_OK) rc = mult(1.0 / 128.0, X, *c, 0.0, X);     // X U / 128
+    }
+    free_mat(c, s);
+    free_mat(y2, s);
+    free_mat(v, s);
+    return rc;
+}
+
 int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sign_stats *st,
                  hipStream_t s) {
     *x_out = nullptr;
@@ -240,7 +283,7 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
     rc = alloc_like_sizes(*X, *X, &Y, s);
     if (rc != BSM_OK) { free_mat(X, s); return rc; }
 
-    const bool want_graph = o.use_graph != 0;
+    const bool want_graph = o.use_graph != 0 && o.order == 2;
     Replay R;
     R.s = s;
     if (want_graph) {
@@ -373,6 +416,12 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
         stall_at[k] = stall;
         const int dcs = decide(o, *st, k, r, &stall);
         if (dcs != kGoOn) { rc = (dcs == kStop) ? BSM_OK : BSM_ENOCONV; break; }
+        if (o.order != 2) {
+            rc = higher_order_update(o, prec, *X, *Y, st, s);
+            if (rc != BSM_OK) break;
+            ++k;
+            continue;
+        }
         if (want_graph && R.psq) {
             rc = snapshot(R, *X, s);
             if (rc != BSM_OK) break;

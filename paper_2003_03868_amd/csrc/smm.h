@@ -27,6 +27,8 @@ enum SmmVariant {
     kSmmF64Class = 4, // one launch per (m, n) class of {5,13,23,26}^2 with an
                       // (m, n)-specialised kernel, run-time k
     kSmmF64Tuned = 5, // tunable run-time-shape kernel, parameters from the table
+    kSmmF64Quad = 6,  // compile-time uniform shapes, one wave per 2 x 2 quad of C
+                      // blocks (default for uniform sizes 5, 13, 23)
 };
 
 struct SmmArgs {
@@ -61,6 +63,11 @@ struct SmmArgs {
     int32_t pad_;
     int32_t prec;               // bsm_precision
     unsigned long long *counter;  // work counter of the persistent kernel (NULL: allocated per launch)
+    // quad kernel: 2 x 2 groups of C blocks with merged product lists
+    int64_t n_quads;
+    const int64_t *q_cblk;      // [4 n_quads] C block (r, c) of the quad at 2r + c, or -1
+    const int64_t *q_seg;       // [n_quads + 1] entry segments
+    const int4 *q_ent;          // A(row 0), A(row 1), B(col 0), B(col 1) block indices or -1
 };
 
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s);
@@ -75,6 +82,10 @@ bool table_lookup(int m, int n, int k, SmmParams *out);    // k = 0: mixed k
 void table_set(int count, const int32_t *mnk, const SmmParams *prm);   // count < 0 clears
 int smm_bench(int m, int n, int k, int64_t n_c, int per_c, int n_prm, const SmmParams *prm,
               int reps, double *ms_out, hipStream_t s);
+
+// Quad kernel (smm_quad.hip): uniform m = n = k in {5, 13, 23}.
+bool smm_quad_available(int m, int n, int k);
+int launch_quad(const SmmArgs &a, hipStream_t s);
 
 // Reduced-precision products (smm_lowp.hip).
 int pack_lowp(const double *v, int64_t n, uint32_t *out, int prec, hipStream_t s);

@@ -490,6 +490,7 @@ int smm_launch(const SmmArgs &a, int variant, hipStream_t s) {
     switch (variant) {
         case kSmmF64M16: return launch_rt(a, SmmParams{0, 1, 0, 0}, s);
         case kSmmF64M4: return launch_rt(a, SmmParams{1, 1, 1, 0}, s);
+        case kSmmF64Quad:   // where the quad kernel does not apply (built by multiply)
         case kSmmF64Fixed: {
             // uniform sizes: the tuning table may choose the family; without
             // an entry the compile-time-shape kernel is used where it exists

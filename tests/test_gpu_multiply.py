@@ -205,7 +205,7 @@ def test_reductions_vs_oracle(orc):
     assert_same_matrix(got, orc.shift_scale(m, 0.7, 0.25), 1e-15, "shift_scale")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 6])
 @pytest.mark.parametrize("maxb", [5, 13, 23, 26, 32])
 def test_multiply_kernel_variants(orc, monkeypatch, variant, maxb):
     """All FP64 block-product kernels (16x16 tiles, 4x4 tiles, fixed shapes)
@@ -224,6 +224,39 @@ def test_multiply_kernel_variants(orc, monkeypatch, variant, maxb):
         ref = orc.multiply(-0.5, a, b, 1.5, c)
         got, _ = _run(-0.5, a, b, 1.5, c)
         assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"variant {variant} maxb {maxb}")
+
+
+@pytest.mark.parametrize("waves", ["1", "2"])
+@pytest.mark.parametrize("b", [5, 13, 23])
+def test_quad_kernel_vs_oracle_and_fixed(orc, monkeypatch, waves, b):
+    """The quad kernel (one or two waves per 2 x 2 group of C blocks, merged
+    product lists) against the oracle -- odd block-row and column counts give
+    partial quads, C_in adds blocks without products, a tiny chunk size and
+    an odd band height give many chunks -- and bit for bit against the
+    one-C-block-per-wave compile-time-shape kernel, which sums the same
+    products in the same order with the same instructions."""
+    monkeypatch.setenv("BSM_QUAD_WAVES", waves)
+    rng = np.random.default_rng(500 + b)
+    nbr, nbk, nbc = 11, 9, 13
+    a = synth.random_bsr(nbr, nbk, np.full(nbr, b), np.full(nbk, b), 0.45, rng)
+    bm = synth.random_bsr(nbk, nbc, np.full(nbk, b), np.full(nbc, b), 0.45, rng)
+    c = synth.random_bsr(nbr, nbc, np.full(nbr, b), np.full(nbc, b), 0.3, rng)
+    for alpha, beta, cc in [(1.0, 0.0, None), (-0.5, 1.5, c)]:
+        ref = orc.multiply(alpha, a, bm, beta, cc)
+        monkeypatch.setenv("BSM_SMM_VARIANT", "6")
+        got, st = _run(alpha, a, bm, beta, cc)
+        assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"quad b={b} beta={beta}")
+        monkeypatch.setenv("BSM_SMM_VARIANT", "2")
+        fixed, _ = _run(alpha, a, bm, beta, cc)
+        assert np.array_equal(got.values, fixed.values), "quad and fixed kernels differ"
+        monkeypatch.setenv("BSM_SMM_VARIANT", "6")
+        monkeypatch.setenv("BSM_CHUNK_PRODUCTS", "50")
+        monkeypatch.setenv("BSM_TILE_ROWS", "3")
+        chunked, st2 = _run(alpha, a, bm, beta, cc)
+        assert st2.smm_launches > 1
+        assert np.array_equal(chunked.values, got.values), "chunking changed the quad result"
+        monkeypatch.delenv("BSM_CHUNK_PRODUCTS")
+        monkeypatch.delenv("BSM_TILE_ROWS")
 
 
 @pytest.mark.parametrize("variant", [1, 2, 3, 4])

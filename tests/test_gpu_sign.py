@@ -102,3 +102,53 @@ def test_sign_mixed_block_sizes_vs_oracle(orc):
     assert stats.iterations == st_ref["iterations"]
     assert_same_matrix(from_dev(x), x_ref, TOL_FP64, "mixed sign")
     assert stats.trace_p == pytest.approx(h.meta["n_occ"], abs=1e-4)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_add_vs_oracle(orc, seed):
+    """bsm_add (C = alpha A + beta B + gamma I, filtered) against the oracle."""
+    from paper_2003_03868_amd import bsm
+    rng = np.random.default_rng(900 + seed)
+    nb = int(rng.integers(1, 12))
+    sizes = rng.integers(1, 24, nb)
+    a = synth.random_bsr(nb, nb, sizes, sizes, float(rng.choice([0.0, 0.3, 0.8])), rng)
+    b = synth.random_bsr(nb, nb, sizes, sizes, float(rng.choice([0.0, 0.3, 0.8])), rng)
+    da, db = to_dev(a), to_dev(b)
+    alpha, beta = float(rng.normal()), float(rng.normal())
+    for gamma in (0.0, 378.0):
+        for norm, eps in (("frob", 0.0), ("frob", 0.8), ("maxabs", 0.3)):
+            ref = orc.add(alpha, a, beta, b, gamma, eps=eps, norm=norm)
+            h = bsm.bsm_add(alpha, da.handle, beta, db.handle, gamma, eps,
+                            bsm.NORM_FROB if norm == "frob" else bsm.NORM_MAXABS)
+            got = from_dev(bsm.Matrix(h, sizes, sizes))
+            assert_same_matrix(got, ref, 1e-14, f"add gamma={gamma} {norm} {eps}")
+    h = bsm.bsm_add(-420.0, da.handle, 0.0, None, 315.0)
+    assert_same_matrix(from_dev(bsm.Matrix(h, sizes, sizes)), orc.add(-420.0, a, gamma=315.0),
+                       1e-14, "add without B")
+
+
+@pytest.mark.parametrize("order", [3, 5])
+@pytest.mark.parametrize("c", [dict(n=64, b=5, rc=4.0, eps=0.0, seed=3),
+                               dict(n=200, b=5, rc=6.0, eps=1e-6, seed=5),
+                               dict(n=100, b=23, rc=4.2, eps=1e-6, seed=6)],
+                         ids=lambda c: f"n{c['n']}b{c['b']}e{c['eps']:g}")
+def test_sign_higher_orders_vs_oracle(orc, order, c):
+    """Third- and fifth-order iterations (Eq. fifth_order_sign: four
+    multiplies per iteration) against the oracle's same iterations."""
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(c["n"], c["b"], cutoff=c["rc"], seed=c["seed"])
+    x_ref, st_ref, s_ref = orc.sign_ns(h, eps=c["eps"], tol=1e-8, order=order)
+    d = to_dev(h)
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol, o.order = c["eps"], 1e-8, order
+    st, xh, stats = bsm.bsm_sign_iterate(d.handle, 0.0, o)
+    assert st == bsm.OK and s_ref == orc.OK, bsm.bsm_last_error()
+    assert stats.iterations == st_ref["iterations"]
+    assert stats.n_multiplies == st_ref["n_multiplies"]
+    assert np.allclose(list(stats.r_hist)[:stats.iterations + 1], st_ref["r_hist"], rtol=1e-6,
+                       atol=1e-15)
+    x = bsm.Matrix(xh, h.row_blk_size, h.col_blk_size)
+    err = assert_same_matrix(from_dev(x), x_ref, TOL_FP64, f"order {order}")
+    assert stats.trace_p == pytest.approx(h.meta["n_occ"], abs=1e-4)
+    print(f"order {order} n={c['n']} b={c['b']}: iters {stats.iterations}, "
+          f"multiplies {stats.n_multiplies}, err {err:.2e}")
