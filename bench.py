@@ -61,15 +61,28 @@ def cpu_baseline(h, rows: int):
                        f"the iteration), eps 1e-6, {flops / 1e9:.1f} GFLOP in {dt:.1f} s")
 
 
-def measured_traffic(kernel_src: str, workload: str):
-    """HBM bytes per launch of the block-product kernel from the committed
-    rocprofv3 counter summary, or None when the kernel source has changed
-    since the counters were taken (or none were taken for this workload)."""
+KERNEL_SOURCES = ["smm.h", "smm_quad.hip", "quad.hip"]
+
+
+def sources_sha256() -> str:
+    """Hash of the sources that decide the default FP64 block-product
+    kernel's memory traffic (the kernel and the order of its work)."""
     import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2003_03868_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the block-product kernel from the committed
+    rocprofv3 counter summary, or None when the kernel sources have changed
+    since the counters were taken (or none were taken for this workload)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     try:
         d = json.load(open(path))
-        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+        sha = sources_sha256()
     except (OSError, ValueError):
         return None
     return d["hbm_bytes_per_launch"] if d.get("source_sha256") == sha else None
@@ -94,6 +107,8 @@ def main():
     ap.add_argument("--table", choices=["exhaustive", "mlp", "none"], default="exhaustive",
                     help="kernel-parameter table: measured (exhaustive autotuning), predicted "
                          "by the MLP, or none (built-in choices)")
+    ap.add_argument("--order", type=int, choices=[2, 3, 5], default=2,
+                    help="sign iteration order: 2 Newton-Schulz, 3, 5 (four multiplies per iteration)")
     ap.add_argument("--graph", type=int, choices=[0, 1], default=0,
                     help="1: replay captured hipGraphs once X's block pattern stops changing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -144,6 +159,7 @@ def main():
     opts.tol = args.tol
     opts.prec = {"fp64": bsm.FP64, "fp32": bsm.FP32, "bf16": bsm.SPLIT_BF16}[args.prec]
     opts.use_graph = args.graph
+    opts.order = args.order
     stream = torch.cuda.current_stream()
 
     def step():
@@ -202,7 +218,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": (f"{args.prec.upper()} Newton-Schulz sign iteration, {h.nbrows}-site "
+            "workload": (f"{args.prec.upper()} {'Newton-Schulz' if args.order == 2 else f'order-{args.order}'} sign iteration, {h.nbrows}-site "
                          "neighbour-list Hamiltonian, "
                          + ("23x23 blocks" if args.workload == "sign23"
                             else "block sizes {5,13,23,26}") +
@@ -211,7 +227,7 @@ def main():
             "n_sites": h.nbrows, "block": 23 if args.workload == "sign23" else "5/13/23/26",
             "n": int(n), "eps_filter": args.eps, "kernel_table": args.table,
             "tol": args.tol, "seed": args.seed, "nnzb_H": h.nnzb,
-            "graph_replay": bool(args.graph),
+            "graph_replay": bool(args.graph), "order": args.order,
         },
         "time_to_sign_ms": ms_per_step,
         "iterations": int(s0.iterations),
@@ -226,17 +242,17 @@ def main():
         "graph_fallbacks": int(s0.graph_fallbacks),
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_smm_f64_fixed<23,23,23>" if args.prec == "fp64" else "k_smm_lowp",
+            "kernel": ("k_smm_f64_quad<23,2,3>" if args.workload == "sign23" else "k_smm_f64_class")
+            if args.prec == "fp64" else "k_smm_lowp",
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": measured_traffic(
-                os.path.join(ROOT, "paper_2003_03868_amd", "csrc", "smm.hip"), "sign23")
+            "traffic": measured_traffic("sign23")
             if (args.prec == "fp64" and args.workload == "sign23" and args.sites == 2048
-                and args.eps == 1e-6) else None,
+                and args.eps == 1e-6 and args.table == "exhaustive") else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, "
-                            "profiles/k_smm_f64_fixed_sign23.md)",
+                            "profiles/k_smm_f64_quad_sign23.md)",
             "smm_ms_per_step": smm_ms / args.steps,
         },
         "cpu_baseline": cpu,

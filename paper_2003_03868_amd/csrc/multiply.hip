@@ -39,6 +39,13 @@ static int smm_variant() {
     return e ? atoi(e) : kSmmF64Quad;
 }
 
+// Work order of the quads: bands of QR row pairs by QC column pairs
+// (BSM_QUAD_TILE_ROWS / BSM_QUAD_TILE_COLS; rows 0 keeps row-pair order).
+static int quad_tile(const char *name, int dflt) {
+    const char *e = getenv(name);
+    return e ? atoi(e) : dflt;
+}
+
 // Kernel family for a chunk with mixed block sizes (uniform sizes keep the
 // requested variant).  Default: per-class launches when every size is in
 // {5, 13, 23, 26}, else the fused persistent kernel.
@@ -298,7 +305,8 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             Scratch ctmp(s);
             auto qbuf = [&](auto **ptr, size_t n) -> int { return pl ? keep_buf(ptr, n) : ctmp.get(ptr, n); };
             const int64_t npairs = (static_cast<int64_t>(r1 - r0) + 1) / 2;
-            int64_t *q_off = nullptr, *q_cblk = nullptr, *e_off = nullptr;
+            int64_t *q_off = nullptr, *q_cblk = nullptr, *e_off = nullptr, *q_order = nullptr;
+            int32_t *q_col = nullptr;
             int4 *ent = nullptr;
             int64_t nq = 0, ne = 0;
             auto read_total = [&](const int64_t *d, int64_t *h) -> int {
@@ -307,21 +315,30 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
                 if (e != hipSuccess) { set_error("quads: %s", hipGetErrorString(e)); return BSM_EDEVICE; }
                 return BSM_OK;
             };
-            st = qbuf(&q_off, npairs + 1);
-            if (st == BSM_OK) st = quad_rows(c_row_ptr, nc.col_idx, r0, r1, q_off, nullptr, nullptr, s);
-            if (st == BSM_OK) st = scan_i64(q_off, q_off, npairs, s);
-            if (st == BSM_OK) st = read_total(q_off + npairs, &nq);
-            if (st == BSM_OK) st = qbuf(&q_cblk, 4 * nq);
-            if (st == BSM_OK) st = quad_rows(c_row_ptr, nc.col_idx, r0, r1, nullptr, q_off, q_cblk, s);
             QuadSymArgs qa{};
             qa.r0 = r0; qa.r1 = r1; qa.nbcols = B.nbcols;
             qa.a_row_ptr = A.row_ptr; qa.a_col_idx = A.col_idx;
             qa.b_row_ptr = B.row_ptr; qa.b_col_idx = B.col_idx;
             qa.c_row_ptr = c_row_ptr; qa.c_col_idx = nc.col_idx;
-            qa.q_off = q_off;
+            st = qbuf(&q_off, npairs + 1);
+            if (st == BSM_OK) st = quad_pairs(qa, q_off, s);
+            if (st == BSM_OK) st = scan_i64(q_off, q_off, npairs, s);
+            if (st == BSM_OK) st = read_total(q_off + npairs, &nq);
+            if (st == BSM_OK) st = qbuf(&q_cblk, 4 * nq);
             if (st == BSM_OK) st = qbuf(&e_off, nq + 1);
+            if (st == BSM_OK) st = qbuf(&q_col, nq);
+            qa.q_off = q_off;
+            qa.q_cblk = q_cblk;
+            qa.q_col = q_col;
             qa.e_off = e_off;
             if (st == BSM_OK) st = quad_stack(qa, false, s);
+            const int qr = quad_tile("BSM_QUAD_TILE_ROWS", 0), qc = quad_tile("BSM_QUAD_TILE_COLS", 16);
+            if (st == BSM_OK && qr > 0 && nq > 0) {
+                st = qbuf(&q_order, nq);
+                if (st == BSM_OK)
+                    st = tile_order(q_off, q_col, static_cast<int32_t>(npairs), (B.nbcols + 1) / 2,
+                                    qr, q_order, s, qc);
+            }
             if (st == BSM_OK) st = scan_i64(e_off, e_off, nq, s);
             if (st == BSM_OK) st = read_total(e_off + nq, &ne);
             if (st == BSM_OK) st = qbuf(&ent, ne);
@@ -335,6 +352,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             op.a.q_cblk = q_cblk;
             op.a.q_seg = e_off;
             op.a.q_ent = ent;
+            op.a.q_order = q_order;
             std::pair<hipEvent_t, hipEvent_t> pe{};
             if (ev.on) {
                 BSM_HIP(hipEventCreate(&pe.first));

@@ -25,36 +25,6 @@ __device__ inline int32_t bit_rank_q(const uint32_t *bits, const int32_t *wpre, 
     return wpre[Q >> 5] + __popc(below);
 }
 
-// One thread per row pair: merge the column lists of rows 2R and 2R + 1 by
-// column pair.  Count pass (q_off == NULL) or fill pass.
-__global__ void __launch_bounds__(kQuadThreads)
-k_quad_rows(const int64_t *c_row_ptr, const int32_t *c_col_idx, int32_t r0, int32_t r1,
-            int64_t *cnt, const int64_t *q_off, int64_t *q_cblk) {
-    const int64_t R = static_cast<int64_t>(blockIdx.x) * kQuadThreads + threadIdx.x;
-    const int64_t npairs = (static_cast<int64_t>(r1 - r0) + 1) / 2;
-    if (R >= npairs) return;
-    const int32_t i0 = r0 + 2 * static_cast<int32_t>(R), i1 = i0 + 1;
-    int64_t p = c_row_ptr[i0], pe = c_row_ptr[i0 + 1];
-    int64_t q = 0, qe = 0;
-    if (i1 < r1) { q = c_row_ptr[i1]; qe = c_row_ptr[i1 + 1]; }
-    int64_t n = 0;
-    const int64_t w = q_off ? q_off[R] : 0;
-    while (p < pe || q < qe) {
-        const int32_t cp = p < pe ? (c_col_idx[p] >> 1) : INT_MAX;
-        const int32_t cq = q < qe ? (c_col_idx[q] >> 1) : INT_MAX;
-        const int32_t Q = cp < cq ? cp : cq;
-        int64_t ids[4] = {-1, -1, -1, -1};
-        while (p < pe && (c_col_idx[p] >> 1) == Q) { ids[c_col_idx[p] & 1] = p; ++p; }
-        while (q < qe && (c_col_idx[q] >> 1) == Q) { ids[2 + (c_col_idx[q] & 1)] = q; ++q; }
-        if (q_off) {
-#pragma unroll
-            for (int z = 0; z < 4; ++z) q_cblk[4 * (w + n) + z] = ids[z];
-        }
-        ++n;
-    }
-    if (!q_off) cnt[R] = n;
-}
-
 // ---------------------------------------------------------------------------
 // Entry lists straight from the patterns of A and B: one workgroup per row
 // pair walks k over the merged column lists of A's rows 2R and 2R + 1
@@ -88,6 +58,48 @@ __device__ inline int64_t qwg_exscan(int64_t v, int64_t *scratch, int64_t *total
     return before + x - v;
 }
 
+// Bitmap of the column pairs Q holding C blocks of rows i0 (and i1) and the
+// exclusive popcount prefix per word; returns the number of quads.
+__device__ inline int64_t quad_rank_map(const QuadSymArgs &q, int32_t i0, bool two, int nwq,
+                                        uint32_t *bits, int32_t *wpre, int64_t *scratch) {
+    for (int w = threadIdx.x; w < nwq; w += kQuadThreads) bits[w] = 0u;
+    __syncthreads();
+    for (int r = 0; r < (two ? 2 : 1); ++r)
+        for (int64_t t = q.c_row_ptr[i0 + r] + threadIdx.x; t < q.c_row_ptr[i0 + r + 1];
+             t += kQuadThreads) {
+            const int32_t Q = q.c_col_idx[t] >> 1;
+            atomicOr(&bits[Q >> 5], 1u << (Q & 31));
+        }
+    __syncthreads();
+    const int per = (nwq + kQuadThreads - 1) / kQuadThreads;
+    const int w0 = threadIdx.x * per;
+    int64_t local = 0;
+    for (int w = w0; w < w0 + per && w < nwq; ++w) local += __popc(bits[w]);
+    int64_t total;
+    int64_t run = qwg_exscan(local, scratch, &total);
+    for (int w = w0; w < w0 + per && w < nwq; ++w) {
+        wpre[w] = static_cast<int32_t>(run);
+        run += __popc(bits[w]);
+    }
+    __syncthreads();
+    return total;
+}
+
+// Quads per row pair (one workgroup per pair).
+__global__ void __launch_bounds__(kQuadThreads)
+k_quad_pairs(QuadSymArgs q, int64_t *cnt) {
+    extern __shared__ uint32_t smem[];
+    __shared__ int64_t scratch[kQuadThreads / kWave];
+    const int nwq = (((q.nbcols + 1) >> 1) + 31) >> 5;
+    const int32_t R = blockIdx.x;
+    const int32_t i0 = q.r0 + 2 * R;
+    const int64_t nq = quad_rank_map(q, i0, i0 + 1 < q.r1, nwq, smem,
+                                     reinterpret_cast<int32_t *>(smem + nwq), scratch);
+    if (threadIdx.x == 0) cnt[R] = nq;
+}
+
+// FILL = false: the quads' C blocks (q_cblk) and entry counts (e_off);
+// FILL = true: the entries.
 template <bool FILL>
 __global__ void __launch_bounds__(kQuadThreads)
 k_quad_stack(QuadSymArgs q) {
@@ -102,32 +114,22 @@ k_quad_stack(QuadSymArgs q) {
     const int32_t R = blockIdx.x;
     const int32_t i0 = q.r0 + 2 * R, i1 = i0 + 1;
     const bool two = i1 < q.r1;
-
-    // rank of the quads of this pair by column pair
-    for (int w = threadIdx.x; w < nwq; w += kQuadThreads) bits[w] = 0u;
-    __syncthreads();
-    for (int r = 0; r < (two ? 2 : 1); ++r)
-        for (int64_t t = q.c_row_ptr[i0 + r] + threadIdx.x; t < q.c_row_ptr[i0 + r + 1];
-             t += kQuadThreads) {
-            const int32_t Q = q.c_col_idx[t] >> 1;
-            atomicOr(&bits[Q >> 5], 1u << (Q & 31));
-        }
-    __syncthreads();
-    {
-        const int per = (nwq + kQuadThreads - 1) / kQuadThreads;
-        const int w0 = threadIdx.x * per;
-        int64_t local = 0;
-        for (int w = w0; w < w0 + per && w < nwq; ++w) local += __popc(bits[w]);
-        int64_t total;
-        int64_t run = qwg_exscan(local, scratch, &total);
-        for (int w = w0; w < w0 + per && w < nwq; ++w) {
-            wpre[w] = static_cast<int32_t>(run);
-            run += __popc(bits[w]);
-        }
-    }
-    __syncthreads();
+    quad_rank_map(q, i0, two, nwq, bits, wpre, scratch);
 
     const int64_t qbase = q.q_off[R], nq = q.q_off[R + 1] - qbase;
+    if (!FILL) {
+        // C blocks of every quad: (r, c) at 4 quad + 2 r + c, -1 where absent
+        for (int64_t t = threadIdx.x; t < 4 * nq; t += kQuadThreads) q.q_cblk[4 * qbase + t] = -1;
+        __syncthreads();
+        for (int r = 0; r < (two ? 2 : 1); ++r)
+            for (int64_t t = q.c_row_ptr[i0 + r] + threadIdx.x; t < q.c_row_ptr[i0 + r + 1];
+                 t += kQuadThreads) {
+                const int32_t j = q.c_col_idx[t];
+                const int64_t rank = bit_rank_q(bits, wpre, j >> 1);
+                q.q_cblk[4 * (qbase + rank) + 2 * r + (j & 1)] = t;
+                q.q_col[qbase + rank] = j >> 1;    // same value from every block of the quad
+            }
+    }
     const int64_t ea = q.a_row_ptr[i0 + 1], eb = two ? q.a_row_ptr[i1 + 1] : 0;
     for (int64_t w0 = 0; w0 < nq; w0 += kQuadWindow) {
         const int wn = static_cast<int>(nq - w0 < kQuadWindow ? nq - w0 : kQuadWindow);
@@ -178,6 +180,15 @@ k_quad_stack(QuadSymArgs q) {
     }
 }
 
+int quad_pairs(const QuadSymArgs &q, int64_t *cnt, hipStream_t s) {
+    const int64_t npairs = (static_cast<int64_t>(q.r1 - q.r0) + 1) / 2;
+    if (npairs <= 0) return BSM_OK;
+    const int nwq = (((q.nbcols + 1) >> 1) + 31) >> 5;
+    k_quad_pairs<<<static_cast<unsigned>(npairs), kQuadThreads, sizeof(uint32_t) * 2 * nwq, s>>>(q, cnt);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
 int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s) {
     const int64_t npairs = (static_cast<int64_t>(q.r1 - q.r0) + 1) / 2;
     if (npairs <= 0) return BSM_OK;
@@ -185,16 +196,6 @@ int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s) {
     const size_t lds = sizeof(uint32_t) * 2 * nwq + sizeof(int32_t) * kQuadWindow;
     if (fill) k_quad_stack<true><<<static_cast<unsigned>(npairs), kQuadThreads, lds, s>>>(q);
     else k_quad_stack<false><<<static_cast<unsigned>(npairs), kQuadThreads, lds, s>>>(q);
-    BSM_HIP(hipGetLastError());
-    return BSM_OK;
-}
-
-int quad_rows(const int64_t *c_row_ptr, const int32_t *c_col_idx, int32_t r0, int32_t r1,
-              int64_t *cnt, const int64_t *q_off, int64_t *q_cblk, hipStream_t s) {
-    const int64_t npairs = (static_cast<int64_t>(r1 - r0) + 1) / 2;
-    if (npairs <= 0) return BSM_OK;
-    k_quad_rows<<<grid_for(npairs, kQuadThreads), kQuadThreads, 0, s>>>(c_row_ptr, c_col_idx, r0,
-                                                                        r1, cnt, q_off, q_cblk);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }

@@ -68,6 +68,7 @@ struct SmmArgs {
     const int64_t *q_cblk;      // [4 n_quads] C block (r, c) of the quad at 2r + c, or -1
     const int64_t *q_seg;       // [n_quads + 1] entry segments
     const int4 *q_ent;          // A(row 0), A(row 1), B(col 0), B(col 1) block indices or -1
+    const int64_t *q_order;     // quad of work item i (NULL: identity)
 };
 
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s);

@@ -45,23 +45,23 @@ __device__ inline double q_wave_max(double v) {
     return v;
 }
 
-// One entry's products for the rows [R0, R0 + NR) of the quad.  ALL: every
-// operand present (no tests); otherwise the wave-uniform flags select the
-// rows, columns and products.
-template <int S, int NR, bool ALL>
-__device__ inline void quad_step(const double *sm, int R0, int ra0, int rb0, bool klast_ok,
-                                 const bool (&h)[4],
-                                 double (&acc)[2 * NR][QShape<S>::H][QShape<S>::H]) {
+// One entry's products for rows [R0, R0 + NR) and columns [C0, C0 + NC)
+// of the quad.  ALL: every operand present (no tests); otherwise the
+// wave-uniform flags hm (bit z: operand z present) select the products.
+template <int S, int NR, int NC, bool ALL>
+__device__ inline void quad_step(const double *sm, int R0, int C0, int ra0, int rb0,
+                                 bool klast_ok, unsigned hm,
+                                 double (&acc)[NR * NC][QShape<S>::H][QShape<S>::H]) {
     using Q = QShape<S>;
     constexpr int H = Q::H;
-    bool ha[NR], hb[2];
+    bool ha[NR], hb[NC];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) ha[r] = ALL || h[R0 + r];
-    hb[0] = ALL || h[2];
-    hb[1] = ALL || h[3];
+    for (int r = 0; r < NR; ++r) ha[r] = ALL || ((hm >> (R0 + r)) & 1u);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) hb[c] = ALL || ((hm >> (2 + C0 + c)) & 1u);
 #pragma unroll
     for (int ks = 0; ks < Q::KS; ++ks) {
-        double av[NR][H], bv[2][H];
+        double av[NR][H], bv[NC][H];
 #pragma unroll
         for (int r = 0; r < NR; ++r)
             if (ha[r]) {
@@ -70,11 +70,11 @@ __device__ inline void quad_step(const double *sm, int R0, int ra0, int rb0, boo
                     av[r][t] = sm[(R0 + r) * Q::B2 + ra0 + 4 * t * S + 4 * ks];
             }
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < NC; ++c)
             if (hb[c]) {
 #pragma unroll
                 for (int u = 0; u < H; ++u)
-                    bv[c][u] = sm[(2 + c) * Q::B2 + rb0 + 4 * u + 4 * ks * S];
+                    bv[c][u] = sm[(2 + C0 + c) * Q::B2 + rb0 + 4 * u + 4 * ks * S];
             }
         if (ks == Q::KS - 1 && Q::KLAST < 4) {
 #pragma unroll
@@ -82,26 +82,27 @@ __device__ inline void quad_step(const double *sm, int R0, int ra0, int rb0, boo
 #pragma unroll
                 for (int r = 0; r < NR; ++r) av[r][t] = klast_ok ? av[r][t] : 0.0;
 #pragma unroll
-                for (int c = 0; c < 2; ++c) bv[c][t] = klast_ok ? bv[c][t] : 0.0;
+                for (int c = 0; c < NC; ++c) bv[c][t] = klast_ok ? bv[c][t] : 0.0;
             }
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r)
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
+            for (int c = 0; c < NC; ++c)
                 if (ha[r] && hb[c]) {
 #pragma unroll
                     for (int t = 0; t < H; ++t)
 #pragma unroll
                         for (int u = 0; u < H; ++u)
-                            acc[2 * r + c][t][u] = __builtin_amdgcn_mfma_f64_4x4x4f64(
-                                av[r][t], bv[c][u], acc[2 * r + c][t][u], 0, 0, 0);
+                            acc[NC * r + c][t][u] = __builtin_amdgcn_mfma_f64_4x4x4f64(
+                                av[r][t], bv[c][u], acc[NC * r + c][t][u], 0, 0, 0);
                 }
     }
 }
 
 // W wavefronts per quad: W = 1, the wave computes all four C blocks; W = 2,
-// wave w computes the two C blocks of row w and stages A(i_w, k), B(k, j_w).
+// wave w computes the two C blocks of row w and stages A(i_w, k), B(k, j_w);
+// W = 4, wave w computes C block (w / 2, w % 2) and stages operand w.
 // WPE: the occupancy (waves per SIMD) the register allocation aims for.
 template <int S, int W, int WPE>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
@@ -109,73 +110,103 @@ k_smm_f64_quad(SmmArgs a) {
     using Q = QShape<S>;
     constexpr int H = Q::H;
     constexpr int NR = (W == 1) ? 2 : 1;        // quad rows per wave
-    constexpr int NZ = (W == 1) ? 4 : 2;        // operand blocks staged per wave
+    constexpr int NC = (W == 4) ? 1 : 2;        // quad columns per wave
+    constexpr int NZ = 4 / W;                   // operand blocks staged per wave
     __shared__ double sm[Q::SIZE];
-    const int64_t item = quad_item(a.n_quads);
-    if (item >= a.n_quads) return;
+    const int64_t it = quad_item(a.n_quads);
+    if (it >= a.n_quads) return;
+    const int64_t item = a.q_order ? a.q_order[it] : it;
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
-    const int R0 = (W == 1) ? 0 : wv;
+    const int R0 = (W == 1) ? 0 : (W == 2 ? wv : wv >> 1);
+    const int C0 = (W == 4) ? (wv & 1) : 0;
     const int x = lane >> 4, blk = (lane >> 2) & 3, y = lane & 3;
     const int bh = blk >> 1, bw = blk & 1;
     // staged block zz of this wave is quad operand zid(zz): A rows 0, 1 then B columns 0, 1
-    auto zid = [&](int zz) { return (W == 1) ? zz : (zz == 0 ? wv : 2 + wv); };
+    auto zid = [&](int zz) { return (W == 1) ? zz : (W == 4 ? wv : (zz == 0 ? wv : 2 + wv)); };
+    auto pick = [](const int4 v, int z) { return z == 0 ? v.x : z == 1 ? v.y : z == 2 ? v.z : v.w; };
 
     for (int e = 4 * Q::B2 + static_cast<int>(threadIdx.x); e < Q::SIZE; e += 64 * W) sm[e] = 0.0;
     const int ra0 = (4 * bh * H + y) * S + x;      // A(4 (bh H + t) + y, 4 ks + x)
     const int rb0 = x * S + 4 * bw * H + y;        // B(4 ks + x, 4 (bw H + u) + y)
     const bool klast_ok = x < Q::KLAST;
 
-    double acc[2 * NR][H][H];
+    double acc[NR * NC][H][H];
 #pragma unroll
-    for (int z = 0; z < 2 * NR; ++z)
+    for (int z = 0; z < NR * NC; ++z)
 #pragma unroll
         for (int t = 0; t < H; ++t)
 #pragma unroll
             for (int u = 0; u < H; ++u) acc[z][t][u] = 0.0;
 
-    const int64_t e0 = a.q_seg[item], e1 = a.q_seg[item + 1];
+    // Pipeline: while entry e is multiplied, the operand blocks of e + 1 are
+    // in flight to registers.  The entry indices come from LDS, where wave 0
+    // stores them in chunks of kEntryChunk (double-buffered; the next chunk
+    // waits in registers), so no global load waits on another global load
+    // issued in the same iteration.
+    constexpr int kEntryChunk = 64;
+    __shared__ int4 ebuf[2][kEntryChunk];
+    const int64_t e0 = a.q_seg[item], ne = a.q_seg[item + 1] - e0;
     double pv[NZ][Q::NV];
-    int4 nxt = make_int4(-1, -1, -1, -1);
-    auto prefetch = [&](int64_t e) {
-        nxt = a.q_ent[e];
-        const int id[4] = {nxt.x, nxt.y, nxt.z, nxt.w};
+    auto load_blocks = [&](const int4 en) {
 #pragma unroll
         for (int zz = 0; zz < NZ; ++zz) {
             const int z = zid(zz);
-            if (id[z] >= 0) {
-                const double *g = (z < 2 ? a.a_vals : a.b_vals) + static_cast<int64_t>(id[z]) * Q::B2;
+            const int id = pick(en, z);
+            if (id >= 0) {
+                const double *g = (z < 2 ? a.a_vals : a.b_vals) + static_cast<int64_t>(id) * Q::B2;
 #pragma unroll
                 for (int q = 0; q < Q::NV; ++q)
                     if (q < Q::NV - 1 || lane + q * kWave < Q::B2) pv[zz][q] = g[lane + q * kWave];
             }
         }
     };
-    if (e0 < e1) prefetch(e0);
-    for (int64_t e = e0; e < e1; ++e) {
+    int4 creg = make_int4(-1, -1, -1, -1);    // wave 0: entry e0 + 64 c + lane of the next chunk
+    if (wv == 0) {
+        if (lane < ne) ebuf[0][lane] = a.q_ent[e0 + lane];
+        if (kEntryChunk + lane < ne) creg = a.q_ent[e0 + kEntryChunk + lane];
+    }
+    __syncthreads();
+    int4 nxt = make_int4(-1, -1, -1, -1);
+    if (ne > 0) {
+        nxt = ebuf[0][0];
+        load_blocks(nxt);
+    }
+    for (int64_t t = 0; t < ne; ++t) {
         const int4 cur = nxt;
-        const bool h[4] = {cur.x >= 0, cur.y >= 0, cur.z >= 0, cur.w >= 0};
+        const unsigned hm = (cur.x >= 0 ? 1u : 0u) | (cur.y >= 0 ? 2u : 0u) |
+                            (cur.z >= 0 ? 4u : 0u) | (cur.w >= 0 ? 8u : 0u);
 #pragma unroll
         for (int zz = 0; zz < NZ; ++zz) {
             const int z = zid(zz);
-            if (h[z]) {
+            if ((hm >> z) & 1u) {
 #pragma unroll
                 for (int q = 0; q < Q::NV; ++q)
                     if (q < Q::NV - 1 || lane + q * kWave < Q::B2)
                         sm[z * Q::B2 + lane + q * kWave] = pv[zz][q];
             }
         }
+        const int64_t t1 = t + 1;
+        if ((t1 % kEntryChunk) == 0 && t1 < ne && wv == 0) {
+            // entering chunk t1 / 64: its indices (loaded a chunk ago) go to
+            // LDS, the chunk after it is fetched into registers
+            ebuf[(t1 / kEntryChunk) & 1][lane] = creg;
+            if (t1 + kEntryChunk + lane < ne) creg = a.q_ent[e0 + t1 + kEntryChunk + lane];
+        }
         __syncthreads();
-        if (e + 1 < e1) prefetch(e + 1);
-        if (h[0] && h[1] && h[2] && h[3])
-            quad_step<S, NR, true>(sm, R0, ra0, rb0, klast_ok, h, acc);
+        if (t1 < ne) {
+            nxt = ebuf[(t1 / kEntryChunk) & 1][t1 % kEntryChunk];
+            load_blocks(nxt);
+        }
+        if (hm == 15u)
+            quad_step<S, NR, NC, true>(sm, R0, C0, ra0, rb0, klast_ok, hm, acc);
         else
-            quad_step<S, NR, false>(sm, R0, ra0, rb0, klast_ok, h, acc);
+            quad_step<S, NR, NC, false>(sm, R0, C0, ra0, rb0, klast_ok, hm, acc);
         __syncthreads();
     }
 
 #pragma unroll
-    for (int zc = 0; zc < 2 * NR; ++zc) {
-        const int64_t c = a.q_cblk[4 * item + 2 * R0 + zc];
+    for (int zc = 0; zc < NR * NC; ++zc) {
+        const int64_t c = a.q_cblk[4 * item + 2 * (R0 + zc / NC) + C0 + zc % NC];
         if (c < 0) continue;
         const int64_t co = a.c_blk_off[c];
         const double *cin = nullptr;
@@ -209,10 +240,11 @@ k_smm_f64_quad(SmmArgs a) {
 
 }  // namespace
 
-// Wavefronts per quad (1 or 2); BSM_QUAD_WAVES overrides the default.
+// Wavefronts per quad (1, 2 or 4); BSM_QUAD_WAVES overrides the default.
 static int quad_waves() {
     const char *e = getenv("BSM_QUAD_WAVES");
-    return (e && atoi(e) == 1) ? 1 : 2;
+    const int w = e ? atoi(e) : 2;
+    return (w == 1 || w == 4) ? w : 2;
 }
 
 bool smm_quad_available(int m, int n, int k) {
@@ -232,11 +264,13 @@ int launch_quad(const SmmArgs &a, hipStream_t s) {
     switch (a.uni_m) {
         case 5: k_smm_f64_quad<5, 1, 8><<<g, 64, 0, s>>>(a); break;
         case 13:
-            if (w == 2) k_smm_f64_quad<13, 2, 4><<<g, 128, 0, s>>>(a);
+            if (w == 4) k_smm_f64_quad<13, 4, 6><<<g, 256, 0, s>>>(a);
+            else if (w == 2) k_smm_f64_quad<13, 2, 4><<<g, 128, 0, s>>>(a);
             else k_smm_f64_quad<13, 1, 4><<<g, 64, 0, s>>>(a);
             break;
         case 23:
-            if (w == 2) k_smm_f64_quad<23, 2, 3><<<g, 128, 0, s>>>(a);
+            if (w == 4) k_smm_f64_quad<23, 4, 5><<<g, 256, 0, s>>>(a);
+            else if (w == 2) k_smm_f64_quad<23, 2, 3><<<g, 128, 0, s>>>(a);
             else k_smm_f64_quad<23, 1, 1><<<g, 64, 0, s>>>(a);
             break;
         default: set_error("no quad kernel for block size %d", a.uni_m); return BSM_EINVAL;

@@ -26,8 +26,9 @@ struct SymArgs {
 
 // Tiled order of the C blocks (bands of `rb` block rows, column bands of
 // tile_cols() columns); writes worklist[c] for every C block.
+// wb < 1: tile_cols() block columns per column band.
 int tile_order(const int64_t *c_row_ptr, const int32_t *c_col_idx, int32_t nbrows,
-               int32_t nbcols, int rb, int64_t *worklist, hipStream_t s);
+               int32_t nbcols, int rb, int64_t *worklist, hipStream_t s, int wb = 0);
 // Tile shape (BSM_TILE_ROWS / BSM_TILE_COLS override the defaults 16 / 32;
 // BSM_TILE_ROWS=1 with BSM_TILE_COLS >= nbcols gives plain CSR order).
 int tile_rows();
@@ -40,17 +41,12 @@ int sort_worklist(const int64_t *wl_in, int64_t *wl_out, int64_t c0, int64_t n, 
                   const int32_t *c_row, const int32_t *c_col, const int32_t *rbs,
                   const int32_t *cbs, const int64_t *seg, int64_t *hist_host, hipStream_t s);
 
-// Quads of C blocks (quad.hip): over the row pairs of block rows [r0, r1)
-// (r0 even), count pass (q_off NULL: cnt[pair] = quads) or fill pass
-// (q_cblk[4 q + 2 r + c] = C block (2R + r, 2Q + c) or -1).
-int quad_rows(const int64_t *c_row_ptr, const int32_t *c_col_idx, int32_t r0, int32_t r1,
-              int64_t *cnt, const int64_t *q_off, int64_t *q_cblk, hipStream_t s);
-
-// Merged entry lists of the quads of block rows [r0, r1) (r0 even) straight
-// from the patterns of A and B (quad.hip).  q_off: first quad of every row
-// pair (scanned quad_rows counts, npairs + 1 entries).  Count pass (fill =
-// false): e_off[quad] = entries; fill pass: ent[e_off[quad] + n] in
-// ascending k.
+// Quads of C blocks and their merged entry lists, straight from the
+// patterns of A, B and the unfiltered C (quad.hip), over the row pairs of
+// block rows [r0, r1) (r0 even).  quad_pairs: cnt[pair] = quads of the pair.
+// quad_stack count pass (fill = false), with q_off = scanned quad counts:
+// q_cblk[4 q + 2 r + c] = C block (2R + r, 2Q + c) or -1, q_col[q] = Q and
+// e_off[q] = entries of quad q; fill pass: ent[e_off[q] + n] in ascending k.
 struct QuadSymArgs {
     int32_t r0, r1, nbcols;
     const int64_t *a_row_ptr;
@@ -60,9 +56,12 @@ struct QuadSymArgs {
     const int64_t *c_row_ptr;    // unfiltered C pattern
     const int32_t *c_col_idx;
     const int64_t *q_off;
+    int64_t *q_cblk;
+    int32_t *q_col;              // column pair Q of every quad (count pass)
     int64_t *e_off;
     int4 *ent;
 };
+int quad_pairs(const QuadSymArgs &q, int64_t *cnt, hipStream_t s);
 int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s);
 
 int sym_count(const SymArgs &a, int64_t *c_cnt, int64_t *c_nval, int64_t *p_cnt, double *flops,

@@ -310,10 +310,10 @@ k_tile_order(const int64_t *c_row_ptr, const int32_t *c_col_idx, int32_t nbrows,
 }
 
 int tile_order(const int64_t *c_row_ptr, const int32_t *c_col_idx, int32_t nbrows,
-               int32_t nbcols, int rb, int64_t *worklist, hipStream_t s) {
+               int32_t nbcols, int rb, int64_t *worklist, hipStream_t s, int wb) {
     if (nbrows == 0) return BSM_OK;
     if (rb < 1 || rb > kOrderMaxRows) { set_error("tile rows must be in [1, %d]", kOrderMaxRows); return BSM_EINVAL; }
-    int wb = tile_cols();
+    if (wb < 1) wb = tile_cols();
     if ((nbcols + wb - 1) / wb > kOrderMaxBands) wb = (nbcols + kOrderMaxBands - 1) / kOrderMaxBands;
     const int nbands = (nbcols + wb - 1) / wb;
     const int nb = (nbrows + rb - 1) / rb;

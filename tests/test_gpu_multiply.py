@@ -226,7 +226,7 @@ def test_multiply_kernel_variants(orc, monkeypatch, variant, maxb):
         assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"variant {variant} maxb {maxb}")
 
 
-@pytest.mark.parametrize("waves", ["1", "2"])
+@pytest.mark.parametrize("waves", ["1", "2", "4"])
 @pytest.mark.parametrize("b", [5, 13, 23])
 def test_quad_kernel_vs_oracle_and_fixed(orc, monkeypatch, waves, b):
     """The quad kernel (one or two waves per 2 x 2 group of C blocks, merged
