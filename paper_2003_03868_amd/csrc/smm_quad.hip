@@ -1,18 +1,20 @@
-// FP64 block products for uniform block sizes, one wavefront per quad of C
+// FP64 block products for uniform block sizes, one workgroup per quad of C
 // blocks (2 x 2 group with a merged product list, built in quad.hip).
 //
-// Per entry k the wave stages the (up to) four operand blocks A(i_0, k),
-// A(i_1, k), B(k, j_0), B(k, j_1) in LDS exactly as they sit in HBM, each read
-// from HBM once, and multiplies every product (r, c) the entry holds.  The
-// instruction and lane roles are those of the compile-time-shape kernel
-// (V_MFMA_F64_4X4X4_4B_F64; lane = 16 x + 4 b + y, block b = 2 bh + bw owns
-// the 4 x 4 tiles of row half bh and column half bw), but a lane's A values of
-// row r serve both column blocks and its B values of column c both row
-// blocks, so per k-step a lane reads 4H values from LDS for 4H^2 MFMAs
-// instead of 2H for H^2.  Each C block's sum runs over its own products in
-// ascending k exactly as in the one-block-per-wave kernels.  With two waves
-// per quad each wave computes one row of the quad (two C blocks) and stages
-// two of the four operand blocks.
+// Per entry k the workgroup stages the (up to) four operand blocks
+// A(i_0, k), A(i_1, k), B(k, j_0), B(k, j_1) in LDS exactly as they sit in HBM,
+// each read from HBM once, and multiplies every product (r, c) the entry
+// holds; each C block's sum runs over its own products in ascending k exactly
+// as in the one-block-per-wave kernels, with the same instructions, so the
+// results are the same bits.  Instruction and lane roles are those of the
+// compile-time-shape kernel (V_MFMA_F64_4X4X4_4B_F64; lane = 16 x + 4 b + y,
+// block b = 2 bh + bw owns the 4 x 4 tiles of row half bh and column half
+// bw).  With W waves per quad, a wave computes 4 / W of the C blocks and
+// stages 4 / W of the operand blocks (W = 4: one each, the fastest form on
+// the sign workload; W = 1: one wave reads each A value once for two column
+// blocks and each B value once for two row blocks).  Operands of the next
+// entry are prefetched into registers; entry indices are staged through LDS
+// in chunks, so no load waits on another load of the same iteration.
 #include <cstdlib>
 
 #include "smm.h"
@@ -31,6 +33,13 @@ struct QShape {
     static constexpr int NV = (B2 + kWave - 1) / kWave;
 };
 
+// Entry indices read from LDS are the same in every lane; saying so keeps
+// the operand tests wave-uniform (scalar branches, no exec-mask merges).
+__device__ inline int4 uniform4(int4 v) {
+    return make_int4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
+                     __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
+}
+
 __device__ inline int64_t quad_item(int64_t n_items) {
     const int64_t per = (n_items + kXcds - 1) / kXcds;
     return static_cast<int64_t>(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
@@ -45,51 +54,48 @@ __device__ inline double q_wave_max(double v) {
     return v;
 }
 
-// One entry's products for rows [R0, R0 + NR) and columns [C0, C0 + NC)
-// of the quad.  ALL: every operand present (no tests); otherwise the
-// wave-uniform flags hm (bit z: operand z present) select the products.
-template <int S, int NR, int NC, bool ALL>
+// One entry's products of the wave: product (r, c) (rows [R0, R0 + NR),
+// columns [C0, C0 + NC) of the quad) is done when bit NC r + c of PM is set.
+// PM is a compile-time constant, so the k loop holds no tests; A rows and B
+// columns no product uses are not read.
+template <int S, int NR, int NC, unsigned PM>
 __device__ inline void quad_step(const double *sm, int R0, int C0, int ra0, int rb0,
-                                 bool klast_ok, unsigned hm,
+                                 bool klast_ok,
                                  double (&acc)[NR * NC][QShape<S>::H][QShape<S>::H]) {
     using Q = QShape<S>;
     constexpr int H = Q::H;
-    bool ha[NR], hb[NC];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) ha[r] = ALL || ((hm >> (R0 + r)) & 1u);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) hb[c] = ALL || ((hm >> (2 + C0 + c)) & 1u);
 #pragma unroll
     for (int ks = 0; ks < Q::KS; ++ks) {
         double av[NR][H], bv[NC][H];
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-            if (ha[r]) {
+        for (int r = 0; r < NR; ++r) {
+            constexpr unsigned rowbits = (1u << NC) - 1u;
+            if ((PM >> (NC * r)) & rowbits) {
 #pragma unroll
-                for (int t = 0; t < H; ++t)
-                    av[r][t] = sm[(R0 + r) * Q::B2 + ra0 + 4 * t * S + 4 * ks];
+                for (int t = 0; t < H; ++t) {
+                    const double v = sm[(R0 + r) * Q::B2 + ra0 + 4 * t * S + 4 * ks];
+                    av[r][t] = (ks == Q::KS - 1 && Q::KLAST < 4 && !klast_ok) ? 0.0 : v;
+                }
             }
+        }
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-            if (hb[c]) {
+        for (int c = 0; c < NC; ++c) {
+            unsigned colbits = 0;
 #pragma unroll
-                for (int u = 0; u < H; ++u)
-                    bv[c][u] = sm[(2 + C0 + c) * Q::B2 + rb0 + 4 * u + 4 * ks * S];
-            }
-        if (ks == Q::KS - 1 && Q::KLAST < 4) {
+            for (int r = 0; r < NR; ++r) colbits |= 1u << (NC * r + c);
+            if (PM & colbits) {
 #pragma unroll
-            for (int t = 0; t < H; ++t) {
-#pragma unroll
-                for (int r = 0; r < NR; ++r) av[r][t] = klast_ok ? av[r][t] : 0.0;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) bv[c][t] = klast_ok ? bv[c][t] : 0.0;
+                for (int u = 0; u < H; ++u) {
+                    const double v = sm[(2 + C0 + c) * Q::B2 + rb0 + 4 * u + 4 * ks * S];
+                    bv[c][u] = (ks == Q::KS - 1 && Q::KLAST < 4 && !klast_ok) ? 0.0 : v;
+                }
             }
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r)
 #pragma unroll
             for (int c = 0; c < NC; ++c)
-                if (ha[r] && hb[c]) {
+                if ((PM >> (NC * r + c)) & 1u) {
 #pragma unroll
                     for (int t = 0; t < H; ++t)
 #pragma unroll
@@ -97,6 +103,77 @@ __device__ inline void quad_step(const double *sm, int R0, int C0, int ra0, int 
                             acc[NC * r + c][t][u] = __builtin_amdgcn_mfma_f64_4x4x4f64(
                                 av[r][t], bv[c][u], acc[NC * r + c][t][u], 0, 0, 0);
                 }
+    }
+}
+
+// The wave's products of an entry with operand flags hm (bit z: operand z
+// present): dispatch on the wave's product mask to a compile-time variant.
+template <int S, int NR, int NC>
+__device__ inline void quad_entry(const double *sm, int R0, int C0, int ra0, int rb0,
+                                  bool klast_ok, unsigned hm,
+                                  double (&acc)[NR * NC][QShape<S>::H][QShape<S>::H]) {
+    unsigned pm = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (((hm >> (R0 + r)) & 1u) && ((hm >> (2 + C0 + c)) & 1u)) pm |= 1u << (NC * r + c);
+#define BSM_QS(M) \
+    case M: quad_step<S, NR, NC, (M)>(sm, R0, C0, ra0, rb0, klast_ok, acc); break;
+    if (NR * NC == 1) {
+        if (pm) quad_step<S, NR, NC, 1u>(sm, R0, C0, ra0, rb0, klast_ok, acc);
+    } else if (NR * NC == 2) {
+        switch (pm) { BSM_QS(1u) BSM_QS(2u) BSM_QS(3u) default: break; }
+    } else {
+        switch (pm) {
+            BSM_QS(1u) BSM_QS(2u) BSM_QS(3u) BSM_QS(4u) BSM_QS(5u) BSM_QS(6u) BSM_QS(7u)
+            BSM_QS(8u) BSM_QS(9u) BSM_QS(10u) BSM_QS(11u) BSM_QS(12u) BSM_QS(13u) BSM_QS(14u)
+            BSM_QS(15u)
+            default: break;
+        }
+    }
+#undef BSM_QS
+}
+
+// alpha * sum + beta * C_in for the wave's C blocks of quad `item`, with the
+// blocks' filter norms.
+template <int S, int NR, int NC>
+__device__ inline void quad_store(const SmmArgs &a, int64_t item, int R0, int C0, int lane,
+                                  const double (&acc)[NR * NC][QShape<S>::H][QShape<S>::H]) {
+    constexpr int H = QShape<S>::H;
+    const int x = lane >> 4, blk = (lane >> 2) & 3, y = lane & 3;
+    const int bh = blk >> 1, bw = blk & 1;
+#pragma unroll
+    for (int zc = 0; zc < NR * NC; ++zc) {
+        const int64_t c = a.q_cblk[4 * item + 2 * (R0 + zc / NC) + C0 + zc % NC];
+        if (c < 0) continue;
+        const int64_t co = a.c_blk_off[c];
+        const double *cin = nullptr;
+        if (a.cin_map) {
+            const int64_t t = a.cin_map[c];
+            if (t >= 0) cin = a.cin_vals + a.cin_blk_off[t];
+        }
+        double sq = 0.0, mx = 0.0;
+#pragma unroll
+        for (int t = 0; t < H; ++t)
+#pragma unroll
+            for (int u = 0; u < H; ++u) {
+                const int row = 4 * (bh * H + t) + x, col = 4 * (bw * H + u) + y;
+                if (row < S && col < S) {
+                    double v = a.alpha * acc[zc][t][u];
+                    if (cin) v += a.beta * cin[row * S + col];
+                    a.c_vals[co + row * S + col] = v;
+                    sq += v * v;
+                    mx = fmax(mx, fabs(v));
+                }
+            }
+        sq = q_wave_sum(sq);
+        mx = q_wave_max(mx);
+        if (lane == 0) {
+            a.sq_out[c] = sq;
+            a.mx_out[c] = mx;
+            if (!isfinite(sq)) atomicOr(a.flags, kFlagNonFinite);
+        }
     }
 }
 
@@ -116,7 +193,8 @@ k_smm_f64_quad(SmmArgs a) {
     const int64_t it = quad_item(a.n_quads);
     if (it >= a.n_quads) return;
     const int64_t item = a.q_order ? a.q_order[it] : it;
-    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));  // wave-uniform
     const int R0 = (W == 1) ? 0 : (W == 2 ? wv : wv >> 1);
     const int C0 = (W == 4) ? (wv & 1) : 0;
     const int x = lane >> 4, blk = (lane >> 2) & 3, y = lane & 3;
@@ -168,7 +246,7 @@ k_smm_f64_quad(SmmArgs a) {
     __syncthreads();
     int4 nxt = make_int4(-1, -1, -1, -1);
     if (ne > 0) {
-        nxt = ebuf[0][0];
+        nxt = uniform4(ebuf[0][0]);
         load_blocks(nxt);
     }
     for (int64_t t = 0; t < ne; ++t) {
@@ -194,57 +272,24 @@ k_smm_f64_quad(SmmArgs a) {
         }
         __syncthreads();
         if (t1 < ne) {
-            nxt = ebuf[(t1 / kEntryChunk) & 1][t1 % kEntryChunk];
+            nxt = uniform4(ebuf[(t1 / kEntryChunk) & 1][t1 % kEntryChunk]);
             load_blocks(nxt);
         }
-        if (hm == 15u)
-            quad_step<S, NR, NC, true>(sm, R0, C0, ra0, rb0, klast_ok, hm, acc);
-        else
-            quad_step<S, NR, NC, false>(sm, R0, C0, ra0, rb0, klast_ok, hm, acc);
+        quad_entry<S, NR, NC>(sm, R0, C0, ra0, rb0, klast_ok, hm, acc);
         __syncthreads();
     }
 
-#pragma unroll
-    for (int zc = 0; zc < NR * NC; ++zc) {
-        const int64_t c = a.q_cblk[4 * item + 2 * (R0 + zc / NC) + C0 + zc % NC];
-        if (c < 0) continue;
-        const int64_t co = a.c_blk_off[c];
-        const double *cin = nullptr;
-        if (a.cin_map) {
-            const int64_t t = a.cin_map[c];
-            if (t >= 0) cin = a.cin_vals + a.cin_blk_off[t];
-        }
-        double sq = 0.0, mx = 0.0;
-#pragma unroll
-        for (int t = 0; t < H; ++t)
-#pragma unroll
-            for (int u = 0; u < H; ++u) {
-                const int row = 4 * (bh * H + t) + x, col = 4 * (bw * H + u) + y;
-                if (row < S && col < S) {
-                    double v = a.alpha * acc[zc][t][u];
-                    if (cin) v += a.beta * cin[row * S + col];
-                    a.c_vals[co + row * S + col] = v;
-                    sq += v * v;
-                    mx = fmax(mx, fabs(v));
-                }
-            }
-        sq = q_wave_sum(sq);
-        mx = q_wave_max(mx);
-        if (lane == 0) {
-            a.sq_out[c] = sq;
-            a.mx_out[c] = mx;
-            if (!isfinite(sq)) atomicOr(a.flags, kFlagNonFinite);
-        }
-    }
+    quad_store<S, NR, NC>(a, item, R0, C0, lane, acc);
 }
+
 
 }  // namespace
 
-// Wavefronts per quad (1, 2 or 4); BSM_QUAD_WAVES overrides the default.
+// Wavefronts per quad (1, 2 or 4; measured best: 4); BSM_QUAD_WAVES overrides it.
 static int quad_waves() {
     const char *e = getenv("BSM_QUAD_WAVES");
-    const int w = e ? atoi(e) : 2;
-    return (w == 1 || w == 4) ? w : 2;
+    const int w = e ? atoi(e) : 4;
+    return (w == 1 || w == 2) ? w : 4;
 }
 
 bool smm_quad_available(int m, int n, int k) {

@@ -229,8 +229,8 @@ def test_multiply_kernel_variants(orc, monkeypatch, variant, maxb):
 @pytest.mark.parametrize("waves", ["1", "2", "4"])
 @pytest.mark.parametrize("b", [5, 13, 23])
 def test_quad_kernel_vs_oracle_and_fixed(orc, monkeypatch, waves, b):
-    """The quad kernel (one or two waves per 2 x 2 group of C blocks, merged
-    product lists) against the oracle -- odd block-row and column counts give
+    """The quad kernel (one, two or four waves per 2 x 2 group of C blocks,
+    merged product lists) against the oracle -- odd block-row and column counts give
     partial quads, C_in adds blocks without products, a tiny chunk size and
     an odd band height give many chunks -- and bit for bit against the
     one-C-block-per-wave compile-time-shape kernel, which sums the same
