@@ -29,6 +29,14 @@ __device__ inline int64_t xcd_item(int64_t n_items) {
     return static_cast<int64_t>(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
 }
 
+// A value that is the same in every lane (read from LDS at a uniform
+// address), made wave-uniform for the compiler.
+__device__ inline int64_t uniform64(int64_t v) {
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v)));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v >> 32)));
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 __device__ inline double wave_sum(double v) {
     for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
     return v;
@@ -314,35 +322,67 @@ k_smm_f64_class(SmmArgs a) {
     for (int t = 0; t < HR; ++t)
 #pragma unroll
         for (int u = 0; u < HC; ++u) acc[t][u] = 0.0;
-    const int64_t p0 = a.seg[c - a.c0], p_end = a.seg[c - a.c0 + 1];
+    // Per-product metadata (operand offsets and k) is fetched for 64 products
+    // at once, one product per lane, and kept in LDS (double-buffered; the next
+    // chunk waits in registers), so the operand loads of product p + 1 never
+    // wait on the chain stack -> block index -> offset of the same iteration.
+    constexpr int kMetaChunk = 64;
+    __shared__ int64_t m_off[2][2][kMetaChunk];   // [buffer][A, B][product]
+    __shared__ int32_t m_k[2][kMetaChunk];
+    const int64_t p0 = a.seg[c - a.c0], np = a.seg[c - a.c0 + 1] - p0;
+    int64_t r_aoff = 0, r_boff = 0;
+    int r_k = 0;
+    auto meta = [&](int64_t q, int64_t &ao, int64_t &bo, int &kk) {   // q < np
+        const int32_t ta = a.stk_a[p0 + q];
+        ao = a.a_blk_off[ta];
+        bo = a.b_blk_off[a.stk_b[p0 + q]];
+        kk = a.k_size[a.a_col_idx[ta]];
+    };
+    if (lane < np) {
+        int64_t ao, bo;
+        int kk;
+        meta(lane, ao, bo, kk);
+        m_off[0][0][lane] = ao;
+        m_off[0][1][lane] = bo;
+        m_k[0][lane] = kk;
+    }
+    if (kMetaChunk + lane < np) meta(kMetaChunk + lane, r_aoff, r_boff, r_k);
+    __syncthreads();
     double pa[NA], pb[NB];
     int kn = 0;
-    auto prefetch = [&](int64_t p) {
-        const int32_t ta = a.stk_a[p];
-        kn = a.k_size[a.a_col_idx[ta]];
-        const double *ga = a.a_vals + a.a_blk_off[ta];
-        const double *gb = a.b_vals + a.b_blk_off[a.stk_b[p]];
+    auto prefetch = [&](int64_t q) {           // operand blocks of product q (from LDS metadata)
+        const int buf = static_cast<int>((q / kMetaChunk) & 1), i = static_cast<int>(q % kMetaChunk);
+        kn = __builtin_amdgcn_readfirstlane(m_k[buf][i]);
+        const double *gA = a.a_vals + uniform64(m_off[buf][0][i]);
+        const double *gB = a.b_vals + uniform64(m_off[buf][1][i]);
 #pragma unroll
-        for (int q = 0; q < NA; ++q)
-            if (lane + q * kWave < M * kn) pa[q] = ga[lane + q * kWave];
+        for (int v = 0; v < NA; ++v)
+            if (lane + v * kWave < M * kn) pa[v] = gA[lane + v * kWave];
 #pragma unroll
-        for (int q = 0; q < NB; ++q)
-            if (lane + q * kWave < kn * N) pb[q] = gb[lane + q * kWave];
+        for (int v = 0; v < NB; ++v)
+            if (lane + v * kWave < kn * N) pb[v] = gB[lane + v * kWave];
     };
-    if (p0 < p_end) prefetch(p0);
-    for (int64_t p = p0; p < p_end; ++p) {
+    if (np > 0) prefetch(0);
+    for (int64_t t = 0; t < np; ++t) {
         const int k = kn;
         double *sA = sm, *sB = sm + M * k;
-        __syncthreads();                       // previous product's reads are done
 #pragma unroll
-        for (int q = 0; q < NA; ++q)
-            if (lane + q * kWave < M * k) sA[lane + q * kWave] = pa[q];
+        for (int v = 0; v < NA; ++v)
+            if (lane + v * kWave < M * k) sA[lane + v * kWave] = pa[v];
 #pragma unroll
-        for (int q = 0; q < NB; ++q)
-            if (lane + q * kWave < k * N) sB[lane + q * kWave] = pb[q];
+        for (int v = 0; v < NB; ++v)
+            if (lane + v * kWave < k * N) sB[lane + v * kWave] = pb[v];
         for (int e = M * k + k * N + lane; e < M * k + k * N + TAIL; e += kWave) sm[e] = 0.0;
+        const int64_t t1 = t + 1;
+        if ((t1 % kMetaChunk) == 0 && t1 < np) {
+            const int buf = static_cast<int>((t1 / kMetaChunk) & 1);
+            m_off[buf][0][lane] = r_aoff;
+            m_off[buf][1][lane] = r_boff;
+            m_k[buf][lane] = r_k;
+            if (t1 + kMetaChunk + lane < np) meta(t1 + kMetaChunk + lane, r_aoff, r_boff, r_k);
+        }
         __syncthreads();
-        if (p + 1 < p_end) prefetch(p + 1);
+        if (t1 < np) prefetch(t1);
         int ra[HR];
 #pragma unroll
         for (int t = 0; t < HR; ++t) ra[t] = (4 * (bh * HR + t) + y) * k + x;
@@ -361,6 +401,7 @@ k_smm_f64_class(SmmArgs a) {
                 for (int u = 0; u < HC; ++u)
                     acc[t][u] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[t], bv[u], acc[t][u], 0, 0, 0);
         }
+        __syncthreads();                       // this product's reads are done
     }
     const int64_t co = a.c_blk_off[c];
     const double *cin = nullptr;

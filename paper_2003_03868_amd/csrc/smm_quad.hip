@@ -181,7 +181,7 @@ __device__ inline void quad_store(const SmmArgs &a, int64_t item, int R0, int C0
 // wave w computes the two C blocks of row w and stages A(i_w, k), B(k, j_w);
 // W = 4, wave w computes C block (w / 2, w % 2) and stages operand w.
 // WPE: the occupancy (waves per SIMD) the register allocation aims for.
-template <int S, int W, int WPE>
+template <int S, int W, int WPE, int EPS>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_smm_f64_quad(SmmArgs a) {
     using Q = QShape<S>;
@@ -189,7 +189,8 @@ k_smm_f64_quad(SmmArgs a) {
     constexpr int NR = (W == 1) ? 2 : 1;        // quad rows per wave
     constexpr int NC = (W == 4) ? 1 : 2;        // quad columns per wave
     constexpr int NZ = 4 / W;                   // operand blocks staged per wave
-    __shared__ double sm[Q::SIZE];
+    constexpr int SLOT = 4 * Q::B2;             // LDS doubles of one staged entry
+    __shared__ double sm[EPS * SLOT + Q::TAIL];
     const int64_t it = quad_item(a.n_quads);
     if (it >= a.n_quads) return;
     const int64_t item = a.q_order ? a.q_order[it] : it;
@@ -203,7 +204,8 @@ k_smm_f64_quad(SmmArgs a) {
     auto zid = [&](int zz) { return (W == 1) ? zz : (W == 4 ? wv : (zz == 0 ? wv : 2 + wv)); };
     auto pick = [](const int4 v, int z) { return z == 0 ? v.x : z == 1 ? v.y : z == 2 ? v.z : v.w; };
 
-    for (int e = 4 * Q::B2 + static_cast<int>(threadIdx.x); e < Q::SIZE; e += 64 * W) sm[e] = 0.0;
+    for (int e = EPS * SLOT + static_cast<int>(threadIdx.x); e < EPS * SLOT + Q::TAIL; e += 64 * W)
+        sm[e] = 0.0;
     const int ra0 = (4 * bh * H + y) * S + x;      // A(4 (bh H + t) + y, 4 ks + x)
     const int rb0 = x * S + 4 * bw * H + y;        // B(4 ks + x, 4 (bw H + u) + y)
     const bool klast_ok = x < Q::KLAST;
@@ -216,16 +218,18 @@ k_smm_f64_quad(SmmArgs a) {
 #pragma unroll
             for (int u = 0; u < H; ++u) acc[z][t][u] = 0.0;
 
-    // Pipeline: while entry e is multiplied, the operand blocks of e + 1 are
-    // in flight to registers.  The entry indices come from LDS, where wave 0
-    // stores them in chunks of kEntryChunk (double-buffered; the next chunk
-    // waits in registers), so no global load waits on another global load
-    // issued in the same iteration.
+    // Pipeline: while the EPS entries of a stage are multiplied, the operand
+    // blocks of the next stage are in flight to registers.  The entry indices
+    // come from LDS, where wave 0 stores them in chunks of kEntryChunk
+    // (double-buffered; the next chunk waits in registers), so no global load
+    // waits on another global load issued in the same iteration.
     constexpr int kEntryChunk = 64;
+    static_assert(kEntryChunk % EPS == 0, "stages must not straddle index chunks");
     __shared__ int4 ebuf[2][kEntryChunk];
     const int64_t e0 = a.q_seg[item], ne = a.q_seg[item + 1] - e0;
-    double pv[NZ][Q::NV];
-    auto load_blocks = [&](const int4 en) {
+    const int4 none = make_int4(-1, -1, -1, -1);
+    double pv[EPS][NZ][Q::NV];
+    auto load_blocks = [&](const int4 en, double (&p)[NZ][Q::NV]) {
 #pragma unroll
         for (int zz = 0; zz < NZ; ++zz) {
             const int z = zid(zz);
@@ -234,36 +238,43 @@ k_smm_f64_quad(SmmArgs a) {
                 const double *g = (z < 2 ? a.a_vals : a.b_vals) + static_cast<int64_t>(id) * Q::B2;
 #pragma unroll
                 for (int q = 0; q < Q::NV; ++q)
-                    if (q < Q::NV - 1 || lane + q * kWave < Q::B2) pv[zz][q] = g[lane + q * kWave];
+                    if (q < Q::NV - 1 || lane + q * kWave < Q::B2) p[zz][q] = g[lane + q * kWave];
             }
         }
     };
-    int4 creg = make_int4(-1, -1, -1, -1);    // wave 0: entry e0 + 64 c + lane of the next chunk
+    auto flags = [](const int4 c) {
+        return (c.x >= 0 ? 1u : 0u) | (c.y >= 0 ? 2u : 0u) | (c.z >= 0 ? 4u : 0u) |
+               (c.w >= 0 ? 8u : 0u);
+    };
+    int4 creg = none;                          // wave 0: entry e0 + 64 c + lane of the next chunk
     if (wv == 0) {
         if (lane < ne) ebuf[0][lane] = a.q_ent[e0 + lane];
         if (kEntryChunk + lane < ne) creg = a.q_ent[e0 + kEntryChunk + lane];
     }
     __syncthreads();
-    int4 nxt = make_int4(-1, -1, -1, -1);
-    if (ne > 0) {
-        nxt = uniform4(ebuf[0][0]);
-        load_blocks(nxt);
+    int4 nxt[EPS];
+#pragma unroll
+    for (int q = 0; q < EPS; ++q) {
+        nxt[q] = q < ne ? uniform4(ebuf[0][q]) : none;
+        load_blocks(nxt[q], pv[q]);
     }
-    for (int64_t t = 0; t < ne; ++t) {
-        const int4 cur = nxt;
-        const unsigned hm = (cur.x >= 0 ? 1u : 0u) | (cur.y >= 0 ? 2u : 0u) |
-                            (cur.z >= 0 ? 4u : 0u) | (cur.w >= 0 ? 8u : 0u);
+    for (int64_t t = 0; t < ne; t += EPS) {
+        unsigned hm[EPS];
 #pragma unroll
-        for (int zz = 0; zz < NZ; ++zz) {
-            const int z = zid(zz);
-            if ((hm >> z) & 1u) {
+        for (int q = 0; q < EPS; ++q) {
+            hm[q] = flags(nxt[q]);
 #pragma unroll
-                for (int q = 0; q < Q::NV; ++q)
-                    if (q < Q::NV - 1 || lane + q * kWave < Q::B2)
-                        sm[z * Q::B2 + lane + q * kWave] = pv[zz][q];
+            for (int zz = 0; zz < NZ; ++zz) {
+                const int z = zid(zz);
+                if ((hm[q] >> z) & 1u) {
+#pragma unroll
+                    for (int v = 0; v < Q::NV; ++v)
+                        if (v < Q::NV - 1 || lane + v * kWave < Q::B2)
+                            sm[q * SLOT + z * Q::B2 + lane + v * kWave] = pv[q][zz][v];
+                }
             }
         }
-        const int64_t t1 = t + 1;
+        const int64_t t1 = t + EPS;
         if ((t1 % kEntryChunk) == 0 && t1 < ne && wv == 0) {
             // entering chunk t1 / 64: its indices (loaded a chunk ago) go to
             // LDS, the chunk after it is fetched into registers
@@ -271,17 +282,20 @@ k_smm_f64_quad(SmmArgs a) {
             if (t1 + kEntryChunk + lane < ne) creg = a.q_ent[e0 + t1 + kEntryChunk + lane];
         }
         __syncthreads();
-        if (t1 < ne) {
-            nxt = uniform4(ebuf[(t1 / kEntryChunk) & 1][t1 % kEntryChunk]);
-            load_blocks(nxt);
+#pragma unroll
+        for (int q = 0; q < EPS; ++q) {
+            nxt[q] = (t1 + q < ne) ? uniform4(ebuf[((t1 + q) / kEntryChunk) & 1][(t1 + q) % kEntryChunk])
+                                   : none;
+            load_blocks(nxt[q], pv[q]);
         }
-        quad_entry<S, NR, NC>(sm, R0, C0, ra0, rb0, klast_ok, hm, acc);
+#pragma unroll
+        for (int q = 0; q < EPS; ++q)
+            quad_entry<S, NR, NC>(sm + q * SLOT, R0, C0, ra0, rb0, klast_ok, hm[q], acc);
         __syncthreads();
     }
 
     quad_store<S, NR, NC>(a, item, R0, C0, lane, acc);
 }
-
 
 }  // namespace
 
@@ -290,6 +304,12 @@ static int quad_waves() {
     const char *e = getenv("BSM_QUAD_WAVES");
     const int w = e ? atoi(e) : 4;
     return (w == 1 || w == 2) ? w : 4;
+}
+
+// Entries staged per barrier pair (1 or 2); BSM_QUAD_STAGE overrides the default.
+static int quad_stage() {
+    const char *e = getenv("BSM_QUAD_STAGE");
+    return (e && atoi(e) == 2) ? 2 : 1;
 }
 
 bool smm_quad_available(int m, int n, int k) {
@@ -305,18 +325,19 @@ int launch_quad(const SmmArgs &a, hipStream_t s) {
         return BSM_EINVAL;
     }
     const unsigned g = static_cast<unsigned>(grid);
-    const int w = quad_waves();
+    const int w = quad_waves(), eps = quad_stage();
     switch (a.uni_m) {
-        case 5: k_smm_f64_quad<5, 1, 8><<<g, 64, 0, s>>>(a); break;
+        case 5: k_smm_f64_quad<5, 1, 8, 1><<<g, 64, 0, s>>>(a); break;
         case 13:
-            if (w == 4) k_smm_f64_quad<13, 4, 6><<<g, 256, 0, s>>>(a);
-            else if (w == 2) k_smm_f64_quad<13, 2, 4><<<g, 128, 0, s>>>(a);
-            else k_smm_f64_quad<13, 1, 4><<<g, 64, 0, s>>>(a);
+            if (w == 4) k_smm_f64_quad<13, 4, 6, 1><<<g, 256, 0, s>>>(a);
+            else if (w == 2) k_smm_f64_quad<13, 2, 4, 1><<<g, 128, 0, s>>>(a);
+            else k_smm_f64_quad<13, 1, 4, 1><<<g, 64, 0, s>>>(a);
             break;
         case 23:
-            if (w == 4) k_smm_f64_quad<23, 4, 5><<<g, 256, 0, s>>>(a);
-            else if (w == 2) k_smm_f64_quad<23, 2, 3><<<g, 128, 0, s>>>(a);
-            else k_smm_f64_quad<23, 1, 1><<<g, 64, 0, s>>>(a);
+            if (w == 4 && eps == 2) k_smm_f64_quad<23, 4, 4, 2><<<g, 256, 0, s>>>(a);
+            else if (w == 4) k_smm_f64_quad<23, 4, 5, 1><<<g, 256, 0, s>>>(a);
+            else if (w == 2) k_smm_f64_quad<23, 2, 3, 1><<<g, 128, 0, s>>>(a);
+            else k_smm_f64_quad<23, 1, 1, 1><<<g, 64, 0, s>>>(a);
             break;
         default: set_error("no quad kernel for block size %d", a.uni_m); return BSM_EINVAL;
     }

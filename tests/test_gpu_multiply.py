@@ -226,16 +226,18 @@ def test_multiply_kernel_variants(orc, monkeypatch, variant, maxb):
         assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"variant {variant} maxb {maxb}")
 
 
-@pytest.mark.parametrize("waves", ["1", "2", "4"])
+@pytest.mark.parametrize("waves,stage", [("1", "1"), ("2", "1"), ("4", "1"), ("4", "2")])
 @pytest.mark.parametrize("b", [5, 13, 23])
-def test_quad_kernel_vs_oracle_and_fixed(orc, monkeypatch, waves, b):
+def test_quad_kernel_vs_oracle_and_fixed(orc, monkeypatch, waves, stage, b):
     """The quad kernel (one, two or four waves per 2 x 2 group of C blocks,
-    merged product lists) against the oracle -- odd block-row and column counts give
+    merged product lists, one or two entries staged per step) against the
+    oracle -- odd block-row and column counts give
     partial quads, C_in adds blocks without products, a tiny chunk size and
     an odd band height give many chunks -- and bit for bit against the
     one-C-block-per-wave compile-time-shape kernel, which sums the same
     products in the same order with the same instructions."""
     monkeypatch.setenv("BSM_QUAD_WAVES", waves)
+    monkeypatch.setenv("BSM_QUAD_STAGE", stage)
     rng = np.random.default_rng(500 + b)
     nbr, nbk, nbc = 11, 9, 13
     a = synth.random_bsr(nbr, nbk, np.full(nbr, b), np.full(nbk, b), 0.45, rng)
