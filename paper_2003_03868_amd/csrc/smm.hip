@@ -302,6 +302,54 @@ k_smm_f64_fixed(SmmArgs a) {
 // index passes the product's k read zero.
 constexpr int kClassKmax = 26;   // largest k of the class set {5, 13, 23, 26}
 
+// Staging and multiply of one product with k known at compile time (the
+// class set's k in {5, 13, 23, 26}): fully unrolled k-steps, only the last
+// one masked.  Layout as in k_smm_f64_class: A (M x K) then B (K x N),
+// row-major, then the zeroed tail; padded rows/columns read neighbouring
+// data that reaches only accumulator elements that are never stored.
+template <int M, int N, int K, int NA, int NB, int TAIL>
+__device__ inline void class_stage(double *sm, int lane, const double (&pa)[NA],
+                                   const double (&pb)[NB]) {
+    double *sA = sm, *sB = sm + M * K;
+#pragma unroll
+    for (int v = 0; v < NA; ++v)
+        if (v * kWave < M * K && lane + v * kWave < M * K) sA[lane + v * kWave] = pa[v];
+#pragma unroll
+    for (int v = 0; v < NB; ++v)
+        if (v * kWave < K * N && lane + v * kWave < K * N) sB[lane + v * kWave] = pb[v];
+#pragma unroll
+    for (int e = M * K + K * N; e < M * K + K * N + TAIL; e += kWave)
+        if (e + lane < M * K + K * N + TAIL) sm[e + lane] = 0.0;
+}
+
+template <int M, int N, int K, int HR, int HC>
+__device__ inline void class_compute(const double *sm, int bh, int bw, int x, int y,
+                                     double (&acc)[HR][HC]) {
+    constexpr int KS = (K + 3) / 4, KLAST = K - 4 * (KS - 1);
+    const double *sA = sm, *sB = sm + M * K;
+    const int ra0 = (4 * bh * HR + y) * K + x, rb0 = x * N + 4 * bw * HC + y;
+    const bool ok = x < KLAST;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        double av[HR], bv[HC];
+#pragma unroll
+        for (int t = 0; t < HR; ++t) {
+            const double v = sA[ra0 + 4 * t * K + 4 * ks];
+            av[t] = (ks == KS - 1 && KLAST < 4 && !ok) ? 0.0 : v;
+        }
+#pragma unroll
+        for (int u = 0; u < HC; ++u) {
+            const double v = sB[rb0 + 4 * u + 4 * ks * N];
+            bv[u] = (ks == KS - 1 && KLAST < 4 && !ok) ? 0.0 : v;
+        }
+#pragma unroll
+        for (int t = 0; t < HR; ++t)
+#pragma unroll
+            for (int u = 0; u < HC; ++u)
+                acc[t][u] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[t], bv[u], acc[t][u], 0, 0, 0);
+    }
+}
+
 template <int M, int N>
 __global__ void __launch_bounds__(64)
 k_smm_f64_class(SmmArgs a) {
@@ -366,13 +414,20 @@ k_smm_f64_class(SmmArgs a) {
     for (int64_t t = 0; t < np; ++t) {
         const int k = kn;
         double *sA = sm, *sB = sm + M * k;
+        switch (k) {
+            case 5: class_stage<M, N, 5, NA, NB, TAIL>(sm, lane, pa, pb); break;
+            case 13: class_stage<M, N, 13, NA, NB, TAIL>(sm, lane, pa, pb); break;
+            case 23: class_stage<M, N, 23, NA, NB, TAIL>(sm, lane, pa, pb); break;
+            case 26: class_stage<M, N, 26, NA, NB, TAIL>(sm, lane, pa, pb); break;
+            default:
 #pragma unroll
-        for (int v = 0; v < NA; ++v)
-            if (lane + v * kWave < M * k) sA[lane + v * kWave] = pa[v];
+                for (int v = 0; v < NA; ++v)
+                    if (lane + v * kWave < M * k) sA[lane + v * kWave] = pa[v];
 #pragma unroll
-        for (int v = 0; v < NB; ++v)
-            if (lane + v * kWave < k * N) sB[lane + v * kWave] = pb[v];
-        for (int e = M * k + k * N + lane; e < M * k + k * N + TAIL; e += kWave) sm[e] = 0.0;
+                for (int v = 0; v < NB; ++v)
+                    if (lane + v * kWave < k * N) sB[lane + v * kWave] = pb[v];
+                for (int e = M * k + k * N + lane; e < M * k + k * N + TAIL; e += kWave) sm[e] = 0.0;
+        }
         const int64_t t1 = t + 1;
         if ((t1 % kMetaChunk) == 0 && t1 < np) {
             const int buf = static_cast<int>((t1 / kMetaChunk) & 1);
@@ -383,23 +438,31 @@ k_smm_f64_class(SmmArgs a) {
         }
         __syncthreads();
         if (t1 < np) prefetch(t1);
-        int ra[HR];
+        switch (k) {
+            case 5: class_compute<M, N, 5, HR, HC>(sm, bh, bw, x, y, acc); break;
+            case 13: class_compute<M, N, 13, HR, HC>(sm, bh, bw, x, y, acc); break;
+            case 23: class_compute<M, N, 23, HR, HC>(sm, bh, bw, x, y, acc); break;
+            case 26: class_compute<M, N, 26, HR, HC>(sm, bh, bw, x, y, acc); break;
+            default: {
+                int ra[HR];
 #pragma unroll
-        for (int t = 0; t < HR; ++t) ra[t] = (4 * (bh * HR + t) + y) * k + x;
-        const int rb = x * N + 4 * bw * HC + y;
+                for (int t = 0; t < HR; ++t) ra[t] = (4 * (bh * HR + t) + y) * k + x;
+                const int rb = x * N + 4 * bw * HC + y;
 #pragma unroll 1
-        for (int ks = 0; 4 * ks < k; ++ks) {
-            const bool ok = 4 * ks + x < k;
-            double av[HR], bv[HC];
+                for (int ks = 0; 4 * ks < k; ++ks) {
+                    const bool ok = 4 * ks + x < k;
+                    double av[HR], bv[HC];
 #pragma unroll
-            for (int t = 0; t < HR; ++t) av[t] = ok ? sA[ra[t] + 4 * ks] : 0.0;
+                    for (int t = 0; t < HR; ++t) av[t] = ok ? sA[ra[t] + 4 * ks] : 0.0;
 #pragma unroll
-            for (int u = 0; u < HC; ++u) bv[u] = ok ? sB[rb + 4 * u + 4 * ks * N] : 0.0;
+                    for (int u = 0; u < HC; ++u) bv[u] = ok ? sB[rb + 4 * u + 4 * ks * N] : 0.0;
 #pragma unroll
-            for (int t = 0; t < HR; ++t)
+                    for (int t = 0; t < HR; ++t)
 #pragma unroll
-                for (int u = 0; u < HC; ++u)
-                    acc[t][u] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[t], bv[u], acc[t][u], 0, 0, 0);
+                        for (int u = 0; u < HC; ++u)
+                            acc[t][u] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[t], bv[u], acc[t][u], 0, 0, 0);
+                }
+            }
         }
         __syncthreads();                       // this product's reads are done
     }
