@@ -197,6 +197,28 @@ def main():
     ms_per_step = total / args.steps * 1e3
     achieved = flops / (smm_ms * 1e-3) / 1e12 if smm_ms > 0 else 0.0
 
+    err64 = None
+    if args.prec != "fp64":
+        # error of the reduced-precision sign against the FP64 GPU path on the
+        # same input (untimed): ||X_p - X_64||_F / ||X_64||_F and trace(P)
+        import math
+        st_p, xp, sp = bsm.bsm_sign_iterate(dh.handle, 0.0, opts, stream=stream)
+        o64 = bsm.bsm_sign_opts_default()
+        for f, _ in bsm.bsm_sign_opts._fields_:
+            setattr(o64, f, getattr(opts, f))
+        o64.prec = bsm.FP64
+        st_64, x64, s64 = bsm.bsm_sign_iterate(dh.handle, 0.0, o64, stream=stream)
+        d = bsm.bsm_add(1.0, xp, -1.0, x64, stream=stream)
+        num = bsm.bsm_sqdist_identity(d, 0.0, stream=stream)
+        den = bsm.bsm_sqdist_identity(x64, 0.0, stream=stream)
+        err64 = {"rel_fro_X_vs_fp64": math.sqrt(num / den), "trace_p": float(sp.trace_p),
+                 "trace_p_fp64": float(s64.trace_p),
+                 "trace_p_diff": float(sp.trace_p - s64.trace_p),
+                 "precisions": list(sp.prec_hist[:sp.iterations + 1])}
+        for hnd in (d, x64, xp):
+            bsm.bsm_destroy(hnd)
+        log(f"error vs FP64 path: {err64}")
+
     cpu = None
     if not args.no_cpu and args.workload == "sign23":
         log("timing the CPU oracle on a sample ...")
@@ -257,6 +279,8 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if err64 is not None:
+        out["error_vs_fp64"] = err64
     print(json.dumps(out), flush=True)
     dh.destroy()
 
