@@ -313,7 +313,7 @@ static int quad_stage() {
 }
 
 bool smm_quad_available(int m, int n, int k) {
-    return m == n && n == k && (m == 5 || m == 13 || m == 23);
+    return m == n && n == k && (m == 5 || m == 13 || m == 23 || m == 26 || m == 32);
 }
 
 int launch_quad(const SmmArgs &a, hipStream_t s) {
@@ -339,6 +339,8 @@ int launch_quad(const SmmArgs &a, hipStream_t s) {
             else if (w == 2) k_smm_f64_quad<23, 2, 3, 1><<<g, 128, 0, s>>>(a);
             else k_smm_f64_quad<23, 1, 1, 1><<<g, 64, 0, s>>>(a);
             break;
+        case 26: k_smm_f64_quad<26, 4, 4, 1><<<g, 256, 0, s>>>(a); break;
+        case 32: k_smm_f64_quad<32, 4, 4, 1><<<g, 256, 0, s>>>(a); break;
         default: set_error("no quad kernel for block size %d", a.uni_m); return BSM_EINVAL;
     }
     BSM_HIP(hipGetLastError());

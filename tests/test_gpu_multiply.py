@@ -227,7 +227,7 @@ def test_multiply_kernel_variants(orc, monkeypatch, variant, maxb):
 
 
 @pytest.mark.parametrize("waves,stage", [("1", "1"), ("2", "1"), ("4", "1"), ("4", "2")])
-@pytest.mark.parametrize("b", [5, 13, 23])
+@pytest.mark.parametrize("b", [5, 13, 23, 26, 32])
 def test_quad_kernel_vs_oracle_and_fixed(orc, monkeypatch, waves, stage, b):
     """The quad kernel (one, two or four waves per 2 x 2 group of C blocks,
     merged product lists, one or two entries staged per step) against the
