@@ -197,6 +197,20 @@ def main():
     ms_per_step = total / args.steps * 1e3
     achieved = flops / (smm_ms * 1e-3) / 1e12 if smm_ms > 0 else 0.0
 
+    # density-matrix diagnostic of the returned iterate (untimed): idempotency
+    # ||P^2 - P||_F / n on the device, P^2 filtered like every product
+    import math
+    st_d, xd, _ = bsm.bsm_sign_iterate(dh.handle, 0.0, opts, stream=stream)
+    pd, _ = bsm.bsm_density_from_sign(xd, stream=stream)
+    p2 = bsm.Matrix.empty_like(h.row_blk_size, h.col_blk_size)
+    bsm.bsm_multiply(1.0, pd, pd, 0.0, p2.handle, args.eps, bsm.NORM_FROB, stream=stream)
+    dd = bsm.bsm_add(1.0, p2.handle, -1.0, pd, stream=stream)
+    idem = math.sqrt(bsm.bsm_sqdist_identity(dd, 0.0, stream=stream)) / float(h.shape[0])
+    for hnd in (dd, pd, xd):
+        bsm.bsm_destroy(hnd)
+    p2.destroy()
+    log(f"||P^2 - P||_F / n = {idem:.3e}")
+
     err64 = None
     if args.prec != "fp64":
         # error of the reduced-precision sign against the FP64 GPU path on the
@@ -260,6 +274,7 @@ def main():
         "tflop_per_step": flops / args.steps / 1e12,
         "products_per_step": int(sum(s.n_products for s, _ in all_stats) / args.steps),
         "nnzb_X_final": int(s0.nnzb_final),
+        "idempotency_P": idem,
         "graph_replays": int(s0.graph_replays),
         "graph_fallbacks": int(s0.graph_fallbacks),
         "roofline": {
