@@ -46,6 +46,15 @@ static int quad_tile(const char *name, int dflt) {
     return e ? atoi(e) : dflt;
 }
 
+// Quads for reduced-precision products: BSM_LOWP_QUAD = 1 always, 0 never;
+// default for split-BF16 only (for FP32 products the one-block-per-wave
+// kernel measured faster).
+static bool lowp_quad(int prec) {
+    const char *e = getenv("BSM_LOWP_QUAD");
+    if (e) return atoi(e) != 0;
+    return prec == BSM_SPLIT_BF16;
+}
+
 // Kernel family for a chunk with mixed block sizes (uniform sizes keep the
 // requested variant).  Default: per-class launches when every size is in
 // {5, 13, 23, 26}, else the fused persistent kernel.
@@ -210,9 +219,10 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     if (st == BSM_OK) st = tile_order(c_row_ptr, nc.col_idx, nbr, B.nbcols, rb, worklist, s);
     std::vector<int32_t> cuts{0};
     {
-        // whole row bands; an even step keeps the quads' row pairs in one chunk
+        // whole row bands; a step that is a multiple of 4 keeps the row
+        // groups of the group kernel (2 or 4 rows) in one chunk
         const int64_t lim = chunk_products();
-        const int step = rb + (rb & 1);
+        const int step = (rb + 3) / 4 * 4;
         int32_t r0 = 0;
         while (r0 < nbr) {
             int32_t r1 = std::min(nbr, r0 + step);
@@ -235,6 +245,13 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         SmmParams tp;
         use_quad = !(table_lookup(A.uni_r, B.uni_c, A.uni_c, &tp) && tp.family != 3);
     }
+    // reduced precision: quads where they pay, unless another kernel
+    // variant is asked for
+    if (prec != BSM_FP64 && variant == kSmmF64Quad && lowp_quad(prec) && A.uni_r && A.uni_c &&
+        B.uni_c && smm_lowp_available(A.uni_r, B.uni_c, A.uni_c))
+        use_quad = true;
+    // group edge: quads, or groups of sixteen (FP64 only)
+    const int G = (use_quad && prec == BSM_FP64) ? quad_group(A.uni_r) : 2;
 
     // one set of stack buffers reused by every chunk; a plan keeps one per
     // chunk; the quad kernel builds its own lists
@@ -300,11 +317,11 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         ma.nC = h_crp[r1] - h_crp[r0];
         if (ma.nC == 0) continue;
         if (use_quad) {
-            // quads of this chunk's C blocks and their merged entry lists;
+            // groups of this chunk's C blocks and their merged entry lists;
             // without a plan the buffers live for this chunk only
             Scratch ctmp(s);
             auto qbuf = [&](auto **ptr, size_t n) -> int { return pl ? keep_buf(ptr, n) : ctmp.get(ptr, n); };
-            const int64_t npairs = (static_cast<int64_t>(r1 - r0) + 1) / 2;
+            const int64_t npairs = (static_cast<int64_t>(r1 - r0) + G - 1) / G;
             int64_t *q_off = nullptr, *q_cblk = nullptr, *e_off = nullptr, *q_order = nullptr;
             int32_t *q_col = nullptr;
             int4 *ent = nullptr;
@@ -316,7 +333,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
                 return BSM_OK;
             };
             QuadSymArgs qa{};
-            qa.r0 = r0; qa.r1 = r1; qa.nbcols = B.nbcols;
+            qa.r0 = r0; qa.r1 = r1; qa.nbcols = B.nbcols; qa.g = G;
             qa.a_row_ptr = A.row_ptr; qa.a_col_idx = A.col_idx;
             qa.b_row_ptr = B.row_ptr; qa.b_col_idx = B.col_idx;
             qa.c_row_ptr = c_row_ptr; qa.c_col_idx = nc.col_idx;
@@ -324,7 +341,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             if (st == BSM_OK) st = quad_pairs(qa, q_off, s);
             if (st == BSM_OK) st = scan_i64(q_off, q_off, npairs, s);
             if (st == BSM_OK) st = read_total(q_off + npairs, &nq);
-            if (st == BSM_OK) st = qbuf(&q_cblk, 4 * nq);
+            if (st == BSM_OK) st = qbuf(&q_cblk, static_cast<size_t>(G) * G * nq);
             if (st == BSM_OK) st = qbuf(&e_off, nq + 1);
             if (st == BSM_OK) st = qbuf(&q_col, nq);
             qa.q_off = q_off;
@@ -336,12 +353,12 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             if (st == BSM_OK && qr > 0 && nq > 0) {
                 st = qbuf(&q_order, nq);
                 if (st == BSM_OK)
-                    st = tile_order(q_off, q_col, static_cast<int32_t>(npairs), (B.nbcols + 1) / 2,
+                    st = tile_order(q_off, q_col, static_cast<int32_t>(npairs), (B.nbcols + G - 1) / G,
                                     qr, q_order, s, qc);
             }
             if (st == BSM_OK) st = scan_i64(e_off, e_off, nq, s);
             if (st == BSM_OK) st = read_total(e_off + nq, &ne);
-            if (st == BSM_OK) st = qbuf(&ent, ne);
+            if (st == BSM_OK) st = qbuf(&ent, static_cast<size_t>(ne) * (G / 2));
             qa.ent = ent;
             if (st == BSM_OK) st = quad_stack(qa, true, s);
             if (st != BSM_OK) break;
@@ -353,6 +370,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             op.a.q_seg = e_off;
             op.a.q_ent = ent;
             op.a.q_order = q_order;
+            op.a.q_group = G;
             std::pair<hipEvent_t, hipEvent_t> pe{};
             if (ev.on) {
                 BSM_HIP(hipEventCreate(&pe.first));

@@ -1,15 +1,17 @@
-// Quads: 2 x 2 groups of C blocks with merged product lists (symbolic part
-// of the quad block-product kernel in smm_quad.hip).  Built straight from
-// the patterns of A, B and C, without per-C-block stacks.
+// Groups of C blocks with merged product lists (symbolic part of the group
+// block-product kernel in smm_quad.hip).  Built straight from the patterns
+// of A, B and C, without per-C-block stacks.
 //
-// A quad is the group C(2R + r, 2Q + c), r, c in {0, 1}, of the C blocks of a
-// chunk (at least one of them present).  Its entry list is the union of the
-// k's of its C blocks' products, ascending; entry k names A(2R + r, k) for
-// each row r and B(k, 2Q + c) for each column c that a product of the quad
-// uses, -1 otherwise.  Product (r, c) of an entry exists exactly when both
-// A(2R + r, k) and B(k, 2Q + c) are named, so the per-C-block sums are those
+// A group is the G x G set C(G R + r, G Q + c), r, c in [0, G), of the C
+// blocks of a chunk (at least one of them present); G = 2 gives quads, G = 4
+// groups of sixteen.  Its entry list is the union of the k's of its C blocks'
+// products, ascending; entry k names A(G R + r, k) for each row r and
+// B(k, G Q + c) for each column c that a product of the group uses, -1
+// otherwise.  Product (r, c) of an entry exists exactly when both
+// A(G R + r, k) and B(k, G Q + c) are named, so the per-C-block sums are those
 // of the plain stacks, in the same (ascending k) order, while every operand
-// block is loaded once for up to four products.
+// block is loaded once for up to G products.  An entry is G / 2 int4: the G
+// A indices, then the G B indices.
 #include <climits>
 
 #include "symbolic.h"
@@ -18,7 +20,7 @@ namespace bsm {
 
 constexpr int kQuadThreads = 256;
 
-// Rank of column pair Q among the marked bits.
+// Rank of column group Q among the marked bits.
 __device__ inline int32_t bit_rank_q(const uint32_t *bits, const int32_t *wpre, int32_t Q) {
     const uint32_t w = bits[Q >> 5];
     const uint32_t below = (Q & 31) ? (w & ((1u << (Q & 31)) - 1u)) : 0u;
@@ -27,14 +29,14 @@ __device__ inline int32_t bit_rank_q(const uint32_t *bits, const int32_t *wpre, 
 
 // ---------------------------------------------------------------------------
 // Entry lists straight from the patterns of A and B: one workgroup per row
-// pair walks k over the merged column lists of A's rows 2R and 2R + 1
+// group walks k over the merged column lists of A's rows G R .. G R + G - 1
 // (ascending); for each k its threads scan B's row k, and the thread holding
-// column j = 2Q (or 2Q + 1 when 2Q is absent) emits the entry of quad Q,
-// naming both of B(k, 2Q), B(k, 2Q + 1) that exist.  Every (quad, k) pair is
-// emitted by one thread, so a per-quad cursor in LDS needs no atomics, and
-// the barrier after each k keeps every list in ascending k.  Quads are ranked
-// within the pair by an LDS bitmap of their column pairs; pairs with more
-// quads than kQuadWindow are done in windows.
+// the first column of group Q present in that row emits the entry of group
+// Q, naming every B(k, G Q + c) that exists.  Every (group, k) pair is
+// emitted by one thread, so a per-group cursor in LDS needs no atomics, and
+// the barrier after each k keeps every list in ascending k.  Groups are
+// ranked within the row group by an LDS bitmap of their column groups; row
+// groups with more groups than kQuadWindow are done in windows.
 constexpr int kQuadWindow = 4096;
 
 __device__ inline int64_t qwg_exscan(int64_t v, int64_t *scratch, int64_t *total) {
@@ -58,16 +60,21 @@ __device__ inline int64_t qwg_exscan(int64_t v, int64_t *scratch, int64_t *total
     return before + x - v;
 }
 
-// Bitmap of the column pairs Q holding C blocks of rows i0 (and i1) and the
-// exclusive popcount prefix per word; returns the number of quads.
-__device__ inline int64_t quad_rank_map(const QuadSymArgs &q, int32_t i0, bool two, int nwq,
+__host__ __device__ inline int quad_words(int32_t nbcols, int g) {
+    return ((nbcols + g - 1) / g + 31) >> 5;
+}
+
+// Bitmap of the column groups Q holding C blocks of rows i0 .. i0 + nr - 1
+// and the exclusive popcount prefix per word; returns the number of groups.
+template <int G>
+__device__ inline int64_t quad_rank_map(const QuadSymArgs &q, int32_t i0, int nr, int nwq,
                                         uint32_t *bits, int32_t *wpre, int64_t *scratch) {
     for (int w = threadIdx.x; w < nwq; w += kQuadThreads) bits[w] = 0u;
     __syncthreads();
-    for (int r = 0; r < (two ? 2 : 1); ++r)
+    for (int r = 0; r < nr; ++r)
         for (int64_t t = q.c_row_ptr[i0 + r] + threadIdx.x; t < q.c_row_ptr[i0 + r + 1];
              t += kQuadThreads) {
-            const int32_t Q = q.c_col_idx[t] >> 1;
+            const int32_t Q = q.c_col_idx[t] / G;
             atomicOr(&bits[Q >> 5], 1u << (Q & 31));
         }
     __syncthreads();
@@ -85,90 +92,97 @@ __device__ inline int64_t quad_rank_map(const QuadSymArgs &q, int32_t i0, bool t
     return total;
 }
 
-// Quads per row pair (one workgroup per pair).
+// Groups per row group (one workgroup per row group).
+template <int G>
 __global__ void __launch_bounds__(kQuadThreads)
 k_quad_pairs(QuadSymArgs q, int64_t *cnt) {
     extern __shared__ uint32_t smem[];
     __shared__ int64_t scratch[kQuadThreads / kWave];
-    const int nwq = (((q.nbcols + 1) >> 1) + 31) >> 5;
+    const int nwq = quad_words(q.nbcols, G);
     const int32_t R = blockIdx.x;
-    const int32_t i0 = q.r0 + 2 * R;
-    const int64_t nq = quad_rank_map(q, i0, i0 + 1 < q.r1, nwq, smem,
-                                     reinterpret_cast<int32_t *>(smem + nwq), scratch);
+    const int32_t i0 = q.r0 + G * R;
+    const int nr = (q.r1 - i0 < G) ? q.r1 - i0 : G;
+    const int64_t nq = quad_rank_map<G>(q, i0, nr, nwq, smem,
+                                        reinterpret_cast<int32_t *>(smem + nwq), scratch);
     if (threadIdx.x == 0) cnt[R] = nq;
 }
 
-// FILL = false: the quads' C blocks (q_cblk) and entry counts (e_off);
+// FILL = false: the groups' C blocks (q_cblk) and entry counts (e_off);
 // FILL = true: the entries.
-template <bool FILL>
+template <bool FILL, int G>
 __global__ void __launch_bounds__(kQuadThreads)
 k_quad_stack(QuadSymArgs q) {
     extern __shared__ uint32_t smem[];
     __shared__ int64_t scratch[kQuadThreads / kWave];
-    __shared__ int64_t s_pa, s_pb;
-    __shared__ int32_t s_k, s_a0, s_a1;
-    const int nwq = (((q.nbcols + 1) >> 1) + 31) >> 5;   // words of the column-pair bitmap
+    __shared__ int64_t s_p[G];
+    __shared__ int32_t s_k, s_a[G];
+    const int nwq = quad_words(q.nbcols, G);   // words of the column-group bitmap
     uint32_t *bits = smem;
     int32_t *wpre = reinterpret_cast<int32_t *>(smem + nwq);
     int32_t *cnt = reinterpret_cast<int32_t *>(smem + 2 * nwq);
     const int32_t R = blockIdx.x;
-    const int32_t i0 = q.r0 + 2 * R, i1 = i0 + 1;
-    const bool two = i1 < q.r1;
-    quad_rank_map(q, i0, two, nwq, bits, wpre, scratch);
+    const int32_t i0 = q.r0 + G * R;
+    const int nr = (q.r1 - i0 < G) ? q.r1 - i0 : G;
+    quad_rank_map<G>(q, i0, nr, nwq, bits, wpre, scratch);
 
     const int64_t qbase = q.q_off[R], nq = q.q_off[R + 1] - qbase;
     if (!FILL) {
-        // C blocks of every quad: (r, c) at 4 quad + 2 r + c, -1 where absent
-        for (int64_t t = threadIdx.x; t < 4 * nq; t += kQuadThreads) q.q_cblk[4 * qbase + t] = -1;
+        // C blocks of every group: (r, c) at G G group + G r + c, -1 where absent
+        for (int64_t t = threadIdx.x; t < G * G * nq; t += kQuadThreads) q.q_cblk[G * G * qbase + t] = -1;
         __syncthreads();
-        for (int r = 0; r < (two ? 2 : 1); ++r)
+        for (int r = 0; r < nr; ++r)
             for (int64_t t = q.c_row_ptr[i0 + r] + threadIdx.x; t < q.c_row_ptr[i0 + r + 1];
                  t += kQuadThreads) {
                 const int32_t j = q.c_col_idx[t];
-                const int64_t rank = bit_rank_q(bits, wpre, j >> 1);
-                q.q_cblk[4 * (qbase + rank) + 2 * r + (j & 1)] = t;
-                q.q_col[qbase + rank] = j >> 1;    // same value from every block of the quad
+                const int64_t rank = bit_rank_q(bits, wpre, j / G);
+                q.q_cblk[G * G * (qbase + rank) + G * r + (j % G)] = t;
+                q.q_col[qbase + rank] = j / G;     // same value from every block of the group
             }
     }
-    const int64_t ea = q.a_row_ptr[i0 + 1], eb = two ? q.a_row_ptr[i1 + 1] : 0;
     for (int64_t w0 = 0; w0 < nq; w0 += kQuadWindow) {
         const int wn = static_cast<int>(nq - w0 < kQuadWindow ? nq - w0 : kQuadWindow);
         for (int t = threadIdx.x; t < wn; t += kQuadThreads) cnt[t] = 0;
-        if (threadIdx.x == 0) {
-            s_pa = q.a_row_ptr[i0];
-            s_pb = two ? q.a_row_ptr[i1] : 0;
-        }
+        if (threadIdx.x == 0)
+            for (int r = 0; r < G; ++r) s_p[r] = r < nr ? q.a_row_ptr[i0 + r] : 0;
         __syncthreads();
         for (;;) {
             if (threadIdx.x == 0) {
-                const int32_t ka = s_pa < ea ? q.a_col_idx[s_pa] : INT_MAX;
-                const int32_t kb = s_pb < eb ? q.a_col_idx[s_pb] : INT_MAX;
-                const int32_t k = ka < kb ? ka : kb;
+                // next k of the merged rows and the A block of each row at k
+                int32_t k = INT_MAX;
+                int32_t kr[G];
+                for (int r = 0; r < G; ++r) {
+                    kr[r] = (r < nr && s_p[r] < q.a_row_ptr[i0 + r + 1]) ? q.a_col_idx[s_p[r]] : INT_MAX;
+                    k = kr[r] < k ? kr[r] : k;
+                }
                 s_k = k;
-                s_a0 = (k != INT_MAX && ka == k) ? static_cast<int32_t>(s_pa++) : -1;
-                s_a1 = (k != INT_MAX && kb == k) ? static_cast<int32_t>(s_pb++) : -1;
+                for (int r = 0; r < G; ++r)
+                    s_a[r] = (k != INT_MAX && kr[r] == k) ? static_cast<int32_t>(s_p[r]++) : -1;
             }
             __syncthreads();
             const int32_t k = s_k;
             if (k == INT_MAX) break;
-            const int32_t a0 = s_a0, a1 = s_a1;
             const int64_t tb0 = q.b_row_ptr[k], tb1 = q.b_row_ptr[k + 1];
             for (int64_t tb = tb0 + threadIdx.x; tb < tb1; tb += kQuadThreads) {
                 const int32_t j = q.b_col_idx[tb];
-                if ((j & 1) && tb > tb0 && q.b_col_idx[tb - 1] == j - 1) continue;  // partner emits
-                const int32_t Q = j >> 1;
+                const int32_t Q = j / G;
+                if (tb > tb0 && q.b_col_idx[tb - 1] / G == Q) continue;   // an earlier column emits
                 const int64_t r = bit_rank_q(bits, wpre, Q) - w0;
                 if (r < 0 || r >= wn) continue;
                 if (FILL) {
-                    int32_t b0 = -1, b1 = -1;
-                    if (j & 1) {
-                        b1 = static_cast<int32_t>(tb);
-                    } else {
-                        b0 = static_cast<int32_t>(tb);
-                        if (tb + 1 < tb1 && q.b_col_idx[tb + 1] == j + 1) b1 = static_cast<int32_t>(tb + 1);
+                    int32_t b[G];
+                    for (int c = 0; c < G; ++c) b[c] = -1;
+                    for (int64_t t = tb; t < tb1 && t < tb + G; ++t) {
+                        const int32_t jj = q.b_col_idx[t];
+                        if (jj / G != Q) break;
+                        b[jj % G] = static_cast<int32_t>(t);
                     }
                     const int64_t slot = q.e_off[qbase + w0 + r] + cnt[r];
-                    q.ent[slot] = make_int4(a0, a1, b0, b1);
+                    if (G == 2) {
+                        q.ent[slot] = make_int4(s_a[0], s_a[G - 1], b[0], b[G - 1]);
+                    } else {
+                        q.ent[2 * slot] = make_int4(s_a[0], s_a[1 % G], s_a[2 % G], s_a[3 % G]);
+                        q.ent[2 * slot + 1] = make_int4(b[0], b[1 % G], b[2 % G], b[3 % G]);
+                    }
                 }
                 cnt[r] += 1;
             }
@@ -181,21 +195,29 @@ k_quad_stack(QuadSymArgs q) {
 }
 
 int quad_pairs(const QuadSymArgs &q, int64_t *cnt, hipStream_t s) {
-    const int64_t npairs = (static_cast<int64_t>(q.r1 - q.r0) + 1) / 2;
-    if (npairs <= 0) return BSM_OK;
-    const int nwq = (((q.nbcols + 1) >> 1) + 31) >> 5;
-    k_quad_pairs<<<static_cast<unsigned>(npairs), kQuadThreads, sizeof(uint32_t) * 2 * nwq, s>>>(q, cnt);
+    const int G = q.g;
+    const int64_t ngroups = (static_cast<int64_t>(q.r1 - q.r0) + G - 1) / G;
+    if (ngroups <= 0) return BSM_OK;
+    const size_t lds = sizeof(uint32_t) * 2 * quad_words(q.nbcols, G);
+    if (G == 4) k_quad_pairs<4><<<static_cast<unsigned>(ngroups), kQuadThreads, lds, s>>>(q, cnt);
+    else k_quad_pairs<2><<<static_cast<unsigned>(ngroups), kQuadThreads, lds, s>>>(q, cnt);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }
 
 int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s) {
-    const int64_t npairs = (static_cast<int64_t>(q.r1 - q.r0) + 1) / 2;
-    if (npairs <= 0) return BSM_OK;
-    const int nwq = (((q.nbcols + 1) >> 1) + 31) >> 5;
-    const size_t lds = sizeof(uint32_t) * 2 * nwq + sizeof(int32_t) * kQuadWindow;
-    if (fill) k_quad_stack<true><<<static_cast<unsigned>(npairs), kQuadThreads, lds, s>>>(q);
-    else k_quad_stack<false><<<static_cast<unsigned>(npairs), kQuadThreads, lds, s>>>(q);
+    const int G = q.g;
+    const int64_t ngroups = (static_cast<int64_t>(q.r1 - q.r0) + G - 1) / G;
+    if (ngroups <= 0) return BSM_OK;
+    const size_t lds = sizeof(uint32_t) * 2 * quad_words(q.nbcols, G) + sizeof(int32_t) * kQuadWindow;
+    const unsigned g = static_cast<unsigned>(ngroups);
+    if (G == 4) {
+        if (fill) k_quad_stack<true, 4><<<g, kQuadThreads, lds, s>>>(q);
+        else k_quad_stack<false, 4><<<g, kQuadThreads, lds, s>>>(q);
+    } else {
+        if (fill) k_quad_stack<true, 2><<<g, kQuadThreads, lds, s>>>(q);
+        else k_quad_stack<false, 2><<<g, kQuadThreads, lds, s>>>(q);
+    }
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }

@@ -63,12 +63,14 @@ struct SmmArgs {
     int32_t pad_;
     int32_t prec;               // bsm_precision
     unsigned long long *counter;  // work counter of the persistent kernel (NULL: allocated per launch)
-    // quad kernel: 2 x 2 groups of C blocks with merged product lists
-    int64_t n_quads;
-    const int64_t *q_cblk;      // [4 n_quads] C block (r, c) of the quad at 2r + c, or -1
+    // group kernel: G x G groups of C blocks (G = 2: quads) with merged product lists
+    int64_t n_quads;            // groups
+    const int64_t *q_cblk;      // [G G n_quads] C block (r, c) of the group at G r + c, or -1
     const int64_t *q_seg;       // [n_quads + 1] entry segments
-    const int4 *q_ent;          // A(row 0), A(row 1), B(col 0), B(col 1) block indices or -1
-    const int64_t *q_order;     // quad of work item i (NULL: identity)
+    const int4 *q_ent;          // G / 2 int4 per entry: A(row 0..G-1), B(col 0..G-1) indices or -1
+    const int64_t *q_order;     // group of work item i (NULL: identity)
+    int32_t q_group;            // G: 2 or 4
+    int32_t pad2_;
 };
 
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s);
@@ -86,11 +88,13 @@ int smm_bench(int m, int n, int k, int64_t n_c, int per_c, int n_prm, const SmmP
 
 // Quad kernel (smm_quad.hip): uniform m = n = k in {5, 13, 23, 26, 32}.
 bool smm_quad_available(int m, int n, int k);
+int quad_group(int m);    // group edge G for uniform block size m (2 or 4)
 int launch_quad(const SmmArgs &a, hipStream_t s);
 
 // Reduced-precision products (smm_lowp.hip).
 int pack_lowp(const double *v, int64_t n, uint32_t *out, int prec, hipStream_t s);
 bool smm_lowp_available(int m, int n, int k);
 int smm_launch_lowp(const SmmArgs &a, hipStream_t s);
+int launch_lowp_quad(const SmmArgs &a, hipStream_t s);   // quads, uniform sizes as above
 
 }  // namespace bsm

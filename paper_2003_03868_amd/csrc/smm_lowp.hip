@@ -285,6 +285,225 @@ k_smm_f32(SmmArgs a) {
     });
 }
 
+// ------------------------------------------------------------------ quads
+// The quad scheme of the FP64 path (smm_quad.hip) with the reduced-precision
+// products above: four waves per 2 x 2 quad of C blocks; per entry k wave w
+// stages operand w (A(i_0, k), A(i_1, k), B(k, j_0), B(k, j_1); each read
+// from HBM once) into its LDS slot in the layout the MFMA reads need, and
+// computes C block (w / 2, w % 2) when the entry holds that product.  Each
+// block product is accumulated in FP32 and added into the FP64 sum of its C
+// block, in ascending k, exactly as in the one-block-per-wave kernels.
+__device__ inline int4 lp_uniform4(int4 v) {
+    return make_int4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
+                     __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
+}
+
+template <int S, bool BF>
+__global__ void __launch_bounds__(256)
+k_lowp_quad(SmmArgs a) {
+    constexpr int B2 = S * S;
+    constexpr int NV = (B2 + kWave - 1) / kWave;
+    constexpr int LDK = 40, PLANE = 32 * LDK;           // split-BF16: [32][LDK] planes
+    constexpr int LDA = 33, LDB = 32, KP = 4 * ((S + 3) / 4);
+    constexpr int FA = 32 * LDA, FB = KP * LDB;          // FP32: A [32][LDA], B [KP][LDB]
+    constexpr int BYTES = BF ? 8 * PLANE * 2 : (2 * FA + 2 * FB) * 4;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[BYTES];
+    __shared__ int4 ebuf[2][64];
+    unsigned short *us = reinterpret_cast<unsigned short *>(smem);
+    float *fs = reinterpret_cast<float *>(smem);
+
+    const int64_t per = (a.n_quads + kXcds - 1) / kXcds;
+    const int64_t it = static_cast<int64_t>(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    if (it >= a.n_quads) return;
+    const int64_t item = a.q_order ? a.q_order[it] : it;
+    const int lane = threadIdx.x % kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
+    const int rr = wv >> 1, cc = wv & 1;                // this wave's C block (rr, cc)
+
+    for (int e = threadIdx.x; e < BYTES / 4; e += 256) reinterpret_cast<uint32_t *>(smem)[e] = 0u;
+    // LDS position of element lane + 64 v of this wave's operand (-1: none)
+    int off[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int e = lane + v * kWave;
+        int o = -1;
+        if (e < B2) {
+            const int i = e / S, j = e % S;            // row, column of the stored block
+            if (BF) o = (wv < 2) ? i * LDK + j : j * LDK + i;
+            else o = (wv < 2) ? wv * FA + i * LDA + j : 2 * FA + (wv - 2) * FB + i * LDB + j;
+        }
+        off[v] = o;
+    }
+
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+
+    constexpr int kEntryChunk = 64;
+    const int64_t e0 = a.q_seg[item], ne = a.q_seg[item + 1] - e0;
+    const int4 none = make_int4(-1, -1, -1, -1);
+    auto pick = [](const int4 v, int z) { return z == 0 ? v.x : z == 1 ? v.y : z == 2 ? v.z : v.w; };
+    uint32_t pv[NV];
+    auto load_block = [&](const int4 en) {
+        const int id = pick(en, wv);
+        if (id >= 0) {
+            const uint32_t *g = (wv < 2 ? a.a_pk : a.b_pk) + static_cast<int64_t>(id) * B2;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < NV - 1 || lane + v * kWave < B2) pv[v] = g[lane + v * kWave];
+        }
+    };
+    int4 creg = none;
+    if (wv == 0) {
+        if (lane < ne) ebuf[0][lane] = a.q_ent[e0 + lane];
+        if (kEntryChunk + lane < ne) creg = a.q_ent[e0 + kEntryChunk + lane];
+    }
+    __syncthreads();
+    int4 nxt = none;
+    if (ne > 0) {
+        nxt = lp_uniform4(ebuf[0][0]);
+        load_block(nxt);
+    }
+    const int r32 = lane & 31, h = lane >> 5, r16 = lane & 15, kq = lane >> 4;
+    for (int64_t t = 0; t < ne; ++t) {
+        const int4 cur = nxt;
+        if (pick(cur, wv) >= 0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (off[v] >= 0) {
+                    if (BF) {
+                        const int plane = 2 * wv;
+                        us[plane * PLANE + off[v]] = static_cast<unsigned short>(pv[v] >> 16);
+                        us[(plane + 1) * PLANE + off[v]] = static_cast<unsigned short>(pv[v] & 0xFFFFu);
+                    } else {
+                        fs[off[v]] = __uint_as_float(pv[v]);
+                    }
+                }
+        }
+        const int64_t t1 = t + 1;
+        if ((t1 % kEntryChunk) == 0 && t1 < ne && wv == 0) {
+            ebuf[(t1 / kEntryChunk) & 1][lane] = creg;
+            if (t1 + kEntryChunk + lane < ne) creg = a.q_ent[e0 + t1 + kEntryChunk + lane];
+        }
+        __syncthreads();
+        if (t1 < ne) {
+            nxt = lp_uniform4(ebuf[(t1 / kEntryChunk) & 1][t1 % kEntryChunk]);
+            load_block(nxt);
+        }
+        if (pick(cur, rr) >= 0 && pick(cur, 2 + cc) >= 0) {
+            if (BF) {
+                const unsigned short *ahi = us + (2 * rr) * PLANE, *alo = ahi + PLANE;
+                const unsigned short *bhi = us + (2 * (2 + cc)) * PLANE, *blo = bhi + PLANE;
+                constexpr int KS = (S + 15) / 16;
+                f16v part = {};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const int o = r32 * LDK + 16 * ks + 8 * h;
+                    const bf8 vah = __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(ahi + o));
+                    const bf8 val = __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(alo + o));
+                    const bf8 vbh = __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(bhi + o));
+                    const bf8 vbl = __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(blo + o));
+                    part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(val, vbh, part, 0, 0, 0);
+                    part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbl, part, 0, 0, 0);
+                    part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbh, part, 0, 0, 0);
+                }
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[q] += static_cast<double>(part[q]);
+            } else {
+                const float *sA = fs + rr * FA, *sB = fs + 2 * FA + cc * FB;
+                constexpr int MT = (S + 15) / 16;
+                f4 part[2][2] = {};
+#pragma unroll
+                for (int ks = 0; ks < KP / 4; ++ks) {
+                    float av[2], bv[2];
+#pragma unroll
+                    for (int tt = 0; tt < MT; ++tt) av[tt] = sA[(16 * tt + r16) * LDA + 4 * ks + kq];
+#pragma unroll
+                    for (int u = 0; u < MT; ++u) bv[u] = sB[(4 * ks + kq) * LDB + 16 * u + r16];
+#pragma unroll
+                    for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+                        for (int u = 0; u < MT; ++u)
+                            part[tt][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tt], bv[u],
+                                                                              part[tt][u], 0, 0, 0);
+                }
+#pragma unroll
+                for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            acc[(tt * 2 + u) * 4 + q] += static_cast<double>(part[tt][u][q]);
+            }
+        }
+        __syncthreads();
+    }
+
+    // epilogue: this wave's C block
+    const int64_t cb = a.q_cblk[4 * item + 2 * rr + cc];
+    if (cb < 0) return;
+    const int64_t co = a.c_blk_off[cb];
+    const double *cin = nullptr;
+    if (a.cin_map) {
+        const int64_t tt = a.cin_map[cb];
+        if (tt >= 0) cin = a.cin_vals + a.cin_blk_off[tt];
+    }
+    double sq = 0.0, mx = 0.0;
+    constexpr int MT = (S + 15) / 16;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        int row, col;
+        if (BF) {
+            row = 8 * (q >> 2) + 4 * h + (q & 3);
+            col = r32;
+        } else {
+            const int tile = q >> 2, tt = tile >> 1, u = tile & 1;
+            row = 16 * tt + 4 * kq + (q & 3);
+            col = 16 * u + r16;
+            if (tt >= MT || u >= MT) row = 1 << 20;
+        }
+        if (row < S && col < S) {
+            double v = a.alpha * acc[q];
+            if (cin) v += a.beta * cin[row * S + col];
+            a.c_vals[co + row * S + col] = v;
+            sq += v * v;
+            mx = fmax(mx, fabs(v));
+        }
+    }
+    sq = lp_wave_sum(sq);
+    mx = lp_wave_max(mx);
+    if (lane == 0) {
+        a.sq_out[cb] = sq;
+        a.mx_out[cb] = mx;
+        if (!isfinite(sq)) atomicOr(a.flags, kFlagNonFinite);
+    }
+}
+
+int launch_lowp_quad(const SmmArgs &a, hipStream_t s) {
+    if (a.n_quads <= 0) return BSM_OK;
+    const int64_t per = (a.n_quads + kXcds - 1) / kXcds;
+    const int64_t grid = per * kXcds;
+    if (grid > (1ll << 31) - 1) { set_error("too many quads in one launch"); return BSM_EINVAL; }
+    const unsigned g = static_cast<unsigned>(grid);
+    const bool bf = a.prec == BSM_SPLIT_BF16;
+#define BSM_LQ(SZ)                                                            \
+    case SZ:                                                                  \
+        if (bf) k_lowp_quad<SZ, true><<<g, 256, 0, s>>>(a);                   \
+        else k_lowp_quad<SZ, false><<<g, 256, 0, s>>>(a);                     \
+        break;
+    switch (a.uni_m) {
+        BSM_LQ(5)
+        BSM_LQ(13)
+        BSM_LQ(23)
+        BSM_LQ(26)
+        BSM_LQ(32)
+        default: set_error("no reduced-precision quad kernel for block size %d", a.uni_m); return BSM_EINVAL;
+    }
+#undef BSM_LQ
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
 bool smm_lowp_available(int m, int n, int k) {
     return (m == n && n == k) && (m == 5 || m == 13 || m == 23 || m == 26 || m == 32);
 }

@@ -1,21 +1,24 @@
-// FP64 block products for uniform block sizes, one workgroup per quad of C
-// blocks (2 x 2 group with a merged product list, built in quad.hip).
+// FP64 block products for uniform block sizes, one workgroup per G x G group
+// of C blocks (G = 2: quads; G = 4: groups of sixteen) with a merged product
+// list (built in quad.hip).
 //
-// Per entry k the workgroup stages the (up to) four operand blocks
-// A(i_0, k), A(i_1, k), B(k, j_0), B(k, j_1) in LDS exactly as they sit in HBM,
-// each read from HBM once, and multiplies every product (r, c) the entry
-// holds; each C block's sum runs over its own products in ascending k exactly
-// as in the one-block-per-wave kernels, with the same instructions, so the
-// results are the same bits.  Instruction and lane roles are those of the
+// Per entry k the workgroup stages the (up to) 2 G operand blocks
+// A(i_r, k), B(k, j_c) in LDS exactly as they sit in HBM, each read from HBM
+// once, and multiplies every product (r, c) the entry holds; each C block's
+// sum runs over its own products in ascending k exactly as in the
+// one-block-per-wave kernels, with the same instructions, so the results are
+// the same bits.  Instruction and lane roles are those of the
 // compile-time-shape kernel (V_MFMA_F64_4X4X4_4B_F64; lane = 16 x + 4 b + y,
 // block b = 2 bh + bw owns the 4 x 4 tiles of row half bh and column half
-// bw).  With W waves per quad, a wave computes 4 / W of the C blocks and
-// stages 4 / W of the operand blocks (W = 4: one each, the fastest form on
-// the sign workload; W = 1: one wave reads each A value once for two column
-// blocks and each B value once for two row blocks).  Operands of the next
-// entry are prefetched into registers; entry indices are staged through LDS
-// in chunks, so no load waits on another load of the same iteration.
+// bw).  With W waves per group, a wave computes G G / W of the C blocks (an
+// NR x NC patch) and stages operands wv, wv + W, ... (quads: W = 4, one
+// each, the fastest form on the sign workload; W = 1: one wave reads each A
+// value once for two column blocks and each B value once for two row
+// blocks).  Operands of the next entry are prefetched into registers; entry
+// indices are staged through LDS in chunks, so no load waits on another load
+// of the same iteration.
 #include <cstdlib>
+#include <type_traits>
 
 #include "smm.h"
 
@@ -29,7 +32,6 @@ struct QShape {
     static constexpr int MT = (S + 3) / 4, KS = MT, H = (MT + 1) / 2;
     static constexpr int KLAST = S - 4 * (KS - 1);   // valid x in the last k-step
     static constexpr int TAIL = 12 * S + 8;          // covers padded reads past the last block
-    static constexpr int SIZE = 4 * B2 + TAIL;
     static constexpr int NV = (B2 + kWave - 1) / kWave;
 };
 
@@ -55,10 +57,10 @@ __device__ inline double q_wave_max(double v) {
 }
 
 // One entry's products of the wave: product (r, c) (rows [R0, R0 + NR),
-// columns [C0, C0 + NC) of the quad) is done when bit NC r + c of PM is set.
+// columns [C0, C0 + NC) of the group) is done when bit NC r + c of PM is set.
 // PM is a compile-time constant, so the k loop holds no tests; A rows and B
 // columns no product uses are not read.
-template <int S, int NR, int NC, unsigned PM>
+template <int S, int G, int NR, int NC, unsigned PM>
 __device__ inline void quad_step(const double *sm, int R0, int C0, int ra0, int rb0,
                                  bool klast_ok,
                                  double (&acc)[NR * NC][QShape<S>::H][QShape<S>::H]) {
@@ -66,6 +68,7 @@ __device__ inline void quad_step(const double *sm, int R0, int C0, int ra0, int 
     constexpr int H = Q::H;
 #pragma unroll
     for (int ks = 0; ks < Q::KS; ++ks) {
+        if (G == 4) __builtin_amdgcn_sched_barrier(0);
         double av[NR][H], bv[NC][H];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -86,7 +89,7 @@ __device__ inline void quad_step(const double *sm, int R0, int C0, int ra0, int 
             if (PM & colbits) {
 #pragma unroll
                 for (int u = 0; u < H; ++u) {
-                    const double v = sm[(2 + C0 + c) * Q::B2 + rb0 + 4 * u + 4 * ks * S];
+                    const double v = sm[(G + C0 + c) * Q::B2 + rb0 + 4 * u + 4 * ks * S];
                     bv[c][u] = (ks == Q::KS - 1 && Q::KLAST < 4 && !klast_ok) ? 0.0 : v;
                 }
             }
@@ -108,7 +111,7 @@ __device__ inline void quad_step(const double *sm, int R0, int C0, int ra0, int 
 
 // The wave's products of an entry with operand flags hm (bit z: operand z
 // present): dispatch on the wave's product mask to a compile-time variant.
-template <int S, int NR, int NC>
+template <int S, int G, int NR, int NC>
 __device__ inline void quad_entry(const double *sm, int R0, int C0, int ra0, int rb0,
                                   bool klast_ok, unsigned hm,
                                   double (&acc)[NR * NC][QShape<S>::H][QShape<S>::H]) {
@@ -117,11 +120,11 @@ __device__ inline void quad_entry(const double *sm, int R0, int C0, int ra0, int
     for (int r = 0; r < NR; ++r)
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (((hm >> (R0 + r)) & 1u) && ((hm >> (2 + C0 + c)) & 1u)) pm |= 1u << (NC * r + c);
+            if (((hm >> (R0 + r)) & 1u) && ((hm >> (G + C0 + c)) & 1u)) pm |= 1u << (NC * r + c);
 #define BSM_QS(M) \
-    case M: quad_step<S, NR, NC, (M)>(sm, R0, C0, ra0, rb0, klast_ok, acc); break;
+    case M: quad_step<S, G, NR, NC, (M)>(sm, R0, C0, ra0, rb0, klast_ok, acc); break;
     if (NR * NC == 1) {
-        if (pm) quad_step<S, NR, NC, 1u>(sm, R0, C0, ra0, rb0, klast_ok, acc);
+        if (pm) quad_step<S, G, NR, NC, 1u>(sm, R0, C0, ra0, rb0, klast_ok, acc);
     } else if (NR * NC == 2) {
         switch (pm) { BSM_QS(1u) BSM_QS(2u) BSM_QS(3u) default: break; }
     } else {
@@ -135,9 +138,9 @@ __device__ inline void quad_entry(const double *sm, int R0, int C0, int ra0, int
 #undef BSM_QS
 }
 
-// alpha * sum + beta * C_in for the wave's C blocks of quad `item`, with the
+// alpha * sum + beta * C_in for the wave's C blocks of group `item`, with the
 // blocks' filter norms.
-template <int S, int NR, int NC>
+template <int S, int G, int NR, int NC>
 __device__ inline void quad_store(const SmmArgs &a, int64_t item, int R0, int C0, int lane,
                                   const double (&acc)[NR * NC][QShape<S>::H][QShape<S>::H]) {
     constexpr int H = QShape<S>::H;
@@ -145,7 +148,7 @@ __device__ inline void quad_store(const SmmArgs &a, int64_t item, int R0, int C0
     const int bh = blk >> 1, bw = blk & 1;
 #pragma unroll
     for (int zc = 0; zc < NR * NC; ++zc) {
-        const int64_t c = a.q_cblk[4 * item + 2 * (R0 + zc / NC) + C0 + zc % NC];
+        const int64_t c = a.q_cblk[G * G * item + G * (R0 + zc / NC) + C0 + zc % NC];
         if (c < 0) continue;
         const int64_t co = a.c_blk_off[c];
         const double *cin = nullptr;
@@ -177,32 +180,57 @@ __device__ inline void quad_store(const SmmArgs &a, int64_t item, int R0, int C0
     }
 }
 
-// W wavefronts per quad: W = 1, the wave computes all four C blocks; W = 2,
-// wave w computes the two C blocks of row w and stages A(i_w, k), B(k, j_w);
-// W = 4, wave w computes C block (w / 2, w % 2) and stages operand w.
+// W wavefronts per group.  Quads: W = 1, the wave computes all four C
+// blocks; W = 2, wave w computes the two C blocks of row w and stages
+// A(i_w, k), B(k, j_w); W = 4, wave w computes C block (w / 2, w % 2) and
+// stages operand w.  Groups of sixteen: W = 16, wave w computes C block
+// (w / 4, w % 4), and waves w and w + 8 stage the two halves of operand
+// w % 8 (with eight waves, two C blocks each, the register demand spills).
 // WPE: the occupancy (waves per SIMD) the register allocation aims for.
-template <int S, int W, int WPE, int EPS>
+template <int S, int G, int W, int WPE, int EPS>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_smm_f64_quad(SmmArgs a) {
     using Q = QShape<S>;
     constexpr int H = Q::H;
-    constexpr int NR = (W == 1) ? 2 : 1;        // quad rows per wave
-    constexpr int NC = (W == 4) ? 1 : 2;        // quad columns per wave
-    constexpr int NZ = 4 / W;                   // operand blocks staged per wave
-    constexpr int SLOT = 4 * Q::B2;             // LDS doubles of one staged entry
+    constexpr int NPW = G * G / W;              // C blocks per wave
+    constexpr int NC = NPW < G ? NPW : G;       // group columns per wave
+    constexpr int NR = NPW / NC;                // group rows per wave
+    constexpr int NOP = 2 * G;                  // operand blocks per entry
+    constexpr int WPO = W > NOP ? W / NOP : 1;  // waves sharing the staging of one block
+    constexpr int NZ = W > NOP ? 1 : NOP / W;   // operand blocks (or parts) staged per wave
+    constexpr int NVP = (Q::NV + WPO - 1) / WPO;  // register slots of one staged part
+    constexpr int NE = G / 2;                   // int4 per entry
+    constexpr int SLOT = NOP * Q::B2;           // LDS doubles of one staged entry
+    static_assert(G == 2 || G == 4, "group edge 2 or 4");
+    static_assert(NR * NC * W == G * G, "waves must tile the group");
     __shared__ double sm[EPS * SLOT + Q::TAIL];
     const int64_t it = quad_item(a.n_quads);
     if (it >= a.n_quads) return;
     const int64_t item = a.q_order ? a.q_order[it] : it;
     const int lane = threadIdx.x % kWave;
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));  // wave-uniform
-    const int R0 = (W == 1) ? 0 : (W == 2 ? wv : wv >> 1);
-    const int C0 = (W == 4) ? (wv & 1) : 0;
+    const int R0 = (wv / (G / NC)) * NR;
+    const int C0 = (wv % (G / NC)) * NC;
     const int x = lane >> 4, blk = (lane >> 2) & 3, y = lane & 3;
     const int bh = blk >> 1, bw = blk & 1;
-    // staged block zz of this wave is quad operand zid(zz): A rows 0, 1 then B columns 0, 1
-    auto zid = [&](int zz) { return (W == 1) ? zz : (W == 4 ? wv : (zz == 0 ? wv : 2 + wv)); };
-    auto pick = [](const int4 v, int z) { return z == 0 ? v.x : z == 1 ? v.y : z == 2 ? v.z : v.w; };
+    // staged block zz of this wave is entry operand wv + W zz (A rows 0 .. G-1,
+    // then B columns); with more waves than operands, wave wv stages part
+    // wv / NOP (slots [part NVP, part NVP + NVP)) of operand wv % NOP
+    static_assert(WPO <= 2, "a block is staged by one or two waves");
+    auto zid = [&](int zz) { return W > NOP ? wv % NOP : wv + W * zz; };
+    const int part = W > NOP ? wv / NOP : 0;
+    // element lane + 64 (P NVP + v) of a block exists (compile-time but for the last slot)
+    auto has = [&](auto P, int v) {
+        constexpr int p0 = decltype(P)::value * NVP;
+        return p0 + v < Q::NV - 1 || (p0 + v == Q::NV - 1 && lane + (p0 + v) * kWave < Q::B2);
+    };
+    using P0 = std::integral_constant<int, 0>;
+    using P1 = std::integral_constant<int, 1>;
+    auto pick = [](const int4 (&v)[NE], int z) {
+        const int4 e = (z < 4) ? v[0] : v[NE - 1];   // selects, not a run-time array index
+        const int c = z & 3;
+        return c == 0 ? e.x : c == 1 ? e.y : c == 2 ? e.z : e.w;
+    };
 
     for (int e = EPS * SLOT + static_cast<int>(threadIdx.x); e < EPS * SLOT + Q::TAIL; e += 64 * W)
         sm[e] = 0.0;
@@ -225,37 +253,56 @@ k_smm_f64_quad(SmmArgs a) {
     // waits on another global load issued in the same iteration.
     constexpr int kEntryChunk = 64;
     static_assert(kEntryChunk % EPS == 0, "stages must not straddle index chunks");
-    __shared__ int4 ebuf[2][kEntryChunk];
+    __shared__ int4 ebuf[2][kEntryChunk][NE];
     const int64_t e0 = a.q_seg[item], ne = a.q_seg[item + 1] - e0;
-    const int4 none = make_int4(-1, -1, -1, -1);
-    double pv[EPS][NZ][Q::NV];
-    auto load_blocks = [&](const int4 en, double (&p)[NZ][Q::NV]) {
+    double pv[EPS][NZ][NVP];
+    auto load_blocks = [&](const int4 (&en)[NE], double (&p)[NZ][NVP]) {
 #pragma unroll
         for (int zz = 0; zz < NZ; ++zz) {
             const int z = zid(zz);
             const int id = pick(en, z);
             if (id >= 0) {
-                const double *g = (z < 2 ? a.a_vals : a.b_vals) + static_cast<int64_t>(id) * Q::B2;
+                const double *g = (z < G ? a.a_vals : a.b_vals) + static_cast<int64_t>(id) * Q::B2;
+                auto ld = [&](auto P) {
+                    constexpr int p0 = decltype(P)::value * NVP;
 #pragma unroll
-                for (int q = 0; q < Q::NV; ++q)
-                    if (q < Q::NV - 1 || lane + q * kWave < Q::B2) p[zz][q] = g[lane + q * kWave];
+                    for (int q = 0; q < NVP; ++q)
+                        if (has(P, q)) p[zz][q] = g[lane + (p0 + q) * kWave];
+                };
+                if (WPO == 1 || part == 0) ld(P0{}); else ld(P1{});
             }
         }
     };
-    auto flags = [](const int4 c) {
-        return (c.x >= 0 ? 1u : 0u) | (c.y >= 0 ? 2u : 0u) | (c.z >= 0 ? 4u : 0u) |
-               (c.w >= 0 ? 8u : 0u);
+    auto flags = [](const int4 (&c)[NE]) {
+        unsigned f = 0;
+#pragma unroll
+        for (int h = 0; h < NE; ++h)
+            f |= ((c[h].x >= 0 ? 1u : 0u) | (c[h].y >= 0 ? 2u : 0u) | (c[h].z >= 0 ? 4u : 0u) |
+                  (c[h].w >= 0 ? 8u : 0u)) << (4 * h);
+        // quads: bits 0, 1 = A rows, 2, 3 = B columns; sixteen: 0..3 A, 4..7 B
+        return f;
     };
-    int4 creg = none;                          // wave 0: entry e0 + 64 c + lane of the next chunk
+    auto fetch = [&](int64_t t, int4 (&out)[NE]) {
+#pragma unroll
+        for (int h = 0; h < NE; ++h)
+            out[h] = (t < ne) ? uniform4(ebuf[(t / kEntryChunk) & 1][t % kEntryChunk][h])
+                              : make_int4(-1, -1, -1, -1);
+    };
+    int4 creg[NE];                             // wave 0: entry e0 + 64 c + lane of the next chunk
+#pragma unroll
+    for (int h = 0; h < NE; ++h) creg[h] = make_int4(-1, -1, -1, -1);
     if (wv == 0) {
-        if (lane < ne) ebuf[0][lane] = a.q_ent[e0 + lane];
-        if (kEntryChunk + lane < ne) creg = a.q_ent[e0 + kEntryChunk + lane];
+#pragma unroll
+        for (int h = 0; h < NE; ++h) {
+            if (lane < ne) ebuf[0][lane][h] = a.q_ent[NE * (e0 + lane) + h];
+            if (kEntryChunk + lane < ne) creg[h] = a.q_ent[NE * (e0 + kEntryChunk + lane) + h];
+        }
     }
     __syncthreads();
-    int4 nxt[EPS];
+    int4 nxt[EPS][NE];
 #pragma unroll
     for (int q = 0; q < EPS; ++q) {
-        nxt[q] = q < ne ? uniform4(ebuf[0][q]) : none;
+        fetch(q, nxt[q]);
         load_blocks(nxt[q], pv[q]);
     }
     for (int64_t t = 0; t < ne; t += EPS) {
@@ -267,10 +314,13 @@ k_smm_f64_quad(SmmArgs a) {
             for (int zz = 0; zz < NZ; ++zz) {
                 const int z = zid(zz);
                 if ((hm[q] >> z) & 1u) {
+                    auto st = [&](auto P) {
+                        constexpr int p0 = decltype(P)::value * NVP;
 #pragma unroll
-                    for (int v = 0; v < Q::NV; ++v)
-                        if (v < Q::NV - 1 || lane + v * kWave < Q::B2)
-                            sm[q * SLOT + z * Q::B2 + lane + v * kWave] = pv[q][zz][v];
+                        for (int v = 0; v < NVP; ++v)
+                            if (has(P, v)) sm[q * SLOT + z * Q::B2 + lane + (p0 + v) * kWave] = pv[q][zz][v];
+                    };
+                    if (WPO == 1 || part == 0) st(P0{}); else st(P1{});
                 }
             }
         }
@@ -278,35 +328,38 @@ k_smm_f64_quad(SmmArgs a) {
         if ((t1 % kEntryChunk) == 0 && t1 < ne && wv == 0) {
             // entering chunk t1 / 64: its indices (loaded a chunk ago) go to
             // LDS, the chunk after it is fetched into registers
-            ebuf[(t1 / kEntryChunk) & 1][lane] = creg;
-            if (t1 + kEntryChunk + lane < ne) creg = a.q_ent[e0 + t1 + kEntryChunk + lane];
+#pragma unroll
+            for (int h = 0; h < NE; ++h) {
+                ebuf[(t1 / kEntryChunk) & 1][lane][h] = creg[h];
+                if (t1 + kEntryChunk + lane < ne) creg[h] = a.q_ent[NE * (e0 + t1 + kEntryChunk + lane) + h];
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < EPS; ++q) {
-            nxt[q] = (t1 + q < ne) ? uniform4(ebuf[((t1 + q) / kEntryChunk) & 1][(t1 + q) % kEntryChunk])
-                                   : none;
+            fetch(t1 + q, nxt[q]);
             load_blocks(nxt[q], pv[q]);
         }
 #pragma unroll
         for (int q = 0; q < EPS; ++q)
-            quad_entry<S, NR, NC>(sm + q * SLOT, R0, C0, ra0, rb0, klast_ok, hm[q], acc);
+            quad_entry<S, G, NR, NC>(sm + q * SLOT, R0, C0, ra0, rb0, klast_ok, hm[q], acc);
         __syncthreads();
     }
 
-    quad_store<S, NR, NC>(a, item, R0, C0, lane, acc);
+    quad_store<S, G, NR, NC>(a, item, R0, C0, lane, acc);
 }
 
 }  // namespace
 
-// Wavefronts per quad (1, 2 or 4; measured best: 4); BSM_QUAD_WAVES overrides it.
+// Wavefronts per quad (1, 2 or 4, measured best 4; groups of sixteen always
+// use 16); BSM_QUAD_WAVES overrides the default.
 static int quad_waves() {
     const char *e = getenv("BSM_QUAD_WAVES");
     const int w = e ? atoi(e) : 4;
     return (w == 1 || w == 2) ? w : 4;
 }
 
-// Entries staged per barrier pair (1 or 2); BSM_QUAD_STAGE overrides the default.
+// Entries staged per barrier pair (1 or 2, quads only); BSM_QUAD_STAGE overrides the default.
 static int quad_stage() {
     const char *e = getenv("BSM_QUAD_STAGE");
     return (e && atoi(e) == 2) ? 2 : 1;
@@ -316,7 +369,14 @@ bool smm_quad_available(int m, int n, int k) {
     return m == n && n == k && (m == 5 || m == 13 || m == 23 || m == 26 || m == 32);
 }
 
+int quad_group(int m) {
+    const char *e = getenv("BSM_QUAD_GROUP");
+    const int g = e ? atoi(e) : 2;
+    return (g == 4 && m != 5) ? 4 : 2;
+}
+
 int launch_quad(const SmmArgs &a, hipStream_t s) {
+    if (a.prec != BSM_FP64) return launch_lowp_quad(a, s);
     if (a.n_quads <= 0) return BSM_OK;
     const int64_t per = (a.n_quads + kXcds - 1) / kXcds;
     const int64_t grid = per * kXcds;
@@ -326,21 +386,33 @@ int launch_quad(const SmmArgs &a, hipStream_t s) {
     }
     const unsigned g = static_cast<unsigned>(grid);
     const int w = quad_waves(), eps = quad_stage();
+    if (a.q_group == 4) {
+        switch (a.uni_m) {
+            case 13: k_smm_f64_quad<13, 4, 16, 8, 1><<<g, 1024, 0, s>>>(a); break;
+            case 23: k_smm_f64_quad<23, 4, 16, 8, 1><<<g, 1024, 0, s>>>(a); break;
+            case 26: k_smm_f64_quad<26, 4, 16, 4, 1><<<g, 1024, 0, s>>>(a); break;
+            case 32: k_smm_f64_quad<32, 4, 16, 4, 1><<<g, 1024, 0, s>>>(a); break;
+            default: set_error("no group-of-sixteen kernel for block size %d", a.uni_m); return BSM_EINVAL;
+        }
+        BSM_HIP(hipGetLastError());
+        return BSM_OK;
+    }
+    if (a.q_group != 2) { set_error("internal: group edge %d", a.q_group); return BSM_EINVAL; }
     switch (a.uni_m) {
-        case 5: k_smm_f64_quad<5, 1, 8, 1><<<g, 64, 0, s>>>(a); break;
+        case 5: k_smm_f64_quad<5, 2, 1, 8, 1><<<g, 64, 0, s>>>(a); break;
         case 13:
-            if (w == 4) k_smm_f64_quad<13, 4, 6, 1><<<g, 256, 0, s>>>(a);
-            else if (w == 2) k_smm_f64_quad<13, 2, 4, 1><<<g, 128, 0, s>>>(a);
-            else k_smm_f64_quad<13, 1, 4, 1><<<g, 64, 0, s>>>(a);
+            if (w == 4) k_smm_f64_quad<13, 2, 4, 6, 1><<<g, 256, 0, s>>>(a);
+            else if (w == 2) k_smm_f64_quad<13, 2, 2, 4, 1><<<g, 128, 0, s>>>(a);
+            else k_smm_f64_quad<13, 2, 1, 4, 1><<<g, 64, 0, s>>>(a);
             break;
         case 23:
-            if (w == 4 && eps == 2) k_smm_f64_quad<23, 4, 4, 2><<<g, 256, 0, s>>>(a);
-            else if (w == 4) k_smm_f64_quad<23, 4, 5, 1><<<g, 256, 0, s>>>(a);
-            else if (w == 2) k_smm_f64_quad<23, 2, 3, 1><<<g, 128, 0, s>>>(a);
-            else k_smm_f64_quad<23, 1, 1, 1><<<g, 64, 0, s>>>(a);
+            if (w == 4 && eps == 2) k_smm_f64_quad<23, 2, 4, 4, 2><<<g, 256, 0, s>>>(a);
+            else if (w == 4) k_smm_f64_quad<23, 2, 4, 5, 1><<<g, 256, 0, s>>>(a);
+            else if (w == 2) k_smm_f64_quad<23, 2, 2, 3, 1><<<g, 128, 0, s>>>(a);
+            else k_smm_f64_quad<23, 2, 1, 1, 1><<<g, 64, 0, s>>>(a);
             break;
-        case 26: k_smm_f64_quad<26, 4, 4, 1><<<g, 256, 0, s>>>(a); break;
-        case 32: k_smm_f64_quad<32, 4, 4, 1><<<g, 256, 0, s>>>(a); break;
+        case 26: k_smm_f64_quad<26, 2, 4, 4, 1><<<g, 256, 0, s>>>(a); break;
+        case 32: k_smm_f64_quad<32, 2, 4, 4, 1><<<g, 256, 0, s>>>(a); break;
         default: set_error("no quad kernel for block size %d", a.uni_m); return BSM_EINVAL;
     }
     BSM_HIP(hipGetLastError());

@@ -41,14 +41,16 @@ int sort_worklist(const int64_t *wl_in, int64_t *wl_out, int64_t c0, int64_t n, 
                   const int32_t *c_row, const int32_t *c_col, const int32_t *rbs,
                   const int32_t *cbs, const int64_t *seg, int64_t *hist_host, hipStream_t s);
 
-// Quads of C blocks and their merged entry lists, straight from the
-// patterns of A, B and the unfiltered C (quad.hip), over the row pairs of
-// block rows [r0, r1) (r0 even).  quad_pairs: cnt[pair] = quads of the pair.
-// quad_stack count pass (fill = false), with q_off = scanned quad counts:
-// q_cblk[4 q + 2 r + c] = C block (2R + r, 2Q + c) or -1, q_col[q] = Q and
-// e_off[q] = entries of quad q; fill pass: ent[e_off[q] + n] in ascending k.
+// G x G groups of C blocks (G = 2: quads) and their merged entry lists,
+// straight from the patterns of A, B and the unfiltered C (quad.hip), over
+// the row groups of block rows [r0, r1) (r0 a multiple of G).  quad_pairs:
+// cnt[R] = groups of row group R.  quad_stack count pass (fill = false),
+// with q_off = scanned group counts: q_cblk[G G q + G r + c] = C block
+// (G R + r, G Q + c) or -1, q_col[q] = Q and e_off[q] = entries of group q;
+// fill pass: entry n of group q at ent[(G / 2) (e_off[q] + n)], ascending k.
 struct QuadSymArgs {
     int32_t r0, r1, nbcols;
+    int32_t g;                   // group edge: 2 (quads) or 4
     const int64_t *a_row_ptr;
     const int32_t *a_col_idx;
     const int64_t *b_row_ptr;
@@ -57,9 +59,9 @@ struct QuadSymArgs {
     const int32_t *c_col_idx;
     const int64_t *q_off;
     int64_t *q_cblk;
-    int32_t *q_col;              // column pair Q of every quad (count pass)
+    int32_t *q_col;              // column group Q of every group (count pass)
     int64_t *e_off;
-    int4 *ent;
+    int4 *ent;                   // G / 2 int4 per entry
 };
 int quad_pairs(const QuadSymArgs &q, int64_t *cnt, hipStream_t s);
 int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s);

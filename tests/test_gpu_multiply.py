@@ -226,16 +226,19 @@ def test_multiply_kernel_variants(orc, monkeypatch, variant, maxb):
         assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"variant {variant} maxb {maxb}")
 
 
-@pytest.mark.parametrize("waves,stage", [("1", "1"), ("2", "1"), ("4", "1"), ("4", "2")])
+@pytest.mark.parametrize("group,waves,stage", [("2", "1", "1"), ("2", "2", "1"), ("2", "4", "1"),
+                                                ("2", "4", "2"), ("4", "16", "1")])
 @pytest.mark.parametrize("b", [5, 13, 23, 26, 32])
-def test_quad_kernel_vs_oracle_and_fixed(orc, monkeypatch, waves, stage, b):
-    """The quad kernel (one, two or four waves per 2 x 2 group of C blocks,
-    merged product lists, one or two entries staged per step) against the
-    oracle -- odd block-row and column counts give
-    partial quads, C_in adds blocks without products, a tiny chunk size and
-    an odd band height give many chunks -- and bit for bit against the
-    one-C-block-per-wave compile-time-shape kernel, which sums the same
-    products in the same order with the same instructions."""
+def test_quad_kernel_vs_oracle_and_fixed(orc, monkeypatch, group, waves, stage, b):
+    """The group kernel (2 x 2 quads with one, two or four waves, one or two
+    entries staged per step; 4 x 4 groups with sixteen waves; merged
+    product lists) against the oracle -- block-row and column counts that
+    are not multiples of the group edge give partial groups, C_in adds
+    blocks without products, a tiny chunk size and an odd band height give
+    many chunks -- and bit for bit against the one-C-block-per-wave
+    compile-time-shape kernel, which sums the same products in the same
+    order with the same instructions."""
+    monkeypatch.setenv("BSM_QUAD_GROUP", group)
     monkeypatch.setenv("BSM_QUAD_WAVES", waves)
     monkeypatch.setenv("BSM_QUAD_STAGE", stage)
     rng = np.random.default_rng(500 + b)

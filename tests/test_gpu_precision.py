@@ -43,6 +43,51 @@ def test_lowp_multiply_error_bound(orc, prec, b):
     assert err > 0.0          # really ran in reduced precision
 
 
+def _lowp_run(prec, alpha, a, bm, beta, c):
+    from paper_2003_03868_amd import bsm
+    da, db = to_dev(a), to_dev(bm)
+    dc = to_dev(c) if c is not None else bsm.Matrix.empty_like(a.row_blk_size, bm.col_blk_size)
+    st = bsm.bsm_multiply(alpha, da.handle, db.handle, beta, dc.handle, 0.0, bsm.NORM_FROB, prec)
+    out = from_dev(dc)
+    for h in (da, db, dc):
+        h.destroy()
+    return out, st
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "split_bf16"])
+@pytest.mark.parametrize("b", [5, 13, 23, 26, 32])
+def test_lowp_quad_vs_one_block_kernel(orc, monkeypatch, prec, b):
+    """Reduced-precision quads (four waves per 2 x 2 group of C blocks) bit
+    for bit against the one-C-block-per-wave reduced-precision kernel (same
+    FP32 block products, added into FP64 in the same ascending-k order), on
+    odd block counts (partial quads), with and without C_in, and in many
+    chunks; and within the precision's bound of the FP64 oracle."""
+    monkeypatch.setenv("BSM_LOWP_QUAD", "1")
+    rng = np.random.default_rng(700 + b)
+    nbr, nbk, nbc = 11, 9, 13
+    a = synth.random_bsr(nbr, nbk, np.full(nbr, b), np.full(nbk, b), 0.45, rng)
+    bm = synth.random_bsr(nbk, nbc, np.full(nbk, b), np.full(nbc, b), 0.45, rng)
+    c = synth.random_bsr(nbr, nbc, np.full(nbr, b), np.full(nbc, b), 0.3, rng)
+    for alpha, beta, cc in [(1.0, 0.0, None), (-0.5, 1.5, c)]:
+        ref = orc.multiply(alpha, a, bm, beta, cc)
+        monkeypatch.setenv("BSM_SMM_VARIANT", "6")
+        got, _ = _lowp_run(prec, alpha, a, bm, beta, cc)
+        assert np.array_equal(got.col_idx, ref.col_idx) and np.array_equal(got.row_ptr, ref.row_ptr)
+        err = rel_fro(got.values, ref.values)
+        assert 0.0 < err <= TOL_MULT[prec], f"b={b} beta={beta}: rel err {err:.2e}"
+        monkeypatch.setenv("BSM_LOWP_QUAD", "0")
+        one, _ = _lowp_run(prec, alpha, a, bm, beta, cc)
+        assert np.array_equal(got.values, one.values), "quad and one-block kernels differ"
+        monkeypatch.setenv("BSM_LOWP_QUAD", "1")
+        monkeypatch.setenv("BSM_CHUNK_PRODUCTS", "50")
+        monkeypatch.setenv("BSM_TILE_ROWS", "3")
+        chunked, st2 = _lowp_run(prec, alpha, a, bm, beta, cc)
+        assert st2.smm_launches > 1
+        assert np.array_equal(chunked.values, got.values), "chunking changed the quad result"
+        monkeypatch.delenv("BSM_CHUNK_PRODUCTS")
+        monkeypatch.delenv("BSM_TILE_ROWS")
+
+
 def test_lowp_rejects_mixed_sizes(orc):
     from paper_2003_03868_amd import bsm
     rng = np.random.default_rng(5)
