@@ -61,7 +61,7 @@ def cpu_baseline(h, rows: int):
                        f"the iteration), eps 1e-6, {flops / 1e9:.1f} GFLOP in {dt:.1f} s")
 
 
-KERNEL_SOURCES = ["smm.h", "smm_quad.hip", "quad.hip"]
+KERNEL_SOURCES = ["smm.h", "smm_quad.hip", "quad.hip", "multiply.hip"]
 
 
 def sources_sha256() -> str:
@@ -162,12 +162,14 @@ def main():
     opts.order = args.order
     stream = torch.cuda.current_stream()
 
-    def step():
+    def step(keep=False):
         st, xh, stats = bsm.bsm_sign_iterate(dh.handle, 0.0, opts, stream=stream)
         if st != bsm.OK:
             raise RuntimeError(f"sign iteration failed: {bsm.STATUS_NAMES[st]} "
                                f"{bsm.bsm_last_error()}")
         ph, tp = bsm.bsm_density_from_sign(xh, stream=stream)
+        if keep:
+            return stats, tp, xh, ph
         bsm.bsm_destroy(ph)
         bsm.bsm_destroy(xh)
         return stats, tp
@@ -179,16 +181,20 @@ def main():
 
     torch.cuda.synchronize()
     times, all_stats = [], []
+    xd = pd = None
     for k in range(args.steps):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        stats, tp = step()
+        if k == args.steps - 1:
+            stats, tp, xd, pd = step(keep=True)   # the last iterate feeds the diagnostics
+        else:
+            stats, tp = step()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t)
         all_stats.append((stats, tp))
         log(f"step {k}: {times[-1] * 1e3:.0f} ms, {stats.iterations} iterations, "
             f"r={stats.r_hist[stats.iterations]:.2e}, trace(P)={tp:.6f}, "
-            f"smm {stats.smm_ms:.0f} ms, nnzb(X)={stats.nnzb_final}, "
+            f"smm {stats.smm_ms:.0f} ms in {stats.smm_launches} launches, nnzb(X)={stats.nnzb_final}, "
             f"graph replays {stats.graph_replays} (fallbacks {stats.graph_fallbacks})")
     total = sum(times)
     flops = sum(s.flops for s, _ in all_stats)
@@ -197,16 +203,14 @@ def main():
     ms_per_step = total / args.steps * 1e3
     achieved = flops / (smm_ms * 1e-3) / 1e12 if smm_ms > 0 else 0.0
 
-    # density-matrix diagnostic of the returned iterate (untimed): idempotency
-    # ||P^2 - P||_F / n on the device, P^2 filtered like every product
+    # density-matrix diagnostic of the last step's iterate (untimed):
+    # idempotency ||P^2 - P||_F / n on the device, P^2 filtered like every product
     import math
-    st_d, xd, _ = bsm.bsm_sign_iterate(dh.handle, 0.0, opts, stream=stream)
-    pd, _ = bsm.bsm_density_from_sign(xd, stream=stream)
     p2 = bsm.Matrix.empty_like(h.row_blk_size, h.col_blk_size)
     bsm.bsm_multiply(1.0, pd, pd, 0.0, p2.handle, args.eps, bsm.NORM_FROB, stream=stream)
     dd = bsm.bsm_add(1.0, p2.handle, -1.0, pd, stream=stream)
     idem = math.sqrt(bsm.bsm_sqdist_identity(dd, 0.0, stream=stream)) / float(h.shape[0])
-    for hnd in (dd, pd, xd):
+    for hnd in (dd, pd):
         bsm.bsm_destroy(hnd)
     p2.destroy()
     log(f"||P^2 - P||_F / n = {idem:.3e}")
@@ -215,8 +219,7 @@ def main():
     if args.prec != "fp64":
         # error of the reduced-precision sign against the FP64 GPU path on the
         # same input (untimed): ||X_p - X_64||_F / ||X_64||_F and trace(P)
-        import math
-        st_p, xp, sp = bsm.bsm_sign_iterate(dh.handle, 0.0, opts, stream=stream)
+        xp, sp = xd, s0
         o64 = bsm.bsm_sign_opts_default()
         for f, _ in bsm.bsm_sign_opts._fields_:
             setattr(o64, f, getattr(opts, f))
@@ -229,9 +232,10 @@ def main():
                  "trace_p_fp64": float(s64.trace_p),
                  "trace_p_diff": float(sp.trace_p - s64.trace_p),
                  "precisions": list(sp.prec_hist[:sp.iterations + 1])}
-        for hnd in (d, x64, xp):
+        for hnd in (d, x64):
             bsm.bsm_destroy(hnd)
         log(f"error vs FP64 path: {err64}")
+    bsm.bsm_destroy(xd)
 
     cpu = None
     if not args.no_cpu and args.workload == "sign23":
@@ -268,6 +272,7 @@ def main():
         "time_to_sign_ms": ms_per_step,
         "iterations": int(s0.iterations),
         "multiplies": int(s0.n_multiplies),
+        "smm_launches_per_step": int(s0.smm_launches),
         "r_final": float(s0.r_hist[s0.iterations]),
         "trace_p": float(tp0),
         "n_occ": int(h.meta["n_occ"]),
@@ -279,7 +284,7 @@ def main():
         "graph_fallbacks": int(s0.graph_fallbacks),
         "roofline": {
             "bound": "mfma",
-            "kernel": ("k_smm_f64_quad<23,4,5>" if args.workload == "sign23" else "k_smm_f64_class")
+            "kernel": ("k_smm_f64_quad<23,2,4,5,1>" if args.workload == "sign23" else "k_smm_f64_class")
             if args.prec == "fp64" else "k_smm_lowp",
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,

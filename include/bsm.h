@@ -113,6 +113,8 @@ typedef struct {
     int32_t graph_replays;   /* iterations run by replaying captured graphs */
     int32_t graph_fallbacks; /* replayed iterations redone on the normal path because
                                 the filter kept other blocks (or NaN/Inf appeared) */
+    int32_t smm_launches;    /* block-product kernel launches of the counted multiplies */
+    int32_t pad_;
 } bsm_sign_stats;
 
 /* Default options: eps 0, tol 1e-6, max_iter 100, FROB, FP64, no graph, order 2. */

@@ -55,7 +55,8 @@ class bsm_sign_stats(C.Structure):
                 ("scale", C.c_double), ("trace_x", C.c_double), ("trace_p", C.c_double),
                 ("flops", C.c_double), ("n_products", C.c_int64), ("smm_ms", C.c_double),
                 ("device_ms", C.c_double), ("nnzb_final", C.c_int64),
-                ("graph_replays", C.c_int32), ("graph_fallbacks", C.c_int32)]
+                ("graph_replays", C.c_int32), ("graph_fallbacks", C.c_int32),
+                ("smm_launches", C.c_int32), ("pad_", C.c_int32)]
 
 
 class bsm_smm_params(C.Structure):

@@ -308,7 +308,9 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         if (pl) { pl->apk = apk; pl->bpk = bpk; }
     }
 
+    int32_t n_launch = 0;
     auto launch = [&](const MulOp &op) -> int {
+        ++n_launch;
         const int r = run_op(op, s);
         if (r == BSM_OK && pl) pl->ops.push_back(op);
         return r;
@@ -517,7 +519,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         stats->flops = flops;
         stats->nnzb_unfiltered = nnzb_c;
         stats->nnzb = nnzb_after;
-        stats->smm_launches = static_cast<int32_t>(ev.smm.size());
+        stats->smm_launches = n_launch;
         float ms = 0.f;
         double smm = 0.0;
         for (auto &p : ev.smm) {

@@ -236,6 +236,7 @@ static int higher_order_update(const bsm_sign_opts &o, int prec, Mat &X, Mat &Y,
         st->n_multiplies++;
         st->flops += ms.flops;
         st->n_products += ms.n_products;
+        st->smm_launches += ms.smm_launches;
         st->smm_ms += ms.smm_ms;
         return rc;
     };
@@ -325,6 +326,7 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
                 st->n_multiplies -= 2;
                 st->flops -= R.psq->flops + R.pup->flops;
                 st->n_products -= R.psq->nprod + R.pup->nprod;
+                st->smm_launches -= static_cast<int32_t>(R.psq->ops.size() + R.pup->ops.size());
                 st->graph_replays--;
                 st->graph_fallbacks++;
                 R.p ^= 1;
@@ -350,6 +352,7 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
                 st->n_multiplies++;
                 st->flops += R.psq->flops;
                 st->n_products += R.psq->nprod;
+                st->smm_launches += static_cast<int32_t>(R.psq->ops.size());
                 rc = refilter(*R.psq, R.psq->compacted ? R.psq->c_vals_u : Y->values, *Y, s);
                 st->graph_fallbacks++;
                 R.leave(*X);
@@ -360,6 +363,7 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
                 st->n_multiplies++;
                 st->flops += R.psq->flops;
                 st->n_products += R.psq->nprod;
+                st->smm_launches += static_cast<int32_t>(R.psq->ops.size());
                 const double r = std::sqrt(h.d) / n;
                 st->r_hist[k] = r;
                 st->iterations = k;
@@ -378,6 +382,7 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
                 st->n_multiplies++;
                 st->flops += R.pup->flops;
                 st->n_products += R.pup->nprod;
+                st->smm_launches += static_cast<int32_t>(R.pup->ops.size());
                 st->graph_replays++;
                 R.p ^= 1;
                 X->values = R.xbuf[R.p];
@@ -399,6 +404,7 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
             st->n_multiplies++;
             st->flops += ms.flops;
             st->n_products += ms.n_products;
+            st->smm_launches += ms.smm_launches;
             st->smm_ms += ms.smm_ms;
         }
         if (rc != BSM_OK && rc != BSM_ENONFINITE) break;
@@ -431,6 +437,7 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
         st->n_multiplies++;
         st->flops += ms.flops;
         st->n_products += ms.n_products;
+        st->smm_launches += ms.smm_launches;
         st->smm_ms += ms.smm_ms;
         if (rc != BSM_OK) break;
         if (want_graph && R.psq && R.pup) {
