@@ -93,7 +93,7 @@ typedef struct {
     int32_t fp64_final_iters;/* mixed precision: last updates done in FP64 */
     int32_t use_graph;       /* 1: replay captured iterations where possible */
     double prec_switch_tol;  /* mixed precision: FP64 once r_k < this */
-    int32_t order;           /* 2 (Newton-Schulz), 3 or 5: see bsm_sign_iterate */
+    int32_t order;           /* 2 (Newton-Schulz), 3, 5 or 7: see bsm_sign_iterate */
     int32_t pad_;
 } bsm_sign_opts;
 
@@ -205,6 +205,11 @@ int bsm_inf_norm(bsm_matrix A, double mu, double *out, void *stream);
  *   5: Y2 = Y Y;  V = 35 Y2 - 180 Y + 378 I (bsm_add);
  *      U = Y2 V + (315 I - 420 Y);  X' = X U / 128            (4 multiplies,
  *      Eq. fifth_order_sign)
+ *   7: Y2 = Y Y;  Y3 = Y Y2;  V = (231 Y3 - 1638 Y2 - 8580 I) + 5005 Y;
+ *      C0 = 9009 Y2 - 6006 Y + 3003 I;  U = Y3 V + C0;  X' = X U / 1024
+ *      (5 multiplies; the seventh order the section names, whose polynomial
+ *      has g'(x) proportional to (1 - x^2)^6 like the printed ones)
+ * Other orders: BSM_EINVAL.
  * opts->use_graph = 1 (order 2 only): once an update leaves X's block pattern unchanged, the
  * following iterations replay captured hipGraphs of the numeric kernels (one
  * wait per iteration; no symbolic phase, allocation or compaction scan).  A

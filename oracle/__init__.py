@@ -198,7 +198,7 @@ def add(alpha: float, a: BSR, beta: float = 0.0, b: BSR | None = None, gamma: fl
 
 def sign_ns(h: BSR, mu: float = 0.0, eps: float = 0.0, tol: float = 1e-6,
             max_iter: int = 100, fixed_iters: int = 0, norm="frob", order: int = 2):
-    """Sign iteration of the given order (2: Newton-Schulz, 3, 5); returns
+    """Sign iteration of the given order (2: Newton-Schulz, 3, 5, 7); returns
     (X, stats, status).
 
     ``status`` is OK, ENOCONV or ENONFINITE; X is the last iterate in every

@@ -501,10 +501,21 @@ static double product_flops(const omat *a, const omat *b)
  *             V  = filter(35 Y2 - 180 Y + 378 I)
  *             U  = filter(Y2 V + (315 I - 420 Y))
  *             X' = filter(X U / 128)                            Eq. fifth_order_sign
+ *   order 7:  Y2 = filter(Y Y),  Y3 = filter(Y Y2)
+ *             V  = filter(filter(231 Y3 - 1638 Y2 - 8580 I) + 5005 Y)
+ *             C0 = filter(9009 Y2 - 6006 Y + 3003 I)
+ *             U  = filter(Y3 V + C0)
+ *             X' = filter(X U / 1024)
  *
  * The fifth-order form uses four multiplies per iteration (with the square
  * Y), as the Sign-Method section states; every product is filtered.  The
- * constant-plus-Y terms enter a multiply as its C_in.
+ * constant-plus-Y terms enter a multiply as its C_in.  The paper states that
+ * the iterations go up to seventh order without printing that one; its
+ * polynomial is the member of the printed family with g'(x) proportional to
+ * (1 - x^2)^6 and g(1) = 1:
+ * q(Y) = 3003 - 6006 Y + 9009 Y^2 - 8580 Y^3 + 5005 Y^4 - 1638 Y^5 + 231 Y^6,
+ * evaluated as (3003 - 6006 Y + 9009 Y^2) + Y^3 (231 Y^3 - 1638 Y^2 + 5005 Y
+ * - 8580) with five multiplies per iteration.
  */
 static int sign_update(int32_t order, const omat *x, const omat *y, double eps, int norm_kind,
                        omat *xn, orc_sign_stats *st)
@@ -529,6 +540,32 @@ static int sign_update(int32_t order, const omat *x, const omat *y, double eps, 
             status = orc_multiply(0.125, x, &w, 0.0, NULL, eps, norm_kind, xn);
         }
         orc_free(&c); orc_free(&w);
+        return status;
+    }
+    if (order == 7) {
+        omat y3 = {0}, v1 = {0};
+        st->flops += product_flops(y, y);
+        st->n_multiplies++;
+        status = orc_multiply(1.0, y, y, 0.0, NULL, eps, norm_kind, &y2);
+        if (status == ORC_OK) {
+            st->flops += product_flops(y, &y2);
+            st->n_multiplies++;
+            status = orc_multiply(1.0, y, &y2, 0.0, NULL, eps, norm_kind, &y3);
+        }
+        if (status == ORC_OK) status = orc_add(231.0, &y3, -1638.0, &y2, -8580.0, eps, norm_kind, &v1);
+        if (status == ORC_OK) status = orc_add(1.0, &v1, 5005.0, y, 0.0, eps, norm_kind, &v);
+        if (status == ORC_OK) status = orc_add(9009.0, &y2, -6006.0, y, 3003.0, eps, norm_kind, &c);
+        if (status == ORC_OK) {
+            st->flops += product_flops(&y3, &v);
+            st->n_multiplies++;
+            status = orc_multiply(1.0, &y3, &v, 1.0, &c, eps, norm_kind, &w);
+        }
+        if (status == ORC_OK) {
+            st->flops += product_flops(x, &w);
+            st->n_multiplies++;
+            status = orc_multiply(1.0 / 1024.0, x, &w, 0.0, NULL, eps, norm_kind, xn);
+        }
+        orc_free(&c); orc_free(&w); orc_free(&y2); orc_free(&v); orc_free(&y3); orc_free(&v1);
         return status;
     }
     /* order 5 */
@@ -574,7 +611,8 @@ int orc_sign(const omat *h, double mu, double eps, int norm_kind, double tol,
              orc_sign_stats *st)
 {
     if (h->nbrows != h->nbcols || eps < 0 || max_iter < 0 || max_iter > 120 ||
-        fixed_iters < 0 || fixed_iters > 120 || (order != 2 && order != 3 && order != 5))
+        fixed_iters < 0 || fixed_iters > 120 ||
+        (order != 2 && order != 3 && order != 5 && order != 7))
         return ORC_EINVAL;
     for (int32_t i = 0; i < h->nbrows; ++i) if (h->rbs[i] != h->cbs[i]) return ORC_EINVAL;
     memset(st, 0, sizeof(*st));

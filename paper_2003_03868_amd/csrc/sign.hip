@@ -17,7 +17,13 @@
 //   3:  W = 3 Y Y + (15 I - 10 Y);  X' = X W / 8              (f_2 of OT/IR)
 //   5:  Y2 = Y Y;  V = 35 Y2 - 180 Y + 378 I;  U = Y2 V + (315 I - 420 Y);
 //       X' = X U / 128
-// where the constant-plus-Y term enters the multiply as its C_in.
+//   7:  Y2 = Y Y;  Y3 = Y Y2;  V = (231 Y3 - 1638 Y2 - 8580 I) + 5005 Y;
+//       C0 = 9009 Y2 - 6006 Y + 3003 I;  U = Y3 V + C0;  X' = X U / 1024
+// where the constant-plus-Y term enters the multiply as its C_in.  The
+// section names a seventh-order iteration without printing it; its
+// polynomial is the member of the printed family with g'(x) proportional to
+// (1 - x^2)^6 and g(1) = 1, evaluated in the Paterson-Stockmeyer split
+// q = (3003 - 6006 Y + 9009 Y^2) + Y^3 (231 Y^3 - 1638 Y^2 + 5005 Y - 8580).
 //
 // Graph replay (opts.use_graph): once an update leaves the block pattern of X
 // unchanged, the symbolic results of both multiplies stay valid for the next
@@ -49,7 +55,10 @@ static int validate_opts(const Mat &H, const bsm_sign_opts &o) {
     if (o.norm != BSM_NORM_FROB && o.norm != BSM_NORM_MAXABS) { set_error("sign: unknown norm"); return BSM_EINVAL; }
     if (o.prec != BSM_FP64 && o.prec != BSM_FP32 && o.prec != BSM_SPLIT_BF16) { set_error("sign: unknown precision"); return BSM_EINVAL; }
     if (o.fp64_final_iters < 0) { set_error("sign: fp64_final_iters must be >= 0"); return BSM_EINVAL; }
-    if (o.order != 2 && o.order != 3 && o.order != 5) { set_error("sign: order must be 2, 3 or 5"); return BSM_EINVAL; }
+    if (o.order != 2 && o.order != 3 && o.order != 5 && o.order != 7) {
+        set_error("sign: order must be 2, 3, 5 or 7");
+        return BSM_EINVAL;
+    }
     return BSM_OK;
 }
 
@@ -227,7 +236,7 @@ static int maybe_enter(Replay &R, Mat &X, Mat &Y, int prec, hipStream_t s) {
     return rc;
 }
 
-// X <- X q(Y) / d for orders 3 and 5 (see the top of this file); Y = X^2.
+// X <- X q(Y) / d for orders 3, 5 and 7 (see the top of this file); Y = X^2.
 static int higher_order_update(const bsm_sign_opts &o, int prec, Mat &X, Mat &Y,
                                bsm_sign_stats *st, hipStream_t s) {
     auto mult = [&](double alpha, Mat &A, Mat &B, double beta, Mat &C) -> int {
@@ -240,9 +249,21 @@ static int higher_order_update(const bsm_sign_opts &o, int prec, Mat &X, Mat &Y,
         st->smm_ms += ms.smm_ms;
         return rc;
     };
-    Mat *c = nullptr, *y2 = nullptr, *v = nullptr;
+    Mat *c = nullptr, *y2 = nullptr, *v = nullptr, *y3 = nullptr, *v1 = nullptr;
     int rc = BSM_OK;
-    if (o.order == 3) {
+    if (o.order == 7) {
+        rc = alloc_like_sizes(Y, Y, &y2, s);
+        if (rc == BSM_OK) rc = mult(1.0, Y, Y, 0.0, *y2);            // Y2
+        if (rc == BSM_OK) rc = alloc_like_sizes(Y, Y, &y3, s);
+        if (rc == BSM_OK) rc = mult(1.0, Y, *y2, 0.0, *y3);          // Y3
+        if (rc == BSM_OK)                                            // 231 Y3 - 1638 Y2 - 8580 I
+            rc = add_mat(231.0, *y3, -1638.0, y2, -8580.0, o.eps_filter, o.norm, &v1, s);
+        if (rc == BSM_OK) rc = add_mat(1.0, *v1, 5005.0, &Y, 0.0, o.eps_filter, o.norm, &v, s);
+        if (rc == BSM_OK)                                            // 9009 Y2 - 6006 Y + 3003 I
+            rc = add_mat(9009.0, *y2, -6006.0, &Y, 3003.0, o.eps_filter, o.norm, &c, s);
+        if (rc == BSM_OK) rc = mult(1.0, *y3, *v, 1.0, *c);          // U = Y3 V + C0
+        if (rc == BSM_OK) rc = mult(1.0 / 1024.0, X, *c, 0.0, X);    // X U / 1024
+    } else if (o.order == 3) {
         rc = shift_scale(Y, 1.5, -10.0, &c, s);                      // 15 I - 10 Y
         if (rc == BSM_OK) rc = mult(3.0, Y, Y, 1.0, *c);             // W = 3 Y Y + C
         if (rc == BSM_OK) rc = mult(0.125, X, *c, 0.0, X);           // X W / 8
@@ -258,6 +279,8 @@ static int higher_order_update(const bsm_sign_opts &o, int prec, Mat &X, Mat &Y,
     free_mat(c, s);
     free_mat(y2, s);
     free_mat(v, s);
+    free_mat(y3, s);
+    free_mat(v1, s);
     return rc;
 }
 

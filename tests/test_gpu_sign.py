@@ -127,14 +127,15 @@ def test_add_vs_oracle(orc, seed):
                        1e-14, "add without B")
 
 
-@pytest.mark.parametrize("order", [3, 5])
+@pytest.mark.parametrize("order", [3, 5, 7])
 @pytest.mark.parametrize("c", [dict(n=64, b=5, rc=4.0, eps=0.0, seed=3),
                                dict(n=200, b=5, rc=6.0, eps=1e-6, seed=5),
                                dict(n=100, b=23, rc=4.2, eps=1e-6, seed=6)],
                          ids=lambda c: f"n{c['n']}b{c['b']}e{c['eps']:g}")
 def test_sign_higher_orders_vs_oracle(orc, order, c):
-    """Third- and fifth-order iterations (Eq. fifth_order_sign: four
-    multiplies per iteration) against the oracle's same iterations."""
+    """Third-, fifth- (Eq. fifth_order_sign: four multiplies per iteration)
+    and seventh-order iterations (five multiplies) against the oracle's same
+    iterations."""
     from paper_2003_03868_amd import bsm
     h = synth.neighbour_hamiltonian(c["n"], c["b"], cutoff=c["rc"], seed=c["seed"])
     x_ref, st_ref, s_ref = orc.sign_ns(h, eps=c["eps"], tol=1e-8, order=order)

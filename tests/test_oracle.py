@@ -444,12 +444,24 @@ def test_add_matches_dense(orc, seed):
 
 # ------------------------------------------- higher-order sign iterations
 
-@pytest.mark.parametrize("order,poly", [(2, "f1"), (3, "f2"), (5, "p5")])
+def _family_poly(order):
+    """q of the order-p member of the family the printed polynomials belong
+    to (g'(x) proportional to (1 - x^2)^(p-1), g(0) = 0, g(1) = 1, g(x) =
+    x q(x^2)), by integrating the closed form with numpy: the paper names
+    the seventh-order iteration without printing it."""
+    P = np.polynomial.polynomial
+    g = P.polyint(P.polypow([1.0, 0.0, -1.0], order - 1))
+    g = g / P.polyval(1.0, g)
+    return list(g[1::2]), 1.0
+
+
+@pytest.mark.parametrize("order,poly", [(2, "f1"), (3, "f2"), (5, "p5"), (7, None)])
 def test_sign_orders_follow_printed_polynomials(orc, order, poly):
     """Diagonal H: every update of the order-p iteration must equal the
-    polynomial printed in the paper (OT/IR f_1, f_2; Eq. fifth_order_sign),
+    polynomial printed in the paper (OT/IR f_1, f_2; Eq. fifth_order_sign)
+    or, for order 7, the family member derived from its closed form,
     g(x) = x q(x^2)/den, evaluated independently with numpy."""
-    _, coef, den = _read_polys()[poly]
+    coef, den = _family_poly(order) if poly is None else _read_polys()[poly][1:]
     rng = np.random.default_rng(40 + order)
     sizes = rng.integers(1, 6, 9)
     n = int(sizes.sum())
@@ -461,11 +473,11 @@ def test_sign_orders_follow_printed_polynomials(orc, order, poly):
         assert status == orc.OK and st["iterations"] == k
         x = x * np.polynomial.polynomial.polyval(x * x, coef) / den
         assert np.allclose(np.diag(xk.to_dense()), x, rtol=1e-13, atol=1e-15)
-        per_update = {2: 2, 3: 3, 5: 4}[order]
+        per_update = {2: 2, 3: 3, 5: 4, 7: 5}[order]
         assert st["n_multiplies"] == per_update * k + 1
 
 
-@pytest.mark.parametrize("order", [3, 5])
+@pytest.mark.parametrize("order", [3, 5, 7])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_sign_higher_orders_match_eigh(orc, order, seed):
     rng = np.random.default_rng(seed)

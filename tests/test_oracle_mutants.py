@@ -27,6 +27,11 @@ MUTANTS = [
     ("o5_coefficient", "orc_add(35.0, &y2, -180.0, y, 378.0,", "orc_add(35.0, &y2, -180.0, y, 387.0,"),
     ("o5_cin", "orc_shift_scale(y, 0.75, -420.0, &c)", "orc_shift_scale(y, 0.75, -410.0, &c)"),
     ("o5_scale", "orc_multiply(1.0 / 128.0, x, &w,", "orc_multiply(1.0 / 64.0, x, &w,"),
+    ("o7_coefficient", "orc_add(231.0, &y3, -1638.0, &y2, -8580.0,", "orc_add(231.0, &y3, -1638.0, &y2, -8508.0,"),
+    ("o7_cube", "orc_multiply(1.0, y, &y2, 0.0, NULL, eps, norm_kind, &y3);",
+     "orc_multiply(1.0, y, y, 0.0, NULL, eps, norm_kind, &y3);"),
+    ("o7_cin", "orc_add(9009.0, &y2, -6006.0, y, 3003.0,", "orc_add(9009.0, &y2, -6006.0, y, 3030.0,"),
+    ("o7_scale", "orc_multiply(1.0 / 1024.0, x, &w,", "orc_multiply(1.0 / 512.0, x, &w,"),
     ("add_gamma", "tmp[r * m + r] = tmp[r * m + r] + gamma;", "tmp[r * m + r] = tmp[r * m + r] - gamma;"),
     ("add_b_index", "tmp[e] = tmp[e] + beta * b->values[offb[tb] + e];",
      "tmp[e] = tmp[e] + beta * b->values[offb[tb]];"),
