@@ -107,7 +107,7 @@ def main():
     ap.add_argument("--table", choices=["exhaustive", "mlp", "none"], default="exhaustive",
                     help="kernel-parameter table: measured (exhaustive autotuning), predicted "
                          "by the MLP, or none (built-in choices)")
-    ap.add_argument("--order", type=int, choices=[2, 3, 5], default=2,
+    ap.add_argument("--order", type=int, choices=[2, 3, 5, 7], default=2,
                     help="sign iteration order: 2 Newton-Schulz, 3, 5 (four multiplies per iteration)")
     ap.add_argument("--graph", type=int, choices=[0, 1], default=0,
                     help="1: replay captured hipGraphs once X's block pattern stops changing")
