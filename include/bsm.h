@@ -117,6 +117,16 @@ typedef struct {
     int32_t pad_;
 } bsm_sign_stats;
 
+/* Bisection record of bsm_mu_bisect. */
+typedef struct bsm_mu_stats {
+    int32_t steps;           /* sign iterations run (one per bisection midpoint) */
+    int32_t sign_noconv;     /* midpoints whose sign iteration ended with BSM_ENOCONV */
+    double mu_hist[64];      /* midpoint mu of step t */
+    double count_hist[64];   /* trace(P) = (n - trace X)/2 at mu_hist[t] */
+    double flops;            /* algorithmic flops of all block products */
+    double device_ms;        /* summed device time of the sign iterations */
+} bsm_mu_stats;
+
 /* Default options: eps 0, tol 1e-6, max_iter 100, FROB, FP64, no graph, order 2. */
 void bsm_sign_opts_default(bsm_sign_opts *opts);
 
@@ -231,6 +241,29 @@ int bsm_sign_iterate(bsm_matrix H, double mu, const bsm_sign_opts *opts,
  */
 int bsm_add(double alpha, bsm_matrix A, double beta, bsm_matrix B, double gamma,
             double eps_filter, int32_t norm, bsm_matrix *out, void *stream);
+
+/*
+ * Chemical potential for a fixed electron count (the canonical ensemble
+ * that the Density-matrix-based-methods paragraph says sign purification
+ * needs extra iterations for): bisection on mu for trace(P(mu)) =
+ * (n - trace sign(H - mu I))/2, which does not decrease with mu.
+ *   step t: mu = (lo + hi)/2; X = sign(H - mu I) (bsm_sign_iterate with opts);
+ *           count = (n - trace X)/2;
+ *           stop if |count - n_target| <= count_tol;
+ *           else lo = mu if count < n_target, hi = mu otherwise.
+ * The caller brackets the answer: count(mu_lo) <= n_target <= count(mu_hi)
+ * (the endpoints themselves are never evaluated); mu_lo < mu_hi finite,
+ * count_tol > 0, 1 <= max_steps <= 64, else BSM_EINVAL.  A midpoint whose
+ * sign iteration ends with BSM_ENOCONV (mu near an eigenvalue) still gives
+ * its count, and is counted in stats->sign_noconv.  Returns BSM_OK with the
+ * accepted mu in *mu_out and its X in *x_out (new handle, caller destroys),
+ * or BSM_ENOCONV after max_steps midpoints with the last mu and X; any other
+ * error of the sign iteration is returned as is, with no X.  stats may be
+ * NULL.  Blocks until the last count is known.
+ */
+int bsm_mu_bisect(bsm_matrix H, double n_target, double mu_lo, double mu_hi, double count_tol,
+                  int32_t max_steps, const bsm_sign_opts *opts, double *mu_out,
+                  bsm_matrix *x_out, bsm_mu_stats *stats, void *stream);
 
 /* P = (I - X)/2 from a sign matrix X, as a new handle; trace_p (may be NULL) gets trace(P). */
 int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void *stream);

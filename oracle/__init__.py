@@ -18,6 +18,14 @@ Parity status of each function (what pins it, see ``tests/test_oracle.py``):
                        closed form, trace = number of negative eigenvalues.
 * ``trace``, ``sqdist_identity``, ``inf_norm_shifted`` -- pinned against
                        ``numpy`` on the dense matrix.
+* ``add``           -- pinned: dense NumPy sum, pattern union, keep rule.
+* ``sign_ns`` orders 3, 5, 7 -- pinned: the printed polynomials (order 7:
+                       derived in the test from its closed form) on diagonal
+                       H, eigen-decomposition sign on tiny dense cases.
+* ``mu_bisect``     -- pinned: diagonal H, whose count is the number of
+                       diagonal entries below mu, so every midpoint follows
+                       by hand; on dense cases the accepted mu lies in the
+                       eigenvalue gap that gives the target count (LAPACK).
 """
 from __future__ import annotations
 
@@ -218,6 +226,36 @@ def sign_ns(h: BSR, mu: float = 0.0, eps: float = 0.0, tol: float = 1e-6,
                  scale=float(st.scale), trace_x=float(st.trace_x),
                  trace_p=float(st.trace_p), flops=float(st.flops))
     return x, stats, int(status)
+
+
+def mu_bisect(h: BSR, n_target: float, mu_lo: float, mu_hi: float, count_tol: float = 0.5,
+              max_steps: int = 40, **sign_kw):
+    """Chemical potential for a fixed electron count by bisection on
+    trace(P(mu)) = (n - trace sign(H - mu I))/2 (the extra iterations the
+    Density-matrix-based-methods paragraph says a canonical ensemble needs):
+    mu = (lo + hi)/2; count from the sign iteration at mu; stop when
+    |count - n_target| <= count_tol, else lo = mu (count < n_target) or
+    hi = mu.  The endpoints are never evaluated.  Returns (mu, X, record,
+    status) with status OK or ENOCONV (no midpoint within count_tol)."""
+    lo, hi = float(mu_lo), float(mu_hi)
+    rec = dict(mu_hist=[], count_hist=[], sign_noconv=0)
+    x = None
+    for _ in range(max_steps):
+        mu = 0.5 * (lo + hi)
+        x, st, status = sign_ns(h, mu=mu, **sign_kw)
+        if status not in (OK, ENOCONV):
+            raise RuntimeError(f"oracle sign iteration failed with status {status}")
+        rec["sign_noconv"] += status == ENOCONV
+        count = st["trace_p"]
+        rec["mu_hist"].append(mu)
+        rec["count_hist"].append(count)
+        if abs(count - n_target) <= count_tol:
+            return mu, x, rec, OK
+        if count < n_target:
+            lo = mu
+        else:
+            hi = mu
+    return mu, x, rec, ENOCONV
 
 
 def density_from_sign(x: BSR) -> BSR:

@@ -59,6 +59,12 @@ class bsm_sign_stats(C.Structure):
                 ("smm_launches", C.c_int32), ("pad_", C.c_int32)]
 
 
+class bsm_mu_stats(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("sign_noconv", C.c_int32),
+                ("mu_hist", C.c_double * 64), ("count_hist", C.c_double * 64),
+                ("flops", C.c_double), ("device_ms", C.c_double)]
+
+
 class bsm_smm_params(C.Structure):
     _fields_ = [("family", C.c_int32), ("wpg", C.c_int32), ("prefetch", C.c_int32),
                 ("reserved", C.c_int32)]
@@ -89,6 +95,9 @@ _SIGS = [
                                    C.POINTER(C.c_void_p), C.POINTER(bsm_sign_stats), C.c_void_p]),
     ("bsm_add", C.c_int, [C.c_double, C.c_void_p, C.c_double, C.c_void_p, C.c_double,
                           C.c_double, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
+    ("bsm_mu_bisect", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double,
+                                C.c_int32, C.POINTER(bsm_sign_opts), C.POINTER(C.c_double),
+                                C.POINTER(C.c_void_p), C.POINTER(bsm_mu_stats), C.c_void_p]),
     ("bsm_density_from_sign", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p),
                                         C.POINTER(C.c_double), C.c_void_p]),
     ("bsm_smm_bench", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
@@ -230,6 +239,22 @@ def bsm_sign_iterate(h, mu=0.0, opts: bsm_sign_opts | None = None, stream=None):
     if st not in (OK, ENOCONV, ENONFINITE):
         _check(st, "bsm_sign_iterate")
     return st, out.value, stats
+
+
+def bsm_mu_bisect(h, n_target, mu_lo, mu_hi, count_tol=0.5, max_steps=40,
+                  opts: bsm_sign_opts | None = None, stream=None):
+    """Returns (status, mu, X handle or None, stats); ENOCONV is returned,
+    not raised, since the last midpoint and its X are still meaningful."""
+    out = C.c_void_p()
+    mu = C.c_double()
+    stats = bsm_mu_stats()
+    o = opts if opts is not None else bsm_sign_opts_default()
+    st = load().bsm_mu_bisect(h, float(n_target), float(mu_lo), float(mu_hi), float(count_tol),
+                              int(max_steps), C.byref(o), C.byref(mu), C.byref(out),
+                              C.byref(stats), _stream(stream))
+    if st not in (OK, ENOCONV):
+        _check(st, "bsm_mu_bisect")
+    return st, mu.value, out.value, stats
 
 
 def bsm_add(alpha, a, beta=0.0, b=None, gamma=0.0, eps_filter=0.0, norm=0, stream=None) -> int:

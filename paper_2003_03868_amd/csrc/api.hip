@@ -252,6 +252,61 @@ int bsm_sign_iterate(bsm_matrix H, double mu, const bsm_sign_opts *opts, bsm_mat
     return rc;
 }
 
+int bsm_mu_bisect(bsm_matrix H, double n_target, double mu_lo, double mu_hi, double count_tol,
+                  int32_t max_steps, const bsm_sign_opts *opts, double *mu_out,
+                  bsm_matrix *x_out, bsm_mu_stats *stats, void *stream) {
+    bsm::clear_error();
+    if (!H || !x_out || !mu_out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    *x_out = nullptr;
+    if (!std::isfinite(mu_lo) || !std::isfinite(mu_hi) || !(mu_lo < mu_hi) ||
+        !std::isfinite(n_target) || !(count_tol > 0.0) || !std::isfinite(count_tol) ||
+        max_steps < 1 || max_steps > 64) {
+        bsm::set_error("mu_bisect: need finite mu_lo < mu_hi, finite n_target, count_tol > 0 "
+                       "and 1 <= max_steps <= 64");
+        return BSM_EINVAL;
+    }
+    bsm_sign_opts o;
+    if (opts) o = *opts; else bsm_sign_opts_default(&o);
+    bsm_mu_stats local;
+    bsm_mu_stats *ms = stats ? stats : &local;
+    std::memset(ms, 0, sizeof(*ms));
+    hipStream_t s = as_stream(stream);
+    double lo = mu_lo, hi = mu_hi;
+    Mat *x = nullptr;
+    int rc = BSM_ENOCONV;
+    double mu = 0.0;
+    for (int32_t t = 0; t < max_steps; ++t) {
+        mu = 0.5 * (lo + hi);
+        if (x) { bsm::free_mat(x, s); x = nullptr; }
+        bsm_sign_stats st;
+        std::memset(&st, 0, sizeof(st));
+        const int src = bsm::sign_iterate(H->m, mu, o, &x, &st, s);
+        ms->flops += st.flops;
+        ms->device_ms += st.device_ms;
+        if (src != BSM_OK && src != BSM_ENOCONV) {
+            if (x) bsm::free_mat(x, s);
+            return src;
+        }
+        if (src == BSM_ENOCONV) ms->sign_noconv++;
+        const double count = st.trace_p;
+        ms->mu_hist[t] = mu;
+        ms->count_hist[t] = count;
+        ms->steps = t + 1;
+        if (std::fabs(count - n_target) <= count_tol) { rc = BSM_OK; break; }
+        if (count < n_target) lo = mu; else hi = mu;
+    }
+    if (rc == BSM_ENOCONV)
+        bsm::set_error("mu_bisect: count not within count_tol after %d steps", max_steps);
+    *mu_out = mu;
+    if (x) {
+        auto *h = new bsm_matrix_s;
+        h->m = std::move(*x);
+        delete x;
+        *x_out = h;
+    }
+    return rc;
+}
+
 int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void *stream) {
     bsm::clear_error();
     if (!X || !p_out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }

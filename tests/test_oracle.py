@@ -506,3 +506,67 @@ def test_sign_higher_orders_filtered_neighbour(orc):
     assert st["trace_p"] == pytest.approx(h.meta["n_occ"], abs=1e-4)
     dx = x.to_dense()
     assert np.linalg.norm(dx @ dx - np.eye(dx.shape[0])) / dx.shape[0] < 1e-5
+
+
+# ------------------------------------------------ chemical potential search
+
+def test_mu_bisect_diagonal_by_hand(orc):
+    """Diagonal H: count(mu) is the number of diagonal entries below mu, so
+    the bisection's midpoints and decisions follow by hand exactly."""
+    rng = np.random.default_rng(21)
+    sizes = rng.integers(1, 6, 12)
+    n = int(sizes.sum())
+    h = rng.uniform(-4.0, 4.0, n)
+    m = _diag_matrix(h, sizes)
+    target = n // 3
+    mu, x, rec, status = orc.mu_bisect(m, target, -5.0, 5.0, count_tol=0.25, max_steps=40,
+                                       eps=0.0, tol=1e-12)
+    assert status == orc.OK
+    lo, hi, hand = -5.0, 5.0, []
+    for _ in range(40):
+        mid = 0.5 * (lo + hi)
+        c = int((h < mid).sum())
+        hand.append((mid, c))
+        if abs(c - target) <= 0.25:
+            break
+        if c < target:
+            lo = mid
+        else:
+            hi = mid
+    assert rec["mu_hist"] == [a for a, _ in hand]
+    assert np.allclose(rec["count_hist"], [c for _, c in hand], atol=1e-8, rtol=0)
+    assert mu == hand[-1][0] and int((h < mu).sum()) == target
+    # the returned X is sign(H - mu I)
+    assert np.allclose(np.diag(x.to_dense()), np.sign(h - mu), atol=1e-10)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_mu_bisect_dense_lands_in_gap(orc, seed):
+    rng = np.random.default_rng(60 + seed)
+    sizes = rng.integers(2, 9, 8)
+    n = int(sizes.sum())
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.sort(rng.uniform(-3.0, 3.0, n))
+    d = (q * lam) @ q.T
+    d = 0.5 * (d + d.T)
+    m = _dense_to_bsr(d, sizes)
+    gaps = np.diff(lam)
+    k = int(np.argmax(gaps[n // 4:3 * n // 4])) + n // 4 + 1    # k eigenvalues below the gap
+    mu, x, rec, status = orc.mu_bisect(m, k, lam[0] - 1.0, lam[-1] + 1.0, count_tol=0.25,
+                                       eps=0.0, tol=1e-12)
+    assert status == orc.OK
+    w = np.linalg.eigvalsh(d)
+    assert int((w < mu).sum()) == k
+    assert rec["count_hist"][-1] == pytest.approx(k, abs=1e-8)
+    ref, _ = _eig_sign(d - mu * np.eye(n))
+    assert _rel(x.to_dense(), ref) <= 1e-11
+
+
+def test_mu_bisect_reports_no_convergence(orc):
+    """A target no midpoint can reach within count_tol (half-integer with a
+    tight tolerance) ends with ENOCONV after max_steps, with the last mu."""
+    h = np.array([-1.0, 1.0, 2.0])
+    m = _diag_matrix(h, [1, 1, 1])
+    mu, x, rec, status = orc.mu_bisect(m, 1.5, -3.0, 3.0, count_tol=0.1, max_steps=6,
+                                       eps=0.0, tol=1e-12)
+    assert status == orc.ENOCONV and len(rec["mu_hist"]) == 6 and x is not None
