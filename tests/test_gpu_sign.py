@@ -188,7 +188,7 @@ def test_mu_bisect_vs_oracle(orc):
 
 def test_mu_bisect_rejects_bad_bracket():
     from paper_2003_03868_amd import bsm
-    h = synth.neighbour_hamiltonian(32, 5, cutoff=4.0, seed=1)
+    h = synth.neighbour_hamiltonian(64, 5, cutoff=4.0, seed=1)
     d = to_dev(h)
     for lo, hi, steps in [(1.0, -1.0, 10), (0.0, 1.0, 0), (0.0, 1.0, 65)]:
         with pytest.raises(bsm.BsmError) as e:
