@@ -22,6 +22,12 @@ Parity status of each function (what pins it, see ``tests/test_oracle.py``):
 * ``sign_ns`` orders 3, 5, 7 -- pinned: the printed polynomials (order 7:
                        derived in the test from its closed form) on diagonal
                        H, eigen-decomposition sign on tiny dense cases.
+* ``sqrt_inv``      -- pinned: eigen-decomposition S^{+-1/2} (LAPACK) on tiny
+                       dense SPD cases; the scalar coupled recurrence on
+                       diagonal S by hand.
+* ``density_nonorth`` -- pinned: P from the generalised eigenproblem
+                       K c = e S c (LAPACK) on tiny cases; P S P = P and
+                       trace(P S) = occupied count on filtered neighbour cases.
 * ``mu_bisect``     -- pinned: diagonal H, whose count is the number of
                        diagonal entries below mu, so every midpoint follows
                        by hand; on dense cases the accepted mu lies in the
@@ -98,6 +104,12 @@ def _load():
             lib.orc_add.argtypes = [C.c_double, P, C.c_double, P, C.c_double, C.c_double,
                                     C.c_int, P]
             lib.orc_density_from_sign.argtypes = [P, P]
+            lib.orc_sqrt_inv.argtypes = [P, C.c_double, C.c_int, C.c_double, C.c_int32, P, P,
+                                         C.POINTER(_SignStats)]
+            lib.orc_density_nonorth.argtypes = [P, P, C.c_double, C.c_double, C.c_int,
+                                                C.c_double, C.c_int32, C.c_int32, P,
+                                                C.POINTER(C.c_double), C.POINTER(_SignStats),
+                                                C.POINTER(_SignStats)]
             lib.orc_free.argtypes = [P]
             lib.orc_num_threads.restype = C.c_int
             _lib = lib
@@ -256,6 +268,49 @@ def mu_bisect(h: BSR, n_target: float, mu_lo: float, mu_hi: float, count_tol: fl
         else:
             hi = mu
     return mu, x, rec, ENOCONV
+
+
+def _stats(st) -> dict:
+    return dict(iterations=int(st.iterations), n_multiplies=int(st.n_multiplies),
+                r_hist=[float(st.r_hist[k]) for k in range(st.iterations + 1)],
+                scale=float(st.scale), trace_x=float(st.trace_x),
+                trace_p=float(st.trace_p), flops=float(st.flops))
+
+
+def sqrt_inv(s: BSR, eps: float = 0.0, tol: float = 1e-10, max_iter: int = 100, norm="frob"):
+    """S^{1/2} and S^{-1/2} of a symmetric positive definite S by the coupled
+    Newton-Schulz iteration (orc_sqrt_inv); returns (sqrt, inv_sqrt, stats,
+    status) with status OK or ENOCONV."""
+    lib = _load()
+    oh, kh = _in(s)
+    o1, o2 = _OMat(), _OMat()
+    st = _SignStats()
+    status = lib.orc_sqrt_inv(C.byref(oh), eps, _norm(norm), tol, max_iter, C.byref(o1),
+                              C.byref(o2), C.byref(st))
+    if status not in (OK, ENOCONV):
+        raise RuntimeError(f"oracle square-root iteration failed with status {status}")
+    return (_out(o1, s.row_blk_size, s.col_blk_size), _out(o2, s.row_blk_size, s.col_blk_size),
+            _stats(st), int(status))
+
+
+def density_nonorth(k: BSR, s: BSR, mu: float = 0.0, eps: float = 0.0, tol: float = 1e-10,
+                    max_iter: int = 100, norm="frob", order: int = 2):
+    """P = (I - sign(S^{-1} K - mu I)) S^{-1} / 2 through the symmetric form
+    Z (I - sign(Z K Z - mu I)) Z / 2 with Z = S^{-1/2} (orc_density_nonorth);
+    returns (P, trace(P S), sqrt stats, sign stats, status)."""
+    lib = _load()
+    ok_, kk = _in(k)
+    os_, ks = _in(s)
+    out = _OMat()
+    tps = C.c_double()
+    s1, s2 = _SignStats(), _SignStats()
+    status = lib.orc_density_nonorth(C.byref(ok_), C.byref(os_), mu, eps, _norm(norm), tol,
+                                     max_iter, order, C.byref(out), C.byref(tps), C.byref(s1),
+                                     C.byref(s2))
+    if status not in (OK, ENOCONV):
+        raise RuntimeError(f"oracle non-orthogonal density failed with status {status}")
+    return (_out(out, k.row_blk_size, k.col_blk_size), float(tps.value), _stats(s1), _stats(s2),
+            int(status))
 
 
 def density_from_sign(x: BSR) -> BSR:

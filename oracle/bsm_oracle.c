@@ -674,6 +674,154 @@ int orc_density_from_sign(const omat *x, omat *p)
     return orc_shift_scale(x, 1.0, -0.5, p);
 }
 
+/* ------------------------------------------- non-orthogonal basis (S != I) */
+
+/*
+ * S^{1/2} and S^{-1/2} of a symmetric positive definite S by the coupled
+ * Newton-Schulz iteration: the second-order sign iteration applied to the
+ * block matrix [[0, A], [I, 0]], whose sign is [[0, A^{1/2}], [A^{-1/2}, 0]]
+ * (the relation of the Sign-Method section used for inverses and square
+ * roots).  With X_k = [[0, Y_k], [Z_k, 0]] the update X(3I - X^2)/2 acts on
+ * the two blocks; with T = Z Y:
+ *
+ *   s = ||S||_inf                         (Gershgorin bound: spectrum of S/s in (0, 1])
+ *   Y_0 = S / s,  Z_0 = I
+ *   for k = 0, 1, ...:
+ *       T   = filter(Z_k Y_k)             (k = 0: T = Y_0, no product)
+ *       r_k = ||T - I||_F / n;  stop if r_k < tol
+ *       W   = 1.5 I - 0.5 T               (not filtered)
+ *       Y_{k+1} = filter(Y_k W),  Z_{k+1} = filter(W Z_k)   (k = 0: Z_1 = W)
+ *   S^{1/2} = sqrt(s) Y,  S^{-1/2} = Z / sqrt(s)
+ *
+ * The stall and max_iter rules are those of orc_sign; st->r_hist holds r_k,
+ * st->scale holds s.  Both outputs are returned for OK and ENOCONV.
+ */
+int orc_sqrt_inv(const omat *s_in, double eps, int norm_kind, double tol, int32_t max_iter,
+                 omat *sqrt_out, omat *isqrt_out, orc_sign_stats *st)
+{
+    if (s_in->nbrows != s_in->nbcols || eps < 0 || max_iter < 0 || max_iter > 120)
+        return ORC_EINVAL;
+    for (int32_t i = 0; i < s_in->nbrows; ++i) if (s_in->rbs[i] != s_in->cbs[i]) return ORC_EINVAL;
+    memset(st, 0, sizeof(*st));
+    double n = 0.0;
+    for (int32_t i = 0; i < s_in->nbrows; ++i) n += s_in->rbs[i];
+    const double sc = orc_inf_norm_shifted(s_in, 0.0);
+    st->scale = sc;
+    if (!isfinite(sc)) return ORC_ENONFINITE;
+    if (sc == 0.0) return ORC_EINVAL;
+    omat y = {0}, z = {0}, t = {0}, w = {0}, yn = {0}, zn = {0};
+    int have_z = 0;                 /* Z_0 = I is implicit */
+    int status = orc_shift_scale(s_in, 0.0, 1.0 / sc, &y);
+    int stall = 0;
+    for (int32_t k = 0; status == ORC_OK; ++k) {
+        if (have_z) {
+            st->flops += product_flops(&z, &y);
+            st->n_multiplies++;
+            status = orc_multiply(1.0, &z, &y, 0.0, NULL, eps, norm_kind, &t);
+        } else {
+            status = orc_shift_scale(&y, 0.0, 1.0, &t);     /* T_0 = Y_0 */
+        }
+        if (status != ORC_OK) break;
+        const double r = sqrt(orc_sqdist_identity(&t, 1.0)) / n;
+        st->r_hist[k] = r;
+        st->iterations = k;
+        if (!isfinite(r)) { status = ORC_ENONFINITE; break; }
+        if (r < tol) break;
+        if (k > 0 && r >= st->r_hist[k - 1]) { if (++stall >= 3) { status = ORC_ENOCONV; break; } }
+        else stall = 0;
+        if (k >= max_iter) { status = ORC_ENOCONV; break; }
+        status = orc_shift_scale(&t, 3.0, -0.5, &w);          /* 1.5 I - 0.5 T */
+        orc_free(&t);
+        if (status == ORC_OK) {
+            st->flops += product_flops(&y, &w);
+            st->n_multiplies++;
+            status = orc_multiply(1.0, &y, &w, 0.0, NULL, eps, norm_kind, &yn);
+        }
+        if (status == ORC_OK) {
+            if (have_z) {
+                st->flops += product_flops(&w, &z);
+                st->n_multiplies++;
+                status = orc_multiply(1.0, &w, &z, 0.0, NULL, eps, norm_kind, &zn);
+            } else {
+                zn = w;                                       /* Z_1 = W Z_0 = W */
+                memset(&w, 0, sizeof(w));
+            }
+        }
+        orc_free(&w);
+        if (status != ORC_OK) break;
+        orc_free(&y); orc_free(&z);
+        y = yn; z = zn;
+        memset(&yn, 0, sizeof(yn)); memset(&zn, 0, sizeof(zn));
+        have_z = 1;
+    }
+    orc_free(&t); orc_free(&yn); orc_free(&zn);
+    if (status == ORC_OK || status == ORC_ENOCONV) {
+        int s2 = orc_shift_scale(&y, 0.0, sqrt(sc), sqrt_out);
+        if (s2 == ORC_OK) {
+            if (have_z) {
+                s2 = orc_shift_scale(&z, 0.0, 1.0 / sqrt(sc), isqrt_out);
+            } else {
+                /* stopped at k = 0, Z_0 = I: I / sqrt(s) with only the diagonal
+                   blocks, as (1/sqrt(s)) (E + I) of the empty matrix E */
+                int64_t *rp = (int64_t *)calloc((size_t)s_in->nbrows + 1, sizeof(int64_t));
+                if (!rp) {
+                    s2 = ORC_ENOMEM;
+                } else {
+                    omat e = {s_in->nbrows, s_in->nbcols, s_in->rbs, s_in->cbs, 0, rp, NULL, NULL};
+                    s2 = orc_shift_scale(&e, -1.0, 1.0 / sqrt(sc), isqrt_out);
+                    free(rp);
+                }
+            }
+        }
+        if (s2 != ORC_OK) status = s2;
+    }
+    orc_free(&y); orc_free(&z);
+    return status;
+}
+
+/*
+ * Density matrix in a non-orthogonal basis, P = (I - sign(S^{-1} K - mu I))
+ * S^{-1} / 2 (Sign-Method section, density relation), through its symmetric
+ * form: with Z = S^{-1/2}, S^{-1} K - mu I = Z (K~ - mu I) Z^{-1} for
+ * K~ = Z K Z, so sign(S^{-1} K - mu I) = Z sign(K~ - mu I) Z^{-1} and
+ *
+ *   P = Z (I - sign(K~ - mu I)) Z / 2.
+ *
+ * Steps: Z from orc_sqrt_inv (eps, tol, max_iter); K~ = filter(filter(Z K) Z);
+ * X = orc_sign(K~, mu) of the given order; P~ = (I - X)/2;
+ * P = filter(filter(Z P~) Z).  trace(P S) = trace(P~ Z S Z) = trace(P~) is
+ * returned in *trace_ps.  Statuses: EINVAL for mismatched shapes; the first
+ * non-OK status of the square root or the sign iteration (ENOCONV still
+ * returns P).
+ */
+int orc_density_nonorth(const omat *k, const omat *s_in, double mu, double eps, int norm_kind,
+                        double tol, int32_t max_iter, int32_t order, omat *p_out,
+                        double *trace_ps, orc_sign_stats *st_sqrt, orc_sign_stats *st_sign)
+{
+    if (k->nbrows != s_in->nbrows || k->nbcols != s_in->nbcols) return ORC_EINVAL;
+    for (int32_t i = 0; i < k->nbrows; ++i) if (k->rbs[i] != s_in->rbs[i]) return ORC_EINVAL;
+    omat sq = {0}, z = {0}, k1 = {0}, kt = {0}, x = {0}, pt = {0}, p1 = {0};
+    memset(st_sign, 0, sizeof(*st_sign));
+    int status = orc_sqrt_inv(s_in, eps, norm_kind, tol, max_iter, &sq, &z, st_sqrt);
+    int first = status;
+    if (status == ORC_OK || status == ORC_ENOCONV)
+        status = orc_multiply(1.0, &z, k, 0.0, NULL, eps, norm_kind, &k1);
+    if (status == ORC_OK) status = orc_multiply(1.0, &k1, &z, 0.0, NULL, eps, norm_kind, &kt);
+    if (status == ORC_OK) {
+        status = orc_sign(&kt, mu, eps, norm_kind, tol, max_iter, 0, order, &x, st_sign);
+        if (first == ORC_OK) first = status;
+    }
+    if (status == ORC_OK || status == ORC_ENOCONV) {
+        int s2 = orc_density_from_sign(&x, &pt);
+        if (s2 == ORC_OK) { *trace_ps = orc_trace(&pt); s2 = orc_multiply(1.0, &z, &pt, 0.0, NULL, eps, norm_kind, &p1); }
+        if (s2 == ORC_OK) s2 = orc_multiply(1.0, &p1, &z, 0.0, NULL, eps, norm_kind, p_out);
+        status = (s2 == ORC_OK) ? first : s2;
+    }
+    orc_free(&sq); orc_free(&z); orc_free(&k1); orc_free(&kt); orc_free(&x); orc_free(&pt);
+    orc_free(&p1);
+    return status;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -23,6 +23,9 @@ Recipes (all seeded through ``numpy.random.default_rng(seed)``):
   atomic basis, blocks present when the minimum-image distance is below the
   cutoff, entries ``exp(-0.5 r) * N(0, 1)``, symmetrised, and the diagonal
   shifted by +-Delta so that a gap is certified around mu = 0 (Gershgorin).
+* :func:`overlap_like` -- a symmetric positive definite overlap matrix S with
+  the block pattern of a symmetric matrix: I plus decaying random couplings
+  scaled so that Gershgorin keeps the spectrum in [1 - tau, 1 + tau].
 """
 from __future__ import annotations
 
@@ -31,7 +34,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "BSR", "random_bsr", "random_bsr_pair", "neighbour_hamiltonian",
+    "BSR", "random_bsr", "random_bsr_pair", "neighbour_hamiltonian", "overlap_like",
     "n_occ_for_block", "config_workload", "mnk_stack",
 ]
 
@@ -331,3 +334,69 @@ def mnk_stack(m: int, n: int, k: int, n_products: int, n_c_blocks: int,
     ai = rng.integers(0, n_a, n_products).astype(np.int32)
     bi = rng.integers(0, n_b, n_products).astype(np.int32)
     return a, b, ai, bi, c_of
+
+
+def overlap_like(h: BSR, tau: float = 0.5, seed: int = 0) -> BSR:
+    """Overlap matrix S = I + tau * N / M with the block pattern of ``h``.
+
+    ``h`` must have a symmetric block pattern with square diagonal blocks.
+    N is symmetric: for each stored pair I < J a block ``G_IJ * w_IJ`` with
+    ``G_IJ ~ N(0, 1)`` (drawn in CSR order of the upper triangle) and
+    ``N_JI = N_IJ^T``; diagonal blocks ``(G_II + G_II^T)/2`` with a zero
+    diagonal.  ``w_IJ = exp(-r_IJ)`` with the minimum-image site distance
+    when ``h.meta`` holds positions and a box, else 1.  M is the largest
+    scalar row abs-sum of N, so every Gershgorin disc of S lies in
+    [1 - tau, 1 + tau] and S is positive definite for tau < 1.
+    """
+    if not 0.0 <= tau < 1.0:
+        raise ValueError("tau must be in [0, 1)")
+    rng = np.random.default_rng(seed)
+    rows = h.block_rows()
+    cols = h.col_idx.astype(np.int64)
+    off = h.block_offsets()
+    rbs, cbs = h.row_blk_size, h.col_blk_size
+    if h.nbrows != h.nbcols or not np.array_equal(rbs, cbs) or \
+            int((rows == cols).sum()) != h.nbrows:
+        raise ValueError("h must be square with every diagonal block stored")
+    pos, box = h.meta.get("positions"), h.meta.get("box")
+    where = {(int(i), int(j)): t for t, (i, j) in enumerate(zip(rows, cols))}
+    values = np.zeros_like(h.values)
+    for t in range(h.nnzb):
+        i, j = int(rows[t]), int(cols[t])
+        if i > j:
+            continue
+        m, n = int(rbs[i]), int(cbs[j])
+        w = 1.0
+        if pos is not None and box is not None and i != j:
+            d = pos[i] - pos[j]
+            d -= box * np.round(d / box)
+            w = float(np.exp(-np.sqrt(float(d @ d))))
+        g = rng.standard_normal((m, n)) * w
+        if i == j:
+            g = 0.5 * (g + g.T)
+            g[np.arange(m), np.arange(m)] = 0.0
+        values[off[t]:off[t + 1]] = g.ravel()
+        if i != j:
+            tt = where.get((j, i))
+            if tt is None:
+                raise ValueError("the block pattern of h must be symmetric")
+            values[off[tt]:off[tt + 1]] = g.T.ravel()
+    # scalar row abs-sums of N
+    scal = np.concatenate([[0], np.cumsum(rbs, dtype=np.int64)])
+    rowsum = np.zeros(int(scal[-1]))
+    for t in range(h.nnzb):
+        i, j = int(rows[t]), int(cols[t])
+        m, n = int(rbs[i]), int(cbs[j])
+        rowsum[scal[i]:scal[i] + m] += np.abs(values[off[t]:off[t + 1]].reshape(m, n)).sum(1)
+    big = float(rowsum.max()) if rowsum.size else 0.0
+    if big > 0.0:
+        values *= tau / big
+    for t in range(h.nnzb):
+        i, j = int(rows[t]), int(cols[t])
+        if i == j:
+            m = int(rbs[i])
+            blk = values[off[t]:off[t + 1]].reshape(m, m)
+            blk[np.arange(m), np.arange(m)] += 1.0
+    s = BSR(rbs.copy(), cbs.copy(), h.row_ptr.copy(), h.col_idx.copy(), values)
+    s.meta.update(dict(tau=tau, seed=seed))
+    return s

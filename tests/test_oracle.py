@@ -570,3 +570,97 @@ def test_mu_bisect_reports_no_convergence(orc):
     mu, x, rec, status = orc.mu_bisect(m, 1.5, -3.0, 3.0, count_tol=0.1, max_steps=6,
                                        eps=0.0, tol=1e-12)
     assert status == orc.ENOCONV and len(rec["mu_hist"]) == 6 and x is not None
+
+
+# --------------------------------------------- non-orthogonal basis (S != I)
+
+def _spd(rng, n, lo=0.3, hi=2.0):
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    d = (q * rng.uniform(lo, hi, n)) @ q.T
+    return 0.5 * (d + d.T)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_sqrt_inv_matches_eigh(orc, seed):
+    """Coupled iteration on tiny dense SPD matrices: S^{1/2} and S^{-1/2}
+    against the eigen-decomposition (LAPACK)."""
+    rng = np.random.default_rng(80 + seed)
+    sizes = rng.integers(1, 9, 7)
+    n = int(sizes.sum())
+    d = _spd(rng, n)
+    w, v = np.linalg.eigh(d)
+    ref_sqrt = (v * np.sqrt(w)) @ v.T
+    ref_isqrt = (v / np.sqrt(w)) @ v.T
+    sq, isq, st, status = orc.sqrt_inv(_dense_to_bsr(d, sizes), eps=0.0, tol=1e-14)
+    assert status == orc.OK
+    assert _rel(sq.to_dense(), ref_sqrt) <= 1e-12
+    assert _rel(isq.to_dense(), ref_isqrt) <= 1e-12
+    assert st["n_multiplies"] == 3 * st["iterations"] - 1
+
+
+def test_sqrt_inv_diagonal_by_hand(orc):
+    """Diagonal S: the coupled iteration decouples into the scalar
+    recurrence y <- y w, z <- w z, w = -0.5 (z y - 3), from y = s/||S||_inf,
+    z = 1 (first step: t = y, z_1 = w), evaluated here in the same order."""
+    rng = np.random.default_rng(31)
+    sizes = rng.integers(1, 6, 9)
+    sv = rng.uniform(0.2, 3.0, int(sizes.sum()))
+    n = sv.size
+    m = _diag_matrix(sv, sizes)
+    sq, isq, st, status = orc.sqrt_inv(m, eps=0.0, tol=1e-13)
+    assert status == orc.OK
+    sc = sv.max()
+    y = sv * (1.0 / sc)
+    z = None
+    rs = []
+    for k in range(100):
+        t = y if z is None else z * y
+        rs.append(math.sqrt(float(((t - 1.0) ** 2).sum())) / n)
+        if rs[-1] < 1e-13:
+            break
+        w = -0.5 * (t - 3.0)
+        y, z = y * w, (w if z is None else w * z)
+    assert st["iterations"] == k
+    assert np.allclose(st["r_hist"], rs, rtol=1e-12, atol=0)
+    assert np.array_equal(np.diag(sq.to_dense()), math.sqrt(sc) * (y - 0.0))
+    assert np.array_equal(np.diag(isq.to_dense()), (1.0 / math.sqrt(sc)) * (z - 0.0))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_density_nonorth_matches_generalised_eigh(orc, seed):
+    """P = (I - sign(S^{-1} K - mu I)) S^{-1} / 2 equals C_occ C_occ^T for the
+    S-orthonormal eigenvectors of K c = e S c with e < mu (LAPACK), and
+    trace(P S) is their number."""
+    import scipy.linalg
+    rng = np.random.default_rng(90 + seed)
+    sizes = rng.integers(1, 8, 7)
+    n = int(sizes.sum())
+    s = _spd(rng, n, 0.5, 1.5)
+    kq, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    k = (kq * (rng.uniform(0.2, 2.0, n) * rng.choice([-1.0, 1.0], n))) @ kq.T
+    k = 0.5 * (k + k.T)
+    mu = 0.05
+    e, c = scipy.linalg.eigh(k, s)
+    occ = c[:, e < mu]
+    p_ref = occ @ occ.T
+    p, tps, st1, st2, status = orc.density_nonorth(_dense_to_bsr(k, sizes), _dense_to_bsr(s, sizes),
+                                                   mu=mu, eps=0.0, tol=1e-13)
+    assert status == orc.OK
+    assert _rel(p.to_dense(), p_ref) <= 1e-10
+    assert tps == pytest.approx(int((e < mu).sum()), abs=1e-9)
+    pd = p.to_dense()
+    assert _rel(pd @ s @ pd, pd) <= 1e-10
+
+
+def test_density_nonorth_neighbour_invariants(orc):
+    """Filtered run on a neighbour Hamiltonian with a decaying overlap: the
+    occupied count is the inertia of K (Sylvester: Z K Z is congruent to K),
+    and P S P = P to the filter's accuracy."""
+    h = synth.neighbour_hamiltonian(100, 5, cutoff=4.5, seed=7)
+    s = synth.overlap_like(h, 0.4, seed=2)
+    p, tps, st1, st2, status = orc.density_nonorth(h, s, eps=1e-8, tol=1e-8)
+    assert status == orc.OK
+    assert tps == pytest.approx(h.meta["n_occ"], abs=1e-4)
+    pd, sd = p.to_dense(), s.to_dense()
+    assert _rel(pd @ sd @ pd, pd) <= 1e-5
+    assert float(np.trace(pd @ sd)) == pytest.approx(h.meta["n_occ"], abs=1e-3)

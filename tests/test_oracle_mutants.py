@@ -32,6 +32,16 @@ MUTANTS = [
      "orc_multiply(1.0, y, y, 0.0, NULL, eps, norm_kind, &y3);"),
     ("o7_cin", "orc_add(9009.0, &y2, -6006.0, y, 3003.0,", "orc_add(9009.0, &y2, -6006.0, y, 3030.0,"),
     ("o7_scale", "orc_multiply(1.0 / 1024.0, x, &w,", "orc_multiply(1.0 / 512.0, x, &w,"),
+    ("sqrt_w_coefficient", "status = orc_shift_scale(&t, 3.0, -0.5, &w);",
+     "status = orc_shift_scale(&t, 3.0, -0.45, &w);"),
+    ("sqrt_scale", "int s2 = orc_shift_scale(&y, 0.0, sqrt(sc), sqrt_out);",
+     "int s2 = orc_shift_scale(&y, 0.0, sc, sqrt_out);"),
+    ("isqrt_scale", "s2 = orc_shift_scale(&z, 0.0, 1.0 / sqrt(sc), isqrt_out);",
+     "s2 = orc_shift_scale(&z, 0.0, 1.0 / sc, isqrt_out);"),
+    ("nonorth_one_sided", "status = orc_multiply(1.0, &k1, &z, 0.0, NULL, eps, norm_kind, &kt);",
+     "status = orc_shift_scale(&k1, 0.0, 1.0, &kt);"),
+    ("nonorth_back", "s2 = orc_multiply(1.0, &p1, &z, 0.0, NULL, eps, norm_kind, p_out);",
+     "s2 = orc_shift_scale(&p1, 0.0, 1.0, p_out);"),
     ("add_gamma", "tmp[r * m + r] = tmp[r * m + r] + gamma;", "tmp[r * m + r] = tmp[r * m + r] - gamma;"),
     ("add_b_index", "tmp[e] = tmp[e] + beta * b->values[offb[tb] + e];",
      "tmp[e] = tmp[e] + beta * b->values[offb[tb]];"),
