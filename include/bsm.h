@@ -265,6 +265,41 @@ int bsm_mu_bisect(bsm_matrix H, double n_target, double mu_lo, double mu_hi, dou
                   int32_t max_steps, const bsm_sign_opts *opts, double *mu_out,
                   bsm_matrix *x_out, bsm_mu_stats *stats, void *stream);
 
+/*
+ * S^{1/2} and S^{-1/2} of a symmetric positive definite S (non-orthogonal
+ * basis) by the coupled Newton-Schulz iteration, i.e. the second-order sign
+ * iteration on [[0, S], [I, 0]], whose sign is [[0, S^{1/2}], [S^{-1/2}, 0]]
+ * (the Sign-Method section's relation for inverses and square roots):
+ *   s = ||S||_inf;  Y_0 = S/s;  Z_0 = I;
+ *   loop k: T = filter(Z_k Y_k) (k = 0: T = Y_0); r_k = ||T - I||_F / n;
+ *           stop if r_k < tol;  W = 1.5 I - 0.5 T;
+ *           Y_{k+1} = filter(Y_k W);  Z_{k+1} = filter(W Z_k) (k = 0: Z_1 = W);
+ *   S^{1/2} = sqrt(s) Y,  S^{-1/2} = Z / sqrt(s).
+ * opts: eps_filter, norm, tol, max_iter (0..120) are used (FP64 products).
+ * stats (may be NULL): iterations, r_hist, scale = s, multiplies, flops.
+ * Both results are new handles (caller destroys) for BSM_OK and BSM_ENOCONV
+ * (r_k grew three times in a row or max_iter reached); BSM_EINVAL for a
+ * non-square S or bad options, BSM_ENONFINITE for NaN/Inf.  Waits.
+ */
+int bsm_sqrt_inv(bsm_matrix S, const bsm_sign_opts *opts, bsm_matrix *sqrt_out,
+                 bsm_matrix *isqrt_out, bsm_sign_stats *stats, void *stream);
+
+/*
+ * Density matrix in a non-orthogonal basis, P = (I - sign(S^{-1} K - mu I))
+ * S^{-1} / 2 (Sign-Method section), through the symmetric form with
+ * Z = S^{-1/2} (bsm_sqrt_inv): sign(S^{-1} K - mu I) = Z sign(Z K Z - mu I) Z^{-1},
+ * so P = Z (I - sign(K~ - mu I)) Z / 2 with K~ = filter(filter(Z K) Z), the
+ * sign by bsm_sign_iterate (opts, any order), and P = filter(filter(Z P~) Z).
+ * *trace_ps (may be NULL) gets trace(P S) = trace(P~), the electron count.
+ * sqrt_stats / sign_stats (may be NULL): the two iterations; sign_stats also
+ * counts the four transform multiplies.  P is a new handle for BSM_OK and
+ * BSM_ENOCONV (either iteration stopped early); BSM_EINVAL when K and S
+ * differ in block sizes.  Waits.
+ */
+int bsm_density_nonorth(bsm_matrix K, bsm_matrix S, double mu, const bsm_sign_opts *opts,
+                        bsm_matrix *p_out, double *trace_ps, bsm_sign_stats *sqrt_stats,
+                        bsm_sign_stats *sign_stats, void *stream);
+
 /* P = (I - X)/2 from a sign matrix X, as a new handle; trace_p (may be NULL) gets trace(P). */
 int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void *stream);
 

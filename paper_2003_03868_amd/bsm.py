@@ -98,6 +98,12 @@ _SIGS = [
     ("bsm_mu_bisect", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double,
                                 C.c_int32, C.POINTER(bsm_sign_opts), C.POINTER(C.c_double),
                                 C.POINTER(C.c_void_p), C.POINTER(bsm_mu_stats), C.c_void_p]),
+    ("bsm_sqrt_inv", C.c_int, [C.c_void_p, C.POINTER(bsm_sign_opts), C.POINTER(C.c_void_p),
+                               C.POINTER(C.c_void_p), C.POINTER(bsm_sign_stats), C.c_void_p]),
+    ("bsm_density_nonorth", C.c_int, [C.c_void_p, C.c_void_p, C.c_double,
+                                      C.POINTER(bsm_sign_opts), C.POINTER(C.c_void_p),
+                                      C.POINTER(C.c_double), C.POINTER(bsm_sign_stats),
+                                      C.POINTER(bsm_sign_stats), C.c_void_p]),
     ("bsm_density_from_sign", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p),
                                         C.POINTER(C.c_double), C.c_void_p]),
     ("bsm_smm_bench", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
@@ -255,6 +261,33 @@ def bsm_mu_bisect(h, n_target, mu_lo, mu_hi, count_tol=0.5, max_steps=40,
     if st not in (OK, ENOCONV):
         _check(st, "bsm_mu_bisect")
     return st, mu.value, out.value, stats
+
+
+def bsm_sqrt_inv(s, opts: bsm_sign_opts | None = None, stream=None):
+    """Returns (status, S^{1/2} handle, S^{-1/2} handle, stats); ENOCONV is
+    returned, not raised (both handles are still set)."""
+    a, b = C.c_void_p(), C.c_void_p()
+    stats = bsm_sign_stats()
+    o = opts if opts is not None else bsm_sign_opts_default()
+    st = load().bsm_sqrt_inv(s, C.byref(o), C.byref(a), C.byref(b), C.byref(stats),
+                             _stream(stream))
+    if st not in (OK, ENOCONV):
+        _check(st, "bsm_sqrt_inv")
+    return st, a.value, b.value, stats
+
+
+def bsm_density_nonorth(k, s, mu=0.0, opts: bsm_sign_opts | None = None, stream=None):
+    """Returns (status, P handle, trace(P S), sqrt stats, sign stats); ENOCONV
+    is returned, not raised."""
+    p = C.c_void_p()
+    tps = C.c_double()
+    s1, s2 = bsm_sign_stats(), bsm_sign_stats()
+    o = opts if opts is not None else bsm_sign_opts_default()
+    st = load().bsm_density_nonorth(k, s, float(mu), C.byref(o), C.byref(p), C.byref(tps),
+                                    C.byref(s1), C.byref(s2), _stream(stream))
+    if st not in (OK, ENOCONV):
+        _check(st, "bsm_density_nonorth")
+    return st, p.value, tps.value, s1, s2
 
 
 def bsm_add(alpha, a, beta=0.0, b=None, gamma=0.0, eps_filter=0.0, norm=0, stream=None) -> int:

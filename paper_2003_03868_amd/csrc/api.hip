@@ -9,6 +9,11 @@ namespace bsm {
 const char *last_error();
 int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sign_stats *st,
                  hipStream_t s);
+int sqrt_inv_iterate(Mat &S, const bsm_sign_opts &o, Mat **sqrt_out, Mat **isqrt_out,
+                     bsm_sign_stats *st, hipStream_t s);
+int density_nonorth(Mat &K, Mat &S, double mu, const bsm_sign_opts &o, Mat **p_out,
+                    double *trace_ps, bsm_sign_stats *st_sqrt, bsm_sign_stats *st_sign,
+                    hipStream_t s);
 }  // namespace bsm
 
 using bsm::Mat;
@@ -304,6 +309,52 @@ int bsm_mu_bisect(bsm_matrix H, double n_target, double mu_lo, double mu_hi, dou
         delete x;
         *x_out = h;
     }
+    return rc;
+}
+
+static bsm_matrix wrap(Mat *m) {
+    auto *h = new bsm_matrix_s;
+    h->m = std::move(*m);
+    delete m;
+    return h;
+}
+
+int bsm_sqrt_inv(bsm_matrix S, const bsm_sign_opts *opts, bsm_matrix *sqrt_out,
+                 bsm_matrix *isqrt_out, bsm_sign_stats *stats, void *stream) {
+    bsm::clear_error();
+    if (!S || !sqrt_out || !isqrt_out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    *sqrt_out = nullptr;
+    *isqrt_out = nullptr;
+    bsm_sign_opts o;
+    if (opts) o = *opts; else bsm_sign_opts_default(&o);
+    bsm_sign_stats local;
+    bsm_sign_stats *st = stats ? stats : &local;
+    std::memset(st, 0, sizeof(*st));
+    Mat *a = nullptr, *b = nullptr;
+    const int rc = bsm::sqrt_inv_iterate(S->m, o, &a, &b, st, as_stream(stream));
+    if (a) *sqrt_out = wrap(a);
+    if (b) *isqrt_out = wrap(b);
+    return rc;
+}
+
+int bsm_density_nonorth(bsm_matrix K, bsm_matrix S, double mu, const bsm_sign_opts *opts,
+                        bsm_matrix *p_out, double *trace_ps, bsm_sign_stats *sqrt_stats,
+                        bsm_sign_stats *sign_stats, void *stream) {
+    bsm::clear_error();
+    if (!K || !S || !p_out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    *p_out = nullptr;
+    bsm_sign_opts o;
+    if (opts) o = *opts; else bsm_sign_opts_default(&o);
+    bsm_sign_stats l1, l2;
+    bsm_sign_stats *s1 = sqrt_stats ? sqrt_stats : &l1;
+    bsm_sign_stats *s2 = sign_stats ? sign_stats : &l2;
+    std::memset(s1, 0, sizeof(*s1));
+    std::memset(s2, 0, sizeof(*s2));
+    double tps = 0.0;
+    Mat *p = nullptr;
+    const int rc = bsm::density_nonorth(K->m, S->m, mu, o, &p, &tps, s1, s2, as_stream(stream));
+    if (trace_ps) *trace_ps = tps;
+    if (p) *p_out = wrap(p);
     return rc;
 }
 
