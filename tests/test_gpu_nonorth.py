@@ -55,7 +55,8 @@ def test_sqrt_inv_of_identity_stops_at_once(orc):
     vals = np.concatenate([(2.0 * np.eye(b)).ravel() for b in sizes])
     s = BSR(sizes, sizes, np.arange(5), np.arange(4), vals)
     sq_ref, isq_ref, st_ref, _ = orc.sqrt_inv(s, eps=0.0, tol=1e-12)
-    st, a, b, stats = bsm.bsm_sqrt_inv(to_dev(s).handle, _opts(0.0, 1e-12))
+    d = to_dev(s)                      # keep the handle alive during the call
+    st, a, b, stats = bsm.bsm_sqrt_inv(d.handle, _opts(0.0, 1e-12))
     assert st == bsm.OK and stats.iterations == 0 and stats.n_multiplies == 0
     assert_same_matrix(from_dev(bsm.Matrix(a, sizes, sizes)), sq_ref, 1e-15, "sqrt(2 I)")
     got = from_dev(bsm.Matrix(b, sizes, sizes))
@@ -74,7 +75,8 @@ def test_density_nonorth_vs_oracle(orc, case):
         h, s, eps=case["eps"], tol=1e-8, order=case["order"])
     o = _opts(case["eps"], 1e-8)
     o.order = case["order"]
-    st, p, tps, st1, st2 = bsm.bsm_density_nonorth(to_dev(h).handle, to_dev(s).handle, 0.0, o)
+    dh, ds = to_dev(h), to_dev(s)      # keep the handles alive during the call
+    st, p, tps, st1, st2 = bsm.bsm_density_nonorth(dh.handle, ds.handle, 0.0, o)
     assert st == s_ref == bsm.OK, bsm.bsm_last_error()
     assert st1.iterations == st1_ref["iterations"] and st2.iterations == st2_ref["iterations"]
     sz = h.row_blk_size
@@ -93,5 +95,6 @@ def test_density_nonorth_rejects_mismatched_sizes():
     h = synth.neighbour_hamiltonian(64, 5, cutoff=4.0, seed=1)
     a = synth.random_bsr(10, 10, 5, 5, 0.5, np.random.default_rng(0))
     with pytest.raises(bsm.BsmError) as e:
-        bsm.bsm_density_nonorth(to_dev(h).handle, to_dev(a).handle, 0.0)
+        dh, da = to_dev(h), to_dev(a)
+        bsm.bsm_density_nonorth(dh.handle, da.handle, 0.0)
     assert e.value.status == bsm.EINVAL
