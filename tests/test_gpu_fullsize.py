@@ -1,0 +1,109 @@
+"""Parity at the full sign workload (2048 sites x 23, cutoff 6 A, eps_filter
+1e-6, tol 1e-6), in the launch configuration the benchmark times (default
+kernels and chunking): sampled block rows of full-size products against the
+oracle computed row by row, and properties of the full sign iteration that
+hold at any size."""
+import numpy as np
+import pytest
+
+import synth
+from synth import BSR
+from tests.gpu_util import TOL_FP64_MULTIPLY, from_dev, need_gpu, rel_fro, to_dev
+
+pytestmark = pytest.mark.gpu
+
+EPS = 1e-6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.fixture(scope="module")
+def h23():
+    return synth.neighbour_hamiltonian(2048, 23, density=0.1, cutoff=6.0, seed=0)
+
+
+def _rows(m: BSR, sel) -> BSR:
+    """The block rows `sel` of m as a matrix of their own."""
+    off = m.block_offsets()
+    rp, ci, va = [0], [], []
+    for i in sel:
+        a, b = int(m.row_ptr[i]), int(m.row_ptr[i + 1])
+        ci.append(m.col_idx[a:b])
+        va.append(m.values[off[a]:off[b]])
+        rp.append(rp[-1] + b - a)
+    return BSR(m.row_blk_size[sel], m.col_blk_size, np.array(rp), np.concatenate(ci),
+               np.concatenate(va))
+
+
+def _check_rows(orc, a: BSR, b: BSR, got: BSR, sel, what):
+    ref = orc.multiply(1.0, _rows(a, sel), b, eps=EPS)
+    mine = _rows(got, sel)
+    assert np.array_equal(mine.row_ptr, ref.row_ptr), f"{what}: block counts differ"
+    assert np.array_equal(mine.col_idx, ref.col_idx), f"{what}: block pattern differs"
+    err = rel_fro(mine.values, ref.values)
+    assert err <= TOL_FP64_MULTIPLY, f"{what}: relative error {err:.2e}"
+    return err, ref.nnzb
+
+
+def _multiply(x, shape_src: BSR):
+    from paper_2003_03868_amd import bsm
+    c = bsm.Matrix.empty_like(shape_src.row_blk_size, shape_src.col_blk_size)
+    st = bsm.bsm_multiply(1.0, x.handle, x.handle, 0.0, c.handle, EPS, bsm.NORM_FROB)
+    return c, st
+
+
+def test_first_product_sampled_rows(orc, h23):
+    """H H at full size (the first product of the iteration): 24 sampled
+    block rows against the oracle's product of those rows."""
+    dh = to_dev(h23)
+    c, st = _multiply(dh, h23)
+    got = from_dev(c)
+    sel = np.sort(np.random.default_rng(5).choice(h23.nbrows, 24, replace=False))
+    err, nb = _check_rows(orc, h23, h23, got, sel, "H H")
+    print(f"H H: {st.n_products} products in {st.smm_launches} launches; "
+          f"24 rows, {nb} blocks, err {err:.2e}")
+
+
+def test_sign_iteration_full_size(orc, h23):
+    """The benchmark's sign iteration: converged residual, trace(P) at the
+    occupied count to the filter's accuracy, X symmetric to the filter's
+    accuracy (sampled block pairs); then X X (the densest product of the
+    run) at full size, 8 sampled block rows against the oracle."""
+    from paper_2003_03868_amd import bsm
+    dh = to_dev(h23)
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol = EPS, 1e-6
+    st, xh, stats = bsm.bsm_sign_iterate(dh.handle, 0.0, o)
+    assert st == bsm.OK, bsm.bsm_last_error()
+    r = list(stats.r_hist)[:stats.iterations + 1]
+    assert r[-1] < 1e-6 and all(np.diff(r) < 0)
+    assert abs(stats.trace_p - h23.meta["n_occ"]) < 0.05
+    x = bsm.Matrix(xh, h23.row_blk_size, h23.col_blk_size)
+    xb = from_dev(x)
+    # symmetry on sampled stored blocks: X_IJ = X_JI^T
+    off = xb.block_offsets()
+    rows = xb.block_rows()
+    rng = np.random.default_rng(9)
+    where = {}
+    for t in rng.choice(xb.nnzb, 200, replace=False):
+        i, j = int(rows[t]), int(xb.col_idx[t])
+        a, b = int(xb.row_ptr[j]), int(xb.row_ptr[j + 1])
+        u = a + int(np.searchsorted(xb.col_idx[a:b], i))
+        assert u < b and xb.col_idx[u] == i, "X pattern is not symmetric"
+        xij = xb.values[off[t]:off[t + 1]].reshape(23, 23)
+        xji = xb.values[off[u]:off[u + 1]].reshape(23, 23)
+        where[(i, j)] = float(np.abs(xij - xji.T).max())
+    # the filter makes Y = filter(X X) commute with X only up to the dropped
+    # blocks, so the update's product X Y, and with it X, is symmetric only
+    # to about eps_filter
+    assert max(where.values()) < EPS
+    c, mst = _multiply(x, h23)
+    got = from_dev(c)
+    sel = np.sort(rng.choice(h23.nbrows, 8, replace=False))
+    err, nb = _check_rows(orc, xb, xb, got, sel, "X X")
+    print(f"sign: {stats.iterations} iterations, r {r[-1]:.2e}, trace(P) {stats.trace_p:.6f}; "
+          f"X X: {mst.n_products} products in {mst.smm_launches} launches; 8 rows, {nb} blocks, "
+          f"err {err:.2e}")
