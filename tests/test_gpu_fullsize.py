@@ -107,3 +107,47 @@ def test_sign_iteration_full_size(orc, h23):
     print(f"sign: {stats.iterations} iterations, r {r[-1]:.2e}, trace(P) {stats.trace_p:.6f}; "
           f"X X: {mst.n_products} products in {mst.smm_launches} launches; 8 rows, {nb} blocks, "
           f"err {err:.2e}")
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 2e-6), (2, 3e-5)], ids=["fp32", "split_bf16"])
+def test_first_product_reduced_precision_sampled_rows(orc, h23, prec, tol):
+    """H H at full size with FP32 or split-BF16 block products (eps 0, so the
+    pattern is the product pattern): 24 sampled block rows within the
+    precision's relative error bound of the FP64 oracle."""
+    from paper_2003_03868_amd import bsm
+    dh = to_dev(h23)
+    c = bsm.Matrix.empty_like(h23.row_blk_size, h23.col_blk_size)
+    bsm.bsm_multiply(1.0, dh.handle, dh.handle, 0.0, c.handle, 0.0, bsm.NORM_FROB, prec)
+    got = from_dev(c)
+    sel = np.sort(np.random.default_rng(6).choice(h23.nbrows, 24, replace=False))
+    ref = orc.multiply(1.0, _rows(h23, sel), h23)
+    mine = _rows(got, sel)
+    assert np.array_equal(mine.col_idx, ref.col_idx) and np.array_equal(mine.row_ptr, ref.row_ptr)
+    err = rel_fro(mine.values, ref.values)
+    assert 0.0 < err <= tol
+    print(f"H H prec {prec}: 24 rows, err {err:.2e}")
+
+
+def test_mixed_workload_full_size(orc):
+    """The mixed-size workload (4096 sites, blocks of 5, 13, 23, 26):
+    sampled block rows of H H against the oracle, and the sign iteration's
+    residual and trace(P)."""
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(4096, density=0.1, cutoff=6.0, seed=0,
+                                    size_choices=(5, 13, 23, 26))
+    dh = to_dev(h)
+    c, st = _multiply(dh, h)
+    got = from_dev(c)
+    sel = np.sort(np.random.default_rng(7).choice(h.nbrows, 24, replace=False))
+    err, nb = _check_rows(orc, h, h, got, sel, "mixed H H")
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol = EPS, 1e-6
+    s2, xh, stats = bsm.bsm_sign_iterate(dh.handle, 0.0, o)
+    assert s2 == bsm.OK, bsm.bsm_last_error()
+    r = list(stats.r_hist)[:stats.iterations + 1]
+    assert r[-1] < 1e-6 and all(np.diff(r) < 0)
+    assert abs(stats.trace_p - h.meta["n_occ"]) < 0.05
+    bsm.bsm_destroy(xh)
+    print(f"mixed: H H {st.n_products} products, 24 rows, {nb} blocks, err {err:.2e}; "
+          f"sign {stats.iterations} iterations, trace(P) {stats.trace_p:.6f} "
+          f"(n_occ {h.meta['n_occ']})")
