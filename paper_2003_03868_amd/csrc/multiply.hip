@@ -17,6 +17,7 @@
 // lists, the launches, the filter's keep-set and compaction maps) are kept in
 // plan-owned memory for numeric-only repetitions (plan.hip).
 #include <algorithm>
+#include <climits>
 #include <vector>
 
 #include "plan.h"
@@ -56,6 +57,18 @@ static bool lowp_quad(int prec) {
     const char *e = getenv("BSM_LOWP_QUAD");
     if (e) return atoi(e) != 0;
     return prec == BSM_SPLIT_BF16;
+}
+
+// k segments of the group lists' symbolic walk (one workgroup per row group
+// and segment, so the serial walk over the merged A rows is nseg times
+// shorter): one per 256 block columns of A, at most 8; BSM_QUAD_KSEG
+// overrides it (tests force several segments on small matrices).
+static int32_t quad_ksegments(int32_t nbk) {
+    const char *e = getenv("BSM_QUAD_KSEG");
+    int32_t v = e ? atoi(e) : nbk / 256;
+    if (v > 8 && !e) v = 8;
+    if (v > 64) v = 64;
+    return v < 1 ? 1 : v;
 }
 
 // Kernel family for a chunk with mixed block sizes (uniform sizes keep the
@@ -327,7 +340,8 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             Scratch ctmp(s);
             auto qbuf = [&](auto **ptr, size_t n) -> int { return pl ? keep_buf(ptr, n) : ctmp.get(ptr, n); };
             const int64_t npairs = (static_cast<int64_t>(r1 - r0) + G - 1) / G;
-            int64_t *q_off = nullptr, *q_cblk = nullptr, *e_off = nullptr, *q_order = nullptr;
+            int64_t *q_off = nullptr, *q_cblk = nullptr, *e_off = nullptr, *q_order = nullptr,
+                    *e_seg = nullptr;
             int32_t *q_col = nullptr;
             int4 *ent = nullptr;
             int64_t nq = 0, ne = 0;
@@ -339,6 +353,9 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             };
             QuadSymArgs qa{};
             qa.r0 = r0; qa.r1 = r1; qa.nbcols = B.nbcols; qa.g = G;
+            qa.nseg = quad_ksegments(A.nbcols);
+            qa.kseg = (A.nbcols + qa.nseg - 1) / qa.nseg;
+            if (qa.kseg < 1) qa.kseg = 1;
             qa.a_row_ptr = A.row_ptr; qa.a_col_idx = A.col_idx;
             qa.b_row_ptr = B.row_ptr; qa.b_col_idx = B.col_idx;
             qa.c_row_ptr = c_row_ptr; qa.c_col_idx = nc.col_idx;
@@ -348,11 +365,13 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             if (st == BSM_OK) st = read_total(q_off + npairs, &nq);
             if (st == BSM_OK) st = qbuf(&q_cblk, static_cast<size_t>(G) * G * nq);
             if (st == BSM_OK) st = qbuf(&e_off, nq + 1);
+            if (st == BSM_OK && qa.nseg > 1) st = qbuf(&e_seg, static_cast<size_t>(nq) * qa.nseg + 1);
+            if (qa.nseg == 1) e_seg = e_off;
             if (st == BSM_OK) st = qbuf(&q_col, nq);
             qa.q_off = q_off;
             qa.q_cblk = q_cblk;
             qa.q_col = q_col;
-            qa.e_off = e_off;
+            qa.e_off = e_seg;
             if (st == BSM_OK) st = quad_stack(qa, false, s);
             const int qr = quad_tile("BSM_QUAD_TILE_ROWS", 0), qc = quad_tile("BSM_QUAD_TILE_COLS", 16);
             if (st == BSM_OK && qr > 0 && nq > 0) {
@@ -361,8 +380,15 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
                     st = tile_order(q_off, q_col, static_cast<int32_t>(npairs), (B.nbcols + G - 1) / G,
                                     qr, q_order, s, qc);
             }
-            if (st == BSM_OK) st = scan_i64(e_off, e_off, nq, s);
-            if (st == BSM_OK) st = read_total(e_off + nq, &ne);
+            const int64_t nsl = nq * qa.nseg;                       // (group, segment) counts
+            if (st == BSM_OK) st = scan_i64(e_seg, e_seg, nsl, s);
+            if (st == BSM_OK && qa.nseg > 1) st = quad_seg_starts(e_seg, qa.nseg, nq, e_off, s);
+            if (st == BSM_OK) st = read_total(e_seg + nsl, &ne);
+            if (st == BSM_OK && ne > INT32_MAX) {
+                // the fill pass keeps entry offsets inside a row group as int32
+                set_error("more than 2^31 group entries in one chunk; lower BSM_CHUNK_PRODUCTS");
+                st = BSM_EINVAL;
+            }
             if (st == BSM_OK) st = qbuf(&ent, static_cast<size_t>(ne) * (G / 2));
             qa.ent = ent;
             if (st == BSM_OK) st = quad_stack(qa, true, s);

@@ -114,19 +114,25 @@ __global__ void __launch_bounds__(kQuadThreads)
 k_quad_stack(QuadSymArgs q) {
     extern __shared__ uint32_t smem[];
     __shared__ int64_t scratch[kQuadThreads / kWave];
-    __shared__ int64_t s_p[G];
-    __shared__ int32_t s_k, s_a[G];
+    __shared__ int64_t s_tb0, s_tb1;
+    __shared__ int32_t s_k, s_a[G], s_skip[G];
     const int nwq = quad_words(q.nbcols, G);   // words of the column-group bitmap
     uint32_t *bits = smem;
     int32_t *wpre = reinterpret_cast<int32_t *>(smem + nwq);
     int32_t *cnt = reinterpret_cast<int32_t *>(smem + 2 * nwq);
-    const int32_t R = blockIdx.x;
+    // fill pass: the window's entry offsets relative to its first group's
+    int32_t *eoff = cnt + kQuadWindow;
+    __shared__ int64_t s_ebase;
+    const int32_t R = blockIdx.x / q.nseg, sg = blockIdx.x % q.nseg;
     const int32_t i0 = q.r0 + G * R;
     const int nr = (q.r1 - i0 < G) ? q.r1 - i0 : G;
+    // this workgroup's k range
+    const int32_t k_lo = sg * q.kseg;
+    const int32_t k_hi = (sg == q.nseg - 1) ? INT_MAX : k_lo + q.kseg;
     quad_rank_map<G>(q, i0, nr, nwq, bits, wpre, scratch);
 
     const int64_t qbase = q.q_off[R], nq = q.q_off[R + 1] - qbase;
-    if (!FILL) {
+    if (!FILL && sg == 0) {
         // C blocks of every group: (r, c) at G G group + G r + c, -1 where absent
         for (int64_t t = threadIdx.x; t < G * G * nq; t += kQuadThreads) q.q_cblk[G * G * qbase + t] = -1;
         __syncthreads();
@@ -142,26 +148,71 @@ k_quad_stack(QuadSymArgs q) {
     for (int64_t w0 = 0; w0 < nq; w0 += kQuadWindow) {
         const int wn = static_cast<int>(nq - w0 < kQuadWindow ? nq - w0 : kQuadWindow);
         for (int t = threadIdx.x; t < wn; t += kQuadThreads) cnt[t] = 0;
-        if (threadIdx.x == 0)
-            for (int r = 0; r < G; ++r) s_p[r] = r < nr ? q.a_row_ptr[i0 + r] : 0;
+        if (threadIdx.x < G) s_skip[threadIdx.x] = 0;
+        if (FILL) {
+            // offsets of this segment's entries for the window's groups (a row
+            // group holds fewer than 2^31 entries, so int32 relative offsets)
+            if (threadIdx.x == 0) s_ebase = q.e_off[(qbase + w0) * q.nseg + sg];
+            __syncthreads();
+            for (int t = threadIdx.x; t < wn; t += kQuadThreads)
+                eoff[t] = static_cast<int32_t>(q.e_off[(qbase + w0 + t) * q.nseg + sg] - s_ebase);
+        }
         __syncthreads();
+        // first entry of each A row at or after k_lo: the count of smaller k's
+        if (k_lo > 0)
+            for (int r = 0; r < nr; ++r) {
+                int32_t c = 0;
+                for (int64_t t = q.a_row_ptr[i0 + r] + threadIdx.x; t < q.a_row_ptr[i0 + r + 1];
+                     t += kQuadThreads)
+                    c += q.a_col_idx[t] < k_lo ? 1 : 0;
+                if (c) atomicAdd(&s_skip[r], c);
+            }
+        __syncthreads();
+        // Thread 0 walks the merged A rows one k ahead of the workgroup: the
+        // head k of every row, the next k with its A blocks and B row range
+        // are in its registers, and the loads behind them are issued one
+        // iteration before they are needed.
+        int64_t pos[G], end[G];
+        int32_t head[G], na[G];
+        int32_t nk = INT_MAX;
+        int64_t ntb0 = 0, ntb1 = 0;
+        auto advance = [&]() {        // thread 0: the next k from the heads
+            nk = INT_MAX;
+            for (int r = 0; r < G; ++r) nk = head[r] < nk ? head[r] : nk;
+            for (int r = 0; r < G; ++r) {
+                na[r] = -1;
+                if (nk != INT_MAX && head[r] == nk) {
+                    na[r] = static_cast<int32_t>(pos[r]++);
+                    const int32_t h = pos[r] < end[r] ? q.a_col_idx[pos[r]] : INT_MAX;
+                    head[r] = h >= k_hi ? INT_MAX : h;
+                }
+            }
+            if (nk != INT_MAX) {
+                ntb0 = q.b_row_ptr[nk];
+                ntb1 = q.b_row_ptr[nk + 1];
+            }
+        };
+        if (threadIdx.x == 0) {
+            for (int r = 0; r < G; ++r) {
+                pos[r] = r < nr ? q.a_row_ptr[i0 + r] + s_skip[r] : 0;
+                end[r] = r < nr ? q.a_row_ptr[i0 + r + 1] : 0;
+                const int32_t h = pos[r] < end[r] ? q.a_col_idx[pos[r]] : INT_MAX;
+                head[r] = h >= k_hi ? INT_MAX : h;
+            }
+            advance();
+        }
         for (;;) {
             if (threadIdx.x == 0) {
-                // next k of the merged rows and the A block of each row at k
-                int32_t k = INT_MAX;
-                int32_t kr[G];
-                for (int r = 0; r < G; ++r) {
-                    kr[r] = (r < nr && s_p[r] < q.a_row_ptr[i0 + r + 1]) ? q.a_col_idx[s_p[r]] : INT_MAX;
-                    k = kr[r] < k ? kr[r] : k;
-                }
-                s_k = k;
-                for (int r = 0; r < G; ++r)
-                    s_a[r] = (k != INT_MAX && kr[r] == k) ? static_cast<int32_t>(s_p[r]++) : -1;
+                s_k = nk;
+                s_tb0 = ntb0;
+                s_tb1 = ntb1;
+                for (int r = 0; r < G; ++r) s_a[r] = na[r];
+                if (nk != INT_MAX) advance();
             }
             __syncthreads();
             const int32_t k = s_k;
             if (k == INT_MAX) break;
-            const int64_t tb0 = q.b_row_ptr[k], tb1 = q.b_row_ptr[k + 1];
+            const int64_t tb0 = s_tb0, tb1 = s_tb1;
             for (int64_t tb = tb0 + threadIdx.x; tb < tb1; tb += kQuadThreads) {
                 const int32_t j = q.b_col_idx[tb];
                 const int32_t Q = j / G;
@@ -176,7 +227,7 @@ k_quad_stack(QuadSymArgs q) {
                         if (jj / G != Q) break;
                         b[jj % G] = static_cast<int32_t>(t);
                     }
-                    const int64_t slot = q.e_off[qbase + w0 + r] + cnt[r];
+                    const int64_t slot = s_ebase + eoff[r] + cnt[r];
                     if (G == 2) {
                         q.ent[slot] = make_int4(s_a[0], s_a[G - 1], b[0], b[G - 1]);
                     } else {
@@ -189,7 +240,8 @@ k_quad_stack(QuadSymArgs q) {
             __syncthreads();
         }
         if (!FILL)
-            for (int t = threadIdx.x; t < wn; t += kQuadThreads) q.e_off[qbase + w0 + t] = cnt[t];
+            for (int t = threadIdx.x; t < wn; t += kQuadThreads)
+                q.e_off[(qbase + w0 + t) * q.nseg + sg] = cnt[t];
         __syncthreads();
     }
 }
@@ -209,8 +261,12 @@ int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s) {
     const int G = q.g;
     const int64_t ngroups = (static_cast<int64_t>(q.r1 - q.r0) + G - 1) / G;
     if (ngroups <= 0) return BSM_OK;
-    const size_t lds = sizeof(uint32_t) * 2 * quad_words(q.nbcols, G) + sizeof(int32_t) * kQuadWindow;
-    const unsigned g = static_cast<unsigned>(ngroups);
+    if (q.nseg < 1 || q.kseg < 1) { set_error("internal: quad k segments"); return BSM_EINVAL; }
+    const size_t lds = sizeof(uint32_t) * 2 * quad_words(q.nbcols, G) +
+                       sizeof(int32_t) * kQuadWindow * (fill ? 2 : 1);
+    const int64_t nblk = ngroups * q.nseg;
+    if (nblk > (1ll << 31) - 1) { set_error("too many row groups in one chunk"); return BSM_EINVAL; }
+    const unsigned g = static_cast<unsigned>(nblk);
     if (G == 4) {
         if (fill) k_quad_stack<true, 4><<<g, kQuadThreads, lds, s>>>(q);
         else k_quad_stack<false, 4><<<g, kQuadThreads, lds, s>>>(q);
@@ -218,6 +274,18 @@ int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s) {
         if (fill) k_quad_stack<true, 2><<<g, kQuadThreads, lds, s>>>(q);
         else k_quad_stack<false, 2><<<g, kQuadThreads, lds, s>>>(q);
     }
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+__global__ void k_seg_starts(const int64_t *seg_off, int32_t nseg, int64_t n, int64_t *starts) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g <= n) starts[g] = seg_off[g * nseg];
+}
+
+int quad_seg_starts(const int64_t *seg_off, int32_t nseg, int64_t n_groups, int64_t *starts,
+                    hipStream_t s) {
+    k_seg_starts<<<grid_for(n_groups + 1, 256), 256, 0, s>>>(seg_off, nseg, n_groups, starts);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }

@@ -46,11 +46,15 @@ int sort_worklist(const int64_t *wl_in, int64_t *wl_out, int64_t c0, int64_t n, 
 // the row groups of block rows [r0, r1) (r0 a multiple of G).  quad_pairs:
 // cnt[R] = groups of row group R.  quad_stack count pass (fill = false),
 // with q_off = scanned group counts: q_cblk[G G q + G r + c] = C block
-// (G R + r, G Q + c) or -1, q_col[q] = Q and e_off[q] = entries of group q;
-// fill pass: entry n of group q at ent[(G / 2) (e_off[q] + n)], ascending k.
+// (G R + r, G Q + c) or -1, q_col[q] = Q and e_off[q nseg + s] = entries of
+// group q with k in segment s; fill pass (e_off scanned): entry n of segment s
+// of group q at ent[(G / 2) (e_off[q nseg + s] + n)], ascending k, so each
+// group's entries are contiguous and in ascending k.  Segment s covers
+// k in [s kseg, (s + 1) kseg); one workgroup per (row group, segment).
 struct QuadSymArgs {
     int32_t r0, r1, nbcols;
     int32_t g;                   // group edge: 2 (quads) or 4
+    int32_t nseg, kseg;          // the k range split into nseg segments of kseg values
     const int64_t *a_row_ptr;
     const int32_t *a_col_idx;
     const int64_t *b_row_ptr;
@@ -60,11 +64,15 @@ struct QuadSymArgs {
     const int64_t *q_off;
     int64_t *q_cblk;
     int32_t *q_col;              // column group Q of every group (count pass)
-    int64_t *e_off;
+    int64_t *e_off;              // [n_groups nseg + 1]: count pass, entries per (group, segment);
+                                 // fill pass, their scanned offsets (group-major)
     int4 *ent;                   // G / 2 int4 per entry
 };
 int quad_pairs(const QuadSymArgs &q, int64_t *cnt, hipStream_t s);
 int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s);
+// starts[g] = seg_off[g nseg] for g in [0, n_groups]: entry offsets per group.
+int quad_seg_starts(const int64_t *seg_off, int32_t nseg, int64_t n_groups, int64_t *starts,
+                    hipStream_t s);
 
 int sym_count(const SymArgs &a, int64_t *c_cnt, int64_t *c_nval, int64_t *p_cnt, double *flops,
               hipStream_t s);

@@ -235,7 +235,8 @@ def test_quad_kernel_vs_oracle_and_fixed(orc, monkeypatch, group, waves, stage, 
     product lists) against the oracle -- block-row and column counts that
     are not multiples of the group edge give partial groups, C_in adds
     blocks without products, a tiny chunk size and an odd band height give
-    many chunks -- and bit for bit against the one-C-block-per-wave
+    many chunks, and the symbolic walk is split into three k segments -- and
+    bit for bit against the one-C-block-per-wave
     compile-time-shape kernel, which sums the same products in the same
     order with the same instructions."""
     monkeypatch.setenv("BSM_QUAD_GROUP", group)
@@ -257,11 +258,13 @@ def test_quad_kernel_vs_oracle_and_fixed(orc, monkeypatch, group, waves, stage, 
         monkeypatch.setenv("BSM_SMM_VARIANT", "6")
         monkeypatch.setenv("BSM_CHUNK_PRODUCTS", "50")
         monkeypatch.setenv("BSM_TILE_ROWS", "3")
+        monkeypatch.setenv("BSM_QUAD_KSEG", "3")      # three k segments per row group
         chunked, st2 = _run(alpha, a, bm, beta, cc)
         assert st2.smm_launches > 1
-        assert np.array_equal(chunked.values, got.values), "chunking changed the quad result"
+        assert np.array_equal(chunked.values, got.values), "chunks or k segments changed the result"
         monkeypatch.delenv("BSM_CHUNK_PRODUCTS")
         monkeypatch.delenv("BSM_TILE_ROWS")
+        monkeypatch.delenv("BSM_QUAD_KSEG")
 
 
 @pytest.mark.parametrize("variant", [1, 2, 3, 4])

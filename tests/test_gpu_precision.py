@@ -81,11 +81,13 @@ def test_lowp_quad_vs_one_block_kernel(orc, monkeypatch, prec, b):
         monkeypatch.setenv("BSM_LOWP_QUAD", "1")
         monkeypatch.setenv("BSM_CHUNK_PRODUCTS", "50")
         monkeypatch.setenv("BSM_TILE_ROWS", "3")
+        monkeypatch.setenv("BSM_QUAD_KSEG", "3")      # three k segments per row group
         chunked, st2 = _lowp_run(prec, alpha, a, bm, beta, cc)
         assert st2.smm_launches > 1
-        assert np.array_equal(chunked.values, got.values), "chunking changed the quad result"
+        assert np.array_equal(chunked.values, got.values), "chunks or k segments changed the result"
         monkeypatch.delenv("BSM_CHUNK_PRODUCTS")
         monkeypatch.delenv("BSM_TILE_ROWS")
+        monkeypatch.delenv("BSM_QUAD_KSEG")
 
 
 def test_lowp_rejects_mixed_sizes(orc):
