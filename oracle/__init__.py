@@ -28,6 +28,9 @@ Parity status of each function (what pins it, see ``tests/test_oracle.py``):
 * ``density_nonorth`` -- pinned: P from the generalised eigenproblem
                        K c = e S c (LAPACK) on tiny cases; P S P = P and
                        trace(P S) = occupied count on filtered neighbour cases.
+* ``tc2``           -- pinned: diagonal H by hand (the scalar maps and the
+                       trace decisions); on dense cases the projector onto
+                       the N lowest eigenvectors (LAPACK).
 * ``mu_bisect``     -- pinned: diagonal H, whose count is the number of
                        diagonal entries below mu, so every midpoint follows
                        by hand; on dense cases the accepted mu lies in the
@@ -104,6 +107,8 @@ def _load():
             lib.orc_add.argtypes = [C.c_double, P, C.c_double, P, C.c_double, C.c_double,
                                     C.c_int, P]
             lib.orc_density_from_sign.argtypes = [P, P]
+            lib.orc_tc2.argtypes = [P, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int32,
+                                    P, C.POINTER(_Tc2Stats)]
             lib.orc_sqrt_inv.argtypes = [P, C.c_double, C.c_int, C.c_double, C.c_int32, P, P,
                                          C.POINTER(_SignStats)]
             lib.orc_density_nonorth.argtypes = [P, P, C.c_double, C.c_double, C.c_int,
@@ -268,6 +273,33 @@ def mu_bisect(h: BSR, n_target: float, mu_lo: float, mu_hi: float, count_tol: fl
         else:
             hi = mu
     return mu, x, rec, ENOCONV
+
+
+class _Tc2Stats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("n_multiplies", C.c_int32),
+                ("e_hist", C.c_double * 128), ("branch", C.c_int32 * 128),
+                ("scale", C.c_double), ("trace_p", C.c_double), ("flops", C.c_double)]
+
+
+def tc2(h: BSR, n_occ: float, eps: float = 0.0, tol: float = 1e-10, max_iter: int = 100,
+        norm="frob"):
+    """Trace-correcting purification (orc_tc2); returns (P, stats, status)
+    with status OK, ENOCONV or ENONFINITE."""
+    lib = _load()
+    oh, kh = _in(h)
+    out = _OMat()
+    st = _Tc2Stats()
+    status = lib.orc_tc2(C.byref(oh), float(n_occ), eps, _norm(norm), tol, max_iter,
+                         C.byref(out), C.byref(st))
+    if status not in (OK, ENOCONV, ENONFINITE):
+        raise RuntimeError(f"oracle purification failed with status {status}")
+    p = _out(out, h.row_blk_size, h.col_blk_size) if out.row_ptr else None
+    k = int(st.iterations)
+    stats = dict(iterations=k, n_multiplies=int(st.n_multiplies),
+                 e_hist=[float(st.e_hist[i]) for i in range(k + 1)],
+                 branch=[int(st.branch[i]) for i in range(k)], scale=float(st.scale),
+                 trace_p=float(st.trace_p), flops=float(st.flops))
+    return p, stats, int(status)
 
 
 def _stats(st) -> dict:

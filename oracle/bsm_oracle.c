@@ -822,6 +822,81 @@ int orc_density_nonorth(const omat *k, const omat *s_in, double mu, double eps, 
     return status;
 }
 
+/* --------------------------------------------- canonical purification (TC2) */
+
+typedef struct {
+    int32_t iterations;     /* updates performed */
+    int32_t n_multiplies;
+    double e_hist[128];     /* e_k = (trace X_k - trace X_k^2) / n */
+    int32_t branch[128];    /* update k: 0 = X^2, 1 = 2X - X^2 */
+    double scale;           /* s = ||H||_inf */
+    double trace_p;         /* trace of the returned P */
+    double flops;
+} orc_tc2_stats;
+
+/*
+ * Density matrix for a fixed occupation N by second-order trace-correcting
+ * purification (TC2, one of the purifications the density-matrix paragraph
+ * names), which needs no chemical potential (canonical ensemble):
+ *
+ *   s = ||H||_inf;  X_0 = (s I - H) / (2 s)        (spectrum in [0, 1], low energies near 1)
+ *   for k = 0, 1, ...:
+ *       Y   = filter(X_k X_k)
+ *       e_k = (trace X_k - trace Y) / n;  stop if e_k < tol (returns X_k)
+ *       X_{k+1} = Y                    if trace X_k > N   (lowers the trace)
+ *               = filter(2 X_k - Y)    otherwise          (raises it)
+ *
+ * Both maps keep [0, 1] and push every eigenvalue to 0 or 1; the trace
+ * test steers the count of those going to 1 towards N.  ORC_ENOCONV after
+ * max_iter updates or when e_k is not finite (then ORC_ENONFINITE).
+ */
+int orc_tc2(const omat *h, double n_occ, double eps, int norm_kind, double tol, int32_t max_iter,
+            omat *p_out, orc_tc2_stats *st)
+{
+    if (h->nbrows != h->nbcols || eps < 0 || max_iter < 0 || max_iter > 120) return ORC_EINVAL;
+    for (int32_t i = 0; i < h->nbrows; ++i) if (h->rbs[i] != h->cbs[i]) return ORC_EINVAL;
+    memset(st, 0, sizeof(*st));
+    double n = 0.0;
+    for (int32_t i = 0; i < h->nbrows; ++i) n += h->rbs[i];
+    const double sc = orc_inf_norm_shifted(h, 0.0);
+    st->scale = sc;
+    if (!isfinite(sc)) return ORC_ENONFINITE;
+    if (sc == 0.0) return ORC_EINVAL;
+    omat x = {0}, y = {0}, xn = {0};
+    int status = orc_shift_scale(h, sc, -0.5 / sc, &x);       /* (s I - H) / (2 s) */
+    for (int32_t k = 0; status == ORC_OK; ++k) {
+        st->flops += product_flops(&x, &x);
+        st->n_multiplies++;
+        status = orc_multiply(1.0, &x, &x, 0.0, NULL, eps, norm_kind, &y);
+        if (status != ORC_OK) break;
+        const double tx = orc_trace(&x), ty = orc_trace(&y);
+        const double e = (tx - ty) / n;
+        st->e_hist[k] = e;
+        st->iterations = k;
+        if (!isfinite(e)) { status = ORC_ENONFINITE; break; }
+        if (e < tol) break;
+        if (k >= max_iter) { status = ORC_ENOCONV; break; }
+        if (tx > n_occ) {
+            st->branch[k] = 0;
+            orc_free(&x);
+            x = y;
+            memset(&y, 0, sizeof(y));
+        } else {
+            st->branch[k] = 1;
+            status = orc_add(2.0, &x, -1.0, &y, 0.0, eps, norm_kind, &xn);
+            orc_free(&y);
+            if (status != ORC_OK) break;
+            orc_free(&x);
+            x = xn;
+            memset(&xn, 0, sizeof(xn));
+        }
+    }
+    orc_free(&y);
+    if (status == ORC_OK || status == ORC_ENOCONV) st->trace_p = orc_trace(&x);
+    *p_out = x;
+    return status;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -664,3 +664,69 @@ def test_density_nonorth_neighbour_invariants(orc):
     pd, sd = p.to_dense(), s.to_dense()
     assert _rel(pd @ sd @ pd, pd) <= 1e-5
     assert float(np.trace(pd @ sd)) == pytest.approx(h.meta["n_occ"], abs=1e-3)
+
+
+# --------------------------------------- trace-correcting purification (TC2)
+
+def test_tc2_diagonal_by_hand(orc):
+    """Diagonal H: X stays diagonal, so every update is the scalar map x^2 or
+    2x - x^2 chosen by the trace against N, evaluated here in the same order."""
+    rng = np.random.default_rng(41)
+    sizes = rng.integers(1, 6, 10)
+    h = rng.uniform(-3.0, 3.0, int(sizes.sum()))
+    n = h.size
+    nocc = int((h < 0.2).sum())
+    m = _diag_matrix(h, sizes)
+    p, st, status = orc.tc2(m, nocc, eps=0.0, tol=1e-13)
+    assert status == orc.OK
+    s = np.abs(h).max()
+    x = -(0.5 / s) * (h - s)
+    branches, es = [], []
+    for k in range(100):
+        y = x * x
+        e = (x.sum() - y.sum()) / n
+        es.append(e)
+        if e < 1e-13:
+            break
+        if x.sum() > nocc:
+            branches.append(0)
+            x = y
+        else:
+            branches.append(1)
+            x = 2.0 * x + (-1.0) * y
+    assert st["iterations"] == k and st["branch"] == branches
+    assert np.allclose(st["e_hist"], es, rtol=1e-10, atol=1e-16)
+    assert np.array_equal(np.diag(p.to_dense()), x)
+    assert np.array_equal(np.round(x), (h < np.sort(h)[nocc - 1] + 1e-12).astype(float))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_tc2_dense_is_the_occupied_projector(orc, seed):
+    rng = np.random.default_rng(70 + seed)
+    sizes = rng.integers(1, 9, 8)
+    n = int(sizes.sum())
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.sort(rng.uniform(-2.0, 2.0, n))
+    nocc = n // 3
+    lam[nocc:] += 0.5                         # a gap above the N-th eigenvalue
+    d = (q * lam) @ q.T
+    d = 0.5 * (d + d.T)
+    p, st, status = orc.tc2(_dense_to_bsr(d, sizes), nocc, eps=0.0, tol=1e-14)
+    assert status == orc.OK
+    w, v = np.linalg.eigh(d)
+    ref = v[:, :nocc] @ v[:, :nocc].T
+    assert _rel(p.to_dense(), ref) <= 1e-10
+    assert st["trace_p"] == pytest.approx(nocc, abs=1e-9)
+
+
+def test_tc2_matches_sign_density_on_neighbour_hamiltonian(orc):
+    """With the gap of the synthetic Hamiltonian, the canonical TC2 density
+    for N = the occupied count and the sign-iteration density at mu = 0 are
+    the same projector, up to the filter."""
+    h = synth.neighbour_hamiltonian(100, 5, cutoff=4.5, seed=3)
+    p, st, status = orc.tc2(h, h.meta["n_occ"], eps=1e-9, tol=1e-9)
+    assert status == orc.OK
+    x, _, s2 = orc.sign_ns(h, eps=1e-9, tol=1e-9)
+    ps = orc.density_from_sign(x)
+    assert _rel(p.to_dense(), ps.to_dense()) <= 1e-6
+    assert st["trace_p"] == pytest.approx(h.meta["n_occ"], abs=1e-5)

@@ -42,6 +42,9 @@ MUTANTS = [
      "status = orc_shift_scale(&k1, 0.0, 1.0, &kt);"),
     ("nonorth_back", "s2 = orc_multiply(1.0, &p1, &z, 0.0, NULL, eps, norm_kind, p_out);",
      "s2 = orc_shift_scale(&p1, 0.0, 1.0, p_out);"),
+    ("tc2_branch", "if (tx > n_occ) {", "if (tx < n_occ) {"),
+    ("tc2_scale", "orc_shift_scale(h, sc, -0.5 / sc, &x)", "orc_shift_scale(h, sc, -1.0 / sc, &x)"),
+    ("tc2_update", "orc_add(2.0, &x, -1.0, &y, 0.0,", "orc_add(2.0, &x, -0.5, &y, 0.0,"),
     ("add_gamma", "tmp[r * m + r] = tmp[r * m + r] + gamma;", "tmp[r * m + r] = tmp[r * m + r] - gamma;"),
     ("add_b_index", "tmp[e] = tmp[e] + beta * b->values[offb[tb] + e];",
      "tmp[e] = tmp[e] + beta * b->values[offb[tb]];"),
