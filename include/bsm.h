@@ -127,6 +127,20 @@ typedef struct bsm_mu_stats {
     double device_ms;        /* summed device time of the sign iterations */
 } bsm_mu_stats;
 
+/* Record of bsm_tc2. */
+typedef struct bsm_tc2_stats {
+    int32_t iterations;      /* updates performed */
+    int32_t n_multiplies;
+    double e_hist[128];      /* e_k = (trace X_k - trace X_k^2) / n, k = 0..iterations */
+    int32_t branch[128];     /* update k: 0 = X^2, 1 = 2X - X^2 */
+    double scale;            /* s = ||H||_inf */
+    double trace_p;          /* trace of the returned P */
+    double flops;            /* algorithmic flops of the block products */
+    int64_t n_products;
+    double smm_ms;           /* block-product kernel time (HIP events) */
+    double device_ms;        /* device time of the whole call */
+} bsm_tc2_stats;
+
 /* Default options: eps 0, tol 1e-6, max_iter 100, FROB, FP64, no graph, order 2. */
 void bsm_sign_opts_default(bsm_sign_opts *opts);
 
@@ -299,6 +313,22 @@ int bsm_sqrt_inv(bsm_matrix S, const bsm_sign_opts *opts, bsm_matrix *sqrt_out,
 int bsm_density_nonorth(bsm_matrix K, bsm_matrix S, double mu, const bsm_sign_opts *opts,
                         bsm_matrix *p_out, double *trace_ps, bsm_sign_stats *sqrt_stats,
                         bsm_sign_stats *sign_stats, void *stream);
+
+/*
+ * Density matrix for a fixed occupation n_occ without a chemical potential,
+ * by second-order trace-correcting purification (TC2, named among the
+ * purifications of the density-matrix-based-methods paragraph):
+ *   s = ||H||_inf;  X_0 = (s I - H)/(2s);
+ *   loop k: Y = filter(X_k X_k); e_k = (trace X_k - trace Y)/n;
+ *           stop if e_k < tol (P = X_k);
+ *           X_{k+1} = Y if trace X_k > n_occ, else filter(2 X_k - Y).
+ * opts: eps_filter, norm, tol, max_iter (0..120); FP64 products.  P is a new
+ * handle (caller destroys) for BSM_OK and BSM_ENOCONV (max_iter reached);
+ * BSM_ENONFINITE for NaN/Inf, BSM_EINVAL for a non-square H or bad options.
+ * stats may be NULL.  Waits (two traces per iteration).
+ */
+int bsm_tc2(bsm_matrix H, double n_occ, const bsm_sign_opts *opts, bsm_matrix *p_out,
+            bsm_tc2_stats *stats, void *stream);
 
 /* P = (I - X)/2 from a sign matrix X, as a new handle; trace_p (may be NULL) gets trace(P). */
 int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void *stream);

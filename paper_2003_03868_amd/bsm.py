@@ -65,6 +65,13 @@ class bsm_mu_stats(C.Structure):
                 ("flops", C.c_double), ("device_ms", C.c_double)]
 
 
+class bsm_tc2_stats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("n_multiplies", C.c_int32),
+                ("e_hist", C.c_double * 128), ("branch", C.c_int32 * 128),
+                ("scale", C.c_double), ("trace_p", C.c_double), ("flops", C.c_double),
+                ("n_products", C.c_int64), ("smm_ms", C.c_double), ("device_ms", C.c_double)]
+
+
 class bsm_smm_params(C.Structure):
     _fields_ = [("family", C.c_int32), ("wpg", C.c_int32), ("prefetch", C.c_int32),
                 ("reserved", C.c_int32)]
@@ -104,6 +111,8 @@ _SIGS = [
                                       C.POINTER(bsm_sign_opts), C.POINTER(C.c_void_p),
                                       C.POINTER(C.c_double), C.POINTER(bsm_sign_stats),
                                       C.POINTER(bsm_sign_stats), C.c_void_p]),
+    ("bsm_tc2", C.c_int, [C.c_void_p, C.c_double, C.POINTER(bsm_sign_opts),
+                          C.POINTER(C.c_void_p), C.POINTER(bsm_tc2_stats), C.c_void_p]),
     ("bsm_density_from_sign", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p),
                                         C.POINTER(C.c_double), C.c_void_p]),
     ("bsm_smm_bench", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
@@ -288,6 +297,19 @@ def bsm_density_nonorth(k, s, mu=0.0, opts: bsm_sign_opts | None = None, stream=
     if st not in (OK, ENOCONV):
         _check(st, "bsm_density_nonorth")
     return st, p.value, tps.value, s1, s2
+
+
+def bsm_tc2(h, n_occ, opts: bsm_sign_opts | None = None, stream=None):
+    """Returns (status, P handle or None, stats); ENOCONV/ENONFINITE are
+    returned, not raised."""
+    out = C.c_void_p()
+    stats = bsm_tc2_stats()
+    o = opts if opts is not None else bsm_sign_opts_default()
+    st = load().bsm_tc2(h, float(n_occ), C.byref(o), C.byref(out), C.byref(stats),
+                        _stream(stream))
+    if st not in (OK, ENOCONV, ENONFINITE):
+        _check(st, "bsm_tc2")
+    return st, out.value, stats
 
 
 def bsm_add(alpha, a, beta=0.0, b=None, gamma=0.0, eps_filter=0.0, norm=0, stream=None) -> int:

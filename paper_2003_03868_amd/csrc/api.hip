@@ -14,6 +14,8 @@ int sqrt_inv_iterate(Mat &S, const bsm_sign_opts &o, Mat **sqrt_out, Mat **isqrt
 int density_nonorth(Mat &K, Mat &S, double mu, const bsm_sign_opts &o, Mat **p_out,
                     double *trace_ps, bsm_sign_stats *st_sqrt, bsm_sign_stats *st_sign,
                     hipStream_t s);
+int tc2_purify(Mat &H, double n_occ, const bsm_sign_opts &o, Mat **p_out, bsm_tc2_stats *st,
+               hipStream_t s);
 }  // namespace bsm
 
 using bsm::Mat;
@@ -354,6 +356,22 @@ int bsm_density_nonorth(bsm_matrix K, bsm_matrix S, double mu, const bsm_sign_op
     Mat *p = nullptr;
     const int rc = bsm::density_nonorth(K->m, S->m, mu, o, &p, &tps, s1, s2, as_stream(stream));
     if (trace_ps) *trace_ps = tps;
+    if (p) *p_out = wrap(p);
+    return rc;
+}
+
+int bsm_tc2(bsm_matrix H, double n_occ, const bsm_sign_opts *opts, bsm_matrix *p_out,
+            bsm_tc2_stats *stats, void *stream) {
+    bsm::clear_error();
+    if (!H || !p_out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    *p_out = nullptr;
+    bsm_sign_opts o;
+    if (opts) o = *opts; else bsm_sign_opts_default(&o);
+    bsm_tc2_stats local;
+    bsm_tc2_stats *st = stats ? stats : &local;
+    std::memset(st, 0, sizeof(*st));
+    Mat *p = nullptr;
+    const int rc = bsm::tc2_purify(H->m, n_occ, o, &p, st, as_stream(stream));
     if (p) *p_out = wrap(p);
     return rc;
 }

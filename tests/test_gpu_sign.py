@@ -194,3 +194,28 @@ def test_mu_bisect_rejects_bad_bracket():
         with pytest.raises(bsm.BsmError) as e:
             bsm.bsm_mu_bisect(d.handle, 10, lo, hi, max_steps=steps)
         assert e.value.status == bsm.EINVAL
+
+
+@pytest.mark.parametrize("c", [dict(n=100, b=5, rc=4.5, eps=0.0, seed=3),
+                               dict(n=100, b=5, rc=4.5, eps=1e-8, seed=4),
+                               dict(n=64, b=13, rc=4.0, eps=1e-7, seed=5)],
+                         ids=lambda c: f"n{c['n']}b{c['b']}e{c['eps']:g}")
+def test_tc2_vs_oracle(orc, c):
+    """Trace-correcting purification: the same updates (branch by branch) as
+    the oracle, P within the FP64 tolerance, trace(P) the occupied count."""
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(c["n"], c["b"], cutoff=c["rc"], seed=c["seed"])
+    p_ref, st_ref, s_ref = orc.tc2(h, h.meta["n_occ"], eps=c["eps"], tol=1e-9)
+    d = to_dev(h)
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol = c["eps"], 1e-9
+    st, ph, stats = bsm.bsm_tc2(d.handle, h.meta["n_occ"], o)
+    assert st == s_ref == bsm.OK, bsm.bsm_last_error()
+    k = stats.iterations
+    assert k == st_ref["iterations"] and list(stats.branch[:k]) == st_ref["branch"]
+    assert np.allclose(list(stats.e_hist[:k + 1]), st_ref["e_hist"], rtol=1e-6, atol=1e-14)
+    p = bsm.Matrix(ph, h.row_blk_size, h.col_blk_size)
+    assert_same_matrix(from_dev(p), p_ref, TOL_FP64, "TC2 P")
+    assert stats.trace_p == pytest.approx(h.meta["n_occ"], abs=1e-5)
+    print(f"tc2 {c}: {k} iterations, branches {list(stats.branch[:k])}, "
+          f"trace(P) {stats.trace_p:.8f}")
