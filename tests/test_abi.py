@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "bsm.h")
 def _declared():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(bsm_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(bsm_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     assert sorted(bsm.EXPORTED) == declared
     out = subprocess.run(["nm", "-D", "--defined-only", bsm.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
-    exported = sorted(set(re.findall(r" T (bsm_[a-z_]+)$", out, flags=re.M)))
+    exported = sorted(set(re.findall(r" T (bsm_[a-z0-9_]+)$", out, flags=re.M)))
     assert exported == declared
 
 
