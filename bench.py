@@ -148,6 +148,59 @@ def bench_nonorth(args, h, dh, bsm, synth, torch):
         "cpu_baseline": None}))
 
 
+def bench_tc2(args, h, dh, bsm, torch):
+    """Timed steps of TC2 purification at the occupied count of the
+    workload; one JSON line."""
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol = args.eps, args.tol
+    stream = torch.cuda.current_stream()
+    nocc = h.meta["n_occ"]
+
+    def step():
+        st, ph, stats = bsm.bsm_tc2(dh.handle, nocc, o, stream=stream)
+        if st != bsm.OK:
+            raise RuntimeError(f"TC2 failed: {bsm.STATUS_NAMES[st]} {bsm.bsm_last_error()}")
+        bsm.bsm_destroy(ph)
+        return stats
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    times, recs = [], []
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        recs.append(step())
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        s = recs[-1]
+        log(f"step {k}: {times[-1] * 1e3:.0f} ms, {s.iterations} iterations, "
+            f"e={s.e_hist[s.iterations]:.2e}, trace(P)={s.trace_p:.6f}, smm {s.smm_ms:.0f} ms")
+    total = sum(times)
+    flops = sum(s.flops for s in recs)
+    smm_ms = sum(s.smm_ms for s in recs)
+    s = recs[-1]
+    achieved = flops / (smm_ms * 1e-3) / 1e12 if smm_ms > 0 else 0.0
+    print(json.dumps({
+        "metric": "block-sparse multiply GFLOP/s (FP64 vs mixed); sign-iteration time to 1e-6",
+        "value": flops / total / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"FP64 TC2 purification to N = {nocc}, {h.nbrows}-site "
+                               f"neighbour-list Hamiltonian, eps_filter {args.eps:g}, "
+                               f"tol {args.tol:g}",
+                   "n_sites": h.nbrows, "seed": args.seed},
+        "iterations": int(s.iterations), "multiplies": int(s.n_multiplies),
+        "branches": list(s.branch[:s.iterations]), "trace_p": float(s.trace_p), "n_occ": nocc,
+        "tflop_per_step": flops / args.steps / 1e12,
+        "roofline": {"bound": "mfma", "kernel": "k_smm_f64_quad", "achieved": achieved,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "smm_ms_per_step": smm_ms / args.steps},
+        "cpu_baseline": None}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +225,9 @@ def main():
     ap.add_argument("--overlap", type=float, default=0.0, metavar="TAU",
                     help="time the non-orthogonal density matrix with a synthetic overlap "
                          "S = I + TAU N/M (0: the orthogonal sign iteration)")
+    ap.add_argument("--purify", choices=["sign", "tc2"], default="sign",
+                    help="density matrix by the sign iteration (default) or by TC2 "
+                         "purification at the occupied count")
     ap.add_argument("--graph", type=int, choices=[0, 1], default=0,
                     help="1: replay captured hipGraphs once X's block pattern stops changing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -219,6 +275,9 @@ def main():
 
     if args.overlap > 0.0:
         bench_nonorth(args, h, dh, bsm, synth, torch)
+        return
+    if args.purify == "tc2":
+        bench_tc2(args, h, dh, bsm, torch)
         return
 
     opts = bsm.bsm_sign_opts_default()
