@@ -410,7 +410,7 @@ def main():
         "graph_fallbacks": int(s0.graph_fallbacks),
         "roofline": {
             "bound": "mfma",
-            "kernel": ("k_smm_f64_quad<23,2,4,6,1>" if args.workload == "sign23" else "k_smm_f64_class")
+            "kernel": ("k_smm_f64_quad<23,2,2,4,6,1>" if args.workload == "sign23" else "k_smm_f64_class")
             if args.prec == "fp64" else "k_smm_lowp",
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,

@@ -266,8 +266,10 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     if (prec != BSM_FP64 && variant == kSmmF64Quad && lowp_quad(prec) && A.uni_r && A.uni_c &&
         B.uni_c && smm_lowp_available(A.uni_r, B.uni_c, A.uni_c))
         use_quad = true;
-    // group edge: quads, or groups of sixteen (FP64 only)
-    const int G = (use_quad && prec == BSM_FP64) ? quad_group(A.uni_r) : 2;
+    // group shape: quads, or other shapes on request (FP64 only)
+    int GR = 2, GC = 2;
+    if (use_quad && prec == BSM_FP64) quad_shape(A.uni_r, &GR, &GC);
+    const int NE = (GR + GC + 3) / 4;                        // int4 per group entry
 
     // one set of stack buffers reused by every chunk; a plan keeps one per
     // chunk; the quad kernel builds its own lists
@@ -339,7 +341,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             // without a plan the buffers live for this chunk only
             Scratch ctmp(s);
             auto qbuf = [&](auto **ptr, size_t n) -> int { return pl ? keep_buf(ptr, n) : ctmp.get(ptr, n); };
-            const int64_t npairs = (static_cast<int64_t>(r1 - r0) + G - 1) / G;
+            const int64_t npairs = (static_cast<int64_t>(r1 - r0) + GR - 1) / GR;
             int64_t *q_off = nullptr, *q_cblk = nullptr, *e_off = nullptr, *q_order = nullptr,
                     *e_seg = nullptr;
             int32_t *q_col = nullptr;
@@ -352,7 +354,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
                 return BSM_OK;
             };
             QuadSymArgs qa{};
-            qa.r0 = r0; qa.r1 = r1; qa.nbcols = B.nbcols; qa.g = G;
+            qa.r0 = r0; qa.r1 = r1; qa.nbcols = B.nbcols; qa.gr = GR; qa.gc = GC;
             qa.nseg = quad_ksegments(A.nbcols);
             qa.kseg = (A.nbcols + qa.nseg - 1) / qa.nseg;
             if (qa.kseg < 1) qa.kseg = 1;
@@ -363,7 +365,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             if (st == BSM_OK) st = quad_pairs(qa, q_off, s);
             if (st == BSM_OK) st = scan_i64(q_off, q_off, npairs, s);
             if (st == BSM_OK) st = read_total(q_off + npairs, &nq);
-            if (st == BSM_OK) st = qbuf(&q_cblk, static_cast<size_t>(G) * G * nq);
+            if (st == BSM_OK) st = qbuf(&q_cblk, static_cast<size_t>(GR) * GC * nq);
             if (st == BSM_OK) st = qbuf(&e_off, nq + 1);
             if (st == BSM_OK && qa.nseg > 1) st = qbuf(&e_seg, static_cast<size_t>(nq) * qa.nseg + 1);
             if (qa.nseg == 1) e_seg = e_off;
@@ -377,7 +379,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             if (st == BSM_OK && qr > 0 && nq > 0) {
                 st = qbuf(&q_order, nq);
                 if (st == BSM_OK)
-                    st = tile_order(q_off, q_col, static_cast<int32_t>(npairs), (B.nbcols + G - 1) / G,
+                    st = tile_order(q_off, q_col, static_cast<int32_t>(npairs), (B.nbcols + GC - 1) / GC,
                                     qr, q_order, s, qc);
             }
             const int64_t nsl = nq * qa.nseg;                       // (group, segment) counts
@@ -389,7 +391,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
                 set_error("more than 2^31 group entries in one chunk; lower BSM_CHUNK_PRODUCTS");
                 st = BSM_EINVAL;
             }
-            if (st == BSM_OK) st = qbuf(&ent, static_cast<size_t>(ne) * (G / 2));
+            if (st == BSM_OK) st = qbuf(&ent, static_cast<size_t>(ne) * NE);
             qa.ent = ent;
             if (st == BSM_OK) st = quad_stack(qa, true, s);
             if (st != BSM_OK) break;
@@ -401,7 +403,8 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             op.a.q_seg = e_off;
             op.a.q_ent = ent;
             op.a.q_order = q_order;
-            op.a.q_group = G;
+            op.a.q_gr = GR;
+            op.a.q_gc = GC;
             std::pair<hipEvent_t, hipEvent_t> pe{};
             if (ev.on) {
                 BSM_HIP(hipEventCreate(&pe.first));

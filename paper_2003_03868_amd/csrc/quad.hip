@@ -2,16 +2,16 @@
 // block-product kernel in smm_quad.hip).  Built straight from the patterns
 // of A, B and C, without per-C-block stacks.
 //
-// A group is the G x G set C(G R + r, G Q + c), r, c in [0, G), of the C
-// blocks of a chunk (at least one of them present); G = 2 gives quads, G = 4
-// groups of sixteen.  Its entry list is the union of the k's of its C blocks'
-// products, ascending; entry k names A(G R + r, k) for each row r and
-// B(k, G Q + c) for each column c that a product of the group uses, -1
-// otherwise.  Product (r, c) of an entry exists exactly when both
-// A(G R + r, k) and B(k, G Q + c) are named, so the per-C-block sums are those
-// of the plain stacks, in the same (ascending k) order, while every operand
-// block is loaded once for up to G products.  An entry is G / 2 int4: the G
-// A indices, then the G B indices.
+// A group is the GR x GC set C(GR R + r, GC Q + c), r < GR, c < GC, of the C
+// blocks of a chunk (at least one of them present); 2 x 2 groups are the
+// quads.  Its entry list is the union of the k's of its C blocks' products,
+// ascending; entry k names A(GR R + r, k) for each row r and B(k, GC Q + c)
+// for each column c that a product of the group uses, -1 otherwise.  Product
+// (r, c) of an entry exists exactly when both A(GR R + r, k) and
+// B(k, GC Q + c) are named, so the per-C-block sums are those of the plain
+// stacks, in the same (ascending k) order, while every operand block is
+// loaded once for up to GC (A) or GR (B) products.  An entry is the GR A
+// indices followed by the GC B indices, padded to whole int4.
 #include <climits>
 
 #include "symbolic.h"
@@ -29,10 +29,10 @@ __device__ inline int32_t bit_rank_q(const uint32_t *bits, const int32_t *wpre, 
 
 // ---------------------------------------------------------------------------
 // Entry lists straight from the patterns of A and B: one workgroup per row
-// group walks k over the merged column lists of A's rows G R .. G R + G - 1
-// (ascending); for each k its threads scan B's row k, and the thread holding
-// the first column of group Q present in that row emits the entry of group
-// Q, naming every B(k, G Q + c) that exists.  Every (group, k) pair is
+// group (and k segment) walks k over the merged column lists of A's rows
+// GR R .. GR R + GR - 1 (ascending); for each k its threads scan B's row k,
+// and the thread holding the first column of group Q present in that row
+// emits the entry of group Q, naming every B(k, GC Q + c) that exists.  Every (group, k) pair is
 // emitted by one thread, so a per-group cursor in LDS needs no atomics, and
 // the barrier after each k keeps every list in ascending k.  Groups are
 // ranked within the row group by an LDS bitmap of their column groups; row
@@ -66,7 +66,7 @@ __host__ __device__ inline int quad_words(int32_t nbcols, int g) {
 
 // Bitmap of the column groups Q holding C blocks of rows i0 .. i0 + nr - 1
 // and the exclusive popcount prefix per word; returns the number of groups.
-template <int G>
+template <int GC>
 __device__ inline int64_t quad_rank_map(const QuadSymArgs &q, int32_t i0, int nr, int nwq,
                                         uint32_t *bits, int32_t *wpre, int64_t *scratch) {
     for (int w = threadIdx.x; w < nwq; w += kQuadThreads) bits[w] = 0u;
@@ -74,7 +74,7 @@ __device__ inline int64_t quad_rank_map(const QuadSymArgs &q, int32_t i0, int nr
     for (int r = 0; r < nr; ++r)
         for (int64_t t = q.c_row_ptr[i0 + r] + threadIdx.x; t < q.c_row_ptr[i0 + r + 1];
              t += kQuadThreads) {
-            const int32_t Q = q.c_col_idx[t] / G;
+            const int32_t Q = q.c_col_idx[t] / GC;
             atomicOr(&bits[Q >> 5], 1u << (Q & 31));
         }
     __syncthreads();
@@ -93,30 +93,32 @@ __device__ inline int64_t quad_rank_map(const QuadSymArgs &q, int32_t i0, int nr
 }
 
 // Groups per row group (one workgroup per row group).
-template <int G>
+template <int GR, int GC>
 __global__ void __launch_bounds__(kQuadThreads)
 k_quad_pairs(QuadSymArgs q, int64_t *cnt) {
     extern __shared__ uint32_t smem[];
     __shared__ int64_t scratch[kQuadThreads / kWave];
-    const int nwq = quad_words(q.nbcols, G);
+    const int nwq = quad_words(q.nbcols, GC);
     const int32_t R = blockIdx.x;
-    const int32_t i0 = q.r0 + G * R;
-    const int nr = (q.r1 - i0 < G) ? q.r1 - i0 : G;
-    const int64_t nq = quad_rank_map<G>(q, i0, nr, nwq, smem,
-                                        reinterpret_cast<int32_t *>(smem + nwq), scratch);
+    const int32_t i0 = q.r0 + GR * R;
+    const int nr = (q.r1 - i0 < GR) ? q.r1 - i0 : GR;
+    const int64_t nq = quad_rank_map<GC>(q, i0, nr, nwq, smem,
+                                         reinterpret_cast<int32_t *>(smem + nwq), scratch);
     if (threadIdx.x == 0) cnt[R] = nq;
 }
 
 // FILL = false: the groups' C blocks (q_cblk) and entry counts (e_off);
 // FILL = true: the entries.
-template <bool FILL, int G>
+template <bool FILL, int GR, int GC>
 __global__ void __launch_bounds__(kQuadThreads)
 k_quad_stack(QuadSymArgs q) {
+    constexpr int GG = GR * GC;
+    constexpr int NE = (GR + GC + 3) / 4;          // int4 per entry
     extern __shared__ uint32_t smem[];
     __shared__ int64_t scratch[kQuadThreads / kWave];
     __shared__ int64_t s_tb0, s_tb1;
-    __shared__ int32_t s_k, s_a[G], s_skip[G];
-    const int nwq = quad_words(q.nbcols, G);   // words of the column-group bitmap
+    __shared__ int32_t s_k, s_a[GR], s_skip[GR];
+    const int nwq = quad_words(q.nbcols, GC);  // words of the column-group bitmap
     uint32_t *bits = smem;
     int32_t *wpre = reinterpret_cast<int32_t *>(smem + nwq);
     int32_t *cnt = reinterpret_cast<int32_t *>(smem + 2 * nwq);
@@ -124,31 +126,31 @@ k_quad_stack(QuadSymArgs q) {
     int32_t *eoff = cnt + kQuadWindow;
     __shared__ int64_t s_ebase;
     const int32_t R = blockIdx.x / q.nseg, sg = blockIdx.x % q.nseg;
-    const int32_t i0 = q.r0 + G * R;
-    const int nr = (q.r1 - i0 < G) ? q.r1 - i0 : G;
+    const int32_t i0 = q.r0 + GR * R;
+    const int nr = (q.r1 - i0 < GR) ? q.r1 - i0 : GR;
     // this workgroup's k range
     const int32_t k_lo = sg * q.kseg;
     const int32_t k_hi = (sg == q.nseg - 1) ? INT_MAX : k_lo + q.kseg;
-    quad_rank_map<G>(q, i0, nr, nwq, bits, wpre, scratch);
+    quad_rank_map<GC>(q, i0, nr, nwq, bits, wpre, scratch);
 
     const int64_t qbase = q.q_off[R], nq = q.q_off[R + 1] - qbase;
     if (!FILL && sg == 0) {
-        // C blocks of every group: (r, c) at G G group + G r + c, -1 where absent
-        for (int64_t t = threadIdx.x; t < G * G * nq; t += kQuadThreads) q.q_cblk[G * G * qbase + t] = -1;
+        // C blocks of every group: (r, c) at GR GC group + GC r + c, -1 where absent
+        for (int64_t t = threadIdx.x; t < GG * nq; t += kQuadThreads) q.q_cblk[GG * qbase + t] = -1;
         __syncthreads();
         for (int r = 0; r < nr; ++r)
             for (int64_t t = q.c_row_ptr[i0 + r] + threadIdx.x; t < q.c_row_ptr[i0 + r + 1];
                  t += kQuadThreads) {
                 const int32_t j = q.c_col_idx[t];
-                const int64_t rank = bit_rank_q(bits, wpre, j / G);
-                q.q_cblk[G * G * (qbase + rank) + G * r + (j % G)] = t;
-                q.q_col[qbase + rank] = j / G;     // same value from every block of the group
+                const int64_t rank = bit_rank_q(bits, wpre, j / GC);
+                q.q_cblk[GG * (qbase + rank) + GC * r + (j % GC)] = t;
+                q.q_col[qbase + rank] = j / GC;    // same value from every block of the group
             }
     }
     for (int64_t w0 = 0; w0 < nq; w0 += kQuadWindow) {
         const int wn = static_cast<int>(nq - w0 < kQuadWindow ? nq - w0 : kQuadWindow);
         for (int t = threadIdx.x; t < wn; t += kQuadThreads) cnt[t] = 0;
-        if (threadIdx.x < G) s_skip[threadIdx.x] = 0;
+        if (threadIdx.x < GR) s_skip[threadIdx.x] = 0;
         if (FILL) {
             // offsets of this segment's entries for the window's groups (a row
             // group holds fewer than 2^31 entries, so int32 relative offsets)
@@ -172,14 +174,14 @@ k_quad_stack(QuadSymArgs q) {
         // head k of every row, the next k with its A blocks and B row range
         // are in its registers, and the loads behind them are issued one
         // iteration before they are needed.
-        int64_t pos[G], end[G];
-        int32_t head[G], na[G];
+        int64_t pos[GR], end[GR];
+        int32_t head[GR], na[GR];
         int32_t nk = INT_MAX;
         int64_t ntb0 = 0, ntb1 = 0;
         auto advance = [&]() {        // thread 0: the next k from the heads
             nk = INT_MAX;
-            for (int r = 0; r < G; ++r) nk = head[r] < nk ? head[r] : nk;
-            for (int r = 0; r < G; ++r) {
+            for (int r = 0; r < GR; ++r) nk = head[r] < nk ? head[r] : nk;
+            for (int r = 0; r < GR; ++r) {
                 na[r] = -1;
                 if (nk != INT_MAX && head[r] == nk) {
                     na[r] = static_cast<int32_t>(pos[r]++);
@@ -193,7 +195,7 @@ k_quad_stack(QuadSymArgs q) {
             }
         };
         if (threadIdx.x == 0) {
-            for (int r = 0; r < G; ++r) {
+            for (int r = 0; r < GR; ++r) {
                 pos[r] = r < nr ? q.a_row_ptr[i0 + r] + s_skip[r] : 0;
                 end[r] = r < nr ? q.a_row_ptr[i0 + r + 1] : 0;
                 const int32_t h = pos[r] < end[r] ? q.a_col_idx[pos[r]] : INT_MAX;
@@ -206,7 +208,7 @@ k_quad_stack(QuadSymArgs q) {
                 s_k = nk;
                 s_tb0 = ntb0;
                 s_tb1 = ntb1;
-                for (int r = 0; r < G; ++r) s_a[r] = na[r];
+                for (int r = 0; r < GR; ++r) s_a[r] = na[r];
                 if (nk != INT_MAX) advance();
             }
             __syncthreads();
@@ -215,25 +217,22 @@ k_quad_stack(QuadSymArgs q) {
             const int64_t tb0 = s_tb0, tb1 = s_tb1;
             for (int64_t tb = tb0 + threadIdx.x; tb < tb1; tb += kQuadThreads) {
                 const int32_t j = q.b_col_idx[tb];
-                const int32_t Q = j / G;
-                if (tb > tb0 && q.b_col_idx[tb - 1] / G == Q) continue;   // an earlier column emits
+                const int32_t Q = j / GC;
+                if (tb > tb0 && q.b_col_idx[tb - 1] / GC == Q) continue;  // an earlier column emits
                 const int64_t r = bit_rank_q(bits, wpre, Q) - w0;
                 if (r < 0 || r >= wn) continue;
                 if (FILL) {
-                    int32_t b[G];
-                    for (int c = 0; c < G; ++c) b[c] = -1;
-                    for (int64_t t = tb; t < tb1 && t < tb + G; ++t) {
+                    int32_t e[4 * NE];
+                    for (int z = 0; z < 4 * NE; ++z) e[z] = -1;
+                    for (int r2 = 0; r2 < GR; ++r2) e[r2] = s_a[r2];
+                    for (int64_t t = tb; t < tb1 && t < tb + GC; ++t) {
                         const int32_t jj = q.b_col_idx[t];
-                        if (jj / G != Q) break;
-                        b[jj % G] = static_cast<int32_t>(t);
+                        if (jj / GC != Q) break;
+                        e[GR + jj % GC] = static_cast<int32_t>(t);
                     }
                     const int64_t slot = s_ebase + eoff[r] + cnt[r];
-                    if (G == 2) {
-                        q.ent[slot] = make_int4(s_a[0], s_a[G - 1], b[0], b[G - 1]);
-                    } else {
-                        q.ent[2 * slot] = make_int4(s_a[0], s_a[1 % G], s_a[2 % G], s_a[3 % G]);
-                        q.ent[2 * slot + 1] = make_int4(b[0], b[1 % G], b[2 % G], b[3 % G]);
-                    }
+                    for (int h = 0; h < NE; ++h)
+                        q.ent[NE * slot + h] = make_int4(e[4 * h], e[4 * h + 1], e[4 * h + 2], e[4 * h + 3]);
                 }
                 cnt[r] += 1;
             }
@@ -246,36 +245,41 @@ k_quad_stack(QuadSymArgs q) {
     }
 }
 
+#define BSM_QUAD_SHAPES(X) X(2, 2) X(4, 4) X(4, 2)
+
 int quad_pairs(const QuadSymArgs &q, int64_t *cnt, hipStream_t s) {
-    const int G = q.g;
-    const int64_t ngroups = (static_cast<int64_t>(q.r1 - q.r0) + G - 1) / G;
+    const int64_t ngroups = (static_cast<int64_t>(q.r1 - q.r0) + q.gr - 1) / q.gr;
     if (ngroups <= 0) return BSM_OK;
-    const size_t lds = sizeof(uint32_t) * 2 * quad_words(q.nbcols, G);
-    if (G == 4) k_quad_pairs<4><<<static_cast<unsigned>(ngroups), kQuadThreads, lds, s>>>(q, cnt);
-    else k_quad_pairs<2><<<static_cast<unsigned>(ngroups), kQuadThreads, lds, s>>>(q, cnt);
-    BSM_HIP(hipGetLastError());
-    return BSM_OK;
+    const size_t lds = sizeof(uint32_t) * 2 * quad_words(q.nbcols, q.gc);
+    const unsigned g = static_cast<unsigned>(ngroups);
+#define BSM_QP(R_, C_) \
+    if (q.gr == R_ && q.gc == C_) { k_quad_pairs<R_, C_><<<g, kQuadThreads, lds, s>>>(q, cnt); BSM_HIP(hipGetLastError()); return BSM_OK; }
+    BSM_QUAD_SHAPES(BSM_QP)
+#undef BSM_QP
+    set_error("internal: no %d x %d group builder", q.gr, q.gc);
+    return BSM_EINVAL;
 }
 
 int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s) {
-    const int G = q.g;
-    const int64_t ngroups = (static_cast<int64_t>(q.r1 - q.r0) + G - 1) / G;
+    const int64_t ngroups = (static_cast<int64_t>(q.r1 - q.r0) + q.gr - 1) / q.gr;
     if (ngroups <= 0) return BSM_OK;
     if (q.nseg < 1 || q.kseg < 1) { set_error("internal: quad k segments"); return BSM_EINVAL; }
-    const size_t lds = sizeof(uint32_t) * 2 * quad_words(q.nbcols, G) +
+    const size_t lds = sizeof(uint32_t) * 2 * quad_words(q.nbcols, q.gc) +
                        sizeof(int32_t) * kQuadWindow * (fill ? 2 : 1);
     const int64_t nblk = ngroups * q.nseg;
     if (nblk > (1ll << 31) - 1) { set_error("too many row groups in one chunk"); return BSM_EINVAL; }
     const unsigned g = static_cast<unsigned>(nblk);
-    if (G == 4) {
-        if (fill) k_quad_stack<true, 4><<<g, kQuadThreads, lds, s>>>(q);
-        else k_quad_stack<false, 4><<<g, kQuadThreads, lds, s>>>(q);
-    } else {
-        if (fill) k_quad_stack<true, 2><<<g, kQuadThreads, lds, s>>>(q);
-        else k_quad_stack<false, 2><<<g, kQuadThreads, lds, s>>>(q);
+#define BSM_QS(R_, C_)                                                                     \
+    if (q.gr == R_ && q.gc == C_) {                                                        \
+        if (fill) k_quad_stack<true, R_, C_><<<g, kQuadThreads, lds, s>>>(q);              \
+        else k_quad_stack<false, R_, C_><<<g, kQuadThreads, lds, s>>>(q);                  \
+        BSM_HIP(hipGetLastError());                                                        \
+        return BSM_OK;                                                                     \
     }
-    BSM_HIP(hipGetLastError());
-    return BSM_OK;
+    BSM_QUAD_SHAPES(BSM_QS)
+#undef BSM_QS
+    set_error("internal: no %d x %d group builder", q.gr, q.gc);
+    return BSM_EINVAL;
 }
 
 __global__ void k_seg_starts(const int64_t *seg_off, int32_t nseg, int64_t n, int64_t *starts) {

@@ -63,14 +63,14 @@ struct SmmArgs {
     int32_t pad_;
     int32_t prec;               // bsm_precision
     unsigned long long *counter;  // work counter of the persistent kernel (NULL: allocated per launch)
-    // group kernel: G x G groups of C blocks (G = 2: quads) with merged product lists
+    // group kernel: GR x GC groups of C blocks (2 x 2: quads) with merged product lists
     int64_t n_quads;            // groups
-    const int64_t *q_cblk;      // [G G n_quads] C block (r, c) of the group at G r + c, or -1
+    const int64_t *q_cblk;      // [GR GC n_quads] C block (r, c) of the group at GC r + c, or -1
     const int64_t *q_seg;       // [n_quads + 1] entry segments
-    const int4 *q_ent;          // G / 2 int4 per entry: A(row 0..G-1), B(col 0..G-1) indices or -1
+    const int4 *q_ent;          // ceil((GR + GC) / 4) int4 per entry: A(row 0..GR-1) then
+                                // B(col 0..GC-1) block indices, -1 where absent
     const int64_t *q_order;     // group of work item i (NULL: identity)
-    int32_t q_group;            // G: 2 or 4
-    int32_t pad2_;
+    int32_t q_gr, q_gc;         // group shape
 };
 
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s);
@@ -88,7 +88,9 @@ int smm_bench(int m, int n, int k, int64_t n_c, int per_c, int n_prm, const SmmP
 
 // Quad kernel (smm_quad.hip): uniform m = n = k in {5, 13, 23, 26, 32}.
 bool smm_quad_available(int m, int n, int k);
-int quad_group(int m);    // group edge G for uniform block size m (2 or 4)
+// Group shape for uniform block size m: 2 x 2 (quads) unless BSM_QUAD_GROUP
+// asks for 4 (4 x 4) or 42 (4 x 2, size 23) and m has that kernel.
+void quad_shape(int m, int *gr, int *gc);
 int launch_quad(const SmmArgs &a, hipStream_t s);
 
 // Reduced-precision products (smm_lowp.hip).

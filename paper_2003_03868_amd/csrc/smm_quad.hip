@@ -1,8 +1,8 @@
-// FP64 block products for uniform block sizes, one workgroup per G x G group
-// of C blocks (G = 2: quads; G = 4: groups of sixteen) with a merged product
-// list (built in quad.hip).
+// FP64 block products for uniform block sizes, one workgroup per GR x GC
+// group of C blocks (2 x 2: quads, the default; 4 x 4 and 4 x 2 on request)
+// with a merged product list (built in quad.hip).
 //
-// Per entry k the workgroup stages the (up to) 2 G operand blocks
+// Per entry k the workgroup stages the (up to) GR + GC operand blocks
 // A(i_r, k), B(k, j_c) in LDS exactly as they sit in HBM, each read from HBM
 // once, and multiplies every product (r, c) the entry holds; each C block's
 // sum runs over its own products in ascending k exactly as in the
@@ -10,8 +10,8 @@
 // the same bits.  Instruction and lane roles are those of the
 // compile-time-shape kernel (V_MFMA_F64_4X4X4_4B_F64; lane = 16 x + 4 b + y,
 // block b = 2 bh + bw owns the 4 x 4 tiles of row half bh and column half
-// bw).  With W waves per group, a wave computes G G / W of the C blocks (an
-// NR x NC patch) and stages operands wv, wv + W, ... (quads: W = 4, one
+// bw).  With W waves per group, a wave computes GR GC / W of the C blocks
+// (an NR x NC patch) and stages operands wv, wv + W, ... (quads: W = 4, one
 // each, the fastest form on the sign workload; W = 1: one wave reads each A
 // value once for two column blocks and each B value once for two row
 // blocks).  Operands of the next entry are prefetched into registers; entry
@@ -60,7 +60,7 @@ __device__ inline double q_wave_max(double v) {
 // columns [C0, C0 + NC) of the group) is done when bit NC r + c of PM is set.
 // PM is a compile-time constant, so the k loop holds no tests; A rows and B
 // columns no product uses are not read.
-template <int S, int G, int NR, int NC, unsigned PM>
+template <int S, int GR, int NR, int NC, unsigned PM>
 __device__ inline void quad_step(const double *sm, int R0, int C0, int ra0, int rb0,
                                  bool klast_ok,
                                  double (&acc)[NR * NC][QShape<S>::H][QShape<S>::H]) {
@@ -68,7 +68,7 @@ __device__ inline void quad_step(const double *sm, int R0, int C0, int ra0, int 
     constexpr int H = Q::H;
 #pragma unroll
     for (int ks = 0; ks < Q::KS; ++ks) {
-        if (G == 4) __builtin_amdgcn_sched_barrier(0);
+        if (GR == 4) __builtin_amdgcn_sched_barrier(0);
         double av[NR][H], bv[NC][H];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -89,7 +89,7 @@ __device__ inline void quad_step(const double *sm, int R0, int C0, int ra0, int 
             if (PM & colbits) {
 #pragma unroll
                 for (int u = 0; u < H; ++u) {
-                    const double v = sm[(G + C0 + c) * Q::B2 + rb0 + 4 * u + 4 * ks * S];
+                    const double v = sm[(GR + C0 + c) * Q::B2 + rb0 + 4 * u + 4 * ks * S];
                     bv[c][u] = (ks == Q::KS - 1 && Q::KLAST < 4 && !klast_ok) ? 0.0 : v;
                 }
             }
@@ -111,7 +111,7 @@ __device__ inline void quad_step(const double *sm, int R0, int C0, int ra0, int 
 
 // The wave's products of an entry with operand flags hm (bit z: operand z
 // present): dispatch on the wave's product mask to a compile-time variant.
-template <int S, int G, int NR, int NC>
+template <int S, int GR, int NR, int NC>
 __device__ inline void quad_entry(const double *sm, int R0, int C0, int ra0, int rb0,
                                   bool klast_ok, unsigned hm,
                                   double (&acc)[NR * NC][QShape<S>::H][QShape<S>::H]) {
@@ -120,11 +120,11 @@ __device__ inline void quad_entry(const double *sm, int R0, int C0, int ra0, int
     for (int r = 0; r < NR; ++r)
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (((hm >> (R0 + r)) & 1u) && ((hm >> (G + C0 + c)) & 1u)) pm |= 1u << (NC * r + c);
+            if (((hm >> (R0 + r)) & 1u) && ((hm >> (GR + C0 + c)) & 1u)) pm |= 1u << (NC * r + c);
 #define BSM_QS(M) \
-    case M: quad_step<S, G, NR, NC, (M)>(sm, R0, C0, ra0, rb0, klast_ok, acc); break;
+    case M: quad_step<S, GR, NR, NC, (M)>(sm, R0, C0, ra0, rb0, klast_ok, acc); break;
     if (NR * NC == 1) {
-        if (pm) quad_step<S, G, NR, NC, 1u>(sm, R0, C0, ra0, rb0, klast_ok, acc);
+        if (pm) quad_step<S, GR, NR, NC, 1u>(sm, R0, C0, ra0, rb0, klast_ok, acc);
     } else if (NR * NC == 2) {
         switch (pm) { BSM_QS(1u) BSM_QS(2u) BSM_QS(3u) default: break; }
     } else {
@@ -140,7 +140,7 @@ __device__ inline void quad_entry(const double *sm, int R0, int C0, int ra0, int
 
 // alpha * sum + beta * C_in for the wave's C blocks of group `item`, with the
 // blocks' filter norms.
-template <int S, int G, int NR, int NC>
+template <int S, int GR, int GC, int NR, int NC>
 __device__ inline void quad_store(const SmmArgs &a, int64_t item, int R0, int C0, int lane,
                                   const double (&acc)[NR * NC][QShape<S>::H][QShape<S>::H]) {
     constexpr int H = QShape<S>::H;
@@ -148,7 +148,7 @@ __device__ inline void quad_store(const SmmArgs &a, int64_t item, int R0, int C0
     const int bh = blk >> 1, bw = blk & 1;
 #pragma unroll
     for (int zc = 0; zc < NR * NC; ++zc) {
-        const int64_t c = a.q_cblk[G * G * item + G * (R0 + zc / NC) + C0 + zc % NC];
+        const int64_t c = a.q_cblk[GR * GC * item + GC * (R0 + zc / NC) + C0 + zc % NC];
         if (c < 0) continue;
         const int64_t co = a.c_blk_off[c];
         const double *cin = nullptr;
@@ -186,39 +186,44 @@ __device__ inline void quad_store(const SmmArgs &a, int64_t item, int R0, int C0
 // stages operand w.  Groups of sixteen: W = 16, wave w computes C block
 // (w / 4, w % 4), and waves w and w + 8 stage the two halves of operand
 // w % 8 (with eight waves, two C blocks each, the register demand spills).
+// 4 x 2 groups: W = 8, wave w computes C block (w / 2, w % 2); waves 0..5
+// stage the four A and two B blocks.
 // WPE: the occupancy (waves per SIMD) the register allocation aims for.
-template <int S, int G, int W, int WPE, int EPS>
+template <int S, int GR, int GC, int W, int WPE, int EPS>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_smm_f64_quad(SmmArgs a) {
     using Q = QShape<S>;
     constexpr int H = Q::H;
-    constexpr int NPW = G * G / W;              // C blocks per wave
-    constexpr int NC = NPW < G ? NPW : G;       // group columns per wave
+    constexpr int NPW = GR * GC / W;            // C blocks per wave
+    constexpr int NC = NPW < GC ? NPW : GC;     // group columns per wave
     constexpr int NR = NPW / NC;                // group rows per wave
-    constexpr int NOP = 2 * G;                  // operand blocks per entry
+    constexpr int NOP = GR + GC;                // operand blocks per entry
     constexpr int WPO = W > NOP ? W / NOP : 1;  // waves sharing the staging of one block
     constexpr int NZ = W > NOP ? 1 : NOP / W;   // operand blocks (or parts) staged per wave
     constexpr int NVP = (Q::NV + WPO - 1) / WPO;  // register slots of one staged part
-    constexpr int NE = G / 2;                   // int4 per entry
+    constexpr int NE = (NOP + 3) / 4;           // int4 per entry
     constexpr int SLOT = NOP * Q::B2;           // LDS doubles of one staged entry
-    static_assert(G == 2 || G == 4, "group edge 2 or 4");
-    static_assert(NR * NC * W == G * G, "waves must tile the group");
+    static_assert(NE <= 2 && GC % NC == 0, "group shapes up to 4 x 4");
+    static_assert(NR * NC * W == GR * GC, "waves must tile the group");
+    static_assert(W > NOP || NOP % W == 0, "operands must split evenly over the waves");
     __shared__ double sm[EPS * SLOT + Q::TAIL];
     const int64_t it = quad_item(a.n_quads);
     if (it >= a.n_quads) return;
     const int64_t item = a.q_order ? a.q_order[it] : it;
     const int lane = threadIdx.x % kWave;
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));  // wave-uniform
-    const int R0 = (wv / (G / NC)) * NR;
-    const int C0 = (wv % (G / NC)) * NC;
+    const int R0 = (wv / (GC / NC)) * NR;
+    const int C0 = (wv % (GC / NC)) * NC;
     const int x = lane >> 4, blk = (lane >> 2) & 3, y = lane & 3;
     const int bh = blk >> 1, bw = blk & 1;
-    // staged block zz of this wave is entry operand wv + W zz (A rows 0 .. G-1,
-    // then B columns); with more waves than operands, wave wv stages part
-    // wv / NOP (slots [part NVP, part NVP + NVP)) of operand wv % NOP
+    // staged block zz of this wave is entry operand wv + W zz (A rows 0 .. GR-1,
+    // then B columns); with more waves than operands, wave wv < WPO NOP stages
+    // part wv / NOP (slots [part NVP, part NVP + NVP)) of operand wv % NOP and
+    // the other waves stage nothing
     static_assert(WPO <= 2, "a block is staged by one or two waves");
     auto zid = [&](int zz) { return W > NOP ? wv % NOP : wv + W * zz; };
     const int part = W > NOP ? wv / NOP : 0;
+    const bool stager = W <= NOP || wv < WPO * NOP;
     // element lane + 64 (P NVP + v) of a block exists (compile-time but for the last slot)
     auto has = [&](auto P, int v) {
         constexpr int p0 = decltype(P)::value * NVP;
@@ -260,9 +265,9 @@ k_smm_f64_quad(SmmArgs a) {
 #pragma unroll
         for (int zz = 0; zz < NZ; ++zz) {
             const int z = zid(zz);
-            const int id = pick(en, z);
+            const int id = stager ? pick(en, z) : -1;
             if (id >= 0) {
-                const double *g = (z < G ? a.a_vals : a.b_vals) + static_cast<int64_t>(id) * Q::B2;
+                const double *g = (z < GR ? a.a_vals : a.b_vals) + static_cast<int64_t>(id) * Q::B2;
                 auto ld = [&](auto P) {
                     constexpr int p0 = decltype(P)::value * NVP;
 #pragma unroll
@@ -279,7 +284,7 @@ k_smm_f64_quad(SmmArgs a) {
         for (int h = 0; h < NE; ++h)
             f |= ((c[h].x >= 0 ? 1u : 0u) | (c[h].y >= 0 ? 2u : 0u) | (c[h].z >= 0 ? 4u : 0u) |
                   (c[h].w >= 0 ? 8u : 0u)) << (4 * h);
-        // quads: bits 0, 1 = A rows, 2, 3 = B columns; sixteen: 0..3 A, 4..7 B
+        // bit z: operand z present (A rows 0 .. GR-1, then B columns)
         return f;
     };
     auto fetch = [&](int64_t t, int4 (&out)[NE]) {
@@ -313,7 +318,7 @@ k_smm_f64_quad(SmmArgs a) {
 #pragma unroll
             for (int zz = 0; zz < NZ; ++zz) {
                 const int z = zid(zz);
-                if ((hm[q] >> z) & 1u) {
+                if (stager && ((hm[q] >> z) & 1u)) {
                     auto st = [&](auto P) {
                         constexpr int p0 = decltype(P)::value * NVP;
 #pragma unroll
@@ -342,11 +347,11 @@ k_smm_f64_quad(SmmArgs a) {
         }
 #pragma unroll
         for (int q = 0; q < EPS; ++q)
-            quad_entry<S, G, NR, NC>(sm + q * SLOT, R0, C0, ra0, rb0, klast_ok, hm[q], acc);
+            quad_entry<S, GR, NR, NC>(sm + q * SLOT, R0, C0, ra0, rb0, klast_ok, hm[q], acc);
         __syncthreads();
     }
 
-    quad_store<S, G, NR, NC>(a, item, R0, C0, lane, acc);
+    quad_store<S, GR, GC, NR, NC>(a, item, R0, C0, lane, acc);
 }
 
 }  // namespace
@@ -369,10 +374,13 @@ bool smm_quad_available(int m, int n, int k) {
     return m == n && n == k && (m == 5 || m == 13 || m == 23 || m == 26 || m == 32);
 }
 
-int quad_group(int m) {
+void quad_shape(int m, int *gr, int *gc) {
     const char *e = getenv("BSM_QUAD_GROUP");
     const int g = e ? atoi(e) : 2;
-    return (g == 4 && m != 5) ? 4 : 2;
+    *gr = *gc = 2;
+    if (m == 5) return;
+    if (g == 4) { *gr = 4; *gc = 4; }
+    else if (g == 42 && m == 23) { *gr = 4; *gc = 2; }
 }
 
 int launch_quad(const SmmArgs &a, hipStream_t s) {
@@ -386,33 +394,41 @@ int launch_quad(const SmmArgs &a, hipStream_t s) {
     }
     const unsigned g = static_cast<unsigned>(grid);
     const int w = quad_waves(), eps = quad_stage();
-    if (a.q_group == 4) {
+    if (a.q_gr == 4 && a.q_gc == 2 && a.uni_m == 23) {
+        k_smm_f64_quad<23, 4, 2, 8, 6, 1><<<g, 512, 0, s>>>(a);
+        BSM_HIP(hipGetLastError());
+        return BSM_OK;
+    }
+    if (a.q_gr == 4 && a.q_gc == 4) {
         switch (a.uni_m) {
-            case 13: k_smm_f64_quad<13, 4, 16, 8, 1><<<g, 1024, 0, s>>>(a); break;
-            case 23: k_smm_f64_quad<23, 4, 16, 8, 1><<<g, 1024, 0, s>>>(a); break;
-            case 26: k_smm_f64_quad<26, 4, 16, 4, 1><<<g, 1024, 0, s>>>(a); break;
-            case 32: k_smm_f64_quad<32, 4, 16, 4, 1><<<g, 1024, 0, s>>>(a); break;
+            case 13: k_smm_f64_quad<13, 4, 4, 16, 8, 1><<<g, 1024, 0, s>>>(a); break;
+            case 23: k_smm_f64_quad<23, 4, 4, 16, 8, 1><<<g, 1024, 0, s>>>(a); break;
+            case 26: k_smm_f64_quad<26, 4, 4, 16, 4, 1><<<g, 1024, 0, s>>>(a); break;
+            case 32: k_smm_f64_quad<32, 4, 4, 16, 4, 1><<<g, 1024, 0, s>>>(a); break;
             default: set_error("no group-of-sixteen kernel for block size %d", a.uni_m); return BSM_EINVAL;
         }
         BSM_HIP(hipGetLastError());
         return BSM_OK;
     }
-    if (a.q_group != 2) { set_error("internal: group edge %d", a.q_group); return BSM_EINVAL; }
+    if (a.q_gr != 2 || a.q_gc != 2) {
+        set_error("internal: no %d x %d group kernel for block size %d", a.q_gr, a.q_gc, a.uni_m);
+        return BSM_EINVAL;
+    }
     switch (a.uni_m) {
-        case 5: k_smm_f64_quad<5, 2, 1, 8, 1><<<g, 64, 0, s>>>(a); break;
+        case 5: k_smm_f64_quad<5, 2, 2, 1, 8, 1><<<g, 64, 0, s>>>(a); break;
         case 13:
-            if (w == 4) k_smm_f64_quad<13, 2, 4, 6, 1><<<g, 256, 0, s>>>(a);
-            else if (w == 2) k_smm_f64_quad<13, 2, 2, 4, 1><<<g, 128, 0, s>>>(a);
-            else k_smm_f64_quad<13, 2, 1, 4, 1><<<g, 64, 0, s>>>(a);
+            if (w == 4) k_smm_f64_quad<13, 2, 2, 4, 6, 1><<<g, 256, 0, s>>>(a);
+            else if (w == 2) k_smm_f64_quad<13, 2, 2, 2, 4, 1><<<g, 128, 0, s>>>(a);
+            else k_smm_f64_quad<13, 2, 2, 1, 4, 1><<<g, 64, 0, s>>>(a);
             break;
         case 23:
-            if (w == 4 && eps == 2) k_smm_f64_quad<23, 2, 4, 4, 2><<<g, 256, 0, s>>>(a);
-            else if (w == 4) k_smm_f64_quad<23, 2, 4, 6, 1><<<g, 256, 0, s>>>(a);   // 6 waves/SIMD: 1% faster than 5
-            else if (w == 2) k_smm_f64_quad<23, 2, 2, 3, 1><<<g, 128, 0, s>>>(a);
-            else k_smm_f64_quad<23, 2, 1, 1, 1><<<g, 64, 0, s>>>(a);
+            if (w == 4 && eps == 2) k_smm_f64_quad<23, 2, 2, 4, 4, 2><<<g, 256, 0, s>>>(a);
+            else if (w == 4) k_smm_f64_quad<23, 2, 2, 4, 6, 1><<<g, 256, 0, s>>>(a);   // 6 waves/SIMD: 1% faster than 5
+            else if (w == 2) k_smm_f64_quad<23, 2, 2, 2, 3, 1><<<g, 128, 0, s>>>(a);
+            else k_smm_f64_quad<23, 2, 2, 1, 1, 1><<<g, 64, 0, s>>>(a);
             break;
-        case 26: k_smm_f64_quad<26, 2, 4, 4, 1><<<g, 256, 0, s>>>(a); break;
-        case 32: k_smm_f64_quad<32, 2, 4, 4, 1><<<g, 256, 0, s>>>(a); break;
+        case 26: k_smm_f64_quad<26, 2, 2, 4, 4, 1><<<g, 256, 0, s>>>(a); break;
+        case 32: k_smm_f64_quad<32, 2, 2, 4, 4, 1><<<g, 256, 0, s>>>(a); break;
         default: set_error("no quad kernel for block size %d", a.uni_m); return BSM_EINVAL;
     }
     BSM_HIP(hipGetLastError());

@@ -41,19 +41,20 @@ int sort_worklist(const int64_t *wl_in, int64_t *wl_out, int64_t c0, int64_t n, 
                   const int32_t *c_row, const int32_t *c_col, const int32_t *rbs,
                   const int32_t *cbs, const int64_t *seg, int64_t *hist_host, hipStream_t s);
 
-// G x G groups of C blocks (G = 2: quads) and their merged entry lists,
+// GR x GC groups of C blocks (2 x 2: quads) and their merged entry lists,
 // straight from the patterns of A, B and the unfiltered C (quad.hip), over
-// the row groups of block rows [r0, r1) (r0 a multiple of G).  quad_pairs:
+// the row groups of block rows [r0, r1) (r0 a multiple of GR).  quad_pairs:
 // cnt[R] = groups of row group R.  quad_stack count pass (fill = false),
-// with q_off = scanned group counts: q_cblk[G G q + G r + c] = C block
-// (G R + r, G Q + c) or -1, q_col[q] = Q and e_off[q nseg + s] = entries of
-// group q with k in segment s; fill pass (e_off scanned): entry n of segment s
-// of group q at ent[(G / 2) (e_off[q nseg + s] + n)], ascending k, so each
-// group's entries are contiguous and in ascending k.  Segment s covers
-// k in [s kseg, (s + 1) kseg); one workgroup per (row group, segment).
+// with q_off = scanned group counts: q_cblk[GR GC q + GC r + c] = C block
+// (GR R + r, GC Q + c) or -1, q_col[q] = Q and e_off[q nseg + s] = entries
+// of group q with k in segment s; fill pass (e_off scanned): entry n of
+// segment s of group q at ent[NE (e_off[q nseg + s] + n)] with
+// NE = ceil((GR + GC) / 4), ascending k, so each group's entries are
+// contiguous and in ascending k.  Segment s covers k in [s kseg, (s + 1) kseg);
+// one workgroup per (row group, segment).  Shapes: 2x2, 4x4, 4x2.
 struct QuadSymArgs {
     int32_t r0, r1, nbcols;
-    int32_t g;                   // group edge: 2 (quads) or 4
+    int32_t gr, gc;              // group shape: rows x columns (2 x 2: quads)
     int32_t nseg, kseg;          // the k range split into nseg segments of kseg values
     const int64_t *a_row_ptr;
     const int32_t *a_col_idx;
@@ -66,7 +67,7 @@ struct QuadSymArgs {
     int32_t *q_col;              // column group Q of every group (count pass)
     int64_t *e_off;              // [n_groups nseg + 1]: count pass, entries per (group, segment);
                                  // fill pass, their scanned offsets (group-major)
-    int4 *ent;                   // G / 2 int4 per entry
+    int4 *ent;                   // ceil((gr + gc) / 4) int4 per entry
 };
 int quad_pairs(const QuadSymArgs &q, int64_t *cnt, hipStream_t s);
 int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s);
