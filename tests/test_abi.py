@@ -45,6 +45,8 @@ def test_struct_layouts_match_header(tmp_path):
     structs = {
         "bsm_info": bsm.bsm_info, "bsm_mult_stats": bsm.bsm_mult_stats,
         "bsm_sign_opts": bsm.bsm_sign_opts, "bsm_sign_stats": bsm.bsm_sign_stats,
+        "bsm_mu_stats": bsm.bsm_mu_stats, "bsm_tc2_stats": bsm.bsm_tc2_stats,
+        "bsm_smm_params": bsm.bsm_smm_params,
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bsm.h"', 'int main(void){']
     for sname, cls in structs.items():
