@@ -148,6 +148,56 @@ def bench_nonorth(args, h, dh, bsm, synth, torch):
         "cpu_baseline": None}))
 
 
+def bench_mult832(args, bsm, synth, torch):
+    """The single FP64 multiply C = A B of 64 x 64 blocks of 13 (832 x 832),
+    each block present with probability 0.2, eps 0: repeated calls on the
+    resident operands, median per call (the launch- and latency-bound end of
+    the range); the oracle times the same multiply on the host."""
+    import numpy as np
+
+    import oracle
+    a, b = synth.random_bsr_pair(64, 13, 0.2, seed=args.seed)
+    da, db = bsm.Matrix.from_bsr(a, device=True), bsm.Matrix.from_bsr(b, device=True)
+    dc = bsm.Matrix.empty_like(a.row_blk_size, b.col_blk_size)
+    stream = torch.cuda.current_stream()
+    reps = max(args.steps, 1) * 100
+    for _ in range(max(args.warmup, 1) * 10):
+        bsm.bsm_multiply(1.0, da.handle, db.handle, 0.0, dc.handle, 0.0, bsm.NORM_FROB,
+                         stream=stream)
+    torch.cuda.synchronize()
+    times, st = [], None
+    for _ in range(reps):
+        t = time.perf_counter()
+        st = bsm.bsm_multiply(1.0, da.handle, db.handle, 0.0, dc.handle, 0.0, bsm.NORM_FROB,
+                              stream=stream)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    med = float(np.median(times))
+    t0 = time.perf_counter()
+    oracle.multiply(1.0, a, b)
+    cpu_dt = time.perf_counter() - t0
+    achieved = st.flops / (st.smm_ms * 1e-3) / 1e12 if st.smm_ms > 0 else 0.0
+    log(f"832 multiply: median {med * 1e3:.3f} ms over {reps} calls, block products "
+        f"{st.smm_ms * 1e3:.1f} us, {st.n_products} products")
+    print(json.dumps({
+        "metric": "block-sparse multiply GFLOP/s (FP64 vs mixed); sign-iteration time to 1e-6",
+        "value": st.flops / med / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": reps,
+        "warmup": max(args.warmup, 1) * 10, "ms_per_step": med * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "FP64 multiply C = A B, 64 x 64 blocks of 13 (832 x 832), "
+                               "20% of blocks present, eps_filter 0; median of repeated calls",
+                   "seed": args.seed},
+        "products": int(st.n_products), "flops": float(st.flops),
+        "roofline": {"bound": "mfma", "kernel": "k_smm_f64_quad<13,2,2,4,6,1>",
+                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "smm_ms_per_step": float(st.smm_ms)},
+        "cpu_baseline": {"value": st.flops / cpu_dt / 1e9, "unit": "GFLOP/s",
+                         "cores": oracle.num_threads(), "kind": "oracle",
+                         "sample": f"the whole multiply, {cpu_dt * 1e3:.1f} ms"}}))
+
+
 def bench_tc2(args, h, dh, bsm, torch):
     """Timed steps of TC2 purification at the occupied count of the
     workload; one JSON line."""
@@ -207,8 +257,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=["sign23", "mixed"], default="sign23",
-                    help="sign23: 2048 sites x 23; mixed: 4096 sites, sizes {5,13,23,26}")
+    ap.add_argument("--workload", choices=["sign23", "mixed", "mult832"], default="sign23",
+                    help="sign23: 2048 sites x 23; mixed: 4096 sites, sizes {5,13,23,26}; "
+                         "mult832: one 832 x 832 multiply (64 x 64 blocks of 13, 20%% present)")
     ap.add_argument("--sites", type=int, default=0, help="override the site count")
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -259,6 +310,10 @@ def main():
     bsm.load()
     torch.cuda.set_device(0)
     tune.install_default(args.table)
+
+    if args.workload == "mult832":
+        bench_mult832(args, bsm, synth, torch)
+        return
 
     t0 = time.perf_counter()
     if args.workload == "sign23":
