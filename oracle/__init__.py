@@ -10,7 +10,8 @@ Parity status of each function (what pins it, see ``tests/test_oracle.py``):
 
 * ``multiply``      -- pinned: dense NumPy GEMM brute force on random tiny
                        cases (mixed sizes, alpha/beta, filter), the block
-                       pattern by Python set logic.
+                       pattern by Python set logic; with screening, the same
+                       brute force leaving out the screened terms.
 * ``filter``        -- pinned: keep rule re-derived per block from the dense
                        matrix.
 * ``sign_ns``       -- pinned: eigen-decomposition sign (LAPACK) on tiny
@@ -103,7 +104,10 @@ def _load():
             lib.orc_sign_ns.argtypes = [P, C.c_double, C.c_double, C.c_int, C.c_double,
                                         C.c_int32, C.c_int32, P, C.POINTER(_SignStats)]
             lib.orc_sign.argtypes = [P, C.c_double, C.c_double, C.c_int, C.c_double,
-                                     C.c_int32, C.c_int32, C.c_int32, P, C.POINTER(_SignStats)]
+                                     C.c_int32, C.c_int32, C.c_int32, C.c_double, P,
+                                     C.POINTER(_SignStats)]
+            lib.orc_multiply_screened.argtypes = [C.c_double, P, P, C.c_double, P, C.c_double,
+                                                  C.c_int, C.c_double, P]
             lib.orc_add.argtypes = [C.c_double, P, C.c_double, P, C.c_double, C.c_double,
                                     C.c_int, P]
             lib.orc_density_from_sign.argtypes = [P, P]
@@ -157,15 +161,21 @@ def _norm(norm) -> int:
 
 
 def multiply(alpha: float, a: BSR, b: BSR, beta: float = 0.0, c: BSR | None = None,
-             eps: float = 0.0, norm="frob") -> BSR:
-    """C = alpha*A*B + beta*Cin, then the block-norm filter (plain loops)."""
+             eps: float = 0.0, norm="frob", screen: float = 0.0) -> BSR:
+    """C = alpha*A*B + beta*Cin, then the block-norm filter (plain loops);
+    screen > 0 leaves out the terms with ||A_ik||^2 ||B_kj||^2 < screen^2."""
     lib = _load()
     oa, ka = _in(a)
     ob, kb = _in(b)
     oc, kc = _in(c) if c is not None else (None, None)
     out = _OMat()
-    st = lib.orc_multiply(alpha, C.byref(oa), C.byref(ob), beta,
-                          C.byref(oc) if oc is not None else None, eps, _norm(norm), C.byref(out))
+    cref = C.byref(oc) if oc is not None else None
+    if screen > 0.0:
+        st = lib.orc_multiply_screened(alpha, C.byref(oa), C.byref(ob), beta, cref, eps,
+                                       _norm(norm), screen, C.byref(out))
+    else:
+        st = lib.orc_multiply(alpha, C.byref(oa), C.byref(ob), beta, cref, eps, _norm(norm),
+                              C.byref(out))
     _check(st, "multiply")
     return _out(out, a.row_blk_size, b.col_blk_size)
 
@@ -222,7 +232,8 @@ def add(alpha: float, a: BSR, beta: float = 0.0, b: BSR | None = None, gamma: fl
 
 
 def sign_ns(h: BSR, mu: float = 0.0, eps: float = 0.0, tol: float = 1e-6,
-            max_iter: int = 100, fixed_iters: int = 0, norm="frob", order: int = 2):
+            max_iter: int = 100, fixed_iters: int = 0, norm="frob", order: int = 2,
+            screen: float = 0.0):
     """Sign iteration of the given order (2: Newton-Schulz, 3, 5, 7); returns
     (X, stats, status).
 
@@ -234,7 +245,7 @@ def sign_ns(h: BSR, mu: float = 0.0, eps: float = 0.0, tol: float = 1e-6,
     out = _OMat()
     st = _SignStats()
     status = lib.orc_sign(C.byref(oh), mu, eps, _norm(norm), tol, max_iter, fixed_iters, order,
-                          C.byref(out), C.byref(st))
+                          screen, C.byref(out), C.byref(st))
     if status not in (OK, ENOCONV, ENONFINITE):
         raise RuntimeError(f"oracle sign iteration failed with status {status}")
     x = _out(out, h.row_blk_size, h.col_blk_size) if out.row_ptr else None

@@ -177,15 +177,30 @@ static void free_rows(rowbuf *rows, int32_t n)
  * Each C_ij is summed over k ascending, and inside a block product over the
  * inner index ascending.  cin may be NULL (treated as empty); with beta == 0
  * its pattern and values are ignored.
+ *
+ * Product-level norm screening (the screening of the Sign-Method section's
+ * discussion of sparsity; tau > 0): the term A_ik B_kj is left out of the
+ * sum when ||A_ik||_F^2 ||B_kj||_F^2 < tau^2 (squared Frobenius norms in
+ * FP64, summed in storage order).  The stored pattern is that of the
+ * unscreened product; a block whose terms were all left out holds
+ * beta C_in (or zeros) before the filter.  tau = 0 screens nothing.
  */
-int orc_multiply(double alpha, const omat *a, const omat *b, double beta,
-                 const omat *cin, double eps, int norm_kind, omat *out)
+static double block_sq(const double *x, int64_t len)
+{
+    double s = 0.0;
+    for (int64_t e = 0; e < len; ++e) s += x[e] * x[e];
+    return s;
+}
+
+int orc_multiply_screened(double alpha, const omat *a, const omat *b, double beta,
+                          const omat *cin, double eps, int norm_kind, double tau, omat *out)
 {
     if (a->nbcols != b->nbrows) return ORC_EINVAL;
     for (int32_t k = 0; k < a->nbcols; ++k) if (a->cbs[k] != b->rbs[k]) return ORC_EINVAL;
     for (int32_t i = 0; i < a->nbrows; ++i) if (a->rbs[i] < 1 || a->rbs[i] > 64) return ORC_EINVAL;
     for (int32_t j = 0; j < b->nbcols; ++j) if (b->cbs[j] < 1 || b->cbs[j] > 64) return ORC_EINVAL;
-    if (eps < 0) return ORC_EINVAL;
+    if (eps < 0 || !(tau >= 0.0)) return ORC_EINVAL;
+    const double tau2 = tau * tau;
     int use_c = (beta != 0.0) && cin != NULL;
     if (use_c && (cin->nbrows != a->nbrows || cin->nbcols != b->nbcols)) return ORC_EINVAL;
 
@@ -230,6 +245,8 @@ int orc_multiply(double alpha, const omat *a, const omat *b, double beta,
                     const int32_t kk = a->cbs[k];
                     const double *ab = a->values + aoff[ta];
                     const double *bb = b->values + boff[tb];
+                    if (tau > 0.0 && block_sq(ab, (int64_t)m * kk) * block_sq(bb, (int64_t)kk * n) < tau2)
+                        continue;                       /* screened term */
                     for (int r = 0; r < m; ++r)
                         for (int t = 0; t < kk; ++t) {
                             const double av = ab[r * kk + t];
@@ -259,6 +276,13 @@ int orc_multiply(double alpha, const omat *a, const omat *b, double beta,
     free_rows(rows, a->nbrows);
     free(aoff); free(boff); free(coff);
     return status;
+}
+
+/* The unscreened multiply. */
+int orc_multiply(double alpha, const omat *a, const omat *b, double beta,
+                 const omat *cin, double eps, int norm_kind, omat *out)
+{
+    return orc_multiply_screened(alpha, a, b, beta, cin, eps, norm_kind, 0.0, out);
 }
 
 /* Filter a matrix on its own (same keep test as after a multiply). */
@@ -518,14 +542,14 @@ static double product_flops(const omat *a, const omat *b)
  * - 8580) with five multiplies per iteration.
  */
 static int sign_update(int32_t order, const omat *x, const omat *y, double eps, int norm_kind,
-                       omat *xn, orc_sign_stats *st)
+                       double tau, omat *xn, orc_sign_stats *st)
 {
     omat c = {0}, w = {0}, y2 = {0}, v = {0};
     int status;
     if (order == 2) {
         st->flops += product_flops(x, y);
         st->n_multiplies++;
-        return orc_multiply(-0.5, x, y, 1.5, x, eps, norm_kind, xn);
+        return orc_multiply_screened(-0.5, x, y, 1.5, x, eps, norm_kind, tau, xn);
     }
     if (order == 3) {
         status = orc_shift_scale(y, 1.5, -10.0, &c);                  /* 15 I - 10 Y */
@@ -607,12 +631,13 @@ static int sign_update(int32_t order, const omat *x, const omat *y, double eps, 
  * tol.
  */
 int orc_sign(const omat *h, double mu, double eps, int norm_kind, double tol,
-             int32_t max_iter, int32_t fixed_iters, int32_t order, omat *x_out,
+             int32_t max_iter, int32_t fixed_iters, int32_t order, double tau, omat *x_out,
              orc_sign_stats *st)
 {
     if (h->nbrows != h->nbcols || eps < 0 || max_iter < 0 || max_iter > 120 ||
         fixed_iters < 0 || fixed_iters > 120 ||
-        (order != 2 && order != 3 && order != 5 && order != 7))
+        (order != 2 && order != 3 && order != 5 && order != 7) ||
+        !(tau >= 0.0) || (tau > 0.0 && order != 2))
         return ORC_EINVAL;
     for (int32_t i = 0; i < h->nbrows; ++i) if (h->rbs[i] != h->cbs[i]) return ORC_EINVAL;
     memset(st, 0, sizeof(*st));
@@ -629,7 +654,7 @@ int orc_sign(const omat *h, double mu, double eps, int norm_kind, double tol,
     int stall = 0;
     for (int32_t k = 0;; ++k) {
         st->flops += product_flops(&x, &x);
-        status = orc_multiply(1.0, &x, &x, 0.0, NULL, eps, norm_kind, &y);
+        status = orc_multiply_screened(1.0, &x, &x, 0.0, NULL, eps, norm_kind, tau, &y);
         st->n_multiplies++;
         if (status != ORC_OK) break;
         double r = sqrt(orc_sqdist_identity(&y, 1.0)) / n;
@@ -644,7 +669,7 @@ int orc_sign(const omat *h, double mu, double eps, int norm_kind, double tol,
             else stall = 0;
             if (k == max_iter) { status = ORC_ENOCONV; break; }
         }
-        status = sign_update(order, &x, &y, eps, norm_kind, &xn, st);
+        status = sign_update(order, &x, &y, eps, norm_kind, tau, &xn, st);
         orc_free(&y);
         if (status != ORC_OK) break;
         orc_free(&x);
@@ -664,7 +689,7 @@ int orc_sign(const omat *h, double mu, double eps, int norm_kind, double tol,
 int orc_sign_ns(const omat *h, double mu, double eps, int norm_kind, double tol,
                 int32_t max_iter, int32_t fixed_iters, omat *x_out, orc_sign_stats *st)
 {
-    return orc_sign(h, mu, eps, norm_kind, tol, max_iter, fixed_iters, 2, x_out, st);
+    return orc_sign(h, mu, eps, norm_kind, tol, max_iter, fixed_iters, 2, 0.0, x_out, st);
 }
 
 /* P = (I - X)/2 as a new matrix (inserts missing diagonal blocks). */
@@ -808,7 +833,7 @@ int orc_density_nonorth(const omat *k, const omat *s_in, double mu, double eps, 
         status = orc_multiply(1.0, &z, k, 0.0, NULL, eps, norm_kind, &k1);
     if (status == ORC_OK) status = orc_multiply(1.0, &k1, &z, 0.0, NULL, eps, norm_kind, &kt);
     if (status == ORC_OK) {
-        status = orc_sign(&kt, mu, eps, norm_kind, tol, max_iter, 0, order, &x, st_sign);
+        status = orc_sign(&kt, mu, eps, norm_kind, tol, max_iter, 0, order, 0.0, &x, st_sign);
         if (first == ORC_OK) first = status;
     }
     if (status == ORC_OK || status == ORC_ENOCONV) {

@@ -730,3 +730,89 @@ def test_tc2_matches_sign_density_on_neighbour_hamiltonian(orc):
     ps = orc.density_from_sign(x)
     assert _rel(p.to_dense(), ps.to_dense()) <= 1e-6
     assert st["trace_p"] == pytest.approx(h.meta["n_occ"], abs=1e-5)
+
+
+# ------------------------------------------------ product-level norm screening
+
+def _scale_blocks(m: BSR, rng, lo=-4.0):
+    """Scale every stored block by 10^U(lo, 0) so block norms spread widely."""
+    off = m.block_offsets()
+    v = m.values.copy()
+    for t in range(m.nnzb):
+        v[off[t]:off[t + 1]] *= 10.0 ** rng.uniform(lo, 0.0)
+    return BSR(m.row_blk_size, m.col_blk_size, m.row_ptr, m.col_idx, v)
+
+
+def _screened_expected(alpha, a, b, beta, c, tau, eps):
+    """Brute force with the screening rule: per C block of the unscreened
+    pattern, the sum of the dense block products whose squared norms'
+    product is not below tau^2, then alpha, beta C_in and the filter.
+    Returns the kept blocks and the smallest relative distance of a norm
+    product from tau^2 (ties)."""
+    ab, bb = _blocks(a), _blocks(b)
+    cb = _blocks(c) if (c is not None and beta != 0.0) else {}
+    sa = {key: float((x * x).sum()) for key, x in ab.items()}
+    sb = {key: float((x * x).sum()) for key, x in bb.items()}
+    rows_of_k = {}
+    for (k, j) in bb:
+        rows_of_k.setdefault(k, []).append(j)
+    pattern = set(cb)
+    for (i, k) in ab:
+        for j in rows_of_k.get(k, ()):
+            pattern.add((i, j))
+    t2, margin, kept = tau * tau, np.inf, {}
+    for (i, j) in pattern:
+        m_, n_ = int(a.row_blk_size[i]), int(b.col_blk_size[j])
+        acc = np.zeros((m_, n_))
+        for (ii, k), x in ab.items():
+            if ii != i or (k, j) not in bb:
+                continue
+            p = sa[(i, k)] * sb[(k, j)]
+            margin = min(margin, abs(p - t2) / t2)
+            if p >= t2:
+                acc += x @ bb[(k, j)]
+        blk = alpha * acc + (beta * cb[(i, j)] if (i, j) in cb else 0.0)
+        if not (float((blk * blk).sum()) < eps * eps):
+            kept[(i, j)] = blk
+    return kept, margin
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_multiply_screened_matches_bruteforce(orc, seed):
+    rng = np.random.default_rng(300 + seed)
+    nb = int(rng.integers(3, 7))
+    sizes = rng.choice([3, 5, 8], nb) if seed % 2 else np.full(nb, 5)
+    a = _scale_blocks(synth.random_bsr(nb, nb, sizes, sizes, 0.6, rng), rng)
+    b = _scale_blocks(synth.random_bsr(nb, nb, sizes, sizes, 0.6, rng), rng)
+    c = synth.random_bsr(nb, nb, sizes, sizes, 0.3, rng)
+    beta = float(rng.choice([0.0, 1.5]))
+    # tau at the median of the norm products, nudged off ties
+    ab, bb = _blocks(a), _blocks(b)
+    prods = sorted(float((x * x).sum()) * float((y * y).sum())
+                   for (i, k), x in ab.items() for (kk, j), y in bb.items() if kk == k)
+    tau = float(np.sqrt(prods[len(prods) // 2])) * 1.0001
+    kept, margin = _screened_expected(-0.7, a, b, beta, c, tau, 0.0)
+    assert margin > 1e-9
+    got = orc.multiply(-0.7, a, b, beta, c, screen=tau)
+    assert got.pattern() == set(kept)
+    gb = _blocks(got)
+    for key, blk in kept.items():
+        assert _rel(gb[key], blk) <= 1e-13, key
+    # screening really removed terms, and tau = 0 is the plain product
+    full = orc.multiply(-0.7, a, b, beta, c)
+    assert _rel(full.values, got.values) > 1e-12
+    assert np.array_equal(orc.multiply(-0.7, a, b, beta, c, screen=0.0).values, full.values)
+
+
+def test_sign_screened_converges_near_the_plain_sign(orc):
+    """The screened Newton-Schulz iteration: with a screening threshold
+    below the filter the result stays within the filter's accuracy of the
+    unscreened one, and trace(P) at the occupied count."""
+    h = synth.neighbour_hamiltonian(100, 5, cutoff=4.5, seed=3)
+    x0, st0, s0 = orc.sign_ns(h, eps=1e-7, tol=1e-7)
+    x1, st1, s1 = orc.sign_ns(h, eps=1e-7, tol=1e-7, screen=1e-9)
+    assert s0 == s1 == orc.OK
+    assert _rel(x1.to_dense(), x0.to_dense()) < 1e-5
+    assert st1["trace_p"] == pytest.approx(h.meta["n_occ"], abs=1e-4)
+    with pytest.raises(RuntimeError):
+        orc.sign_ns(h, eps=1e-7, tol=1e-7, order=3, screen=1e-9)
