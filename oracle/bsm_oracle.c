@@ -188,7 +188,7 @@ static void free_rows(rowbuf *rows, int32_t n)
 static double block_sq(const double *x, int64_t len)
 {
     double s = 0.0;
-    for (int64_t e = 0; e < len; ++e) s += x[e] * x[e];
+    for (int64_t t = 0; t < len; ++t) s += x[t] * x[t];
     return s;
 }
 

@@ -24,8 +24,8 @@ MUTANTS = [
      "orc_multiply_screened(-0.5, x, y, 1.25, x,"),
     ("ns_alpha", "orc_multiply_screened(-0.5, x, y,", "orc_multiply_screened(-0.45, x, y,"),
     ("screen_rule", "block_sq(bb, (int64_t)kk * n) < tau2)", "block_sq(bb, (int64_t)kk * n) < tau)"),
-    ("screen_norm", "for (int64_t e = 0; e < len; ++e) s += x[e] * x[e];",
-     "for (int64_t e = 0; e < len; ++e) s += fabs(x[e]);"),
+    ("screen_norm", "for (int64_t t = 0; t < len; ++t) s += x[t] * x[t];",
+     "for (int64_t t = 0; t < len; ++t) s += fabs(x[t]);"),
     ("o3_coefficient", "orc_shift_scale(y, 1.5, -10.0, &c)", "orc_shift_scale(y, 1.5, -9.0, &c)"),
     ("o3_scale", "orc_multiply(0.125, x, &w,", "orc_multiply(0.25, x, &w,"),
     ("o5_coefficient", "orc_add(35.0, &y2, -180.0, y, 378.0,", "orc_add(35.0, &y2, -180.0, y, 387.0,"),
