@@ -279,6 +279,9 @@ def main():
     ap.add_argument("--purify", choices=["sign", "tc2"], default="sign",
                     help="density matrix by the sign iteration (default) or by TC2 "
                          "purification at the occupied count")
+    ap.add_argument("--screen", type=float, default=0.0, metavar="TAU",
+                    help="leave out block products with ||A_ik|| ||B_kj|| < TAU in the "
+                         "Newton-Schulz multiplies (FP64, order 2)")
     ap.add_argument("--graph", type=int, choices=[0, 1], default=0,
                     help="1: replay captured hipGraphs once X's block pattern stops changing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -341,6 +344,7 @@ def main():
     opts.prec = {"fp64": bsm.FP64, "fp32": bsm.FP32, "bf16": bsm.SPLIT_BF16}[args.prec]
     opts.use_graph = args.graph
     opts.order = args.order
+    opts.eps_screen = args.screen
     stream = torch.cuda.current_stream()
 
     def step(keep=False):
@@ -397,14 +401,16 @@ def main():
     log(f"||P^2 - P||_F / n = {idem:.3e}")
 
     err64 = None
-    if args.prec != "fp64":
-        # error of the reduced-precision sign against the FP64 GPU path on the
-        # same input (untimed): ||X_p - X_64||_F / ||X_64||_F and trace(P)
+    if args.prec != "fp64" or args.screen > 0.0:
+        # error of the reduced-precision or screened sign against the plain
+        # FP64 GPU path on the same input (untimed): ||X_p - X_64||_F / ||X_64||_F
+        # and trace(P)
         xp, sp = xd, s0
         o64 = bsm.bsm_sign_opts_default()
         for f, _ in bsm.bsm_sign_opts._fields_:
             setattr(o64, f, getattr(opts, f))
         o64.prec = bsm.FP64
+        o64.eps_screen = 0.0
         st_64, x64, s64 = bsm.bsm_sign_iterate(dh.handle, 0.0, o64, stream=stream)
         d = bsm.bsm_add(1.0, xp, -1.0, x64, stream=stream)
         num = bsm.bsm_sqdist_identity(d, 0.0, stream=stream)
@@ -449,6 +455,7 @@ def main():
             "n": int(n), "eps_filter": args.eps, "kernel_table": args.table,
             "tol": args.tol, "seed": args.seed, "nnzb_H": h.nnzb,
             "graph_replay": bool(args.graph), "order": args.order,
+            "eps_screen": args.screen,
         },
         "time_to_sign_ms": ms_per_step,
         "iterations": int(s0.iterations),
@@ -459,13 +466,16 @@ def main():
         "n_occ": int(h.meta["n_occ"]),
         "tflop_per_step": flops / args.steps / 1e12,
         "products_per_step": int(sum(s.n_products for s, _ in all_stats) / args.steps),
+        "products_screened_per_step": int(sum(s.n_screened for s, _ in all_stats) / args.steps),
         "nnzb_X_final": int(s0.nnzb_final),
         "idempotency_P": idem,
         "graph_replays": int(s0.graph_replays),
         "graph_fallbacks": int(s0.graph_fallbacks),
         "roofline": {
             "bound": "mfma",
-            "kernel": ("k_smm_f64_quad<23,2,2,4,6,1>" if args.workload == "sign23" else "k_smm_f64_class")
+            "kernel": ("k_smm_f64_quad<23,2,2,4,5,1,true>" if args.screen > 0.0
+                       else "k_smm_f64_quad<23,2,2,4,6,1>" if args.workload == "sign23"
+                       else "k_smm_f64_class")
             if args.prec == "fp64" else "k_smm_lowp",
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,
@@ -473,7 +483,8 @@ def main():
             "frac": achieved / PEAK_FP64_TFLOPS,
             "traffic": measured_traffic("sign23")
             if (args.prec == "fp64" and args.workload == "sign23" and args.sites == 2048
-                and args.eps == 1e-6 and args.table == "exhaustive") else None,
+                and args.eps == 1e-6 and args.table == "exhaustive" and args.screen == 0.0)
+            else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, "
                             "profiles/k_smm_f64_quad_sign23.md)",
             "smm_ms_per_step": smm_ms / args.steps,

@@ -73,14 +73,15 @@ typedef struct {
 } bsm_info;
 
 typedef struct {
-    int64_t n_products;          /* block products A_ik*B_kj executed */
-    double flops;                /* sum over products of 2*m*n*k */
+    int64_t n_products;          /* block products A_ik*B_kj of the operands' patterns */
+    double flops;                /* sum over products done of 2*m*n*k (screened ones left out) */
     int64_t nnzb_unfiltered;     /* stored blocks of the product before the filter */
     int64_t nnzb;                /* stored blocks of C after the filter */
     double smm_ms;               /* device time of the block-product kernels (HIP events) */
     double total_ms;             /* device time of the whole multiply (HIP events) */
     int32_t smm_launches;        /* number of block-product kernel launches */
     int32_t pad_;
+    int64_t n_screened;          /* products left out by norm screening (of n_products) */
 } bsm_mult_stats;
 
 typedef struct {
@@ -95,6 +96,8 @@ typedef struct {
     double prec_switch_tol;  /* mixed precision: FP64 once r_k < this */
     int32_t order;           /* 2 (Newton-Schulz), 3, 5 or 7: see bsm_sign_iterate */
     int32_t pad_;
+    double eps_screen;       /* > 0: product-level norm screening threshold (see
+                                bsm_multiply_screened); order 2, FP64, no graph replay */
 } bsm_sign_opts;
 
 typedef struct {
@@ -115,6 +118,7 @@ typedef struct {
                                 the filter kept other blocks (or NaN/Inf appeared) */
     int32_t smm_launches;    /* block-product kernel launches of the counted multiplies */
     int32_t pad_;
+    int64_t n_screened;      /* products left out by norm screening */
 } bsm_sign_stats;
 
 /* Bisection record of bsm_mu_bisect. */
@@ -141,7 +145,8 @@ typedef struct bsm_tc2_stats {
     double device_ms;        /* device time of the whole call */
 } bsm_tc2_stats;
 
-/* Default options: eps 0, tol 1e-6, max_iter 100, FROB, FP64, no graph, order 2. */
+/* Default options: eps 0, tol 1e-6, max_iter 100, FROB, FP64, no graph, order 2,
+ * no screening. */
 void bsm_sign_opts_default(bsm_sign_opts *opts);
 
 /*
@@ -185,6 +190,22 @@ int bsm_export(bsm_matrix m, int64_t *row_ptr, int32_t *col_idx, double *values,
 int bsm_multiply(double alpha, bsm_matrix A, bsm_matrix B, double beta, bsm_matrix C,
                  double eps_filter, int32_t norm, int32_t prec,
                  bsm_mult_stats *stats, void *stream);
+
+/*
+ * bsm_multiply with product-level norm screening (the Sign-Method section's
+ * lever on the sparsity of the products): the term A_ik B_kj is left out of
+ * C_ij when ||A_ik||_F^2 ||B_kj||_F^2 < eps_screen^2 (squared block norms in
+ * FP64).  The stored pattern is that of the unscreened product (a block
+ * whose terms were all left out holds beta C_in, or zeros, before the
+ * filter); each C block's error is at most the sum of the left-out terms'
+ * norm products, below (left-out terms) * eps_screen.  eps_screen = 0 is
+ * bsm_multiply exactly.  FP64 only, uniform block sizes 5, 13, 23, 26 or 32
+ * (the group kernel); else BSM_EINVAL.  stats->n_screened counts the
+ * left-out products.
+ */
+int bsm_multiply_screened(double alpha, bsm_matrix A, bsm_matrix B, double beta, bsm_matrix C,
+                          double eps_filter, int32_t norm, double eps_screen,
+                          bsm_mult_stats *stats, void *stream);
 
 /* Apply the filter to a matrix in place (same rule as after a multiply). */
 int bsm_filter(bsm_matrix m, double eps_filter, int32_t norm, void *stream);

@@ -39,14 +39,15 @@ class bsm_mult_stats(C.Structure):
     _fields_ = [("n_products", C.c_int64), ("flops", C.c_double),
                 ("nnzb_unfiltered", C.c_int64), ("nnzb", C.c_int64),
                 ("smm_ms", C.c_double), ("total_ms", C.c_double),
-                ("smm_launches", C.c_int32), ("pad_", C.c_int32)]
+                ("smm_launches", C.c_int32), ("pad_", C.c_int32), ("n_screened", C.c_int64)]
 
 
 class bsm_sign_opts(C.Structure):
     _fields_ = [("eps_filter", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("fixed_iters", C.c_int32), ("norm", C.c_int32), ("prec", C.c_int32),
                 ("fp64_final_iters", C.c_int32), ("use_graph", C.c_int32),
-                ("prec_switch_tol", C.c_double), ("order", C.c_int32), ("pad_", C.c_int32)]
+                ("prec_switch_tol", C.c_double), ("order", C.c_int32), ("pad_", C.c_int32),
+                ("eps_screen", C.c_double)]
 
 
 class bsm_sign_stats(C.Structure):
@@ -56,7 +57,8 @@ class bsm_sign_stats(C.Structure):
                 ("flops", C.c_double), ("n_products", C.c_int64), ("smm_ms", C.c_double),
                 ("device_ms", C.c_double), ("nnzb_final", C.c_int64),
                 ("graph_replays", C.c_int32), ("graph_fallbacks", C.c_int32),
-                ("smm_launches", C.c_int32), ("pad_", C.c_int32)]
+                ("smm_launches", C.c_int32), ("pad_", C.c_int32),
+                ("n_screened", C.c_int64)]
 
 
 class bsm_mu_stats(C.Structure):
@@ -91,6 +93,9 @@ _SIGS = [
     ("bsm_multiply", C.c_int, [C.c_double, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                                C.c_double, C.c_int32, C.c_int32, C.POINTER(bsm_mult_stats),
                                C.c_void_p]),
+    ("bsm_multiply_screened", C.c_int, [C.c_double, C.c_void_p, C.c_void_p, C.c_double,
+                                        C.c_void_p, C.c_double, C.c_int32, C.c_double,
+                                        C.POINTER(bsm_mult_stats), C.c_void_p]),
     ("bsm_filter", C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
     ("bsm_block_norms", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("bsm_trace", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
@@ -206,6 +211,16 @@ def bsm_multiply(alpha, A, B, beta, Cm, eps_filter=0.0, norm=NORM_FROB, prec=FP6
     st = load().bsm_multiply(float(alpha), A, B, float(beta), Cm, float(eps_filter), int(norm),
                              int(prec), C.byref(stats), _stream(stream))
     _check(st, "bsm_multiply")
+    return stats
+
+
+def bsm_multiply_screened(alpha, A, B, beta, Cm, eps_filter=0.0, norm=NORM_FROB,
+                          eps_screen=0.0, stream=None) -> bsm_mult_stats:
+    stats = bsm_mult_stats()
+    st = load().bsm_multiply_screened(float(alpha), A, B, float(beta), Cm, float(eps_filter),
+                                      int(norm), float(eps_screen), C.byref(stats),
+                                      _stream(stream))
+    _check(st, "bsm_multiply_screened")
     return stats
 
 

@@ -178,6 +178,20 @@ int bsm_multiply(double alpha, bsm_matrix A, bsm_matrix B, double beta, bsm_matr
                          as_stream(stream));
 }
 
+int bsm_multiply_screened(double alpha, bsm_matrix A, bsm_matrix B, double beta, bsm_matrix C,
+                          double eps_filter, int32_t norm, double eps_screen,
+                          bsm_mult_stats *stats, void *stream) {
+    bsm::clear_error();
+    if (!A || !B || !C) { bsm::set_error("NULL handle"); return BSM_EINVAL; }
+    if (!(eps_screen >= 0.0) || !std::isfinite(eps_screen)) {
+        bsm::set_error("eps_screen must be finite and >= 0");
+        return BSM_EINVAL;
+    }
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    return bsm::multiply(alpha, A->m, B->m, beta, C->m, eps_filter, norm, BSM_FP64, stats,
+                         as_stream(stream), nullptr, eps_screen);
+}
+
 int bsm_filter(bsm_matrix h, double eps, int32_t norm, void *stream) {
     bsm::clear_error();
     if (!h) { bsm::set_error("NULL handle"); return BSM_EINVAL; }

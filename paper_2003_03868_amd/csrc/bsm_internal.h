@@ -90,9 +90,11 @@ struct MulPlan;
 void free_plan(MulPlan *p);
 
 // plan (may be NULL): on success receives the retained symbolic state.
+// tau > 0: product-level norm screening (terms with ||A_ik||^2 ||B_kj||^2 <
+// tau^2 left out; FP64 group kernel only).
 int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps,
              int norm, int prec, bsm_mult_stats *stats, hipStream_t s,
-             MulPlan **plan = nullptr);
+             MulPlan **plan = nullptr, double tau = 0.0);
 int filter_inplace(Mat &m, double eps, int norm, hipStream_t s);
 
 // Reductions (reduce.hip)

@@ -132,8 +132,13 @@ static int check_shapes(const Mat &A, const Mat &B, const Mat &C) {
 }
 
 int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int norm, int prec,
-             bsm_mult_stats *stats, hipStream_t s, MulPlan **plan) {
+             bsm_mult_stats *stats, hipStream_t s, MulPlan **plan, double tau) {
     BSM_TRY(check_shapes(A, B, C));
+    if (!(tau >= 0.0) || !std::isfinite(tau)) { set_error("eps_screen must be finite and >= 0"); return BSM_EINVAL; }
+    if (tau > 0.0 && (prec != BSM_FP64 || plan)) {
+        set_error("product screening needs FP64 products and no retained plan");
+        return BSM_EINVAL;
+    }
     if (!(eps >= 0.0) || !std::isfinite(eps)) { set_error("eps_filter must be finite and >= 0"); return BSM_EINVAL; }
     if (norm != BSM_NORM_FROB && norm != BSM_NORM_MAXABS) { set_error("unknown norm %d", norm); return BSM_EINVAL; }
     if (prec != BSM_FP64 && prec != BSM_FP32 && prec != BSM_SPLIT_BF16) { set_error("unknown precision %d", prec); return BSM_EINVAL; }
@@ -266,9 +271,30 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     if (prec != BSM_FP64 && variant == kSmmF64Quad && lowp_quad(prec) && A.uni_r && A.uni_c &&
         B.uni_c && smm_lowp_available(A.uni_r, B.uni_c, A.uni_c))
         use_quad = true;
-    // group shape: quads, or other shapes on request (FP64 only)
+    // group shape: quads, or other shapes on request (FP64 only); screening
+    // runs through the quads' product masks
     int GR = 2, GC = 2;
-    if (use_quad && prec == BSM_FP64) quad_shape(A.uni_r, &GR, &GC);
+    if (use_quad && prec == BSM_FP64 && tau == 0.0) quad_shape(A.uni_r, &GR, &GC);
+    if (st == BSM_OK && tau > 0.0 && !use_quad) {
+        set_error("product screening needs uniform block sizes 5, 13, 23, 26 or 32 and the "
+                  "default kernel variant");
+        st = BSM_EINVAL;
+    }
+    // squared block norms of the operands, and the count of kept products
+    double *a_sq = nullptr, *b_sq = nullptr;
+    unsigned long long *kept = nullptr;
+    if (st == BSM_OK && tau > 0.0) {
+        st = tmp.get(&a_sq, A.nnzb);
+        if (st == BSM_OK) st = block_sqnorms(A, a_sq, s);
+        if (st == BSM_OK && &A != &B) st = tmp.get(&b_sq, B.nnzb);
+        if (st == BSM_OK && &A != &B) st = block_sqnorms(B, b_sq, s);
+        if (&A == &B) b_sq = a_sq;
+        if (st == BSM_OK) st = tmp.get(&kept, 1);
+        if (st == BSM_OK) {
+            hipError_t e = hipMemsetAsync(kept, 0, sizeof(unsigned long long), s);
+            if (e != hipSuccess) { set_error("memset: %s", hipGetErrorString(e)); st = BSM_EDEVICE; }
+        }
+    }
     const int NE = (GR + GC + 3) / 4;                        // int4 per group entry
 
     // one set of stack buffers reused by every chunk; a plan keeps one per
@@ -344,6 +370,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             const int64_t npairs = (static_cast<int64_t>(r1 - r0) + GR - 1) / GR;
             int64_t *q_off = nullptr, *q_cblk = nullptr, *e_off = nullptr, *q_order = nullptr,
                     *e_seg = nullptr;
+            int32_t *pm = nullptr;
             int32_t *q_col = nullptr;
             int4 *ent = nullptr;
             int64_t nq = 0, ne = 0;
@@ -361,6 +388,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             qa.a_row_ptr = A.row_ptr; qa.a_col_idx = A.col_idx;
             qa.b_row_ptr = B.row_ptr; qa.b_col_idx = B.col_idx;
             qa.c_row_ptr = c_row_ptr; qa.c_col_idx = nc.col_idx;
+            qa.a_sq = a_sq; qa.b_sq = b_sq; qa.tau2 = tau * tau; qa.kept = kept;
             st = qbuf(&q_off, npairs + 1);
             if (st == BSM_OK) st = quad_pairs(qa, q_off, s);
             if (st == BSM_OK) st = scan_i64(q_off, q_off, npairs, s);
@@ -392,7 +420,9 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
                 st = BSM_EINVAL;
             }
             if (st == BSM_OK) st = qbuf(&ent, static_cast<size_t>(ne) * NE);
+            if (st == BSM_OK && tau > 0.0) st = qbuf(&pm, ne);
             qa.ent = ent;
+            qa.pm = pm;
             if (st == BSM_OK) st = quad_stack(qa, true, s);
             if (st != BSM_OK) break;
             MulOp op;
@@ -405,6 +435,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             op.a.q_order = q_order;
             op.a.q_gr = GR;
             op.a.q_gc = GC;
+            op.a.q_pm = pm;
             std::pair<hipEvent_t, hipEvent_t> pe{};
             if (ev.on) {
                 BSM_HIP(hipEventCreate(&pe.first));
@@ -549,6 +580,15 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         stats->nnzb_unfiltered = nnzb_c;
         stats->nnzb = nnzb_after;
         stats->smm_launches = n_launch;
+        if (tau > 0.0 && kept) {
+            unsigned long long h_kept = 0;
+            if (hipMemcpyAsync(&h_kept, kept, sizeof(h_kept), hipMemcpyDeviceToHost, s) == hipSuccess &&
+                hipStreamSynchronize(s) == hipSuccess)
+                stats->n_screened = nprod - static_cast<int64_t>(h_kept);
+            // uniform blocks: every product costs the same, so the flops
+            // actually done scale with the kept count
+            if (nprod > 0) stats->flops = flops * static_cast<double>(h_kept) / static_cast<double>(nprod);
+        }
         float ms = 0.f;
         double smm = 0.0;
         for (auto &p : ev.smm) {

@@ -117,6 +117,7 @@ k_quad_stack(QuadSymArgs q) {
     extern __shared__ uint32_t smem[];
     __shared__ int64_t scratch[kQuadThreads / kWave];
     __shared__ int64_t s_tb0, s_tb1;
+    __shared__ unsigned long long s_kept;      // fill pass with screening: kept products
     __shared__ int32_t s_k, s_a[GR], s_skip[GR];
     const int nwq = quad_words(q.nbcols, GC);  // words of the column-group bitmap
     uint32_t *bits = smem;
@@ -134,6 +135,7 @@ k_quad_stack(QuadSymArgs q) {
     quad_rank_map<GC>(q, i0, nr, nwq, bits, wpre, scratch);
 
     const int64_t qbase = q.q_off[R], nq = q.q_off[R + 1] - qbase;
+    if (threadIdx.x == 0) s_kept = 0;
     if (!FILL && sg == 0) {
         // C blocks of every group: (r, c) at GR GC group + GC r + c, -1 where absent
         for (int64_t t = threadIdx.x; t < GG * nq; t += kQuadThreads) q.q_cblk[GG * qbase + t] = -1;
@@ -221,8 +223,9 @@ k_quad_stack(QuadSymArgs q) {
                 if (tb > tb0 && q.b_col_idx[tb - 1] / GC == Q) continue;  // an earlier column emits
                 const int64_t r = bit_rank_q(bits, wpre, Q) - w0;
                 if (r < 0 || r >= wn) continue;
-                if (FILL) {
-                    int32_t e[4 * NE];
+                int32_t e[4 * NE];
+                unsigned mask = 0;
+                if (FILL || q.tau2 > 0.0) {
                     for (int z = 0; z < 4 * NE; ++z) e[z] = -1;
                     for (int r2 = 0; r2 < GR; ++r2) e[r2] = s_a[r2];
                     for (int64_t t = tb; t < tb1 && t < tb + GC; ++t) {
@@ -230,9 +233,32 @@ k_quad_stack(QuadSymArgs q) {
                         if (jj / GC != Q) break;
                         e[GR + jj % GC] = static_cast<int32_t>(t);
                     }
+                }
+                if (q.tau2 > 0.0) {
+                    // screening: keep product (r2, c) only if its norm product
+                    // reaches tau^2; operands no kept product uses are dropped
+                    for (int r2 = 0; r2 < GR; ++r2)
+                        for (int c = 0; c < GC; ++c)
+                            if (e[r2] >= 0 && e[GR + c] >= 0 &&
+                                q.a_sq[e[r2]] * q.b_sq[e[GR + c]] >= q.tau2)
+                                mask |= 1u << (GC * r2 + c);
+                    if (mask == 0) continue;
+                    for (int r2 = 0; r2 < GR; ++r2)
+                        if (((mask >> (GC * r2)) & ((1u << GC) - 1u)) == 0) e[r2] = -1;
+                    for (int c = 0; c < GC; ++c) {
+                        unsigned colbits = 0;
+                        for (int r2 = 0; r2 < GR; ++r2) colbits |= 1u << (GC * r2 + c);
+                        if ((mask & colbits) == 0) e[GR + c] = -1;
+                    }
+                }
+                if (FILL) {
                     const int64_t slot = s_ebase + eoff[r] + cnt[r];
                     for (int h = 0; h < NE; ++h)
                         q.ent[NE * slot + h] = make_int4(e[4 * h], e[4 * h + 1], e[4 * h + 2], e[4 * h + 3]);
+                    if (q.tau2 > 0.0) {
+                        q.pm[slot] = static_cast<int32_t>(mask);
+                        atomicAdd(&s_kept, static_cast<unsigned long long>(__popc(mask)));
+                    }
                 }
                 cnt[r] += 1;
             }
@@ -243,6 +269,7 @@ k_quad_stack(QuadSymArgs q) {
                 q.e_off[(qbase + w0 + t) * q.nseg + sg] = cnt[t];
         __syncthreads();
     }
+    if (FILL && q.tau2 > 0.0 && threadIdx.x == 0 && s_kept) atomicAdd(q.kept, s_kept);
 }
 
 #define BSM_QUAD_SHAPES(X) X(2, 2) X(4, 4) X(4, 2)

@@ -59,6 +59,14 @@ static int validate_opts(const Mat &H, const bsm_sign_opts &o) {
         set_error("sign: order must be 2, 3, 5 or 7");
         return BSM_EINVAL;
     }
+    if (!(o.eps_screen >= 0.0) || !std::isfinite(o.eps_screen)) {
+        set_error("sign: eps_screen must be finite and >= 0");
+        return BSM_EINVAL;
+    }
+    if (o.eps_screen > 0.0 && (o.order != 2 || o.prec != BSM_FP64)) {
+        set_error("sign: product screening needs order 2 and FP64 products");
+        return BSM_EINVAL;
+    }
     return BSM_OK;
 }
 
@@ -307,7 +315,8 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
     rc = alloc_like_sizes(*X, *X, &Y, s);
     if (rc != BSM_OK) { free_mat(X, s); return rc; }
 
-    const bool want_graph = o.use_graph != 0 && o.order == 2;
+    // graphs replay the symbolic results, which screening makes value-dependent
+    const bool want_graph = o.use_graph != 0 && o.order == 2 && o.eps_screen == 0.0;
     Replay R;
     R.s = s;
     if (want_graph) {
@@ -423,10 +432,11 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
         bsm_mult_stats ms{};
         if (!have_y) {
             rc = multiply(1.0, *X, *X, 0.0, *Y, o.eps_filter, o.norm, prec, &ms, s,
-                          want_graph ? &R.psq : nullptr);
+                          want_graph ? &R.psq : nullptr, o.eps_screen);
             st->n_multiplies++;
             st->flops += ms.flops;
             st->n_products += ms.n_products;
+            st->n_screened += ms.n_screened;
             st->smm_launches += ms.smm_launches;
             st->smm_ms += ms.smm_ms;
         }
@@ -456,10 +466,11 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
             if (rc != BSM_OK) break;
         }
         rc = multiply(-0.5, *X, *Y, 1.5, *X, o.eps_filter, o.norm, prec, &ms, s,
-                      (want_graph && R.psq) ? &R.pup : nullptr);
+                      (want_graph && R.psq) ? &R.pup : nullptr, o.eps_screen);
         st->n_multiplies++;
         st->flops += ms.flops;
         st->n_products += ms.n_products;
+        st->n_screened += ms.n_screened;
         st->smm_launches += ms.smm_launches;
         st->smm_ms += ms.smm_ms;
         if (rc != BSM_OK) break;

@@ -71,6 +71,7 @@ struct SmmArgs {
                                 // B(col 0..GC-1) block indices, -1 where absent
     const int64_t *q_order;     // group of work item i (NULL: identity)
     int32_t q_gr, q_gc;         // group shape
+    const int32_t *q_pm;        // product mask per entry (bit GC r + c), NULL: all products
 };
 
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s);

@@ -111,16 +111,20 @@ __device__ inline void quad_step(const double *sm, int R0, int C0, int ra0, int 
 
 // The wave's products of an entry with operand flags hm (bit z: operand z
 // present): dispatch on the wave's product mask to a compile-time variant.
-template <int S, int GR, int NR, int NC>
+template <int S, int GR, int GC, int NR, int NC>
 __device__ inline void quad_entry(const double *sm, int R0, int C0, int ra0, int rb0,
-                                  bool klast_ok, unsigned hm,
+                                  bool klast_ok, unsigned hm, unsigned gm,
                                   double (&acc)[NR * NC][QShape<S>::H][QShape<S>::H]) {
+    // gm: the entry's product mask over the group (bit GC r + c; all ones
+    // without screening)
     unsigned pm = 0;
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (((hm >> (R0 + r)) & 1u) && ((hm >> (GR + C0 + c)) & 1u)) pm |= 1u << (NC * r + c);
+            if (((hm >> (R0 + r)) & 1u) && ((hm >> (GR + C0 + c)) & 1u) &&
+                ((gm >> (GC * (R0 + r) + C0 + c)) & 1u))
+                pm |= 1u << (NC * r + c);
 #define BSM_QS(M) \
     case M: quad_step<S, GR, NR, NC, (M)>(sm, R0, C0, ra0, rb0, klast_ok, acc); break;
     if (NR * NC == 1) {
@@ -189,7 +193,8 @@ __device__ inline void quad_store(const SmmArgs &a, int64_t item, int R0, int C0
 // 4 x 2 groups: W = 8, wave w computes C block (w / 2, w % 2); waves 0..5
 // stage the four A and two B blocks.
 // WPE: the occupancy (waves per SIMD) the register allocation aims for.
-template <int S, int GR, int GC, int W, int WPE, int EPS>
+// MK: entries carry product masks (norm screening, a.q_pm).
+template <int S, int GR, int GC, int W, int WPE, int EPS, bool MK = false>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_smm_f64_quad(SmmArgs a) {
     using Q = QShape<S>;
@@ -259,6 +264,7 @@ k_smm_f64_quad(SmmArgs a) {
     constexpr int kEntryChunk = 64;
     static_assert(kEntryChunk % EPS == 0, "stages must not straddle index chunks");
     __shared__ int4 ebuf[2][kEntryChunk][NE];
+    __shared__ int32_t pbuf[2][MK ? kEntryChunk : 1];     // product masks of the chunk
     const int64_t e0 = a.q_seg[item], ne = a.q_seg[item + 1] - e0;
     double pv[EPS][NZ][NVP];
     auto load_blocks = [&](const int4 (&en)[NE], double (&p)[NZ][NVP]) {
@@ -287,13 +293,18 @@ k_smm_f64_quad(SmmArgs a) {
         // bit z: operand z present (A rows 0 .. GR-1, then B columns)
         return f;
     };
-    auto fetch = [&](int64_t t, int4 (&out)[NE]) {
+    auto fetch = [&](int64_t t, int4 (&out)[NE], unsigned &gm) {
 #pragma unroll
         for (int h = 0; h < NE; ++h)
             out[h] = (t < ne) ? uniform4(ebuf[(t / kEntryChunk) & 1][t % kEntryChunk][h])
                               : make_int4(-1, -1, -1, -1);
+        gm = ~0u;
+        if (MK && t < ne)
+            gm = static_cast<unsigned>(
+                __builtin_amdgcn_readfirstlane(pbuf[(t / kEntryChunk) & 1][t % kEntryChunk]));
     };
     int4 creg[NE];                             // wave 0: entry e0 + 64 c + lane of the next chunk
+    int32_t cpm = 0;                           // and its product mask
 #pragma unroll
     for (int h = 0; h < NE; ++h) creg[h] = make_int4(-1, -1, -1, -1);
     if (wv == 0) {
@@ -302,19 +313,25 @@ k_smm_f64_quad(SmmArgs a) {
             if (lane < ne) ebuf[0][lane][h] = a.q_ent[NE * (e0 + lane) + h];
             if (kEntryChunk + lane < ne) creg[h] = a.q_ent[NE * (e0 + kEntryChunk + lane) + h];
         }
+        if (MK) {
+            if (lane < ne) pbuf[0][lane] = a.q_pm[e0 + lane];
+            if (kEntryChunk + lane < ne) cpm = a.q_pm[e0 + kEntryChunk + lane];
+        }
     }
     __syncthreads();
     int4 nxt[EPS][NE];
+    unsigned ngm[EPS];
 #pragma unroll
     for (int q = 0; q < EPS; ++q) {
-        fetch(q, nxt[q]);
+        fetch(q, nxt[q], ngm[q]);
         load_blocks(nxt[q], pv[q]);
     }
     for (int64_t t = 0; t < ne; t += EPS) {
-        unsigned hm[EPS];
+        unsigned hm[EPS], gm[EPS];
 #pragma unroll
         for (int q = 0; q < EPS; ++q) {
             hm[q] = flags(nxt[q]);
+            gm[q] = ngm[q];
 #pragma unroll
             for (int zz = 0; zz < NZ; ++zz) {
                 const int z = zid(zz);
@@ -338,16 +355,21 @@ k_smm_f64_quad(SmmArgs a) {
                 ebuf[(t1 / kEntryChunk) & 1][lane][h] = creg[h];
                 if (t1 + kEntryChunk + lane < ne) creg[h] = a.q_ent[NE * (e0 + t1 + kEntryChunk + lane) + h];
             }
+            if (MK) {
+                pbuf[(t1 / kEntryChunk) & 1][lane] = cpm;
+                if (t1 + kEntryChunk + lane < ne) cpm = a.q_pm[e0 + t1 + kEntryChunk + lane];
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < EPS; ++q) {
-            fetch(t1 + q, nxt[q]);
+            fetch(t1 + q, nxt[q], ngm[q]);
             load_blocks(nxt[q], pv[q]);
         }
 #pragma unroll
         for (int q = 0; q < EPS; ++q)
-            quad_entry<S, GR, NR, NC>(sm + q * SLOT, R0, C0, ra0, rb0, klast_ok, hm[q], acc);
+            quad_entry<S, GR, GC, NR, NC>(sm + q * SLOT, R0, C0, ra0, rb0, klast_ok, hm[q], gm[q],
+                                          acc);
         __syncthreads();
     }
 
@@ -394,6 +416,20 @@ int launch_quad(const SmmArgs &a, hipStream_t s) {
     }
     const unsigned g = static_cast<unsigned>(grid);
     const int w = quad_waves(), eps = quad_stage();
+    if (a.q_pm) {
+        // product masks (norm screening): quads with four waves (size 5: one)
+        if (a.q_gr != 2 || a.q_gc != 2) { set_error("internal: masked groups are quads"); return BSM_EINVAL; }
+        switch (a.uni_m) {
+            case 5: k_smm_f64_quad<5, 2, 2, 1, 6, 1, true><<<g, 64, 0, s>>>(a); break;
+            case 13: k_smm_f64_quad<13, 2, 2, 4, 6, 1, true><<<g, 256, 0, s>>>(a); break;
+            case 23: k_smm_f64_quad<23, 2, 2, 4, 5, 1, true><<<g, 256, 0, s>>>(a); break;
+            case 26: k_smm_f64_quad<26, 2, 2, 4, 4, 1, true><<<g, 256, 0, s>>>(a); break;
+            case 32: k_smm_f64_quad<32, 2, 2, 4, 4, 1, true><<<g, 256, 0, s>>>(a); break;
+            default: set_error("no quad kernel for block size %d", a.uni_m); return BSM_EINVAL;
+        }
+        BSM_HIP(hipGetLastError());
+        return BSM_OK;
+    }
     if (a.q_gr == 4 && a.q_gc == 2 && a.uni_m == 23) {
         k_smm_f64_quad<23, 4, 2, 8, 6, 1><<<g, 512, 0, s>>>(a);
         BSM_HIP(hipGetLastError());

@@ -68,6 +68,14 @@ struct QuadSymArgs {
     int64_t *e_off;              // [n_groups nseg + 1]: count pass, entries per (group, segment);
                                  // fill pass, their scanned offsets (group-major)
     int4 *ent;                   // ceil((gr + gc) / 4) int4 per entry
+    // product-level norm screening (tau2 > 0): products with
+    // a_sq[A block] * b_sq[B block] < tau2 are left out of the entries; the
+    // fill pass writes each entry's product mask (bit GC r + c) to pm and
+    // adds the kept products to *kept
+    const double *a_sq, *b_sq;
+    double tau2;
+    int32_t *pm;
+    unsigned long long *kept;
 };
 int quad_pairs(const QuadSymArgs &q, int64_t *cnt, hipStream_t s);
 int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s);
