@@ -32,6 +32,12 @@ Parity status of each function (what pins it, see ``tests/test_oracle.py``):
 * ``tc2``           -- pinned: diagonal H by hand (the scalar maps and the
                        trace decisions); on dense cases the projector onto
                        the N lowest eigenvectors (LAPACK).
+* ``trs4``          -- pinned: on diagonal H one update maps every entry by
+                       one member of the fourth-order family with the trace
+                       reset to N (gamma recovered from one entry, checked on
+                       the rest), the branch rules by hand; on dense cases the
+                       projector onto the N lowest eigenvectors (LAPACK), and
+                       TC2's result.
 * ``mu_bisect``     -- pinned: diagonal H, whose count is the number of
                        diagonal entries below mu, so every midpoint follows
                        by hand; on dense cases the accepted mu lies in the
@@ -113,6 +119,8 @@ def _load():
             lib.orc_density_from_sign.argtypes = [P, P]
             lib.orc_tc2.argtypes = [P, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int32,
                                     P, C.POINTER(_Tc2Stats)]
+            lib.orc_trs4.argtypes = [P, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int32,
+                                     P, C.POINTER(_Tc2Stats)]
             lib.orc_sqrt_inv.argtypes = [P, C.c_double, C.c_int, C.c_double, C.c_int32, P, P,
                                          C.POINTER(_SignStats)]
             lib.orc_density_nonorth.argtypes = [P, P, C.c_double, C.c_double, C.c_int,
@@ -289,28 +297,42 @@ def mu_bisect(h: BSR, n_target: float, mu_lo: float, mu_hi: float, count_tol: fl
 class _Tc2Stats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("n_multiplies", C.c_int32),
                 ("e_hist", C.c_double * 128), ("branch", C.c_int32 * 128),
-                ("scale", C.c_double), ("trace_p", C.c_double), ("flops", C.c_double)]
+                ("scale", C.c_double), ("trace_p", C.c_double), ("flops", C.c_double),
+                ("gamma_hist", C.c_double * 128)]
 
 
-def tc2(h: BSR, n_occ: float, eps: float = 0.0, tol: float = 1e-10, max_iter: int = 100,
-        norm="frob"):
-    """Trace-correcting purification (orc_tc2); returns (P, stats, status)
-    with status OK, ENOCONV or ENONFINITE."""
+def _purify(fn, h: BSR, n_occ: float, eps: float, tol: float, max_iter: int, norm):
     lib = _load()
     oh, kh = _in(h)
     out = _OMat()
     st = _Tc2Stats()
-    status = lib.orc_tc2(C.byref(oh), float(n_occ), eps, _norm(norm), tol, max_iter,
-                         C.byref(out), C.byref(st))
+    status = getattr(lib, fn)(C.byref(oh), float(n_occ), eps, _norm(norm), tol, max_iter,
+                              C.byref(out), C.byref(st))
     if status not in (OK, ENOCONV, ENONFINITE):
         raise RuntimeError(f"oracle purification failed with status {status}")
     p = _out(out, h.row_blk_size, h.col_blk_size) if out.row_ptr else None
     k = int(st.iterations)
     stats = dict(iterations=k, n_multiplies=int(st.n_multiplies),
                  e_hist=[float(st.e_hist[i]) for i in range(k + 1)],
-                 branch=[int(st.branch[i]) for i in range(k)], scale=float(st.scale),
+                 branch=[int(st.branch[i]) for i in range(k)],
+                 gamma=[float(st.gamma_hist[i]) for i in range(k)], scale=float(st.scale),
                  trace_p=float(st.trace_p), flops=float(st.flops))
     return p, stats, int(status)
+
+
+def tc2(h: BSR, n_occ: float, eps: float = 0.0, tol: float = 1e-10, max_iter: int = 100,
+        norm="frob"):
+    """Trace-correcting purification (orc_tc2); returns (P, stats, status)
+    with status OK, ENOCONV or ENONFINITE."""
+    return _purify("orc_tc2", h, n_occ, eps, tol, max_iter, norm)
+
+
+def trs4(h: BSR, n_occ: float, eps: float = 0.0, tol: float = 1e-10, max_iter: int = 100,
+         norm="frob"):
+    """Trace-resetting fourth-order purification (orc_trs4); returns
+    (P, stats, status) as tc2, with stats["gamma"] the gamma of each update
+    and branch 2 for the fourth-order map."""
+    return _purify("orc_trs4", h, n_occ, eps, tol, max_iter, norm)
 
 
 def _stats(st) -> dict:

@@ -853,11 +853,37 @@ typedef struct {
     int32_t iterations;     /* updates performed */
     int32_t n_multiplies;
     double e_hist[128];     /* e_k = (trace X_k - trace X_k^2) / n */
-    int32_t branch[128];    /* update k: 0 = X^2, 1 = 2X - X^2 */
+    int32_t branch[128];    /* update k: 0 = X^2, 1 = 2X - X^2, 2 = F + gamma G (TRS4) */
     double scale;           /* s = ||H||_inf */
     double trace_p;         /* trace of the returned P */
     double flops;
+    double gamma_hist[128]; /* TRS4: gamma_k of update k (0 for TC2) */
 } orc_tc2_stats;
+
+/* Start shared by the purifications: checks, n, s = ||H||_inf and
+ * X_0 = (s I - H) / (2 s), whose spectrum lies in [0, 1] with the low
+ * energies near 1. */
+static int purify_start(const omat *h, double eps, int32_t max_iter, orc_tc2_stats *st,
+                        double *n_out, omat *x)
+{
+    if (h->nbrows != h->nbcols || eps < 0 || max_iter < 0 || max_iter > 120) return ORC_EINVAL;
+    for (int32_t i = 0; i < h->nbrows; ++i) if (h->rbs[i] != h->cbs[i]) return ORC_EINVAL;
+    memset(st, 0, sizeof(*st));
+    double n = 0.0;
+    for (int32_t i = 0; i < h->nbrows; ++i) n += h->rbs[i];
+    *n_out = n;
+    const double sc = orc_inf_norm_shifted(h, 0.0);
+    st->scale = sc;
+    if (!isfinite(sc)) return ORC_ENONFINITE;
+    if (sc == 0.0) return ORC_EINVAL;
+    return orc_shift_scale(h, sc, -0.5 / sc, x);
+}
+
+/* The TC2 map that raises the trace: filter(2 X - Y) with Y = X^2. */
+static int tc2_raise(const omat *x, const omat *y, double eps, int norm_kind, omat *out)
+{
+    return orc_add(2.0, x, -1.0, y, 0.0, eps, norm_kind, out);
+}
 
 /*
  * Density matrix for a fixed occupation N by second-order trace-correcting
@@ -878,17 +904,9 @@ typedef struct {
 int orc_tc2(const omat *h, double n_occ, double eps, int norm_kind, double tol, int32_t max_iter,
             omat *p_out, orc_tc2_stats *st)
 {
-    if (h->nbrows != h->nbcols || eps < 0 || max_iter < 0 || max_iter > 120) return ORC_EINVAL;
-    for (int32_t i = 0; i < h->nbrows; ++i) if (h->rbs[i] != h->cbs[i]) return ORC_EINVAL;
-    memset(st, 0, sizeof(*st));
     double n = 0.0;
-    for (int32_t i = 0; i < h->nbrows; ++i) n += h->rbs[i];
-    const double sc = orc_inf_norm_shifted(h, 0.0);
-    st->scale = sc;
-    if (!isfinite(sc)) return ORC_ENONFINITE;
-    if (sc == 0.0) return ORC_EINVAL;
     omat x = {0}, y = {0}, xn = {0};
-    int status = orc_shift_scale(h, sc, -0.5 / sc, &x);       /* (s I - H) / (2 s) */
+    int status = purify_start(h, eps, max_iter, st, &n, &x);
     for (int32_t k = 0; status == ORC_OK; ++k) {
         st->flops += product_flops(&x, &x);
         st->n_multiplies++;
@@ -908,7 +926,7 @@ int orc_tc2(const omat *h, double n_occ, double eps, int norm_kind, double tol, 
             memset(&y, 0, sizeof(y));
         } else {
             st->branch[k] = 1;
-            status = orc_add(2.0, &x, -1.0, &y, 0.0, eps, norm_kind, &xn);
+            status = tc2_raise(&x, &y, eps, norm_kind, &xn);
             orc_free(&y);
             if (status != ORC_OK) break;
             orc_free(&x);
@@ -917,6 +935,93 @@ int orc_tc2(const omat *h, double n_occ, double eps, int norm_kind, double tol, 
         }
     }
     orc_free(&y);
+    if (status == ORC_OK || status == ORC_ENOCONV) st->trace_p = orc_trace(&x);
+    *p_out = x;
+    return status;
+}
+
+/*
+ * Density matrix for a fixed occupation N by fourth-order trace-resetting
+ * purification (TRS4, the other purification the density-matrix paragraph
+ * names besides TC2 and the sign function).  Same start and stopping rule
+ * as TC2; each update is the fourth-order map
+ *
+ *   F = X^2 (4X - 3X^2),  G = X^2 (I - X)^2,  X <- F + gamma G,
+ *   gamma = (N - trace F) / trace G,
+ *
+ * which fixes 0 and 1 with zero slope for every gamma and, by the choice
+ * of gamma, resets the trace to N.  It keeps [0, 1] only for gamma in
+ * [0, 6]; outside, the TC2 maps move the trace instead:
+ *
+ *   for k = 0, 1, ...:
+ *       Y = filter(X_k X_k);  e_k = (trace X_k - trace Y) / n;  stop if e_k < tol
+ *       F = filter(Y filter(4 X_k - 3 Y))
+ *       G = filter(D D) with D = filter(X_k - Y)       ((X - X^2)^2 = X^2 (I - X)^2)
+ *       gamma = (N - trace F) / trace G, or 0 when the filter has removed all of G
+ *       X_{k+1} = filter(2 X_k - Y) if gamma > 6;  Y if gamma < 0;  filter(F + gamma G) otherwise
+ *
+ * G vanishes only when X is idempotent to the filter's resolution; the
+ * trace correction is then below that resolution too, and the update is F.
+ * Three multiplies per update.  Status as orc_tc2.
+ */
+int orc_trs4(const omat *h, double n_occ, double eps, int norm_kind, double tol, int32_t max_iter,
+             omat *p_out, orc_tc2_stats *st)
+{
+    double n = 0.0;
+    omat x = {0}, y = {0}, w = {0}, f = {0}, d = {0}, g = {0}, xn = {0};
+    int status = purify_start(h, eps, max_iter, st, &n, &x);
+    for (int32_t k = 0; status == ORC_OK; ++k) {
+        st->flops += product_flops(&x, &x);
+        st->n_multiplies++;
+        status = orc_multiply(1.0, &x, &x, 0.0, NULL, eps, norm_kind, &y);
+        if (status != ORC_OK) break;
+        const double tx = orc_trace(&x), ty = orc_trace(&y);
+        const double e = (tx - ty) / n;
+        st->e_hist[k] = e;
+        st->iterations = k;
+        if (!isfinite(e)) { status = ORC_ENONFINITE; break; }
+        if (e < tol) break;
+        if (k >= max_iter) { status = ORC_ENOCONV; break; }
+        status = orc_add(4.0, &x, -3.0, &y, 0.0, eps, norm_kind, &w);
+        if (status == ORC_OK) {
+            st->flops += product_flops(&y, &w);
+            st->n_multiplies++;
+            status = orc_multiply(1.0, &y, &w, 0.0, NULL, eps, norm_kind, &f);
+        }
+        if (status == ORC_OK) status = orc_add(1.0, &x, -1.0, &y, 0.0, eps, norm_kind, &d);
+        if (status == ORC_OK) {
+            st->flops += product_flops(&d, &d);
+            st->n_multiplies++;
+            status = orc_multiply(1.0, &d, &d, 0.0, NULL, eps, norm_kind, &g);
+        }
+        orc_free(&w);
+        orc_free(&d);
+        if (status != ORC_OK) break;
+        const double tf = orc_trace(&f), tg = orc_trace(&g);
+        const double gamma = tg > 0.0 ? (n_occ - tf) / tg : 0.0;
+        st->gamma_hist[k] = gamma;
+        if (gamma > 6.0) {
+            st->branch[k] = 1;
+            status = tc2_raise(&x, &y, eps, norm_kind, &xn);
+        } else if (gamma < 0.0) {
+            st->branch[k] = 0;
+            xn = y;
+            memset(&y, 0, sizeof(y));
+        } else {
+            st->branch[k] = 2;
+            status = orc_add(1.0, &f, gamma, &g, 0.0, eps, norm_kind, &xn);
+        }
+        orc_free(&y);
+        orc_free(&f);
+        orc_free(&g);
+        if (status != ORC_OK) break;
+        orc_free(&x);
+        x = xn;
+        memset(&xn, 0, sizeof(xn));
+    }
+    orc_free(&y);
+    orc_free(&f);
+    orc_free(&g);
     if (status == ORC_OK || status == ORC_ENOCONV) st->trace_p = orc_trace(&x);
     *p_out = x;
     return status;

@@ -732,6 +732,98 @@ def test_tc2_matches_sign_density_on_neighbour_hamiltonian(orc):
     assert st["trace_p"] == pytest.approx(h.meta["n_occ"], abs=1e-5)
 
 
+# ------------------------------------ trace-resetting purification (TRS4)
+
+def _trs4_diag_case(seed, nocc_frac):
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(1, 6, 12)
+    h = rng.uniform(-3.0, 3.0, int(sizes.sum()))
+    h[0], h[1] = 3.5, -3.5                     # entries that start at exactly 0 and 1
+    return h, sizes, int(round(nocc_frac * h.size))
+
+
+@pytest.mark.parametrize("frac", [0.45, 0.6])
+def test_trs4_one_update_is_a_fourth_order_map_with_the_trace_reset(orc, frac):
+    """Diagonal H, one update: every entry moves by the same quartic p with
+    p(0) = 0, p'(0) = 0, p(1) = 1, p'(1) = 0 (the conditions that make the
+    purification fourth-order at both fixed points), and the trace lands on
+    N.  p is fitted here from the data, not taken from the oracle's formula:
+    x1 / x0^2 = a + b x0 + c x0^2 must hold for every entry, with
+    a + b + c = 1 (p(1) = 1) and b + 2c = -2 (p'(1) = 0)."""
+    h, sizes, nocc = _trs4_diag_case(43, frac)
+    p, st, status = orc.trs4(_diag_matrix(h, sizes), nocc, eps=0.0, tol=1e-15, max_iter=1)
+    assert status == orc.ENOCONV and st["branch"] == [2]
+    s = np.abs(h).max()
+    x0 = -(0.5 / s) * (h - s)
+    x1 = np.diag(p.to_dense())
+    assert x0[0] == 0.0 and x0[1] == 1.0 and x1[0] == 0.0 and x1[1] == pytest.approx(1.0, abs=1e-15)
+    sel = x0 > 0.05
+    a, b, c = np.linalg.lstsq(np.stack([np.ones(sel.sum()), x0[sel], x0[sel] ** 2], 1),
+                              x1[sel] / x0[sel] ** 2, rcond=None)[0]
+    assert np.allclose(x1, x0 ** 2 * (a + b * x0 + c * x0 ** 2), rtol=0, atol=1e-13)
+    assert a + b + c == pytest.approx(1.0, abs=1e-11)
+    assert b + 2 * c == pytest.approx(-2.0, abs=1e-11)
+    assert x1.sum() == pytest.approx(nocc, abs=1e-11)
+    # the family's free coefficient is gamma - 3 in the x^4 term
+    assert st["gamma"][0] == pytest.approx(c + 3.0, abs=1e-10) and 0.0 <= st["gamma"][0] <= 6.0
+
+
+@pytest.mark.parametrize("seed,frac,branch", [(44, 0.98, 1), (44, 0.02, 0), (43, 0.65, 1),
+                                               (43, 0.4, 0)])
+def test_trs4_out_of_range_updates_by_hand(orc, seed, frac, branch):
+    """An occupation no member of the family can reach (gamma outside
+    [0, 6]) takes the TC2 map that moves the trace the right way:
+    2x - x^2 to raise it, x^2 to lower it (the last two cases lie just
+    outside the range: gamma 6.4 and -0.6)."""
+    h, sizes, nocc = _trs4_diag_case(seed, frac)
+    p, st, status = orc.trs4(_diag_matrix(h, sizes), nocc, eps=0.0, tol=1e-15, max_iter=1)
+    assert status == orc.ENOCONV and st["branch"] == [branch]
+    assert (st["gamma"][0] > 6.0) if branch == 1 else (st["gamma"][0] < 0.0)
+    s = np.abs(h).max()
+    x0 = -(0.5 / s) * (h - s)
+    want = 2.0 * x0 + (-1.0) * (x0 * x0) if branch == 1 else x0 * x0
+    assert np.array_equal(np.diag(p.to_dense()), want)
+
+
+def test_trs4_diagonal_converges_to_the_occupied_set(orc):
+    h, sizes, nocc = _trs4_diag_case(45, 0.4)
+    p, st, status = orc.trs4(_diag_matrix(h, sizes), nocc, eps=0.0, tol=1e-13)
+    assert status == orc.OK
+    x = np.diag(p.to_dense())
+    assert np.allclose(x, (h <= np.sort(h)[nocc - 1]).astype(float), atol=1e-6)
+    assert st["n_multiplies"] == 3 * st["iterations"] + 1
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_trs4_dense_is_the_occupied_projector(orc, seed):
+    rng = np.random.default_rng(90 + seed)
+    sizes = rng.integers(1, 9, 8)
+    n = int(sizes.sum())
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.sort(rng.uniform(-2.0, 2.0, n))
+    nocc = n // 3 + seed
+    lam[nocc:] += 0.5
+    d = (q * lam) @ q.T
+    d = 0.5 * (d + d.T)
+    p, st, status = orc.trs4(_dense_to_bsr(d, sizes), nocc, eps=0.0, tol=1e-14)
+    assert status == orc.OK
+    w, v = np.linalg.eigh(d)
+    ref = v[:, :nocc] @ v[:, :nocc].T
+    assert _rel(p.to_dense(), ref) <= 1e-10
+    assert st["trace_p"] == pytest.approx(nocc, abs=1e-9)
+    assert 2 in st["branch"]
+
+
+def test_trs4_matches_tc2_on_neighbour_hamiltonian(orc):
+    h = synth.neighbour_hamiltonian(100, 5, cutoff=4.5, seed=3)
+    p, st, status = orc.trs4(h, h.meta["n_occ"], eps=1e-9, tol=1e-9)
+    assert status == orc.OK
+    p2, st2, s2 = orc.tc2(h, h.meta["n_occ"], eps=1e-9, tol=1e-9)
+    assert _rel(p.to_dense(), p2.to_dense()) <= 1e-6
+    assert st["trace_p"] == pytest.approx(h.meta["n_occ"], abs=1e-5)
+    assert st["iterations"] < st2["iterations"]
+
+
 # ------------------------------------------------ product-level norm screening
 
 def _scale_blocks(m: BSR, rng, lo=-4.0):

@@ -47,8 +47,8 @@ MUTANTS = [
     ("nonorth_back", "s2 = orc_multiply(1.0, &p1, &z, 0.0, NULL, eps, norm_kind, p_out);",
      "s2 = orc_shift_scale(&p1, 0.0, 1.0, p_out);"),
     ("tc2_branch", "if (tx > n_occ) {", "if (tx < n_occ) {"),
-    ("tc2_scale", "orc_shift_scale(h, sc, -0.5 / sc, &x)", "orc_shift_scale(h, sc, -1.0 / sc, &x)"),
-    ("tc2_update", "orc_add(2.0, &x, -1.0, &y, 0.0,", "orc_add(2.0, &x, -0.5, &y, 0.0,"),
+    ("tc2_scale", "return orc_shift_scale(h, sc, -0.5 / sc, x);", "return orc_shift_scale(h, sc, -1.0 / sc, x);"),
+    ("tc2_update", "return orc_add(2.0, x, -1.0, y, 0.0,", "return orc_add(2.0, x, -0.5, y, 0.0,"),
     ("add_gamma", "tmp[r * m + r] = tmp[r * m + r] + gamma;", "tmp[r * m + r] = tmp[r * m + r] - gamma;"),
     ("add_b_index", "tmp[e] = tmp[e] + beta * b->values[offb[tb] + e];",
      "tmp[e] = tmp[e] + beta * b->values[offb[tb]];"),
@@ -58,6 +58,11 @@ MUTANTS = [
      "tmp[r * m + r] = scale * (a->values[off[t] + (int64_t)r * m + r] + mu);"),
     ("inf_norm_abs", "s += fabs(x[c] - ((j == i && c == r) ? mu : 0.0));",
      "s += (x[c] - ((j == i && c == r) ? mu : 0.0));"),
+    ("trs4_f_coefficient", "orc_add(4.0, &x, -3.0, &y, 0.0,", "orc_add(4.0, &x, -2.0, &y, 0.0,"),
+    ("trs4_g_operand", "orc_multiply(1.0, &d, &d, 0.0,", "orc_multiply(1.0, &d, &x, 0.0,"),
+    ("trs4_gamma_sign", "(n_occ - tf) / tg", "(tf - n_occ) / tg"),
+    ("trs4_upper_branch", "if (gamma > 6.0) {", "if (gamma > 2.0) {"),
+    ("trs4_no_g", "tg > 0.0 ? (n_occ - tf) / tg : 0.0", "tg > 0.0 ? (n_occ - tf) / tg : 7.0"),
     ("trace_p", "st->trace_p = 0.5 * (n - st->trace_x);", "st->trace_p = 0.5 * (n + st->trace_x);"),
     ("skip_last_k", "for (int64_t ta = a->row_ptr[i]; ta < a->row_ptr[i + 1]; ++ta) {\n                    int32_t k",
      "for (int64_t ta = a->row_ptr[i]; ta + 1 < a->row_ptr[i + 1]; ++ta) {\n                    int32_t k"),
