@@ -199,17 +199,19 @@ def bench_mult832(args, bsm, synth, torch):
 
 
 def bench_tc2(args, h, dh, bsm, torch):
-    """Timed steps of TC2 purification at the occupied count of the
+    """Timed steps of TC2 or TRS4 purification at the occupied count of the
     workload; one JSON line."""
+    name = args.purify.upper()
+    fn = bsm.bsm_trs4 if args.purify == "trs4" else bsm.bsm_tc2
     o = bsm.bsm_sign_opts_default()
     o.eps_filter, o.tol = args.eps, args.tol
     stream = torch.cuda.current_stream()
     nocc = h.meta["n_occ"]
 
     def step():
-        st, ph, stats = bsm.bsm_tc2(dh.handle, nocc, o, stream=stream)
+        st, ph, stats = fn(dh.handle, nocc, o, stream=stream)
         if st != bsm.OK:
-            raise RuntimeError(f"TC2 failed: {bsm.STATUS_NAMES[st]} {bsm.bsm_last_error()}")
+            raise RuntimeError(f"{name} failed: {bsm.STATUS_NAMES[st]} {bsm.bsm_last_error()}")
         bsm.bsm_destroy(ph)
         return stats
 
@@ -237,12 +239,13 @@ def bench_tc2(args, h, dh, bsm, torch):
         "warmup": args.warmup, "ms_per_step": total / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"FP64 TC2 purification to N = {nocc}, {h.nbrows}-site "
+        "config": {"workload": f"FP64 {name} purification to N = {nocc}, {h.nbrows}-site "
                                f"neighbour-list Hamiltonian, eps_filter {args.eps:g}, "
                                f"tol {args.tol:g}",
                    "n_sites": h.nbrows, "seed": args.seed},
         "iterations": int(s.iterations), "multiplies": int(s.n_multiplies),
         "branches": list(s.branch[:s.iterations]), "trace_p": float(s.trace_p), "n_occ": nocc,
+        "gammas": list(s.gamma_hist[:s.iterations]) if args.purify == "trs4" else None,
         "tflop_per_step": flops / args.steps / 1e12,
         "roofline": {"bound": "mfma", "kernel": "k_smm_f64_quad", "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
@@ -276,8 +279,8 @@ def main():
     ap.add_argument("--overlap", type=float, default=0.0, metavar="TAU",
                     help="time the non-orthogonal density matrix with a synthetic overlap "
                          "S = I + TAU N/M (0: the orthogonal sign iteration)")
-    ap.add_argument("--purify", choices=["sign", "tc2"], default="sign",
-                    help="density matrix by the sign iteration (default) or by TC2 "
+    ap.add_argument("--purify", choices=["sign", "tc2", "trs4"], default="sign",
+                    help="density matrix by the sign iteration (default) or by TC2 or TRS4 "
                          "purification at the occupied count")
     ap.add_argument("--screen", type=float, default=0.0, metavar="TAU",
                     help="leave out block products with ||A_ik|| ||B_kj|| < TAU in the "
@@ -334,7 +337,7 @@ def main():
     if args.overlap > 0.0:
         bench_nonorth(args, h, dh, bsm, synth, torch)
         return
-    if args.purify == "tc2":
+    if args.purify in ("tc2", "trs4"):
         bench_tc2(args, h, dh, bsm, torch)
         return
 

@@ -131,18 +131,19 @@ typedef struct bsm_mu_stats {
     double device_ms;        /* summed device time of the sign iterations */
 } bsm_mu_stats;
 
-/* Record of bsm_tc2. */
+/* Record of bsm_tc2 and bsm_trs4. */
 typedef struct bsm_tc2_stats {
     int32_t iterations;      /* updates performed */
     int32_t n_multiplies;
     double e_hist[128];      /* e_k = (trace X_k - trace X_k^2) / n, k = 0..iterations */
-    int32_t branch[128];     /* update k: 0 = X^2, 1 = 2X - X^2 */
+    int32_t branch[128];     /* update k: 0 = X^2, 1 = 2X - X^2, 2 = F + gamma G (TRS4) */
     double scale;            /* s = ||H||_inf */
     double trace_p;          /* trace of the returned P */
     double flops;            /* algorithmic flops of the block products */
     int64_t n_products;
     double smm_ms;           /* block-product kernel time (HIP events) */
     double device_ms;        /* device time of the whole call */
+    double gamma_hist[128];  /* TRS4: gamma of update k (0 for TC2) */
 } bsm_tc2_stats;
 
 /* Default options: eps 0, tol 1e-6, max_iter 100, FROB, FP64, no graph, order 2,
@@ -350,6 +351,21 @@ int bsm_density_nonorth(bsm_matrix K, bsm_matrix S, double mu, const bsm_sign_op
  */
 int bsm_tc2(bsm_matrix H, double n_occ, const bsm_sign_opts *opts, bsm_matrix *p_out,
             bsm_tc2_stats *stats, void *stream);
+
+/*
+ * Density matrix for a fixed occupation n_occ by fourth-order
+ * trace-resetting purification (TRS4, named with TC2 and the sign function
+ * in the density-matrix-based-methods paragraph).  Same start and stopping
+ * rule as bsm_tc2; each update
+ *   F = filter(Y filter(4 X_k - 3 Y)), G = filter(D D), D = filter(X_k - Y),
+ *   gamma = (N - trace F) / trace G   (0 when the filter has removed all of G),
+ *   X_{k+1} = filter(2 X_k - Y) if gamma > 6; Y if gamma < 0;
+ *             filter(F + gamma G) otherwise,
+ * with Y = filter(X_k X_k): three multiplies per update.  Arguments, status
+ * and ownership as bsm_tc2; stats->gamma_hist records gamma per update.
+ */
+int bsm_trs4(bsm_matrix H, double n_occ, const bsm_sign_opts *opts, bsm_matrix *p_out,
+             bsm_tc2_stats *stats, void *stream);
 
 /* P = (I - X)/2 from a sign matrix X, as a new handle; trace_p (may be NULL) gets trace(P). */
 int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void *stream);

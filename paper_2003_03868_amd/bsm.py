@@ -71,7 +71,8 @@ class bsm_tc2_stats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("n_multiplies", C.c_int32),
                 ("e_hist", C.c_double * 128), ("branch", C.c_int32 * 128),
                 ("scale", C.c_double), ("trace_p", C.c_double), ("flops", C.c_double),
-                ("n_products", C.c_int64), ("smm_ms", C.c_double), ("device_ms", C.c_double)]
+                ("n_products", C.c_int64), ("smm_ms", C.c_double), ("device_ms", C.c_double),
+                ("gamma_hist", C.c_double * 128)]
 
 
 class bsm_smm_params(C.Structure):
@@ -118,6 +119,8 @@ _SIGS = [
                                       C.POINTER(bsm_sign_stats), C.c_void_p]),
     ("bsm_tc2", C.c_int, [C.c_void_p, C.c_double, C.POINTER(bsm_sign_opts),
                           C.POINTER(C.c_void_p), C.POINTER(bsm_tc2_stats), C.c_void_p]),
+    ("bsm_trs4", C.c_int, [C.c_void_p, C.c_double, C.POINTER(bsm_sign_opts),
+                           C.POINTER(C.c_void_p), C.POINTER(bsm_tc2_stats), C.c_void_p]),
     ("bsm_density_from_sign", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p),
                                         C.POINTER(C.c_double), C.c_void_p]),
     ("bsm_smm_bench", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
@@ -314,17 +317,26 @@ def bsm_density_nonorth(k, s, mu=0.0, opts: bsm_sign_opts | None = None, stream=
     return st, p.value, tps.value, s1, s2
 
 
-def bsm_tc2(h, n_occ, opts: bsm_sign_opts | None = None, stream=None):
-    """Returns (status, P handle or None, stats); ENOCONV/ENONFINITE are
-    returned, not raised."""
+def _purify(name, h, n_occ, opts, stream):
     out = C.c_void_p()
     stats = bsm_tc2_stats()
     o = opts if opts is not None else bsm_sign_opts_default()
-    st = load().bsm_tc2(h, float(n_occ), C.byref(o), C.byref(out), C.byref(stats),
-                        _stream(stream))
+    st = getattr(load(), name)(h, float(n_occ), C.byref(o), C.byref(out), C.byref(stats),
+                               _stream(stream))
     if st not in (OK, ENOCONV, ENONFINITE):
-        _check(st, "bsm_tc2")
+        _check(st, name)
     return st, out.value, stats
+
+
+def bsm_tc2(h, n_occ, opts: bsm_sign_opts | None = None, stream=None):
+    """Returns (status, P handle or None, stats); ENOCONV/ENONFINITE are
+    returned, not raised."""
+    return _purify("bsm_tc2", h, n_occ, opts, stream)
+
+
+def bsm_trs4(h, n_occ, opts: bsm_sign_opts | None = None, stream=None):
+    """TRS4 purification; returns (status, P handle or None, stats) as bsm_tc2."""
+    return _purify("bsm_trs4", h, n_occ, opts, stream)
 
 
 def bsm_add(alpha, a, beta=0.0, b=None, gamma=0.0, eps_filter=0.0, norm=0, stream=None) -> int:

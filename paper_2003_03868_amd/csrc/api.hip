@@ -14,6 +14,8 @@ int sqrt_inv_iterate(Mat &S, const bsm_sign_opts &o, Mat **sqrt_out, Mat **isqrt
 int density_nonorth(Mat &K, Mat &S, double mu, const bsm_sign_opts &o, Mat **p_out,
                     double *trace_ps, bsm_sign_stats *st_sqrt, bsm_sign_stats *st_sign,
                     hipStream_t s);
+int trs4_purify(Mat &H, double n_occ, const bsm_sign_opts &o, Mat **p_out, bsm_tc2_stats *st,
+                hipStream_t s);
 int tc2_purify(Mat &H, double n_occ, const bsm_sign_opts &o, Mat **p_out, bsm_tc2_stats *st,
                hipStream_t s);
 }  // namespace bsm
@@ -386,6 +388,22 @@ int bsm_tc2(bsm_matrix H, double n_occ, const bsm_sign_opts *opts, bsm_matrix *p
     std::memset(st, 0, sizeof(*st));
     Mat *p = nullptr;
     const int rc = bsm::tc2_purify(H->m, n_occ, o, &p, st, as_stream(stream));
+    if (p) *p_out = wrap(p);
+    return rc;
+}
+
+int bsm_trs4(bsm_matrix H, double n_occ, const bsm_sign_opts *opts, bsm_matrix *p_out,
+             bsm_tc2_stats *stats, void *stream) {
+    bsm::clear_error();
+    if (!H || !p_out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    *p_out = nullptr;
+    bsm_sign_opts o;
+    if (opts) o = *opts; else bsm_sign_opts_default(&o);
+    bsm_tc2_stats local;
+    bsm_tc2_stats *st = stats ? stats : &local;
+    std::memset(st, 0, sizeof(*st));
+    Mat *p = nullptr;
+    const int rc = bsm::trs4_purify(H->m, n_occ, o, &p, st, as_stream(stream));
     if (p) *p_out = wrap(p);
     return rc;
 }

@@ -219,3 +219,50 @@ def test_tc2_vs_oracle(orc, c):
     assert stats.trace_p == pytest.approx(h.meta["n_occ"], abs=1e-5)
     print(f"tc2 {c}: {k} iterations, branches {list(stats.branch[:k])}, "
           f"trace(P) {stats.trace_p:.8f}")
+
+
+@pytest.mark.parametrize("c", [dict(n=100, b=5, rc=4.5, eps=0.0, seed=3),
+                               dict(n=100, b=5, rc=4.5, eps=1e-8, seed=4),
+                               dict(n=64, b=13, rc=4.0, eps=1e-7, seed=5),
+                               dict(n=64, b=23, rc=4.0, eps=1e-9, seed=6)],
+                         ids=lambda c: f"n{c['n']}b{c['b']}e{c['eps']:g}")
+def test_trs4_vs_oracle(orc, c):
+    """Trace-resetting purification: the same updates (branch and gamma) as
+    the oracle, P within the FP64 tolerance, trace(P) the occupied count."""
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(c["n"], c["b"], cutoff=c["rc"], seed=c["seed"])
+    p_ref, st_ref, s_ref = orc.trs4(h, h.meta["n_occ"], eps=c["eps"], tol=1e-9)
+    d = to_dev(h)
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol = c["eps"], 1e-9
+    st, ph, stats = bsm.bsm_trs4(d.handle, h.meta["n_occ"], o)
+    assert st == s_ref == bsm.OK, bsm.bsm_last_error()
+    k = stats.iterations
+    assert k == st_ref["iterations"] and list(stats.branch[:k]) == st_ref["branch"]
+    assert np.allclose(list(stats.gamma_hist[:k]), st_ref["gamma"], rtol=1e-8, atol=1e-10)
+    assert np.allclose(list(stats.e_hist[:k + 1]), st_ref["e_hist"], rtol=1e-6, atol=1e-14)
+    assert stats.n_multiplies == st_ref["n_multiplies"] == 3 * k + 1
+    p = bsm.Matrix(ph, h.row_blk_size, h.col_blk_size)
+    assert_same_matrix(from_dev(p), p_ref, TOL_FP64, "TRS4 P")
+    assert stats.trace_p == pytest.approx(h.meta["n_occ"], abs=1e-5)
+    print(f"trs4 {c}: {k} iterations, branches {list(stats.branch[:k])}, "
+          f"gamma {[round(g, 3) for g in stats.gamma_hist[:k]]}, trace(P) {stats.trace_p:.8f}")
+
+
+@pytest.mark.parametrize("frac", [0.9, 0.1])
+def test_trs4_out_of_range_updates_vs_oracle(orc, frac):
+    """An occupation far from the spectrum's middle: the first updates take
+    the TC2 maps (gamma outside [0, 6]); four updates, then ENOCONV, on both
+    sides with the same branches and the same X."""
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(64, 5, cutoff=4.0, seed=6)
+    nocc = round(frac * h.shape[0])
+    p_ref, st_ref, s_ref = orc.trs4(h, nocc, eps=0.0, tol=1e-12, max_iter=4)
+    d = to_dev(h)
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol, o.max_iter = 0.0, 1e-12, 4
+    st, ph, stats = bsm.bsm_trs4(d.handle, nocc, o)
+    assert st == s_ref == bsm.ENOCONV and ph
+    assert list(stats.branch[:4]) == st_ref["branch"] and st_ref["branch"][0] in (0, 1)
+    p = bsm.Matrix(ph, h.row_blk_size, h.col_blk_size)
+    assert_same_matrix(from_dev(p), p_ref, TOL_FP64, "TRS4 X_4")
