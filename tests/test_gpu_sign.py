@@ -228,7 +228,11 @@ def test_tc2_vs_oracle(orc, c):
                          ids=lambda c: f"n{c['n']}b{c['b']}e{c['eps']:g}")
 def test_trs4_vs_oracle(orc, c):
     """Trace-resetting purification: the same updates (branch and gamma) as
-    the oracle, P within the FP64 tolerance, trace(P) the occupied count."""
+    the oracle, P within the FP64 tolerance, trace(P) the occupied count.
+    gamma = (N - trace F) / trace G divides two quantities that both vanish
+    as X converges: trace F carries a rounding error of about 1e-14 and
+    trace G is of the order n e_k^2, so gamma is compared within
+    1e-6 |gamma| + 1e-12 / (n e_k^2); X is compared at the end."""
     from paper_2003_03868_amd import bsm
     h = synth.neighbour_hamiltonian(c["n"], c["b"], cutoff=c["rc"], seed=c["seed"])
     p_ref, st_ref, s_ref = orc.trs4(h, h.meta["n_occ"], eps=c["eps"], tol=1e-9)
@@ -239,7 +243,10 @@ def test_trs4_vs_oracle(orc, c):
     assert st == s_ref == bsm.OK, bsm.bsm_last_error()
     k = stats.iterations
     assert k == st_ref["iterations"] and list(stats.branch[:k]) == st_ref["branch"]
-    assert np.allclose(list(stats.gamma_hist[:k]), st_ref["gamma"], rtol=1e-8, atol=1e-10)
+    n = h.shape[0]
+    for i in range(k):
+        g, gr, e = stats.gamma_hist[i], st_ref["gamma"][i], st_ref["e_hist"][i]
+        assert abs(g - gr) <= 1e-6 * abs(gr) + 1e-12 / (n * e * e), (i, g, gr, e)
     assert np.allclose(list(stats.e_hist[:k + 1]), st_ref["e_hist"], rtol=1e-6, atol=1e-14)
     assert stats.n_multiplies == st_ref["n_multiplies"] == 3 * k + 1
     p = bsm.Matrix(ph, h.row_blk_size, h.col_blk_size)
