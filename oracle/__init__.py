@@ -38,6 +38,11 @@ Parity status of each function (what pins it, see ``tests/test_oracle.py``):
                        the rest), the branch rules by hand; on dense cases the
                        projector onto the N lowest eigenvectors (LAPACK), and
                        TC2's result.
+* ``submatrix_density`` -- pinned: exact (the full eigendecomposition
+                       density) when every column's neighbourhood is the
+                       whole matrix or a single block, and on the hub column
+                       of an arrow pattern; brute-force dense assembly of
+                       each submatrix on tiny cases.
 * ``mu_bisect``     -- pinned: diagonal H, whose count is the number of
                        diagonal entries below mu, so every midpoint follows
                        by hand; on dense cases the accepted mu lies in the
@@ -262,6 +267,25 @@ def sign_ns(h: BSR, mu: float = 0.0, eps: float = 0.0, tol: float = 1e-6,
                  scale=float(st.scale), trace_x=float(st.trace_x),
                  trace_p=float(st.trace_p), flops=float(st.flops))
     return x, stats, int(status)
+
+
+def _submatrix_module():
+    """oracle/submatrix.py, or the copy BSM_ORACLE_SUBMATRIX names (a test
+    points it at a deliberately broken copy to show the pins fail)."""
+    path = os.environ.get("BSM_ORACLE_SUBMATRIX")
+    if not path:
+        from . import submatrix
+        return submatrix
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("oracle_submatrix_variant", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def submatrix_density(h: BSR, mu: float = 0.0, eps: float = 0.0, norm="frob", columns=None):
+    """P by the submatrix method (see oracle/submatrix.py); returns (P, record)."""
+    return _submatrix_module().submatrix_density(h, mu=mu, eps=eps, norm=norm, columns=columns)
 
 
 def mu_bisect(h: BSR, n_target: float, mu_lo: float, mu_hi: float, count_tol: float = 0.5,

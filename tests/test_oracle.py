@@ -824,6 +824,109 @@ def test_trs4_matches_tc2_on_neighbour_hamiltonian(orc):
     assert st["iterations"] < st2["iterations"]
 
 
+# ------------------------------------------------------ submatrix method
+
+def _exact_density(d, mu):
+    w, v = np.linalg.eigh(d - mu * np.eye(d.shape[0]))
+    return v[:, w < 0] @ v[:, w < 0].T
+
+
+def _sym(rng, n):
+    a = rng.standard_normal((n, n))
+    return 0.5 * (a + a.T)
+
+
+def test_submatrix_single_block_neighbourhoods_are_exact(orc):
+    """Only diagonal blocks stored: every submatrix is one block, so P is the
+    exact density of the block-diagonal H."""
+    rng = np.random.default_rng(60)
+    sizes = rng.integers(1, 8, 9)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    d = np.zeros((off[-1], off[-1]))
+    for i in range(sizes.size):
+        d[off[i]:off[i + 1], off[i]:off[i + 1]] = _sym(rng, sizes[i])
+    p, rec = orc.submatrix_density(_dense_to_bsr(d, sizes), mu=0.15)
+    assert rec["max_dim"] == sizes.max()
+    assert _rel(p.to_dense(), _exact_density(d, 0.15)) <= 1e-12
+
+
+@pytest.mark.parametrize("mu", [-0.4, 0.3])
+def test_submatrix_full_pattern_is_exact(orc, mu):
+    """Every block stored: every submatrix is the whole matrix, so P is the
+    exact density; mu = -0.4 and 0.3 give different occupations."""
+    rng = np.random.default_rng(61)
+    sizes = rng.integers(1, 6, 7)
+    d = _sym(rng, int(sizes.sum()))
+    p, rec = orc.submatrix_density(_dense_to_bsr(d, sizes), mu=mu)
+    assert rec["n_sub"] == sizes.size and rec["max_dim"] == sizes.sum()
+    assert _rel(p.to_dense(), _exact_density(d, mu)) <= 1e-12
+
+
+def test_submatrix_arrow_pattern(orc):
+    """Block 0 coupled to every block, the others only to block 0: column 0's
+    neighbourhood is everything, so P's block column 0 is exact; block
+    column j != 0 comes from the two-block submatrix over {0, j}, assembled
+    here by dense indexing of H."""
+    rng = np.random.default_rng(62)
+    sizes = rng.integers(1, 6, 6)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    n = int(off[-1])
+    d = _sym(rng, n)
+    mask = np.zeros((n, n), bool)
+    for i in range(sizes.size):
+        for j in range(sizes.size):
+            if i == j or i == 0 or j == 0:
+                mask[off[i]:off[i + 1], off[j]:off[j + 1]] = True
+    d = np.where(mask, d, 0.0)
+    mu = 0.05
+    p, rec = orc.submatrix_density(_dense_to_bsr(d, sizes), mu=mu)
+    pd = p.to_dense()
+    ex = _exact_density(d, mu)
+    c0 = slice(off[0], off[1])
+    assert _rel(pd[:, c0], ex[:, c0]) <= 1e-12
+    for j in range(1, sizes.size):
+        idx = np.r_[off[0]:off[1], off[j]:off[j + 1]]
+        pj = _exact_density(d[np.ix_(idx, idx)], mu)
+        cj = slice(off[j], off[j + 1])
+        got = pd[:, cj]
+        assert np.allclose(got[idx], pj[:, sizes[0]:], atol=1e-13)
+        others = np.setdiff1d(np.arange(n), idx)
+        assert not got[others].any()
+
+
+def test_submatrix_neighbour_hamiltonian_approximates_the_density(orc):
+    """On a gapped neighbour Hamiltonian the submatrix density is close to
+    the exact one (the method's approximation, not an identity): within
+    1e-3 in the relative Frobenius norm, trace within 1e-3 of the occupied
+    count, pattern of H; the filter then drops blocks below eps."""
+    h = synth.neighbour_hamiltonian(100, 5, cutoff=4.5, seed=3)
+    p, rec = orc.submatrix_density(h)
+    assert np.array_equal(p.row_ptr, h.row_ptr) and np.array_equal(p.col_idx, h.col_idx)
+    ex = _exact_density(h.to_dense(), 0.0)
+    assert _rel(p.to_dense(), ex) <= 1e-3
+    assert np.trace(p.to_dense()) == pytest.approx(h.meta["n_occ"], abs=1e-3)
+    pf, _ = orc.submatrix_density(h, eps=1e-2)
+    off = p.block_offsets()
+    norms = {(int(i), int(j)): np.sqrt((p.values[off[t]:off[t + 1]] ** 2).sum())
+             for t, (i, j) in enumerate(zip(p.block_rows(), p.col_idx))}
+    kept = {(int(i), int(j)) for i, j in zip(pf.block_rows(), pf.col_idx)}
+    assert kept == {k for k, v in norms.items() if v >= 1e-2} and len(kept) < len(norms)
+
+
+def test_submatrix_column_sample_matches_the_full_run(orc):
+    h = synth.neighbour_hamiltonian(64, 5, cutoff=4.0, seed=8)
+    p, _ = orc.submatrix_density(h)
+    cols = [3, 17, 40]
+    ps, rec = orc.submatrix_density(h, columns=cols)
+    assert rec["n_sub"] == 3
+    full = p.to_dense()
+    part = ps.to_dense()
+    off = np.concatenate([[0], np.cumsum(h.col_blk_size)])
+    for j in cols:
+        sl = slice(off[j], off[j + 1])
+        assert np.array_equal(part[:, sl], full[:, sl])
+
+
 # ------------------------------------------------ product-level norm screening
 
 def _scale_blocks(m: BSR, rng, lo=-4.0):

@@ -69,6 +69,32 @@ MUTANTS = [
     ("stall_rule", "if (k == max_iter) { status = ORC_ENOCONV; break; }", "if (k == max_iter) { break; }"),
 ]
 
+# Planted mistakes in the Python submatrix oracle (oracle/submatrix.py).
+PY_SRC = os.path.join(ROOT, "oracle", "submatrix.py")
+PY_MUTANTS = [
+    ("sub_mu_sign", "t -= mu * np.eye(t.shape[0])", "t += mu * np.eye(t.shape[0])"),
+    ("sub_eigvec", "x = (v * np.sign(w)) @ v.T", "x = (v * np.sign(w)) @ v"),
+    ("sub_half", "pj = 0.5 * (np.eye(t.shape[0]) - x)", "pj = 0.5 * (np.eye(t.shape[0]) + x)"),
+    ("sub_column", "out[(int(i), j)] = pj[st[b]:st[b + 1], st[a]:st[a + 1]]",
+     "out[(int(i), j)] = pj[st[b]:st[b + 1], 0:st[a + 1] - st[a]]"),
+    ("sub_filter", "(blk * blk).sum() < eps * eps", "(blk * blk).sum() < eps"),
+    ("sub_missing_block", "            if blk is not None:\n                t[st[a]",
+     "            if blk is not None and a != b:\n                t[st[a]"),
+]
+
+
+def _run_py_mutant(tmpdir, name, old, new):
+    src = open(PY_SRC).read()
+    assert src.count(old) == 1, name
+    path = os.path.join(tmpdir, f"m_{name}.py")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    env = dict(os.environ, BSM_ORACLE_SUBMATRIX=path)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "-k", "submatrix", os.path.join(ROOT, "tests", "test_oracle.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return name, r.returncode
+
 
 def _run_mutant(tmpdir, name, old, new):
     src = open(SRC).read()
@@ -89,5 +115,6 @@ def _run_mutant(tmpdir, name, old, new):
 def test_every_planted_mistake_is_caught(tmp_path):
     with ThreadPoolExecutor(max_workers=4) as ex:
         res = list(ex.map(lambda m: _run_mutant(str(tmp_path), *m), MUTANTS))
+        res += list(ex.map(lambda m: _run_py_mutant(str(tmp_path), *m), PY_MUTANTS))
     survivors = [name for name, rc in res if rc == 0]
     assert not survivors, f"pins missed planted mistakes: {survivors}"
