@@ -146,6 +146,20 @@ typedef struct bsm_tc2_stats {
     double gamma_hist[128];  /* TRS4: gamma of update k (0 for TC2) */
 } bsm_tc2_stats;
 
+/* Record of bsm_submatrix_density. */
+typedef struct bsm_sub_stats {
+    int32_t n_sub;           /* submatrices (one per block column) */
+    int32_t max_dim;         /* largest submatrix edge (scalars) */
+    double mean_dim;         /* mean submatrix edge */
+    int32_t max_iterations;  /* Newton-Schulz iterations of the slowest submatrix */
+    int32_t n_batches;       /* batches the submatrices were processed in */
+    double flops;            /* algorithmic flops of the dense products, 2 n^3 each */
+    double gemm_ms;          /* device time of the dense product kernels (HIP events) */
+    double device_ms;        /* device time of the whole call */
+    double r_max;            /* largest final residual ||X^2 - I||_F / n over submatrices */
+    int64_t nnzb;            /* stored blocks of P after the filter */
+} bsm_sub_stats;
+
 /* Default options: eps 0, tol 1e-6, max_iter 100, FROB, FP64, no graph, order 2,
  * no screening. */
 void bsm_sign_opts_default(bsm_sign_opts *opts);
@@ -366,6 +380,27 @@ int bsm_tc2(bsm_matrix H, double n_occ, const bsm_sign_opts *opts, bsm_matrix *p
  */
 int bsm_trs4(bsm_matrix H, double n_occ, const bsm_sign_opts *opts, bsm_matrix *p_out,
              bsm_tc2_stats *stats, void *stream);
+
+/*
+ * Density matrix by the submatrix method (section "Submatrix Method"): for
+ * every block column j, the dense principal submatrix T_j of H over the
+ * block rows stored in column j (ascending, j included), its density
+ * matrix P_j = (I - sign(T_j - mu I))/2, and P's block column j = P_j's
+ * block column of j, on H's pattern; P is then filtered (eps_filter, norm).
+ * sign(T_j - mu I) by the dense Newton-Schulz iteration from
+ * X_0 = (T_j - mu I)/||T_j - mu I||_inf, each submatrix stopped when
+ * ||X^2 - I||_F / n_j < tol; FP64 throughout.
+ * H: square, square diagonal blocks, every diagonal block stored, block
+ * columns spanning at most 32768 rows.  opts: eps_filter, norm, tol,
+ * max_iter (0..120); order, prec, graph and screening are ignored.  Device
+ * memory: three dense padded squares per submatrix of a batch (batches of
+ * consecutive columns up to 48 GiB, BSM_SUB_BATCH_BYTES).  P is a new
+ * handle (caller destroys) for BSM_OK and BSM_ENOCONV (some submatrix
+ * above tol after max_iter); BSM_ENONFINITE for NaN/Inf, BSM_EINVAL for bad
+ * arguments.  stats may be NULL.  Waits (a residual read per iteration).
+ */
+int bsm_submatrix_density(bsm_matrix H, double mu, const bsm_sign_opts *opts, bsm_matrix *p_out,
+                          bsm_sub_stats *stats, void *stream);
 
 /* P = (I - X)/2 from a sign matrix X, as a new handle; trace_p (may be NULL) gets trace(P). */
 int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void *stream);

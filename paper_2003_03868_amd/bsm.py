@@ -75,6 +75,13 @@ class bsm_tc2_stats(C.Structure):
                 ("gamma_hist", C.c_double * 128)]
 
 
+class bsm_sub_stats(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("max_dim", C.c_int32), ("mean_dim", C.c_double),
+                ("max_iterations", C.c_int32), ("n_batches", C.c_int32), ("flops", C.c_double),
+                ("gemm_ms", C.c_double), ("device_ms", C.c_double), ("r_max", C.c_double),
+                ("nnzb", C.c_int64)]
+
+
 class bsm_smm_params(C.Structure):
     _fields_ = [("family", C.c_int32), ("wpg", C.c_int32), ("prefetch", C.c_int32),
                 ("reserved", C.c_int32)]
@@ -121,6 +128,9 @@ _SIGS = [
                           C.POINTER(C.c_void_p), C.POINTER(bsm_tc2_stats), C.c_void_p]),
     ("bsm_trs4", C.c_int, [C.c_void_p, C.c_double, C.POINTER(bsm_sign_opts),
                            C.POINTER(C.c_void_p), C.POINTER(bsm_tc2_stats), C.c_void_p]),
+    ("bsm_submatrix_density", C.c_int, [C.c_void_p, C.c_double, C.POINTER(bsm_sign_opts),
+                                        C.POINTER(C.c_void_p), C.POINTER(bsm_sub_stats),
+                                        C.c_void_p]),
     ("bsm_density_from_sign", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p),
                                         C.POINTER(C.c_double), C.c_void_p]),
     ("bsm_smm_bench", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
@@ -337,6 +347,19 @@ def bsm_tc2(h, n_occ, opts: bsm_sign_opts | None = None, stream=None):
 def bsm_trs4(h, n_occ, opts: bsm_sign_opts | None = None, stream=None):
     """TRS4 purification; returns (status, P handle or None, stats) as bsm_tc2."""
     return _purify("bsm_trs4", h, n_occ, opts, stream)
+
+
+def bsm_submatrix_density(h, mu=0.0, opts: bsm_sign_opts | None = None, stream=None):
+    """Submatrix-method density; returns (status, P handle or None, stats);
+    ENOCONV/ENONFINITE are returned, not raised."""
+    out = C.c_void_p()
+    stats = bsm_sub_stats()
+    o = opts if opts is not None else bsm_sign_opts_default()
+    st = load().bsm_submatrix_density(h, float(mu), C.byref(o), C.byref(out), C.byref(stats),
+                                      _stream(stream))
+    if st not in (OK, ENOCONV, ENONFINITE):
+        _check(st, "bsm_submatrix_density")
+    return st, out.value, stats
 
 
 def bsm_add(alpha, a, beta=0.0, b=None, gamma=0.0, eps_filter=0.0, norm=0, stream=None) -> int:

@@ -16,6 +16,8 @@ int density_nonorth(Mat &K, Mat &S, double mu, const bsm_sign_opts &o, Mat **p_o
                     hipStream_t s);
 int trs4_purify(Mat &H, double n_occ, const bsm_sign_opts &o, Mat **p_out, bsm_tc2_stats *st,
                 hipStream_t s);
+int submatrix_density(Mat &H, double mu, const bsm_sign_opts &o, Mat **p_out, bsm_sub_stats *st,
+                      hipStream_t s);
 int tc2_purify(Mat &H, double n_occ, const bsm_sign_opts &o, Mat **p_out, bsm_tc2_stats *st,
                hipStream_t s);
 }  // namespace bsm
@@ -404,6 +406,22 @@ int bsm_trs4(bsm_matrix H, double n_occ, const bsm_sign_opts *opts, bsm_matrix *
     std::memset(st, 0, sizeof(*st));
     Mat *p = nullptr;
     const int rc = bsm::trs4_purify(H->m, n_occ, o, &p, st, as_stream(stream));
+    if (p) *p_out = wrap(p);
+    return rc;
+}
+
+int bsm_submatrix_density(bsm_matrix H, double mu, const bsm_sign_opts *opts, bsm_matrix *p_out,
+                          bsm_sub_stats *stats, void *stream) {
+    bsm::clear_error();
+    if (!H || !p_out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    *p_out = nullptr;
+    bsm_sign_opts o;
+    if (opts) o = *opts; else bsm_sign_opts_default(&o);
+    bsm_sub_stats local;
+    bsm_sub_stats *st = stats ? stats : &local;
+    std::memset(st, 0, sizeof(*st));
+    Mat *p = nullptr;
+    const int rc = bsm::submatrix_density(H->m, mu, o, &p, st, as_stream(stream));
     if (p) *p_out = wrap(p);
     return rc;
 }

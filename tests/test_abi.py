@@ -46,7 +46,7 @@ def test_struct_layouts_match_header(tmp_path):
         "bsm_info": bsm.bsm_info, "bsm_mult_stats": bsm.bsm_mult_stats,
         "bsm_sign_opts": bsm.bsm_sign_opts, "bsm_sign_stats": bsm.bsm_sign_stats,
         "bsm_mu_stats": bsm.bsm_mu_stats, "bsm_tc2_stats": bsm.bsm_tc2_stats,
-        "bsm_smm_params": bsm.bsm_smm_params,
+        "bsm_smm_params": bsm.bsm_smm_params, "bsm_sub_stats": bsm.bsm_sub_stats,
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bsm.h"', 'int main(void){']
     for sname, cls in structs.items():
