@@ -254,15 +254,139 @@ def bench_tc2(args, h, dh, bsm, torch):
         "cpu_baseline": None}))
 
 
+def bench_submatrix(args, h, dh, bsm, torch):
+    """Timed steps of the submatrix method (one dense problem per block
+    column); the sparse Newton-Schulz density on the same H timed beside it;
+    both measured against a reference P from the sparse iteration with a
+    tight filter (untimed).  One JSON line."""
+    import math
+
+    import numpy as np
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol = args.eps, args.sub_tol
+    stream = torch.cuda.current_stream()
+    n = float(h.shape[0])
+
+    def step(keep=False):
+        st, ph, stats = bsm.bsm_submatrix_density(dh.handle, 0.0, o, stream=stream)
+        if st != bsm.OK:
+            raise RuntimeError(f"submatrix failed: {bsm.STATUS_NAMES[st]} {bsm.bsm_last_error()}")
+        if keep:
+            return stats, ph
+        bsm.bsm_destroy(ph)
+        return stats
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    times, recs = [], []
+    ph = None
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        if k == args.steps - 1:
+            stats, ph = step(keep=True)
+        else:
+            stats = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        recs.append(stats)
+        log(f"step {k}: {times[-1] * 1e3:.0f} ms, {stats.n_sub} submatrices (max {stats.max_dim}, "
+            f"mean {stats.mean_dim:.0f}), {stats.max_iterations} iterations, "
+            f"dense products {stats.gemm_ms:.0f} ms, r_max {stats.r_max:.1e}, nnzb(P) {stats.nnzb}")
+    total = sum(times)
+    flops = sum(s.flops for s in recs)
+    gemm_ms = sum(s.gemm_ms for s in recs)
+    achieved = flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
+
+    # the sparse Newton-Schulz density on the same H and eps (timed alone)
+    os_ = bsm.bsm_sign_opts_default()
+    os_.eps_filter, os_.tol = args.eps, args.tol
+    ns_times = []
+    for _ in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, xh, sst = bsm.bsm_sign_iterate(dh.handle, 0.0, os_, stream=stream)
+        pn, tpn = bsm.bsm_density_from_sign(xh, stream=stream)
+        torch.cuda.synchronize()
+        ns_times.append(time.perf_counter() - t)
+        bsm.bsm_destroy(xh)
+        if len(ns_times) < max(1, args.steps):
+            bsm.bsm_destroy(pn)
+    log(f"sparse Newton-Schulz on the same H: {sum(ns_times) / len(ns_times) * 1e3:.0f} ms, "
+        f"{sst.iterations} iterations")
+
+    # reference: sparse iteration with eps 1e-10 (untimed)
+    orf = bsm.bsm_sign_opts_default()
+    orf.eps_filter, orf.tol = 1e-10, 1e-9
+    st, xr, rst = bsm.bsm_sign_iterate(dh.handle, 0.0, orf, stream=stream)
+    pr, tpr = bsm.bsm_density_from_sign(xr, stream=stream)
+    bsm.bsm_destroy(xr)
+
+    def err(p):
+        d = bsm.bsm_add(1.0, p, -1.0, pr, stream=stream)
+        num = bsm.bsm_sqdist_identity(d, 0.0, stream=stream)
+        bsm.bsm_destroy(d)
+        return math.sqrt(num / bsm.bsm_sqdist_identity(pr, 0.0, stream=stream))
+
+    tp_sub = bsm.bsm_trace(ph, stream=stream)
+    e_sub, e_ns = err(ph), err(pn)
+    log(f"vs reference (sparse, eps 1e-10): submatrix {e_sub:.2e} (trace {tp_sub - tpr:+.2e}), "
+        f"Newton-Schulz {e_ns:.2e} (trace {tpn - tpr:+.2e})")
+    for hnd in (ph, pn, pr):
+        bsm.bsm_destroy(hnd)
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        cols = np.random.default_rng(0).choice(h.nbrows, min(args.cpu_cols, h.nbrows), replace=False)
+        t0 = time.perf_counter()
+        _, rec = oracle.submatrix_density(h, columns=cols)
+        dt = time.perf_counter() - t0
+        cpu = dict(value=len(cols) / (dt * h.nbrows), unit="P/s (whole matrix)",
+                   cores=oracle.num_threads(), kind="oracle",
+                   sample=f"{len(cols)} of {h.nbrows} block columns (dense eigendecomposition of "
+                          f"each submatrix, mean edge {np.mean(rec['dims']):.0f}) in {dt:.1f} s, "
+                          f"scaled to all columns: {dt * h.nbrows / len(cols):.1f} s per P")
+        log(f"cpu baseline: {cpu['sample']}")
+
+    s0 = recs[-1]
+    print(json.dumps({
+        "metric": "block-sparse multiply GFLOP/s (FP64 vs mixed); sign-iteration time to 1e-6",
+        "value": flops / total / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"FP64 submatrix-method density, {h.nbrows}-site neighbour-list "
+                               f"Hamiltonian, {int(h.row_blk_size[0])}x{int(h.row_blk_size[0])} "
+                               f"blocks, {args.density:g} sites/A^3, cutoff {args.cutoff:g} A, "
+                               f"eps_filter {args.eps:g}, submatrix tol {args.sub_tol:g}",
+                   "n_sites": h.nbrows, "n": int(n), "nnzb_H": h.nnzb, "seed": args.seed},
+        "time_to_P_ms": total / args.steps * 1e3,
+        "n_sub": int(s0.n_sub), "max_dim": int(s0.max_dim), "mean_dim": float(s0.mean_dim),
+        "iterations_max": int(s0.max_iterations), "r_max": float(s0.r_max),
+        "tflop_per_step": flops / args.steps / 1e12,
+        "rel_err_vs_reference": e_sub, "trace_diff_vs_reference": tp_sub - tpr,
+        "newton_schulz_same_H": {"ms": sum(ns_times) / len(ns_times) * 1e3,
+                                 "iterations": int(sst.iterations), "rel_err_vs_reference": e_ns,
+                                 "trace_diff_vs_reference": tpn - tpr},
+        "roofline": {"bound": "mfma", "kernel": "k_sub_gemm", "achieved": achieved,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "gemm_ms_per_step": gemm_ms / args.steps},
+        "cpu_baseline": cpu}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=["sign23", "mixed", "mult832"], default="sign23",
+    ap.add_argument("--workload", choices=["sign23", "mixed", "mult832", "water"], default="sign23",
                     help="sign23: 2048 sites x 23; mixed: 4096 sites, sizes {5,13,23,26}; "
-                         "mult832: one 832 x 832 multiply (64 x 64 blocks of 13, 20%% present)")
+                         "mult832: one 832 x 832 multiply (64 x 64 blocks of 13, 20%% present); "
+                         "water: 6192 sites x 6 at 0.0334 sites/A^3 (water-like, minimal basis)")
     ap.add_argument("--sites", type=int, default=0, help="override the site count")
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -285,6 +409,13 @@ def main():
     ap.add_argument("--screen", type=float, default=0.0, metavar="TAU",
                     help="leave out block products with ||A_ik|| ||B_kj|| < TAU in the "
                          "Newton-Schulz multiplies (FP64, order 2)")
+    ap.add_argument("--method", choices=["sign", "submatrix"], default="sign",
+                    help="submatrix: the submatrix method (dense problem per block column) "
+                         "on the water-like workload unless --workload says otherwise")
+    ap.add_argument("--sub-tol", type=float, default=1e-8,
+                    help="Newton-Schulz tolerance inside each submatrix")
+    ap.add_argument("--cpu-cols", type=int, default=1500,
+                    help="block columns of the oracle's submatrix sample")
     ap.add_argument("--graph", type=int, choices=[0, 1], default=0,
                     help="1: replay captured hipGraphs once X's block pattern stops changing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -321,8 +452,16 @@ def main():
         bench_mult832(args, bsm, synth, torch)
         return
 
+    if args.method == "submatrix" and args.workload == "sign23" and "--workload" not in sys.argv:
+        args.workload = "water"
+    args.density, args.cutoff = 0.1, 6.0
     t0 = time.perf_counter()
-    if args.workload == "sign23":
+    if args.workload == "water":
+        args.sites = args.sites or 6192
+        args.density = 0.0334
+        h = synth.neighbour_hamiltonian(args.sites, 6, density=args.density, cutoff=args.cutoff,
+                                        seed=args.seed)
+    elif args.workload == "sign23":
         args.sites = args.sites or 2048
         h = synth.neighbour_hamiltonian(args.sites, 23, density=0.1, cutoff=6.0, seed=args.seed)
     else:
@@ -334,6 +473,9 @@ def main():
     dh = bsm.Matrix.from_bsr(h, device=True)
     torch.cuda.synchronize()
 
+    if args.method == "submatrix":
+        bench_submatrix(args, h, dh, bsm, torch)
+        return
     if args.overlap > 0.0:
         bench_nonorth(args, h, dh, bsm, synth, torch)
         return
