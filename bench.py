@@ -390,7 +390,7 @@ def main():
     ap.add_argument("--sites", type=int, default=0, help="override the site count")
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--cpu-rows", type=int, default=512)
+    ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--prec", choices=["fp64", "fp32", "bf16"], default="fp64",
                     help="block-product precision (fp32 / split-bf16 switch to FP64 once "
@@ -592,11 +592,12 @@ def main():
         "config": {
             "workload": (f"{args.prec.upper()} {'Newton-Schulz' if args.order == 2 else f'order-{args.order}'} sign iteration, {h.nbrows}-site "
                          "neighbour-list Hamiltonian, "
-                         + ("23x23 blocks" if args.workload == "sign23"
-                            else "block sizes {5,13,23,26}") +
-                         f", cutoff 6 A, 0.1 sites/A^3, eps_filter {args.eps:g}, "
-                         f"to ||X^2-I||_F/n < {args.tol:g}"),
-            "n_sites": h.nbrows, "block": 23 if args.workload == "sign23" else "5/13/23/26",
+                         + {"sign23": "23x23 blocks", "water": "6x6 blocks"}.get(
+                             args.workload, "block sizes {5,13,23,26}") +
+                         f", cutoff {args.cutoff:g} A, {args.density:g} sites/A^3, "
+                         f"eps_filter {args.eps:g}, to ||X^2-I||_F/n < {args.tol:g}"),
+            "n_sites": h.nbrows,
+            "block": {"sign23": 23, "water": 6}.get(args.workload, "5/13/23/26"),
             "n": int(n), "eps_filter": args.eps, "kernel_table": args.table,
             "tol": args.tol, "seed": args.seed, "nnzb_H": h.nnzb,
             "graph_replay": bool(args.graph), "order": args.order,
@@ -620,6 +621,7 @@ def main():
             "bound": "mfma",
             "kernel": ("k_smm_f64_quad<23,2,2,4,5,1,true>" if args.screen > 0.0
                        else "k_smm_f64_quad<23,2,2,4,6,1>" if args.workload == "sign23"
+                       else "k_smm_f64_quad<6,2,2,1,8,1>" if args.workload == "water"
                        else "k_smm_f64_class")
             if args.prec == "fp64" else "k_smm_lowp",
             "achieved": achieved,

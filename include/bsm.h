@@ -412,7 +412,7 @@ int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void
  *   family   0: 16x16x4 FP64 matrix-core tiles; 1: 4x4x4 (four blocks per
  *            instruction); 2: the (m, n)-specialised kernel (m, n in
  *            {5, 13, 23, 26}, k <= 26); 3: the compile-time-shape kernel
- *            (m = n = k in {5, 13, 23, 26, 32});
+ *            (m = n = k in {5, 6, 13, 23, 26, 32});
  *   wpg      C blocks (wavefronts) per workgroup: 1, 2 or 4;
  *   prefetch 1: load the next product's operands while multiplying.
  */

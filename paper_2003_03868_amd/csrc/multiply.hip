@@ -276,7 +276,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     int GR = 2, GC = 2;
     if (use_quad && prec == BSM_FP64 && tau == 0.0) quad_shape(A.uni_r, &GR, &GC);
     if (st == BSM_OK && tau > 0.0 && !use_quad) {
-        set_error("product screening needs uniform block sizes 5, 13, 23, 26 or 32 and the "
+        set_error("product screening needs uniform block sizes 5, 6, 13, 23, 26 or 32 and the "
                   "default kernel variant");
         st = BSM_EINVAL;
     }

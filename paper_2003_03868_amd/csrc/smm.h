@@ -28,7 +28,7 @@ enum SmmVariant {
                       // (m, n)-specialised kernel, run-time k
     kSmmF64Tuned = 5, // tunable run-time-shape kernel, parameters from the table
     kSmmF64Quad = 6,  // compile-time uniform shapes, one workgroup per 2 x 2 quad of
-                      // C blocks (default for uniform sizes 5, 13, 23, 26, 32)
+                      // C blocks (default for uniform sizes 5, 6, 13, 23, 26, 32)
 };
 
 struct SmmArgs {
@@ -87,7 +87,7 @@ void table_set(int count, const int32_t *mnk, const SmmParams *prm);   // count 
 int smm_bench(int m, int n, int k, int64_t n_c, int per_c, int n_prm, const SmmParams *prm,
               int reps, double *ms_out, hipStream_t s);
 
-// Quad kernel (smm_quad.hip): uniform m = n = k in {5, 13, 23, 26, 32}.
+// Quad kernel (smm_quad.hip): uniform m = n = k in {5, 6, 13, 23, 26, 32}.
 bool smm_quad_available(int m, int n, int k);
 // Group shape for uniform block size m: 2 x 2 (quads) unless BSM_QUAD_GROUP
 // asks for 4 (4 x 4) or 42 (4 x 2, size 23) and m has that kernel.

@@ -554,12 +554,13 @@ static int launch_persistent(const SmmArgs &a, hipStream_t s) {
 
 // Uniform (m, n, k) shapes with a compile-time kernel.
 bool smm_fixed_available(int m, int n, int k) {
-    return (m == n && n == k) && (m == 5 || m == 13 || m == 23 || m == 26 || m == 32);
+    return (m == n && n == k) && (m == 5 || m == 6 || m == 13 || m == 23 || m == 26 || m == 32);
 }
 
 int launch_fixed(const SmmArgs &a, int m, unsigned grid, hipStream_t s) {
     switch (m) {
         case 5: k_smm_f64_fixed<5, 5, 5, 8><<<grid, 64, 0, s>>>(a); break;
+        case 6: k_smm_f64_fixed<6, 6, 6, 8><<<grid, 64, 0, s>>>(a); break;
         case 13: k_smm_f64_fixed<13, 13, 13, 8><<<grid, 64, 0, s>>>(a); break;
         case 23: k_smm_f64_fixed<23, 23, 23, 4><<<grid, 64, 0, s>>>(a); break;
         case 26: k_smm_f64_fixed<26, 26, 26, 3><<<grid, 64, 0, s>>>(a); break;

@@ -393,14 +393,14 @@ static int quad_stage() {
 }
 
 bool smm_quad_available(int m, int n, int k) {
-    return m == n && n == k && (m == 5 || m == 13 || m == 23 || m == 26 || m == 32);
+    return m == n && n == k && (m == 5 || m == 6 || m == 13 || m == 23 || m == 26 || m == 32);
 }
 
 void quad_shape(int m, int *gr, int *gc) {
     const char *e = getenv("BSM_QUAD_GROUP");
     const int g = e ? atoi(e) : 2;
     *gr = *gc = 2;
-    if (m == 5) return;
+    if (m == 5 || m == 6) return;
     if (g == 4) { *gr = 4; *gc = 4; }
     else if (g == 42 && m == 23) { *gr = 4; *gc = 2; }
 }
@@ -417,10 +417,11 @@ int launch_quad(const SmmArgs &a, hipStream_t s) {
     const unsigned g = static_cast<unsigned>(grid);
     const int w = quad_waves(), eps = quad_stage();
     if (a.q_pm) {
-        // product masks (norm screening): quads with four waves (size 5: one)
+        // product masks (norm screening): quads with four waves (sizes 5, 6: one)
         if (a.q_gr != 2 || a.q_gc != 2) { set_error("internal: masked groups are quads"); return BSM_EINVAL; }
         switch (a.uni_m) {
             case 5: k_smm_f64_quad<5, 2, 2, 1, 6, 1, true><<<g, 64, 0, s>>>(a); break;
+            case 6: k_smm_f64_quad<6, 2, 2, 1, 6, 1, true><<<g, 64, 0, s>>>(a); break;
             case 13: k_smm_f64_quad<13, 2, 2, 4, 6, 1, true><<<g, 256, 0, s>>>(a); break;
             case 23: k_smm_f64_quad<23, 2, 2, 4, 5, 1, true><<<g, 256, 0, s>>>(a); break;
             case 26: k_smm_f64_quad<26, 2, 2, 4, 4, 1, true><<<g, 256, 0, s>>>(a); break;
@@ -452,6 +453,7 @@ int launch_quad(const SmmArgs &a, hipStream_t s) {
     }
     switch (a.uni_m) {
         case 5: k_smm_f64_quad<5, 2, 2, 1, 8, 1><<<g, 64, 0, s>>>(a); break;
+        case 6: k_smm_f64_quad<6, 2, 2, 1, 8, 1><<<g, 64, 0, s>>>(a); break;
         case 13:
             if (w == 4) k_smm_f64_quad<13, 2, 2, 4, 6, 1><<<g, 256, 0, s>>>(a);
             else if (w == 2) k_smm_f64_quad<13, 2, 2, 2, 4, 1><<<g, 128, 0, s>>>(a);

@@ -36,7 +36,7 @@ CATALOGUE = [(f, w, p) for f in (0, 1) for w in (1, 2, 4) for p in (0, 1)]
 CLASS_ENTRY = (2, 1, 1)
 FIXED_ENTRY = (3, 1, 1)
 CLASS_SIZES = (5, 13, 23, 26)
-FIXED_SIZES = (5, 13, 23, 26, 32)
+FIXED_SIZES = (5, 6, 13, 23, 26, 32)
 ALL_ENTRIES = CATALOGUE + [CLASS_ENTRY, FIXED_ENTRY]
 
 

@@ -228,7 +228,7 @@ def test_multiply_kernel_variants(orc, monkeypatch, variant, maxb):
 
 @pytest.mark.parametrize("group,waves,stage", [("2", "1", "1"), ("2", "2", "1"), ("2", "4", "1"),
                                                 ("2", "4", "2"), ("4", "16", "1"), ("42", "8", "1")])
-@pytest.mark.parametrize("b", [5, 13, 23, 26, 32])
+@pytest.mark.parametrize("b", [5, 6, 13, 23, 26, 32])
 def test_quad_kernel_vs_oracle_and_fixed(orc, monkeypatch, group, waves, stage, b):
     """The group kernel (2 x 2 quads with one, two or four waves, one or two
     entries staged per step; 4 x 4 groups with sixteen waves; 4 x 2 groups

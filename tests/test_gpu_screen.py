@@ -38,7 +38,7 @@ def _norm_products(a: BSR, b: BSR) -> np.ndarray:
     return np.concatenate(out) if out else np.zeros(0)
 
 
-@pytest.mark.parametrize("b", [5, 13, 23, 26, 32])
+@pytest.mark.parametrize("b", [5, 6, 13, 23, 26, 32])
 def test_multiply_screened_vs_oracle(orc, monkeypatch, b):
     from paper_2003_03868_amd import bsm
     rng = np.random.default_rng(800 + b)
