@@ -30,7 +30,7 @@ namespace {
 
 constexpr int kTile = 64;      // output tile edge of the dense product
 constexpr int kTk = 16;        // k depth staged per LDS stage
-constexpr int kLdA = 72;       // LDS row pitch (doubles) of the k-major A stage
+constexpr int kLdA = 68;       // LDS row pitch (doubles) of the k-major A stage
 constexpr int kLdB = 80;       // LDS row pitch (doubles) of the B stage
 
 struct SubGemm {
@@ -73,25 +73,29 @@ __global__ __launch_bounds__(256) void k_sub_gemm(SubGemm g) {
     const int lane = t & 63, w = t >> 6;
     const int x = lane >> 4, bb = (lane >> 2) & 3, y = lane & 3;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-    // global -> LDS staging: A rows r0 + t/4, four k from (t%4)*4;
-    // B k row t/16, four columns from (t%16)*4
+    // global -> LDS staging: A rows r0 + t/4, four k from (t%4)*4 (pitch 68:
+    // each transposed store spreads over all banks); B k row t/16, columns
+    // 2c, 2c+1 and 32+2c, 33+2c for c = t%16, so each 16-byte store of a row
+    // is contiguous with its neighbours' and the global reads are two
+    // 256-byte runs per row
     const int ar = t >> 2, ak = (t & 3) << 2;
-    const int bk = t >> 4, bc = (t & 15) << 2;
+    const int bk = t >> 4, bc = (t & 15) << 1;
     const double *ga = X + static_cast<int64_t>(r0 + ar) * ld + ak;
     const double *gb = Bm + static_cast<int64_t>(bk) * ld + c0 + bc;
 
     double2 pa0, pa1, pb0, pb1;
     auto load = [&](int k) {
         const double2 *a2 = reinterpret_cast<const double2 *>(ga + k);
-        const double2 *b2 = reinterpret_cast<const double2 *>(gb + static_cast<int64_t>(k) * ld);
+        const double *bp = gb + static_cast<int64_t>(k) * ld;
         pa0 = a2[0]; pa1 = a2[1];
-        pb0 = b2[0]; pb1 = b2[1];
+        pb0 = *reinterpret_cast<const double2 *>(bp);
+        pb1 = *reinterpret_cast<const double2 *>(bp + 32);
     };
     auto stage = [&](int buf) {
         As[buf][ak + 0][ar] = pa0.x; As[buf][ak + 1][ar] = pa0.y;
         As[buf][ak + 2][ar] = pa1.x; As[buf][ak + 3][ar] = pa1.y;
-        double2 *bs = reinterpret_cast<double2 *>(&Bs[buf][bk][bc]);
-        bs[0] = pb0; bs[1] = pb1;
+        *reinterpret_cast<double2 *>(&Bs[buf][bk][bc]) = pb0;
+        *reinterpret_cast<double2 *>(&Bs[buf][bk][bc + 32]) = pb1;
     };
 
     double acc[8][2];
