@@ -50,7 +50,7 @@ struct SubGemm {
 // (x, b, y) = lane / 16, lane / 4 % 4, lane % 4 feeds A(i = y, k = x) and
 // B(k = x, j = y) of block b and receives D(i = x, j = y).  A is staged
 // k-major so the eight A operands of a k step are conflict-free LDS reads.
-__global__ __launch_bounds__(256) void k_sub_gemm(SubGemm g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sub_gemm(SubGemm g) {
     // consecutive tiles (one submatrix) on one XCD: workgroups b, b+8, ...
     // share an XCD's L2
     const int per = (g.ntiles + kXcds - 1) / kXcds;
@@ -83,32 +83,27 @@ __global__ __launch_bounds__(256) void k_sub_gemm(SubGemm g) {
     const double *ga = X + static_cast<int64_t>(r0 + ar) * ld + ak;
     const double *gb = Bm + static_cast<int64_t>(bk) * ld + c0 + bc;
 
-    double2 pa0, pa1, pb0, pb1;
-    auto load = [&](int k) {
+    // two register sets of staged operands in flight: the loads for k step
+    // i + 3 are issued at step i and written to LDS at step i + 2
+    struct Regs { double2 a0, a1, b0, b1; };
+    auto load = [&](int k, Regs &r) {
         const double2 *a2 = reinterpret_cast<const double2 *>(ga + k);
         const double *bp = gb + static_cast<int64_t>(k) * ld;
-        pa0 = a2[0]; pa1 = a2[1];
-        pb0 = *reinterpret_cast<const double2 *>(bp);
-        pb1 = *reinterpret_cast<const double2 *>(bp + 32);
+        r.a0 = a2[0]; r.a1 = a2[1];
+        r.b0 = *reinterpret_cast<const double2 *>(bp);
+        r.b1 = *reinterpret_cast<const double2 *>(bp + 32);
     };
-    auto stage = [&](int buf) {
-        As[buf][ak + 0][ar] = pa0.x; As[buf][ak + 1][ar] = pa0.y;
-        As[buf][ak + 2][ar] = pa1.x; As[buf][ak + 3][ar] = pa1.y;
-        *reinterpret_cast<double2 *>(&Bs[buf][bk][bc]) = pb0;
-        *reinterpret_cast<double2 *>(&Bs[buf][bk][bc + 32]) = pb1;
+    auto stage = [&](int buf, const Regs &r) {
+        As[buf][ak + 0][ar] = r.a0.x; As[buf][ak + 1][ar] = r.a0.y;
+        As[buf][ak + 2][ar] = r.a1.x; As[buf][ak + 3][ar] = r.a1.y;
+        *reinterpret_cast<double2 *>(&Bs[buf][bk][bc]) = r.b0;
+        *reinterpret_cast<double2 *>(&Bs[buf][bk][bc + 32]) = r.b1;
     };
 
     double acc[8][2];
 #pragma unroll
     for (int R = 0; R < 8; ++R) { acc[R][0] = 0.0; acc[R][1] = 0.0; }
-
-    load(0);
-    stage(0);
-    __syncthreads();
-    for (int k = 0; k < ld; k += kTk) {
-        const int cur = (k / kTk) & 1;
-        const bool more = k + kTk < ld;
-        if (more) load(k + kTk);
+    auto compute = [&](int cur) {
 #pragma unroll
         for (int kk = 0; kk < kTk; kk += 4) {
             double a[8], b[2];
@@ -122,7 +117,25 @@ __global__ __launch_bounds__(256) void k_sub_gemm(SubGemm g) {
                 for (int G = 0; G < 2; ++G)
                     acc[R][G] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[R], b[G], acc[R][G], 0, 0, 0);
         }
-        if (more) stage(cur ^ 1);
+    };
+
+    // k steps of kTk: nk = ld / kTk is a multiple of 4.  Set s0 carries steps
+    // 0, 2, 4, ..., set s1 steps 1, 3, 5, ...; buffer i & 1 holds step i.
+    const int nk = ld / kTk;
+    Regs s0, s1;
+    load(0, s0);
+    stage(0, s0);
+    load(kTk, s1);
+    load(2 * kTk, s0);
+    __syncthreads();
+    for (int i = 0; i < nk; i += 2) {
+        compute(0);                                   // step i
+        stage(1, s1);                                 // step i + 1 (exists: nk even)
+        if (i + 3 < nk) load((i + 3) * kTk, s1);
+        __syncthreads();
+        compute(1);                                   // step i + 1
+        if (i + 2 < nk) stage(0, s0);                 // step i + 2
+        if (i + 4 < nk) load((i + 4) * kTk, s0);
         __syncthreads();
     }
 
