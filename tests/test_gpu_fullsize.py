@@ -151,3 +151,49 @@ def test_mixed_workload_full_size(orc):
     print(f"mixed: H H {st.n_products} products, 24 rows, {nb} blocks, err {err:.2e}; "
           f"sign {stats.iterations} iterations, trace(P) {stats.trace_p:.6f} "
           f"(n_occ {h.meta['n_occ']})")
+
+
+def test_submatrix_water_full_size_sampled_columns(orc):
+    """The submatrix method on the water-like workload (6192 sites x 6,
+    0.0334 sites/A^3, cutoff 6 A) with the benchmark's kernels and
+    Newton-Schulz tolerance 1e-8: 24 sampled block columns against the
+    oracle's eigendecomposition of those columns.  The stopping rule leaves
+    ||X - sign||_F <= n tol / 2 per submatrix (n <= 312), so a column of P is
+    within about 1e-6 absolute; the comparison is unfiltered.  With the
+    filter at 1e-6 every kept block is at least 1e-6 and every dropped one
+    below it in the unfiltered result."""
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(6192, 6, density=0.0334, cutoff=6.0, seed=0)
+    dh = to_dev(h)
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol = 0.0, 1e-8
+    st, ph, stats = bsm.bsm_submatrix_density(dh.handle, 0.0, o)
+    assert st == bsm.OK, bsm.bsm_last_error()
+    p = from_dev(bsm.Matrix(ph, h.row_blk_size, h.col_blk_size))
+    cols = np.sort(np.random.default_rng(11).choice(h.nbrows, 24, replace=False))
+    ref, rec = orc.submatrix_density(h, columns=cols)
+    # P's blocks in the sampled columns, in the oracle's (row-major) order
+    off = p.block_offsets()
+    rows = p.block_rows()
+    want = set(int(c) for c in cols)
+    got_vals = [p.values[off[t]:off[t + 1]] for t in range(p.nnzb) if int(p.col_idx[t]) in want]
+    got_keys = [(int(rows[t]), int(p.col_idx[t])) for t in range(p.nnzb) if int(p.col_idx[t]) in want]
+    ref_keys = list(zip(ref.block_rows().tolist(), ref.col_idx.tolist()))
+    assert got_keys == ref_keys
+    g = np.concatenate(got_vals)
+    err = np.abs(g - ref.values).max()
+    assert err <= 5e-6, err
+    assert stats.max_dim == 312 and stats.r_max < 1e-8
+    # the filtered run, checked by property against the unfiltered one
+    o.eps_filter = 1e-6
+    st2, ph2, _ = bsm.bsm_submatrix_density(dh.handle, 0.0, o)
+    assert st2 == bsm.OK
+    pf = from_dev(bsm.Matrix(ph2, h.row_blk_size, h.col_blk_size))
+    sq = np.array([float((p.values[off[t]:off[t + 1]] ** 2).sum()) for t in range(p.nnzb)])
+    kept = set(zip(pf.block_rows().tolist(), pf.col_idx.tolist()))
+    allk = list(zip(rows.tolist(), p.col_idx.tolist()))
+    for key, v in zip(allk, sq):
+        if abs(v - 1e-12) > 1e-18:          # the two sums of squares may round differently
+            assert (key in kept) == (v >= 1e-12), (key, v)
+    print(f"submatrix water: {stats.n_sub} submatrices, max {stats.max_dim}, 24 columns, "
+          f"max abs err {err:.2e}; filter keeps {pf.nnzb} of {p.nnzb} blocks")
