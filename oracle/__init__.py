@@ -20,6 +20,9 @@ Parity status of each function (what pins it, see ``tests/test_oracle.py``):
 * ``trace``, ``sqdist_identity``, ``inf_norm_shifted`` -- pinned against
                        ``numpy`` on the dense matrix.
 * ``add``           -- pinned: dense NumPy sum, pattern union, keep rule.
+* ``transpose``     -- pinned: the dense transpose (NumPy) on rectangular
+                       mixed-size cases with empty rows and columns; twice
+                       is the identity, bit for bit.
 * ``sign_ns`` orders 3, 5, 7 -- pinned: the printed polynomials (order 7:
                        derived in the test from its closed form) on diagonal
                        H, eigen-decomposition sign on tiny dense cases.
@@ -121,6 +124,7 @@ def _load():
                                                   C.c_int, C.c_double, P]
             lib.orc_add.argtypes = [C.c_double, P, C.c_double, P, C.c_double, C.c_double,
                                     C.c_int, P]
+            lib.orc_transpose.argtypes = [P, P]
             lib.orc_density_from_sign.argtypes = [P, P]
             lib.orc_tc2.argtypes = [P, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int32,
                                     P, C.POINTER(_Tc2Stats)]
@@ -242,6 +246,15 @@ def add(alpha: float, a: BSR, beta: float = 0.0, b: BSR | None = None, gamma: fl
     _check(lib.orc_add(alpha, C.byref(oa), beta, C.byref(ob) if ob is not None else None,
                        gamma, eps, _norm(norm), C.byref(out)), "add")
     return _out(out, a.row_blk_size, a.col_blk_size)
+
+
+def transpose(a: BSR) -> BSR:
+    """A^T: block (i, j) becomes block (j, i), transposed."""
+    lib = _load()
+    oa, ka = _in(a)
+    out = _OMat()
+    _check(lib.orc_transpose(C.byref(oa), C.byref(out)), "transpose")
+    return _out(out, a.col_blk_size, a.row_blk_size)
 
 
 def sign_ns(h: BSR, mu: float = 0.0, eps: float = 0.0, tol: float = 1e-6,

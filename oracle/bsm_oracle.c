@@ -420,6 +420,38 @@ int orc_shift_scale(const omat *a, double mu, double scale, omat *out)
 }
 
 /*
+ * B = A^T, the transpose among the DBCSR library's operations: block (i, j)
+ * of A (m x n, row-major) becomes block (j, i) of B, its n x m transpose.
+ * Rows of A are walked in ascending order, so every row of B receives its
+ * columns in ascending order.
+ */
+int orc_transpose(const omat *a, omat *out)
+{
+    for (int32_t i = 0; i < a->nbrows; ++i) if (a->rbs[i] < 1 || a->rbs[i] > 64) return ORC_EINVAL;
+    for (int32_t j = 0; j < a->nbcols; ++j) if (a->cbs[j] < 1 || a->cbs[j] > 64) return ORC_EINVAL;
+    int64_t *off = block_offsets(a);
+    rowbuf *rows = (rowbuf *)calloc((size_t)(a->nbcols ? a->nbcols : 1), sizeof(rowbuf));
+    double *tmp = (double *)malloc(sizeof(double) * 64 * 64);
+    if (!off || !rows || !tmp) { free(off); free(rows); free(tmp); return ORC_ENOMEM; }
+    int status = ORC_OK;
+    for (int32_t i = 0; i < a->nbrows && status == ORC_OK; ++i) {
+        const int32_t m = a->rbs[i];
+        for (int64_t t = a->row_ptr[i]; t < a->row_ptr[i + 1] && status == ORC_OK; ++t) {
+            const int32_t j = a->col_idx[t];
+            const int32_t n = a->cbs[j];
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < n; ++c) tmp[c * m + r] = a->values[off[t] + (int64_t)r * n + c];
+            status = rowbuf_push(&rows[j], i, tmp, (int64_t)m * n);
+        }
+    }
+    if (status == ORC_OK)
+        status = assemble(out, a->nbcols, a->nbrows, a->cbs, a->rbs, rows);
+    free_rows(rows, a->nbcols);
+    free(off); free(tmp);
+    return status;
+}
+
+/*
  * C = alpha * A + beta * B + gamma * I, then the norm filter: the matrix sum
  * of the DBCSR operations (DBCSR section lists multiply, sum, trace and
  * transpose).  Stored pattern = pattern(A) union pattern(B), plus the diagonal

@@ -732,6 +732,22 @@ def test_tc2_matches_sign_density_on_neighbour_hamiltonian(orc):
     assert st["trace_p"] == pytest.approx(h.meta["n_occ"], abs=1e-5)
 
 
+# ---------------------------------------------------------------- transpose
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_transpose_is_the_dense_transpose(orc, seed):
+    rng = np.random.default_rng(300 + seed)
+    nbr, nbc = int(rng.integers(1, 9)), int(rng.integers(1, 9))
+    a = synth.random_bsr(nbr, nbc, rng.integers(1, 33, nbr), rng.integers(1, 33, nbc), 0.4, rng)
+    t = orc.transpose(a)
+    t.check()
+    assert np.array_equal(t.row_blk_size, a.col_blk_size)
+    assert np.array_equal(t.to_dense(), a.to_dense().T)
+    back = orc.transpose(t)
+    for f in ("row_ptr", "col_idx", "values"):
+        assert np.array_equal(getattr(back, f), getattr(a, f))
+
+
 # ------------------------------------ trace-resetting purification (TRS4)
 
 def _trs4_diag_case(seed, nocc_frac):

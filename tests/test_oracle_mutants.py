@@ -63,6 +63,8 @@ MUTANTS = [
     ("trs4_gamma_sign", "(n_occ - tf) / tg", "(tf - n_occ) / tg"),
     ("trs4_upper_branch", "if (gamma > 6.0) {", "if (gamma > 2.0) {"),
     ("trs4_no_g", "tg > 0.0 ? (n_occ - tf) / tg : 0.0", "tg > 0.0 ? (n_occ - tf) / tg : 7.0"),
+    ("transpose_block", "tmp[c * m + r] = a->values[off[t] + (int64_t)r * n + c];",
+     "tmp[r * n + c] = a->values[off[t] + (int64_t)r * n + c];"),
     ("trace_p", "st->trace_p = 0.5 * (n - st->trace_x);", "st->trace_p = 0.5 * (n + st->trace_x);"),
     ("skip_last_k", "for (int64_t ta = a->row_ptr[i]; ta < a->row_ptr[i + 1]; ++ta) {\n                    int32_t k",
      "for (int64_t ta = a->row_ptr[i]; ta + 1 < a->row_ptr[i + 1]; ++ta) {\n                    int32_t k"),
