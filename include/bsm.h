@@ -402,6 +402,16 @@ int bsm_trs4(bsm_matrix H, double n_occ, const bsm_sign_opts *opts, bsm_matrix *
 int bsm_submatrix_density(bsm_matrix H, double mu, const bsm_sign_opts *opts, bsm_matrix *p_out,
                           bsm_sub_stats *stats, void *stream);
 
+/*
+ * B = A^T as a new handle (caller destroys): transpose, one of the
+ * operations of the DBCSR library section.  Block (i, j) of A (m x n,
+ * row-major) becomes block (j, i) of B (its n x m transpose); B's block
+ * rows have A's column sizes and its block columns A's row sizes; columns
+ * ascending in every row.  Any shape, including empty.  BSM_EINVAL for a
+ * NULL argument.
+ */
+int bsm_transpose(bsm_matrix A, bsm_matrix *out, void *stream);
+
 /* P = (I - X)/2 from a sign matrix X, as a new handle; trace_p (may be NULL) gets trace(P). */
 int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void *stream);
 

@@ -128,6 +128,7 @@ _SIGS = [
                           C.POINTER(C.c_void_p), C.POINTER(bsm_tc2_stats), C.c_void_p]),
     ("bsm_trs4", C.c_int, [C.c_void_p, C.c_double, C.POINTER(bsm_sign_opts),
                            C.POINTER(C.c_void_p), C.POINTER(bsm_tc2_stats), C.c_void_p]),
+    ("bsm_transpose", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p]),
     ("bsm_submatrix_density", C.c_int, [C.c_void_p, C.c_double, C.POINTER(bsm_sign_opts),
                                         C.POINTER(C.c_void_p), C.POINTER(bsm_sub_stats),
                                         C.c_void_p]),
@@ -347,6 +348,13 @@ def bsm_tc2(h, n_occ, opts: bsm_sign_opts | None = None, stream=None):
 def bsm_trs4(h, n_occ, opts: bsm_sign_opts | None = None, stream=None):
     """TRS4 purification; returns (status, P handle or None, stats) as bsm_tc2."""
     return _purify("bsm_trs4", h, n_occ, opts, stream)
+
+
+def bsm_transpose(a, stream=None) -> int:
+    """A^T as a new handle."""
+    out = C.c_void_p()
+    _check(load().bsm_transpose(a, C.byref(out), _stream(stream)), "bsm_transpose")
+    return out.value
 
 
 def bsm_submatrix_density(h, mu=0.0, opts: bsm_sign_opts | None = None, stream=None):

@@ -426,6 +426,16 @@ int bsm_submatrix_density(bsm_matrix H, double mu, const bsm_sign_opts *opts, bs
     return rc;
 }
 
+int bsm_transpose(bsm_matrix A, bsm_matrix *out, void *stream) {
+    bsm::clear_error();
+    if (!A || !out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    *out = nullptr;
+    Mat *m = nullptr;
+    BSM_TRY(bsm::transpose_mat(A->m, &m, as_stream(stream)));
+    *out = wrap(m);
+    return BSM_OK;
+}
+
 int bsm_density_from_sign(bsm_matrix X, bsm_matrix *p_out, double *trace_p, void *stream) {
     bsm::clear_error();
     if (!X || !p_out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }

@@ -107,7 +107,14 @@ int copy_mat(const Mat &a, Mat **out, hipStream_t s);
 // C = alpha A + beta B + gamma I (b may be NULL), filtered, as a new matrix (add.hip).
 int add_mat(double alpha, const Mat &a, double beta, const Mat *b, double gamma, double eps,
             int norm, Mat **out, hipStream_t s);
+// A matrix without a pattern whose block rows have the sizes of proto_rows'
+// rows and whose block columns those of proto_cols' columns.
 int alloc_like_sizes(const Mat &proto_rows, const Mat &proto_cols, Mat **out, hipStream_t s);
+// The same with either side taken transposed: rows from r's columns
+// (r_cols), columns from c's rows (c_rows).
+int new_mat_sizes(const Mat &r, bool r_cols, const Mat &c, bool c_rows, Mat **out, hipStream_t s);
+// B = A^T as a new matrix (transpose.hip).
+int transpose_mat(const Mat &a, Mat **out, hipStream_t s);
 
 // Compaction after the filter (reduce.hip).  keep (may be NULL): instead of
 // freeing them, hand over the keep scan kidx[n+1], the kept-value offsets

@@ -388,21 +388,32 @@ k_shift_scale_vals(const int64_t *new_row_ptr, const int32_t *new_col, const int
     }
 }
 
-static int new_mat_like(const Mat &a, Mat **out, hipStream_t s) {
+int new_mat_sizes(const Mat &r, bool r_cols, const Mat &c, bool c_rows, Mat **out, hipStream_t s) {
     Mat *m = new Mat;
-    m->device = a.device;
-    m->nbrows = a.nbrows; m->nbcols = a.nbcols; m->nrows = a.nrows; m->ncols = a.ncols;
-    m->h_rbs = a.h_rbs; m->h_cbs = a.h_cbs;
-    m->max_rbs = a.max_rbs; m->max_cbs = a.max_cbs; m->uni_r = a.uni_r; m->uni_c = a.uni_c;
-    int st = dalloc(&m->rbs, a.nbrows, s);
-    if (st == BSM_OK) st = dalloc(&m->cbs, a.nbcols, s);
-    if (st == BSM_OK) st = dalloc(&m->roff, a.nbrows + 1, s);
-    if (st == BSM_OK) st = dalloc(&m->coff, a.nbcols + 1, s);
+    m->device = r.device;
+    m->nbrows = r_cols ? r.nbcols : r.nbrows;
+    m->nrows = r_cols ? r.ncols : r.nrows;
+    m->h_rbs = r_cols ? r.h_cbs : r.h_rbs;
+    m->max_rbs = r_cols ? r.max_cbs : r.max_rbs;
+    m->uni_r = r_cols ? r.uni_c : r.uni_r;
+    m->nbcols = c_rows ? c.nbrows : c.nbcols;
+    m->ncols = c_rows ? c.nrows : c.ncols;
+    m->h_cbs = c_rows ? c.h_rbs : c.h_cbs;
+    m->max_cbs = c_rows ? c.max_rbs : c.max_cbs;
+    m->uni_c = c_rows ? c.uni_r : c.uni_c;
+    const int32_t *rsz = r_cols ? r.cbs : r.rbs;
+    const int64_t *rof = r_cols ? r.coff : r.roff;
+    const int32_t *csz = c_rows ? c.rbs : c.cbs;
+    const int64_t *cof = c_rows ? c.roff : c.coff;
+    int st = dalloc(&m->rbs, m->nbrows, s);
+    if (st == BSM_OK) st = dalloc(&m->cbs, m->nbcols, s);
+    if (st == BSM_OK) st = dalloc(&m->roff, m->nbrows + 1, s);
+    if (st == BSM_OK) st = dalloc(&m->coff, m->nbcols + 1, s);
     if (st == BSM_OK) {
-        hipError_t e = hipMemcpyAsync(m->rbs, a.rbs, sizeof(int32_t) * a.nbrows, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(m->cbs, a.cbs, sizeof(int32_t) * a.nbcols, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(m->roff, a.roff, sizeof(int64_t) * (a.nbrows + 1), hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(m->coff, a.coff, sizeof(int64_t) * (a.nbcols + 1), hipMemcpyDeviceToDevice, s);
+        hipError_t e = hipMemcpyAsync(m->rbs, rsz, sizeof(int32_t) * m->nbrows, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(m->cbs, csz, sizeof(int32_t) * m->nbcols, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(m->roff, rof, sizeof(int64_t) * (m->nbrows + 1), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(m->coff, cof, sizeof(int64_t) * (m->nbcols + 1), hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) { set_error("copy of block sizes failed: %s", hipGetErrorString(e)); st = BSM_EDEVICE; }
     }
     if (st != BSM_OK) { free_mat(m, s); return st; }
@@ -411,9 +422,12 @@ static int new_mat_like(const Mat &a, Mat **out, hipStream_t s) {
     return BSM_OK;
 }
 
+static int new_mat_like(const Mat &a, Mat **out, hipStream_t s) {
+    return new_mat_sizes(a, false, a, false, out, s);
+}
+
 int alloc_like_sizes(const Mat &rows, const Mat &cols, Mat **out, hipStream_t s) {
-    (void)cols;
-    return new_mat_like(rows, out, s);
+    return new_mat_sizes(rows, false, cols, false, out, s);
 }
 
 int shift_scale(const Mat &a, double mu, double scale, Mat **out, hipStream_t s) {

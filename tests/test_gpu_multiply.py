@@ -339,3 +339,37 @@ def test_smm_bench_entry_point():
         bsm.bsm_smm_bench(7, 5, 5, 10, 4, [(2, 1, 1)], reps=1)   # no class kernel for 7
     with pytest.raises(bsm.BsmError):
         bsm.bsm_set_smm_table([((5, 5, 5), (4, 1, 1))])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_transpose_vs_oracle(orc, seed):
+    """A^T on the GPU against the oracle, bit for bit (data movement only):
+    rectangular, mixed block sizes up to 32, empty rows and columns; twice
+    gives A back."""
+    from paper_2003_03868_amd import bsm
+    rng = np.random.default_rng(900 + seed)
+    nbr, nbc = int(rng.integers(1, 40)), int(rng.integers(1, 40))
+    a = synth.random_bsr(nbr, nbc, rng.integers(1, 33, nbr), rng.integers(1, 33, nbc),
+                         [0.0, 0.05, 0.3, 0.9][seed], rng)
+    ref = orc.transpose(a)
+    da = to_dev(a)
+    th = bsm.bsm_transpose(da.handle)
+    t = bsm.Matrix(th, a.col_blk_size, a.row_blk_size)
+    got = from_dev(t)
+    for f in ("row_ptr", "col_idx", "values"):
+        assert np.array_equal(getattr(got, f), getattr(ref, f)), f
+    bh = bsm.bsm_transpose(t.handle)
+    back = from_dev(bsm.Matrix(bh, a.row_blk_size, a.col_blk_size))
+    for f in ("row_ptr", "col_idx", "values"):
+        assert np.array_equal(getattr(back, f), getattr(a, f)), f
+
+
+def test_transpose_of_the_full_sign_hamiltonian_is_itself(orc):
+    """H of the sign workload is symmetric: H^T == H bit for bit at full size
+    (2048 sites x 23, 187,560 blocks)."""
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(2048, 23, density=0.1, cutoff=6.0, seed=0)
+    dh = to_dev(h)
+    t = from_dev(bsm.Matrix(bsm.bsm_transpose(dh.handle), h.col_blk_size, h.row_blk_size))
+    for f in ("row_ptr", "col_idx", "values"):
+        assert np.array_equal(getattr(t, f), getattr(h, f)), f
