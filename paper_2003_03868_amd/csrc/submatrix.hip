@@ -367,6 +367,7 @@ int submatrix_density(Mat &H, double mu, const bsm_sign_opts &o, Mat **p_out, bs
 
     const size_t cap = batch_bytes_cap();
     std::vector<std::pair<hipEvent_t, hipEvent_t>> gev;
+    int64_t n_noconv = 0;            // submatrices left above tol (every batch still runs)
     int j0 = 0;
     while (rc == BSM_OK && j0 < nb) {
         // the batch: consecutive block columns while three padded squares fit
@@ -550,8 +551,7 @@ int submatrix_density(Mat &H, double mu, const bsm_sign_opts &o, Mat **p_out, bs
             if (rc != BSM_OK) break;
             if (next.empty()) { active.clear(); break; }
             if (k >= o.max_iter) {
-                set_error("submatrix: %zu submatrices above tol after max_iter", next.size());
-                rc = BSM_ENOCONV;
+                n_noconv += static_cast<int64_t>(next.size());   // keep their last iterates
                 break;
             }
             // X' = 1.5 X - 0.5 X Y for those not yet converged (their tiles
@@ -586,7 +586,7 @@ int submatrix_density(Mat &H, double mu, const bsm_sign_opts &o, Mat **p_out, bs
             }
             active.swap(next);
         }
-        if (rc == BSM_OK || rc == BSM_ENOCONV) {
+        if (rc == BSM_OK) {
             for (int q = 0; q < ns; ++q) {
                 st->max_iterations = std::max(st->max_iterations, iters[q]);
                 st->r_max = std::max(st->r_max, rfin[q]);
@@ -600,13 +600,17 @@ int submatrix_density(Mat &H, double mu, const bsm_sign_opts &o, Mat **p_out, bs
             if (r2 != BSM_OK) rc = r2;
         }
         release();
-        if (rc != BSM_OK && rc != BSM_ENOCONV) break;
-        if (rc == BSM_ENOCONV) break;
+        if (rc != BSM_OK) break;
         j0 = j1;
     }
-    if (rc == BSM_OK || rc == BSM_ENOCONV) {
+    if (rc == BSM_OK) {
         const int r2 = filter_inplace(*P, o.eps_filter, o.norm, s);
         if (r2 != BSM_OK) rc = r2;
+    }
+    if (rc == BSM_OK && n_noconv > 0) {
+        set_error("submatrix: %lld submatrices above tol after max_iter",
+                  static_cast<long long>(n_noconv));
+        rc = BSM_ENOCONV;
     }
     (void)hipEventRecord(t1, s);
     (void)hipEventSynchronize(t1);

@@ -124,3 +124,17 @@ def test_submatrix_failure_modes():
             from paper_2003_03868_amd import bsm as b
             d = to_dev(h)
             b.bsm_submatrix_density(d.handle, v, _opts())
+
+
+def test_submatrix_no_convergence_assembles_every_batch(monkeypatch):
+    """Too few iterations: ENOCONV, and the last iterates of every batch are
+    assembled (the many-batch result equals the one-batch result bit for
+    bit)."""
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(100, 5, cutoff=4.5, seed=4)
+    st, p, stats = _run(h, max_iter=2)
+    assert st == bsm.ENOCONV and p is not None and stats.n_batches == 1
+    monkeypatch.setenv("BSM_SUB_BATCH_BYTES", str(7 * 3 * 8 * 320 * 320))
+    st2, p2, stats2 = _run(h, max_iter=2)
+    assert st2 == bsm.ENOCONV and stats2.n_batches > 5
+    assert np.array_equal(from_dev(p).values, from_dev(p2).values)
