@@ -119,24 +119,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         }
     };
 
-    // k steps of kTk: nk = ld / kTk is a multiple of 4.  Set s0 carries steps
-    // 0, 2, 4, ..., set s1 steps 1, 3, 5, ...; buffer i & 1 holds step i.
-    const int nk = ld / kTk;
+    // k steps of kTk up to the edge rounded to kTk (the padding beyond it is
+    // zero, so the remaining steps would add nothing): nk >= 1.  Set s0
+    // carries steps 0, 2, 4, ..., set s1 steps 1, 3, 5, ...; buffer i & 1
+    // holds step i.
+    const int nk = (g.ndim[sub] + kTk - 1) / kTk;
     Regs s0, s1;
     load(0, s0);
     stage(0, s0);
-    load(kTk, s1);
-    load(2 * kTk, s0);
+    if (nk > 1) load(kTk, s1);
+    if (nk > 2) load(2 * kTk, s0);
     __syncthreads();
     for (int i = 0; i < nk; i += 2) {
         compute(0);                                   // step i
-        stage(1, s1);                                 // step i + 1 (exists: nk even)
+        if (i + 1 < nk) stage(1, s1);                 // step i + 1
         if (i + 3 < nk) load((i + 3) * kTk, s1);
         __syncthreads();
-        compute(1);                                   // step i + 1
-        if (i + 2 < nk) stage(0, s0);                 // step i + 2
-        if (i + 4 < nk) load((i + 4) * kTk, s0);
-        __syncthreads();
+        if (i + 1 < nk) {
+            compute(1);                               // step i + 1
+            if (i + 2 < nk) stage(0, s0);             // step i + 2
+            if (i + 4 < nk) load((i + 4) * kTk, s0);
+            __syncthreads();
+        }
     }
 
     const int n = g.ndim[sub];
