@@ -13,9 +13,10 @@
 //   k = 0, 1, ...:  Y = X_k X_k;  r_k = ||Y - I||_F / n_j;  stop if r_k < tol
 //                   X_{k+1} = 1.5 X_k - 0.5 X_k Y
 // with every submatrix of a batch advanced together and each stopped on its
-// own residual.  Submatrices live densely in HBM, padded to multiples of 64
+// own residual.  Submatrices live densely in HBM, padded to multiples of 32
 // (the padding stays zero through both products); the products run on the
-// FP64 matrix cores in one launch over the tiles of all active submatrices.
+// FP64 matrix cores in one launch over the 64 x 64 tiles of all active
+// submatrices, the last tile row and column 32 wide where the edge ends there.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -29,6 +30,7 @@ namespace bsm {
 namespace {
 
 constexpr int kTile = 64;      // output tile edge of the dense product
+constexpr int kPad = 32;       // submatrix edges are padded to a multiple of this
 constexpr int kTk = 16;        // k depth staged per LDS stage
 constexpr int kLdA = 68;       // LDS row pitch (doubles) of the k-major A stage
 constexpr int kLdB = 80;       // LDS row pitch (doubles) of the B stage
@@ -37,7 +39,7 @@ struct SubGemm {
     const int4 *tiles;         // (submatrix, tile row, tile column, buffer of X)
     int32_t ntiles;
     const int64_t *base;       // per submatrix: offset (doubles) in every buffer
-    const int32_t *npad;       // per submatrix: padded edge (multiple of 64)
+    const int32_t *npad;       // per submatrix: padded edge (multiple of 32)
     const int32_t *ndim;       // per submatrix: true edge n_j
     double *buf0, *buf1, *ybuf;
     int32_t mode;              // 0: Y = X X (+ residual partials); 1: X' = 1.5 X - 0.5 X Y
@@ -50,6 +52,10 @@ struct SubGemm {
 // (x, b, y) = lane / 16, lane / 4 % 4, lane % 4 feeds A(i = y, k = x) and
 // B(k = x, j = y) of block b and receives D(i = x, j = y).  A is staged
 // k-major so the eight A operands of a k step are conflict-free LDS reads.
+// A tile that reaches past the padded edge is 32 rows or columns wide: the
+// waves of its missing half skip their products and stores, and the
+// staging loads of that half are clamped to addresses inside the square
+// (data that only those idle waves would read).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sub_gemm(SubGemm g) {
     // consecutive tiles (one submatrix) on one XCD: workgroups b, b+8, ...
     // share an XCD's L2
@@ -64,6 +70,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const double *Bm = g.mode == 0 ? X : g.ybuf + base;
     double *D = g.mode == 0 ? g.ybuf + base : (td.w ? g.buf0 : g.buf1) + base;
     const int r0 = td.y * kTile, c0 = td.z * kTile;
+    const int vr = min(kTile, ld - r0), vc = min(kTile, ld - c0);   // 32 or 64
 
     __shared__ double As[2][kTk][kLdA];
     __shared__ double Bs[2][kTk][kLdB];
@@ -80,8 +87,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     // 256-byte runs per row
     const int ar = t >> 2, ak = (t & 3) << 2;
     const int bk = t >> 4, bc = (t & 15) << 1;
-    const double *ga = X + static_cast<int64_t>(r0 + ar) * ld + ak;
+    const double *ga = X + static_cast<int64_t>(r0 + (ar < vr ? ar : 0)) * ld + ak;
     const double *gb = Bm + static_cast<int64_t>(bk) * ld + c0 + bc;
+    const int bhi = vc > 32 ? 32 : 0;                  // second column half, or a repeat
+    const bool busy = wr < vr && wc < vc;              // wave-uniform
 
     // two register sets of staged operands in flight: the loads for k step
     // i + 3 are issued at step i and written to LDS at step i + 2
@@ -91,7 +100,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const double *bp = gb + static_cast<int64_t>(k) * ld;
         r.a0 = a2[0]; r.a1 = a2[1];
         r.b0 = *reinterpret_cast<const double2 *>(bp);
-        r.b1 = *reinterpret_cast<const double2 *>(bp + 32);
+        r.b1 = *reinterpret_cast<const double2 *>(bp + bhi);
     };
     auto stage = [&](int buf, const Regs &r) {
         As[buf][ak + 0][ar] = r.a0.x; As[buf][ak + 1][ar] = r.a0.y;
@@ -104,6 +113,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
     for (int R = 0; R < 8; ++R) { acc[R][0] = 0.0; acc[R][1] = 0.0; }
     auto compute = [&](int cur) {
+        if (!busy) return;
 #pragma unroll
         for (int kk = 0; kk < kTk; kk += 4) {
             double a[8], b[2];
@@ -146,7 +156,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const int n = g.ndim[sub];
     double res = 0.0;
 #pragma unroll
-    for (int R = 0; R < 8; ++R) {
+    for (int R = 0; R < 8 && busy; ++R) {
         const int r = r0 + wr + 4 * R + x;
 #pragma unroll
         for (int G = 0; G < 2; ++G) {
@@ -351,7 +361,7 @@ int submatrix_density(Mat &H, double mu, const bsm_sign_opts &o, Mat **p_out, bs
             return BSM_EINVAL;
         }
         dim[j] = static_cast<int32_t>(n);
-        pad[j] = static_cast<int32_t>((n + kTile - 1) / kTile * kTile);
+        pad[j] = static_cast<int32_t>((n + kPad - 1) / kPad * kPad);
     }
 
     hipEvent_t t0, t1;
@@ -487,7 +497,7 @@ int submatrix_density(Mat &H, double mu, const bsm_sign_opts &o, Mat **p_out, bs
             std::vector<int4> tiles;
             std::vector<int32_t> tlo, thi;
             for (int q : active) {
-                const int nt = npad[q] / kTile;
+                const int nt = (npad[q] + kTile - 1) / kTile;
                 tlo.push_back(static_cast<int32_t>(tiles.size()));
                 for (int a = 0; a < nt; ++a)
                     for (int b = 0; b < nt; ++b) tiles.push_back(make_int4(q, a, b, parity[q]));
@@ -563,7 +573,7 @@ int submatrix_density(Mat &H, double mu, const bsm_sign_opts &o, Mat **p_out, bs
             if (next.size() != active.size()) {
                 tiles.clear();
                 for (int q : next) {
-                    const int nt = npad[q] / kTile;
+                    const int nt = (npad[q] + kTile - 1) / kTile;
                     for (int a = 0; a < nt; ++a)
                         for (int b = 0; b < nt; ++b) tiles.push_back(make_int4(q, a, b, parity[q]));
                 }
