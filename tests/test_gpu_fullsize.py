@@ -197,3 +197,29 @@ def test_submatrix_water_full_size_sampled_columns(orc):
             assert (key in kept) == (v >= 1e-12), (key, v)
     print(f"submatrix water: {stats.n_sub} submatrices, max {stats.max_dim}, 24 columns, "
           f"max abs err {err:.2e}; filter keeps {pf.nnzb} of {p.nnzb} blocks")
+
+
+def test_trs4_full_size_invariants(h23):
+    """TRS4 purification on the sign workload (2048 sites x 23, eps 1e-6,
+    tol 1e-6): converges, trace(P) within 1e-3 of the occupied count, P
+    idempotent to ||P^2 - P||_F / n < 1e-7 (P^2 filtered like every
+    product), three multiplies per update plus the last square."""
+    import math
+    from paper_2003_03868_amd import bsm
+    dh = to_dev(h23)
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol = EPS, 1e-6
+    st, ph, stats = bsm.bsm_trs4(dh.handle, h23.meta["n_occ"], o)
+    assert st == bsm.OK, bsm.bsm_last_error()
+    k = stats.iterations
+    assert abs(stats.trace_p - h23.meta["n_occ"]) < 1e-3
+    assert stats.n_multiplies == 3 * k + 1
+    p = bsm.Matrix(ph, h23.row_blk_size, h23.col_blk_size)
+    p2 = bsm.Matrix.empty_like(h23.row_blk_size, h23.col_blk_size)
+    bsm.bsm_multiply(1.0, p.handle, p.handle, 0.0, p2.handle, EPS, bsm.NORM_FROB)
+    d = bsm.bsm_add(1.0, p2.handle, -1.0, p.handle)
+    idem = math.sqrt(bsm.bsm_sqdist_identity(d, 0.0)) / h23.shape[0]
+    bsm.bsm_destroy(d)
+    assert idem < 1e-7
+    print(f"trs4: {k} updates, branches {list(stats.branch[:k])}, trace(P) {stats.trace_p:.6f}, "
+          f"||P^2-P||_F/n {idem:.2e}")
