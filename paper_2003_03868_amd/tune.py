@@ -10,9 +10,10 @@ the (m, n, k) it did not tune; "Batched execution" subsection).
   library's tuning table (``bsm_set_smm_table``).
 * ``train``: a 3-layer, width-64 FP32 MLP maps features of a point to the
   predicted log-time of every catalogue entry; its choice is the arg-min.
-  It is trained on 80% of the (m, n, k) triples and judged on the held-out
-  20% by its regret t(predicted) / t(best) - 1; exhaustive tuning is both the
-  fallback for shapes the model is not trusted on and the judge.
+  It is trained on 80% of the (m, n, k) triples and evaluated on the
+  held-out 20% by its regret t(predicted) / t(best) - 1; exhaustive tuning is
+  both the fallback for shapes the model is not trusted on and the reference
+  the regret is measured against.
 
 Usage (GPU for sweep, CPU for train):
     python -m paper_2003_03868_amd.tune sweep --grid 4:32 --out sweep.jsonl
