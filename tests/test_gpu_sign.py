@@ -273,3 +273,41 @@ def test_trs4_out_of_range_updates_vs_oracle(orc, frac):
     assert list(stats.branch[:4]) == st_ref["branch"] and st_ref["branch"][0] in (0, 1)
     p = bsm.Matrix(ph, h.row_blk_size, h.col_blk_size)
     assert_same_matrix(from_dev(p), p_ref, TOL_FP64, "TRS4 X_4")
+
+
+@pytest.mark.parametrize("full", [False, True], ids=["none", "all"])
+def test_degenerate_occupations(full):
+    """The degenerate ends of every density-matrix route: mu above (below)
+    the whole spectrum, or N = n (N = 0), gives P = I (P = 0).  With a
+    filter, P = 0 keeps no block and P = I only the diagonal blocks."""
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(64, 5, cutoff=4.0, seed=2)
+    n = h.shape[0]
+    d = to_dev(h)
+    s_inf = float(np.abs(h.to_dense()).sum(1).max())
+    mu = 2.0 * s_inf if full else -2.0 * s_inf
+    nocc = n if full else 0
+    eye = np.eye(n) if full else np.zeros((n, n))
+    o = bsm.bsm_sign_opts_default()
+    o.eps_filter, o.tol = 1e-9, 1e-10
+
+    def check(ph, what):
+        p = from_dev(bsm.Matrix(ph, h.row_blk_size, h.col_blk_size))
+        assert np.abs(p.to_dense() - eye).max() < 1e-9, what
+        assert p.nnzb == (h.nbrows if full else 0), what
+
+    st, xh, stats = bsm.bsm_sign_iterate(d.handle, mu, o)
+    assert st == bsm.OK, bsm.bsm_last_error()
+    ph, tp = bsm.bsm_density_from_sign(xh)
+    bsm.bsm_destroy(xh)
+    assert tp == pytest.approx(nocc, abs=1e-9)
+    p = from_dev(bsm.Matrix(ph, h.row_blk_size, h.col_blk_size))
+    assert np.abs(p.to_dense() - eye).max() < 1e-9
+    st, ph, _ = bsm.bsm_submatrix_density(d.handle, mu, o)
+    assert st == bsm.OK, bsm.bsm_last_error()
+    check(ph, "submatrix")
+    for fn in (bsm.bsm_tc2, bsm.bsm_trs4):
+        st, ph, stats = fn(d.handle, nocc, o)
+        assert st == bsm.OK, bsm.bsm_last_error()
+        assert stats.trace_p == pytest.approx(nocc, abs=1e-9)
+        check(ph, fn.__name__)
