@@ -29,36 +29,56 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 matrix (= FP64 vector) peak
 PEAK_HBM_GBS = 8000.0
+# dense matrix-core peaks of MI355X by the operand type of the block products
+PEAK_TFLOPS = {"fp64": PEAK_FP64_TFLOPS, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "split-bf16", "bf16x3": "split-bf16x3"}
 
 
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(h, rows: int):
+def cpu_baseline(h, rows: int, step_flops: float = 0.0, rows_1t: int = 96):
     """Oracle multiply of the first `rows` block rows of H by H (the first
-    product of the sign iteration), timed on the host cores."""
+    product of the sign iteration), timed on the host cores; the same with
+    one thread on the first `rows_1t` rows; and the oracle's time to the
+    converged sign extrapolated from the measured rate and the step's flops."""
     import numpy as np
 
     import oracle
     from synth import BSR
-    nnz = int(h.row_ptr[rows])
-    off = h.block_offsets()
-    sub = BSR(h.row_blk_size[:rows], h.col_blk_size, h.row_ptr[:rows + 1].copy(),
-              h.col_idx[:nnz].copy(), h.values[:off[nnz]].copy())
-    # algorithmic flops of the sample
-    rp, ci = h.row_ptr, h.col_idx
-    lens = np.diff(rp)
-    b = int(h.row_blk_size[0])
-    nprod = int(lens[ci[:nnz]].sum())
-    flops = 2.0 * b ** 3 * nprod
-    t0 = time.perf_counter()
-    oracle.multiply(1.0, sub, h, eps=1e-6)
-    dt = time.perf_counter() - t0
-    return dict(value=flops / dt / 1e9, unit="GFLOP/s", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"first {rows} of {h.nbrows} block rows of H*H (the first product of "
-                       f"the iteration), eps 1e-6, {flops / 1e9:.1f} GFLOP in {dt:.1f} s")
+
+    def sample(nrows):
+        nnz = int(h.row_ptr[nrows])
+        off = h.block_offsets()
+        sub = BSR(h.row_blk_size[:nrows], h.col_blk_size, h.row_ptr[:nrows + 1].copy(),
+                  h.col_idx[:nnz].copy(), h.values[:off[nnz]].copy())
+        lens = np.diff(h.row_ptr)
+        b = int(h.row_blk_size[0])
+        flops = 2.0 * b ** 3 * int(lens[h.col_idx[:nnz]].sum())
+        t0 = time.perf_counter()
+        oracle.multiply(1.0, sub, h, eps=1e-6)
+        return flops, time.perf_counter() - t0
+
+    threads = oracle.num_threads()
+    flops, dt = sample(rows)
+    rate = flops / dt
+    oracle.set_threads(1)
+    try:
+        f1, d1 = sample(min(rows_1t, rows))
+    finally:
+        oracle.set_threads(threads)
+    out = dict(value=rate / 1e9, unit="GFLOP/s", cores=threads, kind="oracle",
+               sample=f"first {rows} of {h.nbrows} block rows of H*H (the first product of "
+                      f"the iteration), eps 1e-6, {flops / 1e9:.1f} GFLOP in {dt:.1f} s; "
+                      f"1 thread: first {min(rows_1t, rows)} rows, {f1 / 1e9:.1f} GFLOP in "
+                      f"{d1:.1f} s",
+               value_1thread=f1 / d1 / 1e9)
+    if step_flops > 0.0:
+        out["time_to_sign_s_extrapolated"] = step_flops / rate
+        out["time_to_sign_note"] = ("the step's algorithmic flops at the sampled oracle rate "
+                                    "(extrapolated, not run)")
+    return out
 
 
 KERNEL_SOURCES = ["smm.h", "smm_quad.hip", "quad.hip", "multiply.hip"]
@@ -392,9 +412,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16"], default="fp64",
-                    help="block-product precision (fp32 / split-bf16 switch to FP64 once "
-                         "r_k < 1e-4)")
+    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16", "bf16x3"], default="fp64",
+                    help="block-product precision: fp32, split-bf16 with two (bf16) or three "
+                         "(bf16x3) parts per operand; all switch to FP64 once r_k < 1e-4")
     ap.add_argument("--table", choices=["exhaustive", "mlp", "none"], default="exhaustive",
                     help="kernel-parameter table: measured (exhaustive autotuning), predicted "
                          "by the MLP, or none (built-in choices)")
@@ -486,7 +506,8 @@ def main():
     opts = bsm.bsm_sign_opts_default()
     opts.eps_filter = args.eps
     opts.tol = args.tol
-    opts.prec = {"fp64": bsm.FP64, "fp32": bsm.FP32, "bf16": bsm.SPLIT_BF16}[args.prec]
+    opts.prec = {"fp64": bsm.FP64, "fp32": bsm.FP32, "bf16": bsm.SPLIT_BF16,
+                 "bf16x3": bsm.SPLIT_BF16X3}[args.prec]
     opts.use_graph = args.graph
     opts.order = args.order
     opts.eps_screen = args.screen
@@ -557,6 +578,9 @@ def main():
         o64.prec = bsm.FP64
         o64.eps_screen = 0.0
         st_64, x64, s64 = bsm.bsm_sign_iterate(dh.handle, 0.0, o64, stream=stream)
+        if st_64 != bsm.OK:
+            raise RuntimeError(f"FP64 reference sign iteration failed: {bsm.STATUS_NAMES[st_64]} "
+                               f"{bsm.bsm_last_error()}")
         d = bsm.bsm_add(1.0, xp, -1.0, x64, stream=stream)
         num = bsm.bsm_sqdist_identity(d, 0.0, stream=stream)
         den = bsm.bsm_sqdist_identity(x64, 0.0, stream=stream)
@@ -572,7 +596,8 @@ def main():
     cpu = None
     if not args.no_cpu and args.workload == "sign23":
         log("timing the CPU oracle on a sample ...")
-        cpu = cpu_baseline(h, min(args.cpu_rows, h.nbrows))
+        cpu = cpu_baseline(h, min(args.cpu_rows, h.nbrows),
+                           step_flops=sum(s.flops for s, _ in all_stats) / args.steps)
         log(f"cpu baseline: {cpu['value']:.2f} GFLOP/s on {cpu['cores']} threads")
 
     n = float(h.shape[0])
@@ -587,7 +612,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": DTYPE[args.prec],
         "data": "synthetic",
         "config": {
             "workload": (f"{args.prec.upper()} {'Newton-Schulz' if args.order == 2 else f'order-{args.order}'} sign iteration, {h.nbrows}-site "
@@ -623,11 +648,12 @@ def main():
                        else "k_smm_f64_quad<23,2,2,4,6,1>" if args.workload == "sign23"
                        else "k_smm_f64_quad<6,2,2,1,8,1>" if args.workload == "water"
                        else "k_smm_f64_class")
-            if args.prec == "fp64" else "k_smm_lowp",
+            if args.prec == "fp64" else "k_smm_f32<23,23,23>" if args.prec == "fp32"
+            else f"k_lowp_quad<23,{ {'bf16': 2, 'bf16x3': 3}[args.prec] }>",
             "achieved": achieved,
-            "peak": PEAK_FP64_TFLOPS,
+            "peak": PEAK_TFLOPS[args.prec],
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS,
+            "frac": achieved / PEAK_TFLOPS[args.prec],
             "traffic": measured_traffic("sign23")
             if (args.prec == "fp64" and args.workload == "sign23" and args.sites == 2048
                 and args.eps == 1e-6 and args.table == "exhaustive" and args.screen == 0.0)

@@ -60,7 +60,11 @@ typedef enum {
 typedef enum {
     BSM_FP64 = 0,        /* block products in FP64 */
     BSM_FP32 = 1,        /* operands rounded to FP32, FP32 MFMA, FP32 accumulation per C block */
-    BSM_SPLIT_BF16 = 2   /* x = hi + lo in BF16, hi*hi + hi*lo + lo*hi on MFMA, FP32 accumulation */
+    BSM_SPLIT_BF16 = 2,  /* x = hi + lo in BF16, hi*hi + hi*lo + lo*hi on MFMA, FP32 accumulation
+                            (about 17 significant bits per operand) */
+    BSM_SPLIT_BF16X3 = 3 /* x = hi + mid + lo in BF16; the six products of the three parts whose
+                            size is at least 2^-18 of hi*hi (hi*hi, hi*mid, mid*hi, hi*lo, lo*hi,
+                            mid*mid) on MFMA, FP32 accumulation (about 26 bits per operand) */
 } bsm_precision;
 
 typedef enum { BSM_NORM_FROB = 0, BSM_NORM_MAXABS = 1 } bsm_norm;
@@ -119,6 +123,8 @@ typedef struct {
     int32_t smm_launches;    /* block-product kernel launches of the counted multiplies */
     int32_t pad_;
     int64_t n_screened;      /* products left out by norm screening */
+    int64_t nnzb_x_hist[128];/* stored blocks of X_k, k = 0..iterations */
+    int64_t nnzb_y_hist[128];/* stored blocks of Y_k = filter(X_k X_k), k = 0..iterations */
 } bsm_sign_stats;
 
 /* Bisection record of bsm_mu_bisect. */
@@ -236,6 +242,7 @@ int bsm_trace(bsm_matrix m, double *out, void *stream);
 
 /* ||A - shift*I||_F^2 (missing diagonal blocks count as -shift*I). Waits. */
 int bsm_sqdist_identity(bsm_matrix m, double shift, double *out, void *stream);
+
 
 /*
  * out = scale * (A - mu*I) as a new handle (missing diagonal blocks are

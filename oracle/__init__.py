@@ -77,7 +77,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (OpenMP, no FMA contraction)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC",
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fPIC",
                                "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -94,7 +94,8 @@ class _SignStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("n_multiplies", C.c_int32),
                 ("r_hist", C.c_double * 128), ("scale", C.c_double),
                 ("trace_x", C.c_double), ("trace_p", C.c_double),
-                ("flops", C.c_double)]
+                ("flops", C.c_double), ("nnzb_x", C.c_int64 * 128),
+                ("nnzb_y", C.c_int64 * 128)]
 
 
 def _load():
@@ -138,6 +139,7 @@ def _load():
                                                 C.POINTER(_SignStats)]
             lib.orc_free.argtypes = [P]
             lib.orc_num_threads.restype = C.c_int
+            lib.orc_set_threads.argtypes = [C.c_int]
             _lib = lib
     return _lib
 
@@ -278,7 +280,9 @@ def sign_ns(h: BSR, mu: float = 0.0, eps: float = 0.0, tol: float = 1e-6,
     stats = dict(iterations=int(st.iterations), n_multiplies=int(st.n_multiplies),
                  r_hist=[float(st.r_hist[k]) for k in range(st.iterations + 1)],
                  scale=float(st.scale), trace_x=float(st.trace_x),
-                 trace_p=float(st.trace_p), flops=float(st.flops))
+                 trace_p=float(st.trace_p), flops=float(st.flops),
+                 nnzb_x=[int(st.nnzb_x[k]) for k in range(st.iterations + 1)],
+                 nnzb_y=[int(st.nnzb_y[k]) for k in range(st.iterations + 1)])
     return x, stats, int(status)
 
 
@@ -425,3 +429,8 @@ def density_from_sign(x: BSR) -> BSR:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of later oracle calls (for timing; results do not change)."""
+    _load().orc_set_threads(int(n))

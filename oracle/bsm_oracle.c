@@ -530,6 +530,8 @@ typedef struct {
     double trace_x;
     double trace_p;         /* (n - trace X) / 2 */
     double flops;           /* sum over products of 2 m n k */
+    int64_t nnzb_x[128];    /* stored blocks of X_k, k = 0..iterations (orc_sign only) */
+    int64_t nnzb_y[128];    /* stored blocks of Y_k = filter(X_k X_k) (orc_sign only) */
 } orc_sign_stats;
 
 static double product_flops(const omat *a, const omat *b)
@@ -689,6 +691,8 @@ int orc_sign(const omat *h, double mu, double eps, int norm_kind, double tol,
         status = orc_multiply_screened(1.0, &x, &x, 0.0, NULL, eps, norm_kind, tau, &y);
         st->n_multiplies++;
         if (status != ORC_OK) break;
+        st->nnzb_x[k] = x.nnzb;
+        st->nnzb_y[k] = y.nnzb;
         double r = sqrt(orc_sqdist_identity(&y, 1.0)) / n;
         st->r_hist[k] = r;
         st->iterations = k;
@@ -1065,5 +1069,16 @@ int orc_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Threads of the oracle's later parallel regions (timing only; the results
+ * do not depend on it: every block row is summed by one thread). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

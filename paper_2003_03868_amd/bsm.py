@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbsm.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ENONFINITE, ECAPACITY = 0, -1, -2, -3, -4, -5, -6
-FP64, FP32, SPLIT_BF16 = 0, 1, 2
+FP64, FP32, SPLIT_BF16, SPLIT_BF16X3 = 0, 1, 2, 3
 NORM_FROB, NORM_MAXABS = 0, 1
 STATUS_NAMES = {0: "BSM_OK", -1: "BSM_EINVAL", -2: "BSM_ENOMEM", -3: "BSM_EDEVICE",
                 -4: "BSM_ENOCONV", -5: "BSM_ENONFINITE", -6: "BSM_ECAPACITY"}
@@ -58,7 +58,8 @@ class bsm_sign_stats(C.Structure):
                 ("device_ms", C.c_double), ("nnzb_final", C.c_int64),
                 ("graph_replays", C.c_int32), ("graph_fallbacks", C.c_int32),
                 ("smm_launches", C.c_int32), ("pad_", C.c_int32),
-                ("n_screened", C.c_int64)]
+                ("n_screened", C.c_int64), ("nnzb_x_hist", C.c_int64 * 128),
+                ("nnzb_y_hist", C.c_int64 * 128)]
 
 
 class bsm_mu_stats(C.Structure):

@@ -56,7 +56,7 @@ static int quad_tile(const char *name, int dflt) {
 static bool lowp_quad(int prec) {
     const char *e = getenv("BSM_LOWP_QUAD");
     if (e) return atoi(e) != 0;
-    return prec == BSM_SPLIT_BF16;
+    return prec == BSM_SPLIT_BF16 || prec == BSM_SPLIT_BF16X3;
 }
 
 // k segments of the group lists' symbolic walk (one workgroup per row group
@@ -141,7 +141,10 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     }
     if (!(eps >= 0.0) || !std::isfinite(eps)) { set_error("eps_filter must be finite and >= 0"); return BSM_EINVAL; }
     if (norm != BSM_NORM_FROB && norm != BSM_NORM_MAXABS) { set_error("unknown norm %d", norm); return BSM_EINVAL; }
-    if (prec != BSM_FP64 && prec != BSM_FP32 && prec != BSM_SPLIT_BF16) { set_error("unknown precision %d", prec); return BSM_EINVAL; }
+    if (prec != BSM_FP64 && prec != BSM_FP32 && prec != BSM_SPLIT_BF16 && prec != BSM_SPLIT_BF16X3) {
+        set_error("unknown precision %d", prec);
+        return BSM_EINVAL;
+    }
     if (!std::isfinite(alpha) || !std::isfinite(beta)) { set_error("alpha and beta must be finite"); return BSM_EINVAL; }
 
     const int32_t nbr = A.nbrows;
@@ -336,16 +339,18 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             st = BSM_EINVAL;
         }
         uint32_t *apk = nullptr, *bpk = nullptr;
-        if (st == BSM_OK) st = keep_buf(&apk, A.nvalues);
+        if (st == BSM_OK) st = keep_buf(&apk, lowp_words(A.nvalues, prec));
         if (st == BSM_OK) st = pack_lowp(A.values, A.nvalues, apk, prec, s);
         if (st == BSM_OK && &A != &B) {
-            st = keep_buf(&bpk, B.nvalues);
+            st = keep_buf(&bpk, lowp_words(B.nvalues, prec));
             if (st == BSM_OK) st = pack_lowp(B.values, B.nvalues, bpk, prec, s);
         } else {
             bpk = apk;
         }
         ma.a_pk = apk;
         ma.b_pk = bpk;
+        ma.a_pk_n = A.nvalues;
+        ma.b_pk_n = B.nvalues;
         if (pl) { pl->apk = apk; pl->bpk = bpk; }
     }
 

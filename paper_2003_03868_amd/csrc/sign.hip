@@ -53,7 +53,11 @@ static int validate_opts(const Mat &H, const bsm_sign_opts &o) {
         return BSM_EINVAL;
     }
     if (o.norm != BSM_NORM_FROB && o.norm != BSM_NORM_MAXABS) { set_error("sign: unknown norm"); return BSM_EINVAL; }
-    if (o.prec != BSM_FP64 && o.prec != BSM_FP32 && o.prec != BSM_SPLIT_BF16) { set_error("sign: unknown precision"); return BSM_EINVAL; }
+    if (o.prec != BSM_FP64 && o.prec != BSM_FP32 && o.prec != BSM_SPLIT_BF16 &&
+        o.prec != BSM_SPLIT_BF16X3) {
+        set_error("sign: unknown precision");
+        return BSM_EINVAL;
+    }
     if (o.fp64_final_iters < 0) { set_error("sign: fp64_final_iters must be >= 0"); return BSM_EINVAL; }
     if (o.order != 2 && o.order != 3 && o.order != 5 && o.order != 7) {
         set_error("sign: order must be 2, 3, 5 or 7");
@@ -399,6 +403,8 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
                 const double r = std::sqrt(h.d) / n;
                 st->r_hist[k] = r;
                 st->iterations = k;
+                st->nnzb_x_hist[k] = X->nnzb;
+                st->nnzb_y_hist[k] = Y->nnzb;
                 if (!std::isfinite(r)) {
                     set_error("sign: residual is not finite at iteration %d", k);
                     rc = BSM_ENONFINITE;
@@ -447,6 +453,8 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
         const double r = std::sqrt(d) / n;
         st->r_hist[k] = (rc == BSM_OK) ? r : NAN;
         st->iterations = k;
+        st->nnzb_x_hist[k] = X->nnzb;
+        st->nnzb_y_hist[k] = Y->nnzb;
         if (rc == BSM_ENONFINITE || !std::isfinite(r)) {
             set_error("sign: residual is not finite at iteration %d", k);
             rc = BSM_ENONFINITE;

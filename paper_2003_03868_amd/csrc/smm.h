@@ -50,6 +50,8 @@ struct SmmArgs {
     const int64_t *b_blk_off;
     const double *b_vals;
     const uint32_t *a_pk, *b_pk;  // packed reduced-precision operands (prec != FP64)
+    int64_t a_pk_n, b_pk_n;       // elements packed in a_pk, b_pk (three-term split: the
+                                  // lo parts follow the first a_pk_n words as uint16)
     const int64_t *cin_map;     // C_in block of every C block or -1; NULL when beta == 0
     const int64_t *cin_blk_off;
     const double *cin_vals;
@@ -96,6 +98,10 @@ int launch_quad(const SmmArgs &a, hipStream_t s);
 
 // Reduced-precision products (smm_lowp.hip).
 int pack_lowp(const double *v, int64_t n, uint32_t *out, int prec, hipStream_t s);
+// 32-bit words of the packed form of n elements (lowp_words(n, prec) >= n).
+inline int64_t lowp_words(int64_t n, int prec) {
+    return prec == BSM_SPLIT_BF16X3 ? n + (n + 1) / 2 : n;
+}
 bool smm_lowp_available(int m, int n, int k);
 int smm_launch_lowp(const SmmArgs &a, hipStream_t s);
 int launch_lowp_quad(const SmmArgs &a, hipStream_t s);   // quads, uniform sizes as above

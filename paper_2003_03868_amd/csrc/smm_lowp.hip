@@ -11,10 +11,18 @@
 //  * split-BF16: x = hi + lo with hi = bf16(x), lo = bf16(x - hi) (both
 //                round-to-nearest-even); A*B ~ lo*hi + hi*lo + hi*hi with
 //                V_MFMA_F32_32X32X16_BF16 (the lo*lo term is dropped).
+//                Each operand keeps about 17 significant bits.
+//  * three-term split-BF16: x = hi + mid + lo, each part the RNE bf16 of
+//                what the previous parts leave; with |mid| <= 2^-9 |x| and
+//                |lo| <= 2^-18 |x| the products are kept down to size
+//                2^-18 of hi*hi: mid*mid + hi*lo + lo*hi + mid*hi + hi*mid
+//                + hi*hi (small terms first).  About 26 bits per operand,
+//                so the FP32 accumulation sets the error, as in FP32 mode.
 //
-// Operands are packed once per multiply into one 32-bit word per element:
-// the FP32 bits, or (hi << 16 | lo) for split-BF16.  Kernels exist for
-// uniform block sizes (compile-time shapes, up to 32).
+// Operands are packed once per multiply: one 32-bit word per element (the
+// FP32 bits, or hi << 16 | lo), and for the three-term split hi << 16 | mid
+// followed by an array of the lo parts (uint16).  Kernels exist for uniform
+// block sizes (compile-time shapes, up to 32).
 #include "smm.h"
 
 namespace bsm {
@@ -47,9 +55,16 @@ __global__ void k_pack_lowp(const double *v, int64_t n, uint32_t *out, int prec)
     if (prec == BSM_FP32) {
         out[i] = __float_as_uint(__double2float_rn(x));
     } else {
+        // x - hi and r - mid are exact in FP64 (the parts are RNE roundings
+        // of the value they are subtracted from, far above its last bit)
         const uint32_t hi = bf16_rne(x);
-        const uint32_t lo = bf16_rne(x - bf16_to_double(hi));
-        out[i] = (hi << 16) | lo;
+        const double r = x - bf16_to_double(hi);
+        const uint32_t nxt = bf16_rne(r);
+        out[i] = (hi << 16) | nxt;
+        if (prec == BSM_SPLIT_BF16X3) {
+            const uint32_t lo = bf16_rne(r - bf16_to_double(nxt));
+            reinterpret_cast<unsigned short *>(out + n)[i] = static_cast<unsigned short>(lo);
+        }
     }
 }
 
@@ -113,20 +128,62 @@ __device__ inline void lp_store(const SmmArgs &a, int64_t c, const double (&acc)
 // Lane layout of V_MFMA_F32_32X32X16_BF16 (measured on gfx950):
 // A(i,k): lane i + 32*(k/8), element k%8; B(k,j): lane j + 32*(k/8),
 // element k%8; D(i,j): lane j + 32*((i/4)%2), register 4*(i/8) + i%4.
-template <int M, int N, int K>
+// One split block product over KS k steps of 16, added into the FP64
+// accumulator.  T = 2: LDS planes hi, lo of A then of B, per k step
+// lo*hi + hi*lo + hi*hi.  T = 3: planes hi, mid, lo; first every correction
+// term (mid*mid, lo*hi, hi*lo, mid*hi, hi*mid) of all k steps, then hi*hi of
+// all k steps, so that the small terms are summed while the FP32 sum is
+// still small and are not rounded to the precision of hi*hi.
+template <int T, int KS, int LDK, int PLANE>
+__device__ inline void bf16_split_product(const unsigned short *as, const unsigned short *bs,
+                                          int base, double (&acc)[16]) {
+    auto ld = [&](const unsigned short *p, int q, int ks) {
+        return __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(p + q * PLANE + base + 16 * ks));
+    };
+    f16v part = {};
+    if (T == 3) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf8 ah = ld(as, 0, ks), am = ld(as, 1, ks), al = ld(as, 2, ks);
+            const bf8 bh = ld(bs, 0, ks), bm = ld(bs, 1, ks), bl = ld(bs, 2, ks);
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, part, 0, 0, 0);
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, part, 0, 0, 0);
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, part, 0, 0, 0);
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, part, 0, 0, 0);
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, part, 0, 0, 0);
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ld(as, 0, ks), ld(bs, 0, ks), part, 0, 0, 0);
+    } else {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf8 ah = ld(as, 0, ks), al = ld(as, 1, ks), bh = ld(bs, 0, ks), bl = ld(bs, 1, ks);
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, part, 0, 0, 0);
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, part, 0, 0, 0);
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, part, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] += static_cast<double>(part[q]);
+}
+
+template <int M, int N, int K, int T>
 __global__ void __launch_bounds__(64)
 k_smm_bf16x3(SmmArgs a) {
     constexpr int LDK = 40;                         // 80-byte rows: conflict-free 16 B reads
     constexpr int PLANE = 32 * LDK;
     constexpr int KS = (K + 15) / 16;
     constexpr int NA = (M * K + kWave - 1) / kWave, NB = (K * N + kWave - 1) / kWave;
-    __shared__ __attribute__((aligned(16))) unsigned short sm[4 * PLANE];
-    unsigned short *ahi = sm, *alo = sm + PLANE, *bhi = sm + 2 * PLANE, *blo = sm + 3 * PLANE;
+    __shared__ __attribute__((aligned(16))) unsigned short sm[2 * T * PLANE];
+    unsigned short *as = sm, *bs = sm + T * PLANE;
     const int64_t item = lp_item(a.nC);
     if (item >= a.nC) return;
     const int lane = threadIdx.x;
     const int64_t c = a.worklist ? a.worklist[a.c0 + item] : a.c0 + item;
-    for (int e = lane; e < 4 * PLANE; e += kWave) sm[e] = 0;
+    for (int e = lane; e < 2 * T * PLANE; e += kWave) sm[e] = 0;
+    const unsigned short *alo3 = reinterpret_cast<const unsigned short *>(a.a_pk + a.a_pk_n);
+    const unsigned short *blo3 = reinterpret_cast<const unsigned short *>(a.b_pk + a.b_pk_n);
 
     int oa[NA], ob[NB];
 #pragma unroll
@@ -147,13 +204,21 @@ k_smm_bf16x3(SmmArgs a) {
 
     const int64_t p0 = a.seg[c - a.c0], p_end = a.seg[c - a.c0 + 1];
     uint32_t pa[NA], pb[NB];
+    unsigned short la[T == 3 ? NA : 1], lb[T == 3 ? NB : 1];
     auto prefetch = [&](int64_t p) {
-        const uint32_t *ga = a.a_pk + a.a_blk_off[a.stk_a[p]];
-        const uint32_t *gb = a.b_pk + a.b_blk_off[a.stk_b[p]];
+        const int64_t oa0 = a.a_blk_off[a.stk_a[p]], ob0 = a.b_blk_off[a.stk_b[p]];
+        const uint32_t *ga = a.a_pk + oa0;
+        const uint32_t *gb = a.b_pk + ob0;
 #pragma unroll
         for (int q = 0; q < NA; ++q) pa[q] = (oa[q] >= 0) ? ga[lane + q * kWave] : 0u;
 #pragma unroll
         for (int q = 0; q < NB; ++q) pb[q] = (ob[q] >= 0) ? gb[lane + q * kWave] : 0u;
+        if (T == 3) {
+#pragma unroll
+            for (int q = 0; q < NA; ++q) la[q] = (oa[q] >= 0) ? alo3[oa0 + lane + q * kWave] : 0;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) lb[q] = (ob[q] >= 0) ? blo3[ob0 + lane + q * kWave] : 0;
+        }
     };
     if (p0 < p_end) prefetch(p0);
     __syncthreads();
@@ -161,33 +226,20 @@ k_smm_bf16x3(SmmArgs a) {
 #pragma unroll
         for (int q = 0; q < NA; ++q)
             if (oa[q] >= 0) {
-                ahi[oa[q]] = static_cast<unsigned short>(pa[q] >> 16);
-                alo[oa[q]] = static_cast<unsigned short>(pa[q] & 0xFFFFu);
+                as[oa[q]] = static_cast<unsigned short>(pa[q] >> 16);
+                as[PLANE + oa[q]] = static_cast<unsigned short>(pa[q] & 0xFFFFu);
+                if (T == 3) as[2 * PLANE + oa[q]] = la[q];
             }
 #pragma unroll
         for (int q = 0; q < NB; ++q)
             if (ob[q] >= 0) {
-                bhi[ob[q]] = static_cast<unsigned short>(pb[q] >> 16);
-                blo[ob[q]] = static_cast<unsigned short>(pb[q] & 0xFFFFu);
+                bs[ob[q]] = static_cast<unsigned short>(pb[q] >> 16);
+                bs[PLANE + ob[q]] = static_cast<unsigned short>(pb[q] & 0xFFFFu);
+                if (T == 3) bs[2 * PLANE + ob[q]] = lb[q];
             }
         __syncthreads();
         if (p + 1 < p_end) prefetch(p + 1);
-        f16v part = {};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int off_a = r32 * LDK + 16 * ks + 8 * h;
-            const us8 xah = *reinterpret_cast<const us8 *>(ahi + off_a);
-            const us8 xal = *reinterpret_cast<const us8 *>(alo + off_a);
-            const us8 xbh = *reinterpret_cast<const us8 *>(bhi + off_a);
-            const us8 xbl = *reinterpret_cast<const us8 *>(blo + off_a);
-            const bf8 vah = __builtin_bit_cast(bf8, xah), val = __builtin_bit_cast(bf8, xal);
-            const bf8 vbh = __builtin_bit_cast(bf8, xbh), vbl = __builtin_bit_cast(bf8, xbl);
-            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(val, vbh, part, 0, 0, 0);
-            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbl, part, 0, 0, 0);
-            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbh, part, 0, 0, 0);
-        }
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] += static_cast<double>(part[q]);
+        bf16_split_product<T, KS, LDK, PLANE>(as, bs, r32 * LDK + 8 * h, acc);
         __syncthreads();
     }
     lp_store<M, N>(a, c, acc, [&](int q, int &row, int &col) {
@@ -298,15 +350,18 @@ __device__ inline int4 lp_uniform4(int4 v) {
                      __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
 }
 
-template <int S, bool BF>
-__global__ void __launch_bounds__(256)
+// T = 0: FP32; T = 2 or 3: split-BF16 with that many parts.
+template <int S, int T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_lowp_quad(SmmArgs a) {
+    constexpr bool BF = T >= 2;
+    constexpr int NP = BF ? T : 1;                      // bf16 planes per operand
     constexpr int B2 = S * S;
     constexpr int NV = (B2 + kWave - 1) / kWave;
     constexpr int LDK = 40, PLANE = 32 * LDK;           // split-BF16: [32][LDK] planes
     constexpr int LDA = 33, LDB = 32, KP = 4 * ((S + 3) / 4);
     constexpr int FA = 32 * LDA, FB = KP * LDB;          // FP32: A [32][LDA], B [KP][LDB]
-    constexpr int BYTES = BF ? 8 * PLANE * 2 : (2 * FA + 2 * FB) * 4;
+    constexpr int BYTES = BF ? 4 * NP * PLANE * 2 : (2 * FA + 2 * FB) * 4;
     __shared__ __attribute__((aligned(16))) unsigned char smem[BYTES];
     __shared__ int4 ebuf[2][64];
     unsigned short *us = reinterpret_cast<unsigned short *>(smem);
@@ -321,10 +376,9 @@ k_lowp_quad(SmmArgs a) {
     const int rr = wv >> 1, cc = wv & 1;                // this wave's C block (rr, cc)
 
     for (int e = threadIdx.x; e < BYTES / 4; e += 256) reinterpret_cast<uint32_t *>(smem)[e] = 0u;
-    // LDS position of element lane + 64 v of this wave's operand (-1: none)
-    int off[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
+    // LDS position of element lane + 64 v of this wave's operand (-1: none),
+    // recomputed where it is used (fewer live registers)
+    auto lds_off = [&](int v) {
         const int e = lane + v * kWave;
         int o = -1;
         if (e < B2) {
@@ -332,8 +386,8 @@ k_lowp_quad(SmmArgs a) {
             if (BF) o = (wv < 2) ? i * LDK + j : j * LDK + i;
             else o = (wv < 2) ? wv * FA + i * LDA + j : 2 * FA + (wv - 2) * FB + i * LDB + j;
         }
-        off[v] = o;
-    }
+        return o;
+    };
 
     double acc[16];
 #pragma unroll
@@ -344,13 +398,22 @@ k_lowp_quad(SmmArgs a) {
     const int4 none = make_int4(-1, -1, -1, -1);
     auto pick = [](const int4 v, int z) { return z == 0 ? v.x : z == 1 ? v.y : z == 2 ? v.z : v.w; };
     uint32_t pv[NV];
+    unsigned short pl[T == 3 ? NV : 1];
+    const unsigned short *lo3 = reinterpret_cast<const unsigned short *>(
+        wv < 2 ? a.a_pk + a.a_pk_n : a.b_pk + a.b_pk_n);
     auto load_block = [&](const int4 en) {
         const int id = pick(en, wv);
         if (id >= 0) {
-            const uint32_t *g = (wv < 2 ? a.a_pk : a.b_pk) + static_cast<int64_t>(id) * B2;
+            const int64_t o0 = static_cast<int64_t>(id) * B2;
+            const uint32_t *g = (wv < 2 ? a.a_pk : a.b_pk) + o0;
 #pragma unroll
             for (int v = 0; v < NV; ++v)
                 if (v < NV - 1 || lane + v * kWave < B2) pv[v] = g[lane + v * kWave];
+            if (T == 3) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    if (v < NV - 1 || lane + v * kWave < B2) pl[v] = lo3[o0 + lane + v * kWave];
+            }
         }
     };
     int4 creg = none;
@@ -370,13 +433,14 @@ k_lowp_quad(SmmArgs a) {
         if (pick(cur, wv) >= 0) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                if (off[v] >= 0) {
+                if (const int o = lds_off(v); o >= 0) {
                     if (BF) {
-                        const int plane = 2 * wv;
-                        us[plane * PLANE + off[v]] = static_cast<unsigned short>(pv[v] >> 16);
-                        us[(plane + 1) * PLANE + off[v]] = static_cast<unsigned short>(pv[v] & 0xFFFFu);
+                        const int plane = NP * wv;
+                        us[plane * PLANE + o] = static_cast<unsigned short>(pv[v] >> 16);
+                        us[(plane + 1) * PLANE + o] = static_cast<unsigned short>(pv[v] & 0xFFFFu);
+                        if (T == 3) us[(plane + 2) * PLANE + o] = pl[v];
                     } else {
-                        fs[off[v]] = __uint_as_float(pv[v]);
+                        fs[o] = __uint_as_float(pv[v]);
                     }
                 }
         }
@@ -392,23 +456,10 @@ k_lowp_quad(SmmArgs a) {
         }
         if (pick(cur, rr) >= 0 && pick(cur, 2 + cc) >= 0) {
             if (BF) {
-                const unsigned short *ahi = us + (2 * rr) * PLANE, *alo = ahi + PLANE;
-                const unsigned short *bhi = us + (2 * (2 + cc)) * PLANE, *blo = bhi + PLANE;
+                const unsigned short *as = us + (NP * rr) * PLANE;
+                const unsigned short *bs = us + (NP * (2 + cc)) * PLANE;
                 constexpr int KS = (S + 15) / 16;
-                f16v part = {};
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    const int o = r32 * LDK + 16 * ks + 8 * h;
-                    const bf8 vah = __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(ahi + o));
-                    const bf8 val = __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(alo + o));
-                    const bf8 vbh = __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(bhi + o));
-                    const bf8 vbl = __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(blo + o));
-                    part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(val, vbh, part, 0, 0, 0);
-                    part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbl, part, 0, 0, 0);
-                    part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbh, part, 0, 0, 0);
-                }
-#pragma unroll
-                for (int q = 0; q < 16; ++q) acc[q] += static_cast<double>(part[q]);
+                bf16_split_product<BF ? T : 2, KS, LDK, PLANE>(as, bs, r32 * LDK + 8 * h, acc);
             } else {
                 const float *sA = fs + rr * FA, *sB = fs + 2 * FA + cc * FB;
                 constexpr int MT = (S + 15) / 16;
@@ -485,11 +536,11 @@ int launch_lowp_quad(const SmmArgs &a, hipStream_t s) {
     const int64_t grid = per * kXcds;
     if (grid > (1ll << 31) - 1) { set_error("too many quads in one launch"); return BSM_EINVAL; }
     const unsigned g = static_cast<unsigned>(grid);
-    const bool bf = a.prec == BSM_SPLIT_BF16;
 #define BSM_LQ(SZ)                                                            \
     case SZ:                                                                  \
-        if (bf) k_lowp_quad<SZ, true><<<g, 256, 0, s>>>(a);                   \
-        else k_lowp_quad<SZ, false><<<g, 256, 0, s>>>(a);                     \
+        if (a.prec == BSM_SPLIT_BF16) k_lowp_quad<SZ, 2><<<g, 256, 0, s>>>(a);\
+        else if (a.prec == BSM_SPLIT_BF16X3) k_lowp_quad<SZ, 3><<<g, 256, 0, s>>>(a); \
+        else k_lowp_quad<SZ, 0><<<g, 256, 0, s>>>(a);                         \
         break;
     switch (a.uni_m) {
         BSM_LQ(5)
@@ -519,7 +570,8 @@ int smm_launch_lowp(const SmmArgs &a, hipStream_t s) {
 #define BSM_LP(SZ)                                                                  \
     case SZ:                                                                        \
         if (a.prec == BSM_FP32) k_smm_f32<SZ, SZ, SZ><<<grid, 64, 0, s>>>(a);       \
-        else k_smm_bf16x3<SZ, SZ, SZ><<<grid, 64, 0, s>>>(a);                       \
+        else if (a.prec == BSM_SPLIT_BF16X3) k_smm_bf16x3<SZ, SZ, SZ, 3><<<grid, 64, 0, s>>>(a); \
+        else k_smm_bf16x3<SZ, SZ, SZ, 2><<<grid, 64, 0, s>>>(a);                    \
         break;
     switch (a.uni_m) {
         BSM_LP(5)

@@ -35,7 +35,7 @@ import numpy as np
 
 __all__ = [
     "BSR", "random_bsr", "random_bsr_pair", "neighbour_hamiltonian", "overlap_like",
-    "n_occ_for_block", "config_workload", "mnk_stack",
+    "n_occ_for_block", "config_workload", "mnk_stack", "probe_vectors",
 ]
 
 
@@ -334,6 +334,12 @@ def mnk_stack(m: int, n: int, k: int, n_products: int, n_c_blocks: int,
     ai = rng.integers(0, n_a, n_products).astype(np.int32)
     bi = rng.integers(0, n_b, n_products).astype(np.int32)
     return a, b, ai, bi, c_of
+
+
+def probe_vectors(n: int, count: int = 2, seed: int = 0) -> np.ndarray:
+    """``count`` seeded Gaussian vectors of length ``n`` (rows of the result),
+    for sketching a large matrix X by the products X v."""
+    return np.random.default_rng(seed).standard_normal((count, n))
 
 
 def overlap_like(h: BSR, tau: float = 0.5, seed: int = 0) -> BSR:

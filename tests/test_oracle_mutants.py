@@ -105,7 +105,7 @@ def _run_mutant(tmpdir, name, old, new):
     mlib = os.path.join(tmpdir, f"m_{name}.so")
     with open(msrc, "w") as f:
         f.write(src.replace(old, new))
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC",
+    subprocess.check_call(["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fPIC",
                            "-shared", "-o", mlib, msrc, "-lm"])
     env = dict(os.environ, BSM_ORACLE_LIB=mlib, OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
