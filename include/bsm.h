@@ -243,6 +243,19 @@ int bsm_trace(bsm_matrix m, double *out, void *stream);
 /* ||A - shift*I||_F^2 (missing diagonal blocks count as -shift*I). Waits. */
 int bsm_sqdist_identity(bsm_matrix m, double shift, double *out, void *stream);
 
+/*
+ * bsm_sqdist_identity for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops): the same kernels and the
+ * same summation order, so the same bits, written to the device double
+ * *out_dev on `stream` without a wait.  Its per-block-row partial sums live
+ * in a fixed device array of the library (2^20 doubles, 8 MiB per device,
+ * held until the process ends) instead of allocated memory; nothing is
+ * allocated or freed.  Calls that overlap on one device share that array
+ * and race: order them on one stream.  The matrix must live on the current
+ * device.  BSM_ECAPACITY for more than 2^20 block rows, BSM_EINVAL for a
+ * non-square block matrix or NULL arguments.
+ */
+int bsm_sqdist_identity_noalloc(bsm_matrix m, double shift, double *out_dev, void *stream);
 
 /*
  * out = scale * (A - mu*I) as a new handle (missing diagonal blocks are

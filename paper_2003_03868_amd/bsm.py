@@ -109,6 +109,7 @@ _SIGS = [
     ("bsm_block_norms", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("bsm_trace", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
     ("bsm_sqdist_identity", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double), C.c_void_p]),
+    ("bsm_sqdist_identity_noalloc", C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
     ("bsm_shift_scale", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.POINTER(C.c_void_p),
                                   C.c_void_p]),
     ("bsm_inf_norm", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double), C.c_void_p]),
@@ -258,6 +259,16 @@ def bsm_sqdist_identity(h, shift=1.0, stream=None) -> float:
     _check(load().bsm_sqdist_identity(h, float(shift), C.byref(v), _stream(stream)),
            "bsm_sqdist_identity")
     return v.value
+
+
+def bsm_sqdist_identity_noalloc(h, shift, out_dev_ptr: int, stream=None) -> int:
+    """||A - shift I||_F^2 into the device double at out_dev_ptr (no wait, no
+    allocation); returns the status (BsmError is not raised for ECAPACITY)."""
+    st = load().bsm_sqdist_identity_noalloc(h, float(shift), C.c_void_p(out_dev_ptr),
+                                            _stream(stream))
+    if st not in (OK, ECAPACITY):
+        _check(st, "bsm_sqdist_identity_noalloc")
+    return st
 
 
 def bsm_inf_norm(h, mu=0.0, stream=None) -> float:

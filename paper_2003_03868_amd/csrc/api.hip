@@ -225,6 +225,12 @@ int bsm_sqdist_identity(bsm_matrix h, double shift, double *out, void *stream) {
     return bsm::sqdist_identity(h->m, shift, out, as_stream(stream));
 }
 
+int bsm_sqdist_identity_noalloc(bsm_matrix h, double shift, double *out_dev, void *stream) {
+    bsm::clear_error();
+    if (!h || !out_dev) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    return bsm::sqdist_identity_noalloc(h->m, shift, out_dev, as_stream(stream));
+}
+
 int bsm_inf_norm(bsm_matrix h, double mu, double *out, void *stream) {
     bsm::clear_error();
     if (!h || !out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }

@@ -101,6 +101,9 @@ int filter_inplace(Mat &m, double eps, int norm, hipStream_t s);
 int block_sqnorms(const Mat &m, double *out, hipStream_t s);
 int trace(const Mat &m, double *out, hipStream_t s);
 int sqdist_identity(const Mat &m, double shift, double *out, hipStream_t s);
+// The same sum into a device double, partial sums in fixed device memory
+// (no allocation, no wait); BSM_ECAPACITY beyond 2^20 block rows.
+int sqdist_identity_noalloc(const Mat &m, double shift, double *out_dev, hipStream_t s);
 int inf_norm(const Mat &m, double mu, double *out, hipStream_t s);
 int shift_scale(const Mat &a, double mu, double scale, Mat **out, hipStream_t s);
 int copy_mat(const Mat &a, Mat **out, hipStream_t s);

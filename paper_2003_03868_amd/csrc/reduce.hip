@@ -2,11 +2,49 @@
 // norm), the norm filter with compaction, and the shifted/scaled copy used
 // for X_0 = (H - mu I)/s and P = (I - X)/2.  All reductions are FP64 and sum
 // in a fixed order, so repeated calls give identical bits.
+#include <mutex>
+
 #include "bsm_internal.h"
 
 namespace bsm {
 
 constexpr int kRedThreads = 256;
+
+// Fixed device memory for the residual reduction that allocates nothing
+// (sqdist_identity_noalloc): one partial sum per block row, at most
+// kNoAllocMaxRows rows (8 MiB).  Every device the library runs on holds its
+// own copy until the process ends; calls on one device share it, so calls
+// that overlap on one device race.  Host code never passes the symbol itself
+// to a kernel: its device address comes from hipGetSymbolAddress, taken once
+// per device with that device current.
+constexpr int64_t kNoAllocMaxRows = int64_t{1} << 20;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocMaxRows];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[kNoAllocMaxDevices] = {};
+
+static int scratch_address(double **out) {
+    int dev = 0;
+    BSM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices) {
+        set_error("device %d is beyond the %d devices of the fixed scratch table", dev,
+                  kNoAllocMaxDevices);
+        return BSM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress of the fixed scratch failed: %s", hipGetErrorString(e));
+            return BSM_EDEVICE;
+        }
+        g_scratch_dev[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return BSM_OK;
+}
 
 __device__ inline double wsum(double v) {
     for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -279,6 +317,35 @@ int sqdist_identity_dev(const Mat &m, double shift, double *part, double *d_out,
     k_sqdist_rows<<<m.nbrows, kRedThreads, 0, s>>>(m.row_ptr, m.col_idx, m.blk_off, m.values,
                                                    m.rbs, m.cbs, shift, part);
     k_reduce_final<<<1, 1024, 0, s>>>(part, m.nbrows, d_out, 0);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+__global__ void k_set_f64(double *p, double v) { *p = v; }
+
+int sqdist_identity_noalloc(const Mat &m, double shift, double *out_dev, hipStream_t s) {
+    if (m.nbrows != m.nbcols) { set_error("needs a square block matrix"); return BSM_EINVAL; }
+    if (m.nbrows > kNoAllocMaxRows) {
+        set_error("%d block rows exceed the fixed scratch of %lld rows", m.nbrows,
+                  static_cast<long long>(kNoAllocMaxRows));
+        return BSM_ECAPACITY;
+    }
+    int dev = 0;
+    BSM_HIP(hipGetDevice(&dev));
+    if (dev != m.device) {
+        set_error("the matrix lives on device %d, device %d is current", m.device, dev);
+        return BSM_EINVAL;
+    }
+    if (m.nbrows == 0) {
+        k_set_f64<<<1, 1, 0, s>>>(out_dev, 0.0);
+        BSM_HIP(hipGetLastError());
+        return BSM_OK;
+    }
+    double *part = nullptr;
+    BSM_TRY(scratch_address(&part));
+    k_sqdist_rows<<<m.nbrows, kRedThreads, 0, s>>>(m.row_ptr, m.col_idx, m.blk_off, m.values,
+                                                   m.rbs, m.cbs, shift, part);
+    k_reduce_final<<<1, 1024, 0, s>>>(part, m.nbrows, out_dev, 0);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }
