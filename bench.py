@@ -436,6 +436,10 @@ def main():
                     help="Newton-Schulz tolerance inside each submatrix")
     ap.add_argument("--cpu-cols", type=int, default=1500,
                     help="block columns of the oracle's submatrix sample")
+    ap.add_argument("--mixed-kernel", choices=["fused", "class"], default="fused",
+                    help="mixed workload: every (m, n) class in one persistent launch per "
+                         "multiply with operand sharing (fused, the configuration's form) or "
+                         "one launch per class (the library default, measured faster)")
     ap.add_argument("--graph", type=int, choices=[0, 1], default=0,
                     help="1: replay captured hipGraphs once X's block pattern stops changing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -462,6 +466,8 @@ def main():
         print(json.dumps({"calibrate_copy_mib": args.calibrate_copy, "dispatches": 5}))
         return
 
+    if args.workload == "mixed" and args.mixed_kernel == "fused" and "BSM_SMM_VARIANT" not in os.environ:
+        os.environ["BSM_SMM_VARIANT"] = "7"      # read by the library per multiply
     import synth
     from paper_2003_03868_amd import bsm, tune
     bsm.load()
@@ -626,6 +632,7 @@ def main():
             "n": int(n), "eps_filter": args.eps, "kernel_table": args.table,
             "tol": args.tol, "seed": args.seed, "nnzb_H": h.nnzb,
             "graph_replay": bool(args.graph), "order": args.order,
+            "mixed_kernel": (args.mixed_kernel if args.workload == "mixed" else None),
             "eps_screen": args.screen,
         },
         "time_to_sign_ms": ms_per_step,
@@ -647,6 +654,7 @@ def main():
             "kernel": ("k_smm_f64_quad<23,2,2,4,5,1,true>" if args.screen > 0.0
                        else "k_smm_f64_quad<23,2,2,4,6,1>" if args.workload == "sign23"
                        else "k_smm_f64_quad<6,2,2,1,8,1>" if args.workload == "water"
+                       else "k_smm_f64_mquad" if os.environ.get("BSM_SMM_VARIANT") == "7"
                        else "k_smm_f64_class")
             if args.prec == "fp64" else "k_smm_f32<23,23,23>" if args.prec == "fp32"
             else f"k_lowp_quad<23,{ {'bf16': 2, 'bf16x3': 3}[args.prec] }>",

@@ -72,15 +72,79 @@ static int32_t quad_ksegments(int32_t nbk) {
 }
 
 // Kernel family for a chunk with mixed block sizes (uniform sizes keep the
-// requested variant).  Default: per-class launches when every size is in
-// {5, 13, 23, 26}, else the fused persistent kernel.
+// requested variant).  Default: one launch per (m, n) class when every size
+// is in {5, 13, 23, 26} (measured fastest on the 4096-site mixed workload:
+// 7.1 s per sign step, against 8.8 s for the paired-group kernel of
+// kSmmF64MQuad, whose one persistent launch per multiply shares operands but
+// waits at a barrier per entry for products that are small on average),
+// else the run-time-shape persistent kernel.
 static int mixed_variant(const SmmArgs &a, int requested) {
     const bool uniform = a.uni_m && a.uni_n && a.uni_k;
     if (uniform) return requested;
-    if (requested == kSmmF64Class && !a.fused_ok) return kSmmF64Fused;
+    if ((requested == kSmmF64Class || requested == kSmmF64MQuad) && !a.fused_ok) return kSmmF64Fused;
     if (requested == kSmmF64Fixed || requested == kSmmF64Quad)
         return a.fused_ok ? kSmmF64Class : kSmmF64Fused;
     return requested;
+}
+
+// Pairs of equal-size block rows (within bands of kPairBand rows, so that
+// chunk cuts at band edges never split a pair) and of equal-size block
+// columns (over all columns), for the mixed-size groups: rows of each size
+// in ascending order are paired in turn, the last one alone when their count
+// is odd; groups are listed by their first row (column).  band_g0[b] is the
+// first row group of band b.
+constexpr int32_t kPairBand = 32;
+
+struct MixedPairs {
+    std::vector<int32_t> rg, band_g0, cgrp, cslot, cmap;
+};
+
+static void mixed_pairs(const std::vector<int32_t> &rbs, const std::vector<int32_t> &cbs,
+                        MixedPairs *mp) {
+    const int32_t nbr = static_cast<int32_t>(rbs.size()), nbc = static_cast<int32_t>(cbs.size());
+    mp->rg.clear();
+    mp->band_g0.clear();
+    for (int32_t b0 = 0; b0 < nbr; b0 += kPairBand) {
+        mp->band_g0.push_back(static_cast<int32_t>(mp->rg.size() / 2));
+        const int32_t b1 = std::min(nbr, b0 + kPairBand);
+        std::vector<int32_t> open(kMaxBlock + 1, -1);     // unpaired row of each size
+        std::vector<std::pair<int32_t, int32_t>> groups;
+        for (int32_t i = b0; i < b1; ++i) {
+            int32_t &o = open[rbs[i]];
+            if (o < 0) { o = i; continue; }
+            groups.push_back({o, i});
+            o = -1;
+        }
+        for (int32_t v : open)
+            if (v >= 0) groups.push_back({v, -1});
+        std::sort(groups.begin(), groups.end());
+        for (auto &g : groups) { mp->rg.push_back(g.first); mp->rg.push_back(g.second); }
+    }
+    mp->band_g0.push_back(static_cast<int32_t>(mp->rg.size() / 2));
+    std::vector<int32_t> open(kMaxBlock + 1, -1);
+    std::vector<std::pair<int32_t, int32_t>> groups;
+    for (int32_t j = 0; j < nbc; ++j) {
+        int32_t &o = open[cbs[j]];
+        if (o < 0) { o = j; continue; }
+        groups.push_back({o, j});
+        o = -1;
+    }
+    for (int32_t v : open)
+        if (v >= 0) groups.push_back({v, -1});
+    std::sort(groups.begin(), groups.end());
+    mp->cgrp.assign(nbc, -1);
+    mp->cslot.assign(nbc, 0);
+    mp->cmap.clear();
+    for (size_t q = 0; q < groups.size(); ++q) {
+        mp->cmap.push_back(groups[q].first);
+        mp->cmap.push_back(groups[q].second);
+        mp->cgrp[groups[q].first] = static_cast<int32_t>(q);
+        mp->cslot[groups[q].first] = 0;
+        if (groups[q].second >= 0) {
+            mp->cgrp[groups[q].second] = static_cast<int32_t>(q);
+            mp->cslot[groups[q].second] = 1;
+        }
+    }
 }
 
 namespace {
@@ -241,12 +305,22 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     if (st == BSM_OK) st = keep_buf(&worklist, nnzb_c);
     if (st == BSM_OK) st = keep_buf(&worklist2, nnzb_c);  // target of the work-list sorts
     if (st == BSM_OK) st = tile_order(c_row_ptr, nc.col_idx, nbr, B.nbcols, rb, worklist, s);
+    // mixed sizes in {5, 13, 23, 26}: groups over paired rows and columns
+    // (FP64, no screening), unless another kernel variant is asked for
+    const bool mixed_sizes = !(A.uni_r && A.uni_c && B.uni_c);
+    bool mixed_ok = true;
+    for (const auto *v : {&A.h_rbs, &A.h_cbs, &B.h_cbs})
+        for (int32_t b : *v)
+            if (b != 5 && b != 13 && b != 23 && b != 26) mixed_ok = false;
+    const bool use_mquad = prec == BSM_FP64 && tau == 0.0 && mixed_sizes && mixed_ok &&
+                           variant == kSmmF64MQuad;
     std::vector<int32_t> cuts{0};
     {
         // whole row bands; a step that is a multiple of 4 keeps the row
-        // groups of the group kernel (2 or 4 rows) in one chunk
+        // groups of the group kernel (2 or 4 rows) in one chunk, one of
+        // kPairBand the paired rows of the mixed-size groups
         const int64_t lim = chunk_products();
-        const int step = (rb + 3) / 4 * 4;
+        const int step = use_mquad ? (rb + kPairBand - 1) / kPairBand * kPairBand : (rb + 3) / 4 * 4;
         int32_t r0 = 0;
         while (r0 < nbr) {
             int32_t r1 = std::min(nbr, r0 + step);
@@ -300,13 +374,34 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     }
     const int NE = (GR + GC + 3) / 4;                        // int4 per group entry
 
+    // pair maps of the mixed-size groups (host-built, copied to the device)
+    MixedPairs mp;
+    int32_t *d_rg = nullptr, *d_cgrp = nullptr, *d_cslot = nullptr, *d_cmap = nullptr;
+    unsigned long long *mq_counter = nullptr;
+    if (st == BSM_OK && use_mquad) {
+        mixed_pairs(A.h_rbs, B.h_cbs, &mp);
+        st = keep_buf(&d_rg, mp.rg.size());
+        if (st == BSM_OK) st = keep_buf(&d_cgrp, mp.cgrp.size());
+        if (st == BSM_OK) st = keep_buf(&d_cslot, mp.cslot.size());
+        if (st == BSM_OK) st = keep_buf(&d_cmap, mp.cmap.size());
+        if (st == BSM_OK) st = keep_buf(&mq_counter, 1);
+        hipError_t e = hipSuccess;
+        auto up = [&](int32_t *d, const std::vector<int32_t> &h) {
+            if (e == hipSuccess && !h.empty())
+                e = hipMemcpyAsync(d, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, s);
+        };
+        if (st == BSM_OK) { up(d_rg, mp.rg); up(d_cgrp, mp.cgrp); up(d_cslot, mp.cslot); up(d_cmap, mp.cmap); }
+        if (e != hipSuccess) { set_error("pair maps: %s", hipGetErrorString(e)); st = BSM_EDEVICE; }
+    }
+
     // one set of stack buffers reused by every chunk; a plan keeps one per
-    // chunk; the quad kernel builds its own lists
+    // chunk; the group kernels build their own lists
     int64_t *seg = nullptr;
     int32_t *stk_a = nullptr, *stk_b = nullptr;
-    if (st == BSM_OK && !pl && !use_quad) st = tmp.get(&seg, max_c + 1);
-    if (st == BSM_OK && !pl && !use_quad) st = tmp.get(&stk_a, max_p);
-    if (st == BSM_OK && !pl && !use_quad) st = tmp.get(&stk_b, max_p);
+    const bool groups = use_quad || use_mquad;
+    if (st == BSM_OK && !pl && !groups) st = tmp.get(&seg, max_c + 1);
+    if (st == BSM_OK && !pl && !groups) st = tmp.get(&stk_a, max_p);
+    if (st == BSM_OK && !pl && !groups) st = tmp.get(&stk_b, max_p);
 
     SmmArgs ma{};
     ma.c_row = c_row; ma.c_col = nc.col_idx; ma.c_blk_off = nc.blk_off; ma.c_vals = nc.values;
@@ -331,7 +426,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     ma.prec = prec;
     ma.seg = seg; ma.stk_a = stk_a; ma.stk_b = stk_b;
     ma.worklist = worklist;
-    if (st == BSM_OK && pl) st = keep_buf(&ma.counter, 1);   // persistent kernel's counter
+    if (st == BSM_OK) st = keep_buf(&ma.counter, 1);         // persistent kernels' counter
 
     if (st == BSM_OK && prec != BSM_FP64) {
         if (!(A.uni_r && A.uni_c && B.uni_c && smm_lowp_available(A.uni_r, B.uni_c, A.uni_c))) {
@@ -367,12 +462,17 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         ma.c0 = h_crp[r0];
         ma.nC = h_crp[r1] - h_crp[r0];
         if (ma.nC == 0) continue;
-        if (use_quad) {
+        if (groups) {
             // groups of this chunk's C blocks and their merged entry lists;
             // without a plan the buffers live for this chunk only
             Scratch ctmp(s);
             auto qbuf = [&](auto **ptr, size_t n) -> int { return pl ? keep_buf(ptr, n) : ctmp.get(ptr, n); };
-            const int64_t npairs = (static_cast<int64_t>(r1 - r0) + GR - 1) / GR;
+            int32_t g0 = 0;
+            int64_t npairs = (static_cast<int64_t>(r1 - r0) + GR - 1) / GR;
+            if (use_mquad) {
+                g0 = mp.band_g0[r0 / kPairBand];
+                npairs = mp.band_g0[(r1 + kPairBand - 1) / kPairBand] - g0;
+            }
             int64_t *q_off = nullptr, *q_cblk = nullptr, *e_off = nullptr, *q_order = nullptr,
                     *e_seg = nullptr;
             int32_t *pm = nullptr;
@@ -394,6 +494,13 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             qa.b_row_ptr = B.row_ptr; qa.b_col_idx = B.col_idx;
             qa.c_row_ptr = c_row_ptr; qa.c_col_idx = nc.col_idx;
             qa.a_sq = a_sq; qa.b_sq = b_sq; qa.tau2 = tau * tau; qa.kept = kept;
+            if (use_mquad) {
+                qa.map = 1;
+                qa.g0 = g0;
+                qa.ngroups = npairs;
+                qa.ncg = static_cast<int32_t>(mp.cmap.size() / 2);
+                qa.rg = d_rg; qa.cgrp = d_cgrp; qa.cslot = d_cslot; qa.cmap = d_cmap;
+            }
             st = qbuf(&q_off, npairs + 1);
             if (st == BSM_OK) st = quad_pairs(qa, q_off, s);
             if (st == BSM_OK) st = scan_i64(q_off, q_off, npairs, s);
@@ -409,7 +516,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             qa.e_off = e_seg;
             if (st == BSM_OK) st = quad_stack(qa, false, s);
             const int qr = quad_tile("BSM_QUAD_TILE_ROWS", 0), qc = quad_tile("BSM_QUAD_TILE_COLS", 16);
-            if (st == BSM_OK && qr > 0 && nq > 0) {
+            if (st == BSM_OK && qr > 0 && nq > 0 && !use_mquad) {
                 st = qbuf(&q_order, nq);
                 if (st == BSM_OK)
                     st = tile_order(q_off, q_col, static_cast<int32_t>(npairs), (B.nbcols + GC - 1) / GC,
@@ -432,11 +539,19 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
             if (st != BSM_OK) break;
             MulOp op;
             op.a = ma;
-            op.kind = kOpQuad;
+            op.kind = use_mquad ? kOpMQuad : kOpQuad;
+            op.a.counter = use_mquad ? mq_counter : ma.counter;
             op.a.n_quads = nq;
             op.a.q_cblk = q_cblk;
             op.a.q_seg = e_off;
             op.a.q_ent = ent;
+            if (st == BSM_OK && use_mquad && nq > 0) {
+                int8_t *rank = nullptr;
+                st = ctmp.get(&rank, nq);
+                if (st == BSM_OK) st = qbuf(&q_order, nq);
+                if (st == BSM_OK) st = mquad_order(op.a, rank, q_order, s);
+                if (st != BSM_OK) break;
+            }
             op.a.q_order = q_order;
             op.a.q_gr = GR;
             op.a.q_gc = GC;

@@ -18,7 +18,7 @@ namespace bsm {
 
 constexpr int kFlagPattern = 2;   // the filter would keep a different block set
 
-enum MulOpKind { kOpVariant = 0, kOpClass = 1, kOpRt = 2, kOpLowp = 3, kOpQuad = 4 };
+enum MulOpKind { kOpVariant = 0, kOpClass = 1, kOpRt = 2, kOpLowp = 3, kOpQuad = 4, kOpMQuad = 5 };
 
 // One block-product launch of a multiply.
 struct MulOp {

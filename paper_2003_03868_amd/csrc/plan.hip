@@ -12,6 +12,7 @@ int run_op(const MulOp &op, hipStream_t s) {
         case kOpRt: return launch_rt(op.a, op.prm, s);
         case kOpLowp: return smm_launch_lowp(op.a, s);
         case kOpQuad: return launch_quad(op.a, s);
+        case kOpMQuad: return launch_mquad(op.a, s);
         default: set_error("internal: unknown launch kind %d", op.kind); return BSM_EINVAL;
     }
 }

@@ -12,6 +12,15 @@
 // stacks, in the same (ascending k) order, while every operand block is
 // loaded once for up to GC (A) or GR (B) products.  An entry is the GR A
 // indices followed by the GC B indices, padded to whole int4.
+//
+// Mixed block sizes (MAP): the groups are 2 x 2 over paired rows and paired
+// columns instead of consecutive ones.  Row group g holds rows rg[2g],
+// rg[2g + 1] (the second -1 for a single row), column group Q the columns
+// cmap[2Q], cmap[2Q + 1]; the pairs join blocks of equal size (built on the
+// host, mixed_pairs in multiply.hip), so every C block of a group has the
+// same shape and only k varies between entries.  Entry rules are the same:
+// the column of group Q met first in B's row k emits the entry, finding its
+// partner column by binary search.
 #include <climits>
 
 #include "symbolic.h"
@@ -63,20 +72,45 @@ __device__ inline int64_t qwg_exscan(int64_t v, int64_t *scratch, int64_t *total
 __host__ __device__ inline int quad_words(int32_t nbcols, int g) {
     return ((nbcols + g - 1) / g + 31) >> 5;
 }
+// Words of the column-group bitmap.
+__host__ __device__ inline int quad_nwq(const QuadSymArgs &q) {
+    return q.map ? (q.ncg + 31) >> 5 : quad_words(q.nbcols, q.gc);
+}
 
-// Bitmap of the column groups Q holding C blocks of rows i0 .. i0 + nr - 1
-// and the exclusive popcount prefix per word; returns the number of groups.
-template <int GC>
-__device__ inline int64_t quad_rank_map(const QuadSymArgs &q, int32_t i0, int nr, int nwq,
+// Column group and slot of column j.
+template <int GC, bool MAP>
+__device__ inline int32_t col_group(const QuadSymArgs &q, int32_t j) {
+    return MAP ? q.cgrp[j] : j / GC;
+}
+template <int GC, bool MAP>
+__device__ inline int col_slot(const QuadSymArgs &q, int32_t j) {
+    return MAP ? q.cslot[j] : j % GC;
+}
+
+// Block row r of row group R of the chunk (-1: none).
+template <int GR, bool MAP>
+__device__ inline int32_t group_row(const QuadSymArgs &q, int32_t R, int r) {
+    if (MAP) return q.rg[GR * (q.g0 + R) + r];
+    const int32_t i = q.r0 + GR * R + r;
+    return i < q.r1 ? i : -1;
+}
+
+// Bitmap of the column groups Q holding C blocks of the rows rows[0..GR)
+// (-1: none) and the exclusive popcount prefix per word; returns the number
+// of groups.
+template <int GR, int GC, bool MAP>
+__device__ inline int64_t quad_rank_map(const QuadSymArgs &q, const int32_t (&rows)[GR], int nwq,
                                         uint32_t *bits, int32_t *wpre, int64_t *scratch) {
     for (int w = threadIdx.x; w < nwq; w += kQuadThreads) bits[w] = 0u;
     __syncthreads();
-    for (int r = 0; r < nr; ++r)
-        for (int64_t t = q.c_row_ptr[i0 + r] + threadIdx.x; t < q.c_row_ptr[i0 + r + 1];
+    for (int r = 0; r < GR; ++r) {
+        if (rows[r] < 0) continue;
+        for (int64_t t = q.c_row_ptr[rows[r]] + threadIdx.x; t < q.c_row_ptr[rows[r] + 1];
              t += kQuadThreads) {
-            const int32_t Q = q.c_col_idx[t] / GC;
+            const int32_t Q = col_group<GC, MAP>(q, q.c_col_idx[t]);
             atomicOr(&bits[Q >> 5], 1u << (Q & 31));
         }
+    }
     __syncthreads();
     const int per = (nwq + kQuadThreads - 1) / kQuadThreads;
     const int w0 = threadIdx.x * per;
@@ -93,23 +127,24 @@ __device__ inline int64_t quad_rank_map(const QuadSymArgs &q, int32_t i0, int nr
 }
 
 // Groups per row group (one workgroup per row group).
-template <int GR, int GC>
+template <int GR, int GC, bool MAP>
 __global__ void __launch_bounds__(kQuadThreads)
 k_quad_pairs(QuadSymArgs q, int64_t *cnt) {
     extern __shared__ uint32_t smem[];
     __shared__ int64_t scratch[kQuadThreads / kWave];
-    const int nwq = quad_words(q.nbcols, GC);
+    const int nwq = quad_nwq(q);
     const int32_t R = blockIdx.x;
-    const int32_t i0 = q.r0 + GR * R;
-    const int nr = (q.r1 - i0 < GR) ? q.r1 - i0 : GR;
-    const int64_t nq = quad_rank_map<GC>(q, i0, nr, nwq, smem,
-                                         reinterpret_cast<int32_t *>(smem + nwq), scratch);
+    int32_t rows[GR];
+#pragma unroll
+    for (int r = 0; r < GR; ++r) rows[r] = group_row<GR, MAP>(q, R, r);
+    const int64_t nq = quad_rank_map<GR, GC, MAP>(q, rows, nwq, smem,
+                                                  reinterpret_cast<int32_t *>(smem + nwq), scratch);
     if (threadIdx.x == 0) cnt[R] = nq;
 }
 
 // FILL = false: the groups' C blocks (q_cblk) and entry counts (e_off);
 // FILL = true: the entries.
-template <bool FILL, int GR, int GC>
+template <bool FILL, int GR, int GC, bool MAP>
 __global__ void __launch_bounds__(kQuadThreads)
 k_quad_stack(QuadSymArgs q) {
     constexpr int GG = GR * GC;
@@ -119,7 +154,7 @@ k_quad_stack(QuadSymArgs q) {
     __shared__ int64_t s_tb0, s_tb1;
     __shared__ unsigned long long s_kept;      // fill pass with screening: kept products
     __shared__ int32_t s_k, s_a[GR], s_skip[GR];
-    const int nwq = quad_words(q.nbcols, GC);  // words of the column-group bitmap
+    const int nwq = quad_nwq(q);               // words of the column-group bitmap
     uint32_t *bits = smem;
     int32_t *wpre = reinterpret_cast<int32_t *>(smem + nwq);
     int32_t *cnt = reinterpret_cast<int32_t *>(smem + 2 * nwq);
@@ -127,12 +162,13 @@ k_quad_stack(QuadSymArgs q) {
     int32_t *eoff = cnt + kQuadWindow;
     __shared__ int64_t s_ebase;
     const int32_t R = blockIdx.x / q.nseg, sg = blockIdx.x % q.nseg;
-    const int32_t i0 = q.r0 + GR * R;
-    const int nr = (q.r1 - i0 < GR) ? q.r1 - i0 : GR;
+    int32_t rows[GR];
+#pragma unroll
+    for (int r = 0; r < GR; ++r) rows[r] = group_row<GR, MAP>(q, R, r);
     // this workgroup's k range
     const int32_t k_lo = sg * q.kseg;
     const int32_t k_hi = (sg == q.nseg - 1) ? INT_MAX : k_lo + q.kseg;
-    quad_rank_map<GC>(q, i0, nr, nwq, bits, wpre, scratch);
+    quad_rank_map<GR, GC, MAP>(q, rows, nwq, bits, wpre, scratch);
 
     const int64_t qbase = q.q_off[R], nq = q.q_off[R + 1] - qbase;
     if (threadIdx.x == 0) s_kept = 0;
@@ -140,14 +176,17 @@ k_quad_stack(QuadSymArgs q) {
         // C blocks of every group: (r, c) at GR GC group + GC r + c, -1 where absent
         for (int64_t t = threadIdx.x; t < GG * nq; t += kQuadThreads) q.q_cblk[GG * qbase + t] = -1;
         __syncthreads();
-        for (int r = 0; r < nr; ++r)
-            for (int64_t t = q.c_row_ptr[i0 + r] + threadIdx.x; t < q.c_row_ptr[i0 + r + 1];
+        for (int r = 0; r < GR; ++r) {
+            if (rows[r] < 0) continue;
+            for (int64_t t = q.c_row_ptr[rows[r]] + threadIdx.x; t < q.c_row_ptr[rows[r] + 1];
                  t += kQuadThreads) {
                 const int32_t j = q.c_col_idx[t];
-                const int64_t rank = bit_rank_q(bits, wpre, j / GC);
-                q.q_cblk[GG * (qbase + rank) + GC * r + (j % GC)] = t;
-                q.q_col[qbase + rank] = j / GC;    // same value from every block of the group
+                const int32_t Q = col_group<GC, MAP>(q, j);
+                const int64_t rank = bit_rank_q(bits, wpre, Q);
+                q.q_cblk[GG * (qbase + rank) + GC * r + col_slot<GC, MAP>(q, j)] = t;
+                q.q_col[qbase + rank] = Q;         // same value from every block of the group
             }
+        }
     }
     for (int64_t w0 = 0; w0 < nq; w0 += kQuadWindow) {
         const int wn = static_cast<int>(nq - w0 < kQuadWindow ? nq - w0 : kQuadWindow);
@@ -164,9 +203,10 @@ k_quad_stack(QuadSymArgs q) {
         __syncthreads();
         // first entry of each A row at or after k_lo: the count of smaller k's
         if (k_lo > 0)
-            for (int r = 0; r < nr; ++r) {
+            for (int r = 0; r < GR; ++r) {
+                if (rows[r] < 0) continue;
                 int32_t c = 0;
-                for (int64_t t = q.a_row_ptr[i0 + r] + threadIdx.x; t < q.a_row_ptr[i0 + r + 1];
+                for (int64_t t = q.a_row_ptr[rows[r]] + threadIdx.x; t < q.a_row_ptr[rows[r] + 1];
                      t += kQuadThreads)
                     c += q.a_col_idx[t] < k_lo ? 1 : 0;
                 if (c) atomicAdd(&s_skip[r], c);
@@ -198,8 +238,8 @@ k_quad_stack(QuadSymArgs q) {
         };
         if (threadIdx.x == 0) {
             for (int r = 0; r < GR; ++r) {
-                pos[r] = r < nr ? q.a_row_ptr[i0 + r] + s_skip[r] : 0;
-                end[r] = r < nr ? q.a_row_ptr[i0 + r + 1] : 0;
+                pos[r] = rows[r] >= 0 ? q.a_row_ptr[rows[r]] + s_skip[r] : 0;
+                end[r] = rows[r] >= 0 ? q.a_row_ptr[rows[r] + 1] : 0;
                 const int32_t h = pos[r] < end[r] ? q.a_col_idx[pos[r]] : INT_MAX;
                 head[r] = h >= k_hi ? INT_MAX : h;
             }
@@ -219,8 +259,24 @@ k_quad_stack(QuadSymArgs q) {
             const int64_t tb0 = s_tb0, tb1 = s_tb1;
             for (int64_t tb = tb0 + threadIdx.x; tb < tb1; tb += kQuadThreads) {
                 const int32_t j = q.b_col_idx[tb];
-                const int32_t Q = j / GC;
-                if (tb > tb0 && q.b_col_idx[tb - 1] / GC == Q) continue;  // an earlier column emits
+                const int32_t Q = col_group<GC, MAP>(q, j);
+                int64_t partner = -1;          // MAP: B(k, other column of Q), -1 if absent
+                if (MAP) {
+                    const int sl = col_slot<GC, MAP>(q, j);
+                    const int32_t jp = q.cmap[2 * Q + 1 - sl];
+                    if (jp >= 0) {
+                        int64_t lo = tb0, hi = tb1 - 1;
+                        while (lo <= hi) {
+                            const int64_t mid = (lo + hi) >> 1;
+                            const int32_t cm = q.b_col_idx[mid];
+                            if (cm == jp) { partner = mid; break; }
+                            if (cm < jp) lo = mid + 1; else hi = mid - 1;
+                        }
+                    }
+                    if (sl == 1 && partner >= 0) continue;            // slot 0 emits
+                } else if (tb > tb0 && q.b_col_idx[tb - 1] / GC == Q) {
+                    continue;                                         // an earlier column emits
+                }
                 const int64_t r = bit_rank_q(bits, wpre, Q) - w0;
                 if (r < 0 || r >= wn) continue;
                 int32_t e[4 * NE];
@@ -228,10 +284,16 @@ k_quad_stack(QuadSymArgs q) {
                 if (FILL || q.tau2 > 0.0) {
                     for (int z = 0; z < 4 * NE; ++z) e[z] = -1;
                     for (int r2 = 0; r2 < GR; ++r2) e[r2] = s_a[r2];
-                    for (int64_t t = tb; t < tb1 && t < tb + GC; ++t) {
-                        const int32_t jj = q.b_col_idx[t];
-                        if (jj / GC != Q) break;
-                        e[GR + jj % GC] = static_cast<int32_t>(t);
+                    if (MAP) {
+                        const int sl = col_slot<GC, MAP>(q, j);
+                        e[GR + sl] = static_cast<int32_t>(tb);
+                        if (partner >= 0) e[GR + 1 - sl] = static_cast<int32_t>(partner);
+                    } else {
+                        for (int64_t t = tb; t < tb1 && t < tb + GC; ++t) {
+                            const int32_t jj = q.b_col_idx[t];
+                            if (jj / GC != Q) break;
+                            e[GR + jj % GC] = static_cast<int32_t>(t);
+                        }
                     }
                 }
                 if (q.tau2 > 0.0) {
@@ -274,13 +336,23 @@ k_quad_stack(QuadSymArgs q) {
 
 #define BSM_QUAD_SHAPES(X) X(2, 2) X(4, 4) X(4, 2)
 
+static int64_t quad_groups(const QuadSymArgs &q) {
+    return q.map ? q.ngroups : (static_cast<int64_t>(q.r1 - q.r0) + q.gr - 1) / q.gr;
+}
+
 int quad_pairs(const QuadSymArgs &q, int64_t *cnt, hipStream_t s) {
-    const int64_t ngroups = (static_cast<int64_t>(q.r1 - q.r0) + q.gr - 1) / q.gr;
+    const int64_t ngroups = quad_groups(q);
     if (ngroups <= 0) return BSM_OK;
-    const size_t lds = sizeof(uint32_t) * 2 * quad_words(q.nbcols, q.gc);
+    const size_t lds = sizeof(uint32_t) * 2 * quad_nwq(q);
     const unsigned g = static_cast<unsigned>(ngroups);
+    if (q.map) {
+        if (q.gr != 2 || q.gc != 2) { set_error("internal: mixed groups are 2 x 2"); return BSM_EINVAL; }
+        k_quad_pairs<2, 2, true><<<g, kQuadThreads, lds, s>>>(q, cnt);
+        BSM_HIP(hipGetLastError());
+        return BSM_OK;
+    }
 #define BSM_QP(R_, C_) \
-    if (q.gr == R_ && q.gc == C_) { k_quad_pairs<R_, C_><<<g, kQuadThreads, lds, s>>>(q, cnt); BSM_HIP(hipGetLastError()); return BSM_OK; }
+    if (q.gr == R_ && q.gc == C_) { k_quad_pairs<R_, C_, false><<<g, kQuadThreads, lds, s>>>(q, cnt); BSM_HIP(hipGetLastError()); return BSM_OK; }
     BSM_QUAD_SHAPES(BSM_QP)
 #undef BSM_QP
     set_error("internal: no %d x %d group builder", q.gr, q.gc);
@@ -288,18 +360,25 @@ int quad_pairs(const QuadSymArgs &q, int64_t *cnt, hipStream_t s) {
 }
 
 int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s) {
-    const int64_t ngroups = (static_cast<int64_t>(q.r1 - q.r0) + q.gr - 1) / q.gr;
+    const int64_t ngroups = quad_groups(q);
     if (ngroups <= 0) return BSM_OK;
     if (q.nseg < 1 || q.kseg < 1) { set_error("internal: quad k segments"); return BSM_EINVAL; }
-    const size_t lds = sizeof(uint32_t) * 2 * quad_words(q.nbcols, q.gc) +
+    const size_t lds = sizeof(uint32_t) * 2 * quad_nwq(q) +
                        sizeof(int32_t) * kQuadWindow * (fill ? 2 : 1);
     const int64_t nblk = ngroups * q.nseg;
     if (nblk > (1ll << 31) - 1) { set_error("too many row groups in one chunk"); return BSM_EINVAL; }
     const unsigned g = static_cast<unsigned>(nblk);
+    if (q.map) {
+        if (q.gr != 2 || q.gc != 2) { set_error("internal: mixed groups are 2 x 2"); return BSM_EINVAL; }
+        if (fill) k_quad_stack<true, 2, 2, true><<<g, kQuadThreads, lds, s>>>(q);
+        else k_quad_stack<false, 2, 2, true><<<g, kQuadThreads, lds, s>>>(q);
+        BSM_HIP(hipGetLastError());
+        return BSM_OK;
+    }
 #define BSM_QS(R_, C_)                                                                     \
     if (q.gr == R_ && q.gc == C_) {                                                        \
-        if (fill) k_quad_stack<true, R_, C_><<<g, kQuadThreads, lds, s>>>(q);              \
-        else k_quad_stack<false, R_, C_><<<g, kQuadThreads, lds, s>>>(q);                  \
+        if (fill) k_quad_stack<true, R_, C_, false><<<g, kQuadThreads, lds, s>>>(q);       \
+        else k_quad_stack<false, R_, C_, false><<<g, kQuadThreads, lds, s>>>(q);           \
         BSM_HIP(hipGetLastError());                                                        \
         return BSM_OK;                                                                     \
     }

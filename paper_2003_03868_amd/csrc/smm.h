@@ -29,6 +29,8 @@ enum SmmVariant {
     kSmmF64Tuned = 5, // tunable run-time-shape kernel, parameters from the table
     kSmmF64Quad = 6,  // compile-time uniform shapes, one workgroup per 2 x 2 quad of
                       // C blocks (default for uniform sizes 5, 6, 13, 23, 26, 32)
+    kSmmF64MQuad = 7, // mixed sizes in {5, 13, 23, 26}: 2 x 2 groups over paired rows and
+                      // columns of equal size, every class in one persistent launch
 };
 
 struct SmmArgs {
@@ -95,6 +97,12 @@ bool smm_quad_available(int m, int n, int k);
 // asks for 4 (4 x 4) or 42 (4 x 2, size 23) and m has that kernel.
 void quad_shape(int m, int *gr, int *gc);
 int launch_quad(const SmmArgs &a, hipStream_t s);
+// Mixed-size groups (smm_mquad.hip): one persistent launch over a.n_quads
+// groups built with paired rows and columns (a.counter: work counter).
+int launch_mquad(const SmmArgs &a, hipStream_t s);
+// Work order of the mixed-size groups (largest m n first, group order within
+// a class) into order[a.n_quads]; rank_scratch holds a.n_quads bytes.
+int mquad_order(const SmmArgs &a, int8_t *rank_scratch, int64_t *order, hipStream_t s);
 
 // Reduced-precision products (smm_lowp.hip).
 int pack_lowp(const double *v, int64_t n, uint32_t *out, int prec, hipStream_t s);

@@ -302,6 +302,7 @@ k_smm_f64_fixed(SmmArgs a) {
 // index passes the product's k read zero.
 constexpr int kClassKmax = 26;   // largest k of the class set {5, 13, 23, 26}
 
+
 // Staging and multiply of one product with k known at compile time (the
 // class set's k in {5, 13, 23, 26}): fully unrolled k-steps, only the last
 // one masked.  Layout as in k_smm_f64_class: A (M x K) then B (K x N),
@@ -350,18 +351,24 @@ __device__ inline void class_compute(const double *sm, int bh, int bw, int x, in
     }
 }
 
+// LDS of one class C block: the two operand blocks, a zeroed tail and the
+// product metadata of the per-class kernel.
+template <int N>
+constexpr int class_tail() { return 4 * kClassKmax + 8 * N + 8; }
+constexpr int kMetaChunk = 64;
+struct ClassMeta {
+    int64_t off[2][2][kMetaChunk];   // [buffer][A, B][product]
+    int32_t k[2][kMetaChunk];
+};
+
+// C block c of class (M, N) on one wavefront (the per-class kernel's body).
 template <int M, int N>
-__global__ void __launch_bounds__(64)
-k_smm_f64_class(SmmArgs a) {
+__device__ inline void class_cblock(const SmmArgs &a, int64_t c, double *sm, ClassMeta &md) {
     constexpr int MT = (M + 3) / 4, NT = (N + 3) / 4;
     constexpr int HR = (MT + 1) / 2, HC = (NT + 1) / 2;
     constexpr int NA = (M * kClassKmax + kWave - 1) / kWave;
     constexpr int NB = (kClassKmax * N + kWave - 1) / kWave;
-    constexpr int TAIL = 4 * kClassKmax + 8 * N + 8;
-    __shared__ double sm[M * kClassKmax + kClassKmax * N + TAIL];
-    const int64_t item = xcd_item(a.nC);
-    if (item >= a.nC) return;
-    const int64_t c = a.worklist[a.c0 + item];
+    constexpr int TAIL = class_tail<N>();
     const int lane = threadIdx.x;
     const int x = lane >> 4, blk = (lane >> 2) & 3, y = lane & 3;
     const int bh = blk >> 1, bw = blk & 1;
@@ -374,9 +381,8 @@ k_smm_f64_class(SmmArgs a) {
     // at once, one product per lane, and kept in LDS (double-buffered; the next
     // chunk waits in registers), so the operand loads of product p + 1 never
     // wait on the chain stack -> block index -> offset of the same iteration.
-    constexpr int kMetaChunk = 64;
-    __shared__ int64_t m_off[2][2][kMetaChunk];   // [buffer][A, B][product]
-    __shared__ int32_t m_k[2][kMetaChunk];
+    auto &m_off = md.off;
+    auto &m_k = md.k;
     const int64_t p0 = a.seg[c - a.c0], np = a.seg[c - a.c0 + 1] - p0;
     int64_t r_aoff = 0, r_boff = 0;
     int r_k = 0;
@@ -493,6 +499,16 @@ k_smm_f64_class(SmmArgs a) {
         a.mx_out[c] = mx;
         if (!isfinite(sq)) atomicOr(a.flags, kFlagNonFinite);
     }
+}
+
+template <int M, int N>
+__global__ void __launch_bounds__(64)
+k_smm_f64_class(SmmArgs a) {
+    __shared__ double sm[M * kClassKmax + kClassKmax * N + class_tail<N>()];
+    __shared__ ClassMeta md;
+    const int64_t item = xcd_item(a.nC);
+    if (item >= a.nC) return;
+    class_cblock<M, N>(a, a.worklist[a.c0 + item], sm, md);
 }
 
 int class_of_size(int b) { return b == 5 ? 0 : b == 13 ? 1 : b == 23 ? 2 : b == 26 ? 3 : -1; }

@@ -1,0 +1,364 @@
+// FP64 block products for mixed block sizes in {5, 13, 23, 26}: every
+// (m, n) class of a chunk in one persistent launch, with the operand sharing
+// of the uniform quad kernel (smm_quad.hip).
+//
+// The work items are 2 x 2 groups of C blocks over paired rows and paired
+// columns of equal size (quad.hip, MAP), so all four C blocks of an item are
+// m x n and only k changes from entry to entry.  A fixed grid of four-wave
+// workgroups takes items from an atomic counter until none is left; each
+// item dispatches once on its (m, n) class to compile-time code, and each
+// entry on its k.  Per entry wave w stages operand w (A(i_0, k), A(i_1, k),
+// B(k, j_0), B(k, j_1)), each read from HBM once, into its LDS slot exactly
+// as it sits in HBM, and then multiplies C block (w / 2, w % 2) when the
+// entry holds that product.  The products and their order are those of the
+// per-class kernel (k_smm_f64_class: the same V_MFMA_F64_4X4X4_4B_F64
+// sequence per product, ascending k per C block), so the results are the
+// same bits.
+//
+// Entry metadata (operand offsets and k) is read for 64 entries at a time by
+// wave 0, one entry per lane, and kept in LDS: the entries of chunk c + 2 are
+// loaded at the start of chunk c, their operand offsets (which depend on
+// them) at the start of chunk c + 1, so no load of an iteration waits on
+// another load of the same iteration.
+#include "smm.h"
+
+namespace bsm {
+
+namespace {
+
+constexpr int kMqSlot = 26 * 26;                    // LDS doubles of one operand slot
+constexpr int kMqTail = 4 * 26 + 8 * 26 + 8;        // padded reads past the last slot
+constexpr int kMqChunk = 64;
+constexpr int kMqWaves = 4;
+constexpr int kMqNV = (kMqSlot + kWave - 1) / kWave;  // operand doubles per lane
+
+__device__ inline double mq_wave_sum(double v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ inline double mq_wave_max(double v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+__device__ inline int64_t mq_uniform64(int64_t v) {
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v)));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v >> 32)));
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// One product A (M x K, at sA) times B (K x N, at sB), both row-major in LDS,
+// into the lane's accumulators; the instruction sequence of the per-class
+// kernel's compile-time-k step.
+template <int M, int N, int K, int HR, int HC>
+__device__ inline void mq_compute(const double *sA, const double *sB, int bh, int bw, int x, int y,
+                                  double (&acc)[HR][HC]) {
+    constexpr int KS = (K + 3) / 4, KLAST = K - 4 * (KS - 1);
+    const int ra0 = (4 * bh * HR + y) * K + x, rb0 = x * N + 4 * bw * HC + y;
+    const bool ok = x < KLAST;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        double av[HR], bv[HC];
+#pragma unroll
+        for (int t = 0; t < HR; ++t) {
+            const double v = sA[ra0 + 4 * t * K + 4 * ks];
+            av[t] = (ks == KS - 1 && KLAST < 4 && !ok) ? 0.0 : v;
+        }
+#pragma unroll
+        for (int u = 0; u < HC; ++u) {
+            const double v = sB[rb0 + 4 * u + 4 * ks * N];
+            bv[u] = (ks == KS - 1 && KLAST < 4 && !ok) ? 0.0 : v;
+        }
+#pragma unroll
+        for (int t = 0; t < HR; ++t)
+#pragma unroll
+            for (int u = 0; u < HC; ++u)
+                acc[t][u] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[t], bv[u], acc[t][u], 0, 0, 0);
+    }
+}
+
+struct MqMeta {
+    int64_t off[2][kMqChunk][4];   // operand offsets of an entry (-1: absent)
+    int32_t k[2][kMqChunk];        // k of an entry
+};
+
+// Wave 0: operand offsets and k of the entry en (M rows in the A blocks).
+template <int M>
+__device__ inline void mq_offsets(const SmmArgs &a, int4 en, int64_t (&o)[4], int32_t &kk) {
+    o[0] = en.x >= 0 ? a.a_blk_off[en.x] : -1;
+    o[1] = en.y >= 0 ? a.a_blk_off[en.y] : -1;
+    o[2] = en.z >= 0 ? a.b_blk_off[en.z] : -1;
+    o[3] = en.w >= 0 ? a.b_blk_off[en.w] : -1;
+    const int ai = en.x >= 0 ? en.x : en.y;
+    kk = ai >= 0 ? static_cast<int32_t>((a.a_blk_off[ai + 1] - a.a_blk_off[ai]) / M) : 0;
+}
+
+// One work item (group) of class (M, N).
+template <int M, int N>
+__device__ __attribute__((noinline)) void mq_item(const SmmArgs &a, int64_t item, double *sm, MqMeta &md) {
+    constexpr int MT = (M + 3) / 4, NT = (N + 3) / 4;
+    constexpr int HR = (MT + 1) / 2, HC = (NT + 1) / 2;
+    const int lane = threadIdx.x % kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
+    const int rr = wv >> 1, cc = wv & 1;
+    const int x = lane >> 4, blk = (lane >> 2) & 3, y = lane & 3;
+    const int bh = blk >> 1, bw = blk & 1;
+    const int64_t e0 = a.q_seg[item], ne = a.q_seg[item + 1] - e0;
+
+    double acc[HR][HC];
+#pragma unroll
+    for (int t = 0; t < HR; ++t)
+#pragma unroll
+        for (int u = 0; u < HC; ++u) acc[t][u] = 0.0;
+
+    // metadata pipeline (wave 0): chunk 0 into LDS now, chunk 1's offsets
+    // and chunk 2's entries into registers
+    int64_t roff[4] = {-1, -1, -1, -1};
+    int32_t rk = 0;
+    int4 creg = make_int4(-1, -1, -1, -1);
+    if (wv == 0) {
+        if (lane < ne) {
+            int64_t o[4];
+            int32_t kk;
+            mq_offsets<M>(a, a.q_ent[e0 + lane], o, kk);
+#pragma unroll
+            for (int z = 0; z < 4; ++z) md.off[0][lane][z] = o[z];
+            md.k[0][lane] = kk;
+        }
+        if (kMqChunk + lane < ne) mq_offsets<M>(a, a.q_ent[e0 + kMqChunk + lane], roff, rk);
+        if (2 * kMqChunk + lane < ne) creg = a.q_ent[e0 + 2 * kMqChunk + lane];
+    }
+    __syncthreads();
+
+    // entry t's metadata from LDS (wave-uniform): present operands, this
+    // wave's operand offset, k
+    auto fetch = [&](int64_t t, unsigned &hm, int64_t &my_off, int &kk) {
+        hm = 0;
+        my_off = -1;
+        kk = 0;
+        if (t >= ne) return;
+        const int b = static_cast<int>((t / kMqChunk) & 1), i = static_cast<int>(t % kMqChunk);
+#pragma unroll
+        for (int z = 0; z < 4; ++z) {
+            const int64_t o = mq_uniform64(md.off[b][i][z]);
+            if (o >= 0) hm |= 1u << z;
+            if (z == wv) my_off = o;
+        }
+        kk = __builtin_amdgcn_readfirstlane(md.k[b][i]);
+    };
+    double pv[kMqNV];
+    auto load_op = [&](int64_t off, int kk) {
+        if (off < 0) return;
+        const double *g = (wv < 2 ? a.a_vals : a.b_vals) + off;
+        const int len = (wv < 2 ? M : N) * kk;
+#pragma unroll
+        for (int v = 0; v < kMqNV; ++v)
+            if (lane + v * kWave < len) pv[v] = g[lane + v * kWave];
+    };
+
+    unsigned nhm;
+    int64_t noff;
+    int nk;
+    fetch(0, nhm, noff, nk);
+    load_op(noff, nk);
+    for (int64_t t = 0; t < ne; ++t) {
+        const unsigned hm = nhm;
+        const int k = nk;
+        if ((hm >> wv) & 1u) {
+            const int len = (wv < 2 ? M : N) * k;
+            double *slot = sm + wv * kMqSlot;
+#pragma unroll
+            for (int v = 0; v < kMqNV; ++v)
+                if (lane + v * kWave < len) slot[lane + v * kWave] = pv[v];
+        }
+        const int64_t t1 = t + 1;
+        if ((t1 % kMqChunk) == 0 && t1 < ne && wv == 0) {
+            // entering chunk t1 / 64: its metadata (ready in registers) goes
+            // to LDS; the next chunk's offsets and the one after's entries
+            // are loaded
+            const int b = static_cast<int>((t1 / kMqChunk) & 1);
+#pragma unroll
+            for (int z = 0; z < 4; ++z) md.off[b][lane][z] = roff[z];
+            md.k[b][lane] = rk;
+            if (t1 + kMqChunk + lane < ne) mq_offsets<M>(a, creg, roff, rk);
+            if (t1 + 2 * kMqChunk + lane < ne) creg = a.q_ent[e0 + t1 + 2 * kMqChunk + lane];
+        }
+        __syncthreads();
+        fetch(t1, nhm, noff, nk);
+        load_op(noff, nk);
+        if (((hm >> rr) & 1u) && ((hm >> (2 + cc)) & 1u)) {
+            const double *sA = sm + rr * kMqSlot, *sB = sm + (2 + cc) * kMqSlot;
+            switch (k) {
+                case 5: mq_compute<M, N, 5, HR, HC>(sA, sB, bh, bw, x, y, acc); break;
+                case 13: mq_compute<M, N, 13, HR, HC>(sA, sB, bh, bw, x, y, acc); break;
+                case 23: mq_compute<M, N, 23, HR, HC>(sA, sB, bh, bw, x, y, acc); break;
+                case 26: mq_compute<M, N, 26, HR, HC>(sA, sB, bh, bw, x, y, acc); break;
+                default: break;
+            }
+        }
+        __syncthreads();
+    }
+
+    // epilogue: this wave's C block
+    const int64_t cb = a.q_cblk[4 * item + 2 * rr + cc];
+    if (cb >= 0) {
+        const int64_t co = a.c_blk_off[cb];
+        const double *cin = nullptr;
+        if (a.cin_map) {
+            const int64_t tt = a.cin_map[cb];
+            if (tt >= 0) cin = a.cin_vals + a.cin_blk_off[tt];
+        }
+        double sq = 0.0, mx = 0.0;
+#pragma unroll
+        for (int t = 0; t < HR; ++t)
+#pragma unroll
+            for (int u = 0; u < HC; ++u) {
+                const int row = 4 * (bh * HR + t) + x, col = 4 * (bw * HC + u) + y;
+                if (row < M && col < N) {
+                    double v = a.alpha * acc[t][u];
+                    if (cin) v += a.beta * cin[row * N + col];
+                    a.c_vals[co + row * N + col] = v;
+                    sq += v * v;
+                    mx = fmax(mx, fabs(v));
+                }
+            }
+        sq = mq_wave_sum(sq);
+        mx = mq_wave_max(mx);
+        if (lane == 0) {
+            a.sq_out[cb] = sq;
+            a.mx_out[cb] = mx;
+            if (!isfinite(sq)) atomicOr(a.flags, kFlagNonFinite);
+        }
+    }
+}
+
+// Class of item (m, n) from its first C block: 4 class(m) + class(n), or -1.
+__device__ inline int mq_class(const SmmArgs &a, int64_t item) {
+    int64_t cb = -1;
+    for (int z = 0; z < 4 && cb < 0; ++z) cb = a.q_cblk[4 * item + z];
+    if (cb < 0) return -1;
+    auto cls = [](int b) { return b == 5 ? 0 : b == 13 ? 1 : b == 23 ? 2 : b == 26 ? 3 : -1; };
+    const int cm = cls(a.c_rbs[a.c_row[cb]]), cn = cls(a.c_cbs[a.c_col[cb]]);
+    return (cm < 0 || cn < 0) ? -1 : 4 * cm + cn;
+}
+
+__global__ void __launch_bounds__(64 * kMqWaves) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_smm_f64_mquad(SmmArgs a, unsigned long long *counter) {
+    __shared__ double sm[4 * kMqSlot + kMqTail];
+    __shared__ MqMeta md;
+    __shared__ int64_t s_item;
+    __shared__ int s_cls;
+    for (int e = 4 * kMqSlot + static_cast<int>(threadIdx.x); e < 4 * kMqSlot + kMqTail; e += 64 * kMqWaves)
+        sm[e] = 0.0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int64_t it = static_cast<int64_t>(atomicAdd(counter, 1ull));
+            s_item = it;
+            s_cls = it < a.n_quads ? mq_class(a, a.q_order ? a.q_order[it] : it) : -1;
+        }
+        __syncthreads();
+        const int64_t it = s_item;
+        const int cls = s_cls;
+        __syncthreads();                 // s_item, s_cls are rewritten by the next item
+        if (it >= a.n_quads) break;      // every wave of the workgroup leaves together
+        const int64_t item = a.q_order ? a.q_order[it] : it;
+        switch (cls) {
+#define BSM_MQ(ID, MM, NN) case ID: mq_item<MM, NN>(a, item, sm, md); break;
+            BSM_MQ(0, 5, 5) BSM_MQ(1, 5, 13) BSM_MQ(2, 5, 23) BSM_MQ(3, 5, 26)
+            BSM_MQ(4, 13, 5) BSM_MQ(5, 13, 13) BSM_MQ(6, 13, 23) BSM_MQ(7, 13, 26)
+            BSM_MQ(8, 23, 5) BSM_MQ(9, 23, 13) BSM_MQ(10, 23, 23) BSM_MQ(11, 23, 26)
+            BSM_MQ(12, 26, 5) BSM_MQ(13, 26, 13) BSM_MQ(14, 26, 23) BSM_MQ(15, 26, 26)
+#undef BSM_MQ
+            default: break;
+        }
+    }
+}
+
+__global__ void k_mq_zero(unsigned long long *p) { *p = 0ull; }
+
+// Work order of the groups: by class, the classes with the most work per
+// product first (m n descending), ascending group index inside a class, so
+// that the workgroups of a CU run the same class's code at the same time
+// (the sixteen class bodies together exceed the instruction cache) and a
+// class's groups keep their spatial order.
+constexpr int kMqOrderThreads = 1024;
+__device__ inline int mq_rank_of_class(int cls) {
+    // class 4 cm + cn of sizes {5, 13, 23, 26}, ranked by m n descending
+    // (676, 598, 598, 529, 338, 338, 299, 299, 169, 130, 130, 115, 115, 65, 65, 25)
+    constexpr int rank[16] = {15, 13, 11, 9, 14, 8, 6, 4, 12, 7, 3, 1, 10, 5, 2, 0};
+    return cls < 0 ? 15 : rank[cls];
+}
+
+__global__ void k_mq_class_of(SmmArgs a, int8_t *rank) {
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= a.n_quads) return;
+    rank[q] = static_cast<int8_t>(mq_rank_of_class(mq_class(a, q)));
+}
+
+// One workgroup per rank r: the positions of rank r's groups, in ascending
+// group order, after every group of a smaller rank.
+__global__ void __launch_bounds__(kMqOrderThreads)
+k_mq_order(const int8_t *rank, int64_t n, int64_t *order) {
+    __shared__ int64_t s_wave[kMqOrderThreads / kWave];
+    __shared__ int64_t s_base, s_run;
+    const int r = blockIdx.x;
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    // groups of smaller rank
+    int64_t before = 0;
+    for (int64_t q = threadIdx.x; q < n; q += kMqOrderThreads) before += rank[q] < r ? 1 : 0;
+    for (int o = kWave / 2; o > 0; o >>= 1) before += __shfl_xor(before, o, kWave);
+    if (lane == 0) s_wave[wid] = before;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t b = 0;
+        for (int w = 0; w < kMqOrderThreads / kWave; ++w) b += s_wave[w];
+        s_base = b;
+        s_run = 0;
+    }
+    __syncthreads();
+    for (int64_t q0 = 0; q0 < n; q0 += kMqOrderThreads) {
+        const int64_t q = q0 + threadIdx.x;
+        const int mine = (q < n && rank[q] == r) ? 1 : 0;
+        // block-wide exclusive scan of `mine`
+        const unsigned long long ball = __ballot(mine);
+        const int in_wave = __popcll(ball & ((1ull << lane) - 1ull));
+        __syncthreads();
+        if (lane == 0) s_wave[wid] = __popcll(ball);
+        __syncthreads();
+        int64_t off = 0;
+        for (int w = 0; w < wid; ++w) off += s_wave[w];
+        if (mine) order[s_base + s_run + off + in_wave] = q;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t t = 0;
+            for (int w = 0; w < kMqOrderThreads / kWave; ++w) t += s_wave[w];
+            s_run += t;
+        }
+    }
+}
+
+}  // namespace
+
+int mquad_order(const SmmArgs &a, int8_t *rank_scratch, int64_t *order, hipStream_t s) {
+    if (a.n_quads <= 0) return BSM_OK;
+    k_mq_class_of<<<grid_for(a.n_quads, 256), 256, 0, s>>>(a, rank_scratch);
+    k_mq_order<<<16, kMqOrderThreads, 0, s>>>(rank_scratch, a.n_quads, order);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+int launch_mquad(const SmmArgs &a, hipStream_t s) {
+    if (a.n_quads <= 0) return BSM_OK;
+    if (!a.counter) { set_error("internal: mixed quads need a work counter"); return BSM_EINVAL; }
+    int dev = 0, cus = 256;
+    BSM_HIP(hipGetDevice(&dev));
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // workgroups resident per CU: LDS (about 30 KB each) allows five
+    const int64_t want = static_cast<int64_t>(cus) * 5;
+    const unsigned grid = static_cast<unsigned>(want < a.n_quads ? want : a.n_quads);
+    k_mq_zero<<<1, 1, 0, s>>>(a.counter);
+    k_smm_f64_mquad<<<grid, 64 * kMqWaves, 0, s>>>(a, a.counter);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+}  // namespace bsm

@@ -76,6 +76,16 @@ struct QuadSymArgs {
     double tau2;
     int32_t *pm;
     unsigned long long *kept;
+    // mixed block sizes (map = 1; 2 x 2 only): groups over paired rows and
+    // columns of equal size instead of consecutive ones
+    int32_t map;
+    int32_t g0;                  // first row group of this chunk
+    int64_t ngroups;             // row groups of this chunk
+    int32_t ncg;                 // column groups
+    const int32_t *rg;           // [2 G] rows of row group g (second -1 for a single row)
+    const int32_t *cgrp;         // [nbcols] column group of column j
+    const int32_t *cslot;        // [nbcols] slot (0 or 1) of column j in its group
+    const int32_t *cmap;         // [2 ncg] columns of column group Q (second -1 for one)
 };
 int quad_pairs(const QuadSymArgs &q, int64_t *cnt, hipStream_t s);
 int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s);

@@ -289,6 +289,40 @@ def test_multiply_mixed_class_sizes(orc, monkeypatch, variant):
     assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"variant {variant} chunked")
 
 
+@pytest.mark.parametrize("shape", [(45, 29, 37), (70, 70, 70), (3, 5, 2)], ids=["rect", "square", "tiny"])
+def test_mixed_quads_vs_oracle_and_class_kernel(orc, monkeypatch, shape):
+    """Mixed sizes from {5, 13, 23, 26} through the paired-group kernel (one
+    persistent launch over every (m, n) class): the oracle's product, and
+    bit for bit the per-class kernels' (the default for such sizes), which
+    sum the same products in the same order with the same instructions.
+    Row and column counts that leave rows unpaired, C_in blocks without
+    products, many chunks (bands of 32 rows) and three k segments."""
+    nbr, nbk, nbc = shape
+    rng = np.random.default_rng(900 + nbr)
+    rs, ks, cs = (rng.choice([5, 13, 23, 26], n) for n in (nbr, nbk, nbc))
+    a = synth.random_bsr(nbr, nbk, rs, ks, 0.4, rng)
+    b = synth.random_bsr(nbk, nbc, ks, cs, 0.4, rng)
+    c = synth.random_bsr(nbr, nbc, rs, cs, 0.3, rng)
+    for alpha, beta, cc in [(1.0, 0.0, None), (-0.5, 1.5, c)]:
+        ref = orc.multiply(alpha, a, b, beta, cc)
+        monkeypatch.setenv("BSM_SMM_VARIANT", "7")
+        got, st = _run(alpha, a, b, beta, cc)
+        assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"mixed quads {shape} beta={beta}")
+        for v in ("4", "6"):
+            monkeypatch.setenv("BSM_SMM_VARIANT", v)
+            cls, _ = _run(alpha, a, b, beta, cc)
+            assert np.array_equal(got.values, cls.values), "mixed quads and class kernels differ"
+        monkeypatch.setenv("BSM_SMM_VARIANT", "7")
+        monkeypatch.setenv("BSM_CHUNK_PRODUCTS", "200")
+        monkeypatch.setenv("BSM_QUAD_KSEG", "3")
+        chunked, st2 = _run(alpha, a, b, beta, cc)
+        if nbr > 32:
+            assert st2.smm_launches > 1
+        assert np.array_equal(chunked.values, got.values), "chunks or k segments changed the result"
+        monkeypatch.delenv("BSM_CHUNK_PRODUCTS")
+        monkeypatch.delenv("BSM_QUAD_KSEG")
+
+
 CATALOGUE = [(f, w, p) for f in (0, 1) for w in (1, 2, 4) for p in (0, 1)]
 
 
