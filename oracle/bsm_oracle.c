@@ -9,7 +9,7 @@
  * with the HIP library.
  *
  * Everything here is plain C, FP64, explicit loops, no BLAS, compiled with
- * -O2 -ffp-contract=off so that no multiply-add is fused.  OpenMP only
+ * -O3 -ffp-contract=off so that no multiply-add is fused.  OpenMP only
  * splits independent block rows between threads; each output element is
  * summed by one thread in ascending k.
  *
