@@ -415,9 +415,10 @@ def main():
     ap.add_argument("--prec", choices=["fp64", "fp32", "bf16", "bf16x3"], default="fp64",
                     help="block-product precision: fp32, split-bf16 with two (bf16) or three "
                          "(bf16x3) parts per operand; all switch to FP64 once r_k < 1e-4")
-    ap.add_argument("--table", choices=["exhaustive", "mlp", "none"], default="exhaustive",
+    ap.add_argument("--table", choices=["exhaustive", "mlp", "mlp_raw", "none"], default="exhaustive",
                     help="kernel-parameter table: measured (exhaustive autotuning), predicted "
-                         "by the MLP, or none (built-in choices)")
+                         "by the MLP ensemble (exhaustive where its members disagree; mlp_raw: "
+                         "the prediction everywhere), or none (built-in choices)")
     ap.add_argument("--order", type=int, choices=[2, 3, 5, 7], default=2,
                     help="sign iteration order: 2 Newton-Schulz, 3, 5 (four multiplies per iteration)")
     ap.add_argument("--overlap", type=float, default=0.0, metavar="TAU",

@@ -86,6 +86,8 @@ typedef struct {
     int32_t smm_launches;        /* number of block-product kernel launches */
     int32_t pad_;
     int64_t n_screened;          /* products left out by norm screening (of n_products) */
+    double class_ms[16];         /* mixed sizes, one launch per (m, n) class: device time of
+                                    class 4 c(m) + c(n), c = 0..3 for sizes 5, 13, 23, 26 */
 } bsm_mult_stats;
 
 typedef struct {
@@ -125,6 +127,7 @@ typedef struct {
     int64_t n_screened;      /* products left out by norm screening */
     int64_t nnzb_x_hist[128];/* stored blocks of X_k, k = 0..iterations */
     int64_t nnzb_y_hist[128];/* stored blocks of Y_k = filter(X_k X_k), k = 0..iterations */
+    double class_ms[16];     /* bsm_mult_stats.class_ms summed over the multiplies */
 } bsm_sign_stats;
 
 /* Bisection record of bsm_mu_bisect. */

@@ -39,7 +39,8 @@ class bsm_mult_stats(C.Structure):
     _fields_ = [("n_products", C.c_int64), ("flops", C.c_double),
                 ("nnzb_unfiltered", C.c_int64), ("nnzb", C.c_int64),
                 ("smm_ms", C.c_double), ("total_ms", C.c_double),
-                ("smm_launches", C.c_int32), ("pad_", C.c_int32), ("n_screened", C.c_int64)]
+                ("smm_launches", C.c_int32), ("pad_", C.c_int32), ("n_screened", C.c_int64),
+                ("class_ms", C.c_double * 16)]
 
 
 class bsm_sign_opts(C.Structure):
@@ -59,7 +60,7 @@ class bsm_sign_stats(C.Structure):
                 ("graph_replays", C.c_int32), ("graph_fallbacks", C.c_int32),
                 ("smm_launches", C.c_int32), ("pad_", C.c_int32),
                 ("n_screened", C.c_int64), ("nnzb_x_hist", C.c_int64 * 128),
-                ("nnzb_y_hist", C.c_int64 * 128)]
+                ("nnzb_y_hist", C.c_int64 * 128), ("class_ms", C.c_double * 16)]
 
 
 class bsm_mu_stats(C.Structure):

@@ -152,11 +152,13 @@ struct Events {
     bool on = false;
     hipEvent_t t0{}, t1{};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> smm;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> cls;   // per-class launches
     ~Events() {
         if (!on) return;
         (void)hipEventDestroy(t0);
         (void)hipEventDestroy(t1);
         for (auto &p : smm) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+        for (auto &p : cls) { (void)hipEventDestroy(p.second.first); (void)hipEventDestroy(p.second.second); }
     }
 };
 struct Scratch {
@@ -625,7 +627,17 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
                     op.kind = kOpVariant;
                     op.id = kSmmF64Tuned;
                 }
+                std::pair<hipEvent_t, hipEvent_t> ce{};
+                if (ev.on && b < 16) {
+                    BSM_HIP(hipEventCreate(&ce.first));
+                    BSM_HIP(hipEventCreate(&ce.second));
+                    BSM_HIP(hipEventRecord(ce.first, s));
+                }
                 st = launch(op);
+                if (ev.on && b < 16) {
+                    BSM_HIP(hipEventRecord(ce.second, s));
+                    ev.cls.push_back({b, ce});
+                }
                 off += hist[b];
             }
         } else {
@@ -716,6 +728,10 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         }
         stats->smm_ms = smm;
         stats->total_ms = (hipEventElapsedTime(&ms, ev.t0, ev.t1) == hipSuccess) ? ms : 0.0;
+        for (int b = 0; b < 16; ++b) stats->class_ms[b] = 0.0;
+        for (auto &p : ev.cls)
+            if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess)
+                stats->class_ms[p.first] += ms;
     }
     if (pl) {
         pl->alpha = alpha; pl->beta = beta; pl->eps = eps; pl->norm = norm; pl->prec = prec;

@@ -259,6 +259,7 @@ static int higher_order_update(const bsm_sign_opts &o, int prec, Mat &X, Mat &Y,
         st->n_products += ms.n_products;
         st->smm_launches += ms.smm_launches;
         st->smm_ms += ms.smm_ms;
+        for (int b = 0; b < 16; ++b) st->class_ms[b] += ms.class_ms[b];
         return rc;
     };
     Mat *c = nullptr, *y2 = nullptr, *v = nullptr, *y3 = nullptr, *v1 = nullptr;
@@ -445,6 +446,7 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
             st->n_screened += ms.n_screened;
             st->smm_launches += ms.smm_launches;
             st->smm_ms += ms.smm_ms;
+            for (int b = 0; b < 16; ++b) st->class_ms[b] += ms.class_ms[b];
         }
         if (rc != BSM_OK && rc != BSM_ENONFINITE) break;
         double d = 0.0;
@@ -481,6 +483,7 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
         st->n_screened += ms.n_screened;
         st->smm_launches += ms.smm_launches;
         st->smm_ms += ms.smm_ms;
+        for (int b = 0; b < 16; ++b) st->class_ms[b] += ms.class_ms[b];
         if (rc != BSM_OK) break;
         if (want_graph && R.psq && R.pup) {
             rc = maybe_enter(R, *X, *Y, prec, s);

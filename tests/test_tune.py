@@ -24,6 +24,38 @@ def test_model_choices_are_valid_entries():
     for key in keys:
         assert tab[key] in tune.entries_for(*key)
         assert tab[key] == tune.predict(model, *key, 60000, 32)
+    # with the exhaustive table as fallback, undecided keys take its entry
+    exh = tune.load_table()
+    tab2 = tune.table_from_model(model, keys, fallback=exh)
+    for key in keys:
+        want = tab[key] if key in tune.table_from_model.trusted else exh[key]
+        assert tab2[key] == want
+
+
+def test_ensemble_trust_and_fallback():
+    """An ensemble whose members disagree on a shape falls back to the
+    exhaustive best there (regret 0), and agrees with its members where they
+    agree."""
+    rng = np.random.default_rng(4)
+    recs = _synthetic_records(rng, 200)
+    model, rep = tune.train_ensemble(recs, members=3, epochs=60)
+    assert len(tune.members_of(model)) == 3
+    te = tune.split_triples(recs)[1]
+    assert rep["test_with_fallback"]["mean"] <= rep["test_ensemble"]["mean"] + 1e-12
+    assert 0.0 <= rep["trusted_share_test"] <= 1.0
+    r = te[0]
+    picks = {tune.predict(m, r["m"], r["n"], r["k"], r["n_c"] * r["per_c"], r["per_c"])
+             for m in tune.members_of(model)}
+    if len(picks) == 1:
+        assert tune.predict(model, r["m"], r["n"], r["k"], r["n_c"] * r["per_c"], r["per_c"]) in picks
+
+
+def test_operand_reuse_feature():
+    """The occupancy input: products per operand block of the stack."""
+    assert tune.operand_reuse(2048 * 8, 13) == 8.0
+    assert tune.operand_reuse(2048 * 8 * 4, 0) == 8.0
+    f = tune.features(23, 23, 23, 60000, 32)
+    assert len(f) == 9 and abs(f[-1] - math.log2(60000 / 2048) / 8.0) < 1e-12
 
 
 def _synthetic_records(rng, n_triples=300):
@@ -41,8 +73,10 @@ def _synthetic_records(rng, n_triples=300):
 
 
 def test_training_learns_a_known_rule():
+    # 600 triples: the rule turns on m = 16, 32, so a smaller held-out set
+    # may hold almost none of them
     rng = np.random.default_rng(0)
-    recs = _synthetic_records(rng)
+    recs = _synthetic_records(rng, 600)
     model, rep = tune.train(recs, epochs=150, seed=1)
     assert rep["test"]["mean"] < 0.05
     assert rep["test"]["mean"] < tune.default_regret(tune.split_triples(recs)[1], (0, 2, 0))["mean"]
