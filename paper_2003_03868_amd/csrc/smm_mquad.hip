@@ -20,6 +20,8 @@
 // loaded at the start of chunk c, their operand offsets (which depend on
 // them) at the start of chunk c + 1, so no load of an iteration waits on
 // another load of the same iteration.
+#include <cstdlib>
+
 #include "smm.h"
 
 namespace bsm {
@@ -92,8 +94,9 @@ __device__ inline void mq_offsets(const SmmArgs &a, int4 en, int64_t (&o)[4], in
     kk = ai >= 0 ? static_cast<int32_t>((a.a_blk_off[ai + 1] - a.a_blk_off[ai]) / M) : 0;
 }
 
-// One work item (group) of class (M, N).
-template <int M, int N>
+// One work item (group) of class (M, N); EPS entries are staged per barrier
+// pair (slot set q of LDS holds entry t + q).
+template <int M, int N, int EPS>
 __device__ __attribute__((noinline)) void mq_item(const SmmArgs &a, int64_t item, double *sm, MqMeta &md) {
     constexpr int MT = (M + 3) / 4, NT = (N + 3) / 4;
     constexpr int HR = (MT + 1) / 2, HC = (NT + 1) / 2;
@@ -145,32 +148,40 @@ __device__ __attribute__((noinline)) void mq_item(const SmmArgs &a, int64_t item
         }
         kk = __builtin_amdgcn_readfirstlane(md.k[b][i]);
     };
-    double pv[kMqNV];
-    auto load_op = [&](int64_t off, int kk) {
+    double pv[EPS][kMqNV];
+    auto load_op = [&](int64_t off, int kk, double (&p)[kMqNV]) {
         if (off < 0) return;
         const double *g = (wv < 2 ? a.a_vals : a.b_vals) + off;
         const int len = (wv < 2 ? M : N) * kk;
 #pragma unroll
         for (int v = 0; v < kMqNV; ++v)
-            if (lane + v * kWave < len) pv[v] = g[lane + v * kWave];
+            if (lane + v * kWave < len) p[v] = g[lane + v * kWave];
     };
 
-    unsigned nhm;
-    int64_t noff;
-    int nk;
-    fetch(0, nhm, noff, nk);
-    load_op(noff, nk);
-    for (int64_t t = 0; t < ne; ++t) {
-        const unsigned hm = nhm;
-        const int k = nk;
-        if ((hm >> wv) & 1u) {
-            const int len = (wv < 2 ? M : N) * k;
-            double *slot = sm + wv * kMqSlot;
+    unsigned nhm[EPS];
+    int64_t noff[EPS];
+    int nk[EPS];
 #pragma unroll
-            for (int v = 0; v < kMqNV; ++v)
-                if (lane + v * kWave < len) slot[lane + v * kWave] = pv[v];
+    for (int q = 0; q < EPS; ++q) {
+        fetch(q, nhm[q], noff[q], nk[q]);
+        load_op(noff[q], nk[q], pv[q]);
+    }
+    for (int64_t t = 0; t < ne; t += EPS) {
+        unsigned hm[EPS];
+        int k[EPS];
+#pragma unroll
+        for (int q = 0; q < EPS; ++q) {
+            hm[q] = nhm[q];
+            k[q] = nk[q];
+            if ((hm[q] >> wv) & 1u) {
+                const int len = (wv < 2 ? M : N) * k[q];
+                double *slot = sm + (4 * q + wv) * kMqSlot;
+#pragma unroll
+                for (int v = 0; v < kMqNV; ++v)
+                    if (lane + v * kWave < len) slot[lane + v * kWave] = pv[q][v];
+            }
         }
-        const int64_t t1 = t + 1;
+        const int64_t t1 = t + EPS;
         if ((t1 % kMqChunk) == 0 && t1 < ne && wv == 0) {
             // entering chunk t1 / 64: its metadata (ready in registers) goes
             // to LDS; the next chunk's offsets and the one after's entries
@@ -183,16 +194,22 @@ __device__ __attribute__((noinline)) void mq_item(const SmmArgs &a, int64_t item
             if (t1 + 2 * kMqChunk + lane < ne) creg = a.q_ent[e0 + t1 + 2 * kMqChunk + lane];
         }
         __syncthreads();
-        fetch(t1, nhm, noff, nk);
-        load_op(noff, nk);
-        if (((hm >> rr) & 1u) && ((hm >> (2 + cc)) & 1u)) {
-            const double *sA = sm + rr * kMqSlot, *sB = sm + (2 + cc) * kMqSlot;
-            switch (k) {
-                case 5: mq_compute<M, N, 5, HR, HC>(sA, sB, bh, bw, x, y, acc); break;
-                case 13: mq_compute<M, N, 13, HR, HC>(sA, sB, bh, bw, x, y, acc); break;
-                case 23: mq_compute<M, N, 23, HR, HC>(sA, sB, bh, bw, x, y, acc); break;
-                case 26: mq_compute<M, N, 26, HR, HC>(sA, sB, bh, bw, x, y, acc); break;
-                default: break;
+#pragma unroll
+        for (int q = 0; q < EPS; ++q) {
+            fetch(t1 + q, nhm[q], noff[q], nk[q]);
+            load_op(noff[q], nk[q], pv[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < EPS; ++q) {
+            if (((hm[q] >> rr) & 1u) && ((hm[q] >> (2 + cc)) & 1u)) {
+                const double *sA = sm + (4 * q + rr) * kMqSlot, *sB = sm + (4 * q + 2 + cc) * kMqSlot;
+                switch (k[q]) {
+                    case 5: mq_compute<M, N, 5, HR, HC>(sA, sB, bh, bw, x, y, acc); break;
+                    case 13: mq_compute<M, N, 13, HR, HC>(sA, sB, bh, bw, x, y, acc); break;
+                    case 23: mq_compute<M, N, 23, HR, HC>(sA, sB, bh, bw, x, y, acc); break;
+                    case 26: mq_compute<M, N, 26, HR, HC>(sA, sB, bh, bw, x, y, acc); break;
+                    default: break;
+                }
             }
         }
         __syncthreads();
@@ -241,13 +258,18 @@ __device__ inline int mq_class(const SmmArgs &a, int64_t item) {
     return (cm < 0 || cn < 0) ? -1 : 4 * cm + cn;
 }
 
-__global__ void __launch_bounds__(64 * kMqWaves) __attribute__((amdgpu_waves_per_eu(4, 8)))
+// EPS entries per barrier pair; WPE: the occupancy target (LDS allows five
+// workgroups per CU with one entry per stage, three with two).
+template <int EPS, int WPE>
+__global__ void __launch_bounds__(64 * kMqWaves) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_smm_f64_mquad(SmmArgs a, unsigned long long *counter) {
-    __shared__ double sm[4 * kMqSlot + kMqTail];
+    static_assert(kMqChunk % EPS == 0, "stages must not straddle metadata chunks");
+    __shared__ double sm[EPS * 4 * kMqSlot + kMqTail];
     __shared__ MqMeta md;
     __shared__ int64_t s_item;
     __shared__ int s_cls;
-    for (int e = 4 * kMqSlot + static_cast<int>(threadIdx.x); e < 4 * kMqSlot + kMqTail; e += 64 * kMqWaves)
+    for (int e = EPS * 4 * kMqSlot + static_cast<int>(threadIdx.x); e < EPS * 4 * kMqSlot + kMqTail;
+         e += 64 * kMqWaves)
         sm[e] = 0.0;
     for (;;) {
         if (threadIdx.x == 0) {
@@ -262,7 +284,7 @@ k_smm_f64_mquad(SmmArgs a, unsigned long long *counter) {
         if (it >= a.n_quads) break;      // every wave of the workgroup leaves together
         const int64_t item = a.q_order ? a.q_order[it] : it;
         switch (cls) {
-#define BSM_MQ(ID, MM, NN) case ID: mq_item<MM, NN>(a, item, sm, md); break;
+#define BSM_MQ(ID, MM, NN) case ID: mq_item<MM, NN, EPS>(a, item, sm, md); break;
             BSM_MQ(0, 5, 5) BSM_MQ(1, 5, 13) BSM_MQ(2, 5, 23) BSM_MQ(3, 5, 26)
             BSM_MQ(4, 13, 5) BSM_MQ(5, 13, 13) BSM_MQ(6, 13, 23) BSM_MQ(7, 13, 26)
             BSM_MQ(8, 23, 5) BSM_MQ(9, 23, 13) BSM_MQ(10, 23, 23) BSM_MQ(11, 23, 26)
@@ -346,17 +368,29 @@ int mquad_order(const SmmArgs &a, int8_t *rank_scratch, int64_t *order, hipStrea
     return BSM_OK;
 }
 
+// Entries staged per barrier pair (1 or 2); BSM_MQUAD_STAGE overrides the
+// default.  Two halve the barriers per entry but take occupancy from four
+// workgroups per CU to three: 10.3 s of block products per sign step on the
+// mixed workload against 8.9 s with one.
+static int mquad_stage() {
+    const char *e = getenv("BSM_MQUAD_STAGE");
+    return (e && atoi(e) == 2) ? 2 : 1;
+}
+
 int launch_mquad(const SmmArgs &a, hipStream_t s) {
     if (a.n_quads <= 0) return BSM_OK;
     if (!a.counter) { set_error("internal: mixed quads need a work counter"); return BSM_EINVAL; }
     int dev = 0, cus = 256;
     BSM_HIP(hipGetDevice(&dev));
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // workgroups resident per CU: LDS (about 30 KB each) allows five
-    const int64_t want = static_cast<int64_t>(cus) * 5;
+    // workgroups resident per CU: LDS (about 29 KB each with one entry per
+    // stage, 50 KB with two) allows five or three
+    const int eps = mquad_stage();
+    const int64_t want = static_cast<int64_t>(cus) * (eps == 2 ? 3 : 5);
     const unsigned grid = static_cast<unsigned>(want < a.n_quads ? want : a.n_quads);
     k_mq_zero<<<1, 1, 0, s>>>(a.counter);
-    k_smm_f64_mquad<<<grid, 64 * kMqWaves, 0, s>>>(a, a.counter);
+    if (eps == 2) k_smm_f64_mquad<2, 3><<<grid, 64 * kMqWaves, 0, s>>>(a, a.counter);
+    else k_smm_f64_mquad<1, 4><<<grid, 64 * kMqWaves, 0, s>>>(a, a.counter);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }

@@ -289,14 +289,18 @@ def test_multiply_mixed_class_sizes(orc, monkeypatch, variant):
     assert_same_matrix(got, ref, TOL_FP64_MULTIPLY, f"variant {variant} chunked")
 
 
+@pytest.mark.parametrize("stage", ["1", "2"])
 @pytest.mark.parametrize("shape", [(45, 29, 37), (70, 70, 70), (3, 5, 2)], ids=["rect", "square", "tiny"])
-def test_mixed_quads_vs_oracle_and_class_kernel(orc, monkeypatch, shape):
+def test_mixed_quads_vs_oracle_and_class_kernel(orc, monkeypatch, shape, stage):
     """Mixed sizes from {5, 13, 23, 26} through the paired-group kernel (one
     persistent launch over every (m, n) class): the oracle's product, and
     bit for bit the per-class kernels' (the default for such sizes), which
     sum the same products in the same order with the same instructions.
     Row and column counts that leave rows unpaired, C_in blocks without
-    products, many chunks (bands of 32 rows) and three k segments."""
+    products, many chunks (bands of 32 rows) and three k segments; one or
+    two entries staged per barrier pair (an odd entry count leaves the
+    second stage empty)."""
+    monkeypatch.setenv("BSM_MQUAD_STAGE", stage)
     nbr, nbk, nbc = shape
     rng = np.random.default_rng(900 + nbr)
     rs, ks, cs = (rng.choice([5, 13, 23, 26], n) for n in (nbr, nbk, nbc))
