@@ -481,6 +481,10 @@ const char *bsm_last_error(void);
 /* Library version string. */
 const char *bsm_version(void);
 
+/* The block-product kernel this thread launched last, with its template
+ * arguments ("" before the first); for reports of what ran. */
+const char *bsm_last_smm_kernel(void);
+
 #ifdef __cplusplus
 }
 #endif

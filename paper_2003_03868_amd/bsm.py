@@ -143,6 +143,7 @@ _SIGS = [
     ("bsm_set_smm_table", C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(bsm_smm_params)]),
     ("bsm_last_error", C.c_char_p, []),
     ("bsm_version", C.c_char_p, []),
+    ("bsm_last_smm_kernel", C.c_char_p, []),
 ]
 EXPORTED = [name for name, _, _ in _SIGS]
 
@@ -422,6 +423,10 @@ def bsm_set_smm_table(entries) -> None:
 
 def bsm_last_error() -> str:
     return load().bsm_last_error().decode()
+
+
+def bsm_last_smm_kernel() -> str:
+    return load().bsm_last_smm_kernel().decode()
 
 
 def bsm_version() -> str:

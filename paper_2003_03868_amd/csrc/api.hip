@@ -494,4 +494,6 @@ const char *bsm_last_error(void) { return bsm::last_error(); }
 
 const char *bsm_version(void) { return "bsm 0.1 (gfx950)"; }
 
+const char *bsm_last_smm_kernel(void) { return bsm::last_kernel(); }
+
 }  // extern "C"

@@ -36,6 +36,15 @@ struct Mat {
 void set_error(const char *fmt, ...);
 void clear_error();
 
+// The block-product kernel most recently launched by this thread, as written
+// at its launch (BSM_LAUNCH records it; bsm_last_smm_kernel reports it).
+void note_kernel(const char *launch_text);
+void note_kernelf(const char *fmt, ...);   // the same, formatted (template arguments of a template)
+const char *last_kernel();
+#define BSM_ID(...) __VA_ARGS__
+// BSM_LAUNCH((kernel<args>), grid, block, lds, stream)(kernel arguments)
+#define BSM_LAUNCH(KER, G, ...) BSM_ID KER<<<(::bsm::note_kernel(#KER), (G)), __VA_ARGS__>>>
+
 #define BSM_HIP(expr)                                                          \
     do {                                                                       \
         hipError_t e_ = (expr);                                                \

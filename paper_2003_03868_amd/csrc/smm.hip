@@ -518,7 +518,7 @@ int launch_class(const SmmArgs &a, int cls, hipStream_t s) {
     const int64_t per = (a.nC + kXcds - 1) / kXcds;
     const unsigned grid = static_cast<unsigned>(per * kXcds);
     switch (cls) {
-#define BSM_CL(ID, MM, NN) case ID: k_smm_f64_class<MM, NN><<<grid, 64, 0, s>>>(a); break;
+#define BSM_CL(ID, MM, NN) case ID: BSM_LAUNCH((k_smm_f64_class<MM, NN>), grid, 64, 0, s)(a); break;
         BSM_CL(0, 5, 5) BSM_CL(1, 5, 13) BSM_CL(2, 5, 23) BSM_CL(3, 5, 26)
         BSM_CL(4, 13, 5) BSM_CL(5, 13, 13) BSM_CL(6, 13, 23) BSM_CL(7, 13, 26)
         BSM_CL(8, 23, 5) BSM_CL(9, 23, 13) BSM_CL(10, 23, 23) BSM_CL(11, 23, 26)
@@ -561,7 +561,7 @@ static int launch_persistent(const SmmArgs &a, hipStream_t s) {
     k_zero_u64<<<1, 1, 0, s>>>(counter);
     const int64_t want = static_cast<int64_t>(cus) * 8;    // 2 waves per SIMD (its occupancy)
     const unsigned grid = static_cast<unsigned>(want < a.nC ? want : a.nC);
-    k_smm_f64_persistent<<<grid, 64, lds, s>>>(a, counter);
+    BSM_LAUNCH((k_smm_f64_persistent), grid, 64, lds, s)(a, counter);
     const hipError_t e = hipGetLastError();
     if (!a.counter) dfree(counter, s);
     if (e != hipSuccess) { set_error("persistent launch: %s", hipGetErrorString(e)); return BSM_EDEVICE; }
@@ -575,12 +575,12 @@ bool smm_fixed_available(int m, int n, int k) {
 
 int launch_fixed(const SmmArgs &a, int m, unsigned grid, hipStream_t s) {
     switch (m) {
-        case 5: k_smm_f64_fixed<5, 5, 5, 8><<<grid, 64, 0, s>>>(a); break;
-        case 6: k_smm_f64_fixed<6, 6, 6, 8><<<grid, 64, 0, s>>>(a); break;
-        case 13: k_smm_f64_fixed<13, 13, 13, 8><<<grid, 64, 0, s>>>(a); break;
-        case 23: k_smm_f64_fixed<23, 23, 23, 4><<<grid, 64, 0, s>>>(a); break;
-        case 26: k_smm_f64_fixed<26, 26, 26, 3><<<grid, 64, 0, s>>>(a); break;
-        case 32: k_smm_f64_fixed<32, 32, 32, 2><<<grid, 64, 0, s>>>(a); break;
+        case 5: BSM_LAUNCH((k_smm_f64_fixed<5, 5, 5, 8>), grid, 64, 0, s)(a); break;
+        case 6: BSM_LAUNCH((k_smm_f64_fixed<6, 6, 6, 8>), grid, 64, 0, s)(a); break;
+        case 13: BSM_LAUNCH((k_smm_f64_fixed<13, 13, 13, 8>), grid, 64, 0, s)(a); break;
+        case 23: BSM_LAUNCH((k_smm_f64_fixed<23, 23, 23, 4>), grid, 64, 0, s)(a); break;
+        case 26: BSM_LAUNCH((k_smm_f64_fixed<26, 26, 26, 3>), grid, 64, 0, s)(a); break;
+        case 32: BSM_LAUNCH((k_smm_f64_fixed<32, 32, 32, 2>), grid, 64, 0, s)(a); break;
         default: set_error("no fixed-shape kernel for %d", m); return BSM_EINVAL;
     }
     BSM_HIP(hipGetLastError());

@@ -538,9 +538,9 @@ int launch_lowp_quad(const SmmArgs &a, hipStream_t s) {
     const unsigned g = static_cast<unsigned>(grid);
 #define BSM_LQ(SZ)                                                            \
     case SZ:                                                                  \
-        if (a.prec == BSM_SPLIT_BF16) k_lowp_quad<SZ, 2><<<g, 256, 0, s>>>(a);\
-        else if (a.prec == BSM_SPLIT_BF16X3) k_lowp_quad<SZ, 3><<<g, 256, 0, s>>>(a); \
-        else k_lowp_quad<SZ, 0><<<g, 256, 0, s>>>(a);                         \
+        if (a.prec == BSM_SPLIT_BF16) BSM_LAUNCH((k_lowp_quad<SZ, 2>), g, 256, 0, s)(a);\
+        else if (a.prec == BSM_SPLIT_BF16X3) BSM_LAUNCH((k_lowp_quad<SZ, 3>), g, 256, 0, s)(a); \
+        else BSM_LAUNCH((k_lowp_quad<SZ, 0>), g, 256, 0, s)(a);                         \
         break;
     switch (a.uni_m) {
         BSM_LQ(5)
@@ -569,9 +569,9 @@ int smm_launch_lowp(const SmmArgs &a, hipStream_t s) {
     }
 #define BSM_LP(SZ)                                                                  \
     case SZ:                                                                        \
-        if (a.prec == BSM_FP32) k_smm_f32<SZ, SZ, SZ><<<grid, 64, 0, s>>>(a);       \
-        else if (a.prec == BSM_SPLIT_BF16X3) k_smm_bf16x3<SZ, SZ, SZ, 3><<<grid, 64, 0, s>>>(a); \
-        else k_smm_bf16x3<SZ, SZ, SZ, 2><<<grid, 64, 0, s>>>(a);                    \
+        if (a.prec == BSM_FP32) BSM_LAUNCH((k_smm_f32<SZ, SZ, SZ>), grid, 64, 0, s)(a);       \
+        else if (a.prec == BSM_SPLIT_BF16X3) BSM_LAUNCH((k_smm_bf16x3<SZ, SZ, SZ, 3>), grid, 64, 0, s)(a); \
+        else BSM_LAUNCH((k_smm_bf16x3<SZ, SZ, SZ, 2>), grid, 64, 0, s)(a);                    \
         break;
     switch (a.uni_m) {
         BSM_LP(5)

@@ -389,8 +389,8 @@ int launch_mquad(const SmmArgs &a, hipStream_t s) {
     const int64_t want = static_cast<int64_t>(cus) * (eps == 2 ? 3 : 5);
     const unsigned grid = static_cast<unsigned>(want < a.n_quads ? want : a.n_quads);
     k_mq_zero<<<1, 1, 0, s>>>(a.counter);
-    if (eps == 2) k_smm_f64_mquad<2, 3><<<grid, 64 * kMqWaves, 0, s>>>(a, a.counter);
-    else k_smm_f64_mquad<1, 4><<<grid, 64 * kMqWaves, 0, s>>>(a, a.counter);
+    if (eps == 2) BSM_LAUNCH((k_smm_f64_mquad<2, 3>), grid, 64 * kMqWaves, 0, s)(a, a.counter);
+    else BSM_LAUNCH((k_smm_f64_mquad<1, 4>), grid, 64 * kMqWaves, 0, s)(a, a.counter);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }

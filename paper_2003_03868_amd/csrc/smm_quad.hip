@@ -420,28 +420,28 @@ int launch_quad(const SmmArgs &a, hipStream_t s) {
         // product masks (norm screening): quads with four waves (sizes 5, 6: one)
         if (a.q_gr != 2 || a.q_gc != 2) { set_error("internal: masked groups are quads"); return BSM_EINVAL; }
         switch (a.uni_m) {
-            case 5: k_smm_f64_quad<5, 2, 2, 1, 6, 1, true><<<g, 64, 0, s>>>(a); break;
-            case 6: k_smm_f64_quad<6, 2, 2, 1, 6, 1, true><<<g, 64, 0, s>>>(a); break;
-            case 13: k_smm_f64_quad<13, 2, 2, 4, 6, 1, true><<<g, 256, 0, s>>>(a); break;
-            case 23: k_smm_f64_quad<23, 2, 2, 4, 5, 1, true><<<g, 256, 0, s>>>(a); break;
-            case 26: k_smm_f64_quad<26, 2, 2, 4, 4, 1, true><<<g, 256, 0, s>>>(a); break;
-            case 32: k_smm_f64_quad<32, 2, 2, 4, 4, 1, true><<<g, 256, 0, s>>>(a); break;
+            case 5: BSM_LAUNCH((k_smm_f64_quad<5, 2, 2, 1, 6, 1, true>), g, 64, 0, s)(a); break;
+            case 6: BSM_LAUNCH((k_smm_f64_quad<6, 2, 2, 1, 6, 1, true>), g, 64, 0, s)(a); break;
+            case 13: BSM_LAUNCH((k_smm_f64_quad<13, 2, 2, 4, 6, 1, true>), g, 256, 0, s)(a); break;
+            case 23: BSM_LAUNCH((k_smm_f64_quad<23, 2, 2, 4, 5, 1, true>), g, 256, 0, s)(a); break;
+            case 26: BSM_LAUNCH((k_smm_f64_quad<26, 2, 2, 4, 4, 1, true>), g, 256, 0, s)(a); break;
+            case 32: BSM_LAUNCH((k_smm_f64_quad<32, 2, 2, 4, 4, 1, true>), g, 256, 0, s)(a); break;
             default: set_error("no quad kernel for block size %d", a.uni_m); return BSM_EINVAL;
         }
         BSM_HIP(hipGetLastError());
         return BSM_OK;
     }
     if (a.q_gr == 4 && a.q_gc == 2 && a.uni_m == 23) {
-        k_smm_f64_quad<23, 4, 2, 8, 6, 1><<<g, 512, 0, s>>>(a);
+        BSM_LAUNCH((k_smm_f64_quad<23, 4, 2, 8, 6, 1>), g, 512, 0, s)(a);
         BSM_HIP(hipGetLastError());
         return BSM_OK;
     }
     if (a.q_gr == 4 && a.q_gc == 4) {
         switch (a.uni_m) {
-            case 13: k_smm_f64_quad<13, 4, 4, 16, 8, 1><<<g, 1024, 0, s>>>(a); break;
-            case 23: k_smm_f64_quad<23, 4, 4, 16, 8, 1><<<g, 1024, 0, s>>>(a); break;
-            case 26: k_smm_f64_quad<26, 4, 4, 16, 4, 1><<<g, 1024, 0, s>>>(a); break;
-            case 32: k_smm_f64_quad<32, 4, 4, 16, 4, 1><<<g, 1024, 0, s>>>(a); break;
+            case 13: BSM_LAUNCH((k_smm_f64_quad<13, 4, 4, 16, 8, 1>), g, 1024, 0, s)(a); break;
+            case 23: BSM_LAUNCH((k_smm_f64_quad<23, 4, 4, 16, 8, 1>), g, 1024, 0, s)(a); break;
+            case 26: BSM_LAUNCH((k_smm_f64_quad<26, 4, 4, 16, 4, 1>), g, 1024, 0, s)(a); break;
+            case 32: BSM_LAUNCH((k_smm_f64_quad<32, 4, 4, 16, 4, 1>), g, 1024, 0, s)(a); break;
             default: set_error("no group-of-sixteen kernel for block size %d", a.uni_m); return BSM_EINVAL;
         }
         BSM_HIP(hipGetLastError());
@@ -452,21 +452,21 @@ int launch_quad(const SmmArgs &a, hipStream_t s) {
         return BSM_EINVAL;
     }
     switch (a.uni_m) {
-        case 5: k_smm_f64_quad<5, 2, 2, 1, 8, 1><<<g, 64, 0, s>>>(a); break;
-        case 6: k_smm_f64_quad<6, 2, 2, 1, 8, 1><<<g, 64, 0, s>>>(a); break;
+        case 5: BSM_LAUNCH((k_smm_f64_quad<5, 2, 2, 1, 8, 1>), g, 64, 0, s)(a); break;
+        case 6: BSM_LAUNCH((k_smm_f64_quad<6, 2, 2, 1, 8, 1>), g, 64, 0, s)(a); break;
         case 13:
-            if (w == 4) k_smm_f64_quad<13, 2, 2, 4, 6, 1><<<g, 256, 0, s>>>(a);
-            else if (w == 2) k_smm_f64_quad<13, 2, 2, 2, 4, 1><<<g, 128, 0, s>>>(a);
-            else k_smm_f64_quad<13, 2, 2, 1, 4, 1><<<g, 64, 0, s>>>(a);
+            if (w == 4) BSM_LAUNCH((k_smm_f64_quad<13, 2, 2, 4, 6, 1>), g, 256, 0, s)(a);
+            else if (w == 2) BSM_LAUNCH((k_smm_f64_quad<13, 2, 2, 2, 4, 1>), g, 128, 0, s)(a);
+            else BSM_LAUNCH((k_smm_f64_quad<13, 2, 2, 1, 4, 1>), g, 64, 0, s)(a);
             break;
         case 23:
-            if (w == 4 && eps == 2) k_smm_f64_quad<23, 2, 2, 4, 4, 2><<<g, 256, 0, s>>>(a);
-            else if (w == 4) k_smm_f64_quad<23, 2, 2, 4, 6, 1><<<g, 256, 0, s>>>(a);   // 6 waves/SIMD: 1% faster than 5
-            else if (w == 2) k_smm_f64_quad<23, 2, 2, 2, 3, 1><<<g, 128, 0, s>>>(a);
-            else k_smm_f64_quad<23, 2, 2, 1, 1, 1><<<g, 64, 0, s>>>(a);
+            if (w == 4 && eps == 2) BSM_LAUNCH((k_smm_f64_quad<23, 2, 2, 4, 4, 2>), g, 256, 0, s)(a);
+            else if (w == 4) BSM_LAUNCH((k_smm_f64_quad<23, 2, 2, 4, 6, 1>), g, 256, 0, s)(a);   // 6 waves/SIMD: 1% faster than 5
+            else if (w == 2) BSM_LAUNCH((k_smm_f64_quad<23, 2, 2, 2, 3, 1>), g, 128, 0, s)(a);
+            else BSM_LAUNCH((k_smm_f64_quad<23, 2, 2, 1, 1, 1>), g, 64, 0, s)(a);
             break;
-        case 26: k_smm_f64_quad<26, 2, 2, 4, 4, 1><<<g, 256, 0, s>>>(a); break;
-        case 32: k_smm_f64_quad<32, 2, 2, 4, 4, 1><<<g, 256, 0, s>>>(a); break;
+        case 26: BSM_LAUNCH((k_smm_f64_quad<26, 2, 2, 4, 4, 1>), g, 256, 0, s)(a); break;
+        case 32: BSM_LAUNCH((k_smm_f64_quad<32, 2, 2, 4, 4, 1>), g, 256, 0, s)(a); break;
         default: set_error("no quad kernel for block size %d", a.uni_m); return BSM_EINVAL;
     }
     BSM_HIP(hipGetLastError());

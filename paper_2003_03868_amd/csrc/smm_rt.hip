@@ -214,11 +214,12 @@ static int launch_rt_fam(const SmmArgs &a, int wpg, int pf, hipStream_t s) {
     const unsigned grid = static_cast<unsigned>(per * kXcds);
     const size_t lds = sizeof(double) * static_cast<size_t>(wpg) *
                        (static_cast<size_t>(a.max_m) * a.max_k + static_cast<size_t>(a.max_k) * a.max_n);
-#define BSM_RT(W, P) k_smm_f64_rt<FAM, T1, T2, W, P><<<grid, 64 * W, lds, s>>>(a)
+#define BSM_RT(W, P) BSM_LAUNCH((k_smm_f64_rt<FAM, T1, T2, W, P>), grid, 64 * W, lds, s)(a)
     if (wpg == 1) { if (pf) BSM_RT(1, 1); else BSM_RT(1, 0); }
     else if (wpg == 2) { if (pf) BSM_RT(2, 1); else BSM_RT(2, 0); }
     else { if (pf) BSM_RT(4, 1); else BSM_RT(4, 0); }
 #undef BSM_RT
+    note_kernelf("k_smm_f64_rt<%d, %d, %d, %d, %d>", FAM, T1, T2, wpg == 2 || wpg == 4 ? wpg : 1, pf);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }

@@ -23,6 +23,22 @@ void set_error(const char *fmt, ...) {
 void clear_error() { g_err.clear(); }
 const char *last_error() { return g_err.c_str(); }
 
+static thread_local std::string g_kernel;
+void note_kernel(const char *launch_text) {
+    std::string k = launch_text;                    // "(name<args>)" as written
+    if (k.size() >= 2 && k.front() == '(' && k.back() == ')') k = k.substr(1, k.size() - 2);
+    g_kernel = k;
+}
+void note_kernelf(const char *fmt, ...) {
+    char buf[256];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_kernel = buf;
+}
+const char *last_kernel() { return g_kernel.c_str(); }
+
 // ----------------------------------------------------------------- memory
 // Caching device allocator.  Freed blocks go to a free list of the stream
 // they were released on and are handed out again (best fit, at most 1.25x
