@@ -620,6 +620,15 @@ def main():
         log("timing the CPU oracle on a sample ...")
         cpu = cpu_baseline(h, min(args.cpu_rows, h.nbrows),
                            step_flops=sum(s.flops for s, _ in all_stats) / args.steps)
+        # the oracle's own run of this whole sign iteration, when its record
+        # (tests/golden, written on the build host) is for this configuration
+        rec = os.path.join(ROOT, "tests", "golden", f"fullsize_sign23_s{args.seed}.npz")
+        if (os.path.exists(rec) and args.sites == 2048 and args.eps == 1e-6 and args.tol == 1e-6
+                and args.order == 2 and args.prec == "fp64" and args.screen == 0.0):
+            with np.load(rec, allow_pickle=False) as z:
+                cpu["time_to_sign_s_oracle_record"] = float(z["oracle_seconds"])
+                cpu["oracle_record_threads"] = int(z["oracle_threads"])
+                cpu["oracle_record_note"] = "measured once on the build host when the record was written"
         log(f"cpu baseline: {cpu['value']:.2f} GFLOP/s on {cpu['cores']} threads")
 
     n = float(h.shape[0])

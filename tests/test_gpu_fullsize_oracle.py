@@ -36,7 +36,11 @@ from tests.golden.make_fullsize import (WORKLOADS, hamiltonian, load_fixture, pa
 
 pytestmark = pytest.mark.gpu
 
-CASES = [("sign23", 0), ("sign23", 1), ("sign23", 2), ("sign23_e5", 0), ("mixed", 0)]
+# (workload, seed, kernel variant): the mixed workload both with the
+# paired-group kernel in one launch per multiply (bench.py --workload mixed)
+# and with the library default, one launch per (m, n) class
+CASES = [("sign23", 0, None), ("sign23", 1, None), ("sign23", 2, None), ("sign23_e5", 0, None),
+         ("mixed", 0, "7"), ("mixed", 0, "4")]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -76,9 +80,12 @@ def _probe_err(x, fx):
     return errs, row_err
 
 
-@pytest.mark.parametrize("workload,seed", CASES, ids=[f"{w}-s{s}" for w, s in CASES])
-def test_sign_full_size_matches_oracle(workload, seed):
+@pytest.mark.parametrize("workload,seed,variant", CASES,
+                         ids=[f"{w}-s{s}" + (f"-v{v}" if v else "") for w, s, v in CASES])
+def test_sign_full_size_matches_oracle(monkeypatch, workload, seed, variant):
     fx = _fixture(workload, seed)
+    if variant is not None:
+        monkeypatch.setenv("BSM_SMM_VARIANT", variant)
     h = hamiltonian(workload, seed)
     assert h.nbrows == int(fx["sites"])
     x, st = _sign(h, workload)
