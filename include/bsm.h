@@ -98,7 +98,7 @@ typedef struct {
     int32_t norm;            /* bsm_norm of the filter */
     int32_t prec;            /* bsm_precision of the block products */
     int32_t fp64_final_iters;/* mixed precision: last updates done in FP64 */
-    int32_t use_graph;       /* 1: replay captured iterations where possible */
+    int32_t use_graph;       /* 1, 2: iterations from captured graphs (see bsm_sign_iterate) */
     double prec_switch_tol;  /* mixed precision: FP64 once r_k < this */
     int32_t order;           /* 2 (Newton-Schulz), 3, 5 or 7: see bsm_sign_iterate */
     int32_t pad_;
@@ -120,8 +120,9 @@ typedef struct {
     double device_ms;        /* device time from first to last kernel (HIP events) */
     int64_t nnzb_final;      /* stored blocks of the returned X */
     int32_t graph_replays;   /* iterations run by replaying captured graphs */
-    int32_t graph_fallbacks; /* replayed iterations redone on the normal path because
-                                the filter kept other blocks (or NaN/Inf appeared) */
+    int32_t graph_fallbacks; /* replayed multiplies redone on the normal path: use_graph 1,
+                                a capacity was exceeded; 2, the filter kept other blocks
+                                (either: NaN/Inf appeared) */
     int32_t smm_launches;    /* block-product kernel launches of the counted multiplies */
     int32_t pad_;
     int64_t n_screened;      /* products left out by norm screening */
@@ -293,11 +294,23 @@ int bsm_inf_norm(bsm_matrix A, double mu, double *out, void *stream);
  *      (5 multiplies; the seventh order the section names, whose polynomial
  *      has g'(x) proportional to (1 - x^2)^6 like the printed ones)
  * Other orders: BSM_EINVAL.
- * opts->use_graph = 1 (order 2 only): once an update leaves X's block pattern unchanged, the
- * following iterations replay captured hipGraphs of the numeric kernels (one
- * wait per iteration; no symbolic phase, allocation or compaction scan).  A
- * replayed iteration whose filter would keep other blocks is redone on the
- * normal path, so the results are those of use_graph = 0, bit for bit.
+ * opts->use_graph (order 2, no screening; the results are those of
+ * use_graph = 0, bit for bit):
+ *   1: with uniform block sizes 5, 6, 13, 23, 26 or 32 and FP64 products, once
+ *      an FP64 update has grown X's block count by at most half, iterations
+ *      run from captured hipGraphs of the whole multiply (symbolic phase,
+ *      block products, filter, residual), with every size kept in device
+ *      memory and buffers of fixed capacity (sizes of the last iteration on
+ *      the normal path times BSM_GRAPH_HEADROOM, default 1.25); two waits per
+ *      iteration (r_k, then the update's record).  A multiply that overflows
+ *      a capacity (or meets NaN/Inf) is redone on the normal path, which
+ *      re-sizes the buffers; stats->graph_fallbacks counts these.  Other
+ *      sizes and precisions: as 2.
+ *   2: once an update leaves X's block pattern unchanged, the following
+ *      iterations replay captured hipGraphs of the numeric kernels (one wait
+ *      per iteration; no symbolic phase, allocation or compaction scan).  A
+ *      replayed iteration whose filter would keep other blocks is redone on
+ *      the normal path.
  */
 int bsm_sign_iterate(bsm_matrix H, double mu, const bsm_sign_opts *opts,
                      bsm_matrix *x_out, bsm_sign_stats *stats, void *stream);

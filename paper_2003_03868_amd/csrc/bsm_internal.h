@@ -85,6 +85,10 @@ inline unsigned grid_for(int64_t n, int block) {
 // Exclusive scan of n int64 values into out[0..n]; out[n] = total.
 // `in` and `out` may alias.  Work space is allocated on the stream.
 int scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+// The same with caller-provided work space of scan_ws_words(n) words (no
+// allocation, no copy: capturable into a graph).
+int64_t scan_ws_words(int64_t n);
+int scan_i64_ws(const int64_t *in, int64_t *out, int64_t n, int64_t *ws, hipStream_t s);
 
 // Block value offsets blk_off[nnzb+1] from row_ptr/col_idx/block sizes.
 int compute_blk_off(Mat &m, hipStream_t s);
@@ -98,12 +102,22 @@ int validate_pattern(const Mat &m, hipStream_t s);
 struct MulPlan;
 void free_plan(MulPlan *p);
 
+// Sizes of one multiply's symbolic results (to size fixed-capacity buffers).
+struct MulSizes {
+    int64_t nnzb_u = 0;      // C blocks before the filter
+    int64_t nnzb = 0;        // C blocks after the filter
+    int64_t n_groups = 0;    // groups of C blocks of the group kernel, over all chunks
+    int64_t n_entries = 0;   // their entries
+    bool groups = false;     // the uniform-size FP64 group kernel did the products
+};
+
 // plan (may be NULL): on success receives the retained symbolic state.
 // tau > 0: product-level norm screening (terms with ||A_ik||^2 ||B_kj||^2 <
-// tau^2 left out; FP64 group kernel only).
+// tau^2 left out; FP64 group kernel only).  sizes (may be NULL): receives
+// the sizes above.
 int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps,
              int norm, int prec, bsm_mult_stats *stats, hipStream_t s,
-             MulPlan **plan = nullptr, double tau = 0.0);
+             MulPlan **plan = nullptr, double tau = 0.0, MulSizes *sizes = nullptr);
 int filter_inplace(Mat &m, double eps, int norm, hipStream_t s);
 
 // Reductions (reduce.hip)

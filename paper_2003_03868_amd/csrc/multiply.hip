@@ -38,7 +38,7 @@ static int64_t chunk_products() {
 
 // Block-product kernel variant; BSM_SMM_VARIANT overrides the default
 // (tests and the tuner compare variants).
-static int smm_variant() {
+int smm_variant() {
     const char *e = getenv("BSM_SMM_VARIANT");
     return e ? atoi(e) : kSmmF64Quad;
 }
@@ -63,7 +63,7 @@ static bool lowp_quad(int prec) {
 // and segment, so the serial walk over the merged A rows is nseg times
 // shorter): one per 256 block columns of A, at most 8; BSM_QUAD_KSEG
 // overrides it (tests force several segments on small matrices).
-static int32_t quad_ksegments(int32_t nbk) {
+int32_t quad_ksegments(int32_t nbk) {
     const char *e = getenv("BSM_QUAD_KSEG");
     int32_t v = e ? atoi(e) : nbk / 256;
     if (v > 8 && !e) v = 8;
@@ -198,7 +198,7 @@ static int check_shapes(const Mat &A, const Mat &B, const Mat &C) {
 }
 
 int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int norm, int prec,
-             bsm_mult_stats *stats, hipStream_t s, MulPlan **plan, double tau) {
+             bsm_mult_stats *stats, hipStream_t s, MulPlan **plan, double tau, MulSizes *sizes) {
     BSM_TRY(check_shapes(A, B, C));
     if (!(tau >= 0.0) || !std::isfinite(tau)) { set_error("eps_screen must be finite and >= 0"); return BSM_EINVAL; }
     if (tau > 0.0 && (prec != BSM_FP64 || plan)) {
@@ -452,6 +452,7 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     }
 
     int32_t n_launch = 0;
+    int64_t sum_groups = 0, sum_entries = 0;
     auto launch = [&](const MulOp &op) -> int {
         ++n_launch;
         const int r = run_op(op, s);
@@ -533,6 +534,8 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
                 set_error("more than 2^31 group entries in one chunk; lower BSM_CHUNK_PRODUCTS");
                 st = BSM_EINVAL;
             }
+            sum_groups += nq;
+            sum_entries += ne;
             if (st == BSM_OK) st = qbuf(&ent, static_cast<size_t>(ne) * NE);
             if (st == BSM_OK && tau > 0.0) st = qbuf(&pm, ne);
             qa.ent = ent;
@@ -706,6 +709,13 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     C.nnzb = nc.nnzb; C.nvalues = nc.nvalues;
     C.stream = s;
 
+    if (sizes) {
+        sizes->nnzb_u = nnzb_c;
+        sizes->nnzb = nnzb_after;
+        sizes->n_groups = sum_groups;
+        sizes->n_entries = sum_entries;
+        sizes->groups = use_quad && prec == BSM_FP64;
+    }
     if (stats) {
         stats->n_products = nprod;
         stats->flops = flops;

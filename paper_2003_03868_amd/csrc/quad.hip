@@ -183,6 +183,7 @@ k_quad_stack(QuadSymArgs q) {
                 const int32_t j = q.c_col_idx[t];
                 const int32_t Q = col_group<GC, MAP>(q, j);
                 const int64_t rank = bit_rank_q(bits, wpre, Q);
+                if (rank >= nq) continue;          // only when q_off was emptied after an overflow
                 q.q_cblk[GG * (qbase + rank) + GC * r + col_slot<GC, MAP>(q, j)] = t;
                 q.q_col[qbase + rank] = Q;         // same value from every block of the group
             }

@@ -25,7 +25,14 @@
 // (1 - x^2)^6 and g(1) = 1, evaluated in the Paterson-Stockmeyer split
 // q = (3003 - 6006 Y + 9009 Y^2) + Y^3 (231 Y^3 - 1638 Y^2 + 5005 Y - 8580).
 //
-// Graph replay (opts.use_graph): once an update leaves the block pattern of X
+// Graphs (opts.use_graph = 1): with uniform block sizes that have an FP64
+// group kernel, iterations run from graphs of the whole device-sized
+// multiply (symbolic phase included; graph_iter.hip), captured after an FP64
+// iteration on the normal path whose update grew X's block count by at most
+// half, and re-captured with larger buffers after an overflow.  Otherwise
+// (use_graph = 2 always) the pattern-keyed replay below.
+//
+// Graph replay (pattern-keyed): once an update leaves the block pattern of X
 // unchanged, the symbolic results of both multiplies stay valid for the next
 // iteration as long as the filter keeps the same blocks.  The numeric kernels
 // of the square (with the residual reduction) and of the update are then
@@ -39,6 +46,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "graph_iter.h"
 #include "plan.h"
 
 namespace bsm {
@@ -59,6 +67,7 @@ static int validate_opts(const Mat &H, const bsm_sign_opts &o) {
         return BSM_EINVAL;
     }
     if (o.fp64_final_iters < 0) { set_error("sign: fp64_final_iters must be >= 0"); return BSM_EINVAL; }
+    if (o.use_graph < 0 || o.use_graph > 2) { set_error("sign: use_graph must be 0, 1 or 2"); return BSM_EINVAL; }
     if (o.order != 2 && o.order != 3 && o.order != 5 && o.order != 7) {
         set_error("sign: order must be 2, 3, 5 or 7");
         return BSM_EINVAL;
@@ -321,7 +330,15 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
     if (rc != BSM_OK) { free_mat(X, s); return rc; }
 
     // graphs replay the symbolic results, which screening makes value-dependent
-    const bool want_graph = o.use_graph != 0 && o.order == 2 && o.eps_screen == 0.0;
+    const bool dev_graph = o.use_graph == 1 && o.order == 2 && o.eps_screen == 0.0 &&
+                           graph_iter_ok(*X);
+    const bool want_graph = o.use_graph != 0 && !dev_graph && o.order == 2 && o.eps_screen == 0.0;
+    GraphIter *G = dev_graph ? gi_create(s, o.eps_filter, o.norm) : nullptr;
+    struct GiGuard {
+        GraphIter *g;
+        ~GiGuard() { gi_destroy(g); }
+    } gi_guard{G};
+    const double b3 = dev_graph ? static_cast<double>(X->uni_r) * X->uni_r * X->uni_r : 0.0;
     Replay R;
     R.s = s;
     if (want_graph) {
@@ -338,6 +355,68 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
         const int prec = prec_of(o, *st, k);
         st->prec_hist[k] = prec;
         bool have_y = false;   // Y of iteration k already formed from a replay
+        bool update_only = false;   // square, r_k and the decision done from the graphs
+        MulSizes sz_sq, sz_up;
+        if (gi_on(G) && prec != BSM_FP64) {
+            rc = gi_leave(G, *X, nullptr);
+            if (rc != BSM_OK) break;
+        } else if (gi_on(G)) {
+            // iteration k from the device-sized graphs
+            GiStatus gs{};
+            double gms = 0.0;
+            rc = gi_square(G, &gs, &gms);
+            if (rc != BSM_OK) break;
+            if (gs.over || (gs.flags & kFlagNonFinite)) {
+                // a buffer was too small (or NaN/Inf): iteration k on the
+                // normal path, which re-sizes (or reports the error)
+                st->graph_fallbacks++;
+                rc = gi_leave(G, *X, nullptr);
+                if (rc != BSM_OK) break;
+            } else {
+                st->n_multiplies++;
+                st->flops += 2.0 * b3 * static_cast<double>(gs.n_products);
+                st->n_products += gs.n_products;
+                st->smm_launches += 1;
+                st->smm_ms += gms;
+                const double r = std::sqrt(gs.d) / n;
+                st->r_hist[k] = r;
+                st->iterations = k;
+                st->nnzb_x_hist[k] = gi_x_nnzb(G);
+                st->nnzb_y_hist[k] = gs.nnzb;
+                if (!std::isfinite(r)) {
+                    set_error("sign: residual is not finite at iteration %d", k);
+                    rc = BSM_ENONFINITE;
+                    break;
+                }
+                stall_at[k] = stall;
+                const int dcs = decide(o, *st, k, r, &stall);
+                if (dcs != kGoOn) { rc = (dcs == kStop) ? BSM_OK : BSM_ENOCONV; break; }
+                sz_sq.nnzb_u = gs.nnzb_u;
+                sz_sq.nnzb = gs.nnzb;
+                sz_sq.n_groups = gs.n_groups;
+                sz_sq.n_entries = gs.n_entries;
+                sz_sq.groups = true;
+                GiStatus gu{};
+                rc = gi_update(G, &gu, &gms);
+                if (rc != BSM_OK) break;
+                if (gu.over || (gu.flags & kFlagNonFinite)) {
+                    // X_k and Y_k are intact: the update on the normal path
+                    st->graph_fallbacks++;
+                    rc = gi_leave(G, *X, Y);
+                    if (rc != BSM_OK) break;
+                    update_only = true;
+                } else {
+                    st->n_multiplies++;
+                    st->flops += 2.0 * b3 * static_cast<double>(gu.n_products);
+                    st->n_products += gu.n_products;
+                    st->smm_launches += 1;
+                    st->smm_ms += gms;
+                    st->graph_replays++;
+                    ++k;
+                    continue;
+                }
+            }
+        }
         if (R.on) {
             // numeric-only iteration from the captured graphs
             const bool same_prec = (prec == R.prec);
@@ -437,46 +516,49 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
         // iteration k on the normal path (retaining plans when graphs are wanted)
         R.drop_plans();
         bsm_mult_stats ms{};
-        if (!have_y) {
-            rc = multiply(1.0, *X, *X, 0.0, *Y, o.eps_filter, o.norm, prec, &ms, s,
-                          want_graph ? &R.psq : nullptr, o.eps_screen);
-            st->n_multiplies++;
-            st->flops += ms.flops;
-            st->n_products += ms.n_products;
-            st->n_screened += ms.n_screened;
-            st->smm_launches += ms.smm_launches;
-            st->smm_ms += ms.smm_ms;
-            for (int b = 0; b < 16; ++b) st->class_ms[b] += ms.class_ms[b];
-        }
-        if (rc != BSM_OK && rc != BSM_ENONFINITE) break;
-        double d = 0.0;
-        if (rc == BSM_OK) rc = sqdist_identity(*Y, 1.0, &d, s);
-        if (rc != BSM_OK && rc != BSM_ENONFINITE) break;
-        const double r = std::sqrt(d) / n;
-        st->r_hist[k] = (rc == BSM_OK) ? r : NAN;
-        st->iterations = k;
-        st->nnzb_x_hist[k] = X->nnzb;
-        st->nnzb_y_hist[k] = Y->nnzb;
-        if (rc == BSM_ENONFINITE || !std::isfinite(r)) {
-            set_error("sign: residual is not finite at iteration %d", k);
-            rc = BSM_ENONFINITE;
-            break;
-        }
-        stall_at[k] = stall;
-        const int dcs = decide(o, *st, k, r, &stall);
-        if (dcs != kGoOn) { rc = (dcs == kStop) ? BSM_OK : BSM_ENOCONV; break; }
-        if (o.order != 2) {
-            rc = higher_order_update(o, prec, *X, *Y, st, s);
-            if (rc != BSM_OK) break;
-            ++k;
-            continue;
+        if (!update_only) {
+            if (!have_y) {
+                rc = multiply(1.0, *X, *X, 0.0, *Y, o.eps_filter, o.norm, prec, &ms, s,
+                              want_graph ? &R.psq : nullptr, o.eps_screen, &sz_sq);
+                st->n_multiplies++;
+                st->flops += ms.flops;
+                st->n_products += ms.n_products;
+                st->n_screened += ms.n_screened;
+                st->smm_launches += ms.smm_launches;
+                st->smm_ms += ms.smm_ms;
+                for (int b = 0; b < 16; ++b) st->class_ms[b] += ms.class_ms[b];
+            }
+            if (rc != BSM_OK && rc != BSM_ENONFINITE) break;
+            double d = 0.0;
+            if (rc == BSM_OK) rc = sqdist_identity(*Y, 1.0, &d, s);
+            if (rc != BSM_OK && rc != BSM_ENONFINITE) break;
+            const double r = std::sqrt(d) / n;
+            st->r_hist[k] = (rc == BSM_OK) ? r : NAN;
+            st->iterations = k;
+            st->nnzb_x_hist[k] = X->nnzb;
+            st->nnzb_y_hist[k] = Y->nnzb;
+            if (rc == BSM_ENONFINITE || !std::isfinite(r)) {
+                set_error("sign: residual is not finite at iteration %d", k);
+                rc = BSM_ENONFINITE;
+                break;
+            }
+            stall_at[k] = stall;
+            const int dcs = decide(o, *st, k, r, &stall);
+            if (dcs != kGoOn) { rc = (dcs == kStop) ? BSM_OK : BSM_ENOCONV; break; }
+            if (o.order != 2) {
+                rc = higher_order_update(o, prec, *X, *Y, st, s);
+                if (rc != BSM_OK) break;
+                ++k;
+                continue;
+            }
         }
         if (want_graph && R.psq) {
             rc = snapshot(R, *X, s);
             if (rc != BSM_OK) break;
         }
+        const int64_t x_before = X->nnzb;
         rc = multiply(-0.5, *X, *Y, 1.5, *X, o.eps_filter, o.norm, prec, &ms, s,
-                      (want_graph && R.psq) ? &R.pup : nullptr, o.eps_screen);
+                      (want_graph && R.psq) ? &R.pup : nullptr, o.eps_screen, &sz_up);
         st->n_multiplies++;
         st->flops += ms.flops;
         st->n_products += ms.n_products;
@@ -489,7 +571,16 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
             rc = maybe_enter(R, *X, *Y, prec, s);
             if (rc != BSM_OK) break;
         }
+        // the device-sized graphs, once X's block count has settled
+        if (G && prec == BSM_FP64 && 2 * X->nnzb <= 3 * x_before) {
+            rc = gi_enter(G, *X, *Y, sz_sq, sz_up);
+            if (rc != BSM_OK) break;
+        }
         ++k;
+    }
+    if (gi_on(G)) {
+        const int r2 = gi_leave(G, *X, nullptr);
+        if (rc == BSM_OK) rc = r2;
     }
     R.leave(*X);
     R.drop_plans();

@@ -69,6 +69,8 @@ struct SmmArgs {
     unsigned long long *counter;  // work counter of the persistent kernel (NULL: allocated per launch)
     // group kernel: GR x GC groups of C blocks (2 x 2: quads) with merged product lists
     int64_t n_quads;            // groups
+    const int64_t *n_quads_dev; // FP64 group kernel: the group count in device memory (the
+                                // launch then covers up to n_quads groups); NULL: n_quads
     const int64_t *q_cblk;      // [GR GC n_quads] C block (r, c) of the group at GC r + c, or -1
     const int64_t *q_seg;       // [n_quads + 1] entry segments
     const int4 *q_ent;          // ceil((GR + GC) / 4) int4 per entry: A(row 0..GR-1) then
@@ -79,6 +81,8 @@ struct SmmArgs {
 };
 
 int smm_launch(const SmmArgs &a, int variant, hipStream_t s);
+// Requested block-product variant (kSmmF64Quad unless BSM_SMM_VARIANT says otherwise).
+int smm_variant();
 bool smm_fixed_available(int m, int n, int k);
 int launch_fixed(const SmmArgs &a, int m, unsigned grid, hipStream_t s);
 int class_of_size(int b);                       // 0..3 for 5, 13, 23, 26; else -1

@@ -42,8 +42,12 @@ __device__ inline int4 uniform4(int4 v) {
                      __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
 }
 
+// Work item of this workgroup: the items form kXcds contiguous ranges, range
+// x for the workgroups blockIdx.x % kXcds = x (which run on one XCD); n_items
+// for a workgroup past the last range.
 __device__ inline int64_t quad_item(int64_t n_items) {
     const int64_t per = (n_items + kXcds - 1) / kXcds;
+    if (static_cast<int64_t>(blockIdx.x / kXcds) >= per) return n_items;
     return static_cast<int64_t>(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
 }
 
@@ -212,8 +216,9 @@ k_smm_f64_quad(SmmArgs a) {
     static_assert(NR * NC * W == GR * GC, "waves must tile the group");
     static_assert(W > NOP || NOP % W == 0, "operands must split evenly over the waves");
     __shared__ double sm[EPS * SLOT + Q::TAIL];
-    const int64_t it = quad_item(a.n_quads);
-    if (it >= a.n_quads) return;
+    const int64_t n_items = a.n_quads_dev ? *a.n_quads_dev : a.n_quads;
+    const int64_t it = quad_item(n_items);
+    if (it >= n_items) return;
     const int64_t item = a.q_order ? a.q_order[it] : it;
     const int lane = threadIdx.x % kWave;
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));  // wave-uniform

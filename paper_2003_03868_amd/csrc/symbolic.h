@@ -87,6 +87,8 @@ struct QuadSymArgs {
     const int32_t *cslot;        // [nbcols] slot (0 or 1) of column j in its group
     const int32_t *cmap;         // [2 ncg] columns of column group Q (second -1 for one)
 };
+// k segments of the group lists' walk for nbk block columns of A.
+int32_t quad_ksegments(int32_t nbk);
 int quad_pairs(const QuadSymArgs &q, int64_t *cnt, hipStream_t s);
 int quad_stack(const QuadSymArgs &q, bool fill, hipStream_t s);
 // starts[g] = seg_off[g nseg] for g in [0, n_groups]: entry offsets per group.

@@ -158,24 +158,31 @@ k_sym_pattern(SymArgs a, const int64_t *c_row_ptr, int32_t *c_col_idx, int32_t *
     int32_t *wpre = reinterpret_cast<int32_t *>(smem + nwords);
     const int32_t i = blockIdx.x;
     build_rank(bits, wpre, a, i, scratch);
-    const int64_t base = c_row_ptr[i];
+    // writes stay inside the row's range of c_row_ptr (all of the row's
+    // blocks when the counts came from k_sym_count; none when a caller
+    // emptied the rows after a capacity overflow)
+    const int64_t base = c_row_ptr[i], end = c_row_ptr[i + 1];
     for (int w = threadIdx.x; w < nwords; w += kSymThreads) {
         uint32_t x = bits[w];
         int32_t r = wpre[w];
         while (x) {
             const int b = __ffs(x) - 1;
             x &= x - 1;
-            c_col_idx[base + r] = w * 32 + b;
-            c_row[base + r] = i;
-            if (cin_map) cin_map[base + r] = -1;
+            if (base + r < end) {
+                c_col_idx[base + r] = w * 32 + b;
+                c_row[base + r] = i;
+                if (cin_map) cin_map[base + r] = -1;
+            }
             ++r;
         }
     }
     if (a.use_c && cin_map) {
         __syncthreads();
         for (int64_t tc = a.c_in_row_ptr[i] + threadIdx.x; tc < a.c_in_row_ptr[i + 1];
-             tc += kSymThreads)
-            cin_map[base + bit_rank(bits, wpre, a.c_in_col_idx[tc])] = tc;
+             tc += kSymThreads) {
+            const int64_t pos = base + bit_rank(bits, wpre, a.c_in_col_idx[tc]);
+            if (pos < end) cin_map[pos] = tc;
+        }
     }
 }
 

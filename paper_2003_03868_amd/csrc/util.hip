@@ -212,26 +212,45 @@ __global__ void k_scan_single(const int64_t *in, int64_t *out, int64_t n) {
     if (threadIdx.x == 0) out[n] = total;
 }
 
-int scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
+__global__ void k_copy_i64(const int64_t *src, int64_t *dst) { *dst = *src; }
+
+// Workspace words of a scan of n values: the tile sums of every level.
+int64_t scan_ws_words(int64_t n) {
+    int64_t w = 0;
+    while (n > kScanTile) {
+        const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+        w += tiles + 1;
+        n = tiles;
+    }
+    return w;
+}
+
+// The scan with its tile sums in ws (scan_ws_words(n) words): kernels only,
+// so it can be captured into a graph.
+int scan_i64_ws(const int64_t *in, int64_t *out, int64_t n, int64_t *ws, hipStream_t s) {
     if (n <= kScanTile) {
         k_scan_single<<<1, kScanThreads, 0, s>>>(in, out, n);
         BSM_HIP(hipGetLastError());
         return BSM_OK;
     }
     const int64_t tiles = (n + kScanTile - 1) / kScanTile;
-    int64_t *sums = nullptr;
-    BSM_TRY(dalloc(&sums, tiles + 1, s));
+    int64_t *sums = ws;
     k_scan_tiles<<<static_cast<unsigned>(tiles), kScanThreads, 0, s>>>(in, out, sums, n);
     BSM_HIP(hipGetLastError());
-    int st = scan_i64(sums, sums, tiles, s);   // sums[tiles] = total
-    if (st == BSM_OK) {
-        k_scan_add<<<grid_for(n, 256), 256, 0, s>>>(out, sums, n);
-        // out[n] = total
-        hipError_t e = hipMemcpyAsync(out + n, sums + tiles, sizeof(int64_t),
-                                      hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) { set_error("scan copy failed"); st = BSM_EDEVICE; }
-    }
-    dfree(sums, s);
+    BSM_TRY(scan_i64_ws(sums, sums, tiles, ws + tiles + 1, s));   // sums[tiles] = total
+    k_scan_add<<<grid_for(n, 256), 256, 0, s>>>(out, sums, n);
+    k_copy_i64<<<1, 1, 0, s>>>(sums + tiles, out + n);             // out[n] = total
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+int scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
+    const int64_t w = scan_ws_words(n);
+    if (w == 0) return scan_i64_ws(in, out, n, nullptr, s);
+    int64_t *ws = nullptr;
+    BSM_TRY(dalloc(&ws, w, s));
+    const int st = scan_i64_ws(in, out, n, ws, s);
+    dfree(ws, s);
     return st;
 }
 
