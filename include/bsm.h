@@ -296,8 +296,10 @@ int bsm_inf_norm(bsm_matrix A, double mu, double *out, void *stream);
  * Other orders: BSM_EINVAL.
  * opts->use_graph (order 2, no screening; the results are those of
  * use_graph = 0, bit for bit):
- *   1: with uniform block sizes 5, 6, 13, 23, 26 or 32 and FP64 products, once
- *      an FP64 update has grown X's block count by at most half, iterations
+ *   1: with FP64 products and uniform block sizes 5, 6, 13, 23, 26 or 32 (or
+ *      sizes in {5, 13, 23, 26} with every (m, n) class in one persistent
+ *      launch, BSM_SMM_VARIANT=7), once an FP64 update has grown X's block
+ *      count by at most half, iterations
  *      run from captured hipGraphs of the whole multiply (symbolic phase,
  *      block products, filter, residual), with every size kept in device
  *      memory and buffers of fixed capacity (sizes of the last iteration on

@@ -106,9 +106,12 @@ void free_plan(MulPlan *p);
 struct MulSizes {
     int64_t nnzb_u = 0;      // C blocks before the filter
     int64_t nnzb = 0;        // C blocks after the filter
+    int64_t nval_u = 0;      // C scalars before the filter
+    int64_t nval = 0;        // C scalars after the filter
     int64_t n_groups = 0;    // groups of C blocks of the group kernel, over all chunks
     int64_t n_entries = 0;   // their entries
-    bool groups = false;     // the uniform-size FP64 group kernel did the products
+    bool groups = false;     // an FP64 group kernel did the products (uniform sizes, or
+                             // mixed sizes in one launch)
 };
 
 // plan (may be NULL): on success receives the retained symbolic state.

@@ -9,10 +9,13 @@ namespace bsm {
 // Device record of one multiply run from the graphs.
 struct GiStatus {
     int64_t nnzb_u;      // C blocks before the filter (0 after an overflow)
+    int64_t nval_u;      // C scalars before the filter
     int64_t n_groups;    // groups of the group kernel
     int64_t n_entries;   // their entries
     int64_t nnzb;        // C blocks after the filter
+    int64_t nval;        // C scalars after the filter
     int64_t n_products;  // block products
+    double flops;        // their algorithmic flops, 2 m n k each
     double d;            // square: ||Y - I||_F^2
     int32_t over;        // kGiOver* bits: a fixed-capacity buffer was too small
     int32_t flags;       // kFlagNonFinite from the block products
@@ -21,9 +24,10 @@ constexpr int kGiOverC = 1, kGiOverG = 2, kGiOverE = 4, kGiOverOut = 8;
 
 struct GraphIter;
 
-// True when X (and the options) take the device-sized path: square X with
-// uniform block sizes that have an FP64 group kernel, which the multiply
-// would also pick (no other kernel variant or tuning-table family asked for).
+// True when X takes the device-sized path: square X with uniform block sizes
+// that have an FP64 group kernel, which the multiply would also pick (no
+// other kernel variant or tuning-table family asked for), or with sizes in
+// {5, 13, 23, 26} when the one-launch paired-group kernel is asked for.
 bool graph_iter_ok(const Mat &X);
 
 GraphIter *gi_create(hipStream_t s, double eps, int norm);

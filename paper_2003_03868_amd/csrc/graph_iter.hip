@@ -1,14 +1,15 @@
 // Device-sized Newton-Schulz iterations replayed from captured hipGraphs.
 //
-// The normal multiply learns its sizes on the host (C blocks, groups,
-// entries) and allocates to fit them, so a whole iteration cannot be
+// The normal multiply learns its sizes on the host (C blocks and scalars,
+// groups, entries) and allocates to fit them, so a whole iteration cannot be
 // captured.  Here every size stays in device memory.  Buffers are reserved
 // up front with fixed capacities, taken from an iteration run on the normal
 // path plus headroom; each kernel reads the counts it needs from device
 // memory; and after each scan a capacity check records an overflow in a
 // device status word and empties the structure that overflowed, so the
 // kernels after it do no work and stay inside their buffers.  One iteration
-// (uniform block sizes, FP64 group kernel, one chunk) is six graphs:
+// (FP64 group kernels: uniform block sizes, or sizes in {5, 13, 23, 26} with
+// every (m, n) class in one persistent launch; one chunk) is six graphs:
 //
 //   square  Y = filter(X X):  symbolic | block products | filter, ||Y - I||^2
 //   update  X' = filter(1.5 X - 0.5 X Y):  symbolic | block products | filter
@@ -35,16 +36,17 @@ namespace bsm {
 namespace {
 
 // Headroom of the capacities over the sizes they are taken from
-// (BSM_GRAPH_HEADROOM, >= 1; tests use 1 to force overflows).
+// (BSM_GRAPH_HEADROOM, >= 1).
 double headroom() {
     const char *e = getenv("BSM_GRAPH_HEADROOM");
     const double h = e ? atof(e) : 1.25;
     return h >= 1.0 ? h : 1.0;
 }
 
-// Multipliers of the five capacities (unfiltered blocks, groups, entries,
-// X, Y) from BSM_GRAPH_CAPS="c,g,e,x,y" (default 1 each; tests use values
-// below 1 to make one buffer too small; X keeps room for the current X).
+// Multipliers of the capacities (unfiltered C blocks, groups, entries, X, Y;
+// the scalar capacities follow their blocks) from BSM_GRAPH_CAPS="c,g,e,x,y"
+// (default 1 each; tests use values below 1 to make one buffer too small;
+// X keeps room for the current X).
 void cap_scales(double (&m)[5]) {
     for (double &v : m) v = 1.0;
     const char *e = getenv("BSM_GRAPH_CAPS");
@@ -55,6 +57,12 @@ void cap_scales(double (&m)[5]) {
         if (v > 0.0) m[i] = v;
         e = (*end == ',') ? end + 1 : end;
     }
+}
+
+bool in_mixed_set(const std::vector<int32_t> &v) {
+    for (int32_t b : v)
+        if (b != 5 && b != 13 && b != 23 && b != 26) return false;
+    return true;
 }
 
 __global__ void k_gi_reset(GiStatus *st) {
@@ -74,27 +82,32 @@ __global__ void k_gi_zero_if(const GiStatus *st, int bits, int64_t *arr, int64_t
     if (i < n && (st->over & bits)) arr[i] = 0;
 }
 
-// arr[*from * mul .. n) = 0: the counts past the last group.
+// arr[*from * mul .. n) = 0: the counts past the last item.
 __global__ void k_gi_zero_from(const int64_t *from, int64_t mul, int64_t *arr, int64_t n) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n && i >= *from * mul) arr[i] = 0;
 }
 
-// Value offsets of uniform blocks: off[i] = i * b2.
-__global__ void k_gi_iota(int64_t *off, int64_t n, int64_t b2) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) off[i] = i * b2;
+// Scalars of every C block (m n), to be scanned into value offsets.
+__global__ void k_gi_sizes(const int64_t *rp, const int32_t *col, const int32_t *rbs,
+                           const int32_t *cbs, int64_t *sizes) {
+    const int32_t i = blockIdx.x;
+    const int64_t m = rbs[i];
+    for (int64_t t = rp[i] + threadIdx.x; t < rp[i + 1]; t += blockDim.x) sizes[t] = m * cbs[col[t]];
 }
 
 // The filter's test for the first *n_dev of cap unfiltered blocks (the test
-// of the normal path's compaction), 0 past them.
-__global__ void k_gi_keep(const double *sq, const double *mx, const int64_t *n_dev, int64_t cap,
-                          double eps, int norm, int64_t *keep) {
+// of the normal path's compaction) and the kept blocks' scalar counts; 0
+// past them.
+__global__ void k_gi_keep(const double *sq, const double *mx, const int64_t *bo,
+                          const int64_t *n_dev, int64_t cap, double eps, int norm, int64_t *keep,
+                          int64_t *ksize) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= cap) return;
     bool k = false;
     if (t < *n_dev) k = (norm == BSM_NORM_MAXABS) ? !(mx[t] < eps) : !(sq[t] < eps * eps);
     keep[t] = k ? 1 : 0;
+    ksize[t] = k ? bo[t + 1] - bo[t] : 0;
 }
 
 // Filtered row pointers from the keep scan.
@@ -105,43 +118,74 @@ __global__ void k_gi_rows(const int64_t *c_rp, const int64_t *kidx, int32_t nbr,
 
 // One wave per unfiltered block: a kept block to its filtered place.
 __global__ void __launch_bounds__(64)
-k_gi_compact(const int64_t *kidx, const int64_t *n_dev, const int32_t *col, const double *vals,
-             int64_t b2, int32_t *out_col, double *out_vals) {
+k_gi_compact(const int64_t *kidx, const int64_t *koff, const int64_t *n_dev, const int32_t *col,
+             const int64_t *bo, const double *vals, int32_t *out_col, int64_t *out_bo,
+             double *out_vals) {
     const int64_t t = blockIdx.x;
     if (t >= *n_dev) return;
     const int64_t d = kidx[t];
     if (kidx[t + 1] == d) return;   // dropped
-    if (threadIdx.x == 0) out_col[d] = col[t];
-    for (int64_t e = threadIdx.x; e < b2; e += 64) out_vals[d * b2 + e] = vals[t * b2 + e];
+    const int64_t src = bo[t], len = bo[t + 1] - src, dst = koff[t];
+    if (threadIdx.x == 0) {
+        out_col[d] = col[t];
+        out_bo[d] = dst;
+    }
+    for (int64_t e = threadIdx.x; e < len; e += 64) out_vals[dst + e] = vals[src + e];
 }
 
-// Sizes into the record; the product count summed over the block rows.
+// The closing value offset of the filtered matrix.
+__global__ void k_gi_bo_end(const int64_t *nkept, const int64_t *nval, int64_t *out_bo) {
+    out_bo[*nkept] = *nval;
+}
+
+// Sizes into the record; products and flops summed over the block rows (the
+// flops are sums of integers below 2^53, so the order does not matter).
 __global__ void __launch_bounds__(256)
-k_gi_status(const int64_t *c_rp, const int64_t *q_off, int64_t npairs, const int64_t *e_tot,
-            const int64_t *out_rp, const int64_t *p_cnt, int32_t nbr, GiStatus *st) {
+k_gi_status(const int64_t *c_rp, const int64_t *c_bo, const int64_t *q_off, int64_t nrg,
+            const int64_t *e_tot, const int64_t *out_rp, const int64_t *nval,
+            const int64_t *p_cnt, const double *fl, int32_t nbr, GiStatus *st) {
     __shared__ int64_t part[256 / kWave];
+    __shared__ double partf[256 / kWave];
     int64_t np = 0;
-    for (int32_t i = threadIdx.x; i < nbr; i += 256) np += p_cnt[i];
-    for (int o = kWave / 2; o > 0; o >>= 1) np += __shfl_xor(np, o, kWave);
-    if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = np;
+    double f = 0.0;
+    for (int32_t i = threadIdx.x; i < nbr; i += 256) {
+        np += p_cnt[i];
+        f += fl[i];
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        np += __shfl_xor(np, o, kWave);
+        f += __shfl_xor(f, o, kWave);
+    }
+    if (threadIdx.x % kWave == 0) {
+        part[threadIdx.x / kWave] = np;
+        partf[threadIdx.x / kWave] = f;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t t = 0;
-        for (int w = 0; w < 256 / kWave; ++w) t += part[w];
+        double tf = 0.0;
+        for (int w = 0; w < 256 / kWave; ++w) {
+            t += part[w];
+            tf += partf[w];
+        }
         st->n_products = t;
-        st->nnzb_u = c_rp[nbr];
-        st->n_groups = q_off[npairs];
+        st->flops = tf;
+        const int64_t nu = c_rp[nbr];
+        st->nnzb_u = nu;
+        st->nval_u = c_bo[nu];
+        st->n_groups = q_off[nrg];
         st->n_entries = *e_tot;
         st->nnzb = out_rp[nbr];
+        st->nval = *nval;
     }
 }
 
-// A matrix held in fixed-capacity buffers (uniform blocks: values of block i
-// at i b^2).
+// A matrix held in fixed-capacity buffers: cap blocks, vcap scalars.
 struct PoolMat {
-    int64_t cap = 0;
+    int64_t cap = 0, vcap = 0;
     int64_t *rp = nullptr;
     int32_t *ci = nullptr;
+    int64_t *bo = nullptr;
     double *v = nullptr;
 };
 
@@ -168,6 +212,10 @@ int capture(F body, hipGraphExec_t *out) {
 
 }  // namespace
 
+struct Caps {
+    int64_t c = 0, cv = 0, g = 0, e = 0, x = 0, xv = 0, y = 0, yv = 0;
+};
+
 struct GraphIter {
     hipStream_t s = nullptr;
     double eps = 0.0;
@@ -177,19 +225,23 @@ struct GraphIter {
     int p = 0;
     int32_t captures = 0;
     Mat proto;                // X's sizes (block-size arrays borrowed from X)
-    int32_t nbr = 0, nbc = 0, b = 0;
-    int64_t b2 = 0;
+    int32_t nbr = 0, nbc = 0, b = 0;   // b: the uniform block size, 0 for mixed sizes
+    bool mixed = false;
     int gr = 2, gc = 2;
     int32_t nseg = 1, kseg = 1;
-    int64_t npairs = 0;
-    // capacities: unfiltered C blocks, groups, entries, blocks of X and of Y
-    int64_t cap_c = 0, cap_g = 0, cap_e = 0, cap_x = 0, cap_y = 0;
-    int64_t x_nnzb = 0, y_nnzb = 0;
+    int64_t nrg = 0;          // row groups
+    MixedPairs mp;
+    Caps cap;
+    int64_t x_nnzb = 0, x_nval = 0, y_nnzb = 0, y_nval = 0;
     std::vector<void *> owned;
-    int64_t *blk = nullptr;   // [max(cap_c, cap_x, cap_y) + 1] uniform value offsets
     PoolMat x[2], y;
+    // mixed sizes: pair maps and the persistent kernel's work order
+    int32_t *d_rg = nullptr, *d_cgrp = nullptr, *d_cslot = nullptr, *d_cmap = nullptr;
+    unsigned long long *counter = nullptr;
+    int8_t *rank = nullptr;
+    int64_t *q_order = nullptr;
     // the unfiltered product (shared by the square and the update)
-    int64_t *c_rp = nullptr, *c_nval = nullptr, *p_cnt = nullptr;
+    int64_t *c_rp = nullptr, *c_nval = nullptr, *p_cnt = nullptr, *c_bo = nullptr;
     double *flops_row = nullptr;
     int32_t *c_col = nullptr, *c_row = nullptr;
     int64_t *cin_map = nullptr;
@@ -199,7 +251,7 @@ struct GraphIter {
     int32_t *q_col = nullptr;
     int4 *ent = nullptr;
     // filter, scans, residual, records
-    int64_t *kidx = nullptr, *ws = nullptr;
+    int64_t *kidx = nullptr, *koff = nullptr, *ws = nullptr;
     double *part = nullptr;
     GiStatus *st = nullptr;   // [0] square, [1] update
     hipGraphExec_t g[2][6] = {};
@@ -224,24 +276,24 @@ struct GraphIter {
         if (!owned.empty()) (void)hipStreamSynchronize(s);
         for (void *q : owned) dfree(q, s);
         owned.clear();
-        cap_c = cap_g = cap_e = cap_x = cap_y = 0;
+        cap = Caps{};
     }
     ~GraphIter() {
         release();
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
     }
-    Mat view(const PoolMat &m, int64_t nnzb) const {
+    Mat view(const PoolMat &m) const {
         Mat v = proto;
         v.row_ptr = m.rp;
         v.col_idx = m.ci;
-        v.blk_off = blk;
+        v.blk_off = m.bo;
         v.values = m.v;
-        v.nnzb = nnzb;
-        v.nvalues = nnzb * b2;
+        v.nnzb = 0;
+        v.nvalues = 0;
         return v;
     }
-    int alloc(int64_t cc, int64_t cg, int64_t ce, int64_t cx, int64_t cy);
+    int alloc(const Caps &c);
     int mult_sym(const Mat &A, const Mat &B, bool use_c, GiStatus *rec, hipStream_t cs);
     int mult_smm(const Mat &A, const Mat &B, const Mat *Cin, double alpha, double beta,
                  GiStatus *rec, hipStream_t cs);
@@ -250,14 +302,18 @@ struct GraphIter {
 };
 
 bool graph_iter_ok(const Mat &X) {
-    if (X.nbrows != X.nbcols || X.nbrows == 0 || !X.uni_r || X.uni_r != X.uni_c) return false;
-    const int b = X.uni_r;
-    if (!smm_quad_available(b, b, b) || smm_variant() != kSmmF64Quad) return false;
-    SmmParams tp;
-    if (table_lookup(b, b, b, &tp) && tp.family != 3) return false;
-    int gr = 2, gc = 2;
-    quad_shape(b, &gr, &gc);
-    return gr == 2 && gc == 2;
+    if (X.nbrows != X.nbcols || X.nbrows == 0 || X.h_rbs != X.h_cbs) return false;
+    if (X.uni_r && X.uni_r == X.uni_c) {
+        const int b = X.uni_r;
+        if (!smm_quad_available(b, b, b) || smm_variant() != kSmmF64Quad) return false;
+        SmmParams tp;
+        if (table_lookup(b, b, b, &tp) && tp.family != 3) return false;
+        int gr = 2, gc = 2;
+        quad_shape(b, &gr, &gc);
+        return gr == 2 && gc == 2;
+    }
+    // mixed sizes: the paired groups in one persistent launch per multiply
+    return in_mixed_set(X.h_rbs) && smm_variant() == kSmmF64MQuad;
 }
 
 GraphIter *gi_create(hipStream_t s, double eps, int norm) {
@@ -273,53 +329,76 @@ bool gi_on(const GraphIter *g) { return g && g->on; }
 int64_t gi_x_nnzb(const GraphIter *g) { return g->x_nnzb; }
 int32_t gi_captures(const GraphIter *g) { return g ? g->captures : 0; }
 
-int GraphIter::alloc(int64_t cc, int64_t cg, int64_t ce, int64_t cx, int64_t cy) {
+int GraphIter::alloc(const Caps &c) {
     release();
     const int32_t ne4 = (gr + gc + 3) / 4;
     int r = BSM_OK;
     auto req = [&](auto **ptr, size_t n) {
         if (r == BSM_OK) r = get(ptr, n);
     };
-    const int64_t nb = std::max({cc, cx, cy}) + 1;
-    req(&blk, nb);
     for (PoolMat *m : {&x[0], &x[1], &y}) {
-        m->cap = (m == &y) ? cy : cx;
+        m->cap = (m == &y) ? c.y : c.x;
+        m->vcap = (m == &y) ? c.yv : c.xv;
         req(&m->rp, nbr + 1);
         req(&m->ci, m->cap);
-        req(&m->v, static_cast<size_t>(m->cap) * b2);
+        req(&m->bo, m->cap + 1);
+        req(&m->v, m->vcap);
     }
     req(&c_rp, nbr + 1);
     req(&c_nval, nbr + 1);
     req(&p_cnt, nbr + 1);
     req(&flops_row, nbr + 1);
-    req(&c_col, cc);
-    req(&c_row, cc);
-    req(&cin_map, cc);
-    req(&c_vals, static_cast<size_t>(cc) * b2);
-    req(&sq, cc);
-    req(&mx, cc);
-    req(&q_off, npairs + 1);
-    req(&q_cblk, static_cast<size_t>(gr) * gc * cg);
-    req(&q_col, cg);
-    req(&e_seg, static_cast<size_t>(cg) * nseg + 1);
-    if (nseg > 1) req(&e_off, cg + 1);
-    req(&ent, static_cast<size_t>(ce) * ne4);
-    req(&kidx, cc + 1);
-    const int64_t w = std::max({scan_ws_words(nbr), scan_ws_words(npairs),
-                                scan_ws_words(cg * nseg), scan_ws_words(cc)});
+    req(&c_bo, c.c + 1);
+    req(&c_col, c.c);
+    req(&c_row, c.c);
+    req(&cin_map, c.c);
+    req(&c_vals, c.cv);
+    req(&sq, c.c);
+    req(&mx, c.c);
+    req(&q_off, nrg + 1);
+    req(&q_cblk, static_cast<size_t>(gr) * gc * c.g);
+    req(&q_col, c.g);
+    req(&e_seg, static_cast<size_t>(c.g) * nseg + 1);
+    if (nseg > 1) req(&e_off, c.g + 1);
+    req(&ent, static_cast<size_t>(c.e) * ne4);
+    req(&kidx, c.c + 1);
+    req(&koff, c.c + 1);
+    const int64_t w = std::max({scan_ws_words(nbr), scan_ws_words(nrg),
+                                scan_ws_words(c.g * nseg), scan_ws_words(c.c)});
     req(&ws, std::max<int64_t>(w, 1));
     req(&part, nbr);
     req(&st, 2);
+    if (mixed) {
+        req(&d_rg, mp.rg.size());
+        req(&d_cgrp, mp.cgrp.size());
+        req(&d_cslot, mp.cslot.size());
+        req(&d_cmap, std::max<size_t>(mp.cmap.size(), 1));
+        req(&counter, 1);
+        req(&rank, c.g);
+        req(&q_order, c.g);
+    }
     if (r != BSM_OK) { release(); return r; }
     if (nseg == 1) e_off = e_seg;
-    k_gi_iota<<<grid_for(nb, 256), 256, 0, s>>>(blk, nb, b2);
-    BSM_HIP(hipGetLastError());
-    cap_c = cc; cap_g = cg; cap_e = ce; cap_x = cx; cap_y = cy;
+    if (mixed) {
+        hipError_t e = hipSuccess;
+        auto up = [&](int32_t *d, const std::vector<int32_t> &h) {
+            if (e == hipSuccess && !h.empty())
+                e = hipMemcpyAsync(d, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, s);
+        };
+        up(d_rg, mp.rg); up(d_cgrp, mp.cgrp); up(d_cslot, mp.cslot); up(d_cmap, mp.cmap);
+        if (e != hipSuccess) {
+            release();
+            set_error("graph iteration: pair maps: %s", hipGetErrorString(e));
+            return BSM_EDEVICE;
+        }
+    }
+    cap = c;
     return BSM_OK;
 }
 
-// Symbolic part: pattern of the unfiltered product, groups and their entry
-// lists (the normal path's steps 1-5 for one chunk), with capacity checks.
+// Symbolic part: pattern and value offsets of the unfiltered product, groups
+// and their entry lists (the normal path's steps 1-5 for one chunk), with
+// capacity checks.
 int GraphIter::mult_sym(const Mat &A, const Mat &B, bool use_c, GiStatus *rec, hipStream_t cs) {
     k_gi_reset<<<1, 1, 0, cs>>>(rec);
     SymArgs sa{};
@@ -332,9 +411,15 @@ int GraphIter::mult_sym(const Mat &A, const Mat &B, bool use_c, GiStatus *rec, h
     sa.c_in_col_idx = use_c ? A.col_idx : nullptr;
     BSM_TRY(sym_count(sa, c_rp, c_nval, p_cnt, flops_row, cs));
     BSM_TRY(scan_i64_ws(c_rp, c_rp, nbr, ws, cs));
-    k_gi_check<<<1, 1, 0, cs>>>(c_rp + nbr, cap_c, kGiOverC, rec);
+    k_gi_check<<<1, 1, 0, cs>>>(c_rp + nbr, cap.c, kGiOverC, rec);
     k_gi_zero_if<<<grid_for(nbr + 1, 256), 256, 0, cs>>>(rec, kGiOverC, c_rp, nbr + 1);
     BSM_TRY(sym_pattern(sa, c_rp, c_col, c_row, use_c ? cin_map : nullptr, cs));
+    // value offsets; scalars over capacity empty C as well
+    k_gi_sizes<<<nbr, 128, 0, cs>>>(c_rp, c_col, A.rbs, B.cbs, c_bo);
+    k_gi_zero_from<<<grid_for(cap.c + 1, 256), 256, 0, cs>>>(c_rp + nbr, 1, c_bo, cap.c + 1);
+    BSM_TRY(scan_i64_ws(c_bo, c_bo, cap.c, ws, cs));
+    k_gi_check<<<1, 1, 0, cs>>>(c_bo + cap.c, cap.cv, kGiOverC, rec);
+    k_gi_zero_if<<<grid_for(nbr + 1, 256), 256, 0, cs>>>(rec, kGiOverC, c_rp, nbr + 1);
 
     QuadSymArgs qa{};
     qa.r0 = 0; qa.r1 = nbr; qa.nbcols = nbc; qa.gr = gr; qa.gc = gc;
@@ -343,18 +428,25 @@ int GraphIter::mult_sym(const Mat &A, const Mat &B, bool use_c, GiStatus *rec, h
     qa.b_row_ptr = B.row_ptr; qa.b_col_idx = B.col_idx;
     qa.c_row_ptr = c_rp; qa.c_col_idx = c_col;
     qa.q_off = q_off; qa.q_cblk = q_cblk; qa.q_col = q_col; qa.e_off = e_seg; qa.ent = ent;
+    if (mixed) {
+        qa.map = 1;
+        qa.g0 = 0;
+        qa.ngroups = nrg;
+        qa.ncg = static_cast<int32_t>(mp.cmap.size() / 2);
+        qa.rg = d_rg; qa.cgrp = d_cgrp; qa.cslot = d_cslot; qa.cmap = d_cmap;
+    }
     BSM_TRY(quad_pairs(qa, q_off, cs));
-    BSM_TRY(scan_i64_ws(q_off, q_off, npairs, ws, cs));
-    k_gi_check<<<1, 1, 0, cs>>>(q_off + npairs, cap_g, kGiOverG, rec);
-    k_gi_zero_if<<<grid_for(npairs + 1, 256), 256, 0, cs>>>(rec, kGiOverG, q_off, npairs + 1);
+    BSM_TRY(scan_i64_ws(q_off, q_off, nrg, ws, cs));
+    k_gi_check<<<1, 1, 0, cs>>>(q_off + nrg, cap.g, kGiOverG, rec);
+    k_gi_zero_if<<<grid_for(nrg + 1, 256), 256, 0, cs>>>(rec, kGiOverG, q_off, nrg + 1);
     BSM_TRY(quad_stack(qa, false, cs));
-    const int64_t nsl = cap_g * nseg;
-    k_gi_zero_from<<<grid_for(nsl + 1, 256), 256, 0, cs>>>(q_off + npairs, nseg, e_seg, nsl + 1);
+    const int64_t nsl = cap.g * nseg;
+    k_gi_zero_from<<<grid_for(nsl + 1, 256), 256, 0, cs>>>(q_off + nrg, nseg, e_seg, nsl + 1);
     BSM_TRY(scan_i64_ws(e_seg, e_seg, nsl, ws, cs));
     // entries over capacity: no groups at all from here on
-    k_gi_check<<<1, 1, 0, cs>>>(e_seg + nsl, cap_e, kGiOverE, rec);
-    k_gi_zero_if<<<grid_for(npairs + 1, 256), 256, 0, cs>>>(rec, kGiOverE, q_off, npairs + 1);
-    if (nseg > 1) BSM_TRY(quad_seg_starts(e_seg, nseg, cap_g, e_off, cs));
+    k_gi_check<<<1, 1, 0, cs>>>(e_seg + nsl, cap.e, kGiOverE, rec);
+    k_gi_zero_if<<<grid_for(nrg + 1, 256), 256, 0, cs>>>(rec, kGiOverE, q_off, nrg + 1);
+    if (nseg > 1) BSM_TRY(quad_seg_starts(e_seg, nseg, cap.g, e_off, cs));
     BSM_TRY(quad_stack(qa, true, cs));
     BSM_HIP(hipGetLastError());
     return BSM_OK;
@@ -364,36 +456,46 @@ int GraphIter::mult_sym(const Mat &A, const Mat &B, bool use_c, GiStatus *rec, h
 int GraphIter::mult_smm(const Mat &A, const Mat &B, const Mat *Cin, double alpha, double beta,
                         GiStatus *rec, hipStream_t cs) {
     SmmArgs a{};
-    a.c_row = c_row; a.c_col = c_col; a.c_blk_off = blk; a.c_vals = c_vals;
+    a.c_row = c_row; a.c_col = c_col; a.c_blk_off = c_bo; a.c_vals = c_vals;
     a.c_rbs = A.rbs; a.c_cbs = B.cbs;
-    a.a_col_idx = A.col_idx; a.a_blk_off = blk; a.a_vals = A.values; a.k_size = A.cbs;
-    a.b_blk_off = blk; a.b_vals = B.values;
+    a.a_col_idx = A.col_idx; a.a_blk_off = A.blk_off; a.a_vals = A.values; a.k_size = A.cbs;
+    a.b_blk_off = B.blk_off; a.b_vals = B.values;
     a.cin_map = Cin ? cin_map : nullptr;
-    a.cin_blk_off = Cin ? blk : nullptr;
+    a.cin_blk_off = Cin ? Cin->blk_off : nullptr;
     a.cin_vals = Cin ? Cin->values : nullptr;
     a.alpha = alpha; a.beta = beta;
     a.sq_out = sq; a.mx_out = mx; a.flags = &rec->flags;
-    a.max_m = a.max_n = a.max_k = b;
-    a.uni_m = a.uni_n = a.uni_k = b;
+    a.max_m = A.max_rbs; a.max_n = B.max_cbs; a.max_k = A.max_cbs;
+    a.uni_m = A.uni_r; a.uni_n = B.uni_c; a.uni_k = A.uni_c;
+    a.fused_ok = mixed ? 1 : 0;
     a.prec = BSM_FP64;
-    a.n_quads = cap_g;
-    a.n_quads_dev = q_off + npairs;
+    a.counter = counter;
+    a.n_quads = cap.g;
+    a.n_quads_dev = q_off + nrg;
     a.q_cblk = q_cblk; a.q_seg = e_off; a.q_ent = ent;
     a.q_gr = gr; a.q_gc = gc;
-    return launch_quad(a, cs);
+    if (!mixed) return launch_quad(a, cs);
+    BSM_TRY(mquad_order(a, rank, q_order, cs));
+    a.q_order = q_order;
+    return launch_mquad(a, cs);
 }
 
 // Filter and compaction into `out`, then the record's sizes.
 int GraphIter::mult_post(const PoolMat &out, GiStatus *rec, hipStream_t cs) {
-    k_gi_keep<<<grid_for(cap_c, 256), 256, 0, cs>>>(sq, mx, c_rp + nbr, cap_c, eps, norm, kidx);
-    BSM_TRY(scan_i64_ws(kidx, kidx, cap_c, ws, cs));
-    k_gi_check<<<1, 1, 0, cs>>>(kidx + cap_c, out.cap, kGiOverOut, rec);
-    k_gi_zero_if<<<grid_for(cap_c + 1, 256), 256, 0, cs>>>(rec, kGiOverOut, kidx, cap_c + 1);
+    k_gi_keep<<<grid_for(cap.c, 256), 256, 0, cs>>>(sq, mx, c_bo, c_rp + nbr, cap.c, eps, norm,
+                                                   kidx, koff);
+    BSM_TRY(scan_i64_ws(kidx, kidx, cap.c, ws, cs));
+    BSM_TRY(scan_i64_ws(koff, koff, cap.c, ws, cs));
+    k_gi_check<<<1, 1, 0, cs>>>(kidx + cap.c, out.cap, kGiOverOut, rec);
+    k_gi_check<<<1, 1, 0, cs>>>(koff + cap.c, out.vcap, kGiOverOut, rec);
+    k_gi_zero_if<<<grid_for(cap.c + 1, 256), 256, 0, cs>>>(rec, kGiOverOut, kidx, cap.c + 1);
+    k_gi_zero_if<<<grid_for(cap.c + 1, 256), 256, 0, cs>>>(rec, kGiOverOut, koff, cap.c + 1);
     k_gi_rows<<<grid_for(nbr + 1, 256), 256, 0, cs>>>(c_rp, kidx, nbr, out.rp);
-    k_gi_compact<<<static_cast<unsigned>(cap_c), 64, 0, cs>>>(kidx, c_rp + nbr, c_col, c_vals, b2,
-                                                             out.ci, out.v);
-    k_gi_status<<<1, 256, 0, cs>>>(c_rp, q_off, npairs, e_seg + cap_g * nseg, out.rp, p_cnt, nbr,
-                                   rec);
+    k_gi_compact<<<static_cast<unsigned>(cap.c), 64, 0, cs>>>(kidx, koff, c_rp + nbr, c_col, c_bo,
+                                                             c_vals, out.ci, out.bo, out.v);
+    k_gi_bo_end<<<1, 1, 0, cs>>>(kidx + cap.c, koff + cap.c, out.bo);
+    k_gi_status<<<1, 256, 0, cs>>>(c_rp, c_bo, q_off, nrg, e_seg + cap.g * nseg, out.rp,
+                                   koff + cap.c, p_cnt, flops_row, nbr, rec);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }
@@ -401,7 +503,7 @@ int GraphIter::mult_post(const PoolMat &out, GiStatus *rec, hipStream_t cs) {
 int GraphIter::capture_all() {
     drop_graphs();
     for (int q = 0; q < 2; ++q) {
-        const Mat X = view(x[q], 0), Y = view(y, 0);
+        const Mat X = view(x[q]), Y = view(y);
         // square: Y = filter(X X), then ||Y - I||_F^2
         BSM_TRY(capture([&](hipStream_t cs) { return mult_sym(X, X, false, &st[0], cs); }, &g[q][0]));
         BSM_TRY(capture([&](hipStream_t cs) { return mult_smm(X, X, nullptr, 1.0, 0.0, &st[0], cs); },
@@ -421,9 +523,10 @@ int GraphIter::capture_all() {
     return BSM_OK;
 }
 
-// Copy a matrix's pattern and values into a pool buffer.
+// Copy a matrix's pattern, offsets and values into a pool buffer.
 static int to_pool(const Mat &m, PoolMat &pm, int32_t nbr, hipStream_t s) {
     BSM_HIP(hipMemcpyAsync(pm.rp, m.row_ptr, sizeof(int64_t) * (nbr + 1), hipMemcpyDeviceToDevice, s));
+    BSM_HIP(hipMemcpyAsync(pm.bo, m.blk_off, sizeof(int64_t) * (m.nnzb + 1), hipMemcpyDeviceToDevice, s));
     if (m.nnzb) {
         BSM_HIP(hipMemcpyAsync(pm.ci, m.col_idx, sizeof(int32_t) * m.nnzb, hipMemcpyDeviceToDevice, s));
         BSM_HIP(hipMemcpyAsync(pm.v, m.values, sizeof(double) * m.nvalues, hipMemcpyDeviceToDevice, s));
@@ -431,23 +534,23 @@ static int to_pool(const Mat &m, PoolMat &pm, int32_t nbr, hipStream_t s) {
     return BSM_OK;
 }
 
-// Own arrays for m (nnzb blocks) copied from a pool buffer.
-static int from_pool(const GraphIter &g, const PoolMat &pm, int64_t nnzb, Mat &m) {
+// Own arrays for m (nnzb blocks, nval scalars) copied from a pool buffer.
+static int from_pool(const GraphIter &g, const PoolMat &pm, int64_t nnzb, int64_t nval, Mat &m) {
     hipStream_t s = g.s;
     Mat n;
     int r = dalloc(&n.row_ptr, g.nbr + 1, s);
     if (r == BSM_OK) r = dalloc(&n.col_idx, nnzb, s);
     if (r == BSM_OK) r = dalloc(&n.blk_off, nnzb + 1, s);
-    if (r == BSM_OK) r = dalloc(&n.values, static_cast<size_t>(nnzb) * g.b2, s);
+    if (r == BSM_OK) r = dalloc(&n.values, nval, s);
     hipError_t e = hipSuccess;
     if (r == BSM_OK) {
         e = hipMemcpyAsync(n.row_ptr, pm.rp, sizeof(int64_t) * (g.nbr + 1), hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(n.blk_off, g.blk, sizeof(int64_t) * (nnzb + 1), hipMemcpyDeviceToDevice, s);
+            e = hipMemcpyAsync(n.blk_off, pm.bo, sizeof(int64_t) * (nnzb + 1), hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess && nnzb)
             e = hipMemcpyAsync(n.col_idx, pm.ci, sizeof(int32_t) * nnzb, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess && nnzb)
-            e = hipMemcpyAsync(n.values, pm.v, sizeof(double) * nnzb * g.b2, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && nval)
+            e = hipMemcpyAsync(n.values, pm.v, sizeof(double) * nval, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) { set_error("graph iteration: copy: %s", hipGetErrorString(e)); r = BSM_EDEVICE; }
     }
     if (r != BSM_OK) {
@@ -457,7 +560,7 @@ static int from_pool(const GraphIter &g, const PoolMat &pm, int64_t nnzb, Mat &m
     free_mat_arrays(m, s);
     m.row_ptr = n.row_ptr; m.col_idx = n.col_idx; m.blk_off = n.blk_off; m.values = n.values;
     m.nnzb = nnzb;
-    m.nvalues = nnzb * g.b2;
+    m.nvalues = nval;
     return BSM_OK;
 }
 
@@ -468,13 +571,20 @@ int gi_enter(GraphIter *g, Mat &X, Mat &Y, const MulSizes &sq, const MulSizes &u
         g->proto = X;
         g->proto.row_ptr = nullptr; g->proto.col_idx = nullptr;
         g->proto.blk_off = nullptr; g->proto.values = nullptr;
-        g->nbr = X.nbrows; g->nbc = X.nbcols; g->b = X.uni_r;
-        g->b2 = static_cast<int64_t>(g->b) * g->b;
-        quad_shape(g->b, &g->gr, &g->gc);
+        g->nbr = X.nbrows; g->nbc = X.nbcols;
+        g->mixed = !(X.uni_r && X.uni_r == X.uni_c);
+        g->b = g->mixed ? 0 : X.uni_r;
+        if (g->mixed) {
+            g->gr = g->gc = 2;
+            mixed_pairs(X.h_rbs, X.h_cbs, &g->mp);
+            g->nrg = g->mp.band_g0.back();
+        } else {
+            quad_shape(g->b, &g->gr, &g->gc);
+            g->nrg = (static_cast<int64_t>(g->nbr) + g->gr - 1) / g->gr;
+        }
         g->nseg = quad_ksegments(X.nbcols);
         g->kseg = (X.nbcols + g->nseg - 1) / g->nseg;
         if (g->kseg < 1) g->kseg = 1;
-        g->npairs = (static_cast<int64_t>(g->nbr) + g->gr - 1) / g->gr;
         for (hipEvent_t &e : g->ev)
             if (!e) BSM_HIP(hipEventCreate(&e));
     }
@@ -489,27 +599,37 @@ int gi_enter(GraphIter *g, Mat &X, Mat &Y, const MulSizes &sq, const MulSizes &u
         return std::max<int64_t>(1, static_cast<int64_t>(std::min(v, static_cast<double>(bound))));
     };
     const int64_t dense = static_cast<int64_t>(g->nbr) * g->nbc;
-    const int64_t groups_max = g->npairs * ((g->nbc + g->gc - 1) / g->gc);
-    const int64_t want_c = grow(std::max(sq.nnzb_u, up.nnzb_u), dense, m[0]);
-    const int64_t want_g = grow(std::max(sq.n_groups, up.n_groups), groups_max, m[1]);
-    const int64_t want_e = grow(std::max(sq.n_entries, up.n_entries), INT32_MAX, m[2]);
-    const int64_t want_x = std::max(X.nnzb, grow(std::max(up.nnzb, X.nnzb), dense, m[3]));
-    const int64_t want_y = grow(sq.nnzb, dense, m[4]);
-    if (want_c > INT32_MAX || std::max({sq.n_entries, up.n_entries}) > INT32_MAX) return BSM_OK;
-    if (want_c > g->cap_c || want_g > g->cap_g || want_e > g->cap_e || want_x > g->cap_x ||
-        want_y > g->cap_y) {
-        BSM_TRY(g->alloc(std::max(want_c, g->cap_c), std::max(want_g, g->cap_g),
-                         std::max(want_e, g->cap_e), std::max(want_x, g->cap_x),
-                         std::max(want_y, g->cap_y)));
+    const int64_t dense_v = X.nrows * X.ncols;
+    const int64_t ncg = g->mixed ? static_cast<int64_t>(g->mp.cmap.size() / 2)
+                                 : (g->nbc + g->gc - 1) / g->gc;
+    Caps want;
+    want.c = grow(std::max(sq.nnzb_u, up.nnzb_u), dense, m[0]);
+    want.cv = grow(std::max(sq.nval_u, up.nval_u), dense_v, m[0]);
+    want.g = grow(std::max(sq.n_groups, up.n_groups), g->nrg * ncg, m[1]);
+    want.e = grow(std::max(sq.n_entries, up.n_entries), INT32_MAX, m[2]);
+    want.x = std::max(X.nnzb, grow(std::max(up.nnzb, X.nnzb), dense, m[3]));
+    want.xv = std::max(X.nvalues, grow(std::max(up.nval, X.nvalues), dense_v, m[3]));
+    want.y = grow(sq.nnzb, dense, m[4]);
+    want.yv = grow(sq.nval, dense_v, m[4]);
+    if (want.c > INT32_MAX || std::max({sq.n_entries, up.n_entries}) > INT32_MAX) return BSM_OK;
+    const Caps &c = g->cap;
+    if (want.c > c.c || want.cv > c.cv || want.g > c.g || want.e > c.e || want.x > c.x ||
+        want.xv > c.xv || want.y > c.y || want.yv > c.yv) {
+        Caps n;
+        n.c = std::max(want.c, c.c); n.cv = std::max(want.cv, c.cv);
+        n.g = std::max(want.g, c.g); n.e = std::max(want.e, c.e);
+        n.x = std::max(want.x, c.x); n.xv = std::max(want.xv, c.xv);
+        n.y = std::max(want.y, c.y); n.yv = std::max(want.yv, c.yv);
+        BSM_TRY(g->alloc(n));
     }
-    if (X.nnzb > g->cap_x) return BSM_OK;
     if (!g->have_graphs) BSM_TRY(g->capture_all());
     BSM_TRY(to_pool(X, g->x[0], g->nbr, g->s));
     g->x_nnzb = X.nnzb;
+    g->x_nval = X.nvalues;
     g->p = 0;
     free_mat_arrays(X, g->s);
     X.nnzb = g->x_nnzb;
-    X.nvalues = g->x_nnzb * g->b2;
+    X.nvalues = g->x_nval;
     free_mat_arrays(Y, g->s);
     g->on = true;
     return BSM_OK;
@@ -536,7 +656,10 @@ static int launch3(GraphIter *g, int first, int which) {
 int gi_square(GraphIter *g, GiStatus *out, double *smm_ms) {
     BSM_TRY(launch3(g, 0, 0));
     BSM_TRY(read_status(g, 0, out, smm_ms));
-    if (!out->over) g->y_nnzb = out->nnzb;
+    if (!out->over) {
+        g->y_nnzb = out->nnzb;
+        g->y_nval = out->nval;
+    }
     return BSM_OK;
 }
 
@@ -546,6 +669,7 @@ int gi_update(GraphIter *g, GiStatus *out, double *smm_ms) {
     if (!out->over && !(out->flags & kFlagNonFinite)) {
         g->p ^= 1;
         g->x_nnzb = out->nnzb;
+        g->x_nval = out->nval;
     }
     return BSM_OK;
 }
@@ -553,8 +677,8 @@ int gi_update(GraphIter *g, GiStatus *out, double *smm_ms) {
 int gi_leave(GraphIter *g, Mat &X, Mat *Y) {
     if (!g->on) return BSM_OK;
     g->on = false;
-    BSM_TRY(from_pool(*g, g->x[g->p], g->x_nnzb, X));
-    if (Y) BSM_TRY(from_pool(*g, g->y, g->y_nnzb, *Y));
+    BSM_TRY(from_pool(*g, g->x[g->p], g->x_nnzb, g->x_nval, X));
+    if (Y) BSM_TRY(from_pool(*g, g->y, g->y_nnzb, g->y_nval, *Y));
     return BSM_OK;
 }
 

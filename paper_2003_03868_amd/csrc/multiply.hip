@@ -87,66 +87,6 @@ static int mixed_variant(const SmmArgs &a, int requested) {
     return requested;
 }
 
-// Pairs of equal-size block rows (within bands of kPairBand rows, so that
-// chunk cuts at band edges never split a pair) and of equal-size block
-// columns (over all columns), for the mixed-size groups: rows of each size
-// in ascending order are paired in turn, the last one alone when their count
-// is odd; groups are listed by their first row (column).  band_g0[b] is the
-// first row group of band b.
-constexpr int32_t kPairBand = 32;
-
-struct MixedPairs {
-    std::vector<int32_t> rg, band_g0, cgrp, cslot, cmap;
-};
-
-static void mixed_pairs(const std::vector<int32_t> &rbs, const std::vector<int32_t> &cbs,
-                        MixedPairs *mp) {
-    const int32_t nbr = static_cast<int32_t>(rbs.size()), nbc = static_cast<int32_t>(cbs.size());
-    mp->rg.clear();
-    mp->band_g0.clear();
-    for (int32_t b0 = 0; b0 < nbr; b0 += kPairBand) {
-        mp->band_g0.push_back(static_cast<int32_t>(mp->rg.size() / 2));
-        const int32_t b1 = std::min(nbr, b0 + kPairBand);
-        std::vector<int32_t> open(kMaxBlock + 1, -1);     // unpaired row of each size
-        std::vector<std::pair<int32_t, int32_t>> groups;
-        for (int32_t i = b0; i < b1; ++i) {
-            int32_t &o = open[rbs[i]];
-            if (o < 0) { o = i; continue; }
-            groups.push_back({o, i});
-            o = -1;
-        }
-        for (int32_t v : open)
-            if (v >= 0) groups.push_back({v, -1});
-        std::sort(groups.begin(), groups.end());
-        for (auto &g : groups) { mp->rg.push_back(g.first); mp->rg.push_back(g.second); }
-    }
-    mp->band_g0.push_back(static_cast<int32_t>(mp->rg.size() / 2));
-    std::vector<int32_t> open(kMaxBlock + 1, -1);
-    std::vector<std::pair<int32_t, int32_t>> groups;
-    for (int32_t j = 0; j < nbc; ++j) {
-        int32_t &o = open[cbs[j]];
-        if (o < 0) { o = j; continue; }
-        groups.push_back({o, j});
-        o = -1;
-    }
-    for (int32_t v : open)
-        if (v >= 0) groups.push_back({v, -1});
-    std::sort(groups.begin(), groups.end());
-    mp->cgrp.assign(nbc, -1);
-    mp->cslot.assign(nbc, 0);
-    mp->cmap.clear();
-    for (size_t q = 0; q < groups.size(); ++q) {
-        mp->cmap.push_back(groups[q].first);
-        mp->cmap.push_back(groups[q].second);
-        mp->cgrp[groups[q].first] = static_cast<int32_t>(q);
-        mp->cslot[groups[q].first] = 0;
-        if (groups[q].second >= 0) {
-            mp->cgrp[groups[q].second] = static_cast<int32_t>(q);
-            mp->cslot[groups[q].second] = 1;
-        }
-    }
-}
-
 namespace {
 struct Events {
     bool on = false;
@@ -712,9 +652,11 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
     if (sizes) {
         sizes->nnzb_u = nnzb_c;
         sizes->nnzb = nnzb_after;
+        sizes->nval_u = nval_c;
+        sizes->nval = nc.nvalues;
         sizes->n_groups = sum_groups;
         sizes->n_entries = sum_entries;
-        sizes->groups = use_quad && prec == BSM_FP64;
+        sizes->groups = (use_quad && prec == BSM_FP64) || use_mquad;
     }
     if (stats) {
         stats->n_products = nprod;

@@ -17,10 +17,11 @@
 // columns instead of consecutive ones.  Row group g holds rows rg[2g],
 // rg[2g + 1] (the second -1 for a single row), column group Q the columns
 // cmap[2Q], cmap[2Q + 1]; the pairs join blocks of equal size (built on the
-// host, mixed_pairs in multiply.hip), so every C block of a group has the
+// host, mixed_pairs below), so every C block of a group has the
 // same shape and only k varies between entries.  Entry rules are the same:
 // the column of group Q met first in B's row k emits the entry, finding its
 // partner column by binary search.
+#include <algorithm>
 #include <climits>
 
 #include "symbolic.h"
@@ -399,6 +400,59 @@ int quad_seg_starts(const int64_t *seg_off, int32_t nseg, int64_t n_groups, int6
     k_seg_starts<<<grid_for(n_groups + 1, 256), 256, 0, s>>>(seg_off, nseg, n_groups, starts);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
+}
+
+// Pairs of equal-size block rows (within bands of kPairBand rows, so that
+// chunk cuts at band edges never split a pair) and of equal-size block
+// columns (over all columns), for the mixed-size groups: rows of each size
+// in ascending order are paired in turn, the last one alone when their count
+// is odd; groups are listed by their first row (column).  band_g0[b] is the
+// first row group of band b.
+void mixed_pairs(const std::vector<int32_t> &rbs, const std::vector<int32_t> &cbs, MixedPairs *mp) {
+    const int32_t nbr = static_cast<int32_t>(rbs.size()), nbc = static_cast<int32_t>(cbs.size());
+    mp->rg.clear();
+    mp->band_g0.clear();
+    for (int32_t b0 = 0; b0 < nbr; b0 += kPairBand) {
+        mp->band_g0.push_back(static_cast<int32_t>(mp->rg.size() / 2));
+        const int32_t b1 = std::min(nbr, b0 + kPairBand);
+        std::vector<int32_t> open(kMaxBlock + 1, -1);     // unpaired row of each size
+        std::vector<std::pair<int32_t, int32_t>> groups;
+        for (int32_t i = b0; i < b1; ++i) {
+            int32_t &o = open[rbs[i]];
+            if (o < 0) { o = i; continue; }
+            groups.push_back({o, i});
+            o = -1;
+        }
+        for (int32_t v : open)
+            if (v >= 0) groups.push_back({v, -1});
+        std::sort(groups.begin(), groups.end());
+        for (auto &g : groups) { mp->rg.push_back(g.first); mp->rg.push_back(g.second); }
+    }
+    mp->band_g0.push_back(static_cast<int32_t>(mp->rg.size() / 2));
+    std::vector<int32_t> open(kMaxBlock + 1, -1);
+    std::vector<std::pair<int32_t, int32_t>> groups;
+    for (int32_t j = 0; j < nbc; ++j) {
+        int32_t &o = open[cbs[j]];
+        if (o < 0) { o = j; continue; }
+        groups.push_back({o, j});
+        o = -1;
+    }
+    for (int32_t v : open)
+        if (v >= 0) groups.push_back({v, -1});
+    std::sort(groups.begin(), groups.end());
+    mp->cgrp.assign(nbc, -1);
+    mp->cslot.assign(nbc, 0);
+    mp->cmap.clear();
+    for (size_t q = 0; q < groups.size(); ++q) {
+        mp->cmap.push_back(groups[q].first);
+        mp->cmap.push_back(groups[q].second);
+        mp->cgrp[groups[q].first] = static_cast<int32_t>(q);
+        mp->cslot[groups[q].first] = 0;
+        if (groups[q].second >= 0) {
+            mp->cgrp[groups[q].second] = static_cast<int32_t>(q);
+            mp->cslot[groups[q].second] = 1;
+        }
+    }
 }
 
 }  // namespace bsm

@@ -26,7 +26,9 @@
 // q = (3003 - 6006 Y + 9009 Y^2) + Y^3 (231 Y^3 - 1638 Y^2 + 5005 Y - 8580).
 //
 // Graphs (opts.use_graph = 1): with uniform block sizes that have an FP64
-// group kernel, iterations run from graphs of the whole device-sized
+// group kernel (or mixed sizes in {5, 13, 23, 26} with the one-launch
+// paired-group kernel asked for), iterations run from graphs of the whole
+// device-sized
 // multiply (symbolic phase included; graph_iter.hip), captured after an FP64
 // iteration on the normal path whose update grew X's block count by at most
 // half, and re-captured with larger buffers after an overflow.  Otherwise
@@ -338,7 +340,6 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
         GraphIter *g;
         ~GiGuard() { gi_destroy(g); }
     } gi_guard{G};
-    const double b3 = dev_graph ? static_cast<double>(X->uni_r) * X->uni_r * X->uni_r : 0.0;
     Replay R;
     R.s = s;
     if (want_graph) {
@@ -374,7 +375,7 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
                 if (rc != BSM_OK) break;
             } else {
                 st->n_multiplies++;
-                st->flops += 2.0 * b3 * static_cast<double>(gs.n_products);
+                st->flops += gs.flops;
                 st->n_products += gs.n_products;
                 st->smm_launches += 1;
                 st->smm_ms += gms;
@@ -393,6 +394,8 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
                 if (dcs != kGoOn) { rc = (dcs == kStop) ? BSM_OK : BSM_ENOCONV; break; }
                 sz_sq.nnzb_u = gs.nnzb_u;
                 sz_sq.nnzb = gs.nnzb;
+                sz_sq.nval_u = gs.nval_u;
+                sz_sq.nval = gs.nval;
                 sz_sq.n_groups = gs.n_groups;
                 sz_sq.n_entries = gs.n_entries;
                 sz_sq.groups = true;
@@ -407,7 +410,7 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
                     update_only = true;
                 } else {
                     st->n_multiplies++;
-                    st->flops += 2.0 * b3 * static_cast<double>(gu.n_products);
+                    st->flops += gu.flops;
                     st->n_products += gu.n_products;
                     st->smm_launches += 1;
                     st->smm_ms += gms;

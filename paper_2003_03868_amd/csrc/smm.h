@@ -69,7 +69,7 @@ struct SmmArgs {
     unsigned long long *counter;  // work counter of the persistent kernel (NULL: allocated per launch)
     // group kernel: GR x GC groups of C blocks (2 x 2: quads) with merged product lists
     int64_t n_quads;            // groups
-    const int64_t *n_quads_dev; // FP64 group kernel: the group count in device memory (the
+    const int64_t *n_quads_dev; // FP64 group kernels: the group count in device memory (the
                                 // launch then covers up to n_quads groups); NULL: n_quads
     const int64_t *q_cblk;      // [GR GC n_quads] C block (r, c) of the group at GC r + c, or -1
     const int64_t *q_seg;       // [n_quads + 1] entry segments
@@ -105,7 +105,8 @@ int launch_quad(const SmmArgs &a, hipStream_t s);
 // groups built with paired rows and columns (a.counter: work counter).
 int launch_mquad(const SmmArgs &a, hipStream_t s);
 // Work order of the mixed-size groups (largest m n first, group order within
-// a class) into order[a.n_quads]; rank_scratch holds a.n_quads bytes.
+// a class) into order[a.n_quads]; rank_scratch holds a.n_quads bytes (with
+// a.n_quads_dev, the first *a.n_quads_dev groups are ordered).
 int mquad_order(const SmmArgs &a, int8_t *rank_scratch, int64_t *order, hipStream_t s);
 
 // Reduced-precision products (smm_lowp.hip).

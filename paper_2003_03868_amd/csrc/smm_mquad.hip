@@ -271,17 +271,18 @@ k_smm_f64_mquad(SmmArgs a, unsigned long long *counter) {
     for (int e = EPS * 4 * kMqSlot + static_cast<int>(threadIdx.x); e < EPS * 4 * kMqSlot + kMqTail;
          e += 64 * kMqWaves)
         sm[e] = 0.0;
+    const int64_t n_items = a.n_quads_dev ? *a.n_quads_dev : a.n_quads;
     for (;;) {
         if (threadIdx.x == 0) {
             const int64_t it = static_cast<int64_t>(atomicAdd(counter, 1ull));
             s_item = it;
-            s_cls = it < a.n_quads ? mq_class(a, a.q_order ? a.q_order[it] : it) : -1;
+            s_cls = it < n_items ? mq_class(a, a.q_order ? a.q_order[it] : it) : -1;
         }
         __syncthreads();
         const int64_t it = s_item;
         const int cls = s_cls;
         __syncthreads();                 // s_item, s_cls are rewritten by the next item
-        if (it >= a.n_quads) break;      // every wave of the workgroup leaves together
+        if (it >= n_items) break;        // every wave of the workgroup leaves together
         const int64_t item = a.q_order ? a.q_order[it] : it;
         switch (cls) {
 #define BSM_MQ(ID, MM, NN) case ID: mq_item<MM, NN, EPS>(a, item, sm, md); break;
@@ -310,16 +311,22 @@ __device__ inline int mq_rank_of_class(int cls) {
     return cls < 0 ? 15 : rank[cls];
 }
 
+// Groups counted in device memory (a.n_quads_dev) or a.n_quads.
+__device__ inline int64_t mq_count(const SmmArgs &a) {
+    return a.n_quads_dev ? *a.n_quads_dev : a.n_quads;
+}
+
 __global__ void k_mq_class_of(SmmArgs a, int8_t *rank) {
     const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q >= a.n_quads) return;
+    if (q >= mq_count(a)) return;
     rank[q] = static_cast<int8_t>(mq_rank_of_class(mq_class(a, q)));
 }
 
 // One workgroup per rank r: the positions of rank r's groups, in ascending
 // group order, after every group of a smaller rank.
 __global__ void __launch_bounds__(kMqOrderThreads)
-k_mq_order(const int8_t *rank, int64_t n, int64_t *order) {
+k_mq_order(const int8_t *rank, SmmArgs a, int64_t *order) {
+    const int64_t n = mq_count(a);
     __shared__ int64_t s_wave[kMqOrderThreads / kWave];
     __shared__ int64_t s_base, s_run;
     const int r = blockIdx.x;
@@ -363,7 +370,7 @@ k_mq_order(const int8_t *rank, int64_t n, int64_t *order) {
 int mquad_order(const SmmArgs &a, int8_t *rank_scratch, int64_t *order, hipStream_t s) {
     if (a.n_quads <= 0) return BSM_OK;
     k_mq_class_of<<<grid_for(a.n_quads, 256), 256, 0, s>>>(a, rank_scratch);
-    k_mq_order<<<16, kMqOrderThreads, 0, s>>>(rank_scratch, a.n_quads, order);
+    k_mq_order<<<16, kMqOrderThreads, 0, s>>>(rank_scratch, a, order);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }

@@ -87,6 +87,18 @@ struct QuadSymArgs {
     const int32_t *cslot;        // [nbcols] slot (0 or 1) of column j in its group
     const int32_t *cmap;         // [2 ncg] columns of column group Q (second -1 for one)
 };
+// Pairs of equal-size block rows (within bands of kPairBand rows) and of
+// equal-size block columns for the mixed-size groups (quad.hip): rg[2g],
+// rg[2g + 1] are the rows of row group g (second -1 for a single row),
+// band_g0[b] the first row group of band b (band_g0.back(): all row groups),
+// cmap[2Q], cmap[2Q + 1] the columns of column group Q, cgrp[j] and cslot[j]
+// column j's group and slot.
+constexpr int32_t kPairBand = 32;
+struct MixedPairs {
+    std::vector<int32_t> rg, band_g0, cgrp, cslot, cmap;
+};
+void mixed_pairs(const std::vector<int32_t> &rbs, const std::vector<int32_t> &cbs, MixedPairs *mp);
+
 // k segments of the group lists' walk for nbk block columns of A.
 int32_t quad_ksegments(int32_t nbk);
 int quad_pairs(const QuadSymArgs &q, int64_t *cnt, hipStream_t s);

@@ -166,6 +166,34 @@ def test_device_sized_graphs_match_normal_path_and_oracle(orc, c):
     assert_same_matrix(got[1], x_ref, TOL_FP64, "device-sized graph sign")
 
 
+@pytest.mark.parametrize("eps,chunk", [(0.0, None), (1e-6, None), (1e-6, "3000")],
+                         ids=["unfiltered", "filtered", "filtered_chunks"])
+def test_device_sized_graphs_mixed_sizes(orc, monkeypatch, eps, chunk):
+    """Mixed block sizes {5, 13, 23, 26} with every (m, n) class in one
+    persistent launch per multiply (BSM_SMM_VARIANT=7): the graphs run the
+    paired-group kernel over the device count of groups, with value offsets
+    scanned on the device; the normal path (in chunks of 3000 products when
+    asked) gives the same bits."""
+    from paper_2003_03868_amd import bsm
+    monkeypatch.setenv("BSM_SMM_VARIANT", "7")
+    if chunk:
+        monkeypatch.setenv("BSM_CHUNK_PRODUCTS", chunk)
+    h = synth.neighbour_hamiltonian(120, seed=9, cutoff=4.5, size_choices=(5, 13, 23, 26))
+    print(f"mixed sizes, eps {eps:g}, chunk {chunk}", flush=True)
+    ref = _run(h, eps, 1e-8, 0)
+    got = _run(h, eps, 1e-8, 1)
+    assert got[0] == bsm.OK, bsm.bsm_last_error()
+    _same_run(ref, got)
+    s = got[2]
+    print(f"  iterations {s.iterations}, replays {s.graph_replays}, fallbacks {s.graph_fallbacks}, "
+          f"nnzb(X) {list(s.nnzb_x_hist[:s.iterations + 1])}")
+    assert s.graph_replays > 0
+    assert list(s.nnzb_y_hist[:s.iterations + 1]) == list(ref[2].nnzb_y_hist[:s.iterations + 1])
+    x_ref, st_ref, s_ref = orc.sign_ns(h, eps=eps, tol=1e-8)
+    assert s_ref == orc.OK and s.iterations == st_ref["iterations"]
+    assert_same_matrix(got[1], x_ref, TOL_FP64, "device-sized graph sign, mixed sizes")
+
+
 # BSM_GRAPH_CAPS multiplies the capacities (unfiltered C blocks, groups,
 # entries, X, Y): one of them below the sizes makes that buffer overflow.
 OVERFLOW_CASES = [
@@ -174,6 +202,8 @@ OVERFLOW_CASES = [
     ("entries", "1,1,0.5,1,1", dict(n=96, b=13, rc=4.5, eps=0.0, seed=4, tol=1e-10)),
     ("y", "1,1,1,1,0.5", dict(n=100, b=23, rc=4.2, eps=1e-6, seed=6, tol=1e-8)),
     ("x", "1,1,1,0.01,1", dict(n=100, b=23, rc=4.2, eps=1e-6, seed=6, tol=1e-8)),
+    ("mixed_c", "0.5,1,1,1,1", dict(n=120, b=None, rc=4.5, eps=1e-6, seed=9, tol=1e-8)),
+    ("mixed_y", "1,1,1,1,0.5", dict(n=120, b=None, rc=4.5, eps=1e-6, seed=9, tol=1e-8)),
 ]
 
 
@@ -187,7 +217,12 @@ def test_device_sized_graphs_overflow_falls_back(orc, monkeypatch, which, caps, 
     overflows (the square runs from the graphs, the update is redone)."""
     from paper_2003_03868_amd import bsm
     monkeypatch.setenv("BSM_GRAPH_CAPS", caps)
-    h = synth.neighbour_hamiltonian(case["n"], case["b"], cutoff=case["rc"], seed=case["seed"])
+    if case["b"] is None:
+        monkeypatch.setenv("BSM_SMM_VARIANT", "7")
+        h = synth.neighbour_hamiltonian(case["n"], seed=case["seed"], cutoff=case["rc"],
+                                        size_choices=(5, 13, 23, 26))
+    else:
+        h = synth.neighbour_hamiltonian(case["n"], case["b"], cutoff=case["rc"], seed=case["seed"])
     print(f"overflow of {which}: n={case['n']} b={case['b']}", flush=True)
     ref = _run(h, case["eps"], case["tol"], 0)
     got = _run(h, case["eps"], case["tol"], 1)
