@@ -81,7 +81,7 @@ def cpu_baseline(h, rows: int, step_flops: float = 0.0, rows_1t: int = 96):
     return out
 
 
-KERNEL_SOURCES = ["smm.h", "smm_quad.hip", "quad.hip", "multiply.hip"]
+KERNEL_SOURCES = ["smm.h", "smm_quad.hip", "quad.hip", "multiply.hip", "graph_iter.hip"]
 
 
 def sources_sha256() -> str:
@@ -95,17 +95,20 @@ def sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, graph: int):
     """HBM bytes per launch of the block-product kernel from the committed
     rocprofv3 counter summary, or None when the kernel sources have changed
-    since the counters were taken (or none were taken for this workload)."""
+    since the counters were taken, they were taken with another graph mode
+    (which changes the launches), or none were taken for this workload."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     try:
         d = json.load(open(path))
         sha = sources_sha256()
     except (OSError, ValueError):
         return None
-    return d["hbm_bytes_per_launch"] if d.get("source_sha256") == sha else None
+    if d.get("source_sha256") != sha or d.get("graph") != graph:
+        return None
+    return d["hbm_bytes_per_launch"]
 
 
 def bench_nonorth(args, h, dh, bsm, synth, torch):
@@ -442,8 +445,10 @@ def main():
                     help="mixed workload: every (m, n) class in one persistent launch per "
                          "multiply with operand sharing (fused, the configuration's form) or "
                          "one launch per class (the library default, measured faster)")
-    ap.add_argument("--graph", type=int, choices=[0, 1], default=0,
-                    help="1: replay captured hipGraphs once X's block pattern stops changing")
+    ap.add_argument("--graph", type=int, choices=[0, 1, 2], default=1,
+                    help="1 (default): iterations from captured hipGraphs of the whole "
+                         "device-sized multiply once X's block count settles; 2: replay of "
+                         "the numeric kernels once X's block pattern stops changing; 0: none")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -656,7 +661,7 @@ def main():
             "block": {"sign23": 23, "water": 6}.get(args.workload, "5/13/23/26"),
             "n": int(n), "eps_filter": args.eps, "kernel_table": args.table,
             "tol": args.tol, "seed": args.seed, "nnzb_H": h.nnzb,
-            "graph_replay": bool(args.graph), "order": args.order,
+            "graph_mode": args.graph, "order": args.order,
             "mixed_kernel": (args.mixed_kernel if args.workload == "mixed" else None),
             "eps_screen": args.screen,
         },
@@ -681,7 +686,7 @@ def main():
             "peak": PEAK_TFLOPS[args.prec],
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[args.prec],
-            "traffic": measured_traffic("sign23")
+            "traffic": measured_traffic("sign23", args.graph)
             if (args.prec == "fp64" and args.workload == "sign23" and args.sites == 2048
                 and args.eps == 1e-6 and args.table == "exhaustive" and args.screen == 0.0)
             else None,

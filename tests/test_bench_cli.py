@@ -32,16 +32,21 @@ def test_cpu_baseline_fields():
 def test_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
     import bench
     d = json.load(open(os.path.join(ROOT, "profiles", "traffic_sign23.json")))
-    got = bench.measured_traffic("sign23")
+    got = bench.measured_traffic("sign23", d.get("graph", 0))
     if d["source_sha256"] == bench.sources_sha256():
         assert got == d["hbm_bytes_per_launch"]
     else:
         assert got is None
-    # a profile taken on other sources is not reported
+    # a profile taken on other sources, or with another graph mode (other
+    # launches), is not reported
     prof = tmp_path / "profiles"
     prof.mkdir()
+    d["graph"] = 1
     d["source_sha256"] = "0" * 64
     (prof / "traffic_sign23.json").write_text(json.dumps(d))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "sources_sha256", lambda: "f" * 64)
-    assert bench.measured_traffic("sign23") is None
+    assert bench.measured_traffic("sign23", 1) is None
+    monkeypatch.setattr(bench, "sources_sha256", lambda: "0" * 64)
+    assert bench.measured_traffic("sign23", 1) == d["hbm_bytes_per_launch"]
+    assert bench.measured_traffic("sign23", 0) is None

@@ -5,7 +5,8 @@ The records (``tests/golden/fullsize_<workload>_s<seed>.npz``) are written by
 ``tests/golden/make_fullsize.py``, which runs only the CPU oracle on the same
 seeded workloads (2048 sites x 23 with eps_filter 1e-6 and 1e-5; 4096 sites
 of sizes {5, 13, 23, 26}).  The GPU runs ``bsm_sign_iterate`` with the
-benchmark's settings (default kernels, chunking and options) and must give:
+benchmark's settings (default kernels, chunking and options, iterations from
+the device-sized graphs; sign23 seed 0 also without graphs) and must give:
 
 * the same number of iterations and, at every iterate, the same number of
   stored blocks of X_k and of Y_k = filter(X_k X_k) (Sign-Method section:
@@ -36,11 +37,12 @@ from tests.golden.make_fullsize import (WORKLOADS, hamiltonian, load_fixture, pa
 
 pytestmark = pytest.mark.gpu
 
-# (workload, seed, kernel variant): the mixed workload both with the
-# paired-group kernel in one launch per multiply (bench.py --workload mixed)
-# and with the library default, one launch per (m, n) class
-CASES = [("sign23", 0, None), ("sign23", 1, None), ("sign23", 2, None), ("sign23_e5", 0, None),
-         ("mixed", 0, "7"), ("mixed", 0, "4")]
+# (workload, seed, kernel variant, graph mode): the mixed workload both with
+# the paired-group kernel in one launch per multiply (bench.py --workload
+# mixed) and with the library default, one launch per (m, n) class
+CASES = [("sign23", 0, None, 1), ("sign23", 0, None, 0), ("sign23", 1, None, 1),
+         ("sign23", 2, None, 1), ("sign23_e5", 0, None, 1), ("mixed", 0, "7", 1),
+         ("mixed", 0, "4", 1)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -55,14 +57,15 @@ def _fixture(workload, seed):
     return fx
 
 
-def _sign(h, workload, prec=0):
+def _sign(h, workload, prec=0, graph=1):
     from paper_2003_03868_amd import bsm
     from tests.gpu_util import from_dev, to_dev
     w = WORKLOADS[workload]
     dh = to_dev(h)
     o = bsm.bsm_sign_opts_default()
-    o.eps_filter, o.tol, o.prec = w["eps"], w["tol"], prec
-    print(f"sign iteration: {workload}, {h.nbrows} sites, prec {prec}", flush=True)
+    o.eps_filter, o.tol, o.prec, o.use_graph = w["eps"], w["tol"], prec, graph
+    print(f"sign iteration: {workload}, {h.nbrows} sites, prec {prec}, graph mode {graph}",
+          flush=True)
     st, xh, stats = bsm.bsm_sign_iterate(dh.handle, 0.0, o)
     assert st == bsm.OK, bsm.bsm_last_error()
     x = from_dev(bsm.Matrix(xh, h.row_blk_size, h.col_blk_size))
@@ -80,15 +83,16 @@ def _probe_err(x, fx):
     return errs, row_err
 
 
-@pytest.mark.parametrize("workload,seed,variant", CASES,
-                         ids=[f"{w}-s{s}" + (f"-v{v}" if v else "") for w, s, v in CASES])
-def test_sign_full_size_matches_oracle(monkeypatch, workload, seed, variant):
+@pytest.mark.parametrize("workload,seed,variant,graph", CASES,
+                         ids=[f"{w}-s{s}" + (f"-v{v}" if v else "") + f"-g{g}"
+                              for w, s, v, g in CASES])
+def test_sign_full_size_matches_oracle(monkeypatch, workload, seed, variant, graph):
     fx = _fixture(workload, seed)
     if variant is not None:
         monkeypatch.setenv("BSM_SMM_VARIANT", variant)
     h = hamiltonian(workload, seed)
     assert h.nbrows == int(fx["sites"])
-    x, st = _sign(h, workload)
+    x, st = _sign(h, workload, graph=graph)
     k = int(fx["iterations"])
     assert st.iterations == k, (st.iterations, k)
     gx = np.array(st.nnzb_x_hist[:k + 1])
@@ -107,7 +111,8 @@ def test_sign_full_size_matches_oracle(monkeypatch, workload, seed, variant):
     trace_bound = 0.5 * math.sqrt(n) * TOL_FP64 * x_fro
     dtr = abs(st.trace_p - float(fx["trace_p"]))
     assert dtr <= trace_bound, (dtr, trace_bound)
-    print(f"{workload} seed {seed}: {k} iterations, nnzb(X) {x.nnzb}, probe errors "
+    print(f"{workload} seed {seed}: {k} iterations ({st.graph_replays} from graphs), "
+          f"nnzb(X) {x.nnzb}, probe errors "
           f"{max(errs):.2e}, row-norm error {row_err:.2e}, |dtrace(P)| {dtr:.2e} "
           f"(bound {trace_bound:.1e}), max r_k rel diff "
           f"{float(np.max(np.abs(r / fx['r_hist'] - 1))):.1e}")
