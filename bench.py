@@ -197,12 +197,51 @@ def bench_mult832(args, bsm, synth, torch):
         times.append(time.perf_counter() - t)
     med = float(np.median(times))
     kernel_ran = bsm.bsm_last_smm_kernel()
+
+    # Numeric-only repeats of the same multiply from a plan (kernels only: no
+    # wait, no allocation), back to back, and the same call captured in a
+    # hipGraph and replayed: device time per call between events.
+    dp = bsm.Matrix.empty_like(a.row_blk_size, b.col_blk_size)
+    plan, _ = bsm.bsm_multiply_plan(1.0, da.handle, db.handle, dp.handle, 0.0, stream=stream)
+    for _ in range(10):
+        bsm.bsm_plan_execute(plan, da.handle, db.handle, dp.handle, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        bsm.bsm_plan_execute(plan, da.handle, db.handle, dp.handle, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plan_ms = e0.elapsed_time(e1) / reps
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(stream)
+    with torch.cuda.stream(cs):
+        with torch.cuda.graph(g, stream=cs):
+            bsm.bsm_plan_execute(plan, da.handle, db.handle, dp.handle,
+                                 stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / reps
+    if bsm.bsm_plan_status(plan, stream=stream) != 0:
+        raise RuntimeError("planned 832 multiply: the record flags NaN/Inf or another keep-set")
+    same = np.array_equal(dp.export()[2], dc.export()[2])
+    del g
+    bsm.bsm_plan_destroy(plan)
+    if not same:
+        raise RuntimeError("planned 832 multiply differs from bsm_multiply")
+
     t0 = time.perf_counter()
     oracle.multiply(1.0, a, b)
     cpu_dt = time.perf_counter() - t0
     achieved = st.flops / (st.smm_ms * 1e-3) / 1e12 if st.smm_ms > 0 else 0.0
     log(f"832 multiply: median {med * 1e3:.3f} ms over {reps} calls, block products "
-        f"{st.smm_ms * 1e3:.1f} us, {st.n_products} products")
+        f"{st.smm_ms * 1e3:.1f} us, {st.n_products} products; planned repeats "
+        f"{plan_ms * 1e3:.1f} us per call, graph replays {graph_ms * 1e3:.1f} us per call")
     print(json.dumps({
         "metric": "block-sparse multiply GFLOP/s (FP64 vs mixed); sign-iteration time to 1e-6",
         "value": st.flops / med / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": reps,
@@ -213,6 +252,7 @@ def bench_mult832(args, bsm, synth, torch):
                                "20% of blocks present, eps_filter 0; median of repeated calls",
                    "seed": args.seed},
         "products": int(st.n_products), "flops": float(st.flops),
+        "plan_execute_ms_per_call": plan_ms, "graph_replay_ms_per_call": graph_ms,
         "roofline": {"bound": "mfma", "kernel": kernel_ran,
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,

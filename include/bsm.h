@@ -46,6 +46,7 @@ extern "C" {
 #endif
 
 typedef struct bsm_matrix_s *bsm_matrix;
+typedef struct bsm_plan_s *bsm_plan;
 
 typedef enum {
     BSM_OK = 0,
@@ -215,6 +216,43 @@ int bsm_export(bsm_matrix m, int64_t *row_ptr, int32_t *col_idx, double *values,
 int bsm_multiply(double alpha, bsm_matrix A, bsm_matrix B, double beta, bsm_matrix C,
                  double eps_filter, int32_t norm, int32_t prec,
                  bsm_mult_stats *stats, void *stream);
+
+/*
+ * C = alpha*A*B (beta = 0), then the filter, exactly as bsm_multiply, and a
+ * plan of it: the multiply's symbolic results -- C's pattern, the product
+ * lists or groups, their work order, the filter's keep-set -- kept in device
+ * memory for numeric-only repeats with bsm_plan_execute (the DBCSR section's
+ * Local multiplication: what is multiplied is decided apart from doing it).
+ * *plan_out holds device memory until bsm_plan_destroy and refers to no
+ * handle.  C may not be A or B (BSM_EINVAL); otherwise as bsm_multiply.
+ */
+int bsm_multiply_plan(double alpha, bsm_matrix A, bsm_matrix B, bsm_matrix C,
+                      double eps_filter, int32_t norm, int32_t prec, bsm_plan *plan_out,
+                      bsm_mult_stats *stats, void *stream);
+
+/*
+ * Numeric-only repeat of a planned multiply: C's values become alpha*A*B for
+ * the current values of A and B (same kernels, so the same bits as
+ * bsm_multiply), in the layout C got from bsm_multiply_plan.  Kernels only --
+ * no allocation, copy or wait -- so the call may be captured into a hipGraph.
+ * A and B must have the block patterns of the planning call and C its
+ * result's pattern: block and scalar counts are checked (BSM_EINVAL), equal
+ * positions are the caller's promise.  C may not be A or B.  Whether the
+ * filter would now keep another block set, and whether a NaN/Inf appeared,
+ * is recorded on the device for bsm_plan_status.
+ */
+int bsm_plan_execute(bsm_plan plan, bsm_matrix A, bsm_matrix B, bsm_matrix C, void *stream);
+
+/*
+ * Waits for stream and reports the executes since the last report:
+ * *flags bit 0 = a result block held NaN or Inf, bit 1 = the filter would
+ * have kept another block set (that result is the unfiltered product's kept
+ * part, not a filtered product); then clears the record.
+ */
+int bsm_plan_status(bsm_plan plan, int32_t *flags, void *stream);
+
+/* Release a plan's device memory (NULL: no-op). */
+int bsm_plan_destroy(bsm_plan plan);
 
 /*
  * bsm_multiply with product-level norm screening (the Sign-Method section's

@@ -106,6 +106,12 @@ _SIGS = [
     ("bsm_multiply_screened", C.c_int, [C.c_double, C.c_void_p, C.c_void_p, C.c_double,
                                         C.c_void_p, C.c_double, C.c_int32, C.c_double,
                                         C.POINTER(bsm_mult_stats), C.c_void_p]),
+    ("bsm_multiply_plan", C.c_int, [C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                    C.c_int32, C.c_int32, C.POINTER(C.c_void_p),
+                                    C.POINTER(bsm_mult_stats), C.c_void_p]),
+    ("bsm_plan_execute", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("bsm_plan_status", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
+    ("bsm_plan_destroy", C.c_int, [C.c_void_p]),
     ("bsm_filter", C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
     ("bsm_block_norms", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("bsm_trace", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
@@ -240,6 +246,32 @@ def bsm_multiply_screened(alpha, A, B, beta, Cm, eps_filter=0.0, norm=NORM_FROB,
                                       _stream(stream))
     _check(st, "bsm_multiply_screened")
     return stats
+
+
+def bsm_multiply_plan(alpha, A, B, Cm, eps_filter=0.0, norm=NORM_FROB, prec=FP64,
+                      stream=None):
+    """C = alpha A B and a plan for numeric-only repeats: returns (plan, stats)."""
+    plan = C.c_void_p()
+    stats = bsm_mult_stats()
+    st = load().bsm_multiply_plan(float(alpha), A, B, Cm, float(eps_filter), int(norm), int(prec),
+                                  C.byref(plan), C.byref(stats), _stream(stream))
+    _check(st, "bsm_multiply_plan")
+    return plan.value, stats
+
+
+def bsm_plan_execute(plan, A, B, Cm, stream=None) -> None:
+    _check(load().bsm_plan_execute(plan, A, B, Cm, _stream(stream)), "bsm_plan_execute")
+
+
+def bsm_plan_status(plan, stream=None) -> int:
+    """Bit 0: NaN/Inf; bit 1: the filter would have kept another block set."""
+    f = C.c_int32(0)
+    _check(load().bsm_plan_status(plan, C.byref(f), _stream(stream)), "bsm_plan_status")
+    return f.value
+
+
+def bsm_plan_destroy(plan) -> None:
+    _check(load().bsm_plan_destroy(plan), "bsm_plan_destroy")
 
 
 def bsm_filter(h, eps_filter, norm=NORM_FROB, stream=None) -> None:

@@ -3,6 +3,7 @@
 #include <cstring>
 
 #include "bsm_internal.h"
+#include "plan.h"
 #include "smm.h"
 
 namespace bsm {
@@ -26,6 +27,12 @@ using bsm::Mat;
 
 struct bsm_matrix_s {
     Mat m;
+};
+
+struct bsm_plan_s {
+    bsm::MulPlan *p = nullptr;
+    int *flags = nullptr;        // device record of the executes
+    hipStream_t s = nullptr;     // stream the plan's memory is released on
 };
 
 static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -180,6 +187,79 @@ int bsm_multiply(double alpha, bsm_matrix A, bsm_matrix B, double beta, bsm_matr
     if (stats) std::memset(stats, 0, sizeof(*stats));
     return bsm::multiply(alpha, A->m, B->m, beta, C->m, eps_filter, norm, prec, stats,
                          as_stream(stream));
+}
+
+int bsm_multiply_plan(double alpha, bsm_matrix A, bsm_matrix B, bsm_matrix C, double eps_filter,
+                      int32_t norm, int32_t prec, bsm_plan *plan_out, bsm_mult_stats *stats,
+                      void *stream) {
+    bsm::clear_error();
+    if (!A || !B || !C || !plan_out) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    *plan_out = nullptr;
+    if (C == A || C == B) { bsm::set_error("a planned product may not overwrite an operand"); return BSM_EINVAL; }
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    hipStream_t s = as_stream(stream);
+    bsm::MulPlan *pl = nullptr;
+    int st = bsm::multiply(alpha, A->m, B->m, 0.0, C->m, eps_filter, norm, prec, stats, s, &pl);
+    if (st != BSM_OK) {
+        bsm::free_plan(pl);
+        return st;
+    }
+    bsm_plan_s *h = new bsm_plan_s;
+    h->p = pl;
+    h->s = s;
+    st = bsm::dalloc(&h->flags, 1, s);
+    if (st == BSM_OK) st = bsm::zero_flag(h->flags, s);
+    if (st != BSM_OK) {
+        bsm::dfree(h->flags, s);
+        bsm::free_plan(pl);
+        delete h;
+        return st;
+    }
+    *plan_out = h;
+    return BSM_OK;
+}
+
+int bsm_plan_execute(bsm_plan plan, bsm_matrix A, bsm_matrix B, bsm_matrix C, void *stream) {
+    bsm::clear_error();
+    if (!plan || !A || !B || !C) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    if (C == A || C == B) { bsm::set_error("a planned product may not overwrite an operand"); return BSM_EINVAL; }
+    const bsm::MulPlan &p = *plan->p;
+    if (C->m.nnzb != p.nnzb || C->m.nvalues != p.nval || C->m.nbrows != A->m.nbrows ||
+        C->m.nbcols != B->m.nbcols) {
+        bsm::set_error("C does not have the planned product's pattern (%lld blocks, %lld "
+                       "scalars expected)", static_cast<long long>(p.nnzb),
+                       static_cast<long long>(p.nval));
+        return BSM_EINVAL;
+    }
+    if ((&A->m == &B->m) != p.same_ab) {
+        bsm::set_error("the plan was made for %s operands", p.same_ab ? "identical" : "distinct");
+        return BSM_EINVAL;
+    }
+    hipStream_t s = as_stream(stream);
+    const int st = bsm::replay_multiply(*plan->p, A->m, B->m, nullptr, C->m.values, plan->flags, s);
+    C->m.stream = s;
+    return st;
+}
+
+int bsm_plan_status(bsm_plan plan, int32_t *flags, void *stream) {
+    bsm::clear_error();
+    if (!plan || !flags) { bsm::set_error("NULL argument"); return BSM_EINVAL; }
+    hipStream_t s = as_stream(stream);
+    int h = 0;
+    BSM_HIP(hipMemcpyAsync(&h, plan->flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    BSM_HIP(hipStreamSynchronize(s));
+    BSM_TRY(bsm::zero_flag(plan->flags, s));
+    *flags = ((h & bsm::kFlagNonFinite) ? 1 : 0) | ((h & bsm::kFlagPattern) ? 2 : 0);
+    return BSM_OK;
+}
+
+int bsm_plan_destroy(bsm_plan plan) {
+    bsm::clear_error();
+    if (!plan) return BSM_OK;
+    bsm::dfree(plan->flags, plan->s);
+    bsm::free_plan(plan->p);
+    delete plan;
+    return BSM_OK;
 }
 
 int bsm_multiply_screened(double alpha, bsm_matrix A, bsm_matrix B, double beta, bsm_matrix C,
