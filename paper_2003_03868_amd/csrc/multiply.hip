@@ -50,6 +50,19 @@ static int quad_tile(const char *name, int dflt) {
     return e ? atoi(e) : dflt;
 }
 
+// Fewest products per C block for the FP64 group kernel.  Its group lists
+// cost a symbolic pass and two more host waits, and the operands a group
+// shares are few when C blocks have few products: on random 20%-dense
+// products of 64-384 block rows (3-15 products per C block, 13 x 13 and
+// 23 x 23 blocks) the one-block kernel took 20-35% less time per call, while
+// on the sign workload (16 and more) the groups are faster.  Below this
+// count the one-block kernel runs, unless BSM_SMM_VARIANT names a kernel or
+// screening needs the groups; BSM_QUAD_MIN_REUSE overrides it.
+static double quad_min_reuse() {
+    const char *e = getenv("BSM_QUAD_MIN_REUSE");
+    return e ? atof(e) : 8.0;
+}
+
 // Quads for reduced-precision products: BSM_LOWP_QUAD = 1 always, 0 never;
 // default for split-BF16 only (for FP32 products the one-block-per-wave
 // kernel measured faster).
@@ -284,6 +297,9 @@ int multiply(double alpha, Mat &A, Mat &B, double beta, Mat &C, double eps, int 
         smm_quad_available(A.uni_r, B.uni_c, A.uni_c)) {
         SmmParams tp;
         use_quad = !(table_lookup(A.uni_r, B.uni_c, A.uni_c, &tp) && tp.family != 3);
+        if (use_quad && tau == 0.0 && !getenv("BSM_SMM_VARIANT") &&
+            static_cast<double>(nprod) < quad_min_reuse() * static_cast<double>(nnzb_c))
+            use_quad = false;
     }
     // reduced precision: quads where they pay, unless another kernel
     // variant is asked for
