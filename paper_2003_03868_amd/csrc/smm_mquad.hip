@@ -97,7 +97,7 @@ __device__ inline void mq_offsets(const SmmArgs &a, int4 en, int64_t (&o)[4], in
 // One work item (group) of class (M, N); EPS entries are staged per barrier
 // pair (slot set q of LDS holds entry t + q).
 template <int M, int N, int EPS>
-__device__ __attribute__((noinline)) void mq_item(const SmmArgs &a, int64_t item, double *sm, MqMeta &md) {
+__device__ inline void mq_item(const SmmArgs &a, int64_t item, double *sm, MqMeta &md) {
     constexpr int MT = (M + 3) / 4, NT = (N + 3) / 4;
     constexpr int HR = (MT + 1) / 2, HC = (NT + 1) / 2;
     const int lane = threadIdx.x % kWave;
@@ -258,6 +258,39 @@ __device__ inline int mq_class(const SmmArgs &a, int64_t item) {
     return (cm < 0 || cn < 0) ? -1 : 4 * cm + cn;
 }
 
+// The next work item from the counter into s_item, its class into s_cls
+// (-1 past the end); every wave of the workgroup sees both.
+__device__ inline void mq_next(const SmmArgs &a, int64_t n_items, unsigned long long *counter,
+                               int64_t &s_item, int &s_cls, int64_t &it, int &cls) {
+    if (threadIdx.x == 0) {
+        const int64_t x = static_cast<int64_t>(atomicAdd(counter, 1ull));
+        s_item = x;
+        s_cls = x < n_items ? mq_class(a, a.q_order ? a.q_order[x] : x) : -1;
+    }
+    __syncthreads();
+    it = s_item;
+    cls = s_cls;
+    __syncthreads();                 // s_item, s_cls are rewritten by the next call
+}
+
+// Items of class (M, N) from `it` on, taking the next item from the counter
+// until one of another class (or none) comes: the work order lists a
+// class's groups together, so a workgroup enters this once per class it
+// meets rather than once per group.  Returns that item; *cls its class.
+template <int M, int N, int EPS>
+__device__ __attribute__((noinline)) int64_t
+mq_run(const SmmArgs &a, int64_t n_items, unsigned long long *counter, int64_t it, int *cls,
+       double *sm, MqMeta &md, int64_t &s_item, int &s_cls) {
+    const int me = *cls;
+    int c = me;
+    while (it < n_items && c == me) {
+        mq_item<M, N, EPS>(a, a.q_order ? a.q_order[it] : it, sm, md);
+        mq_next(a, n_items, counter, s_item, s_cls, it, c);
+    }
+    *cls = c;
+    return it;
+}
+
 // EPS entries per barrier pair; WPE: the occupancy target (LDS allows five
 // workgroups per CU with one entry per stage, three with two).
 template <int EPS, int WPE>
@@ -272,26 +305,19 @@ k_smm_f64_mquad(SmmArgs a, unsigned long long *counter) {
          e += 64 * kMqWaves)
         sm[e] = 0.0;
     const int64_t n_items = a.n_quads_dev ? *a.n_quads_dev : a.n_quads;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            const int64_t it = static_cast<int64_t>(atomicAdd(counter, 1ull));
-            s_item = it;
-            s_cls = it < n_items ? mq_class(a, a.q_order ? a.q_order[it] : it) : -1;
-        }
-        __syncthreads();
-        const int64_t it = s_item;
-        const int cls = s_cls;
-        __syncthreads();                 // s_item, s_cls are rewritten by the next item
-        if (it >= n_items) break;        // every wave of the workgroup leaves together
-        const int64_t item = a.q_order ? a.q_order[it] : it;
+    int64_t it = 0;
+    int cls = -1;
+    mq_next(a, n_items, counter, s_item, s_cls, it, cls);
+    while (it < n_items) {           // it and cls are the same in every wave
         switch (cls) {
-#define BSM_MQ(ID, MM, NN) case ID: mq_item<MM, NN, EPS>(a, item, sm, md); break;
+#define BSM_MQ(ID, MM, NN) \
+    case ID: it = mq_run<MM, NN, EPS>(a, n_items, counter, it, &cls, sm, md, s_item, s_cls); break;
             BSM_MQ(0, 5, 5) BSM_MQ(1, 5, 13) BSM_MQ(2, 5, 23) BSM_MQ(3, 5, 26)
             BSM_MQ(4, 13, 5) BSM_MQ(5, 13, 13) BSM_MQ(6, 13, 23) BSM_MQ(7, 13, 26)
             BSM_MQ(8, 23, 5) BSM_MQ(9, 23, 13) BSM_MQ(10, 23, 23) BSM_MQ(11, 23, 26)
             BSM_MQ(12, 26, 5) BSM_MQ(13, 26, 13) BSM_MQ(14, 26, 23) BSM_MQ(15, 26, 26)
 #undef BSM_MQ
-            default: break;
+            default: mq_next(a, n_items, counter, s_item, s_cls, it, cls); break;
         }
     }
 }

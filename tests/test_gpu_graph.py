@@ -194,6 +194,25 @@ def test_device_sized_graphs_mixed_sizes(orc, monkeypatch, eps, chunk):
     assert_same_matrix(got[1], x_ref, TOL_FP64, "device-sized graph sign, mixed sizes")
 
 
+def test_device_sized_graphs_maxabs_filter(orc):
+    """The filter on max |x| per block (BSM_NORM_MAXABS) in the graphs."""
+    from paper_2003_03868_amd import bsm
+    h = synth.neighbour_hamiltonian(200, 5, cutoff=6.0, seed=5)
+    runs = []
+    for g in (0, 1):
+        d = to_dev(h)
+        o = bsm.bsm_sign_opts_default()
+        o.eps_filter, o.tol, o.norm, o.use_graph = 1e-6, 1e-8, bsm.NORM_MAXABS, g
+        st, xh, stats = bsm.bsm_sign_iterate(d.handle, 0.0, o)
+        assert st == bsm.OK, bsm.bsm_last_error()
+        runs.append((st, from_dev(bsm.Matrix(xh, h.row_blk_size, h.col_blk_size)), stats))
+    _same_run(runs[0], runs[1])
+    assert runs[1][2].graph_replays > 0
+    x_ref, st_ref, s_ref = orc.sign_ns(h, eps=1e-6, tol=1e-8, norm="maxabs")
+    assert s_ref == orc.OK and runs[1][2].iterations == st_ref["iterations"]
+    assert_same_matrix(runs[1][1], x_ref, TOL_FP64, "device-sized graph sign, max-abs filter")
+
+
 # BSM_GRAPH_CAPS multiplies the capacities (unfiltered C blocks, groups,
 # entries, X, Y): one of them below the sizes makes that buffer overflow.
 OVERFLOW_CASES = [
