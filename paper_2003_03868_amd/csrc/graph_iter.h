@@ -34,7 +34,6 @@ GraphIter *gi_create(hipStream_t s, double eps, int norm);
 void gi_destroy(GraphIter *g);
 bool gi_on(const GraphIter *g);
 int64_t gi_x_nnzb(const GraphIter *g);
-int32_t gi_captures(const GraphIter *g);
 
 // Take over X (its arrays move into the pools; Y's are released) with
 // capacities from the sizes of an eagerly run iteration (square sq, update

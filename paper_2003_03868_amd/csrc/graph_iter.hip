@@ -223,7 +223,6 @@ struct GraphIter {
     bool on = false;          // X lives in x[p] and the graphs are current
     bool have_graphs = false;
     int p = 0;
-    int32_t captures = 0;
     Mat proto;                // X's sizes (block-size arrays borrowed from X)
     int32_t nbr = 0, nbc = 0, b = 0;   // b: the uniform block size, 0 for mixed sizes
     bool mixed = false;
@@ -327,7 +326,6 @@ GraphIter *gi_create(hipStream_t s, double eps, int norm) {
 void gi_destroy(GraphIter *g) { delete g; }
 bool gi_on(const GraphIter *g) { return g && g->on; }
 int64_t gi_x_nnzb(const GraphIter *g) { return g->x_nnzb; }
-int32_t gi_captures(const GraphIter *g) { return g ? g->captures : 0; }
 
 int GraphIter::alloc(const Caps &c) {
     release();
@@ -519,7 +517,6 @@ int GraphIter::capture_all() {
         BSM_TRY(capture([&](hipStream_t cs) { return mult_post(x[1 - q], &st[1], cs); }, &g[q][5]));
     }
     have_graphs = true;
-    ++captures;
     return BSM_OK;
 }
 
