@@ -350,9 +350,12 @@ __device__ inline int4 lp_uniform4(int4 v) {
                      __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
 }
 
-// T = 0: FP32; T = 2 or 3: split-BF16 with that many parts.
+// T = 0: FP32; T = 2 or 3: split-BF16 with that many parts.  Occupancy
+// target: five waves per SIMD for two parts (96 registers, no spills; 5%
+// faster per sign than four on the 2048-site workload at eps 1e-5; six
+// spill and are slower), four otherwise (three parts need 124 registers).
 template <int S, int T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T == 2 ? 5 : 4, 8)))
 k_lowp_quad(SmmArgs a) {
     constexpr bool BF = T >= 2;
     constexpr int NP = BF ? T : 1;                      // bf16 planes per operand
