@@ -222,6 +222,7 @@ struct GraphIter {
     int norm = 0;
     bool on = false;          // X lives in x[p] and the graphs are current
     bool have_graphs = false;
+    bool off = false;         // the buffers did not fit: iterations stay on the normal path
     int p = 0;
     Mat proto;                // X's sizes (block-size arrays borrowed from X)
     int32_t nbr = 0, nbc = 0, b = 0;   // b: the uniform block size, 0 for mixed sizes
@@ -563,7 +564,7 @@ static int from_pool(const GraphIter &g, const PoolMat &pm, int64_t nnzb, int64_
 
 int gi_enter(GraphIter *g, Mat &X, Mat &Y, const MulSizes &sq, const MulSizes &up) {
     if (g->on) { set_error("internal: graph iteration entered twice"); return BSM_EINVAL; }
-    if (!sq.groups || !up.groups) return BSM_OK;   // another kernel did the products
+    if (g->off || !sq.groups || !up.groups) return BSM_OK;   // another kernel did the products
     if (!g->proto.rbs) {
         g->proto = X;
         g->proto.row_ptr = nullptr; g->proto.col_idx = nullptr;
@@ -617,7 +618,16 @@ int gi_enter(GraphIter *g, Mat &X, Mat &Y, const MulSizes &sq, const MulSizes &u
         n.g = std::max(want.g, c.g); n.e = std::max(want.e, c.e);
         n.x = std::max(want.x, c.x); n.xv = std::max(want.xv, c.xv);
         n.y = std::max(want.y, c.y); n.yv = std::max(want.yv, c.yv);
-        BSM_TRY(g->alloc(n));
+        const int r = g->alloc(n);
+        if (r == BSM_ENOMEM) {
+            // device memory too small for the fixed-capacity buffers: the
+            // iterations continue on the normal path, which sizes each
+            // multiply to fit
+            clear_error();
+            g->off = true;
+            return BSM_OK;
+        }
+        BSM_TRY(r);
     }
     if (!g->have_graphs) BSM_TRY(g->capture_all());
     BSM_TRY(to_pool(X, g->x[0], g->nbr, g->s));
