@@ -239,7 +239,9 @@ int bsm_multiply_plan(double alpha, bsm_matrix A, bsm_matrix B, bsm_matrix C,
  * result's pattern: block and scalar counts are checked (BSM_EINVAL), equal
  * positions are the caller's promise.  C may not be A or B.  Whether the
  * filter would now keep another block set, and whether a NaN/Inf appeared,
- * is recorded on the device for bsm_plan_status.
+ * is recorded on the device for bsm_plan_status.  Executes of one plan share
+ * its device state (work counters, unfiltered values, the record): on
+ * different streams they must not overlap.
  */
 int bsm_plan_execute(bsm_plan plan, bsm_matrix A, bsm_matrix B, bsm_matrix C, void *stream);
 
@@ -251,7 +253,12 @@ int bsm_plan_execute(bsm_plan plan, bsm_matrix A, bsm_matrix B, bsm_matrix C, vo
  */
 int bsm_plan_status(bsm_plan plan, int32_t *flags, void *stream);
 
-/* Release a plan's device memory (NULL: no-op). */
+/*
+ * Release a plan's device memory (NULL: no-op), in the order of the stream
+ * of the plan's last call (as a matrix's arrays are released in the order
+ * of its last stream): work queued on other streams that uses the plan must
+ * be complete or ordered before that stream.
+ */
 int bsm_plan_destroy(bsm_plan plan);
 
 /*

@@ -32,7 +32,8 @@ struct bsm_matrix_s {
 struct bsm_plan_s {
     bsm::MulPlan *p = nullptr;
     int *flags = nullptr;        // device record of the executes
-    hipStream_t s = nullptr;     // stream the plan's memory is released on
+    hipStream_t s = nullptr;     // stream of the last call that used the plan: its
+                                 // memory is released in that stream's order
 };
 
 static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -238,6 +239,8 @@ int bsm_plan_execute(bsm_plan plan, bsm_matrix A, bsm_matrix B, bsm_matrix C, vo
     hipStream_t s = as_stream(stream);
     const int st = bsm::replay_multiply(*plan->p, A->m, B->m, nullptr, C->m.values, plan->flags, s);
     C->m.stream = s;
+    plan->s = s;
+    plan->p->s = s;
     return st;
 }
 
@@ -249,6 +252,8 @@ int bsm_plan_status(bsm_plan plan, int32_t *flags, void *stream) {
     BSM_HIP(hipMemcpyAsync(&h, plan->flags, sizeof(int), hipMemcpyDeviceToHost, s));
     BSM_HIP(hipStreamSynchronize(s));
     BSM_TRY(bsm::zero_flag(plan->flags, s));
+    plan->s = s;
+    plan->p->s = s;
     *flags = ((h & bsm::kFlagNonFinite) ? 1 : 0) | ((h & bsm::kFlagPattern) ? 2 : 0);
     return BSM_OK;
 }
