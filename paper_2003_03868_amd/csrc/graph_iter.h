@@ -45,7 +45,8 @@ int gi_square(GraphIter *g, GiStatus *out, double *smm_ms);
 // unless the record shows an overflow or NaN/Inf.
 int gi_update(GraphIter *g, GiStatus *out, double *smm_ms);
 // Give X (and Y when y is not NULL) their own arrays again, copied from the
-// pools; the pools and graphs stay for a later gi_enter.
+// pools; the pools and graphs stay for a later gi_enter.  If X's copy fails
+// (device memory), X keeps no arrays and the iteration stays entered.
 int gi_leave(GraphIter *g, Mat &X, Mat *Y);
 
 }  // namespace bsm

@@ -683,8 +683,8 @@ int gi_update(GraphIter *g, GiStatus *out, double *smm_ms) {
 
 int gi_leave(GraphIter *g, Mat &X, Mat *Y) {
     if (!g->on) return BSM_OK;
-    g->on = false;
     BSM_TRY(from_pool(*g, g->x[g->p], g->x_nnzb, g->x_nval, X));
+    g->on = false;   // X is whole again (else the pools still hold it)
     if (Y) BSM_TRY(from_pool(*g, g->y, g->y_nnzb, g->y_nval, *Y));
     return BSM_OK;
 }

@@ -583,7 +583,15 @@ int sign_iterate(Mat &H, double mu, const bsm_sign_opts &o, Mat **x_out, bsm_sig
     }
     if (gi_on(G)) {
         const int r2 = gi_leave(G, *X, nullptr);
-        if (rc == BSM_OK) rc = r2;
+        if (r2 != BSM_OK) {
+            // X's values are still in the pools only: there is no X to hand out
+            R.drop_plans();
+            free_mat(Y, s);
+            free_mat(X, s);
+            (void)hipEventDestroy(t0);
+            (void)hipEventDestroy(t1);
+            return r2;
+        }
     }
     R.leave(*X);
     R.drop_plans();
