@@ -20,7 +20,9 @@ Workloads (``--workload``):
                    eps_filter 1e-6, tol 1e-6;
 * ``sign23_e5`` -- the same H with eps_filter 1e-5 (the reduced-precision
                    workload's filter);
-* ``mixed``     -- 4096 sites, block sizes {5, 13, 23, 26}, eps 1e-6, tol 1e-6.
+* ``mixed``     -- 4096 sites, block sizes {5, 13, 23, 26}, eps 1e-6, tol 1e-6;
+* ``sign23_o3``, ``sign23_o5`` -- sign23's H and filter with the third- and
+                   fifth-order iterations (the paper's higher-order updates).
 
 Usage (CPU only; hours at full size on a few cores)::
 
@@ -51,6 +53,8 @@ WORKLOADS = {
     "sign23": dict(sites=2048, block=23, eps=1e-6, tol=1e-6),
     "sign23_e5": dict(sites=2048, block=23, eps=1e-5, tol=1e-6),
     "mixed": dict(sites=4096, block=None, eps=1e-6, tol=1e-6),
+    "sign23_o3": dict(sites=2048, block=23, eps=1e-6, tol=1e-6, order=3),
+    "sign23_o5": dict(sites=2048, block=23, eps=1e-6, tol=1e-6, order=5),
 }
 
 
@@ -131,7 +135,7 @@ def main():
     print(f"{args.workload} seed {args.seed}: {h.nbrows} sites, {h.nnzb} blocks, "
           f"n = {h.shape[0]}, oracle threads {oracle.num_threads()}", flush=True)
     t0 = time.time()
-    x, st, status = oracle.sign_ns(h, eps=w["eps"], tol=w["tol"])
+    x, st, status = oracle.sign_ns(h, eps=w["eps"], tol=w["tol"], order=w.get("order", 2))
     dt = time.time() - t0
     if status != oracle.OK:
         raise SystemExit(f"oracle sign iteration ended with status {status}")
@@ -143,6 +147,7 @@ def main():
     np.savez_compressed(
         out, workload=np.array(args.workload), seed=np.int64(args.seed),
         sites=np.int64(h.nbrows), eps=np.float64(w["eps"]), tol=np.float64(w["tol"]),
+        order=np.int64(w.get("order", 2)),
         iterations=np.int64(st["iterations"]), n_multiplies=np.int64(st["n_multiplies"]),
         r_hist=np.array(st["r_hist"]), nnzb_x=np.array(st["nnzb_x"], np.int64),
         nnzb_y=np.array(st["nnzb_y"], np.int64), trace_x=np.float64(st["trace_x"]),

@@ -3,10 +3,11 @@ the oracle's stored record.
 
 The records (``tests/golden/fullsize_<workload>_s<seed>.npz``) are written by
 ``tests/golden/make_fullsize.py``, which runs only the CPU oracle on the same
-seeded workloads (2048 sites x 23 with eps_filter 1e-6 and 1e-5; 4096 sites
-of sizes {5, 13, 23, 26}).  The GPU runs ``bsm_sign_iterate`` with the
-benchmark's settings (default kernels, chunking and options, iterations from
-the device-sized graphs; sign23 seed 0 also without graphs) and must give:
+seeded workloads (2048 sites x 23 with eps_filter 1e-6 and 1e-5, and with
+the third- and fifth-order iterations; 4096 sites of sizes {5, 13, 23, 26}).
+The GPU runs ``bsm_sign_iterate`` with the benchmark's settings (default
+kernels, chunking and options, iterations from the device-sized graphs;
+sign23 seed 0 also without graphs) and must give:
 
 * the same number of iterations and, at every iterate, the same number of
   stored blocks of X_k and of Y_k = filter(X_k X_k) (Sign-Method section:
@@ -42,7 +43,7 @@ pytestmark = pytest.mark.gpu
 # mixed) and with the library default, one launch per (m, n) class
 CASES = [("sign23", 0, None, 1), ("sign23", 0, None, 0), ("sign23", 1, None, 1),
          ("sign23", 2, None, 1), ("sign23_e5", 0, None, 1), ("mixed", 0, "7", 1),
-         ("mixed", 0, "4", 1)]
+         ("mixed", 0, "4", 1), ("sign23_o3", 0, None, 1), ("sign23_o5", 0, None, 1)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -64,8 +65,9 @@ def _sign(h, workload, prec=0, graph=1):
     dh = to_dev(h)
     o = bsm.bsm_sign_opts_default()
     o.eps_filter, o.tol, o.prec, o.use_graph = w["eps"], w["tol"], prec, graph
-    print(f"sign iteration: {workload}, {h.nbrows} sites, prec {prec}, graph mode {graph}",
-          flush=True)
+    o.order = w.get("order", 2)
+    print(f"sign iteration: {workload}, {h.nbrows} sites, order {o.order}, prec {prec}, "
+          f"graph mode {graph}", flush=True)
     st, xh, stats = bsm.bsm_sign_iterate(dh.handle, 0.0, o)
     assert st == bsm.OK, bsm.bsm_last_error()
     x = from_dev(bsm.Matrix(xh, h.row_blk_size, h.col_blk_size))
