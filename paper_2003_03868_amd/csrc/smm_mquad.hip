@@ -42,6 +42,30 @@ __device__ inline double mq_wave_max(double v) {
     for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
     return v;
 }
+// The class bodies are out-of-line calls.  Handed the kernel's SmmArgs by a
+// plain reference, the compiler copies the struct to the stack and reaches
+// every field, and through the fields every operand, with flat (generic)
+// instructions; a reference into the kernel-argument segment (address space
+// 4) and global-space views of the data pointers give global loads and
+// stores instead (10% less time on the mixed workload, same code otherwise).
+using KArgs = const __attribute__((address_space(4))) SmmArgs;
+template <class T>
+__device__ inline const T *gcp(const T *p) {
+    return (const T *)(const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ inline T *gp(T *p) {
+    return (T *)(__attribute__((address_space(1))) T *)p;
+}
+// The same, read once for the wave (scalar registers).
+template <class T>
+__device__ inline const T *ugcp(const T *p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v)));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v >> 32)));
+    return (const T *)(const __attribute__((address_space(1))) T *)((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 __device__ inline int64_t mq_uniform64(int64_t v) {
     const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v)));
     const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v >> 32)));
@@ -85,19 +109,20 @@ struct MqMeta {
 
 // Wave 0: operand offsets and k of the entry en (M rows in the A blocks).
 template <int M>
-__device__ inline void mq_offsets(const SmmArgs &a, int4 en, int64_t (&o)[4], int32_t &kk) {
-    o[0] = en.x >= 0 ? a.a_blk_off[en.x] : -1;
-    o[1] = en.y >= 0 ? a.a_blk_off[en.y] : -1;
-    o[2] = en.z >= 0 ? a.b_blk_off[en.z] : -1;
-    o[3] = en.w >= 0 ? a.b_blk_off[en.w] : -1;
+__device__ inline void mq_offsets(const int64_t *abo, const int64_t *bbo, int4 en,
+                                  int64_t (&o)[4], int32_t &kk) {
+    o[0] = en.x >= 0 ? abo[en.x] : -1;
+    o[1] = en.y >= 0 ? abo[en.y] : -1;
+    o[2] = en.z >= 0 ? bbo[en.z] : -1;
+    o[3] = en.w >= 0 ? bbo[en.w] : -1;
     const int ai = en.x >= 0 ? en.x : en.y;
-    kk = ai >= 0 ? static_cast<int32_t>((a.a_blk_off[ai + 1] - a.a_blk_off[ai]) / M) : 0;
+    kk = ai >= 0 ? static_cast<int32_t>((abo[ai + 1] - abo[ai]) / M) : 0;
 }
 
 // One work item (group) of class (M, N); EPS entries are staged per barrier
 // pair (slot set q of LDS holds entry t + q).
 template <int M, int N, int EPS>
-__device__ inline void mq_item(const SmmArgs &a, int64_t item, double *sm, MqMeta &md) {
+__device__ inline void mq_item(KArgs &a, int64_t item, double *sm, MqMeta &md) {
     constexpr int MT = (M + 3) / 4, NT = (N + 3) / 4;
     constexpr int HR = (MT + 1) / 2, HC = (NT + 1) / 2;
     const int lane = threadIdx.x % kWave;
@@ -105,7 +130,11 @@ __device__ inline void mq_item(const SmmArgs &a, int64_t item, double *sm, MqMet
     const int rr = wv >> 1, cc = wv & 1;
     const int x = lane >> 4, blk = (lane >> 2) & 3, y = lane & 3;
     const int bh = blk >> 1, bw = blk & 1;
-    const int64_t e0 = a.q_seg[item], ne = a.q_seg[item + 1] - e0;
+    const auto qseg = ugcp(a.q_seg);
+    const auto qent = ugcp(a.q_ent);
+    const auto abo = ugcp(a.a_blk_off), bbo = ugcp(a.b_blk_off);
+    const auto avals = ugcp(a.a_vals), bvals = ugcp(a.b_vals);
+    const int64_t e0 = qseg[item], ne = qseg[item + 1] - e0;
 
     double acc[HR][HC];
 #pragma unroll
@@ -122,13 +151,13 @@ __device__ inline void mq_item(const SmmArgs &a, int64_t item, double *sm, MqMet
         if (lane < ne) {
             int64_t o[4];
             int32_t kk;
-            mq_offsets<M>(a, a.q_ent[e0 + lane], o, kk);
+            mq_offsets<M>(abo, bbo, qent[e0 + lane], o, kk);
 #pragma unroll
             for (int z = 0; z < 4; ++z) md.off[0][lane][z] = o[z];
             md.k[0][lane] = kk;
         }
-        if (kMqChunk + lane < ne) mq_offsets<M>(a, a.q_ent[e0 + kMqChunk + lane], roff, rk);
-        if (2 * kMqChunk + lane < ne) creg = a.q_ent[e0 + 2 * kMqChunk + lane];
+        if (kMqChunk + lane < ne) mq_offsets<M>(abo, bbo, qent[e0 + kMqChunk + lane], roff, rk);
+        if (2 * kMqChunk + lane < ne) creg = qent[e0 + 2 * kMqChunk + lane];
     }
     __syncthreads();
 
@@ -151,7 +180,7 @@ __device__ inline void mq_item(const SmmArgs &a, int64_t item, double *sm, MqMet
     double pv[EPS][kMqNV];
     auto load_op = [&](int64_t off, int kk, double (&p)[kMqNV]) {
         if (off < 0) return;
-        const double *g = (wv < 2 ? a.a_vals : a.b_vals) + off;
+        const auto g = (wv < 2 ? avals : bvals) + off;
         const int len = (wv < 2 ? M : N) * kk;
 #pragma unroll
         for (int v = 0; v < kMqNV; ++v)
@@ -190,8 +219,8 @@ __device__ inline void mq_item(const SmmArgs &a, int64_t item, double *sm, MqMet
 #pragma unroll
             for (int z = 0; z < 4; ++z) md.off[b][lane][z] = roff[z];
             md.k[b][lane] = rk;
-            if (t1 + kMqChunk + lane < ne) mq_offsets<M>(a, creg, roff, rk);
-            if (t1 + 2 * kMqChunk + lane < ne) creg = a.q_ent[e0 + t1 + 2 * kMqChunk + lane];
+            if (t1 + kMqChunk + lane < ne) mq_offsets<M>(abo, bbo, creg, roff, rk);
+            if (t1 + 2 * kMqChunk + lane < ne) creg = qent[e0 + t1 + 2 * kMqChunk + lane];
         }
         __syncthreads();
 #pragma unroll
@@ -216,13 +245,13 @@ __device__ inline void mq_item(const SmmArgs &a, int64_t item, double *sm, MqMet
     }
 
     // epilogue: this wave's C block
-    const int64_t cb = a.q_cblk[4 * item + 2 * rr + cc];
+    const int64_t cb = gcp(a.q_cblk)[4 * item + 2 * rr + cc];
     if (cb >= 0) {
-        const int64_t co = a.c_blk_off[cb];
+        const int64_t co = gcp(a.c_blk_off)[cb];
         const double *cin = nullptr;
         if (a.cin_map) {
-            const int64_t tt = a.cin_map[cb];
-            if (tt >= 0) cin = a.cin_vals + a.cin_blk_off[tt];
+            const int64_t tt = gcp(a.cin_map)[cb];
+            if (tt >= 0) cin = gcp(a.cin_vals) + gcp(a.cin_blk_off)[tt];
         }
         double sq = 0.0, mx = 0.0;
 #pragma unroll
@@ -233,7 +262,7 @@ __device__ inline void mq_item(const SmmArgs &a, int64_t item, double *sm, MqMet
                 if (row < M && col < N) {
                     double v = a.alpha * acc[t][u];
                     if (cin) v += a.beta * cin[row * N + col];
-                    a.c_vals[co + row * N + col] = v;
+                    gp(a.c_vals)[co + row * N + col] = v;
                     sq += v * v;
                     mx = fmax(mx, fabs(v));
                 }
@@ -241,15 +270,16 @@ __device__ inline void mq_item(const SmmArgs &a, int64_t item, double *sm, MqMet
         sq = mq_wave_sum(sq);
         mx = mq_wave_max(mx);
         if (lane == 0) {
-            a.sq_out[cb] = sq;
-            a.mx_out[cb] = mx;
+            gp(a.sq_out)[cb] = sq;
+            gp(a.mx_out)[cb] = mx;
             if (!isfinite(sq)) atomicOr(a.flags, kFlagNonFinite);
         }
     }
 }
 
 // Class of item (m, n) from its first C block: 4 class(m) + class(n), or -1.
-__device__ inline int mq_class(const SmmArgs &a, int64_t item) {
+template <class A>
+__device__ inline int mq_class(A &a, int64_t item) {
     int64_t cb = -1;
     for (int z = 0; z < 4 && cb < 0; ++z) cb = a.q_cblk[4 * item + z];
     if (cb < 0) return -1;
@@ -260,7 +290,7 @@ __device__ inline int mq_class(const SmmArgs &a, int64_t item) {
 
 // The next work item from the counter into s_item, its class into s_cls
 // (-1 past the end); every wave of the workgroup sees both.
-__device__ inline void mq_next(const SmmArgs &a, int64_t n_items, unsigned long long *counter,
+__device__ inline void mq_next(KArgs &a, int64_t n_items, unsigned long long *counter,
                                int64_t &s_item, int &s_cls, int64_t &it, int &cls) {
     if (threadIdx.x == 0) {
         const int64_t x = static_cast<int64_t>(atomicAdd(counter, 1ull));
@@ -279,7 +309,7 @@ __device__ inline void mq_next(const SmmArgs &a, int64_t n_items, unsigned long 
 // meets rather than once per group.  Returns that item; *cls its class.
 template <int M, int N, int EPS>
 __device__ __attribute__((noinline)) int64_t
-mq_run(const SmmArgs &a, int64_t n_items, unsigned long long *counter, int64_t it, int *cls,
+mq_run(KArgs &a, int64_t n_items, unsigned long long *counter, int64_t it, int *cls,
        double *sm, MqMeta &md, int64_t &s_item, int &s_cls) {
     const int me = *cls;
     int c = me;
@@ -305,19 +335,21 @@ k_smm_f64_mquad(SmmArgs a, unsigned long long *counter) {
          e += 64 * kMqWaves)
         sm[e] = 0.0;
     const int64_t n_items = a.n_quads_dev ? *a.n_quads_dev : a.n_quads;
+    // a is the first explicit argument: offset 0 of the kernel-argument segment
+    KArgs &ka = *(KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
     int64_t it = 0;
     int cls = -1;
-    mq_next(a, n_items, counter, s_item, s_cls, it, cls);
+    mq_next(ka, n_items, counter, s_item, s_cls, it, cls);
     while (it < n_items) {           // it and cls are the same in every wave
         switch (cls) {
 #define BSM_MQ(ID, MM, NN) \
-    case ID: it = mq_run<MM, NN, EPS>(a, n_items, counter, it, &cls, sm, md, s_item, s_cls); break;
+    case ID: it = mq_run<MM, NN, EPS>(ka, n_items, counter, it, &cls, sm, md, s_item, s_cls); break;
             BSM_MQ(0, 5, 5) BSM_MQ(1, 5, 13) BSM_MQ(2, 5, 23) BSM_MQ(3, 5, 26)
             BSM_MQ(4, 13, 5) BSM_MQ(5, 13, 13) BSM_MQ(6, 13, 23) BSM_MQ(7, 13, 26)
             BSM_MQ(8, 23, 5) BSM_MQ(9, 23, 13) BSM_MQ(10, 23, 23) BSM_MQ(11, 23, 26)
             BSM_MQ(12, 26, 5) BSM_MQ(13, 26, 13) BSM_MQ(14, 26, 23) BSM_MQ(15, 26, 26)
 #undef BSM_MQ
-            default: mq_next(a, n_items, counter, s_item, s_cls, it, cls); break;
+            default: mq_next(ka, n_items, counter, s_item, s_cls, it, cls); break;
         }
     }
 }
