@@ -435,8 +435,8 @@ int mquad_order(const SmmArgs &a, int8_t *rank_scratch, int64_t *order, hipStrea
 
 // Entries staged per barrier pair (1 or 2); BSM_MQUAD_STAGE overrides the
 // default.  Two halve the barriers per entry but take occupancy from four
-// workgroups per CU to three: 10.3 s of block products per sign step on the
-// mixed workload against 8.9 s with one.
+// workgroups per CU to three: 9.6 s per sign on the mixed workload against
+// 8.3 s with one.
 static int mquad_stage() {
     const char *e = getenv("BSM_MQUAD_STAGE");
     return (e && atoi(e) == 2) ? 2 : 1;
