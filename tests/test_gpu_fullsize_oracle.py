@@ -43,7 +43,8 @@ pytestmark = pytest.mark.gpu
 # mixed) and with the library default, one launch per (m, n) class
 CASES = [("sign23", 0, None, 1), ("sign23", 0, None, 0), ("sign23", 1, None, 1),
          ("sign23", 2, None, 1), ("sign23_e5", 0, None, 1), ("mixed", 0, "7", 1),
-         ("mixed", 0, "4", 1), ("sign23_o3", 0, None, 1), ("sign23_o5", 0, None, 1)]
+         ("mixed", 0, "4", 1), ("mixed", 1, "7", 1), ("sign23_o3", 0, None, 1),
+         ("sign23_o5", 0, None, 1)]
 
 
 @pytest.fixture(scope="module", autouse=True)
